@@ -1,0 +1,82 @@
+// Internal interface between the C ABI (gw_api.hip) and the kernels
+// (gw_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+#include "gwlnl.h"
+
+namespace gw {
+
+constexpr int kBlock = 256;          // threads per block of every kernel; one sample per thread
+constexpr int kMaxDet = GW_MAX_DET;
+
+// Per-sample record, stored field-major ([field][n_samples]) so that a block
+// reads it with coalesced loads.  The ten phase coefficients are those of
+// Phi_0/2, the half phase at detector 0:
+//   Phi_0/2 = u^-5 (c0 + u^2 (c2 + u (c3 + u (c4 + u ((c5 + c5l L)
+//                 + u ((c6 + c6l L) + u (c7 + u c8)))))))
+// with u = f^(1/3), L = ln u, and c8 = pi tau_0 (the time shift 2 pi f tau_0 / 2
+// written as u^8 u^-5).
+enum RecordField : int {
+    kRecC8 = 0, kRecC7, kRecC6, kRecC6L, kRecC5, kRecC5L, kRecC4, kRecC3, kRecC2, kRecC0,
+    kRecStatus,                 // 0 evaluate, 1 out of domain (-inf), 2 non-finite (NaN)
+    kRecDet,                    // then per output channel d: P re, P im, delta (s)
+    kRecFieldsPerDet = 3,
+};
+constexpr int record_fields(int n_out) { return kRecDet + kRecFieldsPerDet * n_out; }
+
+// Detector geometry passed by value to the sample-preparation kernel.
+struct DetGeom {
+    double tensor[kMaxDet][9];
+    double vertex[kMaxDet][3];
+};
+
+// Tables per bin: tab1 = (u, u^2, u^-5, ln u), tab2 = (f, f^-7/6).
+struct Tab1 { double u, u2, um5, lnu; };
+struct Tab2 { double f, amp; };
+
+// Launch plan of the tile kernel for one event.
+struct TilePlan {
+    int n_groups;        // ceil(n_samples / kBlock)
+    int n_chunks;        // bin chunks per sample group
+    int64_t chunk_bins;  // bins per chunk (the last may be shorter)
+    int tile_bins;       // bins staged in LDS at a time
+};
+
+// Sizes of workspace sections for one event.
+struct EventSizes {
+    int64_t n_bins;
+    int n_det;
+    int64_t n_samples;
+    int prep_blocks;
+};
+
+// ---- launchers (gw_kernels.hip); all enqueue on `stream` and return the launch status ----
+hipError_t launch_event_tables(const gw_grid &grid, Tab1 *tab1, Tab2 *tab2, hipStream_t stream);
+
+hipError_t launch_event_data(const gw_grid &grid, int n_det, const gw_c128 *data, const double *psd,
+                             const Tab2 *tab2, double2 *dcoef, double *prep_partials, int prep_blocks,
+                             double *event_sums, hipStream_t stream);
+
+hipError_t launch_sample_prep(int64_t n_samples, int n_param, int n_out, bool polarisations, const DetGeom &geom,
+                              const double *theta, double *records, hipStream_t stream);
+
+hipError_t launch_lnl_tiles(const gw_grid &grid, int n_det, int64_t n_samples, const TilePlan &plan,
+                            const Tab1 *tab1, const double2 *dcoef, const double *records,
+                            double2 *partials, hipStream_t stream);
+
+hipError_t launch_lnl_finalize(int64_t n_samples, int n_det, const TilePlan &plan, const double2 *partials,
+                               const double *records, const double *event_sums, double *lnl_out,
+                               hipStream_t stream);
+
+hipError_t launch_waveform(const gw_grid &grid, int n_out, int64_t n_samples, const Tab1 *tab1, const Tab2 *tab2,
+                           const double *records, gw_c128 *h_out, hipStream_t stream);
+
+// LDS bytes of the tile kernel and its occupancy.
+size_t lnl_tile_lds_bytes(int n_det, int tile_bins);
+int lnl_tile_blocks_per_cu(int n_det, int tile_bins);
+
+}  // namespace gw
