@@ -19,8 +19,10 @@ host cores it is given) on a bounded number of the same samples.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,14 +32,45 @@ if ROOT not in sys.path:
 
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector peak
 HBM_PEAK_GBS = 8000.0
+# Sources whose content fixes the tile kernel's machine code; a profile
+# summary records their SHA-256 next to the traffic it measured.
+KERNEL_SOURCES = ("paper_1904_02863_amd/csrc/gw_kernels.hip", "paper_1904_02863_amd/csrc/gw_device_math.h",
+                  "paper_1904_02863_amd/csrc/gw_internal.h", "paper_1904_02863_amd/build.py")
+PROFILE_SUMMARY = "profiles/lnl_tile_kernel_bbh-3det-128s.md"
 
 
-def flops_per_pair(n_det: int) -> int:
+def flops_per_pair(n_det: int, mixed: bool = False) -> int:
     """Algorithmic FP64 flops of the tile kernel per (sample, bin) pair
-    (FMA = 2, multiply = 1): half-phase polynomial 19, phasor from the half
-    phase 43, detector-0 accumulation 8, and for every further detector
-    rotate (6) + accumulate (8) + advance the delay rotation (6)."""
-    return 19 + 43 + 8 + 20 * (n_det - 1)
+    (FMA = 2, multiply or add = 1, rounding to an integer not counted):
+    phase polynomial in u = f^(1/3) 19 (9 FMA + 1 multiply), phasor
+    e^{-2 pi i x} from the phase in turns 39 (17 FMA + 4 multiplies + 1 add),
+    detector-0 complex accumulation 8 (4 FMA), and for every further detector
+    one Horner step S <- S conj(rho) + D e^{-i Phi} 14 (6 FMA + 2 multiplies).
+    The mixed path replaces the phasor by the reduction to a fractional turn
+    (1 add) and two FP32 hardware transcendentals, which are not counted."""
+    return 19 + (1 if mixed else 39) + 8 + 14 * (n_det - 1)
+
+
+def kernel_fingerprint() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per launch of the tile kernel from the committed counter
+    summary, or None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, PROFILE_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    val = re.search(rf"traffic_bytes_per_launch_{precision}:\s*([0-9.eE+]+)", text)
+    if not sha or not val or sha.group(1) != kernel_fingerprint():
+        return None
+    return float(val.group(1))
 
 
 def build_inputs(name: str, n_samples: int | None):
@@ -91,15 +124,123 @@ def cpu_baseline(w, data, budget_s: float):
                       f"{w.n_det} detectors, {spent:.1f} s"}
 
 
+def bench_ragged(args):
+    """256 neutron-star events of 8..256 s (16,225..519,169 bins), 3 detectors,
+    512 proposals each: one gw_lnl_ragged pass (persistent launch replayed from
+    a HIP graph) per step, against 256 separate gw_lnl_batch calls."""
+    import numpy as np
+    import torch
+
+    import paper_1904_02863_amd as gw
+    import synth
+
+    evs = synth.bns_ragged(n_events=256, n_samples=512)
+    dev = torch.device("cuda", 0)
+    ws = gw.Workspace(0)
+    datas, psds, thetas = [], [], []
+    for e in evs:
+        inj = torch.from_numpy(np.ascontiguousarray(e.theta_inj[None])).to(dev)
+        h = gw.waveform_batch(e.grid, e.tensors, e.vertices, inj, workspace=ws)[0]
+        datas.append((torch.from_numpy(e.noise).to(dev) + h).reshape(-1))
+        psds.append(torch.from_numpy(e.psd.ravel()).to(dev))
+        thetas.append(e.theta)
+    counts = [e.theta.shape[0] for e in evs]
+    events, total, rows = gw.make_events([e.grid for e in evs], [e.tensors for e in evs],
+                                         [e.vertices for e in evs], counts)
+    data = torch.cat(datas).contiguous()
+    psd = torch.cat(psds).contiguous()
+    del datas, psds
+    theta = torch.from_numpy(np.ascontiguousarray(np.concatenate(thetas))).to(dev)
+    out = torch.empty(rows, dtype=torch.float64, device=dev)
+    prec = args.precision
+
+    def ragged_step():
+        gw.lnl_ragged(events, len(evs), data, psd, theta, out=out, workspace=ws, precision=prec)
+
+    views = []
+    for i, e in enumerate(evs):
+        m, off = e.grid.n_bins, events[i].data_offset
+        views.append((e, data[off:off + 3 * m].view(3, m), psd[off:off + 3 * m].view(3, m),
+                      theta[events[i].theta_offset:events[i].theta_offset + counts[i]],
+                      out[events[i].theta_offset:events[i].theta_offset + counts[i]]))
+
+    def separate_step():
+        for e, d, s, th, o in views:
+            gw.lnl_batch(e.grid, e.tensors, e.vertices, d, s, th, out=o, workspace=ws, precision=prec)
+
+    def timed(fn, warmup, steps):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    steps = max(1, args.steps // 10)
+    sep_s = timed(separate_step, 1, steps)
+    ragged_step()                      # first call: autotune and capture (untimed)
+    torch.cuda.synchronize()
+    tuning = ws.ragged_tuning()
+    rag_s = timed(ragged_step, 2, steps)
+    if not torch.isfinite(out).all():
+        raise SystemExit("non-finite lnL in the ragged batch")
+    pairs = sum(c * e.grid.n_bins for c, e in zip(counts, evs))
+    flops = flops_per_pair(3, prec == "mixed") * pairs
+    result = {
+        "metric": "lnL evals/s (256 ragged BNS events, 3 det, 512 proposals each)",
+        "value": rows / rag_s, "unit": "lnL evals/s", "n_gpus": 1, "steps": steps, "warmup": 2,
+        "ms_per_step": rag_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32" if prec == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": "bns-ragged-256", "n_events": len(evs), "rows": rows, "bins_total": total // 3,
+                   "sample_bin_pairs": pairs, "precision": prec, "tile_bins": tuning[0], "chunk_bins": tuning[1]},
+        "separate_launches": {"value": rows / sep_s, "ms_per_step": sep_s * 1e3},
+        "speedup_vs_separate": sep_s / rag_s,
+        "roofline": {"bound": "alu", "achieved": flops / rag_s / 1e12, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": flops / rag_s / 1e12 / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "whole ragged pass (graph)", "flops_per_pair": flops_per_pair(3, prec == "mixed")},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(7)
+        order = rng.permutation(len(evs))
+        threads = oracle.max_threads()
+        spent, done_pairs = 0.0, 0
+        used = []
+        for i in order:
+            if spent >= args.cpu_seconds:
+                break
+            e = evs[i]
+            g = e.grid
+            d = data[events[i].data_offset:events[i].data_offset + 3 * g.n_bins].view(3, g.n_bins).cpu().numpy()
+            n = threads
+            t0 = time.perf_counter()
+            oracle.lnl(g.f_low, g.delta_f, g.n_bins, e.tensors, e.vertices, d, e.psd, e.theta[:n])
+            spent += time.perf_counter() - t0
+            done_pairs += n * g.n_bins
+            used.append(int(i))
+        pair_rate = done_pairs / spent
+        result["cpu_baseline"] = {
+            "value": pair_rate * rows / pairs, "unit": "lnL evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{threads} rows of each of {len(used)} seeded random events ({done_pairs} sample-bin pairs, "
+                      f"{spent:.1f} s), extrapolated to the batch by sample-bin pairs"}
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="bbh-3det-128s", choices=["bbh-3det-128s", "bbh-1det-4s"])
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--workload", default="bbh-3det-128s", choices=["bbh-3det-128s", "bbh-1det-4s", "bns-ragged"])
     ap.add_argument("--samples", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, run one plain device-to-device copy of MIB MiB "
+                         "(reference dispatch for scaling hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -112,6 +253,9 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible: the benchmark runs the HIP library only")
+    if args.workload == "bns-ragged":
+        bench_ragged(args)
+        return
     w, data, psd, theta = build_inputs(args.workload, args.samples)
     g = w.grid
     ws = gw.Workspace(0)
@@ -119,7 +263,7 @@ def main():
     out = torch.empty(w.n_samples, dtype=torch.float64, device=theta.device)
 
     def step():
-        gw.lnl_batch(g, w.tensors, w.vertices, data, psd, theta, out=out, workspace=ws)
+        gw.lnl_batch(g, w.tensors, w.vertices, data, psd, theta, out=out, workspace=ws, precision=args.precision)
 
     for _ in range(args.warmup):
         step()
@@ -133,12 +277,21 @@ def main():
     elapsed = time.perf_counter() - t0
     kernel_ms, launches = ws.kernel_time()
     ws.set_timing(False)
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=theta.device)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not torch.isfinite(out).all():
         raise SystemExit("non-finite lnL in the benchmark batch")
 
     evals = w.n_samples * args.steps
     kernel_avg_s = kernel_ms / 1e3 / max(launches, 1)
-    flops_launch = flops_per_pair(w.n_det) * w.n_samples * g.n_bins
+    mixed = args.precision == "mixed"
+    flops_launch = flops_per_pair(w.n_det, mixed) * w.n_samples * g.n_bins
     achieved = flops_launch / kernel_avg_s / 1e12
     result = {
         "metric": "lnL evals/s (3-det,128 s TaylorF2)" if args.workload == "bbh-3det-128s" else "lnL evals/s",
@@ -151,15 +304,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+f32" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "n_samples": w.n_samples, "n_det": w.n_det, "n_bins": g.n_bins,
                    "delta_f": g.delta_f, "f_low": g.f_low, "f_high": g.f_high, "n_param": w.n_param,
-                   "precision": "fp64"},
+                   "precision": args.precision},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": f"lnl_tile_kernel<{w.n_det}>", "kernel_ms": kernel_avg_s * 1e3,
-                     "flops_per_launch": flops_launch, "flops_per_pair": flops_per_pair(w.n_det)},
+                     "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic(args.precision) if args.workload == "bbh-3det-128s" else None,
+                     "kernel": f"lnl_tile_kernel<{w.n_det},{'mixed' if mixed else 'fp64'}>",
+                     "kernel_ms": kernel_avg_s * 1e3, "flops_per_launch": flops_launch,
+                     "flops_per_pair": flops_per_pair(w.n_det, mixed)},
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, data, args.cpu_seconds)

@@ -174,7 +174,12 @@ typedef struct {
 /*
  * gw_lnl_ragged -- Eq. (cbclike) for many events of different durations
  * (Sec. III: different signals have different numbers of bins), each with its
- * own samples, in one persistent launch.
+ * own samples, in one persistent launch.  The pass (event preparation, sample
+ * preparation, the persistent kernel per detector count, final reduction) is
+ * captured once in a HIP graph and replayed while the events, pointers and
+ * precision stay the same; any other call on the workspace, or a change of
+ * those, rebuilds it (waiting for `stream`).  Events with n_samples == 0 are
+ * skipped.
  *   events          host [n_events].
  *   data_packed     device complex, event e at data_offset_e, [n_det_e][n_bins_e].
  *   psd_packed      device doubles, same offsets as data_packed.
@@ -186,6 +191,108 @@ int gw_lnl_ragged(gw_workspace *ws, int n_events, const gw_event *events,
                   const gw_c128 *data_packed, const double *psd_packed,
                   const double *theta_packed, int n_param,
                   double *lnl_out_packed, int precision, unsigned flags, hipStream_t stream);
+
+/* Tile shape the last gw_lnl_ragged call used: bins staged in LDS per tile and
+ * bins per work item.  The first call for a new size class times every
+ * candidate shape once (several passes, results overwritten) and keeps the
+ * fastest for later calls of that class on this workspace. */
+int gw_ragged_tuning(const gw_workspace *ws, int *tile_bins, int64_t *chunk_bins);
+
+/* ------------------------------------------------------------------------
+ * Learned proposal and many-chain Metropolis-Hastings
+ *
+ * The paper (Sec. I) observes that the sampling algorithm itself is hard to
+ * parallelise while the likelihood is embarrassingly parallel.  These calls
+ * run many chains at once on the GPU, with the exact likelihood above as the
+ * Metropolis-Hastings judge, and a normalising flow trained on the chains'
+ * own samples as an independence proposal.
+ *
+ * Sampler coordinates: x in R^dim (dim 9 or 11), x_i = logit(u_i) with u_i the
+ * position of parameter i in a uniform prior box [lo_i, hi_i]; the parameters
+ * are, in order, Mc, q, d_L, phi_c, t_c, RA, sin Dec, psi, cos iota and, for
+ * dim 11, two aligned spins that the non-spinning waveform does not use.
+ * ------------------------------------------------------------------------ */
+
+/* Philox4x32-10 (Salmon et al., SC 2011) block `i` of counter
+ * (i mod 2^32, i div 2^32, step, stream_id) and key (seed mod 2^32, seed div 2^32),
+ * for i < n_blocks: out (device) [n_blocks][4]. */
+int gw_philox_raw(uint64_t seed, uint32_t stream_id, uint32_t step, int64_t n_blocks, uint32_t *out,
+                  hipStream_t stream);
+
+/* out (device) [n]: kind 0 uniforms in (0,1) (53 random bits; numbers 2i and
+ * 2i+1 from block i), kind 1 standard normals (Box-Muller of that pair). */
+int gw_philox_fill(uint64_t seed, uint32_t stream_id, uint32_t step, int kind, int64_t n, double *out,
+                   hipStream_t stream);
+
+/* out (device) [n_chains][dim]: normal i of chain c is member i mod 2 of the
+ * Box-Muller pair of block c ceil(dim/2) + i div 2. */
+int gw_philox_chain_normals(int dim, int64_t n_chains, uint64_t seed, uint32_t stream_id, uint32_t step,
+                            double *out, hipStream_t stream);
+
+/* theta_out (device) [n][9] in the layout of gw_lnl_batch, and the log prior
+ * density of x, sum_i log u_i (1 - u_i) (logprior_out may be NULL).
+ * box_lo, box_hi: host [dim]; the sin Dec and cos iota boxes lie in [-1, 1]. */
+int gw_mcmc_to_theta(int dim, int64_t n, const double *box_lo, const double *box_hi, const double *x,
+                     double *theta_out, double *logprior_out, hipStream_t stream);
+
+/* Random-walk proposals x_prop = x + L z, z from Philox stream 1 at `step`
+ * (chain c uses the normals of gw_philox_chain_normals).  chol: device [dim][dim],
+ * lower triangular.  With mode non-NULL only chains whose mode is 1 (random
+ * walk) are written. */
+int gw_mcmc_rw_propose(int dim, int64_t n, const double *x, const double *chol, uint64_t seed, uint32_t step,
+                       const int *mode, double *x_prop, hipStream_t stream);
+
+/* Metropolis-Hastings decision for every chain, with the uniform from Philox
+ * stream 2 at `step`:
+ *   log alpha = lnl_prop + lp_prop - lnp  [+ logq - logq_prop for chains in mode 0]
+ * On acceptance x and lnp (= lnl + lp) take the proposal's values, and for
+ * chains in mode 0 so does logq.  mode NULL means every chain used a symmetric
+ * proposal (logq, logq_prop may then be NULL).  Each acceptance adds 1 to
+ * window_accepts[c] and total_accepts[c] (device int32, either may be NULL). */
+int gw_mcmc_accept(int dim, int64_t n, uint64_t seed, uint32_t step, double *x, double *lnp, double *logq,
+                   const double *x_prop, const double *lnl_prop, const double *lp_prop, const double *logq_prop,
+                   const int *mode, int *window_accepts, int *total_accepts, hipStream_t stream);
+
+/* mode[c] = 1 (random walk) when window_accepts[c] < threshold * window, else
+ * 0 (flow proposals); window_accepts restarts at zero. */
+int gw_mcmc_update_mode(int64_t n, int *window_accepts, int window, double threshold, int *mode,
+                        hipStream_t stream);
+
+/* Affine-coupling flow (RealNVP): x = mu + sigma * f_{L-1}(... f_0(z)), z ~ N(0, I).
+ * Layer l keeps the dimensions whose bit is set in cond_masks[l] and maps the
+ * others as y = a exp(s) + t, s = 3 tanh(r/3), (r, t) = MLP_l(masked a),
+ * MLP = Linear(dim, H) ReLU Linear(H, H) ReLU Linear(H, 2 dim) (r first).
+ * The MLPs run on BF16 matrix cores with FP32 accumulation; the coupling, the
+ * state and the log densities are FP64.  Parameters are FP32, per layer in
+ * the order W1 [H][dim], b1 [H], W2 [H][H], b2 [H], W3 [2 dim][H], b3 [2 dim].
+ * A flow object is bound to one device; it is not thread-safe. */
+typedef struct gw_flow gw_flow;
+
+int gw_flow_create(gw_flow **flow, int device, int dim, int n_layers, int hidden, const unsigned *cond_masks);
+int gw_flow_destroy(gw_flow *flow);
+int64_t gw_flow_num_params(const gw_flow *flow);
+
+/* Host copies in/out of the parameters, mu and log sigma; setting resets the
+ * optimiser state.  Both wait for the device. */
+int gw_flow_set_params(gw_flow *flow, const float *params, const double *mu, const double *log_sigma);
+int gw_flow_get_params(const gw_flow *flow, float *params, double *mu, double *log_sigma);
+
+/* z (device) [n][dim] -> x_out [n][dim] and log q(x) (logq_out may be NULL). */
+int gw_flow_forward(gw_flow *flow, const double *z, int64_t n, double *x_out, double *logq_out,
+                    hipStream_t stream);
+
+/* x (device) [n][dim] -> z_out (may be NULL) and log q(x) (may be NULL). */
+int gw_flow_inverse(gw_flow *flow, const double *x, int64_t n, double *z_out, double *logq_out,
+                    hipStream_t stream);
+
+/* Gradient (device, [num_params] FP32) of the mean of -log q over the rows
+ * of x, and that mean (device scalar, may be NULL), without updating. */
+int gw_flow_gradients(gw_flow *flow, const double *x, int64_t n, float *grad_out, double *loss_out,
+                      hipStream_t stream);
+
+/* One Adam step (beta 0.9, 0.999, eps 1e-8, learning rate lr) on the mean of
+ * -log q over the rows of x; the loss before the step goes to loss_out. */
+int gw_flow_train_step(gw_flow *flow, const double *x, int64_t n, float lr, double *loss_out, hipStream_t stream);
 
 /* Message about the last failing call on this thread ("" if none). */
 const char *gw_last_error(void);

@@ -27,7 +27,12 @@ MAX_DET = 8
 
 # Every symbol include/gwlnl.h declares.
 EXPORTED = ("gw_workspace_create", "gw_workspace_destroy", "gw_workspace_reserve", "gw_workspace_bytes",
-            "gw_workspace_set_timing", "gw_workspace_kernel_time", "gw_waveform_batch", "gw_lnl_batch", "gw_lnl_ragged", "gw_last_error", "gw_version")
+            "gw_workspace_set_timing", "gw_workspace_kernel_time", "gw_waveform_batch", "gw_lnl_batch",
+            "gw_lnl_ragged", "gw_ragged_tuning", "gw_last_error", "gw_version",
+            "gw_philox_raw", "gw_philox_fill", "gw_philox_chain_normals", "gw_mcmc_to_theta", "gw_mcmc_rw_propose",
+            "gw_mcmc_accept", "gw_mcmc_update_mode", "gw_flow_create", "gw_flow_destroy", "gw_flow_num_params",
+            "gw_flow_set_params", "gw_flow_get_params", "gw_flow_forward", "gw_flow_inverse", "gw_flow_gradients",
+            "gw_flow_train_step")
 
 
 class GwError(RuntimeError):
@@ -72,6 +77,25 @@ def load_library() -> ctypes.CDLL:
         lib.gw_lnl_batch.argtypes = [vp, ctypes.POINTER(GwGrid), i32, ctypes.POINTER(GwDetector), vp, vp, vp, i32,
                                      i64, vp, i32, u32, vp]
         lib.gw_lnl_ragged.argtypes = [vp, i32, ctypes.POINTER(GwEvent), vp, vp, vp, i32, vp, i32, u32, vp]
+        lib.gw_ragged_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        u64, u32p = ctypes.c_uint64, ctypes.c_uint32
+        lib.gw_philox_raw.argtypes = [u64, u32p, u32p, i64, vp, vp]
+        lib.gw_philox_fill.argtypes = [u64, u32p, u32p, i32, i64, vp, vp]
+        lib.gw_philox_chain_normals.argtypes = [i32, i64, u64, u32p, u32p, vp, vp]
+        lib.gw_mcmc_to_theta.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp]
+        lib.gw_mcmc_rw_propose.argtypes = [i32, i64, vp, vp, u64, u32p, vp, vp, vp]
+        lib.gw_mcmc_accept.argtypes = [i32, i64, u64, u32p, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.gw_mcmc_update_mode.argtypes = [i64, vp, i32, ctypes.c_double, vp, vp]
+        lib.gw_flow_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32, vp]
+        lib.gw_flow_destroy.argtypes = [vp]
+        lib.gw_flow_num_params.argtypes = [vp]
+        lib.gw_flow_num_params.restype = i64
+        lib.gw_flow_set_params.argtypes = [vp, vp, vp, vp]
+        lib.gw_flow_get_params.argtypes = [vp, vp, vp, vp]
+        lib.gw_flow_forward.argtypes = [vp, vp, i64, vp, vp, vp]
+        lib.gw_flow_inverse.argtypes = [vp, vp, i64, vp, vp, vp]
+        lib.gw_flow_gradients.argtypes = [vp, vp, i64, vp, vp, vp]
+        lib.gw_flow_train_step.argtypes = [vp, vp, i64, ctypes.c_float, vp, vp]
         lib.gw_last_error.restype = ctypes.c_char_p
         lib.gw_version.restype = i32
         for name in EXPORTED:
@@ -115,6 +139,12 @@ class Workspace:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         _check(load_library().gw_workspace_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def ragged_tuning(self) -> tuple[int, int]:
+        """(LDS tile bins, bins per work item) of the last ragged call."""
+        t, c = ctypes.c_int(), ctypes.c_int64()
+        _check(load_library().gw_ragged_tuning(self._h, ctypes.byref(t), ctypes.byref(c)))
+        return t.value, c.value
 
     @property
     def handle(self):
@@ -286,3 +316,175 @@ def lnl_ragged(events, n_events: int, data_packed, psd_packed, theta_packed, *, 
 
 def version() -> int:
     return load_library().gw_version()
+
+
+# ---------------------------------------------------------------- sampler calls
+def _ptr_or_null(t):
+    return None if t is None else t.data_ptr()
+
+
+def philox_raw(seed: int, stream_id: int, step: int, n_blocks: int, device=0, stream=None):
+    """Philox4x32-10 blocks as a numpy uint32 array [n_blocks, 4] (computed on the GPU)."""
+    torch = _torch()
+    out = torch.empty((int(n_blocks), 4), dtype=torch.int32, device=torch.device("cuda", device))
+    _check(load_library().gw_philox_raw(int(seed), int(stream_id), int(step), int(n_blocks), out.data_ptr(),
+                                        _stream_ptr(device, stream)))
+    return out.cpu().numpy().view(np.uint32)
+
+
+def philox_fill(seed: int, stream_id: int, step: int, n: int, normal: bool, device=0, stream=None, out=None):
+    """n uniforms (normal=False) or standard normals from (seed, stream_id, step) as float64 on the GPU."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(int(n), dtype=torch.float64, device=torch.device("cuda", device))
+    _check(load_library().gw_philox_fill(int(seed), int(stream_id), int(step), 1 if normal else 0, int(n),
+                                         out.data_ptr(), _stream_ptr(device, stream)))
+    return out
+
+
+def chain_normals(dim: int, n_chains: int, seed: int, stream_id: int, step: int, out=None, device=0, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty((int(n_chains), int(dim)), dtype=torch.float64, device=torch.device("cuda", device))
+    _check(load_library().gw_philox_chain_normals(int(dim), int(n_chains), int(seed), int(stream_id), int(step),
+                                                  out.data_ptr(), _stream_ptr(device, stream)))
+    return out
+
+
+def mcmc_to_theta(box_lo, box_hi, x, theta_out=None, logprior_out=None, stream=None):
+    """theta [n, 9] and log prior [n] of sampler coordinates x [n, dim]."""
+    torch = _torch()
+    x = _cuda_tensor(x, torch.float64, "x")
+    n, dim = x.shape
+    lo = np.ascontiguousarray(box_lo, dtype=np.float64)
+    hi = np.ascontiguousarray(box_hi, dtype=np.float64)
+    if lo.shape != (dim,) or hi.shape != (dim,):
+        raise ValueError("box_lo and box_hi must have one entry per coordinate")
+    if theta_out is None:
+        theta_out = torch.empty((n, 9), dtype=torch.float64, device=x.device)
+    if logprior_out is None:
+        logprior_out = torch.empty(n, dtype=torch.float64, device=x.device)
+    _check(load_library().gw_mcmc_to_theta(dim, n, lo.ctypes.data, hi.ctypes.data, x.data_ptr(), theta_out.data_ptr(),
+                                           logprior_out.data_ptr(), _stream_ptr(x.device.index, stream)))
+    return theta_out, logprior_out
+
+
+def mcmc_rw_propose(x, chol, seed: int, step: int, x_prop, mode=None, stream=None):
+    torch = _torch()
+    x = _cuda_tensor(x, torch.float64, "x")
+    n, dim = x.shape
+    chol = _cuda_tensor(chol, torch.float64, "chol", (dim, dim))
+    x_prop = _cuda_tensor(x_prop, torch.float64, "x_prop", (n, dim))
+    if mode is not None:
+        mode = _cuda_tensor(mode, torch.int32, "mode", (n,))
+    _check(load_library().gw_mcmc_rw_propose(dim, n, x.data_ptr(), chol.data_ptr(), int(seed), int(step),
+                                             _ptr_or_null(mode), x_prop.data_ptr(), _stream_ptr(x.device.index, stream)))
+    return x_prop
+
+
+def mcmc_accept(seed: int, step: int, x, lnp, x_prop, lnl_prop, lp_prop, logq=None, logq_prop=None, mode=None,
+                window_accepts=None, total_accepts=None, stream=None):
+    """One Metropolis-Hastings decision per chain (see gw_mcmc_accept)."""
+    torch = _torch()
+    x = _cuda_tensor(x, torch.float64, "x")
+    n, dim = x.shape
+    for name, t in (("lnp", lnp), ("lnl_prop", lnl_prop), ("lp_prop", lp_prop)):
+        _cuda_tensor(t, torch.float64, name, (n,))
+    _cuda_tensor(x_prop, torch.float64, "x_prop", (n, dim))
+    for name, t in (("window_accepts", window_accepts), ("total_accepts", total_accepts), ("mode", mode)):
+        if t is not None:
+            _cuda_tensor(t, torch.int32, name, (n,))
+    _check(load_library().gw_mcmc_accept(dim, n, int(seed), int(step), x.data_ptr(), lnp.data_ptr(),
+                                         _ptr_or_null(logq), x_prop.data_ptr(), lnl_prop.data_ptr(), lp_prop.data_ptr(),
+                                         _ptr_or_null(logq_prop), _ptr_or_null(mode), _ptr_or_null(window_accepts),
+                                         _ptr_or_null(total_accepts), _stream_ptr(x.device.index, stream)))
+
+
+def mcmc_update_mode(window_accepts, window: int, threshold: float, mode, stream=None):
+    n = mode.shape[0]
+    _check(load_library().gw_mcmc_update_mode(n, window_accepts.data_ptr(), int(window), float(threshold),
+                                              mode.data_ptr(), _stream_ptr(mode.device.index, stream)))
+    return mode
+
+
+class Flow:
+    """Affine-coupling normalising flow on the GPU (gw_flow): BF16 matrix-core
+    MLPs, FP64 coupling and densities, Adam training."""
+
+    def __init__(self, dim: int, cond_masks, hidden: int = 256, device: int = 0):
+        lib = load_library()
+        masks = np.ascontiguousarray(cond_masks, dtype=np.uint32)
+        self.dim, self.layers, self.hidden, self.device = int(dim), len(masks), int(hidden), int(device)
+        self.cond_masks = masks.copy()
+        self._h = ctypes.c_void_p()
+        _check(lib.gw_flow_create(ctypes.byref(self._h), self.device, self.dim, self.layers, self.hidden,
+                                  masks.ctypes.data))
+        self.n_params = lib.gw_flow_num_params(self._h)
+
+    def set_params(self, params, mu, log_sigma):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        m = np.ascontiguousarray(mu, dtype=np.float64)
+        ls = np.ascontiguousarray(log_sigma, dtype=np.float64)
+        if p.shape != (self.n_params,) or m.shape != (self.dim,) or ls.shape != (self.dim,):
+            raise ValueError("parameter shapes do not match the flow")
+        _check(load_library().gw_flow_set_params(self._h, p.ctypes.data, m.ctypes.data, ls.ctypes.data))
+
+    def get_params(self):
+        p = np.empty(self.n_params, dtype=np.float32)
+        m = np.empty(self.dim)
+        ls = np.empty(self.dim)
+        _check(load_library().gw_flow_get_params(self._h, p.ctypes.data, m.ctypes.data, ls.ctypes.data))
+        return p, m, ls
+
+    def _rows(self, a, name):
+        torch = _torch()
+        a = _cuda_tensor(a, torch.float64, name)
+        if a.dim() != 2 or a.shape[1] != self.dim:
+            raise ValueError(f"{name} must be [n, {self.dim}]")
+        return a
+
+    def forward(self, z, x_out=None, logq_out=None, stream=None):
+        torch = _torch()
+        z = self._rows(z, "z")
+        x_out = torch.empty_like(z) if x_out is None else x_out
+        logq_out = torch.empty(z.shape[0], dtype=torch.float64, device=z.device) if logq_out is None else logq_out
+        _check(load_library().gw_flow_forward(self._h, z.data_ptr(), z.shape[0], x_out.data_ptr(), logq_out.data_ptr(),
+                                              _stream_ptr(self.device, stream)))
+        return x_out, logq_out
+
+    def inverse(self, x, z_out=None, logq_out=None, stream=None):
+        torch = _torch()
+        x = self._rows(x, "x")
+        z_out = torch.empty_like(x) if z_out is None else z_out
+        logq_out = torch.empty(x.shape[0], dtype=torch.float64, device=x.device) if logq_out is None else logq_out
+        _check(load_library().gw_flow_inverse(self._h, x.data_ptr(), x.shape[0], z_out.data_ptr(), logq_out.data_ptr(),
+                                              _stream_ptr(self.device, stream)))
+        return z_out, logq_out
+
+    def gradients(self, x, stream=None):
+        torch = _torch()
+        x = self._rows(x, "x")
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float64, device=x.device)
+        _check(load_library().gw_flow_gradients(self._h, x.data_ptr(), x.shape[0], grad.data_ptr(), loss.data_ptr(),
+                                                _stream_ptr(self.device, stream)))
+        return grad, loss
+
+    def train_step(self, x, lr: float, loss_out=None, stream=None):
+        torch = _torch()
+        x = self._rows(x, "x")
+        loss_out = torch.empty(1, dtype=torch.float64, device=x.device) if loss_out is None else loss_out
+        _check(load_library().gw_flow_train_step(self._h, x.data_ptr(), x.shape[0], float(lr), loss_out.data_ptr(),
+                                                 _stream_ptr(self.device, stream)))
+        return loss_out
+
+    def close(self):
+        if self._h:
+            load_library().gw_flow_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

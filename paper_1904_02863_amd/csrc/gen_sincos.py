@@ -1,80 +1,80 @@
 """Generates the polynomial coefficients of the device sine/cosine in
 gw_device_math.h (run:  python paper_1904_02863_amd/csrc/gen_sincos.py).
 
-Method: the classic argument-reduction-plus-polynomial scheme (Cody & Waite,
-Software Manual for the Elementary Functions, 1980).  The kernels only ever
-need e^{-i Phi} for a phase Phi reduced to h = Phi/2 - n pi, |h| <= pi/2, and
-rebuild e^{-i Phi} from the half angle with cos Phi = 1 - 2 sin^2 h and
-sin Phi = 2 sin h cos h.  On |h| <= pi/2, with z = h^2:
+Method: argument reduction plus polynomials (Cody & Waite, Software Manual for
+the Elementary Functions, 1980), applied to phases measured in turns.  The
+kernels need e^{-i Phi} for Phi = 2 pi x; they take r = x - rint(x), which is
+exact, so |r| <= 1/2 and e^{-i Phi} = e^{-2 pi i r}, and rebuild it from the
+half angle pi r with cos 2 pi r = 1 - 2 sin^2 pi r, sin 2 pi r = 2 sin pi r cos pi r.
+With z = r^2:
 
-    sin h = h + h z S(z),   S of degree 7  (odd polynomial of degree 17)
-    cos h = 1 + z C(z),     C of degree 7  (even polynomial of degree 16)
+    sin(pi r) = r P(z),      P of degree 8  (odd polynomial of degree 17)
+    cos(pi r) = 1 + z C(z),  C of degree 7  (even polynomial of degree 16)
 
-S and C are fitted by weighted least squares on Chebyshev nodes in 60-digit
-arithmetic (the weights h^3 and h^2 make the fit minimise the absolute error
-of sin and cos), which lands within a small factor of the minimax error; the
-script then evaluates the double-precision Horner scheme exactly as the
-kernels do and reports its worst absolute error against mpmath.
+P and C are fitted by weighted least squares on Chebyshev nodes in 60-digit
+arithmetic (weights r and r^2 make the fit minimise the absolute error of sin
+and cos), which lands within a small factor of the minimax error; the script
+then evaluates the double-precision Horner scheme exactly as the kernels do
+and reports its worst absolute error against mpmath.
 """
 import mpmath as mp
 import numpy as np
 
 mp.mp.dps = 60
-HALF_PI = mp.pi / 2
-DEG = 7
+RMAX = mp.mpf(1) / 2
+SIN_DEG = 8
+COS_DEG = 7
 NODES = 400
 
 
-def fit(target, weight):
-    zmax = HALF_PI ** 2
+def fit(target, weight, deg):
+    zmax = RMAX ** 2
     zs = [zmax * (1 - mp.cos(mp.pi * (j + mp.mpf(0.5)) / NODES)) / 2 for j in range(NODES)]
-    a = mp.matrix(NODES, DEG + 1)
+    a = mp.matrix(NODES, deg + 1)
     b = mp.matrix(NODES, 1)
     for i, z in enumerate(zs):
         w = weight(z)
-        for k in range(DEG + 1):
+        for k in range(deg + 1):
             a[i, k] = w * z ** k
         b[i] = w * target(z)
     q, r = mp.qr(a)
-    coef = mp.lu_solve(r[:DEG + 1, :DEG + 1], (q.T * b)[:DEG + 1, 0])
-    return [coef[k] for k in range(DEG + 1)]
+    coef = mp.lu_solve(r[:deg + 1, :deg + 1], (q.T * b)[:deg + 1, 0])
+    return [coef[k] for k in range(deg + 1)]
 
 
-def s_true(z):
-    h = mp.sqrt(z)
-    return (mp.sin(h) - h) / (h * z) if z > 0 else mp.mpf(-1) / 6
+def p_true(z):
+    r = mp.sqrt(z)
+    return mp.sin(mp.pi * r) / r if z > 0 else mp.pi
 
 
 def c_true(z):
-    h = mp.sqrt(z)
-    return (mp.cos(h) - 1) / z if z > 0 else mp.mpf(-1) / 2
+    r = mp.sqrt(z)
+    return (mp.cos(mp.pi * r) - 1) / z if z > 0 else -mp.pi ** 2 / 2
+
+
+def horner(coef, z):
+    p = coef[-1]
+    for c in reversed(coef[:-1]):
+        p = p * z + c              # the kernels use fma; the error bound is of the same size
+    return p
 
 
 def main():
-    s = fit(s_true, lambda z: z ** mp.mpf(1.5))
-    c = fit(c_true, lambda z: z)
-    sd = [float(x) for x in s]
-    cd = [float(x) for x in c]
-    hs = np.linspace(-float(HALF_PI), float(HALF_PI), 20001)
+    p = [float(x) for x in fit(p_true, lambda z: mp.sqrt(z), SIN_DEG)]
+    c = [float(x) for x in fit(c_true, lambda z: z, COS_DEG)]
     worst_s = worst_c = 0.0
-    for h in hs:
-        z = h * h
-        p = sd[DEG]
-        for k in range(DEG - 1, -1, -1):
-            p = p * z + sd[k]      # the kernels use fma; the error bound is of the same size
-        sv = h + (h * z) * p
-        p = cd[DEG]
-        for k in range(DEG - 1, -1, -1):
-            p = p * z + cd[k]
-        cv = 1.0 + z * p
-        worst_s = max(worst_s, abs(float(mp.sin(h) - sv)))
-        worst_c = max(worst_c, abs(float(mp.cos(h) - cv)))
-    print("// sin h = h + h z S(z), S coefficients z^0 .. z^7")
-    for k, x in enumerate(sd):
-        print(f"#define GW_SIN_S{k} {x!r}")
-    print("// cos h = 1 + z C(z), C coefficients z^0 .. z^7")
-    for k, x in enumerate(cd):
-        print(f"#define GW_COS_C{k} {x!r}")
+    for r in np.linspace(-0.5, 0.5, 20001):
+        z = r * r
+        sv = r * horner(p, z)
+        cv = 1.0 + z * horner(c, z)
+        worst_s = max(worst_s, abs(float(mp.sin(mp.pi * r) - sv)))
+        worst_c = max(worst_c, abs(float(mp.cos(mp.pi * r) - cv)))
+    print("// sin(pi r) = r P(z), z = r^2, coefficients z^0 .. z^8")
+    for k, x in enumerate(p):
+        print(f"#define GW_SINPI_P{k} {x!r}")
+    print("// cos(pi r) = 1 + z C(z), coefficients z^0 .. z^7")
+    for k, x in enumerate(c):
+        print(f"#define GW_COSPI_C{k} {x!r}")
     print(f"// worst absolute error in double: sin {worst_s:.3e}, cos {worst_c:.3e}")
 
 

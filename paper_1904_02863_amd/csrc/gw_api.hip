@@ -4,10 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "gw_internal.h"
@@ -16,12 +19,22 @@
 struct gw_workspace {
     int device = 0;
     int n_cu = 0;
-    int blocks_per_cu[gw::kMaxDet + 1] = {0};   // tile-kernel occupancy by detector count (0 = unknown)
+    int blocks_per_cu[2][gw::kMaxDet + 1] = {};  // tile-kernel occupancy by precision and detector count (0 = unknown)
     void *base = nullptr;
     size_t capacity = 0;
     bool timing = false;
     std::vector<hipEvent_t> events;   // start/stop pairs of the hot kernel
     int64_t timed = 0;                 // pairs recorded since timing was enabled
+    // ragged batches: a captured graph of the last plan, replayed while the
+    // call (events, pointers, precision) and the workspace stay the same
+    hipStream_t capture_stream = nullptr;
+    std::vector<unsigned char> ragged_key;
+    hipGraph_t ragged_graph = nullptr;
+    hipGraphExec_t ragged_exec = nullptr;
+    // autotuned (tile bins, chunk bins) by (max detectors, precision, size bucket)
+    std::map<std::tuple<int, int, int>, std::pair<int, int64_t>> ragged_tuning;
+    int last_tile_bins = 0;
+    int64_t last_chunk_bins = 0;
 };
 
 namespace {
@@ -70,9 +83,19 @@ struct Carver {
     }
 };
 
+void drop_ragged_graph(gw_workspace *ws)
+{
+    if (ws->ragged_exec) (void)hipGraphExecDestroy(ws->ragged_exec);
+    if (ws->ragged_graph) (void)hipGraphDestroy(ws->ragged_graph);
+    ws->ragged_exec = nullptr;
+    ws->ragged_graph = nullptr;
+    ws->ragged_key.clear();
+}
+
 int ensure_capacity(gw_workspace *ws, size_t bytes)
 {
     if (bytes <= ws->capacity) return GW_OK;
+    drop_ragged_graph(ws);               // its kernels point into the old arena
     if (ws->base) {
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize before growing the workspace");
@@ -118,21 +141,26 @@ int check_dets(int n_det, const gw_detector *dets, int n_param, gw::DetGeom *geo
     return GW_OK;
 }
 
+#ifndef GW_TILE_LDS_BUDGET
+#define GW_TILE_LDS_BUDGET (40 * 1024)
+#endif
+
 int tile_bins_for(int n_det)
 {
-    const size_t budget = 40 * 1024;   // bytes of LDS per block: several blocks per CU fit in 160 KB
-    int t = 512;
+    const size_t budget = GW_TILE_LDS_BUDGET;   // bytes of LDS per block: several blocks per CU fit in 160 KB
+    int t = 2048;
     while (t > 64 && gw::lnl_tile_lds_bytes(n_det, t) > budget) t /= 2;
     return t;
 }
 
-gw::TilePlan plan_tiles(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples)
+gw::TilePlan plan_tiles(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples, bool mixed)
 {
     gw::TilePlan p;
     p.tile_bins = tile_bins_for(n_det);
     p.n_groups = (int)((n_samples + gw::kBlock - 1) / gw::kBlock);
-    if (ws->blocks_per_cu[n_det] == 0) ws->blocks_per_cu[n_det] = gw::lnl_tile_blocks_per_cu(n_det, p.tile_bins);
-    const int64_t target = (int64_t)ws->n_cu * ws->blocks_per_cu[n_det];
+    int &occ = ws->blocks_per_cu[mixed ? 1 : 0][n_det];
+    if (occ == 0) occ = gw::lnl_tile_blocks_per_cu(n_det, p.tile_bins, mixed);
+    const int64_t target = (int64_t)ws->n_cu * occ;
     int64_t chunks = (target + p.n_groups - 1) / p.n_groups;
     const int64_t max_chunks = std::max<int64_t>(1, n_bins / 64);     // at least 64 bins per chunk
     chunks = std::max<int64_t>(1, std::min(chunks, max_chunks));
@@ -180,9 +208,10 @@ int check_common(gw_workspace *ws, const gw_grid *grid, int n_det_min, int n_det
 
 int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::DetGeom &geom, const gw_c128 *data,
                   const double *psd, const double *theta, int n_param, int64_t n_samples, double *lnl_out,
-                  hipStream_t stream)
+                  bool mixed, hipStream_t stream)
 {
-    const gw::TilePlan plan = plan_tiles(ws, grid.n_bins, n_det, n_samples);
+    drop_ragged_graph(ws);               // the arena is about to be laid out for one event
+    const gw::TilePlan plan = plan_tiles(ws, grid.n_bins, n_det, n_samples, mixed);
     const LnlLayout l = lnl_layout(grid.n_bins, n_det, n_samples, plan);
     if (int rc = ensure_capacity(ws, l.total)) return rc;
     auto *tab1 = at<gw::Tab1>(ws, l.tab1);
@@ -210,7 +239,7 @@ int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::De
         if ((e = hipEventRecord(ws->events[2 * ws->timed], stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         stop_event = ws->events[2 * ws->timed + 1];
     }
-    if ((e = gw::launch_lnl_tiles(grid, n_det, n_samples, plan, tab1, dcoef, rec, part, stream)) != hipSuccess)
+    if ((e = gw::launch_lnl_tiles(grid, n_det, n_samples, plan, mixed, tab1, dcoef, rec, part, stream)) != hipSuccess)
         return hip_fail(e, "lnl tiles");
     if (stop_event) {
         if ((e = hipEventRecord(stop_event, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -221,7 +250,293 @@ int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::De
     return GW_OK;
 }
 
+// ------------------------------------------------------------------ ragged batches
+// Host description of one ragged pass: device arrays, their offsets in the
+// workspace arena, and the launch record.
+struct RaggedPlan {
+    std::vector<gw::RaggedEvent> events;
+    std::vector<int2> block_map, groups;
+    std::vector<gw::WorkItem> items;     // all classes, class by class
+    std::vector<int> class_begin;        // first item of each class
+    gw::RaggedLaunch launch{};
+    size_t off_events = 0, off_block_map = 0, off_groups = 0, off_geoms = 0, off_items = 0, off_counters = 0;
+    size_t total = 0;
+};
+
+int64_t ragged_pairs(int n_events, const gw_event *events)
+{
+    int64_t p = 0;
+    for (int i = 0; i < n_events; ++i) p += events[i].n_samples * events[i].grid.n_bins;
+    return p;
+}
+
+// Lays out the workspace for a ragged pass with the given tile shape and
+// fills the host arrays; device pointers are relative to `base`.
+RaggedPlan ragged_plan(gw_workspace *ws, int n_events, const gw_event *events, const gw_c128 *data,
+                       const double *psd, const double *theta, int n_param, double *lnl, bool mixed, int tile_bins,
+                       int64_t chunk_bins, char *base)
+{
+    RaggedPlan p;
+    Carver c;
+    p.events.resize(n_events);
+    std::vector<std::vector<gw::WorkItem>> by_det(gw::kMaxDet + 1);
+    std::vector<int64_t> cost_of;
+    for (int e = 0; e < n_events; ++e) {
+        const gw_event &ev = events[e];
+        gw::RaggedEvent &re = p.events[e];
+        std::memset(&re, 0, sizeof(re));
+        const int64_t m = ev.grid.n_bins, s = ev.n_samples;
+        re.n_bins = m;
+        re.n_samples = s;
+        re.f_low = ev.grid.f_low;
+        re.df = ev.grid.delta_f;
+        re.n_det = ev.n_det;
+        re.chunk_bins = std::min<int64_t>(chunk_bins, m);
+        re.n_chunks = (int)((m + re.chunk_bins - 1) / re.chunk_bins);
+        re.prep_blocks = (int)((m + gw::kBlock - 1) / gw::kBlock);
+        re.data = reinterpret_cast<const double2 *>(data + ev.data_offset);
+        re.psd = psd + ev.data_offset;
+        re.theta = theta ? theta + ev.theta_offset * n_param : nullptr;
+        re.lnl = lnl ? lnl + ev.theta_offset : nullptr;
+        re.tab1 = reinterpret_cast<gw::Tab1 *>(base + c.take(sizeof(gw::Tab1) * m));
+        re.tab2 = reinterpret_cast<gw::Tab2 *>(base + c.take(sizeof(gw::Tab2) * m));
+        re.dcoef = reinterpret_cast<double2 *>(base + c.take(sizeof(double2) * m * ev.n_det));
+        re.rec = reinterpret_cast<double *>(base + c.take(sizeof(double) * gw::record_fields(ev.n_det) *
+                                                           std::max<int64_t>(s, 1)));
+        re.partials = reinterpret_cast<double2 *>(base + c.take(sizeof(double2) * re.n_chunks * s * ev.n_det));
+        re.prep = reinterpret_cast<double *>(base + c.take(sizeof(double) * 2 * ev.n_det * re.prep_blocks));
+        re.sums = reinterpret_cast<double *>(base + c.take(sizeof(double) * (1 + gw::kMaxDet)));
+        for (int b = 0; b < re.prep_blocks; ++b) p.block_map.push_back(make_int2(e, b));
+        const int n_groups = (int)((s + gw::kBlock - 1) / gw::kBlock);
+        for (int gi = 0; gi < n_groups; ++gi) {
+            p.groups.push_back(make_int2(e, gi));
+            const int64_t rows = std::min<int64_t>(gw::kBlock, s - (int64_t)gi * gw::kBlock);
+            for (int ch = 0; ch < re.n_chunks; ++ch) {
+                const int64_t bins = std::min(re.chunk_bins, m - (int64_t)ch * re.chunk_bins);
+                // a block's time follows its bins; rows only change how full it is
+                (void)rows;
+                by_det[ev.n_det].push_back(gw::WorkItem{e, gi, ch, (int)std::min<int64_t>(bins, 0x7fffffff)});
+            }
+        }
+    }
+    gw::RaggedLaunch &L = p.launch;
+    L.n_events = n_events;
+    L.n_prep_blocks = (int)p.block_map.size();
+    L.n_groups = (int)p.groups.size();
+    L.n_param = n_param;
+    L.tile_bins = tile_bins;
+    L.mixed = mixed;
+    L.n_classes = 0;
+    for (int d = 1; d <= gw::kMaxDet; ++d) {
+        auto &v = by_det[d];
+        if (v.empty()) continue;
+        // largest items first, ties by (event, group, chunk) so the order is reproducible
+        std::stable_sort(v.begin(), v.end(), [](const gw::WorkItem &x, const gw::WorkItem &y) {
+            return x.bins > y.bins;
+        });
+        gw::RaggedClass &rc = L.classes[L.n_classes++];
+        rc.n_det = d;
+        rc.n_items = (int)v.size();
+        const int occ = gw::lnl_ragged_blocks_per_cu(d, tile_bins, mixed);
+        rc.grid = (int)std::min<int64_t>((int64_t)ws->n_cu * occ, (int64_t)v.size());
+        p.class_begin.push_back((int)p.items.size());
+        p.items.insert(p.items.end(), v.begin(), v.end());
+    }
+    p.off_events = c.take(sizeof(gw::RaggedEvent) * std::max(n_events, 1));
+    p.off_block_map = c.take(sizeof(int2) * std::max<size_t>(p.block_map.size(), 1));
+    p.off_groups = c.take(sizeof(int2) * std::max<size_t>(p.groups.size(), 1));
+    p.off_geoms = c.take(sizeof(gw::DetGeom) * std::max(n_events, 1));
+    p.off_items = c.take(sizeof(gw::WorkItem) * std::max<size_t>(p.items.size(), 1));
+    p.off_counters = c.take(sizeof(unsigned) * gw::kMaxDet);
+    p.total = c.offset;
+    L.events = reinterpret_cast<const gw::RaggedEvent *>(base + p.off_events);
+    L.block_map = reinterpret_cast<const int2 *>(base + p.off_block_map);
+    L.groups = reinterpret_cast<const int2 *>(base + p.off_groups);
+    L.geoms = reinterpret_cast<const gw::DetGeom *>(base + p.off_geoms);
+    L.counters = reinterpret_cast<unsigned *>(base + p.off_counters);
+    for (int i = 0; i < L.n_classes; ++i) {
+        L.classes[i].items = reinterpret_cast<const gw::WorkItem *>(base + p.off_items) + p.class_begin[i];
+        L.classes[i].counter = L.counters + i;
+    }
+    return p;
+}
+
+// Plans with the arena's real base, growing it first if needed, and copies
+// the host arrays to the device.  Waits for `stream` (the arena may still be
+// in use by earlier work there).
+int ragged_materialise(gw_workspace *ws, int n_events, const gw_event *events, const std::vector<gw::DetGeom> &geoms,
+                       const gw_c128 *data, const double *psd, const double *theta, int n_param, double *lnl,
+                       bool mixed, int tile_bins, int64_t chunk_bins, hipStream_t stream, RaggedPlan *out)
+{
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    RaggedPlan sizing = ragged_plan(ws, n_events, events, data, psd, theta, n_param, lnl, mixed, tile_bins,
+                                    chunk_bins, nullptr);
+    if (int rc = ensure_capacity(ws, sizing.total)) return rc;
+    *out = ragged_plan(ws, n_events, events, data, psd, theta, n_param, lnl, mixed, tile_bins, chunk_bins,
+                       static_cast<char *>(ws->base));
+    char *base = static_cast<char *>(ws->base);
+    struct Copy { size_t off; const void *src; size_t bytes; };
+    const Copy copies[] = {
+        {out->off_events, out->events.data(), sizeof(gw::RaggedEvent) * out->events.size()},
+        {out->off_block_map, out->block_map.data(), sizeof(int2) * out->block_map.size()},
+        {out->off_groups, out->groups.data(), sizeof(int2) * out->groups.size()},
+        {out->off_geoms, geoms.data(), sizeof(gw::DetGeom) * geoms.size()},
+        {out->off_items, out->items.data(), sizeof(gw::WorkItem) * out->items.size()},
+    };
+    for (const Copy &cp : copies) {
+        if (cp.bytes == 0) continue;
+        e = hipMemcpy(base + cp.off, cp.src, cp.bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy of the ragged plan");
+    }
+    return GW_OK;
+}
+
+int capture_stream(gw_workspace *ws)
+{
+    if (ws->capture_stream) return GW_OK;
+    hipError_t e = hipStreamCreateWithFlags(&ws->capture_stream, hipStreamNonBlocking);
+    return e == hipSuccess ? GW_OK : hip_fail(e, "hipStreamCreateWithFlags");
+}
+
+// Times one ragged pass (after one untimed pass) on the workspace's own stream.
+int time_ragged(gw_workspace *ws, const RaggedPlan &p, float *ms)
+{
+    hipEvent_t t0, t1;
+    hipError_t e = hipEventCreate(&t0);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    e = hipEventCreate(&t1);
+    if (e != hipSuccess) { (void)hipEventDestroy(t0); return hip_fail(e, "hipEventCreate"); }
+    int rc = GW_OK;
+    if ((e = gw::launch_ragged(p.launch, ws->capture_stream)) != hipSuccess ||
+        (e = hipEventRecord(t0, ws->capture_stream)) != hipSuccess ||
+        (e = gw::launch_ragged(p.launch, ws->capture_stream)) != hipSuccess ||
+        (e = hipEventRecord(t1, ws->capture_stream)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess ||
+        (e = hipEventElapsedTime(ms, t0, t1)) != hipSuccess)
+        rc = hip_fail(e, "timing a ragged pass");
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    return rc;
+}
+
+// Key of a ragged call: its events, pointers and precision.
+std::vector<unsigned char> ragged_key(int n_events, const gw_event *events, const void *data, const void *psd,
+                                      const void *theta, int n_param, const void *lnl, bool mixed)
+{
+    std::vector<unsigned char> k(sizeof(gw_event) * n_events + 4 * sizeof(void *) + 2 * sizeof(int));
+    unsigned char *w = k.data();
+    if (n_events) std::memcpy(w, events, sizeof(gw_event) * n_events);
+    w += sizeof(gw_event) * n_events;
+    const void *ptrs[4] = {data, psd, theta, lnl};
+    std::memcpy(w, ptrs, sizeof(ptrs));
+    w += sizeof(ptrs);
+    const int tail[2] = {n_param, mixed ? 1 : 0};
+    std::memcpy(w, tail, sizeof(tail));
+    return k;
+}
+
+// Tile shapes the autotuner tries: LDS tile of the tile loop, bins per work item.
+const int kTuneTiles[] = {256, 512};
+const int64_t kTuneChunks[] = {4096, 8192, 16384, 32768};
+
+int ragged_run(gw_workspace *ws, int n_events, const gw_event *events, const std::vector<gw::DetGeom> &geoms,
+               const gw_c128 *data, const double *psd, const double *theta, int n_param, double *lnl, bool mixed,
+               hipStream_t stream)
+{
+    int n_active = 0, max_det = 1;
+    for (int i = 0; i < n_events; ++i) {
+        if (events[i].n_samples > 0) ++n_active;
+        max_det = std::max(max_det, events[i].n_det);
+    }
+    if (n_active == 0) return GW_OK;
+    std::vector<gw_event> active;
+    active.reserve(n_active);
+    for (int i = 0; i < n_events; ++i)
+        if (events[i].n_samples > 0) active.push_back(events[i]);
+    std::vector<gw::DetGeom> active_geoms;
+    for (int i = 0; i < n_events; ++i)
+        if (events[i].n_samples > 0) active_geoms.push_back(geoms[i]);
+    const int na = (int)active.size();
+    const gw_event *ev = active.data();
+
+    std::vector<unsigned char> key = ragged_key(na, ev, data, psd, theta, n_param, lnl, mixed);
+    if (ws->ragged_exec && key == ws->ragged_key) {
+        hipError_t e = hipGraphLaunch(ws->ragged_exec, stream);
+        return e == hipSuccess ? GW_OK : hip_fail(e, "hipGraphLaunch");
+    }
+    drop_ragged_graph(ws);
+    if (int rc = capture_stream(ws)) return rc;
+    // the autotuner and the plan upload run outside the caller's stream order
+    hipError_t se = hipStreamSynchronize(stream);
+    if (se != hipSuccess) return hip_fail(se, "hipStreamSynchronize");
+
+    // tile shape: autotuned once per (detectors, precision, size bucket)
+    const int64_t pairs = ragged_pairs(na, ev);
+    const int bucket = pairs > 0 ? (int)std::floor(std::log2((double)pairs)) : 0;
+    const auto tkey = std::make_tuple(max_det, mixed ? 1 : 0, bucket);
+    auto it = ws->ragged_tuning.find(tkey);
+    int tile_bins = 0;
+    int64_t chunk_bins = 0;
+    RaggedPlan plan;
+    if (it == ws->ragged_tuning.end()) {
+        float best = 0.0f;
+        for (int tb : kTuneTiles) {
+            if (gw::lnl_tile_lds_bytes(max_det, tb) > 64 * 1024) continue;
+            for (int64_t cb : kTuneChunks) {
+                if (int rc = ragged_materialise(ws, na, ev, active_geoms, data, psd, theta, n_param, lnl, mixed, tb,
+                                                cb, ws->capture_stream, &plan))
+                    return rc;
+                float ms = 0.0f;
+                if (int rc = time_ragged(ws, plan, &ms)) return rc;
+                if (tile_bins == 0 || ms < best) {
+                    best = ms;
+                    tile_bins = tb;
+                    chunk_bins = cb;
+                }
+            }
+        }
+        ws->ragged_tuning[tkey] = {tile_bins, chunk_bins};
+    } else {
+        tile_bins = it->second.first;
+        chunk_bins = it->second.second;
+    }
+    ws->last_tile_bins = tile_bins;
+    ws->last_chunk_bins = chunk_bins;
+    if (int rc = ragged_materialise(ws, na, ev, active_geoms, data, psd, theta, n_param, lnl, mixed, tile_bins,
+                                    chunk_bins, stream, &plan))
+        return rc;
+    hipError_t e = hipStreamSynchronize(ws->capture_stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+
+    // capture the pass on the workspace's stream, replay it on the caller's
+    e = hipStreamBeginCapture(ws->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = gw::launch_ragged(plan.launch, ws->capture_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(ws->capture_stream, &graph);
+    if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le, "launching the ragged pass under capture");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    ws->ragged_graph = graph;
+    ws->ragged_exec = exec;
+    ws->ragged_key = std::move(key);
+    e = hipGraphLaunch(exec, stream);
+    return e == hipSuccess ? GW_OK : hip_fail(e, "hipGraphLaunch");
+}
+
 }  // namespace
+
+namespace gw {
+int set_error(int code, const std::string &msg) { return fail(code, msg); }
+}  // namespace gw
 
 extern "C" {
 
@@ -264,6 +579,8 @@ int gw_workspace_destroy(gw_workspace *ws)
         if (e != hipSuccess) rc = hip_fail(e, "freeing the workspace");
     }
     for (hipEvent_t ev : ws->events) (void)hipEventDestroy(ev);
+    drop_ragged_graph(ws);
+    if (ws->capture_stream) (void)hipStreamDestroy(ws->capture_stream);
     delete ws;
     return rc;
 }
@@ -302,7 +619,9 @@ int gw_workspace_reserve(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_
     if (n_bins < 1 || n_det < 1 || n_det > gw::kMaxDet || n_samples < 0) return fail(GW_EINVAL, "bad reserve sizes");
     DeviceGuard g(ws->device);
     if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
-    const gw::TilePlan plan = plan_tiles(ws, n_bins, n_det, n_samples);
+    gw::TilePlan plan = plan_tiles(ws, n_bins, n_det, n_samples, false);
+    const gw::TilePlan plan_mixed = plan_tiles(ws, n_bins, n_det, n_samples, true);
+    if (plan_mixed.n_chunks > plan.n_chunks) plan = plan_mixed;
     const LnlLayout l = lnl_layout(n_bins, n_det, n_samples, plan);
     size_t wave = align_up(sizeof(gw::Tab1) * n_bins) + align_up(sizeof(gw::Tab2) * n_bins) +
                   align_up(sizeof(double) * gw::record_fields(std::max(n_det, 2)) * std::max<int64_t>(n_samples, 1));
@@ -319,14 +638,14 @@ int gw_lnl_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_dete
     if (!data || !psd) return fail(GW_EINVAL, "data or psd is NULL");
     if (n_samples > 0 && (!theta || !lnl_out)) return fail(GW_EINVAL, "theta or lnl_out is NULL");
     if (precision != GW_PREC_FP64 && precision != GW_PREC_MIXED) return fail(GW_EINVAL, "unknown precision");
-    if (precision == GW_PREC_MIXED) return fail(GW_EUNSUPPORTED, "mixed precision is not built yet");
     if (flags != 0) return fail(GW_EINVAL, "flags must be 0");
     gw::DetGeom geom;
     if (int rc = check_dets(n_det, dets, n_param, &geom)) return rc;
     if (n_samples == 0) return GW_OK;
     DeviceGuard g(ws->device);
     if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
-    return lnl_one_event(ws, *grid, n_det, geom, data, psd, theta, n_param, n_samples, lnl_out, stream);
+    return lnl_one_event(ws, *grid, n_det, geom, data, psd, theta, n_param, n_samples, lnl_out,
+                         precision == GW_PREC_MIXED, stream);
 }
 
 int gw_waveform_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_detector *dets,
@@ -345,6 +664,7 @@ int gw_waveform_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw
     if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
     const bool polar = n_det == 0;
     const int n_out = polar ? 2 : n_det;
+    drop_ragged_graph(ws);               // the arena is about to be laid out for the waveform
     Carver c;
     const size_t o1 = c.take(sizeof(gw::Tab1) * grid->n_bins);
     const size_t o2 = c.take(sizeof(gw::Tab2) * grid->n_bins);
@@ -371,28 +691,28 @@ int gw_lnl_ragged(gw_workspace *ws, int n_events, const gw_event *events, const 
     if (n_events > 0 && !events) return fail(GW_EINVAL, "events is NULL");
     if (n_events > 0 && (!data_packed || !psd_packed)) return fail(GW_EINVAL, "data or psd is NULL");
     if (precision != GW_PREC_FP64 && precision != GW_PREC_MIXED) return fail(GW_EINVAL, "unknown precision");
-    if (precision == GW_PREC_MIXED) return fail(GW_EUNSUPPORTED, "mixed precision is not built yet");
     if (flags != 0) return fail(GW_EINVAL, "flags must be 0");
+    if (n_param != 5 && n_param != 9) return fail(GW_EINVAL, "n_param must be 5 or 9");
+    std::vector<gw::DetGeom> geoms(n_events);
     for (int i = 0; i < n_events; ++i) {
         const gw_event &ev = events[i];
         if (int rc = check_common(ws, &ev.grid, 1, ev.n_det, n_param, ev.n_samples)) return rc;
         if (ev.data_offset < 0 || ev.theta_offset < 0) return fail(GW_EINVAL, "negative event offset");
         if (ev.n_samples > 0 && (!theta_packed || !lnl_out_packed)) return fail(GW_EINVAL, "theta or lnl_out is NULL");
-        gw::DetGeom geom;
-        if (int rc = check_dets(ev.n_det, ev.dets, n_param, &geom)) return rc;
+        if (ev.n_samples > (int64_t)0x7fffffff * gw::kBlock) return fail(GW_EINVAL, "too many samples in one event");
+        if (int rc = check_dets(ev.n_det, ev.dets, n_param, &geoms[i])) return rc;
     }
     DeviceGuard g(ws->device);
     if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
-    for (int i = 0; i < n_events; ++i) {
-        const gw_event &ev = events[i];
-        if (ev.n_samples == 0) continue;
-        gw::DetGeom geom;
-        check_dets(ev.n_det, ev.dets, n_param, &geom);
-        if (int rc = lnl_one_event(ws, ev.grid, ev.n_det, geom, data_packed + ev.data_offset,
-                                   psd_packed + ev.data_offset, theta_packed + ev.theta_offset * n_param, n_param,
-                                   ev.n_samples, lnl_out_packed + ev.theta_offset, stream))
-            return rc;
-    }
+    return ragged_run(ws, n_events, events, geoms, data_packed, psd_packed, theta_packed, n_param, lnl_out_packed,
+                      precision == GW_PREC_MIXED, stream);
+}
+
+int gw_ragged_tuning(const gw_workspace *ws, int *tile_bins, int64_t *chunk_bins)
+{
+    if (!ws || !tile_bins || !chunk_bins) return fail(GW_EINVAL, "NULL argument");
+    *tile_bins = ws->last_tile_bins;
+    *chunk_bins = ws->last_chunk_bins;
     return GW_OK;
 }
 

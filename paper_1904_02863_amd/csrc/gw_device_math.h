@@ -1,13 +1,14 @@
 // Device-side mathematics of the TaylorF2 likelihood kernels (gfx950, FP64).
 //
-// * gw_phasor_half: e^{-i Phi} from the half phase Phi/2.  Cody-Waite
-//   reduction of Phi/2 by multiples of pi to |h| <= pi/2 (two-constant pi,
-//   fused multiply-adds), polynomial sine and cosine of h, then the double
-//   angle: cos Phi = 1 - 2 sin^2 h, -sin Phi = -2 sin h cos h.  Working on the
-//   half angle removes the quadrant bookkeeping of a pi/2 reduction: every
-//   step is a floating-point multiply-add, which is what the vector ALU issues
-//   fastest.  Coefficients come from gen_sincos.py (worst absolute error of
-//   the polynomials in double: 2.1e-16).
+// * gw_phasor_turns: e^{-2 pi i x} for a phase x measured in turns.  The
+//   reduction r = x - rint(x) is exact (|r| <= 1/2) and keeps the absolute
+//   accuracy x already has; sin(pi r) and cos(pi r) come from polynomials in
+//   r^2 and e^{-2 pi i r} from the double angle,
+//   cos 2 pi r = 1 - 2 sin^2 pi r, -sin 2 pi r = -2 sin pi r cos pi r.
+//   Working on the half angle removes the quadrant bookkeeping of a quarter-
+//   turn reduction: every step is a floating-point multiply or multiply-add,
+//   which the vector ALU issues at full rate.  Coefficients come from
+//   gen_sincos.py (worst absolute error of the polynomials in double: 3e-16).
 // * gw_pn_coefficients: the non-spinning TaylorF2 phase coefficients through
 //   3.5PN, Buonanno, Iyer, Ochsner, Pan & Sathyaprakash, PRD 80, 084043 (2009),
 //   Eq. (3.18), with the 2.5PN term written phi_5 (1 + 3 ln v) and the 3PN log
@@ -18,9 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #define GW_PI 3.141592653589793
-#define GW_PI_HI 3.141592653589793              // double nearest pi
-#define GW_PI_LO 1.2246467991473532e-16         // pi - GW_PI_HI
-#define GW_INV_PI 0.3183098861837907
+#define GW_TWO_PI 6.283185307179586
 #define GW_EULER_GAMMA 0.5772156649015329
 #define GW_LN4 1.3862943611198906
 #define GW_C_SI 299792458.0                     // m / s
@@ -29,49 +28,49 @@
 #define GW_MSUN_S (GW_GM_SUN_SI / (GW_C_SI * GW_C_SI * GW_C_SI))   // solar mass in seconds
 #define GW_MPC_S (GW_MPC_SI / GW_C_SI)                             // 1 Mpc / c in seconds
 
-// sin h = h + h z S(z), z = h^2, |h| <= pi/2
-#define GW_SIN_S0 -0.16666666666666666
-#define GW_SIN_S1 0.008333333333333106
-#define GW_SIN_S2 -0.0001984126984118389
-#define GW_SIN_S3 2.7557319207506058e-06
-#define GW_SIN_S4 -2.5052106585314903e-08
-#define GW_SIN_S5 1.6058926918823753e-10
-#define GW_SIN_S6 -7.642691997901776e-13
-#define GW_SIN_S7 2.71829976216082e-15
-// cos h = 1 + z C(z)
-#define GW_COS_C0 -0.49999999999999983
-#define GW_COS_C1 0.04166666666666432
-#define GW_COS_C2 -0.0013888888888784095
-#define GW_COS_C3 2.480158727891725e-05
-#define GW_COS_C4 -2.7557316506299984e-07
-#define GW_COS_C5 2.0876566876526882e-09
-#define GW_COS_C6 -1.1463018651812344e-11
-#define GW_COS_C7 4.6100912366850437e-14
+// sin(pi r) = r P(z), z = r^2, |r| <= 1/2
+#define GW_SINPI_P0 3.141592653589793
+#define GW_SINPI_P1 -5.1677127800499685
+#define GW_SINPI_P2 2.550164039877241
+#define GW_SINPI_P3 -0.5992645293174558
+#define GW_SINPI_P4 0.08214588655325346
+#define GW_SINPI_P5 -0.007370430355803027
+#define GW_SINPI_P6 0.00046629916961915324
+#define GW_SINPI_P7 -2.1902019345096585e-05
+#define GW_SINPI_P8 7.68391993043613e-07
+// cos(pi r) = 1 + z C(z)
+#define GW_COSPI_C0 -4.934802200544677
+#define GW_COSPI_C1 4.058712126416539
+#define GW_COSPI_C2 -1.3352627688445147
+#define GW_COSPI_C3 0.23533063014378772
+#define GW_COSPI_C4 -0.025806888844954273
+#define GW_COSPI_C5 0.0019295567379985486
+#define GW_COSPI_C6 -0.0001045676184014752
+#define GW_COSPI_C7 4.1505675232729925e-06
 
-// (re, im) = e^{-i Phi} given half = Phi / 2.
-__device__ __forceinline__ void gw_phasor_half(double half, double &re, double &im)
+// (re, im) = e^{-2 pi i x}.
+__device__ __forceinline__ void gw_phasor_turns(double x, double &re, double &im)
 {
-    const double n = __builtin_rint(half * GW_INV_PI);
-    double h = __builtin_fma(-n, GW_PI_HI, half);
-    h = __builtin_fma(-n, GW_PI_LO, h);
-    const double z = h * h;
-    double s = GW_SIN_S7;
-    s = __builtin_fma(s, z, GW_SIN_S6);
-    s = __builtin_fma(s, z, GW_SIN_S5);
-    s = __builtin_fma(s, z, GW_SIN_S4);
-    s = __builtin_fma(s, z, GW_SIN_S3);
-    s = __builtin_fma(s, z, GW_SIN_S2);
-    s = __builtin_fma(s, z, GW_SIN_S1);
-    s = __builtin_fma(s, z, GW_SIN_S0);
-    s = __builtin_fma(h * z, s, h);
-    double c = GW_COS_C7;
-    c = __builtin_fma(c, z, GW_COS_C6);
-    c = __builtin_fma(c, z, GW_COS_C5);
-    c = __builtin_fma(c, z, GW_COS_C4);
-    c = __builtin_fma(c, z, GW_COS_C3);
-    c = __builtin_fma(c, z, GW_COS_C2);
-    c = __builtin_fma(c, z, GW_COS_C1);
-    c = __builtin_fma(c, z, GW_COS_C0);
+    const double r = x - __builtin_rint(x);
+    const double z = r * r;
+    double p = GW_SINPI_P8;
+    p = __builtin_fma(p, z, GW_SINPI_P7);
+    p = __builtin_fma(p, z, GW_SINPI_P6);
+    p = __builtin_fma(p, z, GW_SINPI_P5);
+    p = __builtin_fma(p, z, GW_SINPI_P4);
+    p = __builtin_fma(p, z, GW_SINPI_P3);
+    p = __builtin_fma(p, z, GW_SINPI_P2);
+    p = __builtin_fma(p, z, GW_SINPI_P1);
+    p = __builtin_fma(p, z, GW_SINPI_P0);
+    const double s = r * p;
+    double c = GW_COSPI_C7;
+    c = __builtin_fma(c, z, GW_COSPI_C6);
+    c = __builtin_fma(c, z, GW_COSPI_C5);
+    c = __builtin_fma(c, z, GW_COSPI_C4);
+    c = __builtin_fma(c, z, GW_COSPI_C3);
+    c = __builtin_fma(c, z, GW_COSPI_C2);
+    c = __builtin_fma(c, z, GW_COSPI_C1);
+    c = __builtin_fma(c, z, GW_COSPI_C0);
     c = __builtin_fma(z, c, 1.0);
     const double m = -2.0 * s;
     re = __builtin_fma(m, s, 1.0);

@@ -1,0 +1,35 @@
+// Internal interface of the flow and sampler kernels (gw_flow.hip).
+#pragma once
+
+#include <cstdint>
+#include <string>
+
+#include <hip/hip_runtime.h>
+
+namespace gw {
+
+// Records msg as the thread's last error (gw_last_error) and returns code.
+int set_error(int code, const std::string &msg);
+namespace flow {
+
+constexpr int kInPad = 16;    // MLP input row (dim <= 16)
+constexpr int kOutPad = 32;   // MLP output row (2 dim <= 32)
+
+struct GemmArgs {
+    int M, N, K;
+    const uint16_t *A;     // BF16
+    int64_t sa_i, sa_k;
+    const uint16_t *B;     // BF16
+    int64_t sb_k, sb_j;
+    float *C;              // FP32 output (may be null)
+    int64_t ldc;
+    uint16_t *Cb;          // BF16 copy of the output (may be null)
+    int64_t ldcb;
+    const float *bias;     // [N] (may be null)
+    int relu;
+};
+
+hipError_t gemm_bf16(const GemmArgs &g, hipStream_t stream);
+
+}  // namespace flow
+}  // namespace gw

@@ -15,10 +15,10 @@ constexpr int kMaxDet = GW_MAX_DET;
 
 // Per-sample record, stored field-major ([field][n_samples]) so that a block
 // reads it with coalesced loads.  The ten phase coefficients are those of
-// Phi_0/2, the half phase at detector 0:
-//   Phi_0/2 = u^-5 (c0 + u^2 (c2 + u (c3 + u (c4 + u ((c5 + c5l L)
-//                 + u ((c6 + c6l L) + u (c7 + u c8)))))))
-// with u = f^(1/3), L = ln u, and c8 = pi tau_0 (the time shift 2 pi f tau_0 / 2
+// Phi_0 / (2 pi), the phase at detector 0 in turns:
+//   Phi_0/(2 pi) = u^-5 (c0 + u^2 (c2 + u (c3 + u (c4 + u ((c5 + c5l L)
+//                      + u ((c6 + c6l L) + u (c7 + u c8)))))))
+// with u = f^(1/3), L = ln u, and c8 = tau_0 (the time shift f tau_0 in turns
 // written as u^8 u^-5).
 enum RecordField : int {
     kRecC8 = 0, kRecC7, kRecC6, kRecC6L, kRecC5, kRecC5L, kRecC4, kRecC3, kRecC2, kRecC0,
@@ -37,6 +37,58 @@ struct DetGeom {
 // Tables per bin: tab1 = (u, u^2, u^-5, ln u), tab2 = (f, f^-7/6).
 struct Tab1 { double u, u2, um5, lnu; };
 struct Tab2 { double f, amp; };
+
+// One event of a ragged batch as the device sees it (pointers into the
+// caller's packed arrays and into the workspace).
+struct RaggedEvent {
+    int64_t n_bins, n_samples;
+    double f_low, df;
+    int n_det, n_chunks, prep_blocks, pad_;
+    int64_t chunk_bins;
+    const double2 *data;
+    const double *psd;
+    const double *theta;
+    double *lnl;
+    Tab1 *tab1;
+    Tab2 *tab2;
+    double2 *dcoef;
+    double *rec;
+    double2 *partials;
+    double *prep;
+    double *sums;
+};
+
+// One unit of the persistent ragged kernel: one sample group of one event
+// against one chunk of its bins.
+struct WorkItem {
+    int event, group, chunk, bins;   // bins: the item's cost, used to sort the list
+};
+
+// The persistent kernel of one detector count within a ragged batch.
+struct RaggedClass {
+    int n_det;
+    int n_items;
+    int grid;                 // persistent blocks
+    const WorkItem *items;    // device, sorted by decreasing cost
+    unsigned *counter;        // device
+};
+
+// Everything one ragged pass launches (device pointers into the workspace).
+struct RaggedLaunch {
+    const RaggedEvent *events;
+    int n_events;
+    const int2 *block_map;    // per prep block: (event, block within event)
+    int n_prep_blocks;
+    const int2 *groups;       // per sample group: (event, group within event)
+    int n_groups;
+    const DetGeom *geoms;     // per event
+    int n_param;
+    unsigned *counters;       // kMaxDet counters
+    RaggedClass classes[kMaxDet];
+    int n_classes;
+    int tile_bins;
+    bool mixed;
+};
 
 // Launch plan of the tile kernel for one event.
 struct TilePlan {
@@ -64,7 +116,7 @@ hipError_t launch_event_data(const gw_grid &grid, int n_det, const gw_c128 *data
 hipError_t launch_sample_prep(int64_t n_samples, int n_param, int n_out, bool polarisations, const DetGeom &geom,
                               const double *theta, double *records, hipStream_t stream);
 
-hipError_t launch_lnl_tiles(const gw_grid &grid, int n_det, int64_t n_samples, const TilePlan &plan,
+hipError_t launch_lnl_tiles(const gw_grid &grid, int n_det, int64_t n_samples, const TilePlan &plan, bool mixed,
                             const Tab1 *tab1, const double2 *dcoef, const double *records,
                             double2 *partials, hipStream_t stream);
 
@@ -75,8 +127,11 @@ hipError_t launch_lnl_finalize(int64_t n_samples, int n_det, const TilePlan &pla
 hipError_t launch_waveform(const gw_grid &grid, int n_out, int64_t n_samples, const Tab1 *tab1, const Tab2 *tab2,
                            const double *records, gw_c128 *h_out, hipStream_t stream);
 
+hipError_t launch_ragged(const RaggedLaunch &r, hipStream_t stream);
+int lnl_ragged_blocks_per_cu(int n_det, int tile_bins, bool mixed);
+
 // LDS bytes of the tile kernel and its occupancy.
 size_t lnl_tile_lds_bytes(int n_det, int tile_bins);
-int lnl_tile_blocks_per_cu(int n_det, int tile_bins);
+int lnl_tile_blocks_per_cu(int n_det, int tile_bins, bool mixed);
 
 }  // namespace gw
