@@ -50,8 +50,8 @@ def _load():
         lib.oracle_antenna.argtypes = [p, d, d, d, p, p]
         lib.oracle_delay.argtypes = [p, d, d]
         lib.oracle_delay.restype = d
-        lib.oracle_waveform.argtypes = [d, d, i64, i32, p, p, p, i32, i64, p]
-        lib.oracle_lnl.argtypes = [d, d, i64, i32, p, p, p, p, p, i32, i64, p, i32]
+        lib.oracle_waveform.argtypes = [d, d, i64, i32, p, p, p, i32, i64, i32, p]
+        lib.oracle_lnl.argtypes = [d, d, i64, i32, p, p, p, p, p, i32, i64, i32, i32, p, i32]
         lib.oracle_max_threads.restype = i32
         _lib = lib
     return _lib
@@ -99,24 +99,27 @@ def _det_arrays(tensors, vertices, n_det):
     return t, v
 
 
-def waveform(f_low: float, delta_f: float, n_bins: int, tensors, vertices, theta) -> np.ndarray:
+def waveform(f_low: float, delta_f: float, n_bins: int, tensors, vertices, theta, isco: bool = False) -> np.ndarray:
     """Detector responses, shape (S, n_det, M) complex128; with tensors None,
-    the polarisations (S, 2, M) instead."""
+    the polarisations (S, 2, M) instead.  isco: zero above each template's
+    innermost-stable-circular-orbit frequency."""
     th = _f64(np.atleast_2d(theta))
     n_det = 0 if tensors is None else np.asarray(tensors).reshape(-1, 9).shape[0]
     t, v = _det_arrays(tensors, vertices, n_det)
     n_out = n_det if n_det else 2
     out = np.empty((th.shape[0], n_out, int(n_bins)), dtype=np.complex128)
     rc = _load().oracle_waveform(float(f_low), float(delta_f), int(n_bins), n_det, _ptr(t), _ptr(v),
-                                 _ptr(th), th.shape[1], th.shape[0], _ptr(out))
+                                 _ptr(th), th.shape[1], th.shape[0], int(bool(isco)), _ptr(out))
     if rc != 0:
         raise ValueError("oracle_waveform rejected its arguments")
     return out
 
 
 def lnl(f_low: float, delta_f: float, n_bins: int, tensors, vertices, data, psd, theta,
-        n_threads: int = 0) -> np.ndarray:
-    """lnL = -2 delta_f sum_d sum_k |d - h|^2 / S for every row of theta."""
+        n_threads: int = 0, isco: bool = False, add_norm: bool = False) -> np.ndarray:
+    """lnL = -2 delta_f sum_d sum_k |d - h|^2 / S for every row of theta
+    (templates ended at f_isco with `isco`; plus -sum ln(2 pi S) with
+    `add_norm`)."""
     th = _f64(np.atleast_2d(theta))
     n_det = np.asarray(tensors).reshape(-1, 9).shape[0]
     t, v = _det_arrays(tensors, vertices, n_det)
@@ -124,7 +127,8 @@ def lnl(f_low: float, delta_f: float, n_bins: int, tensors, vertices, data, psd,
     s = _f64(psd).reshape(n_det, int(n_bins))
     out = np.empty(th.shape[0])
     rc = _load().oracle_lnl(float(f_low), float(delta_f), int(n_bins), n_det, _ptr(t), _ptr(v), _ptr(dat),
-                            _ptr(s), _ptr(th), th.shape[1], th.shape[0], _ptr(out), int(n_threads))
+                            _ptr(s), _ptr(th), th.shape[1], th.shape[0], int(bool(isco)), int(bool(add_norm)),
+                            _ptr(out), int(n_threads))
     if rc != 0:
         raise ValueError("oracle_lnl rejected its arguments")
     return out

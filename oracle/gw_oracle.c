@@ -28,12 +28,16 @@
  *  - h_plus  = A (1 + cos^2 iota)/2 e^{-i Psi},  h_cross = -i A cos(iota) e^{-i Psi};
  *  - detector response h_det = (F+ h_plus + Fx h_cross) e^{-2 pi i f dt_det},
  *    F = D : e (antenna tensors below), dt_det = -n.r_det / c, GMST = 0;
- *  - no upper frequency cut-off: h is evaluated on every bin;
+ *  - no upper frequency cut-off by default: h is evaluated on every bin; on
+ *    request (isco != 0) h = 0 above the gravitational-wave frequency of the
+ *    Schwarzschild innermost stable circular orbit of the total mass M,
+ *    f_isco = c^3 / (6^(3/2) pi G M), the usual end of an inspiral template;
  *  - 5-parameter rows are an optimally oriented source: h = A e^{-i Psi};
  *  - any non-finite parameter gives NaN; Mc <= 0, q outside (0, 1] or
  *    d_L <= 0 give -infinity.
  * Sums use Neumaier compensation per (sample, detector), then across
- * detectors in order.
+ * detectors in order.  On request (add_norm != 0) lnL also carries the
+ * logarithm of the prefactor of Eq. (cbclike), -sum_det sum_bins ln(2 pi S).
  */
 #include <complex.h>
 #include <math.h>
@@ -156,16 +160,26 @@ static int classify(const double *th, int n_param)
 /* Everything about one parameter row that does not depend on frequency. */
 typedef struct {
     double eta, mtot_s, amp0, phic, tc, cos_iota;
+    double f_cut;                 /* h = 0 at f > f_cut (infinity without the cut-off) */
     double phi[8], phi_log[8];
     int n_det;
     double fplus[8], fcross[8], dt[8];
 } source;
 
-static void make_source(const double *th, int n_param, int n_det,
+/* Gravitational-wave frequency (twice the orbital one) at the innermost
+ * stable circular orbit of a test mass around a Schwarzschild black hole of
+ * mass M (seconds): r = 6 M, orbital angular frequency M^(1/2) r^(-3/2). */
+static double isco_frequency(double mtot_s)
+{
+    return 1.0 / (pow(6.0, 1.5) * ORACLE_PI * mtot_s);
+}
+
+static void make_source(const double *th, int n_param, int n_det, int isco,
                         const double *tensors, const double *vertices, source *src)
 {
     const double mc = th[0], q = th[1], dl = th[2];
     masses(mc, q, &src->eta, &src->mtot_s);
+    src->f_cut = isco ? isco_frequency(src->mtot_s) : INFINITY;
     const double mc_s = mc * msun_s();
     const double dist_s = dl * ORACLE_MPC_SI / ORACLE_C_SI;
     src->amp0 = sqrt(5.0 / 24.0) * pow(ORACLE_PI, -2.0 / 3.0) * pow(mc_s, 5.0 / 6.0) / dist_s;
@@ -187,6 +201,7 @@ static void make_source(const double *th, int n_param, int n_det,
 /* The two TaylorF2 polarisations at frequency f. */
 static void polarisations(const source *src, double f, double complex *hp, double complex *hx)
 {
+    if (f > src->f_cut) { *hp = 0.0; *hx = 0.0; return; }
     const double v = cbrt(ORACLE_PI * src->mtot_s * f);
     const double psi = 2.0 * ORACLE_PI * f * src->tc - src->phic - ORACLE_PI / 4.0
                      + pn_series_phase(src->eta, src->phi, src->phi_log, v);
@@ -211,10 +226,11 @@ static int check_args(double delta_f, int64_t n_bins, int n_det, int n_param, in
 /* Waveforms of n_samples parameter rows on bins f_low + k delta_f.
  * n_det > 0: detector responses, out[(s * n_det + d) * n_bins + k].
  * n_det == 0: polarisations, out[(s * 2 + p) * n_bins + k], p = 0 plus, 1 cross.
+ * isco != 0 ends every template at its f_isco.
  * Rows that are out of domain or non-finite produce NaN. */
 int oracle_waveform(double f_low, double delta_f, int64_t n_bins, int n_det,
                     const double *tensors, const double *vertices,
-                    const double *theta, int n_param, int64_t n_samples, double complex *out)
+                    const double *theta, int n_param, int64_t n_samples, int isco, double complex *out)
 {
     if (check_args(delta_f, n_bins, n_det, n_param, n_samples)) return -1;
     const int n_out = n_det > 0 ? n_det : 2;
@@ -223,7 +239,7 @@ int oracle_waveform(double f_low, double delta_f, int64_t n_bins, int n_det,
         const double *th = theta + s * n_param;
         const int ok = classify(th, n_param);
         source src;
-        if (ok == 1) make_source(th, n_param, n_det, tensors, vertices, &src);
+        if (ok == 1) make_source(th, n_param, n_det, isco, tensors, vertices, &src);
         for (int64_t k = 0; k < n_bins; ++k) {
             const double f = f_low + (double)k * delta_f;
             double complex hp = NAN, hx = NAN;
@@ -250,14 +266,26 @@ static void neumaier_add(double *sum, double *comp, double x)
 
 /* lnL of Eq. (cbclike) without its theta-independent factor, for each of the
  * n_samples parameter rows:  lnl[s] = -2 delta_f sum_d sum_k |d_dk - h_dk|^2 / S_dk.
- * data: (n_det, n_bins) complex; psd: (n_det, n_bins).  n_threads <= 0 uses
- * the OpenMP default. */
+ * data: (n_det, n_bins) complex; psd: (n_det, n_bins).  isco != 0 ends every
+ * template at its f_isco; add_norm != 0 adds the log of the factor
+ * prod 1/(2 pi S_dk), -sum_d sum_k ln(2 pi S_dk), to every finite value.
+ * n_threads <= 0 uses the OpenMP default. */
 int oracle_lnl(double f_low, double delta_f, int64_t n_bins, int n_det,
                const double *tensors, const double *vertices,
                const double complex *data, const double *psd,
-               const double *theta, int n_param, int64_t n_samples, double *lnl, int n_threads)
+               const double *theta, int n_param, int64_t n_samples, int isco, int add_norm,
+               double *lnl, int n_threads)
 {
     if (check_args(delta_f, n_bins, n_det, n_param, n_samples) || n_det < 1) return -1;
+    double norm = 0.0;
+    if (add_norm) {
+        double per[8] = {0}, per_c[8] = {0}, nc = 0.0;
+        for (int d = 0; d < n_det; ++d)
+            for (int64_t k = 0; k < n_bins; ++k)
+                neumaier_add(&per[d], &per_c[d], log(2.0 * ORACLE_PI * psd[(size_t)d * n_bins + k]));
+        for (int d = 0; d < n_det; ++d) neumaier_add(&norm, &nc, per[d] + per_c[d]);
+        norm += nc;
+    }
 #ifdef _OPENMP
     extern void omp_set_num_threads(int);
     extern int omp_get_max_threads(void);
@@ -273,7 +301,7 @@ int oracle_lnl(double f_low, double delta_f, int64_t n_bins, int n_det,
         if (ok < 0) { lnl[s] = NAN; continue; }
         if (ok == 0) { lnl[s] = -INFINITY; continue; }
         source src;
-        make_source(th, n_param, n_det, tensors, vertices, &src);
+        make_source(th, n_param, n_det, isco, tensors, vertices, &src);
         double sum[8] = {0}, comp[8] = {0};
         for (int64_t k = 0; k < n_bins; ++k) {
             const double f = f_low + (double)k * delta_f;
@@ -287,7 +315,7 @@ int oracle_lnl(double f_low, double delta_f, int64_t n_bins, int n_det,
         }
         double total = 0.0, total_c = 0.0;
         for (int d = 0; d < n_det; ++d) neumaier_add(&total, &total_c, sum[d] + comp[d]);
-        lnl[s] = -2.0 * delta_f * (total + total_c);
+        lnl[s] = -2.0 * delta_f * (total + total_c) - norm;
     }
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(saved);
