@@ -6,10 +6,13 @@ the Elementary Functions, 1980), applied to phases measured in turns.  The
 kernels need e^{-i Phi} for Phi = 2 pi x; they take r = x - rint(x), which is
 exact, so |r| <= 1/2 and e^{-i Phi} = e^{-2 pi i r}, and rebuild it from the
 half angle pi r with cos 2 pi r = 1 - 2 sin^2 pi r, sin 2 pi r = 2 sin pi r cos pi r.
-With z = r^2:
+With z = r^2 the polynomials carry the double angle's factors:
 
-    sin(pi r) = r P(z),      P of degree 8  (odd polynomial of degree 17)
-    cos(pi r) = 1 + z C(z),  C of degree 7  (even polynomial of degree 16)
+    s2 = sqrt(2) sin(pi r)  = r P(z),               P of degree 7 (odd, degree 15)
+    c2 = -sqrt(2) cos(pi r) = -sqrt(2) + z C(z),    C of degree 6 (even, degree 14)
+
+so that cos 2 pi r = 1 - s2^2 (one FMA with a negated operand) and
+-sin 2 pi r = s2 c2 (one multiply).
 
 P and C are fitted by weighted least squares on Chebyshev nodes in 60-digit
 arithmetic (weights r and r^2 make the fit minimise the absolute error of sin
@@ -22,8 +25,8 @@ import numpy as np
 
 mp.mp.dps = 60
 RMAX = mp.mpf(1) / 2
-SIN_DEG = 8
-COS_DEG = 7
+SIN_DEG = 7
+COS_DEG = 6
 NODES = 400
 
 
@@ -42,14 +45,17 @@ def fit(target, weight, deg):
     return [coef[k] for k in range(deg + 1)]
 
 
+SQRT2 = mp.sqrt(2)
+
+
 def p_true(z):
     r = mp.sqrt(z)
-    return mp.sin(mp.pi * r) / r if z > 0 else mp.pi
+    return SQRT2 * mp.sin(mp.pi * r) / r if z > 0 else SQRT2 * mp.pi
 
 
 def c_true(z):
     r = mp.sqrt(z)
-    return (mp.cos(mp.pi * r) - 1) / z if z > 0 else -mp.pi ** 2 / 2
+    return SQRT2 * (1 - mp.cos(mp.pi * r)) / z if z > 0 else SQRT2 * mp.pi ** 2 / 2
 
 
 def horner(coef, z):
@@ -65,17 +71,20 @@ def main():
     worst_s = worst_c = 0.0
     for r in np.linspace(-0.5, 0.5, 20001):
         z = r * r
-        sv = r * horner(p, z)
-        cv = 1.0 + z * horner(c, z)
-        worst_s = max(worst_s, abs(float(mp.sin(mp.pi * r) - sv)))
-        worst_c = max(worst_c, abs(float(mp.cos(mp.pi * r) - cv)))
-    print("// sin(pi r) = r P(z), z = r^2, coefficients z^0 .. z^8")
+        s2 = r * horner(p, z)
+        c2 = -float(SQRT2) + z * horner(c, z)
+        re = 1.0 - s2 * s2
+        im = s2 * c2
+        worst_s = max(worst_s, abs(float(mp.cos(2 * mp.pi * r) - re)))
+        worst_c = max(worst_c, abs(float(-mp.sin(2 * mp.pi * r) - im)))
+    print("// sqrt(2) sin(pi r) = r P(z), z = r^2, coefficients z^0 .. z^7")
     for k, x in enumerate(p):
         print(f"#define GW_SINPI_P{k} {x!r}")
-    print("// cos(pi r) = 1 + z C(z), coefficients z^0 .. z^7")
+    print("// -sqrt(2) cos(pi r) = -sqrt(2) + z C(z), coefficients z^0 .. z^6")
     for k, x in enumerate(c):
         print(f"#define GW_COSPI_C{k} {x!r}")
-    print(f"// worst absolute error in double: sin {worst_s:.3e}, cos {worst_c:.3e}")
+    print(f"#define GW_SQRT2 {float(SQRT2)!r}")
+    print(f"// worst absolute error of e^(-2 pi i r) in double: re {worst_s:.3e}, im {worst_c:.3e}")
 
 
 if __name__ == "__main__":

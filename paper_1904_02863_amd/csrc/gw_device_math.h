@@ -7,8 +7,9 @@
 //   cos 2 pi r = 1 - 2 sin^2 pi r, -sin 2 pi r = -2 sin pi r cos pi r.
 //   Working on the half angle removes the quadrant bookkeeping of a quarter-
 //   turn reduction: every step is a floating-point multiply or multiply-add,
-//   which the vector ALU issues at full rate.  Coefficients come from
-//   gen_sincos.py (worst absolute error of the polynomials in double: 3e-16).
+//   which the vector ALU issues at full rate.  The polynomials carry the
+//   double angle's factors (sqrt(2) sin, -sqrt(2) cos), so the double angle
+//   costs one FMA and one multiply.  Coefficients come from gen_sincos.py.
 // * gw_pn_coefficients: the non-spinning TaylorF2 phase coefficients through
 //   3.5PN, Buonanno, Iyer, Ochsner, Pan & Sathyaprakash, PRD 80, 084043 (2009),
 //   Eq. (3.18), with the 2.5PN term written phi_5 (1 + 3 ln v) and the 3PN log
@@ -28,33 +29,33 @@
 #define GW_MSUN_S (GW_GM_SUN_SI / (GW_C_SI * GW_C_SI * GW_C_SI))   // solar mass in seconds
 #define GW_MPC_S (GW_MPC_SI / GW_C_SI)                             // 1 Mpc / c in seconds
 
-// sin(pi r) = r P(z), z = r^2, |r| <= 1/2
-#define GW_SINPI_P0 3.141592653589793
-#define GW_SINPI_P1 -5.1677127800499685
-#define GW_SINPI_P2 2.550164039877241
-#define GW_SINPI_P3 -0.5992645293174558
-#define GW_SINPI_P4 0.08214588655325346
-#define GW_SINPI_P5 -0.007370430355803027
-#define GW_SINPI_P6 0.00046629916961915324
-#define GW_SINPI_P7 -2.1902019345096585e-05
-#define GW_SINPI_P8 7.68391993043613e-07
-// cos(pi r) = 1 + z C(z)
-#define GW_COSPI_C0 -4.934802200544677
-#define GW_COSPI_C1 4.058712126416539
-#define GW_COSPI_C2 -1.3352627688445147
-#define GW_COSPI_C3 0.23533063014378772
-#define GW_COSPI_C4 -0.025806888844954273
-#define GW_COSPI_C5 0.0019295567379985486
-#define GW_COSPI_C6 -0.0001045676184014752
-#define GW_COSPI_C7 4.1505675232729925e-06
+// sqrt(2) sin(pi r) = r P(z), z = r^2, |r| <= 1/2
+#define GW_SINPI_P0 4.442882938158362
+#define GW_SINPI_P1 -7.308249499994611
+#define GW_SINPI_P2 3.6064765714243108
+#define GW_SINPI_P3 -0.8474880236471133
+#define GW_SINPI_P4 0.11617181135328143
+#define GW_SINPI_P5 -0.010423245306932737
+#define GW_SINPI_P6 0.000658941477865297
+#define GW_SINPI_P7 -2.981954552480099e-05
+// -sqrt(2) cos(pi r) = -sqrt(2) + z C(z)
+#define GW_COSPI_C0 6.9788641996378855
+#define GW_COSPI_C1 -5.739885734846492
+#define GW_COSPI_C2 1.8883467136058691
+#define GW_COSPI_C3 -0.33280771296175876
+#define GW_COSPI_C4 0.03649596496885426
+#define GW_COSPI_C5 -0.0027264665642378824
+#define GW_COSPI_C6 0.00014206007015282065
+#define GW_SQRT2 1.4142135623730951
 
-// (re, im) = e^{-2 pi i x}.
+// (re, im) = e^{-2 pi i x}: with s2 = sqrt(2) sin(pi r) and c2 = -sqrt(2) cos(pi r),
+// re = cos 2 pi r = 1 - s2^2 and im = -sin 2 pi r = s2 c2 (20 floating-point
+// operations; worst absolute error 5e-15).
 __device__ __forceinline__ void gw_phasor_turns(double x, double &re, double &im)
 {
     const double r = x - __builtin_rint(x);
     const double z = r * r;
-    double p = GW_SINPI_P8;
-    p = __builtin_fma(p, z, GW_SINPI_P7);
+    double p = GW_SINPI_P7;
     p = __builtin_fma(p, z, GW_SINPI_P6);
     p = __builtin_fma(p, z, GW_SINPI_P5);
     p = __builtin_fma(p, z, GW_SINPI_P4);
@@ -62,19 +63,17 @@ __device__ __forceinline__ void gw_phasor_turns(double x, double &re, double &im
     p = __builtin_fma(p, z, GW_SINPI_P2);
     p = __builtin_fma(p, z, GW_SINPI_P1);
     p = __builtin_fma(p, z, GW_SINPI_P0);
-    const double s = r * p;
-    double c = GW_COSPI_C7;
-    c = __builtin_fma(c, z, GW_COSPI_C6);
+    const double s2 = r * p;
+    double c = GW_COSPI_C6;
     c = __builtin_fma(c, z, GW_COSPI_C5);
     c = __builtin_fma(c, z, GW_COSPI_C4);
     c = __builtin_fma(c, z, GW_COSPI_C3);
     c = __builtin_fma(c, z, GW_COSPI_C2);
     c = __builtin_fma(c, z, GW_COSPI_C1);
     c = __builtin_fma(c, z, GW_COSPI_C0);
-    c = __builtin_fma(z, c, 1.0);
-    const double m = -2.0 * s;
-    re = __builtin_fma(m, s, 1.0);
-    im = m * c;
+    const double c2 = __builtin_fma(z, c, -GW_SQRT2);
+    re = __builtin_fma(-s2, s2, 1.0);
+    im = s2 * c2;
 }
 
 // TaylorF2 coefficients phi[k], phi_log[k] (k = 0..7) at symmetric mass ratio eta.
