@@ -7,7 +7,8 @@
  *
  *     lnL(theta) = -(2/T) sum_det sum_bins |d - h(theta)|^2 / S,   T = 1/delta_f,
  *
- * without the theta-independent factor prod (2 pi S)^-1 of that equation.
+ * without the theta-independent factor prod (2 pi S)^-1 of that equation
+ * (GW_FLAG_ADD_NORM adds its logarithm).
  * h is the response of each detector to a non-spinning TaylorF2 inspiral
  * (Sec. II: Newtonian amplitude, 3.5PN phase), projected with the detector's
  * antenna pattern and shifted by exp(-2 pi i f dt_det), the time translation
@@ -15,7 +16,7 @@
  *
  * Conventions
  *  - Frequency bins: f_k = f_low + k * delta_f, k = 0 .. n_bins-1.  Every bin
- *    is evaluated (no upper cut-off).
+ *    is evaluated (no upper cut-off) unless GW_FLAG_TERM_ISCO is given.
  *  - Complex arrays are interleaved (re, im) double pairs, the layout of
  *    torch.complex128 / numpy complex128.
  *  - theta is row-major [n_samples][n_param], n_param 5 or 9, columns
@@ -100,7 +101,26 @@ enum {
 
 enum {
     GW_PREC_FP64 = 0,      /* every step in FP64 */
-    GW_PREC_MIXED = 1      /* FP64 phase and final sums, FP32 phasors and tile sums */
+    GW_PREC_MIXED = 1      /* FP64 phase, reduction and sums; FP32 hardware phasor */
+};
+
+/* Options of the likelihood and waveform calls (bitwise or). */
+enum {
+    /* Accumulate the literal residual sum of Eq. (cbclike),
+     * sum_det sum_k |d - h|^2 / S, for every (sample, bin, detector), instead of
+     * the default split form -<d,d>/2 + sum_det [Re <d,h> - <h,h>/2] (an exact
+     * identity that needs no per-bin template magnitude).  Same value up to
+     * rounding; slower.  Likelihood calls only. */
+    GW_FLAG_DIRECT = 1u,
+    /* End every template at the gravitational-wave frequency of the
+     * Schwarzschild innermost stable circular orbit of its total mass M,
+     * f_isco = c^3 / (6^(3/2) pi G M): h = 0 on bins with f_k > f_isco.
+     * The paper prints no cut-off (Sec. II names TaylorF2 only); this is the
+     * usual end of an inspiral template.  Likelihood and waveform calls. */
+    GW_FLAG_TERM_ISCO = 2u,
+    /* Add the logarithm of the prefactor prod 1/(2 pi S) of Eq. (cbclike),
+     * -sum_det sum_k ln(2 pi S_det,k), to every lnL.  Likelihood calls only. */
+    GW_FLAG_ADD_NORM = 4u
 };
 
 /* Create a workspace bound to HIP device `device` (the current device when
@@ -140,10 +160,11 @@ int gw_workspace_kernel_time(gw_workspace *ws, double *total_ms, int64_t *launch
  *   h_out     device [n_samples][max(n_det,2 if n_det==0)][n_bins] complex:
  *             the detector responses h_det, or (h_plus, h_cross) when n_det == 0.
  *             Rows of out-of-domain or non-finite samples are NaN.
+ *   flags     0 or GW_FLAG_TERM_ISCO; any other bit is GW_EINVAL.
  */
 int gw_waveform_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_detector *dets,
                       const double *theta, int n_param, int64_t n_samples,
-                      gw_c128 *h_out, hipStream_t stream);
+                      gw_c128 *h_out, unsigned flags, hipStream_t stream);
 
 /*
  * gw_lnl_batch -- Eq. (cbclike) for every sample of one event.
@@ -154,7 +175,8 @@ int gw_waveform_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw
  *   theta     device [n_samples][n_param].
  *   lnl_out   device [n_samples] doubles.
  *   precision GW_PREC_FP64 or GW_PREC_MIXED.
- *   flags     must be 0 (reserved).
+ *   flags     any combination of GW_FLAG_DIRECT, GW_FLAG_TERM_ISCO and
+ *             GW_FLAG_ADD_NORM; any other bit is GW_EINVAL.
  */
 int gw_lnl_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_detector *dets,
                  const gw_c128 *data, const double *psd,
@@ -186,6 +208,7 @@ typedef struct {
  *   theta_packed    device [sum n_samples][n_param]; event e uses rows
  *                   theta_offset_e .. theta_offset_e + n_samples_e - 1.
  *   lnl_out_packed  device, one double per row of theta_packed that an event uses.
+ *   precision, flags  as for gw_lnl_batch, applied to every event.
  */
 int gw_lnl_ragged(gw_workspace *ws, int n_events, const gw_event *events,
                   const gw_c128 *data_packed, const double *psd_packed,
@@ -215,9 +238,10 @@ int gw_ragged_tuning(const gw_workspace *ws, int *tile_bins, int64_t *chunk_bins
 
 /* Philox4x32-10 (Salmon et al., SC 2011) block `i` of counter
  * (i mod 2^32, i div 2^32, step, stream_id) and key (seed mod 2^32, seed div 2^32),
- * for i < n_blocks: out (device) [n_blocks][4]. */
-int gw_philox_raw(uint64_t seed, uint32_t stream_id, uint32_t step, int64_t n_blocks, uint32_t *out,
-                  hipStream_t stream);
+ * for i = first .. first + n_blocks - 1 (mod 2^64): out (device) [n_blocks][4],
+ * row j holding block first + j. */
+int gw_philox_raw(uint64_t seed, uint32_t stream_id, uint32_t step, uint64_t first, int64_t n_blocks,
+                  uint32_t *out, hipStream_t stream);
 
 /* out (device) [n]: kind 0 uniforms in (0,1) (53 random bits; numbers 2i and
  * 2i+1 from block i), kind 1 standard normals (Box-Muller of that pair). */

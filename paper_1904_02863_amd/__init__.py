@@ -24,6 +24,10 @@ LIB_PATH = os.path.join(_HERE, "libgwlnl.so")
 GW_OK, GW_EINVAL, GW_ENOMEM, GW_EDEVICE, GW_EUNSUPPORTED = 0, -1, -2, -3, -4
 PRECISIONS = {"fp64": 0, "mixed": 1}
 MAX_DET = 8
+# Options of the likelihood and waveform calls (GW_FLAG_* of include/gwlnl.h).
+FLAG_DIRECT = 1
+FLAG_TERM_ISCO = 2
+FLAG_ADD_NORM = 4
 
 # Every symbol include/gwlnl.h declares.
 EXPORTED = ("gw_workspace_create", "gw_workspace_destroy", "gw_workspace_reserve", "gw_workspace_bytes",
@@ -73,13 +77,13 @@ def load_library() -> ctypes.CDLL:
         lib.gw_workspace_set_timing.argtypes = [vp, i32]
         lib.gw_workspace_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         lib.gw_waveform_batch.argtypes = [vp, ctypes.POINTER(GwGrid), i32, ctypes.POINTER(GwDetector), vp, i32, i64,
-                                          vp, vp]
+                                          vp, u32, vp]
         lib.gw_lnl_batch.argtypes = [vp, ctypes.POINTER(GwGrid), i32, ctypes.POINTER(GwDetector), vp, vp, vp, i32,
                                      i64, vp, i32, u32, vp]
         lib.gw_lnl_ragged.argtypes = [vp, i32, ctypes.POINTER(GwEvent), vp, vp, vp, i32, vp, i32, u32, vp]
         lib.gw_ragged_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         u64, u32p = ctypes.c_uint64, ctypes.c_uint32
-        lib.gw_philox_raw.argtypes = [u64, u32p, u32p, i64, vp, vp]
+        lib.gw_philox_raw.argtypes = [u64, u32p, u32p, u64, i64, vp, vp]
         lib.gw_philox_fill.argtypes = [u64, u32p, u32p, i32, i64, vp, vp]
         lib.gw_philox_chain_normals.argtypes = [i32, i64, u64, u32p, u32p, vp, vp]
         lib.gw_mcmc_to_theta.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp]
@@ -213,12 +217,13 @@ def _stream_ptr(device: int, stream=None) -> ctypes.c_void_p:
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def lnl_batch(grid, tensors, vertices, data, psd, theta, *, precision: str = "fp64", out=None,
+def lnl_batch(grid, tensors, vertices, data, psd, theta, *, precision: str = "fp64", flags: int = 0, out=None,
               workspace: Workspace | None = None, stream=None):
     """lnL for every row of theta (Eq. (cbclike) without its constant factor).
 
     data: complex128 [n_det, M]; psd: float64 [n_det, M]; theta: float64 [S, 5 or 9],
-    all on the same GPU.  Returns (or fills `out`) float64 [S] on that GPU.
+    all on the same GPU.  flags: FLAG_DIRECT | FLAG_TERM_ISCO | FLAG_ADD_NORM.
+    Returns (or fills `out`) float64 [S] on that GPU.
     """
     torch = _torch()
     g = make_grid(grid)
@@ -239,13 +244,14 @@ def lnl_batch(grid, tensors, vertices, data, psd, theta, *, precision: str = "fp
     ws = workspace or default_workspace(dev)
     _check(load_library().gw_lnl_batch(ws.handle, ctypes.byref(g), n_det, dets, data.data_ptr(), psd.data_ptr(),
                                        theta.data_ptr(), n_param, n_samples, out.data_ptr(),
-                                       PRECISIONS[precision], 0, _stream_ptr(dev, stream)))
+                                       PRECISIONS[precision], int(flags), _stream_ptr(dev, stream)))
     return out
 
 
-def waveform_batch(grid, tensors, vertices, theta, *, out=None, workspace: Workspace | None = None, stream=None):
+def waveform_batch(grid, tensors, vertices, theta, *, flags: int = 0, out=None, workspace: Workspace | None = None,
+                   stream=None):
     """Detector responses [S, n_det, M] (complex128); with tensors None the
-    polarisations [S, 2, M] (h_plus, h_cross)."""
+    polarisations [S, 2, M] (h_plus, h_cross).  flags: 0 or FLAG_TERM_ISCO."""
     torch = _torch()
     g = make_grid(grid)
     theta = _cuda_tensor(theta, torch.float64, "theta")
@@ -263,7 +269,7 @@ def waveform_batch(grid, tensors, vertices, theta, *, out=None, workspace: Works
     out = _cuda_tensor(out, torch.complex128, "out", (n_samples, n_out, g.n_bins))
     ws = workspace or default_workspace(dev)
     _check(load_library().gw_waveform_batch(ws.handle, ctypes.byref(g), n_det, dets, theta.data_ptr(), n_param,
-                                            n_samples, out.data_ptr(), _stream_ptr(dev, stream)))
+                                            n_samples, out.data_ptr(), int(flags), _stream_ptr(dev, stream)))
     return out
 
 
@@ -288,10 +294,10 @@ def make_events(grids: Sequence, tensors: Sequence, vertices: Sequence, n_sample
     return events, doff, toff
 
 
-def lnl_ragged(events, n_events: int, data_packed, psd_packed, theta_packed, *, precision: str = "fp64", out=None,
-               workspace: Workspace | None = None, stream=None):
+def lnl_ragged(events, n_events: int, data_packed, psd_packed, theta_packed, *, precision: str = "fp64",
+               flags: int = 0, out=None, workspace: Workspace | None = None, stream=None):
     """lnL of many events of different durations, each with its own rows of
-    theta_packed (see gw_lnl_ragged)."""
+    theta_packed (see gw_lnl_ragged); flags as for lnl_batch."""
     torch = _torch()
     theta_packed = _cuda_tensor(theta_packed, torch.float64, "theta_packed")
     data_packed = _cuda_tensor(data_packed, torch.complex128, "data_packed")
@@ -310,7 +316,7 @@ def lnl_ragged(events, n_events: int, data_packed, psd_packed, theta_packed, *, 
     ws = workspace or default_workspace(dev)
     _check(load_library().gw_lnl_ragged(ws.handle, int(n_events), events, data_packed.data_ptr(),
                                         psd_packed.data_ptr(), theta_packed.data_ptr(), n_param, out.data_ptr(),
-                                        PRECISIONS[precision], 0, _stream_ptr(dev, stream)))
+                                        PRECISIONS[precision], int(flags), _stream_ptr(dev, stream)))
     return out
 
 
@@ -323,12 +329,13 @@ def _ptr_or_null(t):
     return None if t is None else t.data_ptr()
 
 
-def philox_raw(seed: int, stream_id: int, step: int, n_blocks: int, device=0, stream=None):
-    """Philox4x32-10 blocks as a numpy uint32 array [n_blocks, 4] (computed on the GPU)."""
+def philox_raw(seed: int, stream_id: int, step: int, n_blocks: int, first: int = 0, device=0, stream=None):
+    """Philox4x32-10 blocks first .. first + n_blocks - 1 as a numpy uint32
+    array [n_blocks, 4] (computed on the GPU)."""
     torch = _torch()
     out = torch.empty((int(n_blocks), 4), dtype=torch.int32, device=torch.device("cuda", device))
-    _check(load_library().gw_philox_raw(int(seed), int(stream_id), int(step), int(n_blocks), out.data_ptr(),
-                                        _stream_ptr(device, stream)))
+    _check(load_library().gw_philox_raw(int(seed), int(stream_id), int(step), int(first) % 2 ** 64, int(n_blocks),
+                                        out.data_ptr(), _stream_ptr(device, stream)))
     return out.cpu().numpy().view(np.uint32)
 
 

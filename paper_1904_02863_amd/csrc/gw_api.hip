@@ -19,7 +19,8 @@
 struct gw_workspace {
     int device = 0;
     int n_cu = 0;
-    int blocks_per_cu[2][gw::kMaxDet + 1] = {};  // tile-kernel occupancy by precision and detector count (0 = unknown)
+    // tile-kernel occupancy by form, precision and detector count (0 = unknown)
+    int blocks_per_cu[gw::kForms][2][gw::kMaxDet + 1] = {};
     void *base = nullptr;
     size_t capacity = 0;
     bool timing = false;
@@ -69,6 +70,7 @@ struct DeviceGuard {
 };
 
 constexpr size_t kAlign = 256;
+constexpr unsigned kLnlFlags = GW_FLAG_DIRECT | GW_FLAG_TERM_ISCO | GW_FLAG_ADD_NORM;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -145,21 +147,21 @@ int check_dets(int n_det, const gw_detector *dets, int n_param, gw::DetGeom *geo
 #define GW_TILE_LDS_BUDGET (40 * 1024)
 #endif
 
-int tile_bins_for(int n_det)
+int tile_bins_for(int n_det, int form)
 {
     const size_t budget = GW_TILE_LDS_BUDGET;   // bytes of LDS per block: several blocks per CU fit in 160 KB
     int t = 2048;
-    while (t > 64 && gw::lnl_tile_lds_bytes(n_det, t) > budget) t /= 2;
+    while (t > 64 && gw::lnl_tile_lds_bytes(n_det, t, form) > budget) t /= 2;
     return t;
 }
 
-gw::TilePlan plan_tiles(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples, bool mixed)
+gw::TilePlan plan_tiles(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples, bool mixed, int form)
 {
     gw::TilePlan p;
-    p.tile_bins = tile_bins_for(n_det);
+    p.tile_bins = tile_bins_for(n_det, form);
     p.n_groups = (int)((n_samples + gw::kBlock - 1) / gw::kBlock);
-    int &occ = ws->blocks_per_cu[mixed ? 1 : 0][n_det];
-    if (occ == 0) occ = gw::lnl_tile_blocks_per_cu(n_det, p.tile_bins, mixed);
+    int &occ = ws->blocks_per_cu[form][mixed ? 1 : 0][n_det];
+    if (occ == 0) occ = gw::lnl_tile_blocks_per_cu(n_det, p.tile_bins, mixed, form);
     const int64_t target = (int64_t)ws->n_cu * occ;
     int64_t chunks = (target + p.n_groups - 1) / p.n_groups;
     const int64_t max_chunks = std::max<int64_t>(1, n_bins / 64);     // at least 64 bins per chunk
@@ -169,21 +171,28 @@ gw::TilePlan plan_tiles(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_s
     return p;
 }
 
+// Workspace sections of one event.  The direct-form tables and the prefix
+// sums are carved only when the call's flags use them.
 struct LnlLayout {
-    size_t tab1, tab2, dcoef, prep_partials, event_sums, records, partials, total;
+    size_t tab1, tab2, dcoef, edir, vdir, qprefix, prep_partials, event_sums, k_limit, records, partials, total;
     int prep_blocks;
 };
 
-LnlLayout lnl_layout(int64_t n_bins, int n_det, int64_t n_samples, const gw::TilePlan &plan)
+LnlLayout lnl_layout(int64_t n_bins, int n_det, int64_t n_samples, const gw::TilePlan &plan, unsigned flags)
 {
     LnlLayout l;
     Carver c;
-    l.prep_blocks = (int)std::min<int64_t>(1024, (n_bins + gw::kBlock - 1) / gw::kBlock);
+    const bool direct = (flags & GW_FLAG_DIRECT) != 0, isco = (flags & GW_FLAG_TERM_ISCO) != 0;
+    l.prep_blocks = (int)((n_bins + gw::kBlock - 1) / gw::kBlock);
     l.tab1 = c.take(sizeof(gw::Tab1) * n_bins);
     l.tab2 = c.take(sizeof(gw::Tab2) * n_bins);
     l.dcoef = c.take(sizeof(double2) * n_bins * n_det);
-    l.prep_partials = c.take(sizeof(double) * 2 * n_det * l.prep_blocks);
-    l.event_sums = c.take(sizeof(double) * (1 + gw::kMaxDet));
+    l.edir = direct ? c.take(sizeof(double2) * n_bins * n_det) : 0;
+    l.vdir = direct ? c.take(sizeof(double) * n_bins * n_det) : 0;
+    l.qprefix = isco ? c.take(sizeof(double) * n_bins * n_det) : 0;
+    l.prep_partials = c.take(sizeof(double) * gw::kPrepPerDet * n_det * l.prep_blocks);
+    l.event_sums = c.take(sizeof(double) * gw::kEventSums);
+    l.k_limit = c.take(sizeof(int64_t));
     l.records = c.take(sizeof(double) * gw::record_fields(n_det) * std::max<int64_t>(n_samples, 1));
     l.partials = c.take(sizeof(double2) * (size_t)plan.n_chunks * n_samples * n_det);
     l.total = c.offset;
@@ -208,25 +217,36 @@ int check_common(gw_workspace *ws, const gw_grid *grid, int n_det_min, int n_det
 
 int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::DetGeom &geom, const gw_c128 *data,
                   const double *psd, const double *theta, int n_param, int64_t n_samples, double *lnl_out,
-                  bool mixed, hipStream_t stream)
+                  bool mixed, unsigned flags, hipStream_t stream)
 {
     drop_ragged_graph(ws);               // the arena is about to be laid out for one event
-    const gw::TilePlan plan = plan_tiles(ws, grid.n_bins, n_det, n_samples, mixed);
-    const LnlLayout l = lnl_layout(grid.n_bins, n_det, n_samples, plan);
+    const int form = gw::tile_form(flags);
+    const bool isco = (flags & GW_FLAG_TERM_ISCO) != 0;
+    const gw::TilePlan plan = plan_tiles(ws, grid.n_bins, n_det, n_samples, mixed, form);
+    const LnlLayout l = lnl_layout(grid.n_bins, n_det, n_samples, plan, flags);
     if (int rc = ensure_capacity(ws, l.total)) return rc;
-    auto *tab1 = at<gw::Tab1>(ws, l.tab1);
-    auto *tab2 = at<gw::Tab2>(ws, l.tab2);
-    auto *dcoef = at<double2>(ws, l.dcoef);
-    auto *prep = at<double>(ws, l.prep_partials);
-    auto *sums = at<double>(ws, l.event_sums);
+    gw::EventBuffers eb;
+    eb.tab1 = at<gw::Tab1>(ws, l.tab1);
+    eb.tab2 = at<gw::Tab2>(ws, l.tab2);
+    eb.dcoef = at<double2>(ws, l.dcoef);
+    eb.edir = l.edir ? at<double2>(ws, l.edir) : nullptr;
+    eb.vdir = l.vdir ? at<double>(ws, l.vdir) : nullptr;
+    eb.qprefix = l.qprefix ? at<double>(ws, l.qprefix) : nullptr;
+    eb.prep = at<double>(ws, l.prep_partials);
+    eb.prep_blocks = l.prep_blocks;
+    eb.sums = at<double>(ws, l.event_sums);
+    eb.k_limit = at<int64_t>(ws, l.k_limit);
     auto *rec = at<double>(ws, l.records);
     auto *part = at<double2>(ws, l.partials);
     hipError_t e;
-    if ((e = gw::launch_event_tables(grid, tab1, tab2, stream)) != hipSuccess) return hip_fail(e, "event tables");
-    if ((e = gw::launch_event_data(grid, n_det, data, psd, tab2, dcoef, prep, l.prep_blocks, sums, stream)) != hipSuccess)
+    if ((e = gw::launch_event_tables(grid, eb.tab1, eb.tab2, stream)) != hipSuccess) return hip_fail(e, "event tables");
+    if ((e = gw::launch_event_data(grid, n_det, data, psd, eb, flags, stream)) != hipSuccess)
         return hip_fail(e, "event data");
-    if ((e = gw::launch_sample_prep(n_samples, n_param, n_det, false, geom, theta, rec, stream)) != hipSuccess)
+    if ((e = gw::launch_sample_prep(grid, n_samples, n_param, n_det, false, isco, geom, theta, rec, stream)) !=
+        hipSuccess)
         return hip_fail(e, "sample prep");
+    if (form == gw::kFormSplitIsco && (e = gw::launch_isco_limit(n_samples, rec, eb.k_limit, stream)) != hipSuccess)
+        return hip_fail(e, "template-end limit");
     hipEvent_t stop_event = nullptr;
     if (ws->timing) {
         if ((size_t)(2 * ws->timed + 2) > ws->events.size()) {
@@ -239,13 +259,14 @@ int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::De
         if ((e = hipEventRecord(ws->events[2 * ws->timed], stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         stop_event = ws->events[2 * ws->timed + 1];
     }
-    if ((e = gw::launch_lnl_tiles(grid, n_det, n_samples, plan, mixed, tab1, dcoef, rec, part, stream)) != hipSuccess)
+    if ((e = gw::launch_lnl_tiles(grid, n_det, n_samples, plan, mixed, form, eb, rec, part, stream)) != hipSuccess)
         return hip_fail(e, "lnl tiles");
     if (stop_event) {
         if ((e = hipEventRecord(stop_event, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         ++ws->timed;
     }
-    if ((e = gw::launch_lnl_finalize(n_samples, n_det, plan, part, rec, sums, lnl_out, stream)) != hipSuccess)
+    if ((e = gw::launch_lnl_finalize(grid, n_samples, n_det, plan, part, rec, eb, flags, lnl_out, stream)) !=
+        hipSuccess)
         return hip_fail(e, "lnl finalize");
     return GW_OK;
 }
@@ -273,9 +294,11 @@ int64_t ragged_pairs(int n_events, const gw_event *events)
 // Lays out the workspace for a ragged pass with the given tile shape and
 // fills the host arrays; device pointers are relative to `base`.
 RaggedPlan ragged_plan(gw_workspace *ws, int n_events, const gw_event *events, const gw_c128 *data,
-                       const double *psd, const double *theta, int n_param, double *lnl, bool mixed, int tile_bins,
-                       int64_t chunk_bins, char *base)
+                       const double *psd, const double *theta, int n_param, double *lnl, bool mixed, unsigned flags,
+                       int tile_bins, int64_t chunk_bins, char *base)
 {
+    const bool direct = (flags & GW_FLAG_DIRECT) != 0, isco = (flags & GW_FLAG_TERM_ISCO) != 0;
+    const int form = gw::tile_form(flags);
     RaggedPlan p;
     Carver c;
     p.events.resize(n_events);
@@ -301,11 +324,15 @@ RaggedPlan ragged_plan(gw_workspace *ws, int n_events, const gw_event *events, c
         re.tab1 = reinterpret_cast<gw::Tab1 *>(base + c.take(sizeof(gw::Tab1) * m));
         re.tab2 = reinterpret_cast<gw::Tab2 *>(base + c.take(sizeof(gw::Tab2) * m));
         re.dcoef = reinterpret_cast<double2 *>(base + c.take(sizeof(double2) * m * ev.n_det));
+        re.edir = direct ? reinterpret_cast<double2 *>(base + c.take(sizeof(double2) * m * ev.n_det)) : nullptr;
+        re.vdir = direct ? reinterpret_cast<double *>(base + c.take(sizeof(double) * m * ev.n_det)) : nullptr;
+        re.qprefix = isco ? reinterpret_cast<double *>(base + c.take(sizeof(double) * m * ev.n_det)) : nullptr;
         re.rec = reinterpret_cast<double *>(base + c.take(sizeof(double) * gw::record_fields(ev.n_det) *
                                                            std::max<int64_t>(s, 1)));
         re.partials = reinterpret_cast<double2 *>(base + c.take(sizeof(double2) * re.n_chunks * s * ev.n_det));
-        re.prep = reinterpret_cast<double *>(base + c.take(sizeof(double) * 2 * ev.n_det * re.prep_blocks));
-        re.sums = reinterpret_cast<double *>(base + c.take(sizeof(double) * (1 + gw::kMaxDet)));
+        re.prep = reinterpret_cast<double *>(base + c.take(sizeof(double) * gw::kPrepPerDet * ev.n_det *
+                                                            re.prep_blocks));
+        re.sums = reinterpret_cast<double *>(base + c.take(sizeof(double) * gw::kEventSums));
         for (int b = 0; b < re.prep_blocks; ++b) p.block_map.push_back(make_int2(e, b));
         const int n_groups = (int)((s + gw::kBlock - 1) / gw::kBlock);
         for (int gi = 0; gi < n_groups; ++gi) {
@@ -326,6 +353,7 @@ RaggedPlan ragged_plan(gw_workspace *ws, int n_events, const gw_event *events, c
     L.n_param = n_param;
     L.tile_bins = tile_bins;
     L.mixed = mixed;
+    L.flags = flags;
     L.n_classes = 0;
     for (int d = 1; d <= gw::kMaxDet; ++d) {
         auto &v = by_det[d];
@@ -337,7 +365,7 @@ RaggedPlan ragged_plan(gw_workspace *ws, int n_events, const gw_event *events, c
         gw::RaggedClass &rc = L.classes[L.n_classes++];
         rc.n_det = d;
         rc.n_items = (int)v.size();
-        const int occ = gw::lnl_ragged_blocks_per_cu(d, tile_bins, mixed);
+        const int occ = gw::lnl_ragged_blocks_per_cu(d, tile_bins, mixed, form);
         rc.grid = (int)std::min<int64_t>((int64_t)ws->n_cu * occ, (int64_t)v.size());
         p.class_begin.push_back((int)p.items.size());
         p.items.insert(p.items.end(), v.begin(), v.end());
@@ -366,14 +394,15 @@ RaggedPlan ragged_plan(gw_workspace *ws, int n_events, const gw_event *events, c
 // in use by earlier work there).
 int ragged_materialise(gw_workspace *ws, int n_events, const gw_event *events, const std::vector<gw::DetGeom> &geoms,
                        const gw_c128 *data, const double *psd, const double *theta, int n_param, double *lnl,
-                       bool mixed, int tile_bins, int64_t chunk_bins, hipStream_t stream, RaggedPlan *out)
+                       bool mixed, unsigned flags, int tile_bins, int64_t chunk_bins, hipStream_t stream,
+                       RaggedPlan *out)
 {
     hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    RaggedPlan sizing = ragged_plan(ws, n_events, events, data, psd, theta, n_param, lnl, mixed, tile_bins,
+    RaggedPlan sizing = ragged_plan(ws, n_events, events, data, psd, theta, n_param, lnl, mixed, flags, tile_bins,
                                     chunk_bins, nullptr);
     if (int rc = ensure_capacity(ws, sizing.total)) return rc;
-    *out = ragged_plan(ws, n_events, events, data, psd, theta, n_param, lnl, mixed, tile_bins, chunk_bins,
+    *out = ragged_plan(ws, n_events, events, data, psd, theta, n_param, lnl, mixed, flags, tile_bins, chunk_bins,
                        static_cast<char *>(ws->base));
     char *base = static_cast<char *>(ws->base);
     struct Copy { size_t off; const void *src; size_t bytes; };
@@ -419,18 +448,18 @@ int time_ragged(gw_workspace *ws, const RaggedPlan &p, float *ms)
     return rc;
 }
 
-// Key of a ragged call: its events, pointers and precision.
+// Key of a ragged call: its events, pointers, precision and flags.
 std::vector<unsigned char> ragged_key(int n_events, const gw_event *events, const void *data, const void *psd,
-                                      const void *theta, int n_param, const void *lnl, bool mixed)
+                                      const void *theta, int n_param, const void *lnl, bool mixed, unsigned flags)
 {
-    std::vector<unsigned char> k(sizeof(gw_event) * n_events + 4 * sizeof(void *) + 2 * sizeof(int));
+    std::vector<unsigned char> k(sizeof(gw_event) * n_events + 4 * sizeof(void *) + 3 * sizeof(int));
     unsigned char *w = k.data();
     if (n_events) std::memcpy(w, events, sizeof(gw_event) * n_events);
     w += sizeof(gw_event) * n_events;
     const void *ptrs[4] = {data, psd, theta, lnl};
     std::memcpy(w, ptrs, sizeof(ptrs));
     w += sizeof(ptrs);
-    const int tail[2] = {n_param, mixed ? 1 : 0};
+    const int tail[3] = {n_param, mixed ? 1 : 0, (int)flags};
     std::memcpy(w, tail, sizeof(tail));
     return k;
 }
@@ -441,8 +470,9 @@ const int64_t kTuneChunks[] = {4096, 8192, 16384, 32768};
 
 int ragged_run(gw_workspace *ws, int n_events, const gw_event *events, const std::vector<gw::DetGeom> &geoms,
                const gw_c128 *data, const double *psd, const double *theta, int n_param, double *lnl, bool mixed,
-               hipStream_t stream)
+               unsigned flags, hipStream_t stream)
 {
+    const int form = gw::tile_form(flags);
     int n_active = 0, max_det = 1;
     for (int i = 0; i < n_events; ++i) {
         if (events[i].n_samples > 0) ++n_active;
@@ -459,7 +489,7 @@ int ragged_run(gw_workspace *ws, int n_events, const gw_event *events, const std
     const int na = (int)active.size();
     const gw_event *ev = active.data();
 
-    std::vector<unsigned char> key = ragged_key(na, ev, data, psd, theta, n_param, lnl, mixed);
+    std::vector<unsigned char> key = ragged_key(na, ev, data, psd, theta, n_param, lnl, mixed, flags);
     if (ws->ragged_exec && key == ws->ragged_key) {
         hipError_t e = hipGraphLaunch(ws->ragged_exec, stream);
         return e == hipSuccess ? GW_OK : hip_fail(e, "hipGraphLaunch");
@@ -470,10 +500,10 @@ int ragged_run(gw_workspace *ws, int n_events, const gw_event *events, const std
     hipError_t se = hipStreamSynchronize(stream);
     if (se != hipSuccess) return hip_fail(se, "hipStreamSynchronize");
 
-    // tile shape: autotuned once per (detectors, precision, size bucket)
+    // tile shape: autotuned once per (detectors, precision and form, size bucket)
     const int64_t pairs = ragged_pairs(na, ev);
     const int bucket = pairs > 0 ? (int)std::floor(std::log2((double)pairs)) : 0;
-    const auto tkey = std::make_tuple(max_det, mixed ? 1 : 0, bucket);
+    const auto tkey = std::make_tuple(max_det, (mixed ? 1 : 0) + 2 * form, bucket);
     auto it = ws->ragged_tuning.find(tkey);
     int tile_bins = 0;
     int64_t chunk_bins = 0;
@@ -481,10 +511,10 @@ int ragged_run(gw_workspace *ws, int n_events, const gw_event *events, const std
     if (it == ws->ragged_tuning.end()) {
         float best = 0.0f;
         for (int tb : kTuneTiles) {
-            if (gw::lnl_tile_lds_bytes(max_det, tb) > 64 * 1024) continue;
+            if (gw::lnl_tile_lds_bytes(max_det, tb, form) > 64 * 1024) continue;
             for (int64_t cb : kTuneChunks) {
-                if (int rc = ragged_materialise(ws, na, ev, active_geoms, data, psd, theta, n_param, lnl, mixed, tb,
-                                                cb, ws->capture_stream, &plan))
+                if (int rc = ragged_materialise(ws, na, ev, active_geoms, data, psd, theta, n_param, lnl, mixed, flags,
+                                                tb, cb, ws->capture_stream, &plan))
                     return rc;
                 float ms = 0.0f;
                 if (int rc = time_ragged(ws, plan, &ms)) return rc;
@@ -502,8 +532,8 @@ int ragged_run(gw_workspace *ws, int n_events, const gw_event *events, const std
     }
     ws->last_tile_bins = tile_bins;
     ws->last_chunk_bins = chunk_bins;
-    if (int rc = ragged_materialise(ws, na, ev, active_geoms, data, psd, theta, n_param, lnl, mixed, tile_bins,
-                                    chunk_bins, stream, &plan))
+    if (int rc = ragged_materialise(ws, na, ev, active_geoms, data, psd, theta, n_param, lnl, mixed, flags,
+                                    tile_bins, chunk_bins, stream, &plan))
         return rc;
     hipError_t e = hipStreamSynchronize(ws->capture_stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -619,10 +649,14 @@ int gw_workspace_reserve(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_
     if (n_bins < 1 || n_det < 1 || n_det > gw::kMaxDet || n_samples < 0) return fail(GW_EINVAL, "bad reserve sizes");
     DeviceGuard g(ws->device);
     if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
-    gw::TilePlan plan = plan_tiles(ws, n_bins, n_det, n_samples, false);
-    const gw::TilePlan plan_mixed = plan_tiles(ws, n_bins, n_det, n_samples, true);
-    if (plan_mixed.n_chunks > plan.n_chunks) plan = plan_mixed;
-    const LnlLayout l = lnl_layout(n_bins, n_det, n_samples, plan);
+    gw::TilePlan plan = plan_tiles(ws, n_bins, n_det, n_samples, false, gw::kFormSplit);
+    for (int form = 0; form < gw::kForms; ++form)
+        for (int mixed = 0; mixed < 2; ++mixed) {
+            const gw::TilePlan p = plan_tiles(ws, n_bins, n_det, n_samples, mixed != 0, form);
+            if (p.n_chunks > plan.n_chunks) plan = p;
+        }
+    const LnlLayout l = lnl_layout(n_bins, n_det, n_samples, plan,
+                                   GW_FLAG_DIRECT | GW_FLAG_TERM_ISCO | GW_FLAG_ADD_NORM);
     size_t wave = align_up(sizeof(gw::Tab1) * n_bins) + align_up(sizeof(gw::Tab2) * n_bins) +
                   align_up(sizeof(double) * gw::record_fields(std::max(n_det, 2)) * std::max<int64_t>(n_samples, 1));
     return ensure_capacity(ws, std::max(l.total, wave));
@@ -638,21 +672,23 @@ int gw_lnl_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_dete
     if (!data || !psd) return fail(GW_EINVAL, "data or psd is NULL");
     if (n_samples > 0 && (!theta || !lnl_out)) return fail(GW_EINVAL, "theta or lnl_out is NULL");
     if (precision != GW_PREC_FP64 && precision != GW_PREC_MIXED) return fail(GW_EINVAL, "unknown precision");
-    if (flags != 0) return fail(GW_EINVAL, "flags must be 0");
+    if (flags & ~kLnlFlags) return fail(GW_EINVAL, "unknown flag bits");
     gw::DetGeom geom;
     if (int rc = check_dets(n_det, dets, n_param, &geom)) return rc;
     if (n_samples == 0) return GW_OK;
     DeviceGuard g(ws->device);
     if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
     return lnl_one_event(ws, *grid, n_det, geom, data, psd, theta, n_param, n_samples, lnl_out,
-                         precision == GW_PREC_MIXED, stream);
+                         precision == GW_PREC_MIXED, flags, stream);
 }
 
 int gw_waveform_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_detector *dets,
-                      const double *theta, int n_param, int64_t n_samples, gw_c128 *h_out, hipStream_t stream)
+                      const double *theta, int n_param, int64_t n_samples, gw_c128 *h_out, unsigned flags,
+                      hipStream_t stream)
 {
     if (int rc = check_common(ws, grid, 0, n_det, n_param, n_samples)) return rc;
     if (n_samples > 0 && (!theta || !h_out)) return fail(GW_EINVAL, "theta or h_out is NULL");
+    if (flags & ~(unsigned)GW_FLAG_TERM_ISCO) return fail(GW_EINVAL, "waveform flags: only GW_FLAG_TERM_ISCO");
     gw::DetGeom geom;
     if (n_det > 0) {
         if (int rc = check_dets(n_det, dets, n_param, &geom)) return rc;
@@ -675,7 +711,8 @@ int gw_waveform_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw
     auto *rec = at<double>(ws, orec);
     hipError_t e;
     if ((e = gw::launch_event_tables(*grid, tab1, tab2, stream)) != hipSuccess) return hip_fail(e, "event tables");
-    if ((e = gw::launch_sample_prep(n_samples, n_param, n_out, polar, geom, theta, rec, stream)) != hipSuccess)
+    if ((e = gw::launch_sample_prep(*grid, n_samples, n_param, n_out, polar, (flags & GW_FLAG_TERM_ISCO) != 0, geom,
+                                    theta, rec, stream)) != hipSuccess)
         return hip_fail(e, "sample prep");
     if ((e = gw::launch_waveform(*grid, n_out, n_samples, tab1, tab2, rec, h_out, stream)) != hipSuccess)
         return hip_fail(e, "waveform");
@@ -691,7 +728,7 @@ int gw_lnl_ragged(gw_workspace *ws, int n_events, const gw_event *events, const 
     if (n_events > 0 && !events) return fail(GW_EINVAL, "events is NULL");
     if (n_events > 0 && (!data_packed || !psd_packed)) return fail(GW_EINVAL, "data or psd is NULL");
     if (precision != GW_PREC_FP64 && precision != GW_PREC_MIXED) return fail(GW_EINVAL, "unknown precision");
-    if (flags != 0) return fail(GW_EINVAL, "flags must be 0");
+    if (flags & ~kLnlFlags) return fail(GW_EINVAL, "unknown flag bits");
     if (n_param != 5 && n_param != 9) return fail(GW_EINVAL, "n_param must be 5 or 9");
     std::vector<gw::DetGeom> geoms(n_events);
     for (int i = 0; i < n_events; ++i) {
@@ -705,7 +742,7 @@ int gw_lnl_ragged(gw_workspace *ws, int n_events, const gw_event *events, const 
     DeviceGuard g(ws->device);
     if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
     return ragged_run(ws, n_events, events, geoms, data_packed, psd_packed, theta_packed, n_param, lnl_out_packed,
-                      precision == GW_PREC_MIXED, stream);
+                      precision == GW_PREC_MIXED, flags, stream);
 }
 
 int gw_ragged_tuning(const gw_workspace *ws, int *tile_bins, int64_t *chunk_bins)

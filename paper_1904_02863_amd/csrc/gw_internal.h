@@ -23,10 +23,31 @@ constexpr int kMaxDet = GW_MAX_DET;
 enum RecordField : int {
     kRecC8 = 0, kRecC7, kRecC6, kRecC6L, kRecC5, kRecC5L, kRecC4, kRecC3, kRecC2, kRecC0,
     kRecStatus,                 // 0 evaluate, 1 out of domain (-inf), 2 non-finite (NaN)
+    kRecKcut,                   // last bin of the template: n_bins - 1, or below with the ISCO end (-1: none)
     kRecDet,                    // then per output channel d: P re, P im, delta (s)
     kRecFieldsPerDet = 3,
 };
 constexpr int record_fields(int n_out) { return kRecDet + kRecFieldsPerDet * n_out; }
+
+// Per-event sums: [0] <d,d> over all detectors, [1 + d] Q_d = 4 df sum a^2 / S_d,
+// [kSumNorm] sum over detectors and bins of ln(2 pi S).
+constexpr int kSumNorm = 1 + kMaxDet;
+constexpr int kEventSums = 2 + kMaxDet;
+// Per event-preparation block and detector: sums of |d|^2/S, a^2/S, ln(2 pi S)
+// over the block's 256 consecutive bins.
+constexpr int kPrepPerDet = 3;
+
+// What the tile kernel accumulates.
+enum TileForm : int {
+    kFormSplit = 0,       // Z_det = sum_k D_det,k e^{-i Phi_det,k} over every bin
+    kFormSplitIsco = 1,   // the same over each sample's bins k <= K_s (template end)
+    kFormDirect = 2,      // sum_det sum_k a_k^2/S |d/a - P e^{-i Phi}|^2, zero template above K_s
+};
+constexpr int kForms = 3;
+inline int tile_form(unsigned flags)
+{
+    return (flags & GW_FLAG_DIRECT) ? kFormDirect : (flags & GW_FLAG_TERM_ISCO) ? kFormSplitIsco : kFormSplit;
+}
 
 // Detector geometry passed by value to the sample-preparation kernel.
 struct DetGeom {
@@ -52,6 +73,9 @@ struct RaggedEvent {
     Tab1 *tab1;
     Tab2 *tab2;
     double2 *dcoef;
+    double2 *edir;        // direct form: d / a per detector and bin
+    double *vdir;         // direct form: a^2 / S per detector and bin
+    double *qprefix;      // ISCO end: prefix sums of a^2 / S per detector
     double *rec;
     double2 *partials;
     double *prep;
@@ -88,6 +112,7 @@ struct RaggedLaunch {
     int n_classes;
     int tile_bins;
     bool mixed;
+    unsigned flags;           // GW_FLAG_* of the call
 };
 
 // Launch plan of the tile kernel for one event.
@@ -106,32 +131,52 @@ struct EventSizes {
     int prep_blocks;
 };
 
+// Device buffers of one event's preparation (workspace sections).
+struct EventBuffers {
+    Tab1 *tab1;
+    Tab2 *tab2;
+    double2 *dcoef;       // [n_det][n_bins]
+    double2 *edir;        // [n_det][n_bins], direct form only
+    double *vdir;         // [n_det][n_bins], direct form only
+    double *qprefix;      // [n_det][n_bins], ISCO end only
+    double *prep;         // [prep_blocks][kPrepPerDet * n_det]
+    int prep_blocks;      // ceil(n_bins / kBlock)
+    double *sums;         // [kEventSums]
+    int64_t *k_limit;     // ISCO end: 1 + the largest K_s of the batch
+};
+
 // ---- launchers (gw_kernels.hip); all enqueue on `stream` and return the launch status ----
 hipError_t launch_event_tables(const gw_grid &grid, Tab1 *tab1, Tab2 *tab2, hipStream_t stream);
 
+// D, the event sums and, as `flags` ask, the direct-form tables and the
+// prefix sums of a^2/S.
 hipError_t launch_event_data(const gw_grid &grid, int n_det, const gw_c128 *data, const double *psd,
-                             const Tab2 *tab2, double2 *dcoef, double *prep_partials, int prep_blocks,
-                             double *event_sums, hipStream_t stream);
+                             const EventBuffers &eb, unsigned flags, hipStream_t stream);
 
-hipError_t launch_sample_prep(int64_t n_samples, int n_param, int n_out, bool polarisations, const DetGeom &geom,
-                              const double *theta, double *records, hipStream_t stream);
+// Per-sample records; with isco, K_s from the template end (else n_bins - 1).
+hipError_t launch_sample_prep(const gw_grid &grid, int64_t n_samples, int n_param, int n_out, bool polarisations,
+                              bool isco, const DetGeom &geom, const double *theta, double *records,
+                              hipStream_t stream);
+
+// *k_limit = 1 + max over samples of K_s (ISCO end).
+hipError_t launch_isco_limit(int64_t n_samples, const double *records, int64_t *k_limit, hipStream_t stream);
 
 hipError_t launch_lnl_tiles(const gw_grid &grid, int n_det, int64_t n_samples, const TilePlan &plan, bool mixed,
-                            const Tab1 *tab1, const double2 *dcoef, const double *records,
-                            double2 *partials, hipStream_t stream);
+                            int form, const EventBuffers &eb, const double *records, double2 *partials,
+                            hipStream_t stream);
 
-hipError_t launch_lnl_finalize(int64_t n_samples, int n_det, const TilePlan &plan, const double2 *partials,
-                               const double *records, const double *event_sums, double *lnl_out,
-                               hipStream_t stream);
+hipError_t launch_lnl_finalize(const gw_grid &grid, int64_t n_samples, int n_det, const TilePlan &plan,
+                               const double2 *partials, const double *records, const EventBuffers &eb,
+                               unsigned flags, double *lnl_out, hipStream_t stream);
 
 hipError_t launch_waveform(const gw_grid &grid, int n_out, int64_t n_samples, const Tab1 *tab1, const Tab2 *tab2,
                            const double *records, gw_c128 *h_out, hipStream_t stream);
 
 hipError_t launch_ragged(const RaggedLaunch &r, hipStream_t stream);
-int lnl_ragged_blocks_per_cu(int n_det, int tile_bins, bool mixed);
+int lnl_ragged_blocks_per_cu(int n_det, int tile_bins, bool mixed, int form);
 
 // LDS bytes of the tile kernel and its occupancy.
-size_t lnl_tile_lds_bytes(int n_det, int tile_bins);
-int lnl_tile_blocks_per_cu(int n_det, int tile_bins, bool mixed);
+size_t lnl_tile_lds_bytes(int n_det, int tile_bins, int form);
+int lnl_tile_blocks_per_cu(int n_det, int tile_bins, bool mixed, int form);
 
 }  // namespace gw

@@ -62,73 +62,136 @@ __device__ __forceinline__ void bin_tables(double f_low, double df, int64_t k, T
     tab2[k] = t2;
 }
 
-// D_det,k = 4 df a_k conj(d) / S for bin k, accumulating |d|^2/S and a^2/S.
-// A PSD value that is not positive and finite makes its weight NaN, which
-// turns <d,d> and hence every lnL of the event into NaN.
-__device__ __forceinline__ void bin_data(int64_t n_bins, int n_det, double df, int64_t k, double amp,
-                                         const double2 *__restrict__ data, const double *__restrict__ psd,
-                                         double2 *__restrict__ dcoef, double dd[kMaxDet], double qq[kMaxDet])
+// One event's device arrays as the preparation kernels see them.
+struct PrepView {
+    int64_t n_bins;
+    int n_det;
+    double df;
+    const double2 *data;
+    const double *psd;
+    const Tab2 *tab2;
+    double2 *dcoef;
+    double2 *edir;
+    double *vdir;
+};
+
+// Bin k of every detector: D = 4 df a conj(d) / S (split form) and, for the
+// direct form, d / a and a^2 / S; adds |d|^2/S, a^2/S and (with `norm`)
+// ln(2 pi S) to acc[3 d + 0, 1, 2].  A PSD value that is not positive and
+// finite makes its weight NaN, which turns <d,d> and hence every lnL of the
+// event into NaN.
+__device__ __forceinline__ void bin_data(const PrepView &v, int64_t k, bool direct, bool norm,
+                                         double acc[kPrepPerDet * kMaxDet])
 {
+    const double amp = v.tab2[k].amp;
 #pragma unroll
     for (int d = 0; d < kMaxDet; ++d) {
-        if (d < n_det) {
-            const double s = psd[(int64_t)d * n_bins + k];
+        if (d < v.n_det) {
+            const double s = v.psd[(int64_t)d * v.n_bins + k];
             const double w = (s > 0.0 && s < INFINITY) ? 1.0 / s : NAN;
-            const double2 v = data[(int64_t)d * n_bins + k];
-            const double scale = 4.0 * df * amp * w;
-            dcoef[(int64_t)d * n_bins + k] = make_double2(scale * v.x, -scale * v.y);
-            dd[d] += (v.x * v.x + v.y * v.y) * w;
-            qq[d] += amp * amp * w;
+            const double2 x = v.data[(int64_t)d * v.n_bins + k];
+            const double scale = 4.0 * v.df * amp * w;
+            v.dcoef[(int64_t)d * v.n_bins + k] = make_double2(scale * x.x, -scale * x.y);
+            if (direct) {
+                v.edir[(int64_t)d * v.n_bins + k] = make_double2(x.x / amp, x.y / amp);
+                v.vdir[(int64_t)d * v.n_bins + k] = amp * amp * w;
+            }
+            acc[kPrepPerDet * d] = (x.x * x.x + x.y * x.y) * w;
+            acc[kPrepPerDet * d + 1] = amp * amp * w;
+            acc[kPrepPerDet * d + 2] = norm ? log(2.0 * GW_PI * s) : 0.0;
         }
     }
 }
 
-// Fixed-order tree reduction over the block of (dd[d], qq[d]) for d < n_det;
-// thread 0 writes out[2 d] = sum dd[d], out[2 d + 1] = sum qq[d].
-__device__ __forceinline__ void block_reduce_pairs(int n_det, const double dd[kMaxDet], const double qq[kMaxDet],
-                                                   double *red, double *out)
+// Fixed-order tree sum of x over the block; every thread gets the total.
+// `red` is kBlock doubles of LDS.  All threads must call it.
+__device__ __forceinline__ double block_sum(double x, double *red)
 {
-    for (int j = 0; j < 2 * n_det; ++j) {
+    red[threadIdx.x] = x;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double total = red[0];
+    __syncthreads();
+    return total;
+}
+
+// Block b of an event's preparation: bins [256 b, 256 b + 256); thread 0
+// writes the block's sums out[kPrepPerDet d + j].
+__device__ __forceinline__ void prep_block(const PrepView &v, int64_t b, bool direct, bool norm, double *red,
+                                           double *__restrict__ out)
+{
+    double acc[kPrepPerDet * kMaxDet];
+#pragma unroll
+    for (int i = 0; i < kPrepPerDet * kMaxDet; ++i) acc[i] = 0.0;
+    const int64_t k = b * kBlock + threadIdx.x;
+    if (k < v.n_bins) bin_data(v, k, direct, norm, acc);
+    for (int j = 0; j < kPrepPerDet * v.n_det; ++j) {
         double x = 0.0;
 #pragma unroll
-        for (int d = 0; d < kMaxDet; ++d) {
-            if (j == 2 * d) x = dd[d];
-            if (j == 2 * d + 1) x = qq[d];
-        }
-        red[threadIdx.x] = x;
-        __syncthreads();
-        for (int w = kBlock / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[j] = red[0];
-        __syncthreads();
+        for (int i = 0; i < kPrepPerDet * kMaxDet; ++i)
+            if (i == j) x = acc[i];
+        const double total = block_sum(x, red);
+        if (threadIdx.x == 0) out[j] = total;
     }
 }
 
-// Sums the per-block partials of one event in a fixed order:
-// event_sums[0] = <d,d> summed over detectors, event_sums[1 + det] = Q_det.
+// Sums the per-block partials of one event in a fixed order into
+// sums[0] = <d,d>, sums[1 + d] = Q_d, sums[kSumNorm] = sum ln(2 pi S).
 __device__ __forceinline__ void sum_event_partials(int n_blocks, int n_det, double df,
                                                    const double *__restrict__ partials, double *red,
-                                                   double *__restrict__ event_sums)
+                                                   double *__restrict__ sums)
 {
-    double total_dd = 0.0;
-    for (int j = 0; j < 2 * n_det; ++j) {
+    double total_dd = 0.0, total_norm = 0.0;
+    const int per = kPrepPerDet * n_det;
+    for (int j = 0; j < per; ++j) {
         double x = 0.0;
-        for (int b = threadIdx.x; b < n_blocks; b += kBlock) x += partials[(int64_t)b * 2 * n_det + j];
-        red[threadIdx.x] = x;
+        for (int b = threadIdx.x; b < n_blocks; b += kBlock) x += partials[(int64_t)b * per + j];
+        const double total = block_sum(x, red);
+        const int kind = j % kPrepPerDet, d = j / kPrepPerDet;
+        if (kind == 0) total_dd += 4.0 * df * total;
+        else if (kind == 1) { if (threadIdx.x == 0) sums[1 + d] = 4.0 * df * total; }
+        else total_norm += total;
+    }
+    if (threadIdx.x == 0) {
+        sums[0] = total_dd;
+        sums[kSumNorm] = total_norm;
+    }
+}
+
+// Prefix sums of a^2/S for the ISCO end: block b of the event writes
+// qprefix[d][k] = sum_{j <= k} a_j^2 / S_d,j for its 256 bins, from the
+// preceding blocks' sums (added in block order) and a scan of its own bins.
+__device__ __forceinline__ void prefix_block(const PrepView &v, int64_t b, const double *__restrict__ partials,
+                                             double *red, double *__restrict__ qprefix)
+{
+    const int per = kPrepPerDet * v.n_det;
+    const int64_t k = b * kBlock + threadIdx.x;
+    const double amp = k < v.n_bins ? v.tab2[k].amp : 0.0;
+    for (int d = 0; d < v.n_det; ++d) {
+        double before = 0.0;
+        for (int64_t c = threadIdx.x; c < b; c += kBlock) before += partials[c * per + kPrepPerDet * d + 1];
+        const double offset = block_sum(before, red);
+        double q = 0.0;
+        if (k < v.n_bins) {
+            const double s = v.psd[(int64_t)d * v.n_bins + k];
+            const double w = (s > 0.0 && s < INFINITY) ? 1.0 / s : NAN;
+            q = amp * amp * w;
+        }
+        // inclusive Hillis-Steele scan over the block
+        red[threadIdx.x] = q;
         __syncthreads();
-        for (int w = kBlock / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        for (int off = 1; off < kBlock; off <<= 1) {
+            const double add = (int)threadIdx.x >= off ? red[threadIdx.x - off] : 0.0;
+            __syncthreads();
+            red[threadIdx.x] += add;
             __syncthreads();
         }
-        if (threadIdx.x == 0) {
-            if (j % 2 == 0) total_dd += 4.0 * df * red[0];
-            else event_sums[1 + j / 2] = 4.0 * df * red[0];
-        }
+        if (k < v.n_bins) qprefix[(int64_t)d * v.n_bins + k] = offset + red[threadIdx.x];
         __syncthreads();
     }
-    if (threadIdx.x == 0) event_sums[0] = total_dd;
 }
 
 __global__ __launch_bounds__(kBlock) void event_tables_kernel(double f_low, double df, int64_t n_bins,
@@ -139,48 +202,58 @@ __global__ __launch_bounds__(kBlock) void event_tables_kernel(double f_low, doub
         bin_tables(f_low, df, k, tab1, tab2);
 }
 
-__global__ __launch_bounds__(kBlock) void event_data_kernel(int64_t n_bins, int n_det, double df,
-                                                             const double2 *__restrict__ data,
-                                                             const double *__restrict__ psd,
-                                                             const Tab2 *__restrict__ tab2,
-                                                             double2 *__restrict__ dcoef,
+// One block per 256 consecutive bins.
+__global__ __launch_bounds__(kBlock) void event_data_kernel(PrepView v, int direct, int norm,
                                                              double *__restrict__ partials)
 {
     __shared__ double red[kBlock];
-    double dd[kMaxDet], qq[kMaxDet];
-#pragma unroll
-    for (int d = 0; d < kMaxDet; ++d) { dd[d] = 0.0; qq[d] = 0.0; }
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n_bins; k += stride)
-        bin_data(n_bins, n_det, df, k, tab2[k].amp, data, psd, dcoef, dd, qq);
-    block_reduce_pairs(n_det, dd, qq, red, partials + (int64_t)blockIdx.x * 2 * n_det);
+    prep_block(v, blockIdx.x, direct != 0, norm != 0, red, partials + (int64_t)blockIdx.x * kPrepPerDet * v.n_det);
 }
 
 __global__ __launch_bounds__(kBlock) void event_sums_kernel(int n_blocks, int n_det, double df,
                                                              const double *__restrict__ partials,
-                                                             double *__restrict__ event_sums)
+                                                             double *__restrict__ sums)
 {
     __shared__ double red[kBlock];
-    sum_event_partials(n_blocks, n_det, df, partials, red, event_sums);
+    sum_event_partials(n_blocks, n_det, df, partials, red, sums);
+}
+
+__global__ __launch_bounds__(kBlock) void event_prefix_kernel(PrepView v, const double *__restrict__ partials,
+                                                               double *__restrict__ qprefix)
+{
+    __shared__ double red[kBlock];
+    prefix_block(v, blockIdx.x, partials, red, qprefix);
+}
+
+__device__ __forceinline__ PrepView prep_view(const RaggedEvent &re)
+{
+    PrepView v;
+    v.n_bins = re.n_bins;
+    v.n_det = re.n_det;
+    v.df = re.df;
+    v.data = re.data;
+    v.psd = re.psd;
+    v.tab2 = re.tab2;
+    v.dcoef = re.dcoef;
+    v.edir = re.edir;
+    v.vdir = re.vdir;
+    return v;
 }
 
 // Ragged batch, all events at once: block b handles bins
 // [256 local, 256 local + 256) of event e, (e, local) = block_map[b].
 __global__ __launch_bounds__(kBlock) void ragged_event_prep_kernel(const RaggedEvent *__restrict__ events,
-                                                                    const int2 *__restrict__ block_map)
+                                                                    const int2 *__restrict__ block_map,
+                                                                    int direct, int norm)
 {
     __shared__ double red[kBlock];
     const int2 em = block_map[blockIdx.x];
     const RaggedEvent &re = events[em.x];
-    double dd[kMaxDet], qq[kMaxDet];
-#pragma unroll
-    for (int d = 0; d < kMaxDet; ++d) { dd[d] = 0.0; qq[d] = 0.0; }
     const int64_t k = (int64_t)em.y * kBlock + threadIdx.x;
-    if (k < re.n_bins) {
-        bin_tables(re.f_low, re.df, k, re.tab1, re.tab2);
-        bin_data(re.n_bins, re.n_det, re.df, k, re.tab2[k].amp, re.data, re.psd, re.dcoef, dd, qq);
-    }
-    block_reduce_pairs(re.n_det, dd, qq, red, re.prep + (int64_t)em.y * 2 * re.n_det);
+    if (k < re.n_bins) bin_tables(re.f_low, re.df, k, re.tab1, re.tab2);
+    __syncthreads();
+    prep_block(prep_view(re), em.y, direct != 0, norm != 0, red,
+               re.prep + (int64_t)em.y * kPrepPerDet * re.n_det);
 }
 
 // Ragged batch: block e sums event e's per-block partials.
@@ -191,13 +264,26 @@ __global__ __launch_bounds__(kBlock) void ragged_event_sums_kernel(const RaggedE
     sum_event_partials(re.prep_blocks, re.n_det, re.df, re.prep, red, re.sums);
 }
 
+// Ragged batch: prefix sums of a^2/S, blocks as in ragged_event_prep_kernel.
+__global__ __launch_bounds__(kBlock) void ragged_prefix_kernel(const RaggedEvent *__restrict__ events,
+                                                                const int2 *__restrict__ block_map)
+{
+    __shared__ double red[kBlock];
+    const int2 em = block_map[blockIdx.x];
+    const RaggedEvent &re = events[em.x];
+    prefix_block(prep_view(re), em.y, re.prep, red, re.qprefix);
+}
+
 // ---------------------------------------------------------------- per-sample preparation
 // Row s: mass ratios, the phase polynomial coefficients (in turns), antenna
 // patterns F = D : e, delays -n.r/c, and the complex amplitudes
 //   P_det = A0 [F+ (1 + cos^2 iota)/2 - i Fx cos iota] e^{i (phi_c + pi/4)}.
 // In polarisation mode (n_out == 2, no detectors) channel 0 is h_plus and
-// channel 1 is h_cross.
-__device__ __forceinline__ void prep_sample(int64_t s, int64_t n_samples, int n_param, int n_out, bool polarisations,
+// channel 1 is h_cross.  The template's last bin K_s is n_bins - 1, or with
+// the ISCO end the last bin with f_k <= f_isco = 1 / (6^(3/2) pi M) (-1 when
+// there is none, and for samples that are not evaluated).
+__device__ __forceinline__ void prep_sample(double f_low, double df, int64_t n_bins, int64_t s, int64_t n_samples,
+                                            int n_param, int n_out, bool polarisations, bool isco,
                                             const DetGeom &geom, const double *__restrict__ theta,
                                             double *__restrict__ rec)
 {
@@ -290,6 +376,20 @@ __device__ __forceinline__ void prep_sample(int64_t s, int64_t n_samples, int n_
     rec[kRecC2 * ns + s] = cj[2];
     rec[kRecC0 * ns + s] = cj[0];
     rec[kRecStatus * ns + s] = (double)status;
+    double kcut = (double)(n_bins - 1);
+    if (isco) {
+        kcut = -1.0;
+        if (status == 0) {
+            const double f_isco = 1.0 / (pow(6.0, 1.5) * GW_PI * mtot_s);
+            const double kf = fmin(fmax(floor((f_isco - f_low) / df), -1.0), (double)(n_bins - 1));
+            int64_t k = (int64_t)kf;
+            // settle the rounding: the same f_k = f_low + k df as every table
+            while (k + 1 < n_bins && __dadd_rn(f_low, __dmul_rn((double)(k + 1), df)) <= f_isco) ++k;
+            while (k >= 0 && __dadd_rn(f_low, __dmul_rn((double)k, df)) > f_isco) --k;
+            kcut = (double)k;
+        }
+    }
+    rec[kRecKcut * ns + s] = kcut;
 #pragma unroll
     for (int d = 0; d < kMaxDet; ++d) {
         if (d < n_out) {
@@ -308,26 +408,45 @@ __device__ __forceinline__ void prep_sample(int64_t s, int64_t n_samples, int n_
     }
 }
 
-__global__ __launch_bounds__(kBlock) void sample_prep_kernel(int64_t n_samples, int n_param, int n_out,
-                                                              int polarisations, DetGeom geom,
+__global__ __launch_bounds__(kBlock) void sample_prep_kernel(double f_low, double df, int64_t n_bins,
+                                                              int64_t n_samples, int n_param, int n_out,
+                                                              int polarisations, int isco, DetGeom geom,
                                                               const double *__restrict__ theta,
                                                               double *__restrict__ rec)
 {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= n_samples) return;
-    prep_sample(s, n_samples, n_param, n_out, polarisations != 0, geom, theta, rec);
+    prep_sample(f_low, df, n_bins, s, n_samples, n_param, n_out, polarisations != 0, isco != 0, geom, theta, rec);
+}
+
+// *k_limit = 1 + the largest K_s of the batch (one block).
+__global__ __launch_bounds__(kBlock) void isco_limit_kernel(int64_t n_samples, const double *__restrict__ rec,
+                                                             int64_t *__restrict__ k_limit)
+{
+    __shared__ double red[kBlock];
+    double m = -1.0;
+    for (int64_t s = threadIdx.x; s < n_samples; s += kBlock) m = fmax(m, rec[kRecKcut * n_samples + s]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *k_limit = (int64_t)red[0] + 1;
 }
 
 // Ragged batch: block (event, group) prepares the group's rows.
 __global__ __launch_bounds__(kBlock) void ragged_sample_prep_kernel(const RaggedEvent *__restrict__ events,
                                                                      const int2 *__restrict__ groups,
-                                                                     const DetGeom *__restrict__ geoms, int n_param)
+                                                                     const DetGeom *__restrict__ geoms, int n_param,
+                                                                     int isco)
 {
     const int2 eg = groups[blockIdx.x];
     const RaggedEvent &re = events[eg.x];
     const int64_t s = (int64_t)eg.y * kBlock + threadIdx.x;
     if (s >= re.n_samples) return;
-    prep_sample(s, re.n_samples, n_param, re.n_det, false, geoms[eg.x], re.theta, re.rec);
+    prep_sample(re.f_low, re.df, re.n_bins, s, re.n_samples, n_param, re.n_det, false, isco != 0, geoms[eg.x],
+                re.theta, re.rec);
 }
 
 // Sets n counters to zero (a kernel rather than a memset, so that it can be
@@ -379,41 +498,68 @@ struct EventView {
     int64_t n_bins, n_samples;
     double f_low, df;
     const Tab1 *tab1;
-    const double2 *dcoef;
+    const double2 *dcoef;      // split forms: D [n_det][n_bins]
+    const double2 *edir;       // direct form: d / a [n_det][n_bins]
+    const double *vdir;        // direct form: a^2 / S [n_det][n_bins]
     const double *rec;
-    double2 *partials;     // [chunk][n_samples][NDET]
+    const int64_t *k_limit;    // split form with the ISCO end: 1 + max K_s (device)
+    double2 *partials;         // split: [chunk][n_samples][NDET]; direct: double [chunk][n_samples]
 };
+
+// LDS layout of a tile: tab1 [tile], then per detector D (split) or d/a
+// (direct) [NDET][tile] double2, then for the direct form a^2/S [NDET][tile].
+__host__ __device__ constexpr size_t tile_lds_bytes(int n_det, int tile_bins, int form)
+{
+    return (size_t)tile_bins * (sizeof(Tab1) + (size_t)n_det * sizeof(double2) +
+                                (form == kFormDirect ? (size_t)n_det * sizeof(double) : 0));
+}
 
 // The 256 samples of `group` (one per thread) against bins [k_begin, k_end)
 // of one event, staged through LDS tile by tile and shared by all the
-// block's samples; writes Z_det of every sample for chunk `chunk`.
+// block's samples; writes the chunk's partial sums of every sample.
 // MIXED selects the mixed-precision path: the phase polynomial and its
 // reduction to a fractional turn stay FP64 (the phase reaches ~1e4 rad), the
 // phasor e^{-i Phi_0} comes from the FP32 hardware sine/cosine, and the
 // projection, accumulation and all sums stay FP64.
+// FORM (TileForm): the split forms accumulate Z_det (kFormSplitIsco only
+// over bins k <= K_s of each sample); the direct form accumulates
+// sum_det a^2/S |d/a - P_det e^{-i Phi_det}|^2 with the template zero above K_s.
 // All threads of the block must call this with the same arguments.
-template <int NDET, bool MIXED>
+template <int NDET, bool MIXED, int FORM>
 __device__ __forceinline__ void tile_chunk(const EventView &ev, int group, int64_t chunk, int64_t k_begin,
-                                           int64_t k_end, int tile_bins, Tab1 *lt, double2 *ld)
+                                           int64_t k_end, int tile_bins, double *lds)
 {
+    constexpr bool kDirect = FORM == kFormDirect;
+    constexpr bool kMasked = FORM != kFormSplit;
     const int64_t n_bins = ev.n_bins, n_samples = ev.n_samples;
     const double f_low = ev.f_low, df = ev.df;
     const Tab1 *__restrict__ tab1 = ev.tab1;
-    const double2 *__restrict__ dcoef = ev.dcoef;
+    const double2 *__restrict__ dsrc = kDirect ? ev.edir : ev.dcoef;
+    const double *__restrict__ vdir = ev.vdir;
     const double *__restrict__ rec = ev.rec;
     const int64_t s = (int64_t)group * kBlock + threadIdx.x;
     const int64_t sr = s < n_samples ? s : n_samples - 1;
+    Tab1 *lt = reinterpret_cast<Tab1 *>(lds);
+    double2 *ld = reinterpret_cast<double2 *>(lt + tile_bins);
+    double *lv = reinterpret_cast<double *>(ld + NDET * tile_bins);
 
     const PhaseCoef cf = load_coef(rec, n_samples, sr);
-    double rho_re[NDET], rho_im[NDET], delta[NDET];
+    const int64_t kcut = kMasked ? (int64_t)rec[kRecKcut * n_samples + sr] : n_bins - 1;
+    double rho_re[NDET], rho_im[NDET], delta[NDET], p_re[NDET], p_im[NDET];
 #pragma unroll
-    for (int d = 1; d < NDET; ++d) {
+    for (int d = 0; d < NDET; ++d) {
+        if (kDirect) {
+            p_re[d] = rec[(kRecDet + kRecFieldsPerDet * d) * n_samples + sr];
+            p_im[d] = rec[(kRecDet + kRecFieldsPerDet * d + 1) * n_samples + sr];
+        }
+        if (d == 0) continue;
         delta[d] = rec[(kRecDet + kRecFieldsPerDet * d + 2) * n_samples + sr];
         gw_phasor_turns(df * delta[d], rho_re[d], rho_im[d]);
     }
     double zr[NDET], zi[NDET];
 #pragma unroll
     for (int d = 0; d < NDET; ++d) { zr[d] = 0.0; zi[d] = 0.0; }
+    double acc = 0.0;
 
     for (int64_t t0 = k_begin; t0 < k_end; t0 += tile_bins) {
         const int nk = (int)min((int64_t)tile_bins, k_end - t0);
@@ -421,12 +567,33 @@ __device__ __forceinline__ void tile_chunk(const EventView &ev, int group, int64
         for (int i = threadIdx.x; i < nk; i += kBlock) {
             lt[i] = tab1[t0 + i];
 #pragma unroll
-            for (int d = 0; d < NDET; ++d) ld[d * tile_bins + i] = dcoef[(int64_t)d * n_bins + t0 + i];
+            for (int d = 0; d < NDET; ++d) {
+                ld[d * tile_bins + i] = dsrc[(int64_t)d * n_bins + t0 + i];
+                if (kDirect) lv[d * tile_bins + i] = vdir[(int64_t)d * n_bins + t0 + i];
+            }
         }
         __syncthreads();
+        // last live bin of this lane within the tile (template end)
+        const int jcut = kMasked ? (int)max((int64_t)-1, min(kcut - t0, (int64_t)nk - 1)) : nk - 1;
+        // split: Horner sums S_d over the tile; direct: T_d = P_d e^{-2 pi i f delta_d} at the current bin
         double sr_[NDET], si_[NDET];
 #pragma unroll
-        for (int d = 1; d < NDET; ++d) { sr_[d] = 0.0; si_[d] = 0.0; }
+        for (int d = 0; d < NDET; ++d) { sr_[d] = 0.0; si_[d] = 0.0; }
+        if (kDirect) {
+            const double f_first = __dadd_rn(f_low, __dmul_rn((double)t0, df));
+#pragma unroll
+            for (int d = 0; d < NDET; ++d) {
+                if (d == 0) {
+                    sr_[0] = p_re[0];
+                    si_[0] = p_im[0];
+                    continue;
+                }
+                double rr, ri;
+                gw_phasor_turns(f_first * delta[d], rr, ri);
+                sr_[d] = p_re[d] * rr - p_im[d] * ri;
+                si_[d] = p_re[d] * ri + p_im[d] * rr;
+            }
+        }
 #pragma unroll kTileUnroll
         for (int j = 0; j < nk; ++j) {
             const Tab1 tb = lt[j];
@@ -441,27 +608,50 @@ __device__ __forceinline__ void tile_chunk(const EventView &ev, int group, int64
             } else {
                 gw_phasor_turns(turns_phase(cf, tb), er, ei);
             }
-            const double2 d0 = ld[j];
-            zr[0] = __builtin_fma(d0.x, er, zr[0]);
-            zr[0] = __builtin_fma(-d0.y, ei, zr[0]);
-            zi[0] = __builtin_fma(d0.x, ei, zi[0]);
-            zi[0] = __builtin_fma(d0.y, er, zi[0]);
+            if (kMasked && j > jcut) {
+                er = 0.0;
+                ei = 0.0;
+            }
+            if constexpr (kDirect) {
 #pragma unroll
-            for (int d = 1; d < NDET; ++d) {
-                const double2 dv = ld[d * tile_bins + j];
-                double tr = dv.x * er;
-                tr = __builtin_fma(-dv.y, ei, tr);
-                tr = __builtin_fma(sr_[d], rho_re[d], tr);
-                tr = __builtin_fma(si_[d], rho_im[d], tr);
-                double ti = dv.x * ei;
-                ti = __builtin_fma(dv.y, er, ti);
-                ti = __builtin_fma(si_[d], rho_re[d], ti);
-                ti = __builtin_fma(-sr_[d], rho_im[d], ti);
-                sr_[d] = tr;
-                si_[d] = ti;
+                for (int d = 0; d < NDET; ++d) {
+                    const double2 e = ld[d * tile_bins + j];
+                    const double v = lv[d * tile_bins + j];
+                    // residual d/a - P_d e^{-i Phi_d}
+                    double rr = __builtin_fma(-er, sr_[d], e.x);
+                    rr = __builtin_fma(ei, si_[d], rr);
+                    double ri = __builtin_fma(-er, si_[d], e.y);
+                    ri = __builtin_fma(-ei, sr_[d], ri);
+                    acc = __builtin_fma(v, __builtin_fma(rr, rr, ri * ri), acc);
+                    if (d > 0) {
+                        const double tr = sr_[d] * rho_re[d] - si_[d] * rho_im[d];
+                        si_[d] = sr_[d] * rho_im[d] + si_[d] * rho_re[d];
+                        sr_[d] = tr;
+                    }
+                }
+            } else {
+                const double2 d0 = ld[j];
+                zr[0] = __builtin_fma(d0.x, er, zr[0]);
+                zr[0] = __builtin_fma(-d0.y, ei, zr[0]);
+                zi[0] = __builtin_fma(d0.x, ei, zi[0]);
+                zi[0] = __builtin_fma(d0.y, er, zi[0]);
+#pragma unroll
+                for (int d = 1; d < NDET; ++d) {
+                    const double2 dv = ld[d * tile_bins + j];
+                    double tr = dv.x * er;
+                    tr = __builtin_fma(-dv.y, ei, tr);
+                    tr = __builtin_fma(sr_[d], rho_re[d], tr);
+                    tr = __builtin_fma(si_[d], rho_im[d], tr);
+                    double ti = dv.x * ei;
+                    ti = __builtin_fma(dv.y, er, ti);
+                    ti = __builtin_fma(si_[d], rho_re[d], ti);
+                    ti = __builtin_fma(-sr_[d], rho_im[d], ti);
+                    sr_[d] = tr;
+                    si_[d] = ti;
+                }
             }
         }
-        if (NDET > 1) {
+        if (!kDirect && NDET > 1) {
             const double f_last = __dadd_rn(f_low, __dmul_rn((double)(t0 + nk - 1), df));
 #pragma unroll
             for (int d = 1; d < NDET; ++d) {
@@ -475,37 +665,47 @@ __device__ __forceinline__ void tile_chunk(const EventView &ev, int group, int64
         }
     }
     if (s < n_samples) {
+        if (kDirect) {
+            reinterpret_cast<double *>(ev.partials)[chunk * n_samples + s] = acc;
+        } else {
 #pragma unroll
-        for (int d = 0; d < NDET; ++d)
-            ev.partials[(chunk * n_samples + s) * NDET + d] = make_double2(zr[d], zi[d]);
+            for (int d = 0; d < NDET; ++d)
+                ev.partials[(chunk * n_samples + s) * NDET + d] = make_double2(zr[d], zi[d]);
+        }
     }
 }
 
 // One event: block (chunk, group).  Blocks are dispatched round-robin over the
 // 8 XCDs; when the grid is a multiple of 8 the linear work index is remapped
 // so that the blocks of one XCD cover consecutive chunks (and all sample
-// groups of each), keeping their bin data in that XCD's L2.
-template <int NDET, bool MIXED>
-__global__ __launch_bounds__(kBlock) GW_TILE_ATTR void lnl_tile_kernel(EventView ev, int n_groups, int64_t chunk_bins,
-                                                                       int tile_bins)
+// groups of each), keeping their bin data in that XCD's L2.  With the ISCO
+// end (split form) the n_chunks chunks cover only bins below 1 + max K_s,
+// read from the device, so that no block works on bins every template has
+// left.
+template <int NDET, bool MIXED, int FORM>
+__global__ __launch_bounds__(kBlock) GW_TILE_ATTR void lnl_tile_kernel(EventView ev, int n_groups, int n_chunks,
+                                                                       int64_t chunk_bins, int tile_bins)
 {
     extern __shared__ double4 lds_raw[];
-    Tab1 *lt = reinterpret_cast<Tab1 *>(lds_raw);
-    double2 *ld = reinterpret_cast<double2 *>(lt + tile_bins);
     const unsigned nb = gridDim.x, b = blockIdx.x;
     const unsigned w = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + b / 8u : b;
     const int group = (int)(w % (unsigned)n_groups);
     const int64_t chunk = (int64_t)(w / (unsigned)n_groups);
-    const int64_t k_begin = chunk * chunk_bins;
-    const int64_t k_end = min(ev.n_bins, k_begin + chunk_bins);
-    tile_chunk<NDET, MIXED>(ev, group, chunk, k_begin, k_end, tile_bins, lt, ld);
+    int64_t n_eff = ev.n_bins, cb = chunk_bins;
+    if (FORM == kFormSplitIsco) {
+        n_eff = min(ev.n_bins, max((int64_t)0, *ev.k_limit));
+        cb = max((int64_t)1, (n_eff + n_chunks - 1) / n_chunks);
+    }
+    const int64_t k_begin = min(n_eff, chunk * cb);
+    const int64_t k_end = min(n_eff, k_begin + cb);
+    tile_chunk<NDET, MIXED, FORM>(ev, group, chunk, k_begin, k_end, tile_bins, reinterpret_cast<double *>(lds_raw));
 }
 
 // Many events: a persistent grid.  Every block repeatedly takes the next work
 // item (event, sample group, bin chunk) from a device counter until the list
 // is exhausted; the list is sorted by decreasing cost, so the large items go
 // first and the small ones fill the tail.  The counter must be zero at launch.
-template <int NDET, bool MIXED>
+template <int NDET, bool MIXED, int FORM>
 __global__ __launch_bounds__(kBlock) GW_TILE_ATTR void lnl_ragged_kernel(const RaggedEvent *__restrict__ events,
                                                                          const WorkItem *__restrict__ items,
                                                                          int n_items, unsigned *__restrict__ counter,
@@ -513,8 +713,6 @@ __global__ __launch_bounds__(kBlock) GW_TILE_ATTR void lnl_ragged_kernel(const R
 {
     extern __shared__ double4 lds_raw[];
     __shared__ int next;
-    Tab1 *lt = reinterpret_cast<Tab1 *>(lds_raw);
-    double2 *ld = reinterpret_cast<double2 *>(lt + tile_bins);
     for (;;) {
         __syncthreads();                 // every thread has read `next` and left the LDS
         if (threadIdx.x == 0) next = (int)atomicAdd(counter, 1u);
@@ -530,63 +728,88 @@ __global__ __launch_bounds__(kBlock) GW_TILE_ATTR void lnl_ragged_kernel(const R
         ev.df = re.df;
         ev.tab1 = re.tab1;
         ev.dcoef = re.dcoef;
+        ev.edir = re.edir;
+        ev.vdir = re.vdir;
         ev.rec = re.rec;
+        ev.k_limit = nullptr;
         ev.partials = re.partials;
         const int64_t k_begin = (int64_t)wi.chunk * re.chunk_bins;
         const int64_t k_end = min(re.n_bins, k_begin + re.chunk_bins);
-        tile_chunk<NDET, MIXED>(ev, wi.group, wi.chunk, k_begin, k_end, tile_bins, lt, ld);
+        tile_chunk<NDET, MIXED, FORM>(ev, wi.group, wi.chunk, k_begin, k_end, tile_bins,
+                                      reinterpret_cast<double *>(lds_raw));
     }
 }
 
-// lnL = -1/2 <d,d> + sum_det [Re(P Z) - 1/2 |P|^2 Q], chunks summed in order.
+// lnL of row s.  Split forms: -1/2 <d,d> + sum_det [Re(P Z) - 1/2 |P|^2 Q_det],
+// Q_det from the event sums, or with the ISCO end 4 df times the prefix sum
+// of a^2/S up to K_s.  Direct form: -2 df times the summed residual.  Chunks
+// are summed in order; GW_FLAG_ADD_NORM subtracts sum ln(2 pi S).
 __device__ __forceinline__ double finalize_row(int64_t s, int64_t n_samples, int n_det, int n_chunks,
+                                               int64_t n_bins, double df, unsigned flags,
                                                const double2 *__restrict__ partials, const double *__restrict__ rec,
-                                               const double *__restrict__ event_sums)
+                                               const double *__restrict__ sums, const double *__restrict__ qprefix)
 {
-    const double dd = event_sums[0];
-    double acc = -0.5 * dd;
-    for (int d = 0; d < n_det; ++d) {
-        double zr = 0.0, zi = 0.0;
-        for (int c = 0; c < n_chunks; ++c) {
-            const double2 z = partials[((int64_t)c * n_samples + s) * n_det + d];
-            zr += z.x;
-            zi += z.y;
+    const double dd = sums[0];
+    double out;
+    if (flags & GW_FLAG_DIRECT) {
+        const double *pd = reinterpret_cast<const double *>(partials);
+        double acc = 0.0;
+        for (int c = 0; c < n_chunks; ++c) acc += pd[(int64_t)c * n_samples + s];
+        out = -2.0 * df * acc;
+    } else {
+        const bool isco = (flags & GW_FLAG_TERM_ISCO) != 0;
+        const int64_t kcut = (int64_t)rec[kRecKcut * n_samples + s];
+        double acc = -0.5 * dd;
+        for (int d = 0; d < n_det; ++d) {
+            double zr = 0.0, zi = 0.0;
+            for (int c = 0; c < n_chunks; ++c) {
+                const double2 z = partials[((int64_t)c * n_samples + s) * n_det + d];
+                zr += z.x;
+                zi += z.y;
+            }
+            const double pr = rec[(kRecDet + kRecFieldsPerDet * d) * n_samples + s];
+            const double pi = rec[(kRecDet + kRecFieldsPerDet * d + 1) * n_samples + s];
+            double q = sums[1 + d];
+            if (isco) q = kcut >= 0 ? 4.0 * df * qprefix[(int64_t)d * n_bins + kcut] : 0.0;
+            acc += (pr * zr - pi * zi) - 0.5 * (pr * pr + pi * pi) * q;
         }
-        const double pr = rec[(kRecDet + kRecFieldsPerDet * d) * n_samples + s];
-        const double pi = rec[(kRecDet + kRecFieldsPerDet * d + 1) * n_samples + s];
-        acc += (pr * zr - pi * zi) - 0.5 * (pr * pr + pi * pi) * event_sums[1 + d];
+        out = acc;
     }
+    if (flags & GW_FLAG_ADD_NORM) out -= sums[kSumNorm];
     const int status = (int)rec[kRecStatus * n_samples + s];
-    double out = acc;
     if (status == 1) out = -INFINITY;
     if (status == 2 || isnan(dd)) out = NAN;
     return out;
 }
 
 __global__ __launch_bounds__(kBlock) void lnl_finalize_kernel(int64_t n_samples, int n_det, int n_chunks,
+                                                               int64_t n_bins, double df, unsigned flags,
                                                                const double2 *__restrict__ partials,
                                                                const double *__restrict__ rec,
-                                                               const double *__restrict__ event_sums,
+                                                               const double *__restrict__ sums,
+                                                               const double *__restrict__ qprefix,
                                                                double *__restrict__ lnl)
 {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= n_samples) return;
-    lnl[s] = finalize_row(s, n_samples, n_det, n_chunks, partials, rec, event_sums);
+    lnl[s] = finalize_row(s, n_samples, n_det, n_chunks, n_bins, df, flags, partials, rec, sums, qprefix);
 }
 
 // Ragged batch: block (event, group) finalizes the group's rows.
 __global__ __launch_bounds__(kBlock) void ragged_finalize_kernel(const RaggedEvent *__restrict__ events,
-                                                                  const int2 *__restrict__ groups)
+                                                                  const int2 *__restrict__ groups, unsigned flags)
 {
     const int2 eg = groups[blockIdx.x];
     const RaggedEvent &re = events[eg.x];
     const int64_t s = (int64_t)eg.y * kBlock + threadIdx.x;
     if (s >= re.n_samples) return;
-    re.lnl[s] = finalize_row(s, re.n_samples, re.n_det, re.n_chunks, re.partials, re.rec, re.sums);
+    re.lnl[s] = finalize_row(s, re.n_samples, re.n_det, re.n_chunks, re.n_bins, re.df, flags, re.partials, re.rec,
+                             re.sums, re.qprefix);
 }
 
 // ---------------------------------------------------------------- waveform materialisation
-// h[s][ch][k] = a_k P_ch e^{-i Phi_0,k} e^{-2 pi i f_k delta_ch}; one thread per bin,
+// h[s][ch][k] = a_k P_ch e^{-i Phi_0,k} e^{-2 pi i f_k delta_ch} for k <= K_s
+// (zero above the template end); one thread per bin,
 // consecutive bins in consecutive lanes for coalesced 16-byte stores.
 __global__ __launch_bounds__(kBlock) void waveform_kernel(int64_t n_bins, int n_out, int64_t n_samples,
                                                            int64_t blocks_per_sample,
@@ -599,6 +822,7 @@ __global__ __launch_bounds__(kBlock) void waveform_kernel(int64_t n_bins, int n_
     const int64_t k = ((int64_t)blockIdx.x % blocks_per_sample) * kBlock + threadIdx.x;
     if (k >= n_bins) return;
     const int status = (int)rec[kRecStatus * n_samples + s];
+    const int64_t kcut = (int64_t)rec[kRecKcut * n_samples + s];
     const PhaseCoef cf = load_coef(rec, n_samples, s);
     const Tab1 tb = tab1[k];
     const Tab2 t2 = tab2[k];
@@ -618,6 +842,7 @@ __global__ __launch_bounds__(kBlock) void waveform_kernel(int64_t n_bins, int n_
         double2 h;
         h.x = t2.amp * (pr * gr - pi * gi);
         h.y = t2.amp * (pr * gi + pi * gr);
+        if (k > kcut) h = make_double2(0.0, 0.0);
         if (status != 0) h = make_double2(NAN, NAN);
         h_out[((int64_t)s * n_out + d) * n_bins + k] = h;
     }
@@ -638,179 +863,178 @@ hipError_t launch_event_tables(const gw_grid &grid, Tab1 *tab1, Tab2 *tab2, hipS
 }
 
 hipError_t launch_event_data(const gw_grid &grid, int n_det, const gw_c128 *data, const double *psd,
-                             const Tab2 *tab2, double2 *dcoef, double *prep_partials, int prep_blocks,
-                             double *event_sums, hipStream_t stream)
+                             const EventBuffers &eb, unsigned flags, hipStream_t stream)
 {
-    hipLaunchKernelGGL(event_data_kernel, dim3(prep_blocks), dim3(kBlock), 0, stream, grid.n_bins, n_det,
-                       grid.delta_f, reinterpret_cast<const double2 *>(data), psd, tab2, dcoef, prep_partials);
+    PrepView v;
+    v.n_bins = grid.n_bins;
+    v.n_det = n_det;
+    v.df = grid.delta_f;
+    v.data = reinterpret_cast<const double2 *>(data);
+    v.psd = psd;
+    v.tab2 = eb.tab2;
+    v.dcoef = eb.dcoef;
+    v.edir = eb.edir;
+    v.vdir = eb.vdir;
+    const int direct = (flags & GW_FLAG_DIRECT) ? 1 : 0, norm = (flags & GW_FLAG_ADD_NORM) ? 1 : 0;
+    hipLaunchKernelGGL(event_data_kernel, dim3(eb.prep_blocks), dim3(kBlock), 0, stream, v, direct, norm, eb.prep);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(event_sums_kernel, dim3(1), dim3(kBlock), 0, stream, prep_blocks, n_det, grid.delta_f,
-                       prep_partials, event_sums);
-    return hipGetLastError();
+    hipLaunchKernelGGL(event_sums_kernel, dim3(1), dim3(kBlock), 0, stream, eb.prep_blocks, n_det, grid.delta_f,
+                       eb.prep, eb.sums);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (flags & GW_FLAG_TERM_ISCO) {
+        hipLaunchKernelGGL(event_prefix_kernel, dim3(eb.prep_blocks), dim3(kBlock), 0, stream, v, eb.prep,
+                           eb.qprefix);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
-hipError_t launch_sample_prep(int64_t n_samples, int n_param, int n_out, bool polarisations, const DetGeom &geom,
-                              const double *theta, double *records, hipStream_t stream)
+hipError_t launch_sample_prep(const gw_grid &grid, int64_t n_samples, int n_param, int n_out, bool polarisations,
+                              bool isco, const DetGeom &geom, const double *theta, double *records,
+                              hipStream_t stream)
 {
     hipLaunchKernelGGL(sample_prep_kernel, dim3(grid_blocks(n_samples, 1 << 30)), dim3(kBlock), 0, stream,
-                       n_samples, n_param, n_out, polarisations ? 1 : 0, geom, theta, records);
+                       grid.f_low, grid.delta_f, grid.n_bins, n_samples, n_param, n_out, polarisations ? 1 : 0,
+                       isco ? 1 : 0, geom, theta, records);
     return hipGetLastError();
 }
 
-size_t lnl_tile_lds_bytes(int n_det, int tile_bins)
+hipError_t launch_isco_limit(int64_t n_samples, const double *records, int64_t *k_limit, hipStream_t stream)
 {
-    return (size_t)tile_bins * (sizeof(Tab1) + (size_t)n_det * sizeof(double2));
+    hipLaunchKernelGGL(isco_limit_kernel, dim3(1), dim3(kBlock), 0, stream, n_samples, records, k_limit);
+    return hipGetLastError();
 }
 
-template <int NDET>
-static const void *tile_kernel_ptr(bool mixed)
-{
-    return mixed ? reinterpret_cast<const void *>(&lnl_tile_kernel<NDET, true>)
-                 : reinterpret_cast<const void *>(&lnl_tile_kernel<NDET, false>);
-}
+size_t lnl_tile_lds_bytes(int n_det, int tile_bins, int form) { return tile_lds_bytes(n_det, tile_bins, form); }
 
-static const void *tile_kernel_for(int n_det, bool mixed)
+template <int NDET, bool MIXED>
+static const void *tile_kernel_form(int form)
 {
-    switch (n_det) {
-    case 1: return tile_kernel_ptr<1>(mixed);
-    case 2: return tile_kernel_ptr<2>(mixed);
-    case 3: return tile_kernel_ptr<3>(mixed);
-    case 4: return tile_kernel_ptr<4>(mixed);
-    case 5: return tile_kernel_ptr<5>(mixed);
-    case 6: return tile_kernel_ptr<6>(mixed);
-    case 7: return tile_kernel_ptr<7>(mixed);
-    default: return tile_kernel_ptr<8>(mixed);
+    switch (form) {
+    case kFormSplit: return reinterpret_cast<const void *>(&lnl_tile_kernel<NDET, MIXED, kFormSplit>);
+    case kFormSplitIsco: return reinterpret_cast<const void *>(&lnl_tile_kernel<NDET, MIXED, kFormSplitIsco>);
+    default: return reinterpret_cast<const void *>(&lnl_tile_kernel<NDET, MIXED, kFormDirect>);
     }
 }
 
-int lnl_tile_blocks_per_cu(int n_det, int tile_bins, bool mixed)
+template <int NDET, bool MIXED>
+static const void *ragged_kernel_form(int form)
+{
+    switch (form) {
+    case kFormSplit: return reinterpret_cast<const void *>(&lnl_ragged_kernel<NDET, MIXED, kFormSplit>);
+    case kFormSplitIsco: return reinterpret_cast<const void *>(&lnl_ragged_kernel<NDET, MIXED, kFormSplitIsco>);
+    default: return reinterpret_cast<const void *>(&lnl_ragged_kernel<NDET, MIXED, kFormDirect>);
+    }
+}
+
+// The kernel (tile or ragged) for a detector count, precision and form.
+static const void *kernel_for(bool ragged, int n_det, bool mixed, int form)
+{
+#define GW_KERNEL_CASE(N)                                                                                        \
+    case N:                                                                                                    \
+        if (ragged) return mixed ? ragged_kernel_form<N, true>(form) : ragged_kernel_form<N, false>(form);      \
+        return mixed ? tile_kernel_form<N, true>(form) : tile_kernel_form<N, false>(form);
+    switch (n_det) {
+        GW_KERNEL_CASE(1)
+        GW_KERNEL_CASE(2)
+        GW_KERNEL_CASE(3)
+        GW_KERNEL_CASE(4)
+        GW_KERNEL_CASE(5)
+        GW_KERNEL_CASE(6)
+        GW_KERNEL_CASE(7)
+        GW_KERNEL_CASE(8)
+    default: return nullptr;
+    }
+#undef GW_KERNEL_CASE
+}
+
+static int occupancy(const void *fn, size_t lds)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tile_kernel_for(n_det, mixed), kBlock,
-                                                     lnl_tile_lds_bytes(n_det, tile_bins)) != hipSuccess)
-        return 1;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kBlock, lds) != hipSuccess) return 1;
     return n < 1 ? 1 : n;
 }
 
-template <int NDET>
-static void launch_tiles_t(const EventView &ev, const TilePlan &plan, bool mixed, hipStream_t stream)
+int lnl_tile_blocks_per_cu(int n_det, int tile_bins, bool mixed, int form)
 {
-    const unsigned blocks = (unsigned)plan.n_groups * (unsigned)plan.n_chunks;
-    const size_t lds = lnl_tile_lds_bytes(NDET, plan.tile_bins);
-    if (mixed)
-        hipLaunchKernelGGL((lnl_tile_kernel<NDET, true>), dim3(blocks), dim3(kBlock), lds, stream, ev, plan.n_groups,
-                           plan.chunk_bins, plan.tile_bins);
-    else
-        hipLaunchKernelGGL((lnl_tile_kernel<NDET, false>), dim3(blocks), dim3(kBlock), lds, stream, ev, plan.n_groups,
-                           plan.chunk_bins, plan.tile_bins);
+    return occupancy(kernel_for(false, n_det, mixed, form), tile_lds_bytes(n_det, tile_bins, form));
+}
+
+int lnl_ragged_blocks_per_cu(int n_det, int tile_bins, bool mixed, int form)
+{
+    return occupancy(kernel_for(true, n_det, mixed, form), tile_lds_bytes(n_det, tile_bins, form));
 }
 
 hipError_t launch_lnl_tiles(const gw_grid &grid, int n_det, int64_t n_samples, const TilePlan &plan, bool mixed,
-                            const Tab1 *tab1, const double2 *dcoef, const double *records,
-                            double2 *partials, hipStream_t stream)
+                            int form, const EventBuffers &eb, const double *records, double2 *partials,
+                            hipStream_t stream)
 {
     EventView ev;
     ev.n_bins = grid.n_bins;
     ev.n_samples = n_samples;
     ev.f_low = grid.f_low;
     ev.df = grid.delta_f;
-    ev.tab1 = tab1;
-    ev.dcoef = dcoef;
+    ev.tab1 = eb.tab1;
+    ev.dcoef = eb.dcoef;
+    ev.edir = eb.edir;
+    ev.vdir = eb.vdir;
     ev.rec = records;
+    ev.k_limit = eb.k_limit;
     ev.partials = partials;
-    switch (n_det) {
-    case 1: launch_tiles_t<1>(ev, plan, mixed, stream); break;
-    case 2: launch_tiles_t<2>(ev, plan, mixed, stream); break;
-    case 3: launch_tiles_t<3>(ev, plan, mixed, stream); break;
-    case 4: launch_tiles_t<4>(ev, plan, mixed, stream); break;
-    case 5: launch_tiles_t<5>(ev, plan, mixed, stream); break;
-    case 6: launch_tiles_t<6>(ev, plan, mixed, stream); break;
-    case 7: launch_tiles_t<7>(ev, plan, mixed, stream); break;
-    case 8: launch_tiles_t<8>(ev, plan, mixed, stream); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <int NDET>
-static void launch_ragged_t(const RaggedClass &c, const RaggedEvent *events, bool mixed, int tile_bins,
-                            hipStream_t stream)
-{
-    const size_t lds = lnl_tile_lds_bytes(NDET, tile_bins);
-    if (mixed)
-        hipLaunchKernelGGL((lnl_ragged_kernel<NDET, true>), dim3(c.grid), dim3(kBlock), lds, stream, events, c.items,
-                           c.n_items, c.counter, tile_bins);
-    else
-        hipLaunchKernelGGL((lnl_ragged_kernel<NDET, false>), dim3(c.grid), dim3(kBlock), lds, stream, events, c.items,
-                           c.n_items, c.counter, tile_bins);
+    const void *fn = kernel_for(false, n_det, mixed, form);
+    if (!fn) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)plan.n_groups * (unsigned)plan.n_chunks;
+    int n_groups = plan.n_groups, n_chunks = plan.n_chunks, tile_bins = plan.tile_bins;
+    int64_t chunk_bins = plan.chunk_bins;
+    void *args[] = {&ev, &n_groups, &n_chunks, &chunk_bins, &tile_bins};
+    return hipLaunchKernel(fn, dim3(blocks), dim3(kBlock), args, tile_lds_bytes(n_det, plan.tile_bins, form), stream);
 }
 
 hipError_t launch_ragged(const RaggedLaunch &r, hipStream_t stream)
 {
+    const int direct = (r.flags & GW_FLAG_DIRECT) ? 1 : 0, norm = (r.flags & GW_FLAG_ADD_NORM) ? 1 : 0;
+    const int form = tile_form(r.flags);
     hipLaunchKernelGGL(ragged_event_prep_kernel, dim3(r.n_prep_blocks), dim3(kBlock), 0, stream, r.events,
-                       r.block_map);
+                       r.block_map, direct, norm);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(ragged_event_sums_kernel, dim3(r.n_events), dim3(kBlock), 0, stream, r.events);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (r.flags & GW_FLAG_TERM_ISCO) {
+        hipLaunchKernelGGL(ragged_prefix_kernel, dim3(r.n_prep_blocks), dim3(kBlock), 0, stream, r.events,
+                           r.block_map);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(ragged_sample_prep_kernel, dim3(r.n_groups), dim3(kBlock), 0, stream, r.events, r.groups,
-                       r.geoms, r.n_param);
+                       r.geoms, r.n_param, (r.flags & GW_FLAG_TERM_ISCO) ? 1 : 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, stream, r.counters, kMaxDet);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int i = 0; i < r.n_classes; ++i) {
         const RaggedClass &c = r.classes[i];
-        switch (c.n_det) {
-        case 1: launch_ragged_t<1>(c, r.events, r.mixed, r.tile_bins, stream); break;
-        case 2: launch_ragged_t<2>(c, r.events, r.mixed, r.tile_bins, stream); break;
-        case 3: launch_ragged_t<3>(c, r.events, r.mixed, r.tile_bins, stream); break;
-        case 4: launch_ragged_t<4>(c, r.events, r.mixed, r.tile_bins, stream); break;
-        case 5: launch_ragged_t<5>(c, r.events, r.mixed, r.tile_bins, stream); break;
-        case 6: launch_ragged_t<6>(c, r.events, r.mixed, r.tile_bins, stream); break;
-        case 7: launch_ragged_t<7>(c, r.events, r.mixed, r.tile_bins, stream); break;
-        case 8: launch_ragged_t<8>(c, r.events, r.mixed, r.tile_bins, stream); break;
-        default: return hipErrorInvalidValue;
-        }
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const void *fn = kernel_for(true, c.n_det, r.mixed, form);
+        if (!fn) return hipErrorInvalidValue;
+        const RaggedEvent *events = r.events;
+        const WorkItem *items = c.items;
+        int n_items = c.n_items, tile_bins = r.tile_bins;
+        unsigned *counter = c.counter;
+        void *args[] = {&events, &items, &n_items, &counter, &tile_bins};
+        e = hipLaunchKernel(fn, dim3(c.grid), dim3(kBlock), args, tile_lds_bytes(c.n_det, r.tile_bins, form), stream);
+        if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(ragged_finalize_kernel, dim3(r.n_groups), dim3(kBlock), 0, stream, r.events, r.groups);
+    hipLaunchKernelGGL(ragged_finalize_kernel, dim3(r.n_groups), dim3(kBlock), 0, stream, r.events, r.groups,
+                       r.flags);
     return hipGetLastError();
 }
 
-template <int NDET>
-static const void *ragged_kernel_ptr(bool mixed)
-{
-    return mixed ? reinterpret_cast<const void *>(&lnl_ragged_kernel<NDET, true>)
-                 : reinterpret_cast<const void *>(&lnl_ragged_kernel<NDET, false>);
-}
-
-int lnl_ragged_blocks_per_cu(int n_det, int tile_bins, bool mixed)
-{
-    const void *fn = nullptr;
-    switch (n_det) {
-    case 1: fn = ragged_kernel_ptr<1>(mixed); break;
-    case 2: fn = ragged_kernel_ptr<2>(mixed); break;
-    case 3: fn = ragged_kernel_ptr<3>(mixed); break;
-    case 4: fn = ragged_kernel_ptr<4>(mixed); break;
-    case 5: fn = ragged_kernel_ptr<5>(mixed); break;
-    case 6: fn = ragged_kernel_ptr<6>(mixed); break;
-    case 7: fn = ragged_kernel_ptr<7>(mixed); break;
-    default: fn = ragged_kernel_ptr<8>(mixed); break;
-    }
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kBlock, lnl_tile_lds_bytes(n_det, tile_bins)) !=
-        hipSuccess)
-        return 1;
-    return n < 1 ? 1 : n;
-}
-
-hipError_t launch_lnl_finalize(int64_t n_samples, int n_det, const TilePlan &plan, const double2 *partials,
-                               const double *records, const double *event_sums, double *lnl_out,
-                               hipStream_t stream)
+hipError_t launch_lnl_finalize(const gw_grid &grid, int64_t n_samples, int n_det, const TilePlan &plan,
+                               const double2 *partials, const double *records, const EventBuffers &eb,
+                               unsigned flags, double *lnl_out, hipStream_t stream)
 {
     hipLaunchKernelGGL(lnl_finalize_kernel, dim3(grid_blocks(n_samples, 1 << 30)), dim3(kBlock), 0, stream,
-                       n_samples, n_det, plan.n_chunks, partials, records, event_sums, lnl_out);
+                       n_samples, n_det, plan.n_chunks, grid.n_bins, grid.delta_f, flags, partials, records, eb.sums,
+                       eb.qprefix, lnl_out);
     return hipGetLastError();
 }
 

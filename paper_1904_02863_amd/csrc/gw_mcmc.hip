@@ -73,12 +73,13 @@ __device__ __forceinline__ void normal_pair(const uint32_t a[4], double &z0, dou
 }
 
 __global__ __launch_bounds__(256) void philox_raw_kernel(uint64_t seed, uint32_t stream, uint32_t step,
-                                                         int64_t n_blocks, uint32_t *__restrict__ out)
+                                                         uint64_t first, int64_t n_blocks,
+                                                         uint32_t *__restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_blocks) return;
     uint32_t a[4];
-    philox_block(seed, stream, step, (uint64_t)i, a);
+    philox_block(seed, stream, step, first + (uint64_t)i, a);
     for (int j = 0; j < 4; ++j) out[4 * i + j] = a[j];
 }
 
@@ -222,11 +223,12 @@ __global__ __launch_bounds__(256) void update_mode_kernel(int64_t n, int *__rest
 // ---------------------------------------------------------------- launchers
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-hipError_t philox_raw(uint64_t seed, uint32_t stream, uint32_t step, int64_t n_blocks, uint32_t *out, hipStream_t s)
+hipError_t philox_raw(uint64_t seed, uint32_t stream, uint32_t step, uint64_t first, int64_t n_blocks, uint32_t *out,
+                      hipStream_t s)
 {
     if (n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(philox_raw_kernel, dim3(blocks_for(n_blocks)), dim3(256), 0, s, seed, stream, step, n_blocks,
-                       out);
+    hipLaunchKernelGGL(philox_raw_kernel, dim3(blocks_for(n_blocks)), dim3(256), 0, s, seed, stream, step, first,
+                       n_blocks, out);
     return hipGetLastError();
 }
 
@@ -292,11 +294,11 @@ int hip_fail(hipError_t e, const char *where) { return fail(GW_EDEVICE, std::str
 
 extern "C" {
 
-int gw_philox_raw(uint64_t seed, uint32_t stream_id, uint32_t step, int64_t n_blocks, uint32_t *out,
-                  hipStream_t stream)
+int gw_philox_raw(uint64_t seed, uint32_t stream_id, uint32_t step, uint64_t first, int64_t n_blocks,
+                  uint32_t *out, hipStream_t stream)
 {
     if (n_blocks < 0 || (n_blocks > 0 && !out)) return fail(GW_EINVAL, "bad philox arguments");
-    hipError_t e = gw::mcmc::philox_raw(seed, stream_id, step, n_blocks, out, stream);
+    hipError_t e = gw::mcmc::philox_raw(seed, stream_id, step, first, n_blocks, out, stream);
     return e == hipSuccess ? GW_OK : hip_fail(e, "gw_philox_raw");
 }
 

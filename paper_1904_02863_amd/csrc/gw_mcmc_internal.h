@@ -22,7 +22,8 @@ struct Box {
     double lo[kMaxDim], hi[kMaxDim];
 };
 
-hipError_t philox_raw(uint64_t seed, uint32_t stream, uint32_t step, int64_t n_blocks, uint32_t *out, hipStream_t s);
+hipError_t philox_raw(uint64_t seed, uint32_t stream, uint32_t step, uint64_t first, int64_t n_blocks, uint32_t *out,
+                      hipStream_t s);
 hipError_t philox_fill(uint64_t seed, uint32_t stream, uint32_t step, int kind, int64_t n, double *out, hipStream_t s);
 hipError_t normals_for_chains(int dim, int64_t n, uint64_t seed, uint32_t stream, uint32_t step, double *out,
                               hipStream_t s);

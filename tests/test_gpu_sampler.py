@@ -30,9 +30,12 @@ def test_philox_known_answers_through_gpu_counter_layout(gw):
     # counter (index lo, index hi, step, stream), key (seed lo, seed hi)
     a = gw.philox_raw(0, 0, 0, 1)[0]
     assert tuple(int(v) for v in a) == (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)
+    ones = gw.philox_raw(2 ** 64 - 1, 0xffffffff, 0xffffffff, 1, first=2 ** 64 - 1)[0]
+    assert tuple(int(v) for v in ones) == (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)
     seed = 0x299f31d0 << 32 | 0xa4093822
-    out = gw.philox_raw(seed, 0x03707344, 0x13198a2e, 0x85a308d3 * 2 ** 32 + 0x243f6a88 + 1)
-    assert tuple(int(v) for v in out[-1]) == (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1)
+    first = 0x85a308d3 << 32 | 0x243f6a88
+    out = gw.philox_raw(seed, 0x03707344, 0x13198a2e, 3, first=first - 1)
+    assert tuple(int(v) for v in out[1]) == (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1)
 
 
 @pytest.mark.parametrize("seed,stream,step", [(1, 1, 0), (2 ** 40 + 7, 3, 12345), (99, 2, 2 ** 31 + 5)])
