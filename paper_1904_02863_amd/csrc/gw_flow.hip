@@ -42,7 +42,8 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_floa
 // ---------------------------------------------------------------- GEMM on MFMA
 // C[M x N] = A[M x K] B[K x N] (+ bias[N]) (ReLU if relu), FP32 accumulation.
 // A(i, k) = A[i sa_i + k sa_k], B(k, j) = B[k sb_k + j sb_j], both BF16.
-// Block: 256 threads, 64 x 64 output tile, K in steps of 16 through LDS; each
+// Block: 256 threads, 64 x 64 output tile (blockIdx.z: K slice when split),
+// K in steps of 16 through LDS; each
 // of the 4 waves owns a 32 x 32 quarter as 2 x 2 tiles of
 // v_mfma_f32_16x16x16_bf16.  Operand layout of that instruction (wave64):
 // lane l supplies A(row l%16, k = 4(l/16)+0..3) and B(k = 4(l/16)+0..3,
@@ -58,13 +59,16 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
     const int lane = tid & 63, wave = tid >> 6;
     const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    // K slice of this block (the whole range unless split)
+    const int ks = ((g.K + g.split - 1) / g.split + 15) / 16 * 16;
+    const int k_lo = (int)blockIdx.z * ks, k_hi = min(g.K, k_lo + ks);
     float4_t acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = float4_t{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < g.K; k0 += 16) {
+    for (int k0 = k_lo; k0 < k_hi; k0 += 16) {
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -72,12 +76,12 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
             {   // A tile 64 x 16
                 const int i = idx >> 4, k = idx & 15;
                 const int gi = row0 + i, gk = k0 + k;
-                as[i][k] = (gi < g.M && gk < g.K) ? g.A[(int64_t)gi * g.sa_i + (int64_t)gk * g.sa_k] : (uint16_t)0;
+                as[i][k] = (gi < g.M && gk < k_hi) ? g.A[(int64_t)gi * g.sa_i + (int64_t)gk * g.sa_k] : (uint16_t)0;
             }
             {   // B tile 16 x 64
                 const int k = idx >> 6, j = idx & 63;
                 const int gk = k0 + k, gj = col0 + j;
-                bs[k][j] = (gk < g.K && gj < g.N) ? g.B[(int64_t)gk * g.sb_k + (int64_t)gj * g.sb_j] : (uint16_t)0;
+                bs[k][j] = (gk < k_hi && gj < g.N) ? g.B[(int64_t)gk * g.sb_k + (int64_t)gj * g.sb_j] : (uint16_t)0;
             }
         }
         __syncthreads();
@@ -107,6 +111,10 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
                 const int j = col0 + wc + 16 * b + lc;
                 if (i < g.M && j < g.N) {
                     float v = acc[a][b][r];
+                    if (g.split > 1) {
+                        g.partial[((int64_t)blockIdx.z * g.M + i) * g.N + j] = v;
+                        continue;
+                    }
                     if (g.bias) v += g.bias[j];
                     if (g.relu) v = v > 0.f ? v : 0.f;
                     if (g.C) g.C[(int64_t)i * g.ldc + j] = v;
@@ -115,11 +123,30 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
             }
 }
 
+// Sums the split-K slices in slice order, then bias, ReLU and the outputs.
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)g.M * g.N) return;
+    const int i = (int)(t / g.N), j = (int)(t % g.N);
+    float v = 0.f;
+    for (int z = 0; z < g.split; ++z) v += g.partial[(int64_t)z * g.M * g.N + t];
+    if (g.bias) v += g.bias[j];
+    if (g.relu) v = v > 0.f ? v : 0.f;
+    if (g.C) g.C[(int64_t)i * g.ldc + j] = v;
+    if (g.Cb) g.Cb[(int64_t)i * g.ldcb + j] = f32_to_bf16(v);
+}
+
 hipError_t gemm_bf16(const GemmArgs &g, hipStream_t stream)
 {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
-    const dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+    if (g.split < 1 || g.split > kMaxSplit || (g.split > 1 && !g.partial)) return hipErrorInvalidValue;
+    const dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.split);
     hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, stream, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || g.split == 1) return e;
+    const int64_t total = (int64_t)g.M * g.N;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, g);
     return hipGetLastError();
 }
 
@@ -263,13 +290,29 @@ __global__ __launch_bounds__(256) void relu_backward_kernel(int64_t count, float
 }
 
 // out[j] = sum_b m[b][j] (fixed order over b), j < cols.
-__global__ __launch_bounds__(256) void column_sum_kernel(int rows, int cols, int ld, const float *__restrict__ m,
-                                                         float *__restrict__ out)
+// Column sums of m [rows][cols] (leading dimension ld) in two passes: slice
+// y of the rows into part[y][cols] (FP64), then the slices in order.
+constexpr int kColSlices = 32;
+
+__global__ __launch_bounds__(256) void column_partial_kernel(int rows, int cols, int ld, const float *__restrict__ m,
+                                                             double *__restrict__ part)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cols) return;
+    const int per = (rows + kColSlices - 1) / kColSlices;
+    const int r0 = (int)blockIdx.y * per, r1 = min(rows, r0 + per);
+    double acc = 0.0;
+    for (int b = r0; b < r1; ++b) acc += (double)m[(int64_t)b * ld + j];
+    part[(int64_t)blockIdx.y * cols + j] = acc;
+}
+
+__global__ __launch_bounds__(256) void column_finish_kernel(int cols, const double *__restrict__ part,
+                                                            float *__restrict__ out)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= cols) return;
     double acc = 0.0;
-    for (int b = 0; b < rows; ++b) acc += (double)m[(int64_t)b * ld + j];
+    for (int y = 0; y < kColSlices; ++y) acc += part[(int64_t)y * cols + j];
     out[j] = (float)acc;
 }
 
@@ -354,6 +397,8 @@ struct gw_flow {
     float *dh = nullptr;                  // [cap][hidden]
     uint16_t *dpre_b = nullptr;           // [cap][hidden]
     float *dxm = nullptr;                 // [cap][dim]
+    float *splitk = nullptr;              // split-K partials of the weight gradients
+    double *colpart = nullptr;            // column-sum partials [kColSlices][max(hidden, 2 dim)]
 };
 
 namespace {
@@ -409,12 +454,12 @@ hipError_t alloc(T **p, int64_t count)
 void free_batch(gw_flow *f)
 {
     void *ptrs[] = {f->bound, f->s_store, f->sum_s, f->loss, f->g, f->gy, f->xm_b, f->h1_b, f->h2_b,
-                    f->out_f, f->dout_f, f->dout_b, f->dh, f->dpre_b, f->dxm};
+                    f->out_f, f->dout_f, f->dout_b, f->dh, f->dpre_b, f->dxm, f->splitk, f->colpart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    f->bound = f->s_store = f->sum_s = f->loss = f->g = f->gy = nullptr;
+    f->bound = f->s_store = f->sum_s = f->loss = f->g = f->gy = f->colpart = nullptr;
     f->xm_b = f->h1_b = f->h2_b = f->dout_b = f->dpre_b = nullptr;
-    f->out_f = f->dout_f = f->dh = f->dxm = nullptr;
+    f->out_f = f->dout_f = f->dh = f->dxm = f->splitk = nullptr;
     f->cap = 0;
 }
 
@@ -430,7 +475,9 @@ int ensure_batch(gw_flow *f, int64_t n)
         alloc(&f->loss, c) || alloc(&f->g, c * D) || alloc(&f->gy, c * D) || alloc(&f->xm_b, L * c * kInPad) ||
         alloc(&f->h1_b, L * c * H) || alloc(&f->h2_b, L * c * H) || alloc(&f->out_f, c * 2 * D) ||
         alloc(&f->dout_f, c * kOutPad) || alloc(&f->dout_b, c * kOutPad) || alloc(&f->dh, c * H) ||
-        alloc(&f->dpre_b, c * H) || alloc(&f->dxm, c * D)) {
+        alloc(&f->dpre_b, c * H) || alloc(&f->dxm, c * D) ||
+        alloc(&f->splitk, (int64_t)gw::flow::kMaxSplit * std::max<int64_t>(H, 2 * D) * H) ||
+        alloc(&f->colpart, (int64_t)gw::flow::kColSlices * std::max<int64_t>(H, 2 * D))) {
         free_batch(f);
         return fail(GW_ENOMEM, "flow batch buffers");
     }
@@ -515,9 +562,21 @@ hipError_t forward_pass(gw_flow *f, int n, const double *z, hipStream_t s)
 
 // Gradient of the mean negative log density of rows x[0, n) with respect to
 // every parameter (into f->grads); the mean loss goes to loss_out (device).
+// Column sums of m [n][cols] (leading dimension ld) into out [cols].
+hipError_t column_sum(gw_flow *f, int n, int cols, int ld, const float *m, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(gw::flow::column_partial_kernel, dim3(blocks_for(cols), gw::flow::kColSlices), dim3(256), 0, s,
+                       n, cols, ld, m, f->colpart);
+    GW_TRY(hipGetLastError());
+    hipLaunchKernelGGL(gw::flow::column_finish_kernel, dim3(blocks_for(cols)), dim3(256), 0, s, cols, f->colpart, out);
+    return hipGetLastError();
+}
+
 hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipStream_t s)
 {
     const int D = f->dim, H = f->hidden, L = f->layers;
+    // weight gradients sum over the n rows: split K = n into slices of >= 256 rows
+    const int split = std::max(1, std::min(gw::flow::kMaxSplit, n / 256));
     GW_TRY(inverse_pass(f, n, x, s));
     hipLaunchKernelGGL(gw::flow::base_density_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, boundary(f, 0),
                        f->sum_s, nullptr, f->loss);
@@ -540,21 +599,20 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
                            f->dout_f, f->gy);
         GW_TRY(hipGetLastError());
         // layer 3: dW3 = dout^T h2, db3 = colsum(dout), dh2 = dout W3
-        GemmArgs gw3{2 * D, H, n, f->dout_b, 1, kOutPad, h2, H, 1, f->grads + o.w3, H, nullptr, 0, nullptr, 0};
+        GemmArgs gw3{2 * D, H, n, f->dout_b, 1, kOutPad, h2, H, 1, f->grads + o.w3, H, nullptr, 0, nullptr, 0,
+                     split, f->splitk};
         GW_TRY(gw::flow::gemm_bf16(gw3, s));
-        hipLaunchKernelGGL(gw::flow::column_sum_kernel, dim3(1), dim3(256), 0, s, n, 2 * D, kOutPad, f->dout_f,
-                           f->grads + o.b3);
-        GW_TRY(hipGetLastError());
+        GW_TRY(column_sum(f, n, 2 * D, kOutPad, f->dout_f, f->grads + o.b3, s));
         GemmArgs gh2{n, H, 2 * D, f->dout_b, kOutPad, 1, f->wb + o.w3, H, 1, f->dh, H, nullptr, 0, nullptr, 0};
         GW_TRY(gw::flow::gemm_bf16(gh2, s));
         hipLaunchKernelGGL(gw::flow::relu_backward_kernel, dim3(blocks_for((int64_t)n * H)), dim3(256), 0, s,
                            (int64_t)n * H, f->dh, h2, f->dpre_b);
         GW_TRY(hipGetLastError());
         // layer 2: dW2 = dpre2^T h1, db2 = colsum(dpre2), dh1 = dpre2 W2
-        GemmArgs gw2{H, H, n, f->dpre_b, 1, H, h1, H, 1, f->grads + o.w2, H, nullptr, 0, nullptr, 0};
+        GemmArgs gw2{H, H, n, f->dpre_b, 1, H, h1, H, 1, f->grads + o.w2, H, nullptr, 0, nullptr, 0,
+                     split, f->splitk};
         GW_TRY(gw::flow::gemm_bf16(gw2, s));
-        hipLaunchKernelGGL(gw::flow::column_sum_kernel, dim3(1), dim3(256), 0, s, n, H, H, f->dh, f->grads + o.b2);
-        GW_TRY(hipGetLastError());
+        GW_TRY(column_sum(f, n, H, H, f->dh, f->grads + o.b2, s));
         GemmArgs gh1{n, H, H, f->dpre_b, H, 1, f->wb + o.w2, H, 1, f->dh, H, nullptr, 0, nullptr, 0};
         // dh1 overwrites dh only after the two reads above have been enqueued before it (stream order)
         GW_TRY(gw::flow::gemm_bf16(gh1, s));
@@ -562,10 +620,10 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
                            (int64_t)n * H, f->dh, h1, f->dpre_b);
         GW_TRY(hipGetLastError());
         // layer 1: dW1 = dpre1^T xm, db1 = colsum(dpre1), dxm = dpre1 W1
-        GemmArgs gw1{H, D, n, f->dpre_b, 1, H, xm, kInPad, 1, f->grads + o.w1, D, nullptr, 0, nullptr, 0};
+        GemmArgs gw1{H, D, n, f->dpre_b, 1, H, xm, kInPad, 1, f->grads + o.w1, D, nullptr, 0, nullptr, 0,
+                     split, f->splitk};
         GW_TRY(gw::flow::gemm_bf16(gw1, s));
-        hipLaunchKernelGGL(gw::flow::column_sum_kernel, dim3(1), dim3(256), 0, s, n, H, H, f->dh, f->grads + o.b1);
-        GW_TRY(hipGetLastError());
+        GW_TRY(column_sum(f, n, H, H, f->dh, f->grads + o.b1, s));
         GemmArgs gx{n, D, H, f->dpre_b, H, 1, f->wb + o.w1, D, 1, f->dxm, D, nullptr, 0, nullptr, 0};
         GW_TRY(gw::flow::gemm_bf16(gx, s));
         hipLaunchKernelGGL(gw::flow::add_input_grad_kernel, dim3(blocks_for((int64_t)n * D)), dim3(256), 0, s, n, D,

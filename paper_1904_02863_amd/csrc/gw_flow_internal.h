@@ -27,7 +27,14 @@ struct GemmArgs {
     int64_t ldcb;
     const float *bias;     // [N] (may be null)
     int relu;
+    // split-K: with split > 1 the K range is cut into `split` slices whose
+    // FP32 partial products go to partial [split][M][N]; a second kernel sums
+    // them in slice order and applies bias, ReLU and the outputs
+    int split = 1;
+    float *partial = nullptr;
 };
+
+constexpr int kMaxSplit = 16;
 
 hipError_t gemm_bf16(const GemmArgs &g, hipStream_t stream);
 

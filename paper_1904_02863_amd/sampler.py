@@ -8,7 +8,8 @@ together, every step is one batched likelihood call, and every proposal,
 random number and acceptance decision is computed by the library's kernels:
 
 * random-walk MH: x' = x + L z (Philox normals), L the Cholesky factor of
-  (2.38^2/d) times the chains' sample covariance, adapted during burn-in;
+  (2.38^2/d) times the chains' sample covariance and a global scale tuned
+  toward 23.4% acceptance, both adapted during burn-in;
 * learned proposal: an affine-coupling flow (gw_flow) trained by maximum
   likelihood on random-walk samples, used as an independence proposal
   x' = F(z); the exact likelihood stays the judge, and a chain whose flow
@@ -113,17 +114,24 @@ def init_chains(problem: Problem, x0: np.ndarray, ws: Workspace) -> ChainState:
 
 
 def run_random_walk(problem: Problem, state: ChainState, n_steps: int, seed: int, chol: np.ndarray, ws: Workspace,
-                    adapt_every: int = 0, record_every: int = 0):
+                    adapt_every: int = 0, record_every: int = 0, record_track: int | None = None,
+                    collect_every: int = 0, target_accept: float = 0.234):
     """n_steps random-walk MH steps on every chain.  With adapt_every > 0 the
-    proposal Cholesky factor is re-estimated from the chains that often.
-    Returns (records [n_records, n_chains, dim] or None, acceptance rate,
-    seconds, final Cholesky factor)."""
+    proposal is re-fitted that often: the Cholesky factor of (2.38^2/d) times
+    the chains' sample covariance, times a global scale that a Robbins-Monro
+    step moves toward the acceptance rate target_accept over the last window
+    (0.234, the optimum of Roberts, Gelman & Gilks 1997, by default).
+    Records the first record_track chains every record_every steps and
+    collects all chains every collect_every steps.  Returns (records
+    [n_records, track, dim] or None, acceptance rate, seconds, final Cholesky
+    factor, collected [n_collect * n_chains, dim] or None)."""
     import torch
     n, dim = state.x.shape
     dev = state.x.device
     buf = _Buffers(torch, n, dim, dev)
     chol_t = torch.from_numpy(np.ascontiguousarray(chol)).to(dev)
-    records = []
+    records, collected = [], []
+    log_scale, window_start = 0.0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(n_steps):
@@ -133,14 +141,21 @@ def run_random_walk(problem: Problem, state: ChainState, n_steps: int, seed: int
         mcmc_accept(seed, step, state.x, state.lnp, buf.x_prop, buf.lnl, buf.lp, total_accepts=buf.total)
         state.step += 1
         if adapt_every and (i + 1) % adapt_every == 0:
-            chol = adapted_cholesky(state.x.cpu().numpy())
+            accepted = int(buf.total.sum().item())
+            rate = (accepted - window_start) / (n * adapt_every)
+            window_start = accepted
+            log_scale = float(np.clip(log_scale + 2.0 * (rate - target_accept), -8.0, 2.0))
+            chol = adapted_cholesky(state.x.cpu().numpy()) * math.exp(log_scale)
             chol_t = torch.from_numpy(np.ascontiguousarray(chol)).to(dev)
         if record_every and (i + 1) % record_every == 0:
-            records.append(state.x.cpu().numpy())
+            records.append(state.x[:record_track].cpu().numpy())
+        if collect_every and (i + 1) % collect_every == 0:
+            collected.append(state.x.cpu().numpy())
     torch.cuda.synchronize()
     seconds = time.perf_counter() - t0
     rate = float(buf.total.sum().item()) / (n * max(n_steps, 1))
-    return (np.stack(records) if records else None), rate, seconds, chol
+    return ((np.stack(records) if records else None), rate, seconds, chol,
+            (np.concatenate(collected) if collected else None))
 
 
 # ---------------------------------------------------------------- flow
@@ -208,7 +223,8 @@ def train_flow(samples: np.ndarray, n_layers: int = 8, hidden: int = 256, steps:
 
 
 def run_flow_mh(problem: Problem, state: ChainState, flow: Flow, n_steps: int, seed: int, chol: np.ndarray,
-                ws: Workspace, window: int = 64, threshold: float = 0.05, record_every: int = 0):
+                ws: Workspace, window: int = 64, threshold: float = 0.05, record_every: int = 0,
+                record_track: int | None = None):
     """Independence MH with flow proposals (random-walk fallback per chain).
     Returns (records or None, acceptance rate, seconds, fraction of chain-steps
     in fallback mode)."""
@@ -236,7 +252,7 @@ def run_flow_mh(problem: Problem, state: ChainState, flow: Flow, n_steps: int, s
             flow.inverse(state.x, z_out=buf.z, logq_out=state.logq)     # refresh after random-walk moves
             fallback += int(mode.sum().item()) * window
         if record_every and (i + 1) % record_every == 0:
-            records.append(state.x.cpu().numpy())
+            records.append(state.x[:record_track].cpu().numpy())
     torch.cuda.synchronize()
     seconds = time.perf_counter() - t0
     rate = float(buf.total.sum().item()) / (n * max(n_steps, 1))
