@@ -279,3 +279,39 @@ def bns_ragged(n_events: int = 256, n_samples: int = 512, index: int = 2,
         theta = draw(g["samples"], n_samples)
         events.append(RaggedEvent(grid, tensors, vertices, s, nz, inj, theta))
     return events
+
+
+def population_samples(n_events: int, n_per_event: int, index: int = 5) -> np.ndarray:
+    """Stand-in posterior samples for population studies: [7, n_events, n]
+    with fields m1, q, a1, a2, cos t1, cos t2, ln p(theta | 0).
+
+    Each event has a true (m1, q, a1, a2, cos t1, cos t2): m1 log-uniform in
+    [8, 60] solar masses, q U[0.3, 1], a U[0, 1], cos t U[-1, 1].  Its samples
+    scatter around the truth with measurement-like widths (m1 10-25%,
+    q 0.15, a 0.25, cos t 0.5), kept inside the support of the sampling prior
+    (uniform in m1 on [2, 100], in q on [0.05, 1], in a on [0, 1], in cos t on
+    [-1, 1]) by redrawing; ln p(theta | 0) is that prior's log density."""
+    g = seeds(index)
+    rng = g["samples"]
+    truth = g["injection"]
+    m1_t = np.exp(truth.uniform(math.log(8.0), math.log(60.0), n_events))
+    q_t = truth.uniform(0.3, 1.0, n_events)
+    a_t = truth.uniform(0.0, 1.0, (2, n_events))
+    c_t = truth.uniform(-1.0, 1.0, (2, n_events))
+    rel = truth.uniform(0.10, 0.25, n_events)
+    lo = np.array([2.0, 0.05, 0.0, 0.0, -1.0, -1.0])
+    hi = np.array([100.0, 1.0, 1.0, 1.0, 1.0, 1.0])
+    centre = np.stack([m1_t, q_t, a_t[0], a_t[1], c_t[0], c_t[1]])          # [6, events]
+    width = np.stack([rel * m1_t, np.full(n_events, 0.15), np.full(n_events, 0.25), np.full(n_events, 0.25),
+                      np.full(n_events, 0.5), np.full(n_events, 0.5)])
+    out = np.empty((7, n_events, n_per_event))
+    for f in range(6):
+        x = centre[f][:, None] + width[f][:, None] * rng.standard_normal((n_events, n_per_event))
+        bad = (x < lo[f]) | (x > hi[f])
+        while bad.any():
+            x[bad] = (np.broadcast_to(centre[f][:, None], x.shape)[bad]
+                      + np.broadcast_to(width[f][:, None], x.shape)[bad] * rng.standard_normal(int(bad.sum())))
+            bad = (x < lo[f]) | (x > hi[f])
+        out[f] = x
+    out[6] = -float(np.log(hi - lo).sum())
+    return out
