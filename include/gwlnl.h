@@ -215,6 +215,35 @@ int gw_lnl_ragged(gw_workspace *ws, int n_events, const gw_event *events,
                   const double *theta_packed, int n_param,
                   double *lnl_out_packed, int precision, unsigned flags, hipStream_t stream);
 
+/*
+ * gw_pop_lnl -- the recycled population likelihood of Eq. (poplike), Sec. IV:
+ *     ln L(Lambda) = sum_i ln[ (1/n) sum_j p(theta_ij | Lambda) / p(theta_ij | 0) ]
+ * for each of n_hyper hyper-parameter points, over n posterior samples of
+ * each of n_events events, without the rate and selection factors
+ * R^N e^{-R VT(Lambda)} (the paper leaves VT out of its timings).
+ * The population model (named, not printed, in Sec. IV): primary mass a
+ * power law m1^-alpha plus a Gaussian peak N(mu_m, sigma_m), mixed with
+ * weight lam, on [m_min, m_max]; q = m2/m1 a power law q^beta on
+ * [m_min/m1, 1]; spin magnitudes a1, a2 Beta(alpha_chi, beta_chi); spin tilt
+ * cosines (1 - xi)/4 + xi N_T(c1; 1, sigma_1) N_T(c2; 1, sigma_2) on
+ * [-1, 1]^2 (N_T a Gaussian truncated to [-1, 1]).  Every factor is
+ * normalised in closed form.
+ *   samples  device, field-major [7][n_events][n]: m1 (solar masses), q, a1,
+ *            a2, cos t1, cos t2, and ln p(theta | 0), the log density of the
+ *            prior the samples were drawn under.  A sample outside the
+ *            supports (q not in (0, 1], a or cos t outside their ranges,
+ *            non-finite ln prior) has weight 0.
+ *   hyper    device [n_hyper][12]: alpha, beta, m_min, m_max, lam, mu_m,
+ *            sigma_m, alpha_chi, beta_chi, xi, sigma_1, sigma_2.
+ *   lnl_out  device [n_hyper].  A point outside its domain (m_min >= m_max or
+ *            <= 0, a width <= 0, lam or xi outside [0, 1], alpha_chi or
+ *            beta_chi <= 0) gives -infinity; a non-finite one NaN; an event
+ *            whose samples all have weight 0 gives -infinity.
+ * Uses the workspace (a call with other shapes relays it out).
+ */
+int gw_pop_lnl(gw_workspace *ws, int64_t n_events, int64_t n_per_event, const double *samples, int64_t n_hyper,
+               const double *hyper, double *lnl_out, hipStream_t stream);
+
 /* Tile shape the last gw_lnl_ragged call used: bins staged in LDS per tile and
  * bins per work item.  The first call for a new size class times every
  * candidate shape once (several passes, results overwritten) and keeps the

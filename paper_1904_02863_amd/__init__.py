@@ -32,7 +32,7 @@ FLAG_ADD_NORM = 4
 # Every symbol include/gwlnl.h declares.
 EXPORTED = ("gw_workspace_create", "gw_workspace_destroy", "gw_workspace_reserve", "gw_workspace_bytes",
             "gw_workspace_set_timing", "gw_workspace_kernel_time", "gw_waveform_batch", "gw_lnl_batch",
-            "gw_lnl_ragged", "gw_ragged_tuning", "gw_last_error", "gw_version",
+            "gw_lnl_ragged", "gw_ragged_tuning", "gw_pop_lnl", "gw_last_error", "gw_version",
             "gw_philox_raw", "gw_philox_fill", "gw_philox_chain_normals", "gw_mcmc_to_theta", "gw_mcmc_rw_propose",
             "gw_mcmc_accept", "gw_mcmc_update_mode", "gw_flow_create", "gw_flow_destroy", "gw_flow_num_params",
             "gw_flow_set_params", "gw_flow_get_params", "gw_flow_forward", "gw_flow_inverse", "gw_flow_gradients",
@@ -82,6 +82,7 @@ def load_library() -> ctypes.CDLL:
                                      i64, vp, i32, u32, vp]
         lib.gw_lnl_ragged.argtypes = [vp, i32, ctypes.POINTER(GwEvent), vp, vp, vp, i32, vp, i32, u32, vp]
         lib.gw_ragged_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        lib.gw_pop_lnl.argtypes = [vp, i64, i64, vp, i64, vp, vp, vp]
         u64, u32p = ctypes.c_uint64, ctypes.c_uint32
         lib.gw_philox_raw.argtypes = [u64, u32p, u32p, u64, i64, vp, vp]
         lib.gw_philox_fill.argtypes = [u64, u32p, u32p, i32, i64, vp, vp]
@@ -317,6 +318,30 @@ def lnl_ragged(events, n_events: int, data_packed, psd_packed, theta_packed, *, 
     _check(load_library().gw_lnl_ragged(ws.handle, int(n_events), events, data_packed.data_ptr(),
                                         psd_packed.data_ptr(), theta_packed.data_ptr(), n_param, out.data_ptr(),
                                         PRECISIONS[precision], int(flags), _stream_ptr(dev, stream)))
+    return out
+
+
+def pop_lnl(samples, hyper, *, out=None, workspace: Workspace | None = None, stream=None):
+    """Population ln L (Eq. (poplike)) for every row of hyper [K, 12] over
+    samples [7, n_events, n] (m1, q, a1, a2, cos t1, cos t2, ln prior), both
+    float64 on the same GPU; returns float64 [K] there."""
+    torch = _torch()
+    samples = _cuda_tensor(samples, torch.float64, "samples")
+    if samples.dim() != 3 or samples.shape[0] != 7:
+        raise ValueError("samples must be [7, n_events, n_per_event]")
+    hyper = _cuda_tensor(hyper, torch.float64, "hyper")
+    if hyper.dim() != 2 or hyper.shape[1] != 12:
+        raise ValueError("hyper must be [n_hyper, 12]")
+    dev = samples.device.index
+    if hyper.device.index != dev:
+        raise ValueError("samples and hyper must be on the same device")
+    k = hyper.shape[0]
+    if out is None:
+        out = torch.empty(k, dtype=torch.float64, device=samples.device)
+    out = _cuda_tensor(out, torch.float64, "out", (k,))
+    ws = workspace or default_workspace(dev)
+    _check(load_library().gw_pop_lnl(ws.handle, samples.shape[1], samples.shape[2], samples.data_ptr(), k,
+                                     hyper.data_ptr(), out.data_ptr(), _stream_ptr(dev, stream)))
     return out
 
 

@@ -36,6 +36,11 @@ struct gw_workspace {
     std::map<std::tuple<int, int, int>, std::pair<int, int64_t>> ragged_tuning;
     int last_tile_bins = 0;
     int64_t last_chunk_bins = 0;
+    // the bin tables (tab1, tab2) in the arena are those of this grid at
+    // these offsets, written by an earlier call on the workspace's stream order
+    bool tables_valid = false;
+    gw_grid tables_grid{};
+    size_t tables_tab1 = 0, tables_tab2 = 0;
 };
 
 namespace {
@@ -94,9 +99,29 @@ void drop_ragged_graph(gw_workspace *ws)
     ws->ragged_key.clear();
 }
 
+// Bin tables of `grid` at (tab1, tab2): launch their kernel unless the arena
+// already holds them there.
+hipError_t bin_tables(gw_workspace *ws, const gw_grid &grid, size_t off1, size_t off2, gw::Tab1 *tab1,
+                      gw::Tab2 *tab2, hipStream_t stream)
+{
+    if (ws->tables_valid && ws->tables_tab1 == off1 && ws->tables_tab2 == off2 &&
+        ws->tables_grid.f_low == grid.f_low && ws->tables_grid.delta_f == grid.delta_f &&
+        ws->tables_grid.n_bins == grid.n_bins)
+        return hipSuccess;
+    ws->tables_valid = false;
+    hipError_t e = gw::launch_event_tables(grid, tab1, tab2, stream);
+    if (e != hipSuccess) return e;
+    ws->tables_valid = true;
+    ws->tables_grid = grid;
+    ws->tables_tab1 = off1;
+    ws->tables_tab2 = off2;
+    return hipSuccess;
+}
+
 int ensure_capacity(gw_workspace *ws, size_t bytes)
 {
     if (bytes <= ws->capacity) return GW_OK;
+    ws->tables_valid = false;
     drop_ragged_graph(ws);               // its kernels point into the old arena
     if (ws->base) {
         hipError_t e = hipDeviceSynchronize();
@@ -239,7 +264,8 @@ int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::De
     auto *rec = at<double>(ws, l.records);
     auto *part = at<double2>(ws, l.partials);
     hipError_t e;
-    if ((e = gw::launch_event_tables(grid, eb.tab1, eb.tab2, stream)) != hipSuccess) return hip_fail(e, "event tables");
+    if ((e = bin_tables(ws, grid, l.tab1, l.tab2, eb.tab1, eb.tab2, stream)) != hipSuccess)
+        return hip_fail(e, "event tables");
     if ((e = gw::launch_event_data(grid, n_det, data, psd, eb, flags, stream)) != hipSuccess)
         return hip_fail(e, "event data");
     if ((e = gw::launch_sample_prep(grid, n_samples, n_param, n_det, false, isco, geom, theta, rec, stream)) !=
@@ -402,6 +428,7 @@ int ragged_materialise(gw_workspace *ws, int n_events, const gw_event *events, c
     RaggedPlan sizing = ragged_plan(ws, n_events, events, data, psd, theta, n_param, lnl, mixed, flags, tile_bins,
                                     chunk_bins, nullptr);
     if (int rc = ensure_capacity(ws, sizing.total)) return rc;
+    ws->tables_valid = false;            // the ragged layout overwrites the arena
     *out = ragged_plan(ws, n_events, events, data, psd, theta, n_param, lnl, mixed, flags, tile_bins, chunk_bins,
                        static_cast<char *>(ws->base));
     char *base = static_cast<char *>(ws->base);
@@ -710,7 +737,7 @@ int gw_waveform_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw
     auto *tab2 = at<gw::Tab2>(ws, o2);
     auto *rec = at<double>(ws, orec);
     hipError_t e;
-    if ((e = gw::launch_event_tables(*grid, tab1, tab2, stream)) != hipSuccess) return hip_fail(e, "event tables");
+    if ((e = bin_tables(ws, *grid, o1, o2, tab1, tab2, stream)) != hipSuccess) return hip_fail(e, "event tables");
     if ((e = gw::launch_sample_prep(*grid, n_samples, n_param, n_out, polar, (flags & GW_FLAG_TERM_ISCO) != 0, geom,
                                     theta, rec, stream)) != hipSuccess)
         return hip_fail(e, "sample prep");
@@ -743,6 +770,24 @@ int gw_lnl_ragged(gw_workspace *ws, int n_events, const gw_event *events, const 
     if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
     return ragged_run(ws, n_events, events, geoms, data_packed, psd_packed, theta_packed, n_param, lnl_out_packed,
                       precision == GW_PREC_MIXED, flags, stream);
+}
+
+int gw_pop_lnl(gw_workspace *ws, int64_t n_events, int64_t n_per_event, const double *samples, int64_t n_hyper,
+               const double *hyper, double *lnl_out, hipStream_t stream)
+{
+    if (!ws) return fail(GW_EINVAL, "workspace is NULL");
+    if (n_events < 1 || n_per_event < 1 || n_hyper < 0) return fail(GW_EINVAL, "bad population sizes");
+    if (!samples || (n_hyper > 0 && (!hyper || !lnl_out))) return fail(GW_EINVAL, "NULL population argument");
+    if (gw::pop::weight_blocks(n_events, n_per_event) > 0x7fffffffLL || n_hyper > 0x7fffffffLL)
+        return fail(GW_EINVAL, "population batch too large for one launch");
+    if (n_hyper == 0) return GW_OK;
+    DeviceGuard g(ws->device);
+    if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
+    drop_ragged_graph(ws);               // the arena is about to be laid out for the population pass
+    if (int rc = ensure_capacity(ws, gw::pop::workspace_bytes(n_events, n_per_event, n_hyper))) return rc;
+    ws->tables_valid = false;
+    hipError_t e = gw::pop::launch(n_events, n_per_event, samples, n_hyper, hyper, ws->base, lnl_out, stream);
+    return e == hipSuccess ? GW_OK : hip_fail(e, "gw_pop_lnl");
 }
 
 int gw_ragged_tuning(const gw_workspace *ws, int *tile_bins, int64_t *chunk_bins)

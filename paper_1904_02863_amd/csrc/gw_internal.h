@@ -29,13 +29,11 @@ enum RecordField : int {
 };
 constexpr int record_fields(int n_out) { return kRecDet + kRecFieldsPerDet * n_out; }
 
-// Per-event sums: [0] <d,d> over all detectors, [1 + d] Q_d = 4 df sum a^2 / S_d,
-// [kSumNorm] sum over detectors and bins of ln(2 pi S).
-constexpr int kSumNorm = 1 + kMaxDet;
-constexpr int kEventSums = 2 + kMaxDet;
 // Per event-preparation block and detector: sums of |d|^2/S, a^2/S, ln(2 pi S)
-// over the block's 256 consecutive bins.
+// over the block's 256 consecutive bins.  The event sums hold the same three
+// quantities summed over all bins, at [kPrepPerDet d + 0, 1, 2].
 constexpr int kPrepPerDet = 3;
+constexpr int kEventSums = kPrepPerDet * kMaxDet;
 
 // What the tile kernel accumulates.
 enum TileForm : int {
@@ -174,6 +172,15 @@ hipError_t launch_waveform(const gw_grid &grid, int n_out, int64_t n_samples, co
 
 hipError_t launch_ragged(const RaggedLaunch &r, hipStream_t stream);
 int lnl_ragged_blocks_per_cu(int n_det, int tile_bins, bool mixed, int form);
+
+// Population likelihood (gw_pop.hip): workspace bytes, weight-kernel blocks
+// and the launch of the hyper-parameter, weights and finalize kernels.
+namespace pop {
+size_t workspace_bytes(int64_t n_events, int64_t n_per, int64_t n_hyper);
+int64_t weight_blocks(int64_t n_events, int64_t n_per);
+hipError_t launch(int64_t n_events, int64_t n_per, const double *samples, int64_t n_hyper, const double *hyper,
+                  void *work, double *lnl, hipStream_t stream);
+}  // namespace pop
 
 // LDS bytes of the tile kernel and its occupancy.
 size_t lnl_tile_lds_bytes(int n_det, int tile_bins, int form);

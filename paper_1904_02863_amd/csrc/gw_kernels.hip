@@ -118,47 +118,50 @@ __device__ __forceinline__ double block_sum(double x, double *red)
     return total;
 }
 
-// Block b of an event's preparation: bins [256 b, 256 b + 256); thread 0
-// writes the block's sums out[kPrepPerDet d + j].
+// Sum over the 64 lanes of a wave by a fixed butterfly (lane 0's value is
+// the one used).
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Block b of an event's preparation: bins [256 b, 256 b + 256); writes the
+// block's sums out[kPrepPerDet d + j] (wave sums, then the 4 waves in order).
+// `red` holds at least 4 kPrepPerDet kMaxDet doubles of LDS.
 __device__ __forceinline__ void prep_block(const PrepView &v, int64_t b, bool direct, bool norm, double *red,
                                            double *__restrict__ out)
 {
-    double acc[kPrepPerDet * kMaxDet];
+    constexpr int kQ = kPrepPerDet * kMaxDet;
+    double acc[kQ];
 #pragma unroll
-    for (int i = 0; i < kPrepPerDet * kMaxDet; ++i) acc[i] = 0.0;
+    for (int i = 0; i < kQ; ++i) acc[i] = 0.0;
     const int64_t k = b * kBlock + threadIdx.x;
     if (k < v.n_bins) bin_data(v, k, direct, norm, acc);
-    for (int j = 0; j < kPrepPerDet * v.n_det; ++j) {
-        double x = 0.0;
+    const int nq = kPrepPerDet * v.n_det, lane = threadIdx.x % 64, wave = threadIdx.x / 64;
 #pragma unroll
-        for (int i = 0; i < kPrepPerDet * kMaxDet; ++i)
-            if (i == j) x = acc[i];
-        const double total = block_sum(x, red);
-        if (threadIdx.x == 0) out[j] = total;
+    for (int j = 0; j < kQ; ++j) {
+        if (j < nq) {
+            const double t = wave_sum(acc[j]);
+            if (lane == 0) red[wave * kQ + j] = t;
+        }
     }
+    __syncthreads();
+    if ((int)threadIdx.x < nq)
+        out[threadIdx.x] = ((red[threadIdx.x] + red[kQ + threadIdx.x]) + red[2 * kQ + threadIdx.x]) +
+                           red[3 * kQ + threadIdx.x];
+    __syncthreads();
 }
 
-// Sums the per-block partials of one event in a fixed order into
-// sums[0] = <d,d>, sums[1 + d] = Q_d, sums[kSumNorm] = sum ln(2 pi S).
-__device__ __forceinline__ void sum_event_partials(int n_blocks, int n_det, double df,
-                                                   const double *__restrict__ partials, double *red,
-                                                   double *__restrict__ sums)
+// Column j of an event's per-block partials summed over its n_blocks blocks
+// (strided per thread, then a fixed tree): the event-wide sum of quantity j.
+__device__ __forceinline__ double column_total(int n_blocks, int per, int j, const double *__restrict__ partials,
+                                               double *red)
 {
-    double total_dd = 0.0, total_norm = 0.0;
-    const int per = kPrepPerDet * n_det;
-    for (int j = 0; j < per; ++j) {
-        double x = 0.0;
-        for (int b = threadIdx.x; b < n_blocks; b += kBlock) x += partials[(int64_t)b * per + j];
-        const double total = block_sum(x, red);
-        const int kind = j % kPrepPerDet, d = j / kPrepPerDet;
-        if (kind == 0) total_dd += 4.0 * df * total;
-        else if (kind == 1) { if (threadIdx.x == 0) sums[1 + d] = 4.0 * df * total; }
-        else total_norm += total;
-    }
-    if (threadIdx.x == 0) {
-        sums[0] = total_dd;
-        sums[kSumNorm] = total_norm;
-    }
+    double x = 0.0;
+    for (int b = threadIdx.x; b < n_blocks; b += kBlock) x += partials[(int64_t)b * per + j];
+    return block_sum(x, red);
 }
 
 // Prefix sums of a^2/S for the ISCO end: block b of the event writes
@@ -210,12 +213,14 @@ __global__ __launch_bounds__(kBlock) void event_data_kernel(PrepView v, int dire
     prep_block(v, blockIdx.x, direct != 0, norm != 0, red, partials + (int64_t)blockIdx.x * kPrepPerDet * v.n_det);
 }
 
-__global__ __launch_bounds__(kBlock) void event_sums_kernel(int n_blocks, int n_det, double df,
+// Block j: sums[j] = the event-wide sum of quantity j (kPrepPerDet n_det blocks).
+__global__ __launch_bounds__(kBlock) void event_sums_kernel(int n_blocks, int n_det,
                                                              const double *__restrict__ partials,
                                                              double *__restrict__ sums)
 {
     __shared__ double red[kBlock];
-    sum_event_partials(n_blocks, n_det, df, partials, red, sums);
+    const double t = column_total(n_blocks, kPrepPerDet * n_det, blockIdx.x, partials, red);
+    if (threadIdx.x == 0) sums[blockIdx.x] = t;
 }
 
 __global__ __launch_bounds__(kBlock) void event_prefix_kernel(PrepView v, const double *__restrict__ partials,
@@ -261,7 +266,10 @@ __global__ __launch_bounds__(kBlock) void ragged_event_sums_kernel(const RaggedE
 {
     __shared__ double red[kBlock];
     const RaggedEvent &re = events[blockIdx.x];
-    sum_event_partials(re.prep_blocks, re.n_det, re.df, re.prep, red, re.sums);
+    for (int j = 0; j < kPrepPerDet * re.n_det; ++j) {
+        const double t = column_total(re.prep_blocks, kPrepPerDet * re.n_det, j, re.prep, red);
+        if (threadIdx.x == 0) re.sums[j] = t;
+    }
 }
 
 // Ragged batch: prefix sums of a^2/S, blocks as in ragged_event_prep_kernel.
@@ -740,47 +748,73 @@ __global__ __launch_bounds__(kBlock) GW_TILE_ATTR void lnl_ragged_kernel(const R
     }
 }
 
-// lnL of row s.  Split forms: -1/2 <d,d> + sum_det [Re(P Z) - 1/2 |P|^2 Q_det],
-// Q_det from the event sums, or with the ISCO end 4 df times the prefix sum
-// of a^2/S up to K_s.  Direct form: -2 df times the summed residual.  Chunks
-// are summed in order; GW_FLAG_ADD_NORM subtracts sum ln(2 pi S).
-__device__ __forceinline__ double finalize_row(int64_t s, int64_t n_samples, int n_det, int n_chunks,
-                                               int64_t n_bins, double df, unsigned flags,
-                                               const double2 *__restrict__ partials, const double *__restrict__ rec,
-                                               const double *__restrict__ sums, const double *__restrict__ qprefix)
+// lnL of row s from its chunk totals: split forms -1/2 <d,d> + sum_det
+// [Re(P Z_det) - 1/2 |P|^2 Q_det], Q_det from the event sums or, with the
+// ISCO end, 4 df times the prefix sum of a^2/S up to K_s; direct form -2 df
+// times the residual sum.  GW_FLAG_ADD_NORM subtracts sum ln(2 pi S).
+// sums: the event-wide totals of |d|^2/S, a^2/S, ln(2 pi S) per detector.
+__device__ __forceinline__ double assemble_row(int64_t s, int64_t n_samples, int n_det, int64_t n_bins, double df,
+                                               unsigned flags, const double *zr, const double *zi, double resid,
+                                               const double *__restrict__ rec, const double *__restrict__ sums,
+                                               const double *__restrict__ qprefix)
 {
-    const double dd = sums[0];
+    double dd = 0.0, norm = 0.0;
+    for (int d = 0; d < n_det; ++d) {
+        dd += sums[kPrepPerDet * d];
+        norm += sums[kPrepPerDet * d + 2];
+    }
+    dd *= 4.0 * df;
     double out;
     if (flags & GW_FLAG_DIRECT) {
-        const double *pd = reinterpret_cast<const double *>(partials);
-        double acc = 0.0;
-        for (int c = 0; c < n_chunks; ++c) acc += pd[(int64_t)c * n_samples + s];
-        out = -2.0 * df * acc;
+        out = -2.0 * df * resid;
     } else {
         const bool isco = (flags & GW_FLAG_TERM_ISCO) != 0;
         const int64_t kcut = (int64_t)rec[kRecKcut * n_samples + s];
         double acc = -0.5 * dd;
         for (int d = 0; d < n_det; ++d) {
-            double zr = 0.0, zi = 0.0;
-            for (int c = 0; c < n_chunks; ++c) {
-                const double2 z = partials[((int64_t)c * n_samples + s) * n_det + d];
-                zr += z.x;
-                zi += z.y;
-            }
             const double pr = rec[(kRecDet + kRecFieldsPerDet * d) * n_samples + s];
             const double pi = rec[(kRecDet + kRecFieldsPerDet * d + 1) * n_samples + s];
-            double q = sums[1 + d];
+            double q = 4.0 * df * sums[kPrepPerDet * d + 1];
             if (isco) q = kcut >= 0 ? 4.0 * df * qprefix[(int64_t)d * n_bins + kcut] : 0.0;
-            acc += (pr * zr - pi * zi) - 0.5 * (pr * pr + pi * pi) * q;
+            acc += (pr * zr[d] - pi * zi[d]) - 0.5 * (pr * pr + pi * pi) * q;
         }
         out = acc;
     }
-    if (flags & GW_FLAG_ADD_NORM) out -= sums[kSumNorm];
+    if (flags & GW_FLAG_ADD_NORM) out -= norm;
     const int status = (int)rec[kRecStatus * n_samples + s];
     if (status == 1) out = -INFINITY;
     if (status == 2 || isnan(dd)) out = NAN;
     return out;
 }
+
+// Row s with its chunks summed in order (one thread per row).
+__device__ __forceinline__ double finalize_row(int64_t s, int64_t n_samples, int n_det, int n_chunks,
+                                               int64_t n_bins, double df, unsigned flags,
+                                               const double2 *__restrict__ partials, const double *__restrict__ rec,
+                                               const double *__restrict__ sums, const double *__restrict__ qprefix)
+{
+    double zr[kMaxDet], zi[kMaxDet], resid = 0.0;
+    if (flags & GW_FLAG_DIRECT) {
+        const double *pd = reinterpret_cast<const double *>(partials);
+        for (int c = 0; c < n_chunks; ++c) resid += pd[(int64_t)c * n_samples + s];
+    } else {
+        for (int d = 0; d < n_det; ++d) {
+            double r = 0.0, i = 0.0;
+            for (int c = 0; c < n_chunks; ++c) {
+                const double2 z = partials[((int64_t)c * n_samples + s) * n_det + d];
+                r += z.x;
+                i += z.y;
+            }
+            zr[d] = r;
+            zi[d] = i;
+        }
+    }
+    return assemble_row(s, n_samples, n_det, n_bins, df, flags, zr, zi, resid, rec, sums, qprefix);
+}
+
+// One event: 32 rows per block, 8 threads per row; thread part p sums chunks
+// p, p + 8, ... in order, then the parts are added in order 0..7.
+constexpr int kFinRows = 32, kFinParts = kBlock / kFinRows;
 
 __global__ __launch_bounds__(kBlock) void lnl_finalize_kernel(int64_t n_samples, int n_det, int n_chunks,
                                                                int64_t n_bins, double df, unsigned flags,
@@ -790,9 +824,46 @@ __global__ __launch_bounds__(kBlock) void lnl_finalize_kernel(int64_t n_samples,
                                                                const double *__restrict__ qprefix,
                                                                double *__restrict__ lnl)
 {
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= n_samples) return;
-    lnl[s] = finalize_row(s, n_samples, n_det, n_chunks, n_bins, df, flags, partials, rec, sums, qprefix);
+    __shared__ double red[kFinParts][kFinRows][2 * kMaxDet];
+    const int r = threadIdx.x % kFinRows, part = threadIdx.x / kFinRows;
+    const int64_t s = (int64_t)blockIdx.x * kFinRows + r;
+    const bool direct = (flags & GW_FLAG_DIRECT) != 0;
+    if (s < n_samples) {
+        if (direct) {
+            const double *pd = reinterpret_cast<const double *>(partials);
+            double acc = 0.0;
+            for (int c = part; c < n_chunks; c += kFinParts) acc += pd[(int64_t)c * n_samples + s];
+            red[part][r][0] = acc;
+        } else {
+            for (int d = 0; d < n_det; ++d) {
+                double zr = 0.0, zi = 0.0;
+                for (int c = part; c < n_chunks; c += kFinParts) {
+                    const double2 z = partials[((int64_t)c * n_samples + s) * n_det + d];
+                    zr += z.x;
+                    zi += z.y;
+                }
+                red[part][r][2 * d] = zr;
+                red[part][r][2 * d + 1] = zi;
+            }
+        }
+    }
+    __syncthreads();
+    if (part != 0 || s >= n_samples) return;
+    double zr[kMaxDet], zi[kMaxDet], resid = 0.0;
+    if (direct) {
+        for (int p = 0; p < kFinParts; ++p) resid += red[p][r][0];
+    } else {
+        for (int d = 0; d < n_det; ++d) {
+            double a = 0.0, b = 0.0;
+            for (int p = 0; p < kFinParts; ++p) {
+                a += red[p][r][2 * d];
+                b += red[p][r][2 * d + 1];
+            }
+            zr[d] = a;
+            zi[d] = b;
+        }
+    }
+    lnl[s] = assemble_row(s, n_samples, n_det, n_bins, df, flags, zr, zi, resid, rec, sums, qprefix);
 }
 
 // Ragged batch: block (event, group) finalizes the group's rows.
@@ -879,7 +950,7 @@ hipError_t launch_event_data(const gw_grid &grid, int n_det, const gw_c128 *data
     hipLaunchKernelGGL(event_data_kernel, dim3(eb.prep_blocks), dim3(kBlock), 0, stream, v, direct, norm, eb.prep);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(event_sums_kernel, dim3(1), dim3(kBlock), 0, stream, eb.prep_blocks, n_det, grid.delta_f,
+    hipLaunchKernelGGL(event_sums_kernel, dim3(kPrepPerDet * n_det), dim3(kBlock), 0, stream, eb.prep_blocks, n_det,
                        eb.prep, eb.sums);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (flags & GW_FLAG_TERM_ISCO) {
@@ -1032,9 +1103,10 @@ hipError_t launch_lnl_finalize(const gw_grid &grid, int64_t n_samples, int n_det
                                const double2 *partials, const double *records, const EventBuffers &eb,
                                unsigned flags, double *lnl_out, hipStream_t stream)
 {
-    hipLaunchKernelGGL(lnl_finalize_kernel, dim3(grid_blocks(n_samples, 1 << 30)), dim3(kBlock), 0, stream,
-                       n_samples, n_det, plan.n_chunks, grid.n_bins, grid.delta_f, flags, partials, records, eb.sums,
-                       eb.qprefix, lnl_out);
+    const int64_t blocks = (n_samples + kFinRows - 1) / kFinRows;
+    hipLaunchKernelGGL(lnl_finalize_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, n_samples, n_det,
+                       plan.n_chunks, grid.n_bins, grid.delta_f, flags, partials, records, eb.sums, eb.qprefix,
+                       lnl_out);
     return hipGetLastError();
 }
 

@@ -1,0 +1,243 @@
+// Population likelihood of Eq. (poplike), Sec. IV of arXiv:1904.02863, for
+// gfx950: the recycled hierarchical likelihood
+//     ln L(Lambda) = sum_i ln[ (1/n) sum_j p(theta_ij | Lambda) / p(theta_ij | 0) ]
+// for a batch of hyper-parameter points Lambda over the posterior samples of
+// N events (n samples each), without the rate and selection factors.
+//
+// The population model (the paper names its three components without
+// printing them): a power law plus a Gaussian peak in the primary mass on
+// [m_min, m_max]; a power law in q = m2/m1 on [m_min/m1, 1]; independent Beta
+// spin magnitudes; spin tilt cosines from a mixture of isotropic and two
+// Gaussians centred on aligned spins, truncated to [-1, 1].  Every
+// normalisation is closed-form and computed once per Lambda.
+//
+// Layout: samples field-major [7][N][n] (m1, q, a1, a2, cos t1, cos t2,
+// ln p(theta | 0)).  Each block keeps 4 samples per thread of one event in
+// registers (their logarithms computed once) and loops over every Lambda,
+// whose constants it reads with wave-uniform loads; each wave writes its own
+// partial sum, so the weights kernel has no barrier.  A finalize kernel sums
+// the partials of each (Lambda, event) in order, takes the log of the mean
+// and adds the events in order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+
+#include "gw_internal.h"
+
+namespace gw {
+namespace pop {
+
+constexpr int kThreads = 256;
+constexpr int kPerThread = 4;
+constexpr int kPerBlock = kThreads * kPerThread;   // samples of one event per block
+constexpr int kWaves = kThreads / 64;
+
+// Constants of one hyper-parameter point.
+struct HyperC {
+    double neg_alpha, ln_zpl;             // power law: m^-alpha / Z_pl
+    double mu, inv_sigma, ln_zg;          // peak: exp(-((m - mu)/sigma)^2 / 2) / (sigma sqrt(2 pi) Z_g)
+    double one_m_lam, lam;
+    double mmin, mmax, ln_mmin, beta, one_p_beta;
+    double ach_m1, bch_m1, ln_beta_fn;    // spin magnitudes
+    double iso, xi, k1, k2, ln_zt;        // tilts
+    int status;                           // 1 evaluate, 0 out of domain, -1 non-finite
+    int beta_is_m1;                       // beta == -1: log normalisation of q
+};
+
+__device__ __forceinline__ double gauss_mass(double mu, double sigma, double lo, double hi)
+{
+    const double s = sigma * 1.4142135623730951;
+    return 0.5 * (erf((hi - mu) / s) - erf((lo - mu) / s));
+}
+
+__global__ __launch_bounds__(kThreads) void hyper_kernel(int64_t n_hyper, const double *__restrict__ hyper,
+                                                         HyperC *__restrict__ out)
+{
+    const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= n_hyper) return;
+    const double *h = hyper + k * 12;
+    const double alpha = h[0], beta = h[1], mmin = h[2], mmax = h[3], lam = h[4], mpp = h[5], sigpp = h[6];
+    const double ach = h[7], bch = h[8], xi = h[9], s1 = h[10], s2 = h[11];
+    HyperC c{};
+    int status = 1;
+    for (int i = 0; i < 12; ++i)
+        if (!isfinite(h[i])) status = -1;
+    if (status == 1 && (!(mmin > 0.0 && mmin < mmax) || !(sigpp > 0.0) || !(lam >= 0.0 && lam <= 1.0) ||
+                        !(ach > 0.0) || !(bch > 0.0) || !(xi >= 0.0 && xi <= 1.0) || !(s1 > 0.0) || !(s2 > 0.0)))
+        status = 0;
+    c.status = status;
+    if (status == 1) {
+        // Z_pl = int m^-alpha dm over [m_min, m_max]
+        const double L = log(mmax / mmin);
+        const double e = 1.0 - alpha;
+        const double zpl = alpha == 1.0 ? L : exp(e * log(mmin)) * expm1(e * L) / e;
+        c.neg_alpha = -alpha;
+        c.ln_zpl = log(zpl);
+        c.mu = mpp;
+        c.inv_sigma = 1.0 / sigpp;
+        c.ln_zg = log(sigpp * 2.5066282746310002 * gauss_mass(mpp, sigpp, mmin, mmax));
+        c.one_m_lam = 1.0 - lam;
+        c.lam = lam;
+        c.mmin = mmin;
+        c.mmax = mmax;
+        c.ln_mmin = log(mmin);
+        c.beta = beta;
+        c.one_p_beta = 1.0 + beta;
+        c.beta_is_m1 = beta == -1.0 ? 1 : 0;
+        c.ach_m1 = ach - 1.0;
+        c.bch_m1 = bch - 1.0;
+        c.ln_beta_fn = lgamma(ach) + lgamma(bch) - lgamma(ach + bch);
+        c.iso = (1.0 - xi) / 4.0;
+        c.xi = xi;
+        c.k1 = 0.5 / (s1 * s1);
+        c.k2 = 0.5 / (s2 * s2);
+        c.ln_zt = log(s1 * 2.5066282746310002 * gauss_mass(1.0, s1, -1.0, 1.0)) +
+                  log(s2 * 2.5066282746310002 * gauss_mass(1.0, s2, -1.0, 1.0));
+    }
+    out[k] = c;
+}
+
+// One sample's logarithms and flags, kept across the hyper-parameter loop.
+struct Sample {
+    double m1, ln_m1, ln_q, q, ln_a_sum, ln_1ma_sum, c1m, c2m, ln_prior;
+    bool ok;   // inside every support that does not depend on Lambda
+};
+
+__device__ __forceinline__ Sample load_sample(const double *__restrict__ s, int64_t plane, int64_t idx, bool live)
+{
+    Sample x{};
+    x.ok = false;
+    if (!live) return x;
+    const double m1 = s[idx], q = s[plane + idx], a1 = s[2 * plane + idx], a2 = s[3 * plane + idx];
+    const double c1 = s[4 * plane + idx], c2 = s[5 * plane + idx];
+    x.ln_prior = s[6 * plane + idx];
+    x.ok = m1 > 0.0 && q > 0.0 && q <= 1.0 && a1 >= 0.0 && a1 <= 1.0 && a2 >= 0.0 && a2 <= 1.0 &&
+           fabs(c1) <= 1.0 && fabs(c2) <= 1.0 && isfinite(x.ln_prior);
+    if (!x.ok) return x;
+    x.m1 = m1;
+    x.ln_m1 = log(m1);
+    x.q = q;
+    x.ln_q = log(q);
+    x.ln_a_sum = log(a1) + log(a2);
+    x.ln_1ma_sum = log1p(-a1) + log1p(-a2);
+    x.c1m = c1 - 1.0;
+    x.c2m = c2 - 1.0;
+    return x;
+}
+
+// p(theta | Lambda) / p(theta | 0) of one sample.
+__device__ __forceinline__ double weight(const Sample &x, const HyperC &c)
+{
+    if (!x.ok || x.m1 < c.mmin || x.m1 > c.mmax) return 0.0;
+    const double ln_qmin = c.ln_mmin - x.ln_m1;          // q_min = m_min / m1
+    if (x.m1 <= c.mmin || x.ln_q < ln_qmin) return 0.0;
+    // primary mass
+    const double p_pl = exp(__builtin_fma(c.neg_alpha, x.ln_m1, -c.ln_zpl));
+    const double z = (x.m1 - c.mu) * c.inv_sigma;
+    const double p_g = exp(__builtin_fma(-0.5 * z, z, -c.ln_zg));
+    const double p_m1 = __builtin_fma(c.one_m_lam, p_pl, c.lam * p_g);
+    // mass ratio normalisation int_{q_min}^1 x^beta dx
+    const double z_q = c.beta_is_m1 ? -ln_qmin : -expm1(c.one_p_beta * ln_qmin) / c.one_p_beta;
+    // q^beta, the two spin magnitudes and the prior in one exponential
+    double e = __builtin_fma(c.beta, x.ln_q, -x.ln_prior);
+    e = __builtin_fma(c.ach_m1, x.ln_a_sum, e);
+    e = __builtin_fma(c.bch_m1, x.ln_1ma_sum, e);
+    e -= 2.0 * c.ln_beta_fn;
+    // tilts
+    const double g = exp(-(c.k1 * x.c1m * x.c1m + c.k2 * x.c2m * x.c2m) - c.ln_zt);
+    const double p_t = __builtin_fma(c.xi, g, c.iso);
+    return p_m1 * p_t * exp(e) / z_q;
+}
+
+// Block b = event * chunks + chunk: kPerBlock samples of the event; for every
+// Lambda each wave writes the sum of its samples' weights to
+// partials[(k * n_events + event) * n_slots + chunk * kWaves + wave].
+__global__ __launch_bounds__(kThreads) void weights_kernel(int64_t n_events, int64_t n_per, int64_t chunks,
+                                                           const double *__restrict__ s, int64_t n_hyper,
+                                                           const HyperC *__restrict__ hc, int64_t n_slots,
+                                                           double *__restrict__ partials)
+{
+    const int64_t event = (int64_t)blockIdx.x / chunks, chunk = (int64_t)blockIdx.x % chunks;
+    const int64_t plane = n_events * n_per;
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    Sample x[kPerThread];
+#pragma unroll
+    for (int i = 0; i < kPerThread; ++i) {
+        // consecutive lanes read consecutive samples
+        const int64_t j = chunk * kPerBlock + (int64_t)i * kThreads + threadIdx.x;
+        x[i] = load_sample(s, plane, event * n_per + j, j < n_per);
+    }
+    for (int64_t k = 0; k < n_hyper; ++k) {
+        const HyperC c = hc[k];
+        double w = 0.0;
+        if (c.status == 1) {
+#pragma unroll
+            for (int i = 0; i < kPerThread; ++i) w += weight(x[i], c);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+        if (lane == 0) partials[(k * n_events + event) * n_slots + chunk * kWaves + wave] = w;
+    }
+}
+
+// Block k: ln L(Lambda_k).  Thread i sums event i's partials in order and
+// takes ln(mean); the events are then added by a fixed tree.
+__global__ __launch_bounds__(kThreads) void finalize_kernel(int64_t n_events, int64_t n_per, int64_t n_slots,
+                                                            const HyperC *__restrict__ hc,
+                                                            const double *__restrict__ partials,
+                                                            double *__restrict__ lnl)
+{
+    __shared__ double red[kThreads];
+    const int64_t k = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n_events; i += kThreads) {
+        const double *p = partials + (k * n_events + i) * n_slots;
+        double sum = 0.0;
+        for (int64_t t = 0; t < n_slots; ++t) sum += p[t];
+        acc += log(sum / (double)n_per);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int status = hc[k].status;
+        lnl[k] = status == 1 ? red[0] : (status == 0 ? -INFINITY : NAN);
+    }
+}
+
+int64_t slots_per_event(int64_t n_per) { return (n_per + kPerBlock - 1) / kPerBlock * kWaves; }
+
+int64_t weight_blocks(int64_t n_events, int64_t n_per) { return (n_per + kPerBlock - 1) / kPerBlock * n_events; }
+
+size_t workspace_bytes(int64_t n_events, int64_t n_per, int64_t n_hyper)
+{
+    return (size_t)n_hyper * sizeof(HyperC) + 256 +
+           (size_t)n_hyper * (size_t)n_events * (size_t)slots_per_event(n_per) * sizeof(double);
+}
+
+hipError_t launch(int64_t n_events, int64_t n_per, const double *samples, int64_t n_hyper, const double *hyper,
+                  void *work, double *lnl, hipStream_t stream)
+{
+    HyperC *hc = static_cast<HyperC *>(work);
+    const size_t hc_bytes = ((size_t)n_hyper * sizeof(HyperC) + 255) / 256 * 256;
+    double *partials = reinterpret_cast<double *>(static_cast<char *>(work) + hc_bytes);
+    hipLaunchKernelGGL(hyper_kernel, dim3((unsigned)((n_hyper + kThreads - 1) / kThreads)), dim3(kThreads), 0, stream,
+                       n_hyper, hyper, hc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t chunks = (n_per + kPerBlock - 1) / kPerBlock;
+    const int64_t n_slots = slots_per_event(n_per);
+    hipLaunchKernelGGL(weights_kernel, dim3((unsigned)(chunks * n_events)), dim3(kThreads), 0, stream, n_events, n_per,
+                       chunks, samples, n_hyper, hc, n_slots, partials);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)n_hyper), dim3(kThreads), 0, stream, n_events, n_per, n_slots,
+                       hc, partials, lnl);
+    return hipGetLastError();
+}
+
+}  // namespace pop
+}  // namespace gw

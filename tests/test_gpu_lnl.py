@@ -109,6 +109,16 @@ def test_three_detector_128s_full_size_sampled(gw):
     assert abs(got[0] + n) < 5 * math.sqrt(n)
 
 
+def test_three_detector_128s_every_row(gw):
+    """All 4096 rows of the benchmark batch against the oracle (about 3.2e9
+    sample-bin-detector terms; seconds on the host's cores)."""
+    w = synth.bbh_3det_128s(4096)
+    data = oracle.workload_data(w)
+    got = _gpu_lnl(gw, w, data)
+    ref = _oracle_lnl(w, data)
+    _assert_parity(got, ref, "3 det 128 s, all 4096 rows")
+
+
 def test_noise_free_maximum(gw):
     w = synth.small_event(20, 3, 3000, 40)
     g = w.grid

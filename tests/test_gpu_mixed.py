@@ -108,3 +108,52 @@ def test_mixed_small_shapes(gw, n_det, n_bins, n_samples):
     got = gw.lnl_batch(g, w.tensors, w.vertices, torch.from_numpy(data).to(dev), torch.from_numpy(w.psd).to(dev),
                        torch.from_numpy(w.theta).to(dev), precision="mixed").cpu().numpy()
     assert np.abs(got - ref).max() <= TOL_MIXED
+
+
+def test_mixed_precision_over_1024_injections(gw):
+    """1024 injections on the 3-detector 128 s grid, network optimal SNR
+    log-uniform in [8, 100], each with 4096 rows (the injection, half from the
+    prior, half close to the injection).  Per injection the oracle checks the
+    injection and 7 more rows for both paths (FP64 1e-10 relative, mixed 1e-3),
+    and all 4096 mixed values stay within 1e-3 of the FP64 ones.  Injections
+    are made with the oracle's waveform, 64 at a time."""
+    import torch
+    w = synth.bbh_3det_128s(8)
+    g = w.grid
+    rng = np.random.default_rng(1904_02863 + 4)
+    dev = torch.device("cuda", 0)
+    psd_t = torch.from_numpy(w.psd).to(dev)
+    noise_t = torch.from_numpy(w.noise).to(dev)
+    weight = 4.0 * g.delta_f / w.psd
+    n_inj, batch = 1024, 64
+    worst_mixed, worst_all, worst_fp64 = 0.0, 0.0, 0.0
+    for b0 in range(0, n_inj, batch):
+        injs = synth.Prior().sample(rng, batch, 9)
+        hs = oracle.waveform(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, injs)
+        snr_now = np.sqrt(np.einsum("sdk,dk->s", np.abs(hs) ** 2, weight))
+        target = np.exp(rng.uniform(math.log(8.0), math.log(100.0), batch))
+        for i in range(batch):
+            scale = target[i] / snr_now[i]
+            inj = injs[i].copy()
+            inj[2] /= scale                       # h is proportional to 1 / d_L
+            d_t = noise_t + torch.from_numpy(hs[i] * scale).to(dev)
+            prior = synth.Prior().sample(rng, 2047, 9)
+            near = np.repeat(inj[None], 2048, 0)
+            near += rng.standard_normal(near.shape) * np.array(
+                [1e-4 * inj[0], 1e-3, 1e-3 * inj[2], 0.05, 1e-4, 0.01, 0.01, 0.02, 0.02])
+            near[:, 1] = np.minimum(near[:, 1], 1.0)
+            rows = np.vstack([inj[None], prior, near])
+            th_t = torch.from_numpy(rows).to(dev)
+            fp64 = gw.lnl_batch(g, w.tensors, w.vertices, d_t, psd_t, th_t).cpu().numpy()
+            mixed = gw.lnl_batch(g, w.tensors, w.vertices, d_t, psd_t, th_t, precision="mixed").cpu().numpy()
+            worst_all = max(worst_all, float(np.abs(mixed - fp64).max()))
+            pick = np.concatenate([[0], rng.choice(np.arange(1, 4096), 7, replace=False)])
+            data = w.noise + hs[i] * scale
+            ref = oracle.lnl(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, data, w.psd, rows[pick])
+            worst_mixed = max(worst_mixed, float(np.abs(mixed[pick] - ref).max()))
+            worst_fp64 = max(worst_fp64, float((np.abs(fp64[pick] - ref) / np.abs(ref)).max()))
+        print(f"{b0 + batch} injections: worst |mixed - oracle| {worst_mixed:.2e}, "
+              f"worst |mixed - fp64| {worst_all:.2e}, worst fp64 rel {worst_fp64:.2e}", flush=True)
+    assert worst_fp64 <= RTOL_FP64
+    assert worst_mixed <= TOL_MIXED
+    assert worst_all <= TOL_MIXED
