@@ -39,7 +39,7 @@ KERNEL_SOURCES = ("paper_1904_02863_amd/csrc/gw_kernels.hip", "paper_1904_02863_
 PROFILE_SUMMARY = "profiles/lnl_tile_kernel_bbh-3det-128s.md"
 
 
-def flops_per_pair(n_det: int, mixed: bool = False) -> int:
+def flops_per_pair(n_det: int, mixed: bool = False, direct: bool = False) -> int:
     """Algorithmic FP64 flops of the tile kernel per (sample, bin) pair
     (FMA = 2, multiply or add = 1, rounding to an integer not counted):
     phase polynomial in u = f^(1/3) 19 (9 FMA + 1 multiply), phasor
@@ -47,8 +47,12 @@ def flops_per_pair(n_det: int, mixed: bool = False) -> int:
     detector-0 complex accumulation 8 (4 FMA), and for every further detector
     one Horner step S <- S conj(rho) + D e^{-i Phi} 14 (6 FMA + 2 multiplies).
     The mixed path replaces the phasor by the reduction to a fractional turn
-    (1 add) and two FP32 hardware transcendentals, which are not counted."""
-    return 19 + (1 if mixed else 34) + 8 + 14 * (n_det - 1)
+    (1 add) and two FP32 hardware transcendentals, which are not counted.
+    Direct form (GW_FLAG_DIRECT): per detector the residual d/a - T e^{-i Phi}
+    and a^2/S |.|^2 accumulated, 13 (6 FMA + 1 multiply), plus for every
+    further detector the rotation T <- T rho, 6 (2 FMA + 2 multiplies)."""
+    per_det = (13, 19) if direct else (8, 14)
+    return 19 + (1 if mixed else 34) + per_det[0] + per_det[1] * (n_det - 1)
 
 
 def kernel_fingerprint() -> str:
@@ -84,6 +88,8 @@ def build_inputs(name: str, n_samples: int | None):
         w = synth.bbh_3det_128s(n_samples or 4096)
     elif name == "bbh-1det-4s":
         w = synth.bbh_1det_4s(n_samples or 1000)
+    elif name == "bns-15hz-512s":
+        w = synth.long_bns(15.0, 512.0, 3, n_samples or 4096)
     else:
         raise SystemExit(f"unknown workload {name}")
     dev = torch.device("cuda", 0)
@@ -97,7 +103,7 @@ def build_inputs(name: str, n_samples: int | None):
     return w, data, psd, theta
 
 
-def cpu_baseline(w, data, budget_s: float):
+def cpu_baseline(w, data, budget_s: float, flags: int = 0):
     """Oracle evals/s on a bounded number of the workload's samples."""
     import numpy as np
 
@@ -112,7 +118,7 @@ def cpu_baseline(w, data, budget_s: float):
         take = min(n, w.n_samples - done)
         t0 = time.perf_counter()
         vals = oracle.lnl(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, d, w.psd,
-                          w.theta[done:done + take])
+                          w.theta[done:done + take], isco=bool(flags & 2), add_norm=bool(flags & 4))
         spent += time.perf_counter() - t0
         assert np.isfinite(vals).all()
         done += take
@@ -124,7 +130,7 @@ def cpu_baseline(w, data, budget_s: float):
     while spent1 < budget_s / 3 and one < w.n_samples:
         t0 = time.perf_counter()
         vals = oracle.lnl(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, d, w.psd,
-                          w.theta[one:one + 1], n_threads=1)
+                          w.theta[one:one + 1], n_threads=1, isco=bool(flags & 2), add_norm=bool(flags & 4))
         spent1 += time.perf_counter() - t0
         assert np.isfinite(vals).all()
         one += 1
@@ -400,6 +406,56 @@ def bench_population(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_waveform(args):
+    """gw_waveform_batch (the template of Sec. II, Fig. 1): detector responses
+    of 256 samples on the 3-detector 128 s grid, 3.19 GB of complex128 written
+    per call, so the call is bounded by HBM write bandwidth."""
+    import torch
+
+    import paper_1904_02863_amd as gw
+    import synth
+
+    n = args.samples or 256
+    w = synth.bbh_3det_128s(n)
+    g = w.grid
+    dev = torch.device("cuda", 0)
+    theta = torch.from_numpy(w.theta).to(dev)
+    out = torch.empty((n, w.n_det, g.n_bins), dtype=torch.complex128, device=dev)
+    ws = gw.Workspace(0)
+    for _ in range(args.warmup):
+        gw.waveform_batch(g, w.tensors, w.vertices, theta, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gw.waveform_batch(g, w.tensors, w.vertices, theta, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    if not torch.isfinite(torch.view_as_real(out)).all():
+        raise SystemExit("non-finite waveform")
+    written = out.numel() * 16
+    read = g.n_bins * (32 + 16)
+    result = {
+        "metric": "waveforms/s (3-det,128 s TaylorF2 responses)", "value": n / t, "unit": "waveforms/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "waveform", "n_samples": n, "n_det": w.n_det, "n_bins": g.n_bins},
+        "roofline": {"bound": "hbm", "achieved": (written + read) / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (written + read) / t / 1e9 / HBM_PEAK_GBS, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        done, spent = 0, 0.0
+        while spent < args.cpu_seconds / 3 and done < n:
+            t0 = time.perf_counter()
+            oracle.waveform(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, w.theta[done:done + 16])
+            spent += time.perf_counter() - t0
+            done += 16
+        result["cpu_baseline"] = {"value": done / spent, "unit": "waveforms/s", "cores": oracle.max_threads(),
+                                  "kind": "oracle", "sample": f"{done} of the {n} samples, {spent:.1f} s"}
+    ws.close()
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,11 +463,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--workload", default="bbh-3det-128s",
-                    choices=["bbh-3det-128s", "bbh-1det-4s", "bns-ragged", "flow-mcmc", "population"])
+                    choices=["bbh-3det-128s", "bbh-1det-4s", "bns-15hz-512s", "bns-ragged", "flow-mcmc",
+                             "population", "waveform"])
     ap.add_argument("--mcmc-burn", type=int, default=4000, help="flow-mcmc: random-walk burn-in steps")
     ap.add_argument("--mcmc-steps", type=int, default=1024, help="flow-mcmc: production steps of each sampler")
     ap.add_argument("--flow-steps", type=int, default=3000, help="flow-mcmc: Adam steps")
     ap.add_argument("--samples", type=int, default=None)
+    ap.add_argument("--flags", type=int, default=0,
+                    help="likelihood options: 1 direct form, 2 ISCO template end, 4 log prefactor (or-ed)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -438,6 +497,9 @@ def main():
     if args.workload == "population":
         bench_population(args)
         return
+    if args.workload == "waveform":
+        bench_waveform(args)
+        return
     w, data, psd, theta = build_inputs(args.workload, args.samples)
     g = w.grid
     ws = gw.Workspace(0)
@@ -445,7 +507,8 @@ def main():
     out = torch.empty(w.n_samples, dtype=torch.float64, device=theta.device)
 
     def step():
-        gw.lnl_batch(g, w.tensors, w.vertices, data, psd, theta, out=out, workspace=ws, precision=args.precision)
+        gw.lnl_batch(g, w.tensors, w.vertices, data, psd, theta, out=out, workspace=ws, precision=args.precision,
+                     flags=args.flags)
 
     for _ in range(args.warmup):
         step()
@@ -473,7 +536,8 @@ def main():
     evals = w.n_samples * args.steps
     kernel_avg_s = kernel_ms / 1e3 / max(launches, 1)
     mixed = args.precision == "mixed"
-    flops_launch = flops_per_pair(w.n_det, mixed) * w.n_samples * g.n_bins
+    direct = bool(args.flags & 1)
+    flops_launch = flops_per_pair(w.n_det, mixed, direct) * w.n_samples * g.n_bins
     achieved = flops_launch / kernel_avg_s / 1e12
     result = {
         "metric": "lnL evals/s (3-det,128 s TaylorF2)" if args.workload == "bbh-3det-128s" else "lnL evals/s",
@@ -490,16 +554,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n_samples": w.n_samples, "n_det": w.n_det, "n_bins": g.n_bins,
                    "delta_f": g.delta_f, "f_low": g.f_low, "f_high": g.f_high, "n_param": w.n_param,
-                   "precision": args.precision},
+                   "precision": args.precision, "flags": args.flags},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(args.precision) if args.workload == "bbh-3det-128s" else None,
+                     "traffic": (measured_traffic(args.precision)
+                                 if args.workload == "bbh-3det-128s" and args.flags == 0 else None),
                      "kernel": f"lnl_tile_kernel<{w.n_det},{'mixed' if mixed else 'fp64'}>",
                      "kernel_ms": kernel_avg_s * 1e3, "flops_per_launch": flops_launch,
-                     "flops_per_pair": flops_per_pair(w.n_det, mixed)},
+                     "flops_per_pair": flops_per_pair(w.n_det, mixed, direct)},
     }
+    if args.flags & 2:
+        # the kernel skips the bins above the batch's largest cut-off, so a
+        # tally over every bin would overstate the rate
+        result["roofline"] = None
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(w, data, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(w, data, args.cpu_seconds, args.flags)
     print(json.dumps(result), flush=True)
 
 

@@ -199,7 +199,8 @@ gw::TilePlan plan_tiles(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_s
 // Workspace sections of one event.  The direct-form tables and the prefix
 // sums are carved only when the call's flags use them.
 struct LnlLayout {
-    size_t tab1, tab2, dcoef, edir, vdir, qprefix, prep_partials, event_sums, k_limit, records, partials, total;
+    size_t tab1, tab2, dcoef, edir, vdir, qprefix, qoffsets, prep_partials, event_sums, k_limit, records, partials,
+        total;
     int prep_blocks;
 };
 
@@ -215,6 +216,7 @@ LnlLayout lnl_layout(int64_t n_bins, int n_det, int64_t n_samples, const gw::Til
     l.edir = direct ? c.take(sizeof(double2) * n_bins * n_det) : 0;
     l.vdir = direct ? c.take(sizeof(double) * n_bins * n_det) : 0;
     l.qprefix = isco ? c.take(sizeof(double) * n_bins * n_det) : 0;
+    l.qoffsets = isco ? c.take(sizeof(double) * (size_t)l.prep_blocks * n_det) : 0;
     l.prep_partials = c.take(sizeof(double) * gw::kPrepPerDet * n_det * l.prep_blocks);
     l.event_sums = c.take(sizeof(double) * gw::kEventSums);
     l.k_limit = c.take(sizeof(int64_t));
@@ -257,6 +259,7 @@ int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::De
     eb.edir = l.edir ? at<double2>(ws, l.edir) : nullptr;
     eb.vdir = l.vdir ? at<double>(ws, l.vdir) : nullptr;
     eb.qprefix = l.qprefix ? at<double>(ws, l.qprefix) : nullptr;
+    eb.qoffsets = l.qoffsets ? at<double>(ws, l.qoffsets) : nullptr;
     eb.prep = at<double>(ws, l.prep_partials);
     eb.prep_blocks = l.prep_blocks;
     eb.sums = at<double>(ws, l.event_sums);
@@ -353,6 +356,8 @@ RaggedPlan ragged_plan(gw_workspace *ws, int n_events, const gw_event *events, c
         re.edir = direct ? reinterpret_cast<double2 *>(base + c.take(sizeof(double2) * m * ev.n_det)) : nullptr;
         re.vdir = direct ? reinterpret_cast<double *>(base + c.take(sizeof(double) * m * ev.n_det)) : nullptr;
         re.qprefix = isco ? reinterpret_cast<double *>(base + c.take(sizeof(double) * m * ev.n_det)) : nullptr;
+        re.qoffsets = isco ? reinterpret_cast<double *>(base + c.take(sizeof(double) * re.prep_blocks * ev.n_det))
+                           : nullptr;
         re.rec = reinterpret_cast<double *>(base + c.take(sizeof(double) * gw::record_fields(ev.n_det) *
                                                            std::max<int64_t>(s, 1)));
         re.partials = reinterpret_cast<double2 *>(base + c.take(sizeof(double2) * re.n_chunks * s * ev.n_det));
@@ -778,7 +783,8 @@ int gw_pop_lnl(gw_workspace *ws, int64_t n_events, int64_t n_per_event, const do
     if (!ws) return fail(GW_EINVAL, "workspace is NULL");
     if (n_events < 1 || n_per_event < 1 || n_hyper < 0) return fail(GW_EINVAL, "bad population sizes");
     if (!samples || (n_hyper > 0 && (!hyper || !lnl_out))) return fail(GW_EINVAL, "NULL population argument");
-    if (gw::pop::weight_blocks(n_events, n_per_event) > 0x7fffffffLL || n_hyper > 0x7fffffffLL)
+    if (gw::pop::weight_blocks(n_events, n_per_event) > 0x7fffffffLL || n_hyper > 0x7fffffffLL ||
+        n_hyper * n_events / 4 > 0x7fffffffLL)
         return fail(GW_EINVAL, "population batch too large for one launch");
     if (n_hyper == 0) return GW_OK;
     DeviceGuard g(ws->device);

@@ -74,6 +74,7 @@ struct RaggedEvent {
     double2 *edir;        // direct form: d / a per detector and bin
     double *vdir;         // direct form: a^2 / S per detector and bin
     double *qprefix;      // ISCO end: prefix sums of a^2 / S per detector
+    double *qoffsets;     // ISCO end: a^2 / S totals of the preceding 256-bin blocks [n_det][prep_blocks]
     double *rec;
     double2 *partials;
     double *prep;
@@ -137,6 +138,7 @@ struct EventBuffers {
     double2 *edir;        // [n_det][n_bins], direct form only
     double *vdir;         // [n_det][n_bins], direct form only
     double *qprefix;      // [n_det][n_bins], ISCO end only
+    double *qoffsets;     // [n_det][prep_blocks], ISCO end only
     double *prep;         // [prep_blocks][kPrepPerDet * n_det]
     int prep_blocks;      // ceil(n_bins / kBlock)
     double *sums;         // [kEventSums]

@@ -164,36 +164,59 @@ __device__ __forceinline__ double column_total(int n_blocks, int per, int j, con
     return block_sum(x, red);
 }
 
+// Inclusive Hillis-Steele scan of x over the block (fixed order); `red` is
+// kBlock doubles of LDS.  All threads must call it.
+__device__ __forceinline__ double block_scan(double x, double *red)
+{
+    red[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const double add = (int)threadIdx.x >= off ? red[threadIdx.x - off] : 0.0;
+        __syncthreads();
+        red[threadIdx.x] += add;
+        __syncthreads();
+    }
+    const double total = red[threadIdx.x];
+    __syncthreads();
+    return total;
+}
+
+// offsets[b] = sum over blocks b' < b of column j of an event's per-block
+// partials, for every b < n_blocks (one block: each thread scans a
+// contiguous segment of blocks on top of the preceding segments' totals).
+__device__ __forceinline__ void block_offsets(int64_t n_blocks, int per, int j, const double *__restrict__ partials,
+                                              double *red, double *__restrict__ offsets)
+{
+    const int64_t seg = (n_blocks + kBlock - 1) / kBlock;
+    const int64_t b0 = (int64_t)threadIdx.x * seg, b1 = min(n_blocks, b0 + seg);
+    double mine = 0.0;
+    for (int64_t b = b0; b < b1; ++b) mine += partials[b * per + j];
+    double run = block_scan(mine, red) - mine;      // exclusive: the preceding segments
+    for (int64_t b = b0; b < b1; ++b) {
+        offsets[b] = run;
+        run += partials[b * per + j];
+    }
+}
+
 // Prefix sums of a^2/S for the ISCO end: block b of the event writes
 // qprefix[d][k] = sum_{j <= k} a_j^2 / S_d,j for its 256 bins, from the
-// preceding blocks' sums (added in block order) and a scan of its own bins.
-__device__ __forceinline__ void prefix_block(const PrepView &v, int64_t b, const double *__restrict__ partials,
-                                             double *red, double *__restrict__ qprefix)
+// preceding blocks' total qoffsets[d][b] and a scan of its own bins.
+__device__ __forceinline__ void prefix_block(const PrepView &v, int64_t b, int64_t n_blocks,
+                                             const double *__restrict__ qoffsets, double *red,
+                                             double *__restrict__ qprefix)
 {
-    const int per = kPrepPerDet * v.n_det;
     const int64_t k = b * kBlock + threadIdx.x;
     const double amp = k < v.n_bins ? v.tab2[k].amp : 0.0;
     for (int d = 0; d < v.n_det; ++d) {
-        double before = 0.0;
-        for (int64_t c = threadIdx.x; c < b; c += kBlock) before += partials[c * per + kPrepPerDet * d + 1];
-        const double offset = block_sum(before, red);
+        const double offset = qoffsets[(int64_t)d * n_blocks + b];
         double q = 0.0;
         if (k < v.n_bins) {
             const double s = v.psd[(int64_t)d * v.n_bins + k];
             const double w = (s > 0.0 && s < INFINITY) ? 1.0 / s : NAN;
             q = amp * amp * w;
         }
-        // inclusive Hillis-Steele scan over the block
-        red[threadIdx.x] = q;
-        __syncthreads();
-        for (int off = 1; off < kBlock; off <<= 1) {
-            const double add = (int)threadIdx.x >= off ? red[threadIdx.x - off] : 0.0;
-            __syncthreads();
-            red[threadIdx.x] += add;
-            __syncthreads();
-        }
-        if (k < v.n_bins) qprefix[(int64_t)d * v.n_bins + k] = offset + red[threadIdx.x];
-        __syncthreads();
+        const double incl = block_scan(q, red);
+        if (k < v.n_bins) qprefix[(int64_t)d * v.n_bins + k] = offset + incl;
     }
 }
 
@@ -223,11 +246,22 @@ __global__ __launch_bounds__(kBlock) void event_sums_kernel(int n_blocks, int n_
     if (threadIdx.x == 0) sums[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(kBlock) void event_prefix_kernel(PrepView v, const double *__restrict__ partials,
+// Block d: qoffsets[d][b], the a^2/S total of the blocks before b.
+__global__ __launch_bounds__(kBlock) void event_offsets_kernel(int64_t n_blocks, int n_det,
+                                                                const double *__restrict__ partials,
+                                                                double *__restrict__ qoffsets)
+{
+    __shared__ double red[kBlock];
+    const int d = blockIdx.x;
+    block_offsets(n_blocks, kPrepPerDet * n_det, kPrepPerDet * d + 1, partials, red, qoffsets + (int64_t)d * n_blocks);
+}
+
+__global__ __launch_bounds__(kBlock) void event_prefix_kernel(PrepView v, int64_t n_blocks,
+                                                               const double *__restrict__ qoffsets,
                                                                double *__restrict__ qprefix)
 {
     __shared__ double red[kBlock];
-    prefix_block(v, blockIdx.x, partials, red, qprefix);
+    prefix_block(v, blockIdx.x, n_blocks, qoffsets, red, qprefix);
 }
 
 __device__ __forceinline__ PrepView prep_view(const RaggedEvent &re)
@@ -272,6 +306,16 @@ __global__ __launch_bounds__(kBlock) void ragged_event_sums_kernel(const RaggedE
     }
 }
 
+// Ragged batch: block e computes event e's qoffsets for every detector.
+__global__ __launch_bounds__(kBlock) void ragged_offsets_kernel(const RaggedEvent *__restrict__ events)
+{
+    __shared__ double red[kBlock];
+    const RaggedEvent &re = events[blockIdx.x];
+    for (int d = 0; d < re.n_det; ++d)
+        block_offsets(re.prep_blocks, kPrepPerDet * re.n_det, kPrepPerDet * d + 1, re.prep, red,
+                      re.qoffsets + (int64_t)d * re.prep_blocks);
+}
+
 // Ragged batch: prefix sums of a^2/S, blocks as in ragged_event_prep_kernel.
 __global__ __launch_bounds__(kBlock) void ragged_prefix_kernel(const RaggedEvent *__restrict__ events,
                                                                 const int2 *__restrict__ block_map)
@@ -279,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void ragged_prefix_kernel(const RaggedEvent
     __shared__ double red[kBlock];
     const int2 em = block_map[blockIdx.x];
     const RaggedEvent &re = events[em.x];
-    prefix_block(prep_view(re), em.y, re.prep, red, re.qprefix);
+    prefix_block(prep_view(re), em.y, re.prep_blocks, re.qoffsets, red, re.qprefix);
 }
 
 // ---------------------------------------------------------------- per-sample preparation
@@ -954,8 +998,11 @@ hipError_t launch_event_data(const gw_grid &grid, int n_det, const gw_c128 *data
                        eb.prep, eb.sums);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (flags & GW_FLAG_TERM_ISCO) {
-        hipLaunchKernelGGL(event_prefix_kernel, dim3(eb.prep_blocks), dim3(kBlock), 0, stream, v, eb.prep,
-                           eb.qprefix);
+        hipLaunchKernelGGL(event_offsets_kernel, dim3(n_det), dim3(kBlock), 0, stream, (int64_t)eb.prep_blocks, n_det,
+                           eb.prep, eb.qoffsets);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(event_prefix_kernel, dim3(eb.prep_blocks), dim3(kBlock), 0, stream, v,
+                           (int64_t)eb.prep_blocks, eb.qoffsets, eb.qprefix);
         e = hipGetLastError();
     }
     return e;
@@ -1073,6 +1120,8 @@ hipError_t launch_ragged(const RaggedLaunch &r, hipStream_t stream)
     hipLaunchKernelGGL(ragged_event_sums_kernel, dim3(r.n_events), dim3(kBlock), 0, stream, r.events);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (r.flags & GW_FLAG_TERM_ISCO) {
+        hipLaunchKernelGGL(ragged_offsets_kernel, dim3(r.n_events), dim3(kBlock), 0, stream, r.events);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(ragged_prefix_kernel, dim3(r.n_prep_blocks), dim3(kBlock), 0, stream, r.events,
                            r.block_map);
         if ((e = hipGetLastError()) != hipSuccess) return e;

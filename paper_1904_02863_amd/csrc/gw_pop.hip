@@ -15,9 +15,9 @@
 // ln p(theta | 0)).  Each block keeps 4 samples per thread of one event in
 // registers (their logarithms computed once) and loops over every Lambda,
 // whose constants it reads with wave-uniform loads; each wave writes its own
-// partial sum, so the weights kernel has no barrier.  A finalize kernel sums
-// the partials of each (Lambda, event) in order, takes the log of the mean
-// and adds the events in order.
+// partial sum, so the weights kernel has no barrier.  One wave per (Lambda,
+// event) then sums that event's partials and takes the log of the mean, and
+// a last kernel adds the events of each Lambda by a fixed tree.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -132,22 +132,23 @@ __device__ __forceinline__ double weight(const Sample &x, const HyperC &c)
     if (!x.ok || x.m1 < c.mmin || x.m1 > c.mmax) return 0.0;
     const double ln_qmin = c.ln_mmin - x.ln_m1;          // q_min = m_min / m1
     if (x.m1 <= c.mmin || x.ln_q < ln_qmin) return 0.0;
-    // primary mass
-    const double p_pl = exp(__builtin_fma(c.neg_alpha, x.ln_m1, -c.ln_zpl));
-    const double z = (x.m1 - c.mu) * c.inv_sigma;
-    const double p_g = exp(__builtin_fma(-0.5 * z, z, -c.ln_zg));
-    const double p_m1 = __builtin_fma(c.one_m_lam, p_pl, c.lam * p_g);
-    // mass ratio normalisation int_{q_min}^1 x^beta dx
-    const double z_q = c.beta_is_m1 ? -ln_qmin : -expm1(c.one_p_beta * ln_qmin) / c.one_p_beta;
-    // q^beta, the two spin magnitudes and the prior in one exponential
+    // q^beta, the two spin magnitudes and the prior: the log of every factor
+    // but the primary mass, tilts and q normalisation
     double e = __builtin_fma(c.beta, x.ln_q, -x.ln_prior);
     e = __builtin_fma(c.ach_m1, x.ln_a_sum, e);
     e = __builtin_fma(c.bch_m1, x.ln_1ma_sum, e);
     e -= 2.0 * c.ln_beta_fn;
+    // primary mass times exp(e): both mixture components carry it
+    const double a_pl = __builtin_fma(c.neg_alpha, x.ln_m1, e - c.ln_zpl);
+    const double z = (x.m1 - c.mu) * c.inv_sigma;
+    const double a_g = __builtin_fma(-0.5 * z, z, e - c.ln_zg);
+    const double p_me = __builtin_fma(c.one_m_lam, exp(a_pl), c.lam * exp(a_g));
+    // mass ratio normalisation int_{q_min}^1 x^beta dx
+    const double z_q = c.beta_is_m1 ? -ln_qmin : -expm1(c.one_p_beta * ln_qmin) / c.one_p_beta;
     // tilts
     const double g = exp(-(c.k1 * x.c1m * x.c1m + c.k2 * x.c2m * x.c2m) - c.ln_zt);
     const double p_t = __builtin_fma(c.xi, g, c.iso);
-    return p_m1 * p_t * exp(e) / z_q;
+    return p_me * p_t / z_q;
 }
 
 // Block b = event * chunks + chunk: kPerBlock samples of the event; for every
@@ -181,22 +182,34 @@ __global__ __launch_bounds__(kThreads) void weights_kernel(int64_t n_events, int
     }
 }
 
-// Block k: ln L(Lambda_k).  Thread i sums event i's partials in order and
-// takes ln(mean); the events are then added by a fixed tree.
-__global__ __launch_bounds__(kThreads) void finalize_kernel(int64_t n_events, int64_t n_per, int64_t n_slots,
-                                                            const HyperC *__restrict__ hc,
-                                                            const double *__restrict__ partials,
+// Wave w of block b handles (Lambda k, event i) with k * n_events + i =
+// b * kWaves + w: its lanes sum the event's partials (strided, then a fixed
+// butterfly) and lane 0 writes ln(mean) to lmean[k][i].
+__global__ __launch_bounds__(kThreads) void event_means_kernel(int64_t n_events, int64_t n_per, int64_t n_slots,
+                                                               int64_t n_pairs, const double *__restrict__ partials,
+                                                               double *__restrict__ lmean)
+{
+    const int lane = threadIdx.x % 64;
+    const int64_t pair = (int64_t)blockIdx.x * kWaves + threadIdx.x / 64;
+    if (pair >= n_pairs) return;
+    const double *p = partials + pair * n_slots;
+    double sum = 0.0;
+    for (int64_t t = lane; t < n_slots; t += 64) sum += p[t];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    if (lane == 0) lmean[pair] = log(sum / (double)n_per);
+}
+
+// Block k: ln L(Lambda_k) = sum over events of lmean[k][i] (strided per
+// thread, then a fixed tree), or -inf / NaN for points outside the domain.
+__global__ __launch_bounds__(kThreads) void finalize_kernel(int64_t n_events, const HyperC *__restrict__ hc,
+                                                            const double *__restrict__ lmean,
                                                             double *__restrict__ lnl)
 {
     __shared__ double red[kThreads];
     const int64_t k = blockIdx.x;
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < n_events; i += kThreads) {
-        const double *p = partials + (k * n_events + i) * n_slots;
-        double sum = 0.0;
-        for (int64_t t = 0; t < n_slots; ++t) sum += p[t];
-        acc += log(sum / (double)n_per);
-    }
+    for (int64_t i = threadIdx.x; i < n_events; i += kThreads) acc += lmean[k * n_events + i];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int w = kThreads / 2; w > 0; w >>= 1) {
@@ -215,7 +228,7 @@ int64_t weight_blocks(int64_t n_events, int64_t n_per) { return (n_per + kPerBlo
 
 size_t workspace_bytes(int64_t n_events, int64_t n_per, int64_t n_hyper)
 {
-    return (size_t)n_hyper * sizeof(HyperC) + 256 +
+    return (size_t)n_hyper * sizeof(HyperC) + 512 + (size_t)n_hyper * (size_t)n_events * sizeof(double) +
            (size_t)n_hyper * (size_t)n_events * (size_t)slots_per_event(n_per) * sizeof(double);
 }
 
@@ -224,7 +237,9 @@ hipError_t launch(int64_t n_events, int64_t n_per, const double *samples, int64_
 {
     HyperC *hc = static_cast<HyperC *>(work);
     const size_t hc_bytes = ((size_t)n_hyper * sizeof(HyperC) + 255) / 256 * 256;
-    double *partials = reinterpret_cast<double *>(static_cast<char *>(work) + hc_bytes);
+    const size_t lm_bytes = ((size_t)n_hyper * (size_t)n_events * sizeof(double) + 255) / 256 * 256;
+    double *lmean = reinterpret_cast<double *>(static_cast<char *>(work) + hc_bytes);
+    double *partials = reinterpret_cast<double *>(static_cast<char *>(work) + hc_bytes + lm_bytes);
     hipLaunchKernelGGL(hyper_kernel, dim3((unsigned)((n_hyper + kThreads - 1) / kThreads)), dim3(kThreads), 0, stream,
                        n_hyper, hyper, hc);
     hipError_t e = hipGetLastError();
@@ -234,8 +249,11 @@ hipError_t launch(int64_t n_events, int64_t n_per, const double *samples, int64_
     hipLaunchKernelGGL(weights_kernel, dim3((unsigned)(chunks * n_events)), dim3(kThreads), 0, stream, n_events, n_per,
                        chunks, samples, n_hyper, hc, n_slots, partials);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)n_hyper), dim3(kThreads), 0, stream, n_events, n_per, n_slots,
-                       hc, partials, lnl);
+    const int64_t n_pairs = n_hyper * n_events;
+    hipLaunchKernelGGL(event_means_kernel, dim3((unsigned)((n_pairs + kWaves - 1) / kWaves)), dim3(kThreads), 0,
+                       stream, n_events, n_per, n_slots, n_pairs, partials, lmean);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)n_hyper), dim3(kThreads), 0, stream, n_events, hc, lmean, lnl);
     return hipGetLastError();
 }
 

@@ -315,3 +315,27 @@ def population_samples(n_events: int, n_per_event: int, index: int = 5) -> np.nd
         out[f] = x
     out[6] = -float(np.log(hi - lo).sum())
     return out
+
+
+def long_bns(f_low: float, duration: float, n_det: int, n_samples: int, index: int = 6) -> Workload:
+    """A long neutron-star event: f_low .. 2048 Hz in `duration` seconds
+    (15 Hz / 512 s: 1,040,897 bins; 10 Hz / 2048 s: 4,173,825; 5 Hz / 8192 s:
+    16,736,257), m1, m2 ~ U[1, 2] solar masses, d_L ~ U[40, 200] Mpc, the
+    coalescence time within +-0.1 s of the segment's reference time."""
+    g = seeds(index)
+    grid = make_grid(f_low, 2048.0, duration)
+    tensors, vertices = stack_detectors(network(g["detectors"], n_det))
+    f = grid.frequencies()
+    s = np.ascontiguousarray(np.broadcast_to(psd(f), (n_det, grid.n_bins)))
+    nz = np.ascontiguousarray(np.stack([noise(g["noise"], s[d], grid.delta_f) for d in range(n_det)]))
+
+    def draw(rng, n):
+        m1 = rng.uniform(1.0, 2.0, n)
+        m2 = rng.uniform(1.0, 2.0, n)
+        mc, q = component_masses_to_mc_q(m1, m2)
+        th = Prior(dl=(40.0, 200.0)).sample(rng, n, 9)
+        th[:, 0], th[:, 1] = mc, q
+        return th
+    inj = draw(g["injection"], 1)[0]
+    theta = draw(g["samples"], n_samples)
+    return Workload(f"bns-{f_low:g}hz-{duration:g}s", grid, 9, tensors, vertices, s, nz, inj, theta)
