@@ -37,6 +37,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_1904_02863_amd/csrc/gw_kernels.hip", "paper_1904_02863_amd/csrc/gw_device_math.h",
                   "paper_1904_02863_amd/csrc/gw_internal.h", "paper_1904_02863_amd/build.py")
 PROFILE_SUMMARY = "profiles/lnl_tile_kernel_bbh-3det-128s.md"
+WAVEFORM_PROFILE = "profiles/waveform_kernel_bbh-3det-128s.md"
 
 
 def flops_per_pair(n_det: int, mixed: bool = False, direct: bool = False) -> int:
@@ -63,18 +64,31 @@ def kernel_fingerprint() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(precision: str):
-    """HBM bytes per launch of the tile kernel from the committed counter
-    summary, or None when the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, PROFILE_SUMMARY)
+def measured_traffic(key: str, summary: str = PROFILE_SUMMARY):
+    """HBM bytes per launch of a kernel from a committed counter summary, or
+    None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, summary)
     if not os.path.exists(path):
         return None
     text = open(path).read()
     sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
-    val = re.search(rf"traffic_bytes_per_launch_{precision}:\s*([0-9.eE+]+)", text)
+    val = re.search(rf"traffic_bytes_per_launch_{key}:\s*([0-9.eE+]+)", text)
     if not sha or not val or sha.group(1) != kernel_fingerprint():
         return None
     return float(val.group(1))
+
+
+def calibration_copy(mib: int, device):
+    """One plain device-to-device copy of `mib` MiB (the reference dispatch
+    for scaling hardware traffic counters)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device=device)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def build_inputs(name: str, n_samples: int | None):
@@ -425,11 +439,17 @@ def bench_waveform(args):
     for _ in range(args.warmup):
         gw.waveform_batch(g, w.tensors, w.vertices, theta, out=out, workspace=ws)
     torch.cuda.synchronize()
+    ws.set_timing(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         gw.waveform_batch(g, w.tensors, w.vertices, theta, out=out, workspace=ws)
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / args.steps
+    kernel_ms, launches = ws.kernel_time()
+    ws.set_timing(False)
+    kernel_s = kernel_ms / launches / 1e3
+    if args.calibrate_copy > 0:
+        calibration_copy(args.calibrate_copy, dev)
     if not torch.isfinite(torch.view_as_real(out)).all():
         raise SystemExit("non-finite waveform")
     written = out.numel() * 16
@@ -439,8 +459,11 @@ def bench_waveform(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "waveform", "n_samples": n, "n_det": w.n_det, "n_bins": g.n_bins},
-        "roofline": {"bound": "hbm", "achieved": (written + read) / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (written + read) / t / 1e9 / HBM_PEAK_GBS, "traffic": None},
+        "roofline": {"bound": "hbm", "achieved": (written + read) / kernel_s / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": (written + read) / kernel_s / 1e9 / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("waveform", WAVEFORM_PROFILE) if n == 256 else None,
+                     "kernel": "waveform_kernel", "kernel_ms": kernel_s * 1e3,
+                     "algorithmic_bytes": written + read},
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -523,13 +546,7 @@ def main():
     kernel_ms, launches = ws.kernel_time()
     ws.set_timing(False)
     if args.calibrate_copy > 0:
-        n = args.calibrate_copy * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device=theta.device)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copy(args.calibrate_copy, theta.device)
     if not torch.isfinite(out).all():
         raise SystemExit("non-finite lnL in the benchmark batch")
 

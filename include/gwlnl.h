@@ -140,9 +140,11 @@ int gw_workspace_reserve(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_
 int64_t gw_workspace_bytes(const gw_workspace *ws);
 
 /* Measurement support.  While timing is enabled (enable != 0), every
- * likelihood call made with this workspace records a pair of HIP events on
- * its own stream around its hot kernel (the tile kernel that forms Z for
- * every sample, bin and detector).  Enabling clears earlier records. */
+ * gw_lnl_batch, gw_waveform_batch and gw_pop_lnl call made with this
+ * workspace records a pair of HIP events on its own stream around its hot
+ * kernel: the tile kernel that forms Z for every sample, bin and detector;
+ * the kernel that writes the templates; the kernel that forms the population
+ * weights.  Enabling (or disabling) clears earlier records. */
 int gw_workspace_set_timing(gw_workspace *ws, int enable);
 
 /* Sum of the recorded hot-kernel durations in milliseconds and the number of

@@ -242,6 +242,32 @@ int check_common(gw_workspace *ws, const gw_grid *grid, int n_det_min, int n_det
     return GW_OK;
 }
 
+// The start/stop events of the next timed hot-kernel launch, or two nullptrs
+// while timing is off.  The pair counts once timer_stop has recorded its stop.
+int timer_pair(gw_workspace *ws, hipEvent_t *start, hipEvent_t *stop)
+{
+    *start = *stop = nullptr;
+    if (!ws->timing) return GW_OK;
+    while ((size_t)(2 * ws->timed + 2) > ws->events.size()) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+        ws->events.push_back(ev);
+    }
+    *start = ws->events[2 * ws->timed];
+    *stop = ws->events[2 * ws->timed + 1];
+    return GW_OK;
+}
+
+int timer_stop(gw_workspace *ws, hipEvent_t stop, hipStream_t stream)
+{
+    if (!stop) return GW_OK;
+    hipError_t e = hipEventRecord(stop, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    ++ws->timed;
+    return GW_OK;
+}
+
 int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::DetGeom &geom, const gw_c128 *data,
                   const double *psd, const double *theta, int n_param, int64_t n_samples, double *lnl_out,
                   bool mixed, unsigned flags, hipStream_t stream)
@@ -276,24 +302,12 @@ int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::De
         return hip_fail(e, "sample prep");
     if (form == gw::kFormSplitIsco && (e = gw::launch_isco_limit(n_samples, rec, eb.k_limit, stream)) != hipSuccess)
         return hip_fail(e, "template-end limit");
-    hipEvent_t stop_event = nullptr;
-    if (ws->timing) {
-        if ((size_t)(2 * ws->timed + 2) > ws->events.size()) {
-            for (int i = 0; i < 2; ++i) {
-                hipEvent_t ev;
-                if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(e, "hipEventCreate");
-                ws->events.push_back(ev);
-            }
-        }
-        if ((e = hipEventRecord(ws->events[2 * ws->timed], stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-        stop_event = ws->events[2 * ws->timed + 1];
-    }
+    hipEvent_t t_start, t_stop;
+    if (int rc = timer_pair(ws, &t_start, &t_stop)) return rc;
+    if (t_start && (e = hipEventRecord(t_start, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if ((e = gw::launch_lnl_tiles(grid, n_det, n_samples, plan, mixed, form, eb, rec, part, stream)) != hipSuccess)
         return hip_fail(e, "lnl tiles");
-    if (stop_event) {
-        if ((e = hipEventRecord(stop_event, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-        ++ws->timed;
-    }
+    if (int rc = timer_stop(ws, t_stop, stream)) return rc;
     if ((e = gw::launch_lnl_finalize(grid, n_samples, n_det, plan, part, rec, eb, flags, lnl_out, stream)) !=
         hipSuccess)
         return hip_fail(e, "lnl finalize");
@@ -746,9 +760,12 @@ int gw_waveform_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw
     if ((e = gw::launch_sample_prep(*grid, n_samples, n_param, n_out, polar, (flags & GW_FLAG_TERM_ISCO) != 0, geom,
                                     theta, rec, stream)) != hipSuccess)
         return hip_fail(e, "sample prep");
+    hipEvent_t t_start, t_stop;
+    if (int rc = timer_pair(ws, &t_start, &t_stop)) return rc;
+    if (t_start && (e = hipEventRecord(t_start, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if ((e = gw::launch_waveform(*grid, n_out, n_samples, tab1, tab2, rec, h_out, stream)) != hipSuccess)
         return hip_fail(e, "waveform");
-    return GW_OK;
+    return timer_stop(ws, t_stop, stream);
 }
 
 int gw_lnl_ragged(gw_workspace *ws, int n_events, const gw_event *events, const gw_c128 *data_packed,
@@ -792,8 +809,13 @@ int gw_pop_lnl(gw_workspace *ws, int64_t n_events, int64_t n_per_event, const do
     drop_ragged_graph(ws);               // the arena is about to be laid out for the population pass
     if (int rc = ensure_capacity(ws, gw::pop::workspace_bytes(n_events, n_per_event, n_hyper))) return rc;
     ws->tables_valid = false;
-    hipError_t e = gw::pop::launch(n_events, n_per_event, samples, n_hyper, hyper, ws->base, lnl_out, stream);
-    return e == hipSuccess ? GW_OK : hip_fail(e, "gw_pop_lnl");
+    hipEvent_t t_start, t_stop;
+    if (int rc = timer_pair(ws, &t_start, &t_stop)) return rc;
+    hipError_t e = gw::pop::launch(n_events, n_per_event, samples, n_hyper, hyper, ws->base, lnl_out, t_start, t_stop,
+                                   stream);
+    if (e != hipSuccess) return hip_fail(e, "gw_pop_lnl");
+    if (t_stop) ++ws->timed;
+    return GW_OK;
 }
 
 int gw_ragged_tuning(const gw_workspace *ws, int *tile_bins, int64_t *chunk_bins)

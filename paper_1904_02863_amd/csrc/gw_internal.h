@@ -180,8 +180,9 @@ int lnl_ragged_blocks_per_cu(int n_det, int tile_bins, bool mixed, int form);
 namespace pop {
 size_t workspace_bytes(int64_t n_events, int64_t n_per, int64_t n_hyper);
 int64_t weight_blocks(int64_t n_events, int64_t n_per);
+// t_start / t_stop (either may be null): events recorded around the weights kernel.
 hipError_t launch(int64_t n_events, int64_t n_per, const double *samples, int64_t n_hyper, const double *hyper,
-                  void *work, double *lnl, hipStream_t stream);
+                  void *work, double *lnl, hipEvent_t t_start, hipEvent_t t_stop, hipStream_t stream);
 }  // namespace pop
 
 // LDS bytes of the tile kernel and its occupancy.

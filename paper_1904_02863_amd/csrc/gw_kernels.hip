@@ -924,42 +924,62 @@ __global__ __launch_bounds__(kBlock) void ragged_finalize_kernel(const RaggedEve
 
 // ---------------------------------------------------------------- waveform materialisation
 // h[s][ch][k] = a_k P_ch e^{-i Phi_0,k} e^{-2 pi i f_k delta_ch} for k <= K_s
-// (zero above the template end); one thread per bin,
-// consecutive bins in consecutive lanes for coalesced 16-byte stores.
+// (zero above the template end).  Block (sample s, span of kWaveBins bins):
+// thread t writes bins span + t + kBlock j, j < kWaveSteps, so that every
+// store instruction of a wave covers 64 consecutive bins.  The delay phasor
+// of each channel is evaluated exactly at the thread's first bin and advanced
+// by the fixed rotation e^{-2 pi i kBlock df delta} to its next bins.
+constexpr int kWaveSteps = 4;
+constexpr int kWaveBins = kBlock * kWaveSteps;
+
 __global__ __launch_bounds__(kBlock) void waveform_kernel(int64_t n_bins, int n_out, int64_t n_samples,
-                                                           int64_t blocks_per_sample,
+                                                           int64_t blocks_per_sample, double df,
                                                            const Tab1 *__restrict__ tab1,
                                                            const Tab2 *__restrict__ tab2,
                                                            const double *__restrict__ rec,
                                                            double2 *__restrict__ h_out)
 {
     const int64_t s = (int64_t)blockIdx.x / blocks_per_sample;
-    const int64_t k = ((int64_t)blockIdx.x % blocks_per_sample) * kBlock + threadIdx.x;
-    if (k >= n_bins) return;
+    const int64_t k0 = ((int64_t)blockIdx.x % blocks_per_sample) * kWaveBins + threadIdx.x;
+    if (k0 >= n_bins) return;
     const int status = (int)rec[kRecStatus * n_samples + s];
     const int64_t kcut = (int64_t)rec[kRecKcut * n_samples + s];
     const PhaseCoef cf = load_coef(rec, n_samples, s);
-    const Tab1 tb = tab1[k];
-    const Tab2 t2 = tab2[k];
-    double er, ei;
-    gw_phasor_turns(turns_phase(cf, tb), er, ei);
+    double er[kWaveSteps], ei[kWaveSteps], amp[kWaveSteps];
+#pragma unroll
+    for (int j = 0; j < kWaveSteps; ++j) {
+        const int64_t k = min(k0 + (int64_t)kBlock * j, n_bins - 1);
+        gw_phasor_turns(turns_phase(cf, tab1[k]), er[j], ei[j]);
+        amp[j] = tab2[k].amp;
+    }
+    const double f0 = tab2[k0].f;
     for (int d = 0; d < n_out; ++d) {
         const double pr = rec[(kRecDet + kRecFieldsPerDet * d) * n_samples + s];
         const double pi = rec[(kRecDet + kRecFieldsPerDet * d + 1) * n_samples + s];
         const double delta = rec[(kRecDet + kRecFieldsPerDet * d + 2) * n_samples + s];
-        double gr = er, gi = ei;
+        // T = P e^{-2 pi i f delta} at the thread's first bin; step rotation
+        double rr = 1.0, ri = 0.0, sr = 1.0, si = 0.0;
         if (delta != 0.0) {
-            double rr, ri;
-            gw_phasor_turns(t2.f * delta, rr, ri);
-            gr = er * rr - ei * ri;
-            gi = er * ri + ei * rr;
+            gw_phasor_turns(f0 * delta, rr, ri);
+            gw_phasor_turns((double)kBlock * df * delta, sr, si);
         }
-        double2 h;
-        h.x = t2.amp * (pr * gr - pi * gi);
-        h.y = t2.amp * (pr * gi + pi * gr);
-        if (k > kcut) h = make_double2(0.0, 0.0);
-        if (status != 0) h = make_double2(NAN, NAN);
-        h_out[((int64_t)s * n_out + d) * n_bins + k] = h;
+        double tr = pr * rr - pi * ri, ti = pr * ri + pi * rr;
+        double2 *out = h_out + ((int64_t)s * n_out + d) * n_bins;
+#pragma unroll
+        for (int j = 0; j < kWaveSteps; ++j) {
+            const int64_t k = k0 + (int64_t)kBlock * j;
+            if (k < n_bins) {
+                double2 h;
+                h.x = amp[j] * (tr * er[j] - ti * ei[j]);
+                h.y = amp[j] * (tr * ei[j] + ti * er[j]);
+                if (k > kcut) h = make_double2(0.0, 0.0);
+                if (status != 0) h = make_double2(NAN, NAN);
+                out[k] = h;
+            }
+            const double nr = tr * sr - ti * si;
+            ti = tr * si + ti * sr;
+            tr = nr;
+        }
     }
 }
 
@@ -1162,11 +1182,11 @@ hipError_t launch_lnl_finalize(const gw_grid &grid, int64_t n_samples, int n_det
 hipError_t launch_waveform(const gw_grid &grid, int n_out, int64_t n_samples, const Tab1 *tab1, const Tab2 *tab2,
                            const double *records, gw_c128 *h_out, hipStream_t stream)
 {
-    const int64_t per = (grid.n_bins + kBlock - 1) / kBlock;
+    const int64_t per = (grid.n_bins + kWaveBins - 1) / kWaveBins;
     const int64_t blocks = per * n_samples;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(waveform_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, grid.n_bins, n_out,
-                       n_samples, per, tab1, tab2, records, reinterpret_cast<double2 *>(h_out));
+                       n_samples, per, grid.delta_f, tab1, tab2, records, reinterpret_cast<double2 *>(h_out));
     return hipGetLastError();
 }
 

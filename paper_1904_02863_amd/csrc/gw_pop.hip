@@ -233,7 +233,7 @@ size_t workspace_bytes(int64_t n_events, int64_t n_per, int64_t n_hyper)
 }
 
 hipError_t launch(int64_t n_events, int64_t n_per, const double *samples, int64_t n_hyper, const double *hyper,
-                  void *work, double *lnl, hipStream_t stream)
+                  void *work, double *lnl, hipEvent_t t_start, hipEvent_t t_stop, hipStream_t stream)
 {
     HyperC *hc = static_cast<HyperC *>(work);
     const size_t hc_bytes = ((size_t)n_hyper * sizeof(HyperC) + 255) / 256 * 256;
@@ -246,9 +246,11 @@ hipError_t launch(int64_t n_events, int64_t n_per, const double *samples, int64_
     if (e != hipSuccess) return e;
     const int64_t chunks = (n_per + kPerBlock - 1) / kPerBlock;
     const int64_t n_slots = slots_per_event(n_per);
+    if (t_start && (e = hipEventRecord(t_start, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(weights_kernel, dim3((unsigned)(chunks * n_events)), dim3(kThreads), 0, stream, n_events, n_per,
                        chunks, samples, n_hyper, hc, n_slots, partials);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (t_stop && (e = hipEventRecord(t_stop, stream)) != hipSuccess) return e;
     const int64_t n_pairs = n_hyper * n_events;
     hipLaunchKernelGGL(event_means_kernel, dim3((unsigned)((n_pairs + kWaves - 1) / kWaves)), dim3(kThreads), 0,
                        stream, n_events, n_per, n_slots, n_pairs, partials, lmean);
