@@ -51,6 +51,7 @@ def _load():
         lib.oracle_delay.argtypes = [p, d, d]
         lib.oracle_delay.restype = d
         lib.oracle_waveform.argtypes = [d, d, i64, i32, p, p, p, i32, i64, i32, p]
+        lib.oracle_waveform_at.argtypes = [p, i64, i32, p, p, p, i32, i64, p]
         lib.oracle_lnl.argtypes = [d, d, i64, i32, p, p, p, p, p, i32, i64, i32, i32, p, i32]
         lib.oracle_max_threads.restype = i32
         _lib = lib
@@ -112,6 +113,21 @@ def waveform(f_low: float, delta_f: float, n_bins: int, tensors, vertices, theta
                                  _ptr(th), th.shape[1], th.shape[0], int(bool(isco)), _ptr(out))
     if rc != 0:
         raise ValueError("oracle_waveform rejected its arguments")
+    return out
+
+
+def waveform_at(freqs, tensors, vertices, theta) -> np.ndarray:
+    """Detector responses at an arbitrary list of frequencies, shape
+    (S, n_det, len(freqs)) complex128 (no template end)."""
+    th = _f64(np.atleast_2d(theta))
+    fr = _f64(np.atleast_1d(freqs))
+    n_det = np.asarray(tensors).reshape(-1, 9).shape[0]
+    t, v = _det_arrays(tensors, vertices, n_det)
+    out = np.empty((th.shape[0], n_det, fr.size), dtype=np.complex128)
+    rc = _load().oracle_waveform_at(_ptr(fr), fr.size, n_det, _ptr(t), _ptr(v), _ptr(th), th.shape[1],
+                                    th.shape[0], _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle_waveform_at rejected its arguments")
     return out
 
 

@@ -255,6 +255,31 @@ int oracle_waveform(double f_low, double delta_f, int64_t n_bins, int n_det,
     return 0;
 }
 
+/* Detector responses of n_samples parameter rows at an arbitrary list of
+ * n_freq frequencies (the unevenly spaced frequencies of relative binning):
+ * out[(s * n_det + d) * n_freq + j] = h_det(freqs[j]), n_det >= 1.  Rows that
+ * are out of domain or non-finite produce NaN. */
+int oracle_waveform_at(const double *freqs, int64_t n_freq, int n_det,
+                       const double *tensors, const double *vertices,
+                       const double *theta, int n_param, int64_t n_samples, double complex *out)
+{
+    if (check_args(1.0, n_freq, n_det, n_param, n_samples) || n_det < 1) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < n_samples; ++s) {
+        const double *th = theta + s * n_param;
+        const int ok = classify(th, n_param);
+        source src;
+        if (ok == 1) make_source(th, n_param, n_det, 0, tensors, vertices, &src);
+        for (int64_t j = 0; j < n_freq; ++j) {
+            double complex hp = NAN, hx = NAN;
+            if (ok == 1) polarisations(&src, freqs[j], &hp, &hx);
+            for (int d = 0; d < n_det; ++d)
+                out[((size_t)s * n_det + d) * n_freq + j] = ok == 1 ? response(&src, d, freqs[j], hp, hx) : NAN;
+        }
+    }
+    return 0;
+}
+
 /* Neumaier's compensated summation step. */
 static void neumaier_add(double *sum, double *comp, double x)
 {

@@ -339,3 +339,48 @@ def long_bns(f_low: float, duration: float, n_det: int, n_samples: int, index: i
     inj = draw(g["injection"], 1)[0]
     theta = draw(g["samples"], n_samples)
     return Workload(f"bns-{f_low:g}hz-{duration:g}s", grid, 9, tensors, vertices, s, nz, inj, theta)
+
+
+def near_fiducial(theta0: np.ndarray, n_samples: int, rng: np.random.Generator, scale: float = 1.0) -> np.ndarray:
+    """Parameter rows scattered around theta0 the way a binary-neutron-star
+    posterior is (the regime of relative binning): chirp mass to ~1e-5
+    relative, q +-0.05 (kept in (0, 1]), d_L +-10 %, phi_c +-0.3 rad, t_c
+    +-0.3 ms, sky position +-0.02 rad, psi and iota +-0.1 rad; `scale`
+    widens or narrows every spread."""
+    th = np.repeat(np.asarray(theta0, dtype=np.float64)[None], n_samples, axis=0)
+    z = rng.standard_normal((n_samples, th.shape[1]))
+    spread = np.array([1e-5 * th[0, 0], 0.05, 0.1 * th[0, 2], 0.3, 3e-4, 0.02, 0.02, 0.1, 0.1])[:th.shape[1]]
+    th = th + scale * spread * z
+    th[:, 1] = np.minimum(np.abs(th[:, 1]), 1.0)
+    return th
+
+
+def relbin_bns(f_low: float, duration: float, n_det: int, n_samples: int, index: int = 7) -> Workload:
+    """A neutron-star event for relative binning: the grid, noise and
+    detectors of `long_bns` (f_low .. 2048 Hz), an injection with m1, m2 in
+    [1.2, 1.6] solar masses at 100 Mpc, and rows near the injection
+    (`near_fiducial`).  Callers that want a given SNR scale the distance of
+    the injection and of every row with `scale_distance`."""
+    g = seeds(index)
+    grid = make_grid(f_low, 2048.0, duration)
+    tensors, vertices = stack_detectors(network(g["detectors"], n_det))
+    f = grid.frequencies()
+    s = np.ascontiguousarray(np.broadcast_to(psd(f), (n_det, grid.n_bins)))
+    nz = np.ascontiguousarray(np.stack([noise(g["noise"], s[d], grid.delta_f) for d in range(n_det)]))
+    rng = g["injection"]
+    m1, m2 = rng.uniform(1.2, 1.6, 2)
+    mc, q = component_masses_to_mc_q(np.array([m1]), np.array([m2]))
+    inj = Prior(dl=(100.0, 100.0)).sample(rng, 1, 9)[0]
+    inj[0], inj[1] = mc[0], q[0]
+    theta = near_fiducial(inj, n_samples, g["samples"])
+    return Workload(f"bns-relbin-{f_low:g}hz-{duration:g}s", grid, 9, tensors, vertices, s, nz, inj, theta)
+
+
+def scale_distance(w: Workload, factor: float) -> Workload:
+    """The same workload with the luminosity distance of the injection and of
+    every row multiplied by `factor` (the signal amplitude scales as 1/d_L)."""
+    inj = w.theta_inj.copy()
+    th = w.theta.copy()
+    inj[2] *= factor
+    th[:, 2] *= factor
+    return dataclasses.replace(w, theta_inj=inj, theta=th)
