@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -479,6 +480,106 @@ def bench_waveform(args):
     print(json.dumps(result), flush=True)
 
 
+def rb_flops_per_pair(n_det: int) -> int:
+    """Algorithmic FP64 flops of the relative-binning kernel per (sample, bin)
+    (FMA = 2): the phase difference polynomial at the bin's upper edge 19
+    (9 FMA + 1 multiply), and per detector the delay term 2, the phasor 34,
+    the ratio (P/P0) e^{-i dPhi} 6, the edge sum and difference 4, and the
+    bin's quadratic form 23 (4 FMA for the A terms, three squared forms of 3
+    each, 3 FMA for the B terms)."""
+    return 19 + 69 * n_det
+
+
+def bench_relbin(args):
+    """Relative binning (named in Secs. I and V): the 15 Hz / 512 s neutron-star
+    event (3 detectors, 1,040,897 bins, network SNR 30) cut into ~10^3 bins by
+    the phase-bound rule (chi 1, eps 0.03); one step = one gw_rb_lnl call over
+    65,536 rows near the fiducial (the injection)."""
+    import torch
+
+    import paper_1904_02863_amd as gw
+    import synth
+
+    n = args.samples or 65536
+    dev = torch.device("cuda", 0)
+    ws = gw.Workspace(0)
+    w = synth.relbin_bns(15.0, 512.0, 3, n, index=6)
+    g = w.grid
+    psd = torch.from_numpy(w.psd).to(dev)
+    h = gw.waveform_batch(g, w.tensors, w.vertices, torch.from_numpy(w.theta_inj[None]).to(dev), workspace=ws)[0]
+    rho = math.sqrt(float((4.0 * g.delta_f * (h.real ** 2 + h.imag ** 2) / psd).sum()))
+    w = synth.scale_distance(w, rho / 30.0)
+    data = torch.from_numpy(w.noise).to(dev) + h * (30.0 / rho)
+    del h
+    edges = gw.rb_edges(g, 1.0, 0.03)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rbh = gw.RelativeBinning(g, w.tensors, w.vertices, data, psd, w.theta_inj, edges, workspace=ws)
+    prep_s = time.perf_counter() - t0
+    n_rb, n_det = rbh.shape
+    theta = torch.from_numpy(w.theta).to(dev)
+    out = torch.empty(n, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        rbh.lnl(theta, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    ws.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rbh.lnl(theta, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    kernel_ms, launches = ws.kernel_time()
+    ws.set_timing(False)
+    kernel_s = kernel_ms / launches / 1e3
+    if not torch.isfinite(out).all():
+        raise SystemExit("non-finite relative-binning lnL")
+    # the full likelihood of the same event, for its rate and the estimate's error
+    m = min(n, 4096)
+    full = gw.lnl_batch(g, w.tensors, w.vertices, data, psd, theta[:m].contiguous(), workspace=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(3):
+        gw.lnl_batch(g, w.tensors, w.vertices, data, psd, theta[:m].contiguous(), out=full, workspace=ws)
+    torch.cuda.synchronize()
+    full_s = (time.perf_counter() - t1) / 3
+    rbh.lnl(theta, out=out, workspace=ws)
+    err = (out[:m] - full).abs().max().item()
+    flops = rb_flops_per_pair(n_det) * n * n_rb
+    result = {
+        "metric": "lnL evals/s (relative binning, BNS 15 Hz 512 s, 3 det)", "value": n / t, "unit": "lnL evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "bns-relbin-15hz-512s", "n_samples": n, "n_det": n_det, "n_bins": g.n_bins,
+                   "rb_bins": n_rb, "chi": 1.0, "eps": 0.03},
+        "roofline": {"bound": "alu", "achieved": flops / kernel_s / 1e12, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": flops / kernel_s / 1e12 / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "relative-binning lnl_kernel<3>", "kernel_ms": kernel_s * 1e3,
+                     "flops_per_pair": rb_flops_per_pair(n_det)},
+        "preparation_ms": prep_s * 1e3,
+        "full_likelihood": {"value": m / full_s, "ms_per_call": full_s * 1e3, "rows": m},
+        "max_abs_error_vs_full": err,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import relbin as rb
+        d_np = data.cpu().numpy()
+        t0 = time.perf_counter()
+        summ = rb.summary(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, d_np, w.psd, w.theta_inj, edges)
+        prep_cpu = time.perf_counter() - t0
+        done, spent = 0, 0.0
+        while spent < args.cpu_seconds / 2 and done < n:
+            t0 = time.perf_counter()
+            rb.lnl(summ, w.tensors, w.vertices, w.theta[done:done + 256])
+            spent += time.perf_counter() - t0
+            done += 256
+        result["cpu_baseline"] = {"value": done / spent, "unit": "lnL evals/s", "cores": oracle.max_threads(),
+                                  "kind": "oracle", "sample": f"{done} of the {n} rows, {spent:.1f} s "
+                                  f"(summary data {prep_cpu:.1f} s, not counted)"}
+    rbh.close()
+    ws.close()
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -487,7 +588,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--workload", default="bbh-3det-128s",
                     choices=["bbh-3det-128s", "bbh-1det-4s", "bns-15hz-512s", "bns-ragged", "flow-mcmc",
-                             "population", "waveform"])
+                             "population", "waveform", "bns-relbin"])
     ap.add_argument("--mcmc-burn", type=int, default=4000, help="flow-mcmc: random-walk burn-in steps")
     ap.add_argument("--mcmc-steps", type=int, default=1024, help="flow-mcmc: production steps of each sampler")
     ap.add_argument("--flow-steps", type=int, default=3000, help="flow-mcmc: Adam steps")
@@ -522,6 +623,9 @@ def main():
         return
     if args.workload == "waveform":
         bench_waveform(args)
+        return
+    if args.workload == "bns-relbin":
+        bench_relbin(args)
         return
     w, data, psd, theta = build_inputs(args.workload, args.samples)
     g = w.grid

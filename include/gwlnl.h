@@ -140,11 +140,11 @@ int gw_workspace_reserve(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_
 int64_t gw_workspace_bytes(const gw_workspace *ws);
 
 /* Measurement support.  While timing is enabled (enable != 0), every
- * gw_lnl_batch, gw_waveform_batch and gw_pop_lnl call made with this
- * workspace records a pair of HIP events on its own stream around its hot
- * kernel: the tile kernel that forms Z for every sample, bin and detector;
- * the kernel that writes the templates; the kernel that forms the population
- * weights.  Enabling (or disabling) clears earlier records. */
+ * gw_lnl_batch, gw_waveform_batch, gw_pop_lnl and gw_rb_lnl call made with
+ * this workspace records a pair of HIP events on its own stream around its
+ * hot kernel: the tile kernel that forms Z for every sample, bin and
+ * detector; the kernel that writes the templates; the kernel that forms the
+ * population weights; the per-sample relative-binning kernel.  Enabling (or disabling) clears earlier records. */
 int gw_workspace_set_timing(gw_workspace *ws, int enable);
 
 /* Sum of the recorded hot-kernel durations in milliseconds and the number of
@@ -245,6 +245,84 @@ int gw_lnl_ragged(gw_workspace *ws, int n_events, const gw_event *events,
  */
 int gw_pop_lnl(gw_workspace *ws, int64_t n_events, int64_t n_per_event, const double *samples, int64_t n_hyper,
                const double *hyper, double *lnl_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Relative binning: Eq. (cbclike) from about 10^3 frequencies.
+ *
+ * Secs. I and V name relative binning (Zackay, Dai & Venumadhav 2018,
+ * arXiv:1806.08792) as the other route to long signals.  Around a fiducial
+ * template h0 (parameters theta0) the ratio r = h(theta) / h0 is smooth in
+ * frequency, so the grid is cut into B bins by edges e_0 = 0 < ... < e_B =
+ * n_bins - 1 (bin b holds grid bins e_b .. e_{b+1} - 1, the last bin also
+ * e_B), r is taken as linear in each bin between its values at the two
+ * edges, and a sample needs the template only at the B + 1 edge frequencies
+ * plus summary data formed once per event (w = 4 delta_f / S, fm the bin
+ * centre, r0 and r1 the ratio's value at fm and its slope):
+ *   A0 = sum w d conj(h0),  A1 = sum w d conj(h0) (f - fm),
+ *   B0 = sum w |h0|^2,      B1 = sum w |h0|^2 (f - fm),  B2 = sum w |h0|^2 (f - fm)^2,
+ *   lnL = Re sum [A0 conj(r0) + A1 conj(r1)]
+ *         - 1/2 sum [B0 |r0|^2 + 2 B1 Re(r0 conj(r1)) + B2 |r1|^2] - <d,d>/2.
+ * The |r1|^2 B2 term, which Zackay et al. drop, is kept: the estimate is then
+ * exact where r is linear in every bin (an edge at every grid bin) and at
+ * theta0.  Elsewhere it approximates gw_lnl_batch with an error that falls as
+ * the bins narrow.  Templates are never ended at f_isco here.
+ */
+
+/* Bin edges by the phase-bound rule of Zackay et al. (their Sec. III):
+ *   dPsi(f) = 2 pi chi sum_i sgn(g_i) (f / f*_i)^g_i,  g = (-5/3, -2/3, 1, 5/3, 7/3),
+ *   f*_i = f_min for g_i < 0 and f_max otherwise (first and last grid frequency);
+ * edges at grid bin 0, at every bin k where floor((dPsi(f_k) - dPsi(f_0)) / eps)
+ * steps up, and at n_bins - 1.  Host computation; no device is used.
+ *   grid       host; n_bins >= 2.
+ *   chi, eps   finite and > 0.
+ *   edges_out  host [capacity] int64, or NULL to ask for the count only.
+ *   n_edges    receives the number of edges (B + 1).
+ * Returns GW_EINVAL when edges_out is not NULL and capacity < *n_edges
+ * (*n_edges is set all the same). */
+int gw_rb_edges(const gw_grid *grid, double chi, double eps, int64_t *edges_out, int64_t capacity,
+                int64_t *n_edges);
+
+typedef struct gw_relbin gw_relbin;
+
+/* Prepare one event: the edge tables, the summary data of every detector and
+ * bin, <d,d> and sum ln(2 pi S).  Synchronous: returns once the work it
+ * enqueued on `stream` has finished, so data and psd may be released then.
+ *   ws       workspace; the handle lives on its device and the call uses its
+ *            arena for the grid tables.
+ *   grid, n_det, dets, data, psd  as for gw_lnl_batch, with n_bins >= 2.
+ *   theta0   host [n_param]: the fiducial parameters.  They must be in the
+ *            domain (finite, Mc > 0, q in (0, 1], d_L > 0) and give a non-zero
+ *            response on every detector, else GW_EINVAL.
+ *   n_param  5 or 9; rows passed to gw_rb_lnl use the same layout.
+ *   edges    host [n_edges], n_edges >= 2, strictly increasing from 0 to
+ *            n_bins - 1 (for instance from gw_rb_edges).
+ *   flags    0 or GW_FLAG_ADD_NORM (every lnL then carries -sum ln(2 pi S));
+ *            any other bit is GW_EINVAL.
+ *   rb       receives the handle, which owns about 72 (B + 1) + (120 n_det + 16) B
+ *            bytes of device memory until gw_rb_destroy. */
+int gw_rb_create(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_detector *dets, const gw_c128 *data,
+                 const double *psd, const double *theta0, int n_param, const int64_t *edges, int64_t n_edges,
+                 unsigned flags, gw_relbin **rb, hipStream_t stream);
+
+/* Free a handle and its device memory (waits for the device).  NULL is ignored. */
+int gw_rb_destroy(gw_relbin *rb);
+
+/* Relative-binning lnL of every row of theta.
+ *   ws       workspace on the handle's device: scratch for the sample records
+ *            and partial sums, and the hot-kernel timer (gw_workspace_set_timing).
+ *   theta    device [n_samples][n_param of the handle]; lnl_out device [n_samples].
+ * Per-row domain rules as for gw_lnl_batch. */
+int gw_rb_lnl(gw_workspace *ws, const gw_relbin *rb, const double *theta, int64_t n_samples, double *lnl_out,
+              hipStream_t stream);
+
+/* Number of bins B and of detectors of a handle. */
+int gw_rb_shape(const gw_relbin *rb, int64_t *n_rb, int *n_det);
+
+/* Copies of the summary data as formed (inspection and test support; waits
+ * for the device):
+ *   raw_out     host [B][n_det][7]: A0 re, A0 im, A1 re, A1 im, B0, B1, B2;
+ *   totals_out  host [2]: <d,d> and sum ln(2 pi S).  Either may be NULL. */
+int gw_rb_summary(const gw_relbin *rb, double *raw_out, double *totals_out);
 
 /* Tile shape the last gw_lnl_ragged call used: bins staged in LDS per tile and
  * bins per work item.  The first call for a new size class times every

@@ -32,7 +32,8 @@ FLAG_ADD_NORM = 4
 # Every symbol include/gwlnl.h declares.
 EXPORTED = ("gw_workspace_create", "gw_workspace_destroy", "gw_workspace_reserve", "gw_workspace_bytes",
             "gw_workspace_set_timing", "gw_workspace_kernel_time", "gw_waveform_batch", "gw_lnl_batch",
-            "gw_lnl_ragged", "gw_ragged_tuning", "gw_pop_lnl", "gw_last_error", "gw_version",
+            "gw_lnl_ragged", "gw_ragged_tuning", "gw_pop_lnl", "gw_rb_edges", "gw_rb_create", "gw_rb_destroy",
+            "gw_rb_lnl", "gw_rb_shape", "gw_rb_summary", "gw_last_error", "gw_version",
             "gw_philox_raw", "gw_philox_fill", "gw_philox_chain_normals", "gw_mcmc_to_theta", "gw_mcmc_rw_propose",
             "gw_mcmc_accept", "gw_mcmc_update_mode", "gw_flow_create", "gw_flow_destroy", "gw_flow_num_params",
             "gw_flow_set_params", "gw_flow_get_params", "gw_flow_forward", "gw_flow_inverse", "gw_flow_gradients",
@@ -83,6 +84,14 @@ def load_library() -> ctypes.CDLL:
         lib.gw_lnl_ragged.argtypes = [vp, i32, ctypes.POINTER(GwEvent), vp, vp, vp, i32, vp, i32, u32, vp]
         lib.gw_ragged_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         lib.gw_pop_lnl.argtypes = [vp, i64, i64, vp, i64, vp, vp, vp]
+        lib.gw_rb_edges.argtypes = [ctypes.POINTER(GwGrid), ctypes.c_double, ctypes.c_double, vp, i64,
+                                    ctypes.POINTER(i64)]
+        lib.gw_rb_create.argtypes = [vp, ctypes.POINTER(GwGrid), i32, ctypes.POINTER(GwDetector), vp, vp, vp, i32,
+                                     vp, i64, u32, ctypes.POINTER(vp), vp]
+        lib.gw_rb_destroy.argtypes = [vp]
+        lib.gw_rb_lnl.argtypes = [vp, vp, vp, i64, vp, vp]
+        lib.gw_rb_shape.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]
+        lib.gw_rb_summary.argtypes = [vp, vp, vp]
         u64, u32p = ctypes.c_uint64, ctypes.c_uint32
         lib.gw_philox_raw.argtypes = [u64, u32p, u32p, u64, i64, vp, vp]
         lib.gw_philox_fill.argtypes = [u64, u32p, u32p, i32, i64, vp, vp]
@@ -343,6 +352,96 @@ def pop_lnl(samples, hyper, *, out=None, workspace: Workspace | None = None, str
     _check(load_library().gw_pop_lnl(ws.handle, samples.shape[1], samples.shape[2], samples.data_ptr(), k,
                                      hyper.data_ptr(), out.data_ptr(), _stream_ptr(dev, stream)))
     return out
+
+
+def rb_edges(grid, chi: float = 1.0, eps: float = 0.5) -> np.ndarray:
+    """Relative-binning bin edges (grid indices) by the phase-bound rule of
+    gw_rb_edges; a host computation."""
+    g = make_grid(grid)
+    lib = load_library()
+    n = ctypes.c_int64()
+    _check(lib.gw_rb_edges(ctypes.byref(g), float(chi), float(eps), None, 0, ctypes.byref(n)))
+    out = np.empty(n.value, dtype=np.int64)
+    _check(lib.gw_rb_edges(ctypes.byref(g), float(chi), float(eps), out.ctypes.data_as(ctypes.c_void_p), out.size,
+                           ctypes.byref(n)))
+    return out
+
+
+class RelativeBinning:
+    """One event prepared for the relative-binning likelihood (gw_relbin).
+
+    data complex128 [n_det, M] and psd float64 [n_det, M] on one GPU; theta0
+    the fiducial parameters (host, 5 or 9 values); edges the bin edges (host
+    int64, from `rb_edges` or any strictly rising list from 0 to M - 1);
+    flags 0 or FLAG_ADD_NORM.  The preparation is synchronous."""
+
+    def __init__(self, grid, tensors, vertices, data, psd, theta0, edges, *, flags: int = 0,
+                 workspace: Workspace | None = None, stream=None):
+        torch = _torch()
+        g = make_grid(grid)
+        th0 = np.ascontiguousarray(theta0, dtype=np.float64).reshape(-1)
+        n_param = th0.size
+        n_det = data.shape[0] if data.dim() == 2 else -1
+        data = _cuda_tensor(data, torch.complex128, "data", (n_det, g.n_bins))
+        psd = _cuda_tensor(psd, torch.float64, "psd", (n_det, g.n_bins))
+        dev = data.device.index
+        if psd.device.index != dev:
+            raise ValueError("data and psd must be on the same device")
+        e = np.ascontiguousarray(edges, dtype=np.int64).reshape(-1)
+        dets = make_detectors(tensors, vertices) if n_param != 5 or tensors is not None else (GwDetector * 1)()
+        self.device = dev
+        self.n_param = n_param
+        self._ws = workspace or default_workspace(dev)
+        h = ctypes.c_void_p()
+        _check(load_library().gw_rb_create(self._ws.handle, ctypes.byref(g), n_det, dets, data.data_ptr(),
+                                           psd.data_ptr(), th0.ctypes.data_as(ctypes.c_void_p), n_param,
+                                           e.ctypes.data_as(ctypes.c_void_p), e.size, int(flags), ctypes.byref(h),
+                                           _stream_ptr(dev, stream)))
+        self._h = h
+
+    @property
+    def shape(self) -> tuple[int, int]:
+        """(bins B, detectors)."""
+        nb, nd = ctypes.c_int64(), ctypes.c_int()
+        _check(load_library().gw_rb_shape(self._h, ctypes.byref(nb), ctypes.byref(nd)))
+        return nb.value, nd.value
+
+    def lnl(self, theta, *, out=None, workspace: Workspace | None = None, stream=None):
+        """Relative-binning lnL of every row of theta (float64 [S, n_param] on the handle's GPU)."""
+        torch = _torch()
+        theta = _cuda_tensor(theta, torch.float64, "theta")
+        if theta.dim() != 2 or theta.shape[1] != self.n_param:
+            raise ValueError(f"theta must be [n_samples, {self.n_param}]")
+        if theta.device.index != self.device:
+            raise ValueError("theta must be on the handle's device")
+        n = theta.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=theta.device)
+        out = _cuda_tensor(out, torch.float64, "out", (n,))
+        ws = workspace or self._ws
+        _check(load_library().gw_rb_lnl(ws.handle, self._h, theta.data_ptr(), n, out.data_ptr(),
+                                        _stream_ptr(self.device, stream)))
+        return out
+
+    def summary(self) -> tuple[np.ndarray, np.ndarray]:
+        """(raw [B, n_det, 7]: A0 re, A0 im, A1 re, A1 im, B0, B1, B2; totals [<d,d>, sum ln 2 pi S])."""
+        nb, nd = self.shape
+        raw = np.empty((nb, nd, 7))
+        tot = np.empty(2)
+        _check(load_library().gw_rb_summary(self._h, raw.ctypes.data_as(ctypes.c_void_p),
+                                            tot.ctypes.data_as(ctypes.c_void_p)))
+        return raw, tot
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(load_library().gw_rb_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> int:

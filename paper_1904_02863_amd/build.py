@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgwlnl.so")
-SOURCES = ["gw_api.hip", "gw_kernels.hip", "gw_flow.hip", "gw_mcmc.hip", "gw_pop.hip"]
+SOURCES = ["gw_api.hip", "gw_kernels.hip", "gw_flow.hip", "gw_mcmc.hip", "gw_pop.hip", "gw_relbin.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -43,6 +43,22 @@ struct gw_workspace {
     size_t tables_tab1 = 0, tables_tab2 = 0;
 };
 
+// One event prepared for relative binning: a single device allocation
+// carved into the sections below (layout in gw_internal.h, namespace rb).
+struct gw_relbin {
+    int device = 0;
+    gw_grid grid{};
+    int n_det = 0, n_param = 0;
+    unsigned flags = 0;
+    int64_t n_rb = 0;                 // bins B; edges B + 1
+    gw::DetGeom geom{};
+    void *mem = nullptr;
+    int64_t *edge_idx = nullptr;
+    gw::rb::RbEdge *edges = nullptr;
+    gw::rb::RbCoef *coef = nullptr;
+    double *raw = nullptr, *bin_dd = nullptr, *totals = nullptr, *fid = nullptr;
+};
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -75,6 +91,7 @@ struct DeviceGuard {
 };
 
 constexpr size_t kAlign = 256;
+#define GW_PI_HOST 3.141592653589793
 constexpr unsigned kLnlFlags = GW_FLAG_DIRECT | GW_FLAG_TERM_ISCO | GW_FLAG_ADD_NORM;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -608,6 +625,29 @@ int ragged_run(gw_workspace *ws, int n_events, const gw_event *events, const std
     return e == hipSuccess ? GW_OK : hip_fail(e, "hipGraphLaunch");
 }
 
+// dPsi(f) of the relative-binning edge rule, evaluated term by term in a
+// fixed order without contraction into fused multiply-adds, so that the same
+// arithmetic gives the same edges wherever it runs.
+double rb_phase_bound(double f, double f_min, double f_max, double chi)
+{
+#pragma clang fp contract(off)
+    static const double kGamma[5] = {-5.0 / 3.0, -2.0 / 3.0, 1.0, 5.0 / 3.0, 7.0 / 3.0};
+    double total = 0.0;
+    for (double g : kGamma) {
+        const double fstar = g < 0.0 ? f_min : f_max;
+        total = total + std::copysign(1.0, g) * std::pow(f / fstar, g);
+    }
+    return 2.0 * GW_PI_HOST * chi * total;
+}
+
+// Level of grid bin k under the edge rule: floor((dPsi(f_k) - dPsi(f_0)) / eps).
+double rb_level(const gw_grid &g, int64_t k, double psi0, double f_max, double chi, double eps)
+{
+#pragma clang fp contract(off)
+    const double f = g.f_low + (double)k * g.delta_f;
+    return std::floor((rb_phase_bound(f, g.f_low, f_max, chi) - psi0) / eps);
+}
+
 }  // namespace
 
 namespace gw {
@@ -815,6 +855,221 @@ int gw_pop_lnl(gw_workspace *ws, int64_t n_events, int64_t n_per_event, const do
                                    stream);
     if (e != hipSuccess) return hip_fail(e, "gw_pop_lnl");
     if (t_stop) ++ws->timed;
+    return GW_OK;
+}
+
+int gw_rb_edges(const gw_grid *grid, double chi, double eps, int64_t *edges_out, int64_t capacity, int64_t *n_edges)
+{
+    if (!n_edges) return fail(GW_EINVAL, "n_edges is NULL");
+    *n_edges = 0;
+    if (int rc = check_grid(grid)) return rc;
+    if (grid->n_bins < 2) return fail(GW_EINVAL, "relative binning needs n_bins >= 2");
+    if (!(chi > 0.0) || !std::isfinite(chi) || !(eps > 0.0) || !std::isfinite(eps))
+        return fail(GW_EINVAL, "chi and eps must be finite and > 0");
+    const gw_grid g = *grid;
+    const int64_t last = g.n_bins - 1;
+    double f_max;
+    {
+#pragma clang fp contract(off)
+        f_max = g.f_low + (double)last * g.delta_f;
+    }
+    const double psi0 = rb_phase_bound(g.f_low, g.f_low, f_max, chi);
+    // dPsi rises with f, so the level never falls: each next edge is the first
+    // bin whose level exceeds the current edge's, found by bisection.
+    const double top = rb_level(g, last, psi0, f_max, chi, eps);
+    std::vector<int64_t> out{0};
+    int64_t k = 0;
+    double level = rb_level(g, 0, psi0, f_max, chi, eps);
+    while (level < top) {
+        int64_t lo = k + 1, hi = last;
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (rb_level(g, mid, psi0, f_max, chi, eps) > level) hi = mid;
+            else lo = mid + 1;
+        }
+        k = lo;
+        level = rb_level(g, k, psi0, f_max, chi, eps);
+        out.push_back(k);
+    }
+    if (out.back() != last) out.push_back(last);
+    *n_edges = (int64_t)out.size();
+    if (!edges_out) return GW_OK;
+    if (capacity < *n_edges) return fail(GW_EINVAL, "edges_out too small");
+    std::memcpy(edges_out, out.data(), sizeof(int64_t) * out.size());
+    return GW_OK;
+}
+
+int gw_rb_create(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_detector *dets, const gw_c128 *data,
+                 const double *psd, const double *theta0, int n_param, const int64_t *edges, int64_t n_edges,
+                 unsigned flags, gw_relbin **rb, hipStream_t stream)
+{
+    if (!rb) return fail(GW_EINVAL, "rb is NULL");
+    *rb = nullptr;
+    if (int rc = check_common(ws, grid, 1, n_det, n_param, 1)) return rc;
+    if (!data || !psd || !theta0 || !edges) return fail(GW_EINVAL, "NULL argument");
+    if (grid->n_bins < 2) return fail(GW_EINVAL, "relative binning needs n_bins >= 2");
+    if (flags & ~(unsigned)GW_FLAG_ADD_NORM) return fail(GW_EINVAL, "relative binning flags: only GW_FLAG_ADD_NORM");
+    if (n_edges < 2 || edges[0] != 0 || edges[n_edges - 1] != grid->n_bins - 1)
+        return fail(GW_EINVAL, "edges must run from 0 to n_bins - 1");
+    for (int64_t i = 1; i < n_edges; ++i)
+        if (edges[i] <= edges[i - 1]) return fail(GW_EINVAL, "edges must rise strictly");
+    if (n_edges - 1 > 0x7fffffffLL) return fail(GW_EINVAL, "too many bins");
+    for (int i = 0; i < n_param; ++i)
+        if (!std::isfinite(theta0[i])) return fail(GW_EINVAL, "theta0 is not finite");
+    if (!(theta0[0] > 0.0) || !(theta0[1] > 0.0 && theta0[1] <= 1.0) || !(theta0[2] > 0.0))
+        return fail(GW_EINVAL, "theta0 is outside the domain");
+    gw::DetGeom geom;
+    if (int rc = check_dets(n_det, dets, n_param, &geom)) return rc;
+    DeviceGuard g(ws->device);
+    if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
+    drop_ragged_graph(ws);               // the arena is about to be laid out for the preparation
+    const int64_t n_rb = n_edges - 1;
+    const int n_fields = gw::record_fields(n_det);
+    Carver w;
+    const size_t o1 = w.take(sizeof(gw::Tab1) * grid->n_bins);
+    const size_t o2 = w.take(sizeof(gw::Tab2) * grid->n_bins);
+    const size_t oth = w.take(sizeof(double) * n_param);
+    if (int rc = ensure_capacity(ws, w.offset)) return rc;
+    Carver c;
+    const size_t h_idx = c.take(sizeof(int64_t) * n_edges);
+    const size_t h_edges = c.take(sizeof(gw::rb::RbEdge) * n_edges);
+    const size_t h_coef = c.take(sizeof(gw::rb::RbCoef) * n_rb * n_det);
+    const size_t h_raw = c.take(sizeof(double) * gw::rb::kRawPerDet * n_rb * n_det);
+    const size_t h_dd = c.take(sizeof(double) * 2 * n_rb);
+    const size_t h_tot = c.take(sizeof(double) * 2);
+    const size_t h_fid = c.take(sizeof(double) * n_fields);
+    auto *h = new gw_relbin();
+    h->device = ws->device;
+    h->grid = *grid;
+    h->n_det = n_det;
+    h->n_param = n_param;
+    h->flags = flags;
+    h->n_rb = n_rb;
+    h->geom = geom;
+    hipError_t e = hipMalloc(&h->mem, c.offset);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(GW_ENOMEM, "relative-binning hipMalloc failed");
+    }
+    char *base = static_cast<char *>(h->mem);
+    h->edge_idx = reinterpret_cast<int64_t *>(base + h_idx);
+    h->edges = reinterpret_cast<gw::rb::RbEdge *>(base + h_edges);
+    h->coef = reinterpret_cast<gw::rb::RbCoef *>(base + h_coef);
+    h->raw = reinterpret_cast<double *>(base + h_raw);
+    h->bin_dd = reinterpret_cast<double *>(base + h_dd);
+    h->totals = reinterpret_cast<double *>(base + h_tot);
+    h->fid = reinterpret_cast<double *>(base + h_fid);
+    auto *tab1 = at<gw::Tab1>(ws, o1);
+    auto *tab2 = at<gw::Tab2>(ws, o2);
+    auto *th = at<double>(ws, oth);
+    const char *where = nullptr;
+    if ((e = hipMemcpyAsync(h->edge_idx, edges, sizeof(int64_t) * n_edges, hipMemcpyHostToDevice, stream)) !=
+        hipSuccess)
+        where = "copying the edges";
+    else if ((e = hipMemcpyAsync(th, theta0, sizeof(double) * n_param, hipMemcpyHostToDevice, stream)) != hipSuccess)
+        where = "copying theta0";
+    else if ((e = bin_tables(ws, *grid, o1, o2, tab1, tab2, stream)) != hipSuccess)
+        where = "event tables";
+    else if ((e = gw::launch_sample_prep(*grid, 1, n_param, n_det, false, false, geom, th, h->fid, stream)) !=
+             hipSuccess)
+        where = "fiducial record";
+    else if ((e = gw::rb::launch_edges(*grid, n_edges, h->edge_idx, h->edges, stream)) != hipSuccess)
+        where = "edge tables";
+    else if ((e = gw::rb::launch_summary(*grid, n_det, n_rb, h->edge_idx, tab1, tab2, h->fid, data, psd, h->raw,
+                                         h->coef, h->bin_dd, h->totals, stream)) != hipSuccess)
+        where = "summary data";
+    else if ((e = hipStreamSynchronize(stream)) != hipSuccess)
+        where = "waiting for the preparation";
+    if (where) {
+        (void)hipFree(h->mem);
+        delete h;
+        return hip_fail(e, where);
+    }
+    std::vector<double> rec(n_fields);
+    if ((e = hipMemcpy(rec.data(), h->fid, sizeof(double) * n_fields, hipMemcpyDeviceToHost)) != hipSuccess) {
+        (void)hipFree(h->mem);
+        delete h;
+        return hip_fail(e, "reading the fiducial record");
+    }
+    for (int d = 0; d < n_det; ++d) {
+        const double pr = rec[gw::kRecDet + gw::kRecFieldsPerDet * d];
+        const double pi = rec[gw::kRecDet + gw::kRecFieldsPerDet * d + 1];
+        if (!(pr * pr + pi * pi > 0.0) || !std::isfinite(pr * pr + pi * pi)) {
+            (void)hipFree(h->mem);
+            delete h;
+            return fail(GW_EINVAL, "the fiducial template vanishes on a detector");
+        }
+    }
+    *rb = h;
+    return GW_OK;
+}
+
+int gw_rb_destroy(gw_relbin *rb)
+{
+    if (!rb) return GW_OK;
+    DeviceGuard g(rb->device);
+    hipError_t e = hipFree(rb->mem);
+    delete rb;
+    return e == hipSuccess ? GW_OK : hip_fail(e, "hipFree");
+}
+
+int gw_rb_shape(const gw_relbin *rb, int64_t *n_rb, int *n_det)
+{
+    if (!rb || !n_rb || !n_det) return fail(GW_EINVAL, "NULL argument");
+    *n_rb = rb->n_rb;
+    *n_det = rb->n_det;
+    return GW_OK;
+}
+
+int gw_rb_summary(const gw_relbin *rb, double *raw_out, double *totals_out)
+{
+    if (!rb) return fail(GW_EINVAL, "rb is NULL");
+    DeviceGuard g(rb->device);
+    if (!g.ok) return fail(GW_EDEVICE, "cannot select the handle's device");
+    hipError_t e;
+    if (raw_out &&
+        (e = hipMemcpy(raw_out, rb->raw, sizeof(double) * gw::rb::kRawPerDet * rb->n_rb * rb->n_det,
+                       hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "copying the summary data");
+    if (totals_out && (e = hipMemcpy(totals_out, rb->totals, sizeof(double) * 2, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "copying the totals");
+    return GW_OK;
+}
+
+int gw_rb_lnl(gw_workspace *ws, const gw_relbin *rb, const double *theta, int64_t n_samples, double *lnl_out,
+              hipStream_t stream)
+{
+    if (!ws || !rb) return fail(GW_EINVAL, "workspace or handle is NULL");
+    if (n_samples < 0) return fail(GW_EINVAL, "n_samples must be >= 0");
+    if (ws->device != rb->device) return fail(GW_EINVAL, "workspace and handle are on different devices");
+    if (n_samples == 0) return GW_OK;
+    if (!theta || !lnl_out) return fail(GW_EINVAL, "theta or lnl_out is NULL");
+    DeviceGuard g(ws->device);
+    if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
+    const int n_chunks = gw::rb::lnl_chunks(n_samples, rb->n_rb, ws->n_cu);
+    if ((n_samples + gw::kBlock - 1) / gw::kBlock * n_chunks > 0x7fffffffLL)
+        return fail(GW_EINVAL, "too many samples for one launch");
+    drop_ragged_graph(ws);               // the arena is about to be laid out for this pass
+    Carver c;
+    const size_t orec = c.take(sizeof(double) * gw::record_fields(rb->n_det) * n_samples);
+    const size_t opart = c.take(sizeof(double) * n_chunks * n_samples);
+    if (int rc = ensure_capacity(ws, c.offset)) return rc;
+    ws->tables_valid = false;
+    auto *rec = at<double>(ws, orec);
+    auto *part = at<double>(ws, opart);
+    hipError_t e;
+    if ((e = gw::launch_sample_prep(rb->grid, n_samples, rb->n_param, rb->n_det, false, false, rb->geom, theta, rec,
+                                    stream)) != hipSuccess)
+        return hip_fail(e, "sample prep");
+    hipEvent_t t_start, t_stop;
+    if (int rc = timer_pair(ws, &t_start, &t_stop)) return rc;
+    if ((e = gw::rb::launch_lnl(rb->n_det, n_samples, rb->n_rb, n_chunks, rb->edges, rb->coef, rb->fid, rec, part,
+                                t_start, t_stop, stream)) != hipSuccess)
+        return hip_fail(e, "relative-binning pass");
+    if (t_stop) ++ws->timed;
+    if ((e = gw::rb::launch_finalize(n_samples, n_chunks, part, rec, rb->totals, (rb->flags & GW_FLAG_ADD_NORM) != 0,
+                                     lnl_out, stream)) != hipSuccess)
+        return hip_fail(e, "relative-binning finalize");
     return GW_OK;
 }
 

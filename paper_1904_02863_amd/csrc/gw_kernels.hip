@@ -25,6 +25,7 @@
 
 #include "gw_device_math.h"
 #include "gw_internal.h"
+#include "gw_template.h"
 
 // Tuning of the tile kernel's inner loop: bins per unrolled step, and the
 // number of waves per SIMD the register allocation must leave room for.
@@ -45,21 +46,9 @@ namespace gw {
 constexpr int kTileUnroll = GW_TILE_UNROLL;
 
 // ---------------------------------------------------------------- event tables
-// Tables of bin k: u = f^(1/3), u^2, u^-5, ln u, f and the amplitude f^-7/6.
 __device__ __forceinline__ void bin_tables(double f_low, double df, int64_t k, Tab1 *tab1, Tab2 *tab2)
 {
-    const double f = __dadd_rn(f_low, __dmul_rn((double)k, df));
-    const double u = cbrt(f);
-    Tab1 t1;
-    t1.u = u;
-    t1.u2 = u * u;
-    t1.um5 = pow(f, -5.0 / 3.0);
-    t1.lnu = log(f) / 3.0;
-    tab1[k] = t1;
-    Tab2 t2;
-    t2.f = f;
-    t2.amp = pow(f, -7.0 / 6.0);
-    tab2[k] = t2;
+    freq_tables(bin_frequency(f_low, df, k), tab1[k], tab2[k]);
 }
 
 // One event's device arrays as the preparation kernels see them.
@@ -510,41 +499,6 @@ __global__ void zero_counters_kernel(unsigned *__restrict__ p, int n)
 }
 
 // ---------------------------------------------------------------- the hot loop
-// Phase at detector 0 for one bin, in turns (Horner in u, see RecordField).
-struct PhaseCoef {
-    double c8, c7, c6, c6l, c5, c5l, c4, c3, c2, c0;
-};
-
-__device__ __forceinline__ double turns_phase(const PhaseCoef &c, const Tab1 &t)
-{
-    const double t6 = __builtin_fma(c.c6l, t.lnu, c.c6);
-    const double t5 = __builtin_fma(c.c5l, t.lnu, c.c5);
-    double p = __builtin_fma(c.c8, t.u, c.c7);
-    p = __builtin_fma(p, t.u, t6);
-    p = __builtin_fma(p, t.u, t5);
-    p = __builtin_fma(p, t.u, c.c4);
-    p = __builtin_fma(p, t.u, c.c3);
-    p = __builtin_fma(p, t.u, c.c2);
-    p = __builtin_fma(p, t.u2, c.c0);
-    return p * t.um5;
-}
-
-__device__ __forceinline__ PhaseCoef load_coef(const double *__restrict__ rec, int64_t ns, int64_t s)
-{
-    PhaseCoef c;
-    c.c8 = rec[kRecC8 * ns + s];
-    c.c7 = rec[kRecC7 * ns + s];
-    c.c6 = rec[kRecC6 * ns + s];
-    c.c6l = rec[kRecC6L * ns + s];
-    c.c5 = rec[kRecC5 * ns + s];
-    c.c5l = rec[kRecC5L * ns + s];
-    c.c4 = rec[kRecC4 * ns + s];
-    c.c3 = rec[kRecC3 * ns + s];
-    c.c2 = rec[kRecC2 * ns + s];
-    c.c0 = rec[kRecC0 * ns + s];
-    return c;
-}
-
 // One event seen by the tile loop.
 struct EventView {
     int64_t n_bins, n_samples;

@@ -1,0 +1,345 @@
+// Relative binning (Zackay, Dai & Venumadhav 2018) for the likelihood of
+// Eq. (cbclike): the route to long signals that Secs. I and V of
+// arXiv:1904.02863 name beside GPU waveforms.  About 10^3 unevenly spaced
+// frequencies stand for the whole grid, and no exponential over the grid is
+// evaluated per sample.
+//
+// With the fiducial template h0 (parameters theta0) the ratio on detector d,
+//     r_d(f) = h_d(f; theta) / h0_d(f)
+//            = (P_d / P0_d) e^{-2 pi i [dPhi_0(f) + f (delta_d - delta0_d)]},
+// needs no amplitude (f^-7/6 cancels) and only the phase difference at
+// detector 0, dPhi_0 = Phi_0(theta) - Phi_0(theta0).  Phi_0 is linear in the
+// record's coefficients, so dPhi_0 is the same Horner polynomial evaluated
+// with the differences of the two records' coefficients: a small number of
+// turns near the fiducial, evaluated with the same absolute accuracy.
+// Within a bin r is taken as linear between its values at the two edges, and
+// the bin's share of <d, h> - <h, h>/2 is a quadratic form in those two
+// values whose coefficients (the summary data A0, A1, B0, B1, B2) are sums
+// over the fiducial template, formed once per event by summary_kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "gw_device_math.h"
+#include "gw_internal.h"
+#include "gw_template.h"
+
+namespace gw {
+namespace rb {
+
+namespace {
+
+// Sums v[0..N-1] over the block: wave butterflies, then the four waves in a
+// fixed order.  The totals are valid in thread 0; `red` holds 4 N doubles.
+template <int N>
+__device__ __forceinline__ void block_reduce(double (&v)[N], double *red)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off);
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < N; ++i) red[wave * N + i] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = ((red[i] + red[N + i]) + red[2 * N + i]) + red[3 * N + i];
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- event preparation
+__global__ __launch_bounds__(kBlock) void edges_kernel(double f_low, double df, int64_t n_edges,
+                                                        const int64_t *__restrict__ idx, RbEdge *__restrict__ edges)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n_edges) return;
+    RbEdge e;
+    Tab2 t2;
+    freq_tables(bin_frequency(f_low, df, idx[i]), e.t1, t2);
+    e.f = t2.f;
+    e.pad[0] = e.pad[1] = e.pad[2] = 0.0;
+    edges[i] = e;
+}
+
+// One block per bin b: the summary data of every detector over the grid bins
+// k in [e_b, e_{b+1}) (the last bin also e_B), with w = 4 df / S and the
+// fiducial h0 = a P0 e^{-2 pi i (Phi_0 + f delta0)}:
+//   A0 = sum w d conj(h0), A1 = sum w d conj(h0) (f - fm), B0 = sum w |h0|^2,
+//   B1 = sum w |h0|^2 (f - fm), B2 = sum w |h0|^2 (f - fm)^2,   fm = (f_lo + f_hi)/2,
+// and, over all detectors, sum w |d|^2 and sum ln(2 pi S).  A PSD value <= 0
+// or non-finite makes w NaN.
+__global__ __launch_bounds__(kBlock) void summary_kernel(int n_det, int64_t n_rb, int64_t n_bins, double f_low,
+                                                          double df, const int64_t *__restrict__ idx,
+                                                          const Tab1 *__restrict__ tab1, const Tab2 *__restrict__ tab2,
+                                                          const double *__restrict__ fid,
+                                                          const double2 *__restrict__ data,
+                                                          const double *__restrict__ psd, double *__restrict__ raw,
+                                                          RbCoef *__restrict__ coef, double *__restrict__ bin_dd)
+{
+    __shared__ double red[4 * kRawPerDet];
+    const int64_t b = blockIdx.x;
+    const int64_t lo = idx[b], up = idx[b + 1];
+    const int64_t last = b == n_rb - 1 ? up : up - 1;
+    const double f_lo = bin_frequency(f_low, df, lo), f_hi = bin_frequency(f_low, df, up);
+    const double fm = 0.5 * (f_lo + f_hi);
+    const double width = f_hi - f_lo;
+    const PhaseCoef cf = load_coef(fid, 1, 0);
+    const double wscale = 4.0 * df;
+    double dd = 0.0, nrm = 0.0;
+    for (int d = 0; d < n_det; ++d) {
+        const double pr = fid[kRecDet + kRecFieldsPerDet * d];
+        const double pi = fid[kRecDet + kRecFieldsPerDet * d + 1];
+        const double delta = fid[kRecDet + kRecFieldsPerDet * d + 2];
+        const double2 *__restrict__ dd_row = data + (int64_t)d * n_bins;
+        const double *__restrict__ s_row = psd + (int64_t)d * n_bins;
+        double v[kRawPerDet] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int64_t k = lo + threadIdx.x; k <= last; k += kBlock) {
+            const Tab1 t1 = tab1[k];
+            const Tab2 t2 = tab2[k];
+            double er, ei;
+            gw_phasor_turns(__builtin_fma(t2.f, delta, turns_phase(cf, t1)), er, ei);
+            const double hr = t2.amp * (pr * er - pi * ei);
+            const double hi = t2.amp * (pr * ei + pi * er);
+            const double s = s_row[k];
+            const double w = (s > 0.0 && s < INFINITY) ? wscale / s : NAN;
+            const double2 dk = dd_row[k];
+            const double xr = w * (dk.x * hr + dk.y * hi);
+            const double xi = w * (dk.y * hr - dk.x * hi);
+            const double y = w * (hr * hr + hi * hi);
+            const double x = t2.f - fm;
+            v[0] += xr;
+            v[1] += xi;
+            v[2] += xr * x;
+            v[3] += xi * x;
+            v[4] += y;
+            v[5] += y * x;
+            v[6] += y * x * x;
+            dd += w * (dk.x * dk.x + dk.y * dk.y);
+            nrm += log(2.0 * GW_PI * s);
+        }
+        block_reduce(v, red);
+        if (threadIdx.x == 0) {
+            double *r = raw + (b * n_det + d) * kRawPerDet;
+#pragma unroll
+            for (int i = 0; i < kRawPerDet; ++i) r[i] = v[i];
+            RbCoef c;
+            c.a0r = 0.5 * v[0];
+            c.a0i = 0.5 * v[1];
+            c.a1r = v[2] / width;
+            c.a1i = v[3] / width;
+            c.c0 = -0.125 * v[4];
+            c.c1 = -0.5 * v[5] / width;
+            c.c2 = -0.5 * v[6] / (width * width);
+            c.pad = 0.0;
+            coef[b * n_det + d] = c;
+        }
+    }
+    double t[2] = {dd, nrm};
+    block_reduce(t, red);
+    if (threadIdx.x == 0) {
+        bin_dd[2 * b] = t[0];
+        bin_dd[2 * b + 1] = t[1];
+    }
+}
+
+// One block: totals[0] = <d, d>, totals[1] = sum ln(2 pi S) from the per-bin
+// sums (each thread a strided set of bins, then the fixed block tree).
+__global__ __launch_bounds__(kBlock) void totals_kernel(int64_t n_rb, const double *__restrict__ bin_dd,
+                                                         double *__restrict__ totals)
+{
+    __shared__ double red[4 * 2];
+    double t[2] = {0.0, 0.0};
+    for (int64_t b = threadIdx.x; b < n_rb; b += kBlock) {
+        t[0] += bin_dd[2 * b];
+        t[1] += bin_dd[2 * b + 1];
+    }
+    block_reduce(t, red);
+    if (threadIdx.x == 0) {
+        totals[0] = t[0];
+        totals[1] = t[1];
+    }
+}
+
+// ---------------------------------------------------------------- per-sample pass
+// Block (sample group g, chunk c): thread t takes sample 256 g + t over the
+// bins [b0, b1) of chunk c.  The ratio at the chunk's first edge is formed
+// once; each bin then forms the ratio at its upper edge and adds its share,
+// so every edge inside the chunk is evaluated once.  The edge tables and the
+// summary coefficients are the same for every lane of a wave (the loop index
+// is uniform), so they come through the scalar cache.  Writes the chunk's
+// partial sum of <d, h> - <h, h>/2 for every sample.
+template <int NDET>
+__global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t n_rb, int n_chunks,
+                                                      const RbEdge *__restrict__ edges,
+                                                      const RbCoef *__restrict__ coef, const double *__restrict__ fid,
+                                                      const double *__restrict__ rec, double *__restrict__ partials)
+{
+    const int64_t group = blockIdx.x / n_chunks;
+    const int chunk = (int)(blockIdx.x % n_chunks);
+    const int64_t s = group * kBlock + threadIdx.x;
+    const int64_t sr = s < n_samples ? s : n_samples - 1;
+    const int64_t b0 = n_rb * chunk / n_chunks, b1 = n_rb * (chunk + 1) / n_chunks;
+
+    PhaseCoef c = load_coef(rec, n_samples, sr);
+    const PhaseCoef c0 = load_coef(fid, 1, 0);
+    c.c8 -= c0.c8;
+    c.c7 -= c0.c7;
+    c.c6 -= c0.c6;
+    c.c6l -= c0.c6l;
+    c.c5 -= c0.c5;
+    c.c5l -= c0.c5l;
+    c.c4 -= c0.c4;
+    c.c3 -= c0.c3;
+    c.c2 -= c0.c2;
+    c.c0 -= c0.c0;
+    double qr[NDET], qi[NDET], dl[NDET], rr[NDET], ri[NDET], acc[NDET];
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) {
+        const double pr = rec[(kRecDet + kRecFieldsPerDet * d) * n_samples + sr];
+        const double pi = rec[(kRecDet + kRecFieldsPerDet * d + 1) * n_samples + sr];
+        const double delta = rec[(kRecDet + kRecFieldsPerDet * d + 2) * n_samples + sr];
+        const double p0r = fid[kRecDet + kRecFieldsPerDet * d];
+        const double p0i = fid[kRecDet + kRecFieldsPerDet * d + 1];
+        const double inv = 1.0 / (p0r * p0r + p0i * p0i);
+        qr[d] = (pr * p0r + pi * p0i) * inv;     // P / P0
+        qi[d] = (pi * p0r - pr * p0i) * inv;
+        dl[d] = delta - fid[kRecDet + kRecFieldsPerDet * d + 2];
+        acc[d] = 0.0;
+    }
+    {
+        const RbEdge e = edges[b0];
+        const double dphi = turns_phase(c, e.t1);
+#pragma unroll
+        for (int d = 0; d < NDET; ++d) {
+            double er, ei;
+            gw_phasor_turns(__builtin_fma(e.f, dl[d], dphi), er, ei);
+            rr[d] = qr[d] * er - qi[d] * ei;
+            ri[d] = qr[d] * ei + qi[d] * er;
+        }
+    }
+    for (int64_t b = b0; b < b1; ++b) {
+        const RbEdge e = edges[b + 1];
+        const double dphi = turns_phase(c, e.t1);
+#pragma unroll
+        for (int d = 0; d < NDET; ++d) {
+            double er, ei;
+            gw_phasor_turns(__builtin_fma(e.f, dl[d], dphi), er, ei);
+            const double nr = qr[d] * er - qi[d] * ei;
+            const double ni = qr[d] * ei + qi[d] * er;
+            const double sr_ = rr[d] + nr, si = ri[d] + ni;
+            const double tr = nr - rr[d], ti = ni - ri[d];
+            const RbCoef k = coef[b * NDET + d];
+            double a = acc[d];
+            a = __builtin_fma(k.a0r, sr_, a);
+            a = __builtin_fma(k.a0i, si, a);
+            a = __builtin_fma(k.a1r, tr, a);
+            a = __builtin_fma(k.a1i, ti, a);
+            a = __builtin_fma(k.c0, __builtin_fma(sr_, sr_, si * si), a);
+            a = __builtin_fma(k.c1, __builtin_fma(sr_, tr, si * ti), a);
+            a = __builtin_fma(k.c2, __builtin_fma(tr, tr, ti * ti), a);
+            acc[d] = a;
+            rr[d] = nr;
+            ri[d] = ni;
+        }
+    }
+    double total = 0.0;
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) total += acc[d];
+    if (s < n_samples) partials[(int64_t)chunk * n_samples + s] = total;
+}
+
+// lnL[s] = sum over chunks of the partials - <d, d>/2 (- sum ln 2 pi S), with
+// the record's domain status applied.
+__global__ __launch_bounds__(kBlock) void finalize_kernel(int64_t n_samples, int n_chunks,
+                                                           const double *__restrict__ partials,
+                                                           const double *__restrict__ rec,
+                                                           const double *__restrict__ totals, int add_norm,
+                                                           double *__restrict__ lnl)
+{
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n_samples) return;
+    double sum = 0.0;
+    for (int c = 0; c < n_chunks; ++c) sum += partials[(int64_t)c * n_samples + s];
+    double v = sum - 0.5 * totals[0];
+    if (add_norm) v -= totals[1];
+    const int status = (int)rec[kRecStatus * n_samples + s];
+    if (status == 1) v = -INFINITY;
+    if (status == 2) v = NAN;
+    lnl[s] = v;
+}
+
+template <int NDET>
+void *lnl_kernel_ptr()
+{
+    return reinterpret_cast<void *>(&lnl_kernel<NDET>);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_edges(const gw_grid &grid, int64_t n_edges, const int64_t *edge_idx, RbEdge *edges,
+                        hipStream_t stream)
+{
+    hipLaunchKernelGGL(edges_kernel, dim3((unsigned)((n_edges + kBlock - 1) / kBlock)), dim3(kBlock), 0, stream,
+                       grid.f_low, grid.delta_f, n_edges, edge_idx, edges);
+    return hipGetLastError();
+}
+
+hipError_t launch_summary(const gw_grid &grid, int n_det, int64_t n_rb, const int64_t *edge_idx, const Tab1 *tab1,
+                          const Tab2 *tab2, const double *fid, const gw_c128 *data, const double *psd, double *raw,
+                          RbCoef *coef, double *bin_dd, double *totals, hipStream_t stream)
+{
+    hipLaunchKernelGGL(summary_kernel, dim3((unsigned)n_rb), dim3(kBlock), 0, stream, n_det, n_rb, grid.n_bins,
+                       grid.f_low, grid.delta_f, edge_idx, tab1, tab2, fid,
+                       reinterpret_cast<const double2 *>(data), psd, raw, coef, bin_dd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(kBlock), 0, stream, n_rb, bin_dd, totals);
+    return hipGetLastError();
+}
+
+int lnl_chunks(int64_t n_samples, int64_t n_rb, int n_cu)
+{
+    const int64_t groups = (n_samples + kBlock - 1) / kBlock;
+    // about four blocks per compute unit in one wave of blocks, chunks of at
+    // least 16 bins
+    const int64_t target = 4 * (int64_t)(n_cu > 0 ? n_cu : 256);
+    int64_t chunks = (target + groups - 1) / groups;
+    chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, n_rb / 16));
+    chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, 4096));
+    return (int)chunks;
+}
+
+hipError_t launch_lnl(int n_det, int64_t n_samples, int64_t n_rb, int n_chunks, const RbEdge *edges,
+                      const RbCoef *coef, const double *fid, const double *rec, double *partials,
+                      hipEvent_t t_start, hipEvent_t t_stop, hipStream_t stream)
+{
+    static void *const kernels[kMaxDet] = {lnl_kernel_ptr<1>(), lnl_kernel_ptr<2>(), lnl_kernel_ptr<3>(),
+                                           lnl_kernel_ptr<4>(), lnl_kernel_ptr<5>(), lnl_kernel_ptr<6>(),
+                                           lnl_kernel_ptr<7>(), lnl_kernel_ptr<8>()};
+    if (n_det < 1 || n_det > kMaxDet) return hipErrorInvalidValue;
+    const int64_t groups = (n_samples + kBlock - 1) / kBlock;
+    const int64_t blocks = groups * n_chunks;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    void *args[] = {&n_samples, &n_rb, &n_chunks, &edges, &coef, &fid, &rec, &partials};
+    hipError_t e;
+    if (t_start && (e = hipEventRecord(t_start, stream)) != hipSuccess) return e;
+    e = hipLaunchKernel(kernels[n_det - 1], dim3((unsigned)blocks), dim3(kBlock), args, 0, stream);
+    if (e != hipSuccess) return e;
+    if (t_stop && (e = hipEventRecord(t_stop, stream)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+hipError_t launch_finalize(int64_t n_samples, int n_chunks, const double *partials, const double *rec,
+                           const double *totals, bool add_norm, double *lnl_out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((n_samples + kBlock - 1) / kBlock)), dim3(kBlock), 0, stream,
+                       n_samples, n_chunks, partials, rec, totals, add_norm ? 1 : 0, lnl_out);
+    return hipGetLastError();
+}
+
+}  // namespace rb
+}  // namespace gw
