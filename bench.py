@@ -481,13 +481,13 @@ def bench_waveform(args):
 
 
 def rb_flops_per_pair(n_det: int) -> int:
-    """Algorithmic FP64 flops of the relative-binning kernel per (sample, bin)
-    (FMA = 2): the phase difference polynomial at the bin's upper edge 19
-    (9 FMA + 1 multiply), and per detector the delay term 2, the phasor 34,
-    the ratio (P/P0) e^{-i dPhi} 6, the edge sum and difference 4, and the
-    bin's quadratic form 23 (4 FMA for the A terms, three squared forms of 3
-    each, 3 FMA for the B terms)."""
-    return 19 + 69 * n_det
+    """Algorithmic FP64 flops of the relative-binning kernel per (sample, bin),
+    i.e. per edge (FMA = 2, multiply or add = 1): the phase-difference
+    polynomial 19 (9 FMA + 1 multiply); per detector the phasor 34, the ratio
+    (P/P0) e^{-i dPhi} 6, the linear term 4, the squared term 5 and the cross
+    term with the previous edge 5, plus 2 for the delay term on every
+    detector but the first."""
+    return 19 + 54 * n_det + 2 * (n_det - 1)
 
 
 def bench_relbin(args):

@@ -298,8 +298,8 @@ typedef struct gw_relbin gw_relbin;
  *            n_bins - 1 (for instance from gw_rb_edges).
  *   flags    0 or GW_FLAG_ADD_NORM (every lnL then carries -sum ln(2 pi S));
  *            any other bit is GW_EINVAL.
- *   rb       receives the handle, which owns about 72 (B + 1) + (120 n_det + 16) B
- *            bytes of device memory until gw_rb_destroy. */
+ *   rb       receives the handle, which owns about (72 + 96 n_det) (B + 1)
+ *            + (56 n_det + 16) B bytes of device memory until gw_rb_destroy. */
 int gw_rb_create(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_detector *dets, const gw_c128 *data,
                  const double *psd, const double *theta0, int n_param, const int64_t *edges, int64_t n_edges,
                  unsigned flags, gw_relbin **rb, hipStream_t stream);

@@ -56,6 +56,7 @@ struct gw_relbin {
     int64_t *edge_idx = nullptr;
     gw::rb::RbEdge *edges = nullptr;
     gw::rb::RbCoef *coef = nullptr;
+    gw::rb::RbEnds *ends = nullptr;
     double *raw = nullptr, *bin_dd = nullptr, *totals = nullptr, *fid = nullptr;
 };
 
@@ -933,7 +934,8 @@ int gw_rb_create(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_dete
     Carver c;
     const size_t h_idx = c.take(sizeof(int64_t) * n_edges);
     const size_t h_edges = c.take(sizeof(gw::rb::RbEdge) * n_edges);
-    const size_t h_coef = c.take(sizeof(gw::rb::RbCoef) * n_rb * n_det);
+    const size_t h_coef = c.take(sizeof(gw::rb::RbCoef) * n_edges * n_det);
+    const size_t h_ends = c.take(sizeof(gw::rb::RbEnds) * n_edges * n_det);
     const size_t h_raw = c.take(sizeof(double) * gw::rb::kRawPerDet * n_rb * n_det);
     const size_t h_dd = c.take(sizeof(double) * 2 * n_rb);
     const size_t h_tot = c.take(sizeof(double) * 2);
@@ -955,6 +957,7 @@ int gw_rb_create(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_dete
     h->edge_idx = reinterpret_cast<int64_t *>(base + h_idx);
     h->edges = reinterpret_cast<gw::rb::RbEdge *>(base + h_edges);
     h->coef = reinterpret_cast<gw::rb::RbCoef *>(base + h_coef);
+    h->ends = reinterpret_cast<gw::rb::RbEnds *>(base + h_ends);
     h->raw = reinterpret_cast<double *>(base + h_raw);
     h->bin_dd = reinterpret_cast<double *>(base + h_dd);
     h->totals = reinterpret_cast<double *>(base + h_tot);
@@ -975,8 +978,8 @@ int gw_rb_create(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_dete
         where = "fiducial record";
     else if ((e = gw::rb::launch_edges(*grid, n_edges, h->edge_idx, h->edges, stream)) != hipSuccess)
         where = "edge tables";
-    else if ((e = gw::rb::launch_summary(*grid, n_det, n_rb, h->edge_idx, tab1, tab2, h->fid, data, psd, h->raw,
-                                         h->coef, h->bin_dd, h->totals, stream)) != hipSuccess)
+    else if ((e = gw::rb::launch_summary(*grid, n_det, n_rb, h->edge_idx, tab1, tab2, h->fid, data, psd, h->edges,
+                                         h->raw, h->coef, h->ends, h->bin_dd, h->totals, stream)) != hipSuccess)
         where = "summary data";
     else if ((e = hipStreamSynchronize(stream)) != hipSuccess)
         where = "waiting for the preparation";
@@ -1046,7 +1049,7 @@ int gw_rb_lnl(gw_workspace *ws, const gw_relbin *rb, const double *theta, int64_
     if (!theta || !lnl_out) return fail(GW_EINVAL, "theta or lnl_out is NULL");
     DeviceGuard g(ws->device);
     if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
-    const int n_chunks = gw::rb::lnl_chunks(n_samples, rb->n_rb, ws->n_cu);
+    const int n_chunks = gw::rb::lnl_chunks(n_samples, rb->n_rb, rb->n_det, ws->n_cu);
     if ((n_samples + gw::kBlock - 1) / gw::kBlock * n_chunks > 0x7fffffffLL)
         return fail(GW_EINVAL, "too many samples for one launch");
     drop_ragged_graph(ws);               // the arena is about to be laid out for this pass
@@ -1063,8 +1066,8 @@ int gw_rb_lnl(gw_workspace *ws, const gw_relbin *rb, const double *theta, int64_
         return hip_fail(e, "sample prep");
     hipEvent_t t_start, t_stop;
     if (int rc = timer_pair(ws, &t_start, &t_stop)) return rc;
-    if ((e = gw::rb::launch_lnl(rb->n_det, n_samples, rb->n_rb, n_chunks, rb->edges, rb->coef, rb->fid, rec, part,
-                                t_start, t_stop, stream)) != hipSuccess)
+    if ((e = gw::rb::launch_lnl(rb->n_det, n_samples, rb->n_rb, n_chunks, rb->edges, rb->coef, rb->ends, rb->fid,
+                                rec, part, t_start, t_stop, stream)) != hipSuccess)
         return hip_fail(e, "relative-binning pass");
     if (t_stop) ++ws->timed;
     if ((e = gw::rb::launch_finalize(n_samples, n_chunks, part, rec, rb->totals, (rb->flags & GW_FLAG_ADD_NORM) != 0,

@@ -186,11 +186,12 @@ hipError_t launch(int64_t n_events, int64_t n_per, const double *samples, int64_
 }  // namespace pop
 
 // Relative binning (gw_relbin.hip).  Device layout of one prepared event:
-//   edges  [B + 1] RbEdge      the tables of every edge frequency;
-//   coef   [B][n_det] RbCoef   the scaled summary data the per-sample loop uses;
-//   raw    [B][n_det][7]       A0 re, A0 im, A1 re, A1 im, B0, B1, B2;
-//   bin_dd [B][2]              per bin: sum w |d|^2 and sum ln(2 pi S) over detectors;
-//   totals [2]                 <d, d> and sum ln(2 pi S) over the whole grid;
+//   edges  [B + 1] RbEdge           the tables of every edge frequency;
+//   coef   [B + 1][n_det] RbCoef    what the per-sample loop needs at each edge;
+//   ends   [B + 1][n_det] RbEnds    the one-sided coefficients of chunk ends;
+//   raw    [B][n_det][7]            A0 re, A0 im, A1 re, A1 im, B0, B1, B2;
+//   bin_dd [B][2]                   per bin: sum w |d|^2 and sum ln(2 pi S) over detectors;
+//   totals [2]                      <d, d> and sum ln(2 pi S) over the whole grid;
 //   fid    record of the fiducial sample (record_fields(n_det) doubles).
 namespace rb {
 struct RbEdge {
@@ -198,25 +199,37 @@ struct RbEdge {
     double f;
     double pad[3];
 };
-// For bin b with edges f_lo < f_hi, w = f_hi - f_lo and the ratio s = r_lo + r_hi,
-// t = r_hi - r_lo at its edges, the bin adds
-//   a0r s.re + a0i s.im + a1r t.re + a1i t.im + c0 |s|^2 + c1 Re(s conj t) + c2 |t|^2
-// to <d, h> - <h, h>/2: a0 = A0/2, a1 = A1/w, c0 = -B0/8, c1 = -B1/(2w), c2 = -B2/(2w^2).
+// Bin b, with edges f_lo < f_hi, w = f_hi - f_lo and the ratio r_lo, r_hi at
+// its edges, adds to <d, h> - <h, h>/2
+//   Re(Llo conj r_lo) + Re(Lhi conj r_hi) + alpha |r_lo|^2 + beta |r_hi|^2 + X Re(r_lo conj r_hi),
+//   Llo = A0/2 - A1/w, Lhi = A0/2 + A1/w,  alpha = -B0/8 - B2/(2w^2) + B1/(2w),
+//   beta = -B0/8 - B2/(2w^2) - B1/(2w),    X = -B0/4 + B2/w^2
+// (the linear model r = r0 + r1 (f - fm) written in the two edge values).
+// At an edge e inside a chunk the two bins that meet there are combined:
+// L = Lhi(e-1) + Llo(e), q = beta(e-1) + alpha(e); xb = X(e-1) is the cross
+// term of the bin that ends at e.
 struct RbCoef {
-    double a0r, a0i, a1r, a1i, c0, c1, c2, pad;
+    double lr, li, q, xb;
+};
+// The same per bin side: hi = the bin that ends at e (e - 1), lo = the bin that
+// starts there (e); used at the last and first edge of a chunk.
+struct RbEnds {
+    double hi_r, hi_i, hi_q, lo_r, lo_i, lo_q, pad0, pad1;
 };
 constexpr int kRawPerDet = 7;
 
 hipError_t launch_edges(const gw_grid &grid, int64_t n_edges, const int64_t *edge_idx, RbEdge *edges,
                         hipStream_t stream);
+// Summary data, per-bin totals and then the edge coefficients.
 hipError_t launch_summary(const gw_grid &grid, int n_det, int64_t n_rb, const int64_t *edge_idx, const Tab1 *tab1,
-                          const Tab2 *tab2, const double *fid, const gw_c128 *data, const double *psd, double *raw,
-                          RbCoef *coef, double *bin_dd, double *totals, hipStream_t stream);
+                          const Tab2 *tab2, const double *fid, const gw_c128 *data, const double *psd,
+                          const RbEdge *edges, double *raw, RbCoef *coef, RbEnds *ends, double *bin_dd,
+                          double *totals, hipStream_t stream);
 // Chunks of bins per sample group for n_samples samples over n_rb bins.
-int lnl_chunks(int64_t n_samples, int64_t n_rb, int n_cu);
+int lnl_chunks(int64_t n_samples, int64_t n_rb, int n_det, int n_cu);
 hipError_t launch_lnl(int n_det, int64_t n_samples, int64_t n_rb, int n_chunks, const RbEdge *edges,
-                      const RbCoef *coef, const double *fid, const double *rec, double *partials,
-                      hipEvent_t t_start, hipEvent_t t_stop, hipStream_t stream);
+                      const RbCoef *coef, const RbEnds *ends, const double *fid, const double *rec,
+                      double *partials, hipEvent_t t_start, hipEvent_t t_stop, hipStream_t stream);
 hipError_t launch_finalize(int64_t n_samples, int n_chunks, const double *partials, const double *rec,
                            const double *totals, bool add_norm, double *lnl_out, hipStream_t stream);
 }  // namespace rb

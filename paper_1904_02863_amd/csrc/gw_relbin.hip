@@ -14,8 +14,11 @@
 // turns near the fiducial, evaluated with the same absolute accuracy.
 // Within a bin r is taken as linear between its values at the two edges, and
 // the bin's share of <d, h> - <h, h>/2 is a quadratic form in those two
-// values whose coefficients (the summary data A0, A1, B0, B1, B2) are sums
-// over the fiducial template, formed once per event by summary_kernel.
+// values whose coefficients come from the summary data A0, A1, B0, B1, B2
+// (sums over the fiducial template, formed once per event by
+// summary_kernel).  Written per edge (coef_kernel), the two bins that meet at
+// an edge share one linear and one squared term, so a sample pays, per edge
+// and detector, one phasor and eight more floating-point operations.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,6 +27,12 @@
 #include "gw_device_math.h"
 #include "gw_internal.h"
 #include "gw_template.h"
+
+// Blocks per compute unit the per-sample pass is sized for; 0 asks the
+// runtime for the kernel's occupancy limit.
+#ifndef GW_RB_BLOCKS_PER_CU
+#define GW_RB_BLOCKS_PER_CU 0
+#endif
 
 namespace gw {
 namespace rb {
@@ -77,15 +86,13 @@ __global__ __launch_bounds__(kBlock) void summary_kernel(int n_det, int64_t n_rb
                                                           const double *__restrict__ fid,
                                                           const double2 *__restrict__ data,
                                                           const double *__restrict__ psd, double *__restrict__ raw,
-                                                          RbCoef *__restrict__ coef, double *__restrict__ bin_dd)
+                                                          double *__restrict__ bin_dd)
 {
     __shared__ double red[4 * kRawPerDet];
     const int64_t b = blockIdx.x;
     const int64_t lo = idx[b], up = idx[b + 1];
     const int64_t last = b == n_rb - 1 ? up : up - 1;
-    const double f_lo = bin_frequency(f_low, df, lo), f_hi = bin_frequency(f_low, df, up);
-    const double fm = 0.5 * (f_lo + f_hi);
-    const double width = f_hi - f_lo;
+    const double fm = 0.5 * (bin_frequency(f_low, df, lo) + bin_frequency(f_low, df, up));
     const PhaseCoef cf = load_coef(fid, 1, 0);
     const double wscale = 4.0 * df;
     double dd = 0.0, nrm = 0.0;
@@ -125,16 +132,6 @@ __global__ __launch_bounds__(kBlock) void summary_kernel(int n_det, int64_t n_rb
             double *r = raw + (b * n_det + d) * kRawPerDet;
 #pragma unroll
             for (int i = 0; i < kRawPerDet; ++i) r[i] = v[i];
-            RbCoef c;
-            c.a0r = 0.5 * v[0];
-            c.a0i = 0.5 * v[1];
-            c.a1r = v[2] / width;
-            c.a1i = v[3] / width;
-            c.c0 = -0.125 * v[4];
-            c.c1 = -0.5 * v[5] / width;
-            c.c2 = -0.5 * v[6] / (width * width);
-            c.pad = 0.0;
-            coef[b * n_det + d] = c;
         }
     }
     double t[2] = {dd, nrm};
@@ -143,6 +140,44 @@ __global__ __launch_bounds__(kBlock) void summary_kernel(int n_det, int64_t n_rb
         bin_dd[2 * b] = t[0];
         bin_dd[2 * b + 1] = t[1];
     }
+}
+
+// One thread per (edge e, detector): the coefficients of the ratio at e from
+// the summary data of the bins that end (e - 1) and start (e) there; see
+// RbCoef.  Edge 0 has no bin below it and edge B none above.
+__global__ __launch_bounds__(kBlock) void coef_kernel(int n_det, int64_t n_rb, const RbEdge *__restrict__ edges,
+                                                       const double *__restrict__ raw, RbCoef *__restrict__ coef,
+                                                       RbEnds *__restrict__ ends)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= (n_rb + 1) * n_det) return;
+    const int64_t e = i / n_det;
+    const int d = (int)(i % n_det);
+    RbEnds x;
+    x.hi_r = x.hi_i = x.hi_q = x.lo_r = x.lo_i = x.lo_q = x.pad0 = x.pad1 = 0.0;
+    double xb = 0.0;
+    if (e >= 1) {          // bin e - 1 ends at e
+        const double *v = raw + ((e - 1) * n_det + d) * kRawPerDet;
+        const double w = edges[e].f - edges[e - 1].f;
+        x.hi_r = __builtin_fma(0.5, v[0], v[2] / w);
+        x.hi_i = __builtin_fma(0.5, v[1], v[3] / w);
+        x.hi_q = -0.125 * v[4] - 0.5 * v[6] / (w * w) - 0.5 * v[5] / w;
+        xb = -0.25 * v[4] + v[6] / (w * w);
+    }
+    if (e < n_rb) {        // bin e starts at e
+        const double *v = raw + (e * n_det + d) * kRawPerDet;
+        const double w = edges[e + 1].f - edges[e].f;
+        x.lo_r = __builtin_fma(0.5, v[0], -v[2] / w);
+        x.lo_i = __builtin_fma(0.5, v[1], -v[3] / w);
+        x.lo_q = -0.125 * v[4] - 0.5 * v[6] / (w * w) + 0.5 * v[5] / w;
+    }
+    RbCoef c;
+    c.lr = x.hi_r + x.lo_r;
+    c.li = x.hi_i + x.lo_i;
+    c.q = x.hi_q + x.lo_q;
+    c.xb = xb;
+    coef[i] = c;
+    ends[i] = x;
 }
 
 // One block: totals[0] = <d, d>, totals[1] = sum ln(2 pi S) from the per-bin
@@ -165,17 +200,34 @@ __global__ __launch_bounds__(kBlock) void totals_kernel(int64_t n_rb, const doub
 
 // ---------------------------------------------------------------- per-sample pass
 // Block (sample group g, chunk c): thread t takes sample 256 g + t over the
-// bins [b0, b1) of chunk c.  The ratio at the chunk's first edge is formed
-// once; each bin then forms the ratio at its upper edge and adds its share,
-// so every edge inside the chunk is evaluated once.  The edge tables and the
-// summary coefficients are the same for every lane of a wave (the loop index
-// is uniform), so they come through the scalar cache.  Writes the chunk's
-// partial sum of <d, h> - <h, h>/2 for every sample.
+// bins [b0, b1) of chunk c, i.e. the edges b0 .. b1.  The ratio is formed
+// once per edge; each edge adds its linear and squared terms (one-sided at
+// the chunk's two end edges, whose other bin belongs to the next chunk) and
+// the cross term of the bin below it.  The edge tables and coefficients are
+// the same for every lane of a wave (the loop index is uniform), so they come
+// through the scalar cache.  Writes the chunk's partial sum of
+// <d, h> - <h, h>/2 for every sample.
+template <int NDET>
+__device__ __forceinline__ void edge_ratio(const PhaseCoef &c, const RbEdge &e, const double (&qr)[NDET],
+                                           const double (&qi)[NDET], const double (&dl)[NDET], double (&rr)[NDET],
+                                           double (&ri)[NDET])
+{
+    const double dphi = turns_phase(c, e.t1);
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) {
+        double er, ei;
+        gw_phasor_turns(d == 0 ? dphi : __builtin_fma(e.f, dl[d], dphi), er, ei);
+        rr[d] = qr[d] * er - qi[d] * ei;
+        ri[d] = qr[d] * ei + qi[d] * er;
+    }
+}
+
 template <int NDET>
 __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t n_rb, int n_chunks,
                                                       const RbEdge *__restrict__ edges,
-                                                      const RbCoef *__restrict__ coef, const double *__restrict__ fid,
-                                                      const double *__restrict__ rec, double *__restrict__ partials)
+                                                      const RbCoef *__restrict__ coef, const RbEnds *__restrict__ ends,
+                                                      const double *__restrict__ fid, const double *__restrict__ rec,
+                                                      double *__restrict__ partials)
 {
     const int64_t group = blockIdx.x / n_chunks;
     const int chunk = (int)(blockIdx.x % n_chunks);
@@ -195,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
     c.c3 -= c0.c3;
     c.c2 -= c0.c2;
     c.c0 -= c0.c0;
-    double qr[NDET], qi[NDET], dl[NDET], rr[NDET], ri[NDET], acc[NDET];
+    double qr[NDET], qi[NDET], dl[NDET], rr[NDET], ri[NDET], nr[NDET], ni[NDET], acc[NDET];
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
         const double pr = rec[(kRecDet + kRecFieldsPerDet * d) * n_samples + sr];
@@ -206,48 +258,48 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
         const double inv = 1.0 / (p0r * p0r + p0i * p0i);
         qr[d] = (pr * p0r + pi * p0i) * inv;     // P / P0
         qi[d] = (pi * p0r - pr * p0i) * inv;
-        dl[d] = delta - fid[kRecDet + kRecFieldsPerDet * d + 2];
-        acc[d] = 0.0;
+        dl[d] = delta - fid[kRecDet + kRecFieldsPerDet * d + 2];   // zero for detector 0
     }
-    {
-        const RbEdge e = edges[b0];
-        const double dphi = turns_phase(c, e.t1);
+    // first edge: the lower side of bin b0 only
+    edge_ratio<NDET>(c, edges[b0], qr, qi, dl, rr, ri);
+#pragma unroll
+    for (int d = 0; d < NDET; ++d) {
+        const RbEnds k = ends[b0 * NDET + d];
+        double a = k.lo_r * rr[d];
+        a = __builtin_fma(k.lo_i, ri[d], a);
+        acc[d] = __builtin_fma(k.lo_q, __builtin_fma(rr[d], rr[d], ri[d] * ri[d]), a);
+    }
+    // edges inside the chunk: both bins that meet there
+#pragma unroll 2
+    for (int64_t e = b0 + 1; e < b1; ++e) {
+        edge_ratio<NDET>(c, edges[e], qr, qi, dl, nr, ni);
 #pragma unroll
         for (int d = 0; d < NDET; ++d) {
-            double er, ei;
-            gw_phasor_turns(__builtin_fma(e.f, dl[d], dphi), er, ei);
-            rr[d] = qr[d] * er - qi[d] * ei;
-            ri[d] = qr[d] * ei + qi[d] * er;
-        }
-    }
-    for (int64_t b = b0; b < b1; ++b) {
-        const RbEdge e = edges[b + 1];
-        const double dphi = turns_phase(c, e.t1);
-#pragma unroll
-        for (int d = 0; d < NDET; ++d) {
-            double er, ei;
-            gw_phasor_turns(__builtin_fma(e.f, dl[d], dphi), er, ei);
-            const double nr = qr[d] * er - qi[d] * ei;
-            const double ni = qr[d] * ei + qi[d] * er;
-            const double sr_ = rr[d] + nr, si = ri[d] + ni;
-            const double tr = nr - rr[d], ti = ni - ri[d];
-            const RbCoef k = coef[b * NDET + d];
+            const RbCoef k = coef[e * NDET + d];
             double a = acc[d];
-            a = __builtin_fma(k.a0r, sr_, a);
-            a = __builtin_fma(k.a0i, si, a);
-            a = __builtin_fma(k.a1r, tr, a);
-            a = __builtin_fma(k.a1i, ti, a);
-            a = __builtin_fma(k.c0, __builtin_fma(sr_, sr_, si * si), a);
-            a = __builtin_fma(k.c1, __builtin_fma(sr_, tr, si * ti), a);
-            a = __builtin_fma(k.c2, __builtin_fma(tr, tr, ti * ti), a);
+            a = __builtin_fma(k.xb, __builtin_fma(rr[d], nr[d], ri[d] * ni[d]), a);
+            a = __builtin_fma(k.lr, nr[d], a);
+            a = __builtin_fma(k.li, ni[d], a);
+            a = __builtin_fma(k.q, __builtin_fma(nr[d], nr[d], ni[d] * ni[d]), a);
             acc[d] = a;
-            rr[d] = nr;
-            ri[d] = ni;
+            rr[d] = nr[d];
+            ri[d] = ni[d];
         }
     }
+    // last edge: the upper side of bin b1 - 1 only
+    edge_ratio<NDET>(c, edges[b1], qr, qi, dl, nr, ni);
     double total = 0.0;
 #pragma unroll
-    for (int d = 0; d < NDET; ++d) total += acc[d];
+    for (int d = 0; d < NDET; ++d) {
+        const RbEnds k = ends[b1 * NDET + d];
+        const double xb = coef[b1 * NDET + d].xb;
+        double a = acc[d];
+        a = __builtin_fma(xb, __builtin_fma(rr[d], nr[d], ri[d] * ni[d]), a);
+        a = __builtin_fma(k.hi_r, nr[d], a);
+        a = __builtin_fma(k.hi_i, ni[d], a);
+        a = __builtin_fma(k.hi_q, __builtin_fma(nr[d], nr[d], ni[d] * ni[d]), a);
+        total += a;
+    }
     if (s < n_samples) partials[(int64_t)chunk * n_samples + s] = total;
 }
 
@@ -289,24 +341,48 @@ hipError_t launch_edges(const gw_grid &grid, int64_t n_edges, const int64_t *edg
 }
 
 hipError_t launch_summary(const gw_grid &grid, int n_det, int64_t n_rb, const int64_t *edge_idx, const Tab1 *tab1,
-                          const Tab2 *tab2, const double *fid, const gw_c128 *data, const double *psd, double *raw,
-                          RbCoef *coef, double *bin_dd, double *totals, hipStream_t stream)
+                          const Tab2 *tab2, const double *fid, const gw_c128 *data, const double *psd,
+                          const RbEdge *edges, double *raw, RbCoef *coef, RbEnds *ends, double *bin_dd,
+                          double *totals, hipStream_t stream)
 {
     hipLaunchKernelGGL(summary_kernel, dim3((unsigned)n_rb), dim3(kBlock), 0, stream, n_det, n_rb, grid.n_bins,
                        grid.f_low, grid.delta_f, edge_idx, tab1, tab2, fid,
-                       reinterpret_cast<const double2 *>(data), psd, raw, coef, bin_dd);
+                       reinterpret_cast<const double2 *>(data), psd, raw, bin_dd);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(kBlock), 0, stream, n_rb, bin_dd, totals);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t n = (n_rb + 1) * n_det;
+    hipLaunchKernelGGL(coef_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, stream, n_det, n_rb,
+                       edges, raw, coef, ends);
     return hipGetLastError();
 }
 
-int lnl_chunks(int64_t n_samples, int64_t n_rb, int n_cu)
+int lnl_blocks_per_cu(int n_det)
+{
+    static int cache[kMaxDet] = {};
+    if (GW_RB_BLOCKS_PER_CU > 0) return GW_RB_BLOCKS_PER_CU;
+    if (n_det < 1 || n_det > kMaxDet) return 1;
+    if (cache[n_det - 1] == 0) {
+        static void *const kernels[kMaxDet] = {lnl_kernel_ptr<1>(), lnl_kernel_ptr<2>(), lnl_kernel_ptr<3>(),
+                                               lnl_kernel_ptr<4>(), lnl_kernel_ptr<5>(), lnl_kernel_ptr<6>(),
+                                               lnl_kernel_ptr<7>(), lnl_kernel_ptr<8>()};
+        int blocks = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernels[n_det - 1], kBlock, 0) != hipSuccess ||
+            blocks < 1)
+            blocks = 4;
+        cache[n_det - 1] = blocks;
+    }
+    return cache[n_det - 1];
+}
+
+int lnl_chunks(int64_t n_samples, int64_t n_rb, int n_det, int n_cu)
 {
     const int64_t groups = (n_samples + kBlock - 1) / kBlock;
-    // about four blocks per compute unit in one wave of blocks, chunks of at
-    // least 16 bins
-    const int64_t target = 4 * (int64_t)(n_cu > 0 ? n_cu : 256);
+    // enough blocks to fill every compute unit to its occupancy limit in one
+    // wave of blocks (more resident waves hide the latency of the long
+    // dependent chains of the phasor polynomials), chunks of at least 16 bins
+    const int64_t target = (int64_t)lnl_blocks_per_cu(n_det) * (n_cu > 0 ? n_cu : 256);
     int64_t chunks = (target + groups - 1) / groups;
     chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, n_rb / 16));
     chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, 4096));
@@ -314,8 +390,8 @@ int lnl_chunks(int64_t n_samples, int64_t n_rb, int n_cu)
 }
 
 hipError_t launch_lnl(int n_det, int64_t n_samples, int64_t n_rb, int n_chunks, const RbEdge *edges,
-                      const RbCoef *coef, const double *fid, const double *rec, double *partials,
-                      hipEvent_t t_start, hipEvent_t t_stop, hipStream_t stream)
+                      const RbCoef *coef, const RbEnds *ends, const double *fid, const double *rec,
+                      double *partials, hipEvent_t t_start, hipEvent_t t_stop, hipStream_t stream)
 {
     static void *const kernels[kMaxDet] = {lnl_kernel_ptr<1>(), lnl_kernel_ptr<2>(), lnl_kernel_ptr<3>(),
                                            lnl_kernel_ptr<4>(), lnl_kernel_ptr<5>(), lnl_kernel_ptr<6>(),
@@ -324,7 +400,7 @@ hipError_t launch_lnl(int n_det, int64_t n_samples, int64_t n_rb, int n_chunks, 
     const int64_t groups = (n_samples + kBlock - 1) / kBlock;
     const int64_t blocks = groups * n_chunks;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    void *args[] = {&n_samples, &n_rb, &n_chunks, &edges, &coef, &fid, &rec, &partials};
+    void *args[] = {&n_samples, &n_rb, &n_chunks, &edges, &coef, &ends, &fid, &rec, &partials};
     hipError_t e;
     if (t_start && (e = hipEventRecord(t_start, stream)) != hipSuccess) return e;
     e = hipLaunchKernel(kernels[n_det - 1], dim3((unsigned)blocks), dim3(kBlock), args, 0, stream);
