@@ -45,6 +45,7 @@ def _load():
         d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int
         p = ctypes.c_void_p
         lib.oracle_pn_coefficients.argtypes = [d, p, p]
+        lib.oracle_pn_spin_terms.argtypes = [d, d, d, d, p, p]
         lib.oracle_pn_phase.argtypes = [d, d, d]
         lib.oracle_pn_phase.restype = d
         lib.oracle_antenna.argtypes = [p, d, d, d, p, p]
@@ -70,6 +71,14 @@ def pn_coefficients(eta: float) -> tuple[np.ndarray, np.ndarray]:
     """TaylorF2 coefficients (phi_k, phi_k^l), k = 0..7, at symmetric mass ratio eta."""
     phi, phil = np.zeros(8), np.zeros(8)
     _load().oracle_pn_coefficients(float(eta), _ptr(phi), _ptr(phil))
+    return phi, phil
+
+
+def pn_spin_terms(eta: float, delta: float, chi1: float, chi2: float) -> tuple[np.ndarray, np.ndarray]:
+    """Aligned-spin additions to (phi_k, phi_k^l), k = 0..7, for symmetric mass
+    ratio eta, delta = (m1 - m2)/M and spins chi1 (heavier body), chi2."""
+    phi, phil = np.zeros(8), np.zeros(8)
+    _load().oracle_pn_spin_terms(float(eta), float(delta), float(chi1), float(chi2), _ptr(phi), _ptr(phil))
     return phi, phil
 
 

@@ -33,6 +33,10 @@
  *    Schwarzschild innermost stable circular orbit of the total mass M,
  *    f_isco = c^3 / (6^(3/2) pi G M), the usual end of an inspiral template;
  *  - 5-parameter rows are an optimally oriented source: h = A e^{-i Psi};
+ *  - 7- and 11-parameter rows are the 5- and 9-parameter rows followed by
+ *    the aligned spins chi1 (of the heavier body) and chi2, which add the
+ *    spin terms of oracle_pn_spin_terms to the phase (the amplitude stays
+ *    Newtonian); |chi| > 1 gives -infinity;
  *  - any non-finite parameter gives NaN; Mc <= 0, q outside (0, 1] or
  *    d_L <= 0 give -infinity.
  * Sums use Neumaier compensation per (sample, detector), then across
@@ -74,6 +78,35 @@ int oracle_pn_coefficients(double eta, double phi[8], double phi_log[8])
     phi_log[6] = -6848.0 / 21.0;
     phi[7] = pi * (77096675.0 / 254016.0 + 378515.0 / 1512.0 * eta - 74045.0 / 756.0 * e2);
     return 0;
+}
+
+/* Aligned-spin additions to phi_k (and to phi_5^l) for dimensionless spins
+ * chi1 (heavier body, m1) and chi2 (lighter, m2) along the orbital angular
+ * momentum, written with chi_s = (chi1 + chi2)/2, chi_a = (chi1 - chi2)/2 and
+ * delta = (m1 - m2)/M:
+ *   1.5PN spin-orbit (Kidder 1995; Arun, Buonanno, Faye & Ochsner 2009),
+ *   2PN spin-spin with the black-hole quadrupole-monopole term, kappa = 1
+ *     (Kidder 1995; Poisson 1998),
+ *   2.5PN spin-orbit, entering as phi_5 (1 + 3 ln v) like the non-spinning
+ *     2.5PN term (Blanchet, Buonanno & Faye 2006),
+ *   3PN spin-orbit including its tail (Blanchet 2014, Living Rev. Relativ. 17, 2),
+ *   3.5PN spin-orbit (Bohe, Marsat, Faye & Blanchet 2013).
+ * Spin-spin terms beyond 2PN and cubic-in-spin terms are not included. */
+void oracle_pn_spin_terms(double eta, double delta, double chi1, double chi2, double phi[8], double phi_log[8])
+{
+    const double pi = ORACLE_PI, e2 = eta * eta, e3 = eta * eta * eta;
+    const double cs = 0.5 * (chi1 + chi2), ca = 0.5 * (chi1 - chi2);
+    phi[3] += 113.0 / 3.0 * delta * ca + (113.0 / 3.0 - 76.0 / 3.0 * eta) * cs;
+    phi[4] += -(405.0 / 8.0 - 200.0 * eta) * ca * ca - 405.0 / 4.0 * delta * cs * ca
+              - (405.0 / 8.0 - 5.0 / 2.0 * eta) * cs * cs;
+    const double gamma = (732985.0 / 2268.0 - 24260.0 / 81.0 * eta - 340.0 / 9.0 * e2) * cs
+                       + (732985.0 / 2268.0 + 140.0 / 9.0 * eta) * delta * ca;
+    phi[5] -= gamma;
+    phi_log[5] -= 3.0 * gamma;
+    phi[6] += pi * (2270.0 / 3.0 * delta * ca + (2270.0 / 3.0 - 520.0 * eta) * cs);
+    phi[7] += (-25150083775.0 / 3048192.0 + 10566655595.0 / 762048.0 * eta - 1042165.0 / 3024.0 * e2
+               + 5345.0 / 36.0 * e3) * cs
+            + delta * (-25150083775.0 / 3048192.0 + 26804935.0 / 6048.0 * eta - 1985.0 / 48.0 * e2) * ca;
 }
 
 /* The post-Newtonian part of the TaylorF2 phase at v = (pi M f)^(1/3):
@@ -147,6 +180,11 @@ double oracle_delay(const double vertex[3], double ra, double dec)
     return -(n[0] * vertex[0] + n[1] * vertex[1] + n[2] * vertex[2]) / ORACLE_C_SI;
 }
 
+/* Rows with aligned spins carry chi1, chi2 as their last two columns. */
+static int has_spins(int n_param) { return n_param == 7 || n_param == 11; }
+/* Rows with a sky position, polarisation and inclination (columns 5-8). */
+static int has_sky(int n_param) { return n_param == 9 || n_param == 11; }
+
 /* Classification of one parameter row: 1 = evaluate, 0 = out of domain
  * (-infinity), -1 = non-finite (NaN). */
 static int classify(const double *th, int n_param)
@@ -154,6 +192,7 @@ static int classify(const double *th, int n_param)
     for (int i = 0; i < n_param; ++i)
         if (!isfinite(th[i])) return -1;
     if (!(th[0] > 0.0) || !(th[1] > 0.0 && th[1] <= 1.0) || !(th[2] > 0.0)) return 0;
+    if (has_spins(n_param) && (fabs(th[n_param - 2]) > 1.0 || fabs(th[n_param - 1]) > 1.0)) return 0;
     return 1;
 }
 
@@ -185,11 +224,16 @@ static void make_source(const double *th, int n_param, int n_det, int isco,
     src->amp0 = sqrt(5.0 / 24.0) * pow(ORACLE_PI, -2.0 / 3.0) * pow(mc_s, 5.0 / 6.0) / dist_s;
     src->phic = th[3];
     src->tc = th[4];
-    src->cos_iota = n_param == 9 ? cos(th[8]) : 1.0;
+    src->cos_iota = has_sky(n_param) ? cos(th[8]) : 1.0;
     oracle_pn_coefficients(src->eta, src->phi, src->phi_log);
+    if (has_spins(n_param)) {
+        const double q = th[1];
+        const double delta = (1.0 - q) / (1.0 + q);
+        oracle_pn_spin_terms(src->eta, delta, th[n_param - 2], th[n_param - 1], src->phi, src->phi_log);
+    }
     src->n_det = n_det;
     for (int d = 0; d < n_det; ++d) {
-        if (n_param == 9) {
+        if (has_sky(n_param)) {
             oracle_antenna(tensors + 9 * d, th[5], th[6], th[7], &src->fplus[d], &src->fcross[d]);
             src->dt[d] = oracle_delay(vertices + 3 * d, th[5], th[6]);
         } else {   /* optimally oriented, overhead source */
@@ -219,7 +263,7 @@ static double complex response(const source *src, int d, double f, double comple
 static int check_args(double delta_f, int64_t n_bins, int n_det, int n_param, int64_t n_samples)
 {
     if (!(delta_f > 0.0) || n_bins < 0 || n_det < 0 || n_det > 8 || n_samples < 0) return -1;
-    if (n_param != 5 && n_param != 9) return -1;
+    if (n_param != 5 && n_param != 7 && n_param != 9 && n_param != 11) return -1;
     return 0;
 }
 

@@ -100,3 +100,121 @@ def numeric_r(eta_value: float):
     rk, rl = r_series()
     return ([float(sp.N(sp.sympify(x).subs(eta, eta_value), 30)) for x in rk],
             [float(sp.N(sp.sympify(x).subs(eta, eta_value), 30)) for x in rl])
+
+
+# ---------------------------------------------------------------- aligned spins
+# Spin terms of the energy and flux for spins along the orbital angular
+# momentum, with S_l = m1^2 chi1 + m2^2 chi2 and Sigma_l = M (m2 chi2 - m1 chi1)
+# in units of M^2 (s and sig below), delta = (m1 - m2)/M and x1 = m1/M:
+#  * spin-orbit energy at v^3, v^5, v^7 and flux at v^3, v^5, v^6 (tail),
+#    v^7: Blanchet, Living Rev. Relativ. 17, 2 (2014), Eqs. (414)-(415);
+#  * spin-spin (S1 S2) energy and flux at v^4: Kidder, PRD 52, 821 (1995),
+#    for aligned spins S1.S2 - 3 (L.S1)(L.S2) = -2 S1 S2 and
+#    -103 S1.S2 + 289 (L.S1)(L.S2) = 186 S1 S2.
+x1, chi1, chi2 = sp.symbols("x1 chi1 chi2")
+
+
+def _spin_energy_flux():
+    x2 = 1 - x1
+    eta_x = x1 * x2
+    dl = x1 - x2
+    s = x1 ** 2 * chi1 + x2 ** 2 * chi2
+    sig = x2 * chi2 - x1 * chi1
+    e = {k: sp.sympify(c).subs(eta, eta_x) for k, c in _energy_coefficients().items()}
+    f = {k: sp.sympify(c).subs(eta, eta_x) for k, c in _flux_coefficients().items()}
+    e[3] = _R(14, 3) * s + 2 * dl * sig
+    e[5] = (11 - _R(61, 9) * eta_x) * s + dl * (3 - _R(10, 3) * eta_x) * sig
+    e[7] = ((_R(135, 4) - _R(367, 4) * eta_x + _R(29, 12) * eta_x ** 2) * s
+            + dl * (_R(27, 4) - 39 * eta_x + _R(5, 4) * eta_x ** 2) * sig)
+    e[4] = e[4] - 2 * eta_x * chi1 * chi2
+    f[3] = f[3] - (4 * s + _R(5, 4) * dl * sig)
+    f[5] = f[5] + (-_R(9, 2) + _R(272, 9) * eta_x) * s + (-_R(13, 16) + _R(43, 4) * eta_x) * dl * sig
+    f[6] = f[6] - 16 * _pi * s - _R(31, 6) * _pi * dl * sig
+    f[7] = f[7] + ((_R(476645, 6804) + _R(6172, 189) * eta_x - _R(2810, 27) * eta_x ** 2) * s
+                   + (_R(9535, 336) + _R(1849, 126) * eta_x - _R(1501, 36) * eta_x ** 2) * dl * sig)
+    f[4] = f[4] + _R(31, 8) * eta_x * chi1 * chi2
+    return e, f
+
+
+def _phase_from(e, fl, order=ORDER):
+    num = [0] * order
+    for k, c in e.items():
+        if k < order:
+            num[k] = c * (1 + _R(k, 2))
+    fc = [fl.get(k, 0) for k in range(order)]
+    inv = [0] * order
+    inv[0] = 1
+    for k in range(1, order):
+        inv[k] = sp.expand(-sum(fc[j] * inv[k - j] for j in range(1, k + 1)))
+    r = [sp.expand(sum(num[j] * inv[k - j] for j in range(k + 1))) for k in range(order)]
+    rk, rl = [x.coeff(ell, 0) for x in r], [x.coeff(ell, 1) for x in r]
+    p, q = {}, {}
+    for k in range(order):
+        n = k - 5
+        if k == 5:
+            q[5] = -40 * rk[5] / 3
+            continue
+        q[k] = 40 * rl[k] / (n * (n - 3))
+        p[k] = (40 * rk[k] - q[k] * (2 * n - 3)) / (n * (n - 3))
+    return p, q
+
+
+@functools.lru_cache(maxsize=None)
+def spin_phase_coefficients():
+    """(p, q) with aligned spins: sympy expressions in x1, chi1, chi2."""
+    e, f = _spin_energy_flux()
+    return _phase_from(e, f)
+
+
+def spin_linear_term(k: int, x1_value, which: int = 1) -> float:
+    """Coefficient of chi_which (the other spin zero) in p_k (k != 5) or in
+    q_5 / 3 (the 2.5PN term, which appears as phi_5 (1 + 3 ln v))."""
+    p, q = spin_phase_coefficients()
+    expr = q[5] / 3 if k == 5 else p[k]
+    ex = sp.expand(expr)
+    own, other = (chi1, chi2) if which == 1 else (chi2, chi1)
+    lin = ex.coeff(own, 1).subs(other, 0)
+    return float(sp.N(lin.subs(x1, x1_value), 30))
+
+
+def spin_spin_term(x1_value) -> float:
+    """Coefficient of chi1 chi2 in p_4."""
+    p, _ = spin_phase_coefficients()
+    return float(sp.N(sp.expand(p[4]).coeff(chi1, 1).coeff(chi2, 1).subs(x1, x1_value), 30))
+
+
+# Test-mass limit (m2 -> 0) around a Kerr black hole of spin a: the binding
+# energy of circular equatorial orbits, E/mu = (1 - 2u + a u^(3/2)) /
+# sqrt(1 - 3u + 2a u^(3/2)) - 1 with u = M/r and M omega = u^(3/2) / (1 + a
+# u^(3/2)) (Bardeen, Press & Teukolsky 1972), expanded here exactly, and the
+# flux of black-hole perturbation theory through v^6 (Tagoshi, Shibata, Tanaka
+# & Sasaki 1996): the spin enters as -11/4 a v^3, +33/16 a^2 v^4,
+# -59/16 a v^5 and -65/6 pi a v^6.
+kerr_a = sp.symbols("kerr_a")
+
+
+@functools.lru_cache(maxsize=None)
+def kerr_energy_series(order: int = 8):
+    """eps(v) = E / (-mu v^2 / 2) for the test mass, coefficients v^0..v^(order-1)."""
+    w, y = sp.symbols("w y", positive=True)
+    e_w = (1 - 2 * w ** 2 + kerr_a * w ** 3) / sp.sqrt(1 - 3 * w ** 2 + 2 * kerr_a * w ** 3) - 1
+    w_y = y
+    for _ in range(order + 2):       # w = y (1 + a w^3)^(1/3), iterated to the series order
+        w_y = sp.series(y * (1 + kerr_a * w_y ** 3) ** _R(1, 3), y, 0, order + 2).removeO()
+    e_y = sp.series(e_w.subs(w, w_y), y, 0, order + 2).removeO()
+    eps = sp.expand(sp.simplify(e_y / (-y ** 2 / 2)))
+    return {k: sp.expand(eps.coeff(y, k)) for k in range(order)}
+
+
+def kerr_flux_spin_terms():
+    return {3: -_R(11, 4) * kerr_a, 4: _R(33, 16) * kerr_a ** 2, 5: -_R(59, 16) * kerr_a,
+            6: -_R(65, 6) * _pi * kerr_a}
+
+
+def test_mass_self_spin_term() -> float:
+    """Coefficient of a^2 in p_4 for the test mass around Kerr."""
+    e = kerr_energy_series(5)
+    f = {0: 1, 2: -_R(1247, 336), 3: 4 * _pi + kerr_flux_spin_terms()[3],
+         4: -_R(44711, 9072) + kerr_flux_spin_terms()[4]}
+    p, _ = _phase_from({k: e[k] for k in range(5)}, f, order=5)
+    return float(sp.N(sp.expand(p[4]).coeff(kerr_a, 2), 30))
