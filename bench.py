@@ -36,9 +36,11 @@ HBM_PEAK_GBS = 8000.0
 # Sources whose content fixes the tile kernel's machine code; a profile
 # summary records their SHA-256 next to the traffic it measured.
 KERNEL_SOURCES = ("paper_1904_02863_amd/csrc/gw_kernels.hip", "paper_1904_02863_amd/csrc/gw_device_math.h",
-                  "paper_1904_02863_amd/csrc/gw_internal.h", "paper_1904_02863_amd/build.py")
+                  "paper_1904_02863_amd/csrc/gw_internal.h", "paper_1904_02863_amd/csrc/gw_template.h",
+                  "paper_1904_02863_amd/csrc/gw_relbin.hip", "paper_1904_02863_amd/build.py")
 PROFILE_SUMMARY = "profiles/lnl_tile_kernel_bbh-3det-128s.md"
 WAVEFORM_PROFILE = "profiles/waveform_kernel_bbh-3det-128s.md"
+RELBIN_PROFILE = "profiles/relbin_lnl_kernel_bns-15hz-512s.md"
 
 
 def flops_per_pair(n_det: int, mixed: bool = False, direct: bool = False) -> int:
@@ -92,7 +94,9 @@ def calibration_copy(mib: int, device):
     del src, dst
 
 
-def build_inputs(name: str, n_samples: int | None):
+def build_inputs(name: str, n_samples: int | None, spins: bool = False):
+    import dataclasses
+
     import numpy as np
     import torch
 
@@ -107,11 +111,15 @@ def build_inputs(name: str, n_samples: int | None):
         w = synth.long_bns(15.0, 512.0, 3, n_samples or 4096)
     else:
         raise SystemExit(f"unknown workload {name}")
+    if spins:       # aligned spins chi1, chi2 ~ U[-1, 1] appended to every row and the injection
+        rng = np.random.default_rng(11)
+        w = dataclasses.replace(w, theta_inj=synth.add_spins(w.theta_inj, rng)[0],
+                                theta=synth.add_spins(w.theta, rng), n_param=w.n_param + 2)
     dev = torch.device("cuda", 0)
     theta = torch.from_numpy(np.ascontiguousarray(w.theta)).to(dev)
     inj = torch.from_numpy(np.ascontiguousarray(w.theta_inj[None, :])).to(dev)
     # the injection is made with the library's own waveform generator
-    h = gw.waveform_batch(w.grid, w.tensors if w.n_param == 9 else w.tensors, w.vertices, inj)[0]
+    h = gw.waveform_batch(w.grid, w.tensors, w.vertices, inj)[0]
     data = (torch.from_numpy(w.noise).to(dev) + h).contiguous()
     psd = torch.from_numpy(w.psd).to(dev)
     torch.cuda.synchronize()
@@ -379,19 +387,24 @@ def bench_population(args):
     out = torch.empty(k, dtype=torch.float64, device=dev)
 
     def timed(n_hyper, steps, warmup):
+        """(wall seconds per call, mean seconds of the weights kernel from HIP events)"""
         h = h_t[:n_hyper].contiguous()
         o = out[:n_hyper]
         for _ in range(warmup):
             gw.pop_lnl(s_t, h, out=o, workspace=ws)
         torch.cuda.synchronize()
+        ws.set_timing(True)
         t0 = time.perf_counter()
         for _ in range(steps):
             gw.pop_lnl(s_t, h, out=o, workspace=ws)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps
+        wall = (time.perf_counter() - t0) / steps
+        kernel_ms, launches = ws.kernel_time()
+        ws.set_timing(False)
+        return wall, kernel_ms / launches / 1e3
 
-    t1 = timed(1, max(args.steps, 50), args.warmup)
-    tk = timed(k, args.steps, args.warmup)
+    t1, k1 = timed(1, max(args.steps, 50), args.warmup)
+    tk, kk = timed(k, args.steps, args.warmup)
     if not torch.isfinite(out).all():
         raise SystemExit("non-finite population lnL")
     n = n_events * n_per
@@ -402,10 +415,13 @@ def bench_population(args):
         "ms_per_step": tk * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "population", "n_events": n_events, "n_per_event": n_per, "hyper_per_call": k},
+        "weights_kernel_ms": kk * 1e3,
         "one_point_per_call": {"value": 1.0 / t1, "ms_per_call": t1 * 1e3,
-                               "roofline": {"bound": "hbm", "achieved": bytes_per_call / t1 / 1e9,
+                               "roofline": {"bound": "hbm", "achieved": bytes_per_call / k1 / 1e9,
                                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                            "frac": bytes_per_call / t1 / 1e9 / HBM_PEAK_GBS}},
+                                            "frac": bytes_per_call / k1 / 1e9 / HBM_PEAK_GBS,
+                                            "kernel": "weights_kernel", "kernel_ms": k1 * 1e3,
+                                            "algorithmic_bytes": bytes_per_call}},
     }
     if not args.no_cpu_baseline:
         from oracle import population as pop
@@ -531,6 +547,8 @@ def bench_relbin(args):
     kernel_ms, launches = ws.kernel_time()
     ws.set_timing(False)
     kernel_s = kernel_ms / launches / 1e3
+    if args.calibrate_copy > 0:
+        calibration_copy(args.calibrate_copy, dev)
     if not torch.isfinite(out).all():
         raise SystemExit("non-finite relative-binning lnL")
     # the full likelihood of the same event, for its rate and the estimate's error
@@ -552,7 +570,8 @@ def bench_relbin(args):
         "config": {"workload": "bns-relbin-15hz-512s", "n_samples": n, "n_det": n_det, "n_bins": g.n_bins,
                    "rb_bins": n_rb, "chi": 1.0, "eps": 0.03},
         "roofline": {"bound": "alu", "achieved": flops / kernel_s / 1e12, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": flops / kernel_s / 1e12 / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": flops / kernel_s / 1e12 / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic("relbin", RELBIN_PROFILE) if n == 65536 else None,
                      "kernel": "relative-binning lnl_kernel<3>", "kernel_ms": kernel_s * 1e3,
                      "flops_per_pair": rb_flops_per_pair(n_det)},
         "preparation_ms": prep_s * 1e3,
@@ -595,6 +614,8 @@ def main():
     ap.add_argument("--samples", type=int, default=None)
     ap.add_argument("--flags", type=int, default=0,
                     help="likelihood options: 1 direct form, 2 ISCO template end, 4 log prefactor (or-ed)")
+    ap.add_argument("--spins", action="store_true",
+                    help="single-event workloads: aligned spins chi1, chi2 ~ U[-1, 1] on every row")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -627,7 +648,7 @@ def main():
     if args.workload == "bns-relbin":
         bench_relbin(args)
         return
-    w, data, psd, theta = build_inputs(args.workload, args.samples)
+    w, data, psd, theta = build_inputs(args.workload, args.samples, args.spins)
     g = w.grid
     ws = gw.Workspace(0)
     ws.reserve(g.n_bins, w.n_det, w.n_samples)
@@ -675,11 +696,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n_samples": w.n_samples, "n_det": w.n_det, "n_bins": g.n_bins,
                    "delta_f": g.delta_f, "f_low": g.f_low, "f_high": g.f_high, "n_param": w.n_param,
-                   "precision": args.precision, "flags": args.flags},
+                   "precision": args.precision, "flags": args.flags, "spins": args.spins},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": (measured_traffic(args.precision)
-                                 if args.workload == "bbh-3det-128s" and args.flags == 0 else None),
+                                 if args.workload == "bbh-3det-128s" and args.flags == 0 and not args.spins
+                                 else None),
                      "kernel": f"lnl_tile_kernel<{w.n_det},{'mixed' if mixed else 'fp64'}>",
                      "kernel_ms": kernel_avg_s * 1e3, "flops_per_launch": flops_launch,
                      "flops_per_pair": flops_per_pair(w.n_det, mixed, direct)},

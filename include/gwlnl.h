@@ -19,23 +19,31 @@
  *    is evaluated (no upper cut-off) unless GW_FLAG_TERM_ISCO is given.
  *  - Complex arrays are interleaved (re, im) double pairs, the layout of
  *    torch.complex128 / numpy complex128.
- *  - theta is row-major [n_samples][n_param], n_param 5 or 9, columns
+ *  - theta is row-major [n_samples][n_param], n_param 5, 7, 9 or 11, columns
  *      0 Mc   chirp mass, solar masses      1 q     m2/m1 in (0, 1]
  *      2 dL   luminosity distance, Mpc      3 phic  coalescence phase, rad
  *      4 tc   coalescence time at the geocentre relative to the segment, s
  *      5 ra   right ascension, rad (Greenwich sidereal time taken as 0)
  *      6 dec  declination, rad              7 psi   polarisation angle, rad
  *      8 iota inclination, rad
- *    With n_param == 5 the source is optimally oriented (F+ = 1, Fx = 0,
- *    iota = 0, no delay) and the detector geometry is not used.
+ *    With n_param 5 or 7 the source is optimally oriented (F+ = 1, Fx = 0,
+ *    iota = 0, no delay) and the detector geometry is not used.  With
+ *    n_param 7 or 11 the last two columns are the dimensionless spins chi1
+ *    (of the heavier body m1) and chi2, along the orbital angular momentum,
+ *    in [-1, 1].
  *  - h_plus = A (1 + cos^2 iota)/2 e^{-i Psi}, h_cross = -i A cos iota e^{-i Psi},
  *    A = sqrt(5/24) pi^(-2/3) Mc^(5/6) f^(-7/6) / dL (geometric units),
  *    Psi = 2 pi f tc - phic - pi/4 + 3/(128 eta v^5) sum_k (phi_k + phi_k^l ln v) v^k,
  *    v = (pi M f)^(1/3), coefficients of Buonanno et al. 2009, Eq. (3.18).
+ *    Rows with spins add the aligned-spin terms to phi_k: spin-orbit at 1.5,
+ *    2.5 (as phi_5 (1 + 3 ln v)), 3 and 3.5PN, spin-spin at 2PN with the
+ *    black-hole quadrupole-monopole term (Kidder 1995; Poisson 1998;
+ *    Blanchet 2014; Bohe et al. 2013); the amplitude stays Newtonian.
  *    Response h_det = (F+ h_plus + Fx h_cross) e^{-2 pi i f dt_det},
  *    F = D : e with the polarisation tensors of the sky basis, dt_det = -n.r/c.
  *  - Per-sample domain: any non-finite parameter gives lnL = NaN; Mc <= 0,
- *    q outside (0, 1] or dL <= 0 give lnL = -infinity.  These are not errors.
+ *    q outside (0, 1], dL <= 0 or |chi| > 1 give lnL = -infinity.  These are
+ *    not errors.
  *
  * Calls and ownership
  *  - Every pointer marked "device" is a device pointer (e.g. a PyTorch tensor's
@@ -55,7 +63,7 @@
  *    returns a thread-local message about the last failing call.  Structural
  *    problems are reported synchronously and enqueue nothing: null pointers,
  *    n_bins < 1, delta_f <= 0 or non-finite, f_low <= 0 or non-finite,
- *    n_det outside 1..8, n_param not 5 or 9, n_samples < 0.
+ *    n_det outside 1..8, n_param not 5, 7, 9 or 11, n_samples < 0.
  *  - A PSD value that is <= 0 or non-finite cannot be seen without waiting
  *    for the device: the call then writes NaN to every lnL of that call.
  */
@@ -291,9 +299,9 @@ typedef struct gw_relbin gw_relbin;
  *            arena for the grid tables.
  *   grid, n_det, dets, data, psd  as for gw_lnl_batch, with n_bins >= 2.
  *   theta0   host [n_param]: the fiducial parameters.  They must be in the
- *            domain (finite, Mc > 0, q in (0, 1], d_L > 0) and give a non-zero
+ *            domain (finite, Mc > 0, q in (0, 1], d_L > 0, |chi| <= 1) and give a non-zero
  *            response on every detector, else GW_EINVAL.
- *   n_param  5 or 9; rows passed to gw_rb_lnl use the same layout.
+ *   n_param  5, 7, 9 or 11; rows passed to gw_rb_lnl use the same layout.
  *   edges    host [n_edges], n_edges >= 2, strictly increasing from 0 to
  *            n_bins - 1 (for instance from gw_rb_edges).
  *   flags    0 or GW_FLAG_ADD_NORM (every lnL then carries -sum ln(2 pi S));
@@ -362,11 +370,15 @@ int gw_philox_fill(uint64_t seed, uint32_t stream_id, uint32_t step, int kind, i
 int gw_philox_chain_normals(int dim, int64_t n_chains, uint64_t seed, uint32_t stream_id, uint32_t step,
                             double *out, hipStream_t stream);
 
-/* theta_out (device) [n][9] in the layout of gw_lnl_batch, and the log prior
- * density of x, sum_i log u_i (1 - u_i) (logprior_out may be NULL).
- * box_lo, box_hi: host [dim]; the sin Dec and cos iota boxes lie in [-1, 1]. */
+/* theta_out (device) [n][theta_cols] in the layout of gw_lnl_batch, and the
+ * log prior density of x, sum_i log u_i (1 - u_i) (logprior_out may be NULL).
+ * box_lo, box_hi: host [dim]; the sin Dec and cos iota boxes lie in [-1, 1].
+ * theta_cols 9: the nine non-spinning columns (with dim 11 the two spin
+ * coordinates stay sampler-only); theta_cols 11 (dim 11 only): the spin
+ * coordinates become chi1, chi2 in columns 9 and 10, their boxes within
+ * [-1, 1]. */
 int gw_mcmc_to_theta(int dim, int64_t n, const double *box_lo, const double *box_hi, const double *x,
-                     double *theta_out, double *logprior_out, hipStream_t stream);
+                     int theta_cols, double *theta_out, double *logprior_out, hipStream_t stream);
 
 /* Random-walk proposals x_prop = x + L z, z from Philox stream 1 at `step`
  * (chain c uses the normals of gw_philox_chain_normals).  chol: device [dim][dim],

@@ -96,7 +96,7 @@ def load_library() -> ctypes.CDLL:
         lib.gw_philox_raw.argtypes = [u64, u32p, u32p, u64, i64, vp, vp]
         lib.gw_philox_fill.argtypes = [u64, u32p, u32p, i32, i64, vp, vp]
         lib.gw_philox_chain_normals.argtypes = [i32, i64, u64, u32p, u32p, vp, vp]
-        lib.gw_mcmc_to_theta.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp]
+        lib.gw_mcmc_to_theta.argtypes = [i32, i64, vp, vp, vp, i32, vp, vp, vp]
         lib.gw_mcmc_rw_propose.argtypes = [i32, i64, vp, vp, u64, u32p, vp, vp, vp]
         lib.gw_mcmc_accept.argtypes = [i32, i64, u64, u32p, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.gw_mcmc_update_mode.argtypes = [i64, vp, i32, ctypes.c_double, vp, vp]
@@ -231,7 +231,7 @@ def lnl_batch(grid, tensors, vertices, data, psd, theta, *, precision: str = "fp
               workspace: Workspace | None = None, stream=None):
     """lnL for every row of theta (Eq. (cbclike) without its constant factor).
 
-    data: complex128 [n_det, M]; psd: float64 [n_det, M]; theta: float64 [S, 5 or 9],
+    data: complex128 [n_det, M]; psd: float64 [n_det, M]; theta: float64 [S, 5, 7, 9 or 11],
     all on the same GPU.  flags: FLAG_DIRECT | FLAG_TERM_ISCO | FLAG_ADD_NORM.
     Returns (or fills `out`) float64 [S] on that GPU.
     """
@@ -250,7 +250,7 @@ def lnl_batch(grid, tensors, vertices, data, psd, theta, *, precision: str = "fp
     if out is None:
         out = torch.empty(n_samples, dtype=torch.float64, device=theta.device)
     out = _cuda_tensor(out, torch.float64, "out", (n_samples,))
-    dets = make_detectors(tensors, vertices) if n_param != 5 or tensors is not None else (GwDetector * 1)()
+    dets = make_detectors(tensors, vertices) if n_param in (9, 11) or tensors is not None else (GwDetector * 1)()
     ws = workspace or default_workspace(dev)
     _check(load_library().gw_lnl_batch(ws.handle, ctypes.byref(g), n_det, dets, data.data_ptr(), psd.data_ptr(),
                                        theta.data_ptr(), n_param, n_samples, out.data_ptr(),
@@ -371,7 +371,7 @@ class RelativeBinning:
     """One event prepared for the relative-binning likelihood (gw_relbin).
 
     data complex128 [n_det, M] and psd float64 [n_det, M] on one GPU; theta0
-    the fiducial parameters (host, 5 or 9 values); edges the bin edges (host
+    the fiducial parameters (host, 5, 7, 9 or 11 values); edges the bin edges (host
     int64, from `rb_edges` or any strictly rising list from 0 to M - 1);
     flags 0 or FLAG_ADD_NORM.  The preparation is synchronous."""
 
@@ -388,7 +388,7 @@ class RelativeBinning:
         if psd.device.index != dev:
             raise ValueError("data and psd must be on the same device")
         e = np.ascontiguousarray(edges, dtype=np.int64).reshape(-1)
-        dets = make_detectors(tensors, vertices) if n_param != 5 or tensors is not None else (GwDetector * 1)()
+        dets = make_detectors(tensors, vertices) if n_param in (9, 11) or tensors is not None else (GwDetector * 1)()
         self.device = dev
         self.n_param = n_param
         self._ws = workspace or default_workspace(dev)
@@ -482,8 +482,10 @@ def chain_normals(dim: int, n_chains: int, seed: int, stream_id: int, step: int,
     return out
 
 
-def mcmc_to_theta(box_lo, box_hi, x, theta_out=None, logprior_out=None, stream=None):
-    """theta [n, 9] and log prior [n] of sampler coordinates x [n, dim]."""
+def mcmc_to_theta(box_lo, box_hi, x, theta_out=None, logprior_out=None, stream=None, theta_cols: int | None = None):
+    """theta [n, theta_cols] and log prior [n] of sampler coordinates x [n, dim].
+    theta_cols 9 (default), or 11 with dim 11 to pass the spin coordinates on
+    as chi1, chi2; with theta_out given its width decides."""
     torch = _torch()
     x = _cuda_tensor(x, torch.float64, "x")
     n, dim = x.shape
@@ -491,12 +493,16 @@ def mcmc_to_theta(box_lo, box_hi, x, theta_out=None, logprior_out=None, stream=N
     hi = np.ascontiguousarray(box_hi, dtype=np.float64)
     if lo.shape != (dim,) or hi.shape != (dim,):
         raise ValueError("box_lo and box_hi must have one entry per coordinate")
+    if theta_cols is None:
+        theta_cols = theta_out.shape[1] if theta_out is not None else 9
     if theta_out is None:
-        theta_out = torch.empty((n, 9), dtype=torch.float64, device=x.device)
+        theta_out = torch.empty((n, theta_cols), dtype=torch.float64, device=x.device)
+    theta_out = _cuda_tensor(theta_out, torch.float64, "theta_out", (n, theta_cols))
     if logprior_out is None:
         logprior_out = torch.empty(n, dtype=torch.float64, device=x.device)
-    _check(load_library().gw_mcmc_to_theta(dim, n, lo.ctypes.data, hi.ctypes.data, x.data_ptr(), theta_out.data_ptr(),
-                                           logprior_out.data_ptr(), _stream_ptr(x.device.index, stream)))
+    _check(load_library().gw_mcmc_to_theta(dim, n, lo.ctypes.data, hi.ctypes.data, x.data_ptr(), theta_cols,
+                                           theta_out.data_ptr(), logprior_out.data_ptr(),
+                                           _stream_ptr(x.device.index, stream)))
     return theta_out, logprior_out
 
 

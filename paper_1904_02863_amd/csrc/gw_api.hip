@@ -171,7 +171,7 @@ int check_grid(const gw_grid *grid)
 int check_dets(int n_det, const gw_detector *dets, int n_param, gw::DetGeom *geom)
 {
     std::memset(geom, 0, sizeof(*geom));
-    if (n_param == 5) return GW_OK;          // optimally oriented: geometry unused
+    if (!gw::param_has_sky(n_param)) return GW_OK;   // optimally oriented: geometry unused
     if (!dets) return fail(GW_EINVAL, "dets is NULL");
     for (int d = 0; d < n_det; ++d) {
         for (int i = 0; i < 9; ++i) {
@@ -255,7 +255,7 @@ int check_common(gw_workspace *ws, const gw_grid *grid, int n_det_min, int n_det
     if (!ws) return fail(GW_EINVAL, "workspace is NULL");
     if (int rc = check_grid(grid)) return rc;
     if (n_det < n_det_min || n_det > gw::kMaxDet) return fail(GW_EINVAL, "n_det out of range");
-    if (n_param != 5 && n_param != 9) return fail(GW_EINVAL, "n_param must be 5 or 9");
+    if (!gw::valid_n_param(n_param)) return fail(GW_EINVAL, "n_param must be 5, 7, 9 or 11");
     if (n_samples < 0) return fail(GW_EINVAL, "n_samples must be >= 0");
     return GW_OK;
 }
@@ -819,7 +819,7 @@ int gw_lnl_ragged(gw_workspace *ws, int n_events, const gw_event *events, const 
     if (n_events > 0 && (!data_packed || !psd_packed)) return fail(GW_EINVAL, "data or psd is NULL");
     if (precision != GW_PREC_FP64 && precision != GW_PREC_MIXED) return fail(GW_EINVAL, "unknown precision");
     if (flags & ~kLnlFlags) return fail(GW_EINVAL, "unknown flag bits");
-    if (n_param != 5 && n_param != 9) return fail(GW_EINVAL, "n_param must be 5 or 9");
+    if (!gw::valid_n_param(n_param)) return fail(GW_EINVAL, "n_param must be 5, 7, 9 or 11");
     std::vector<gw::DetGeom> geoms(n_events);
     for (int i = 0; i < n_events; ++i) {
         const gw_event &ev = events[i];
@@ -917,7 +917,9 @@ int gw_rb_create(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_dete
     if (n_edges - 1 > 0x7fffffffLL) return fail(GW_EINVAL, "too many bins");
     for (int i = 0; i < n_param; ++i)
         if (!std::isfinite(theta0[i])) return fail(GW_EINVAL, "theta0 is not finite");
-    if (!(theta0[0] > 0.0) || !(theta0[1] > 0.0 && theta0[1] <= 1.0) || !(theta0[2] > 0.0))
+    if (!(theta0[0] > 0.0) || !(theta0[1] > 0.0 && theta0[1] <= 1.0) || !(theta0[2] > 0.0) ||
+        (gw::param_has_spins(n_param) &&
+         (std::fabs(theta0[n_param - 2]) > 1.0 || std::fabs(theta0[n_param - 1]) > 1.0)))
         return fail(GW_EINVAL, "theta0 is outside the domain");
     gw::DetGeom geom;
     if (int rc = check_dets(n_det, dets, n_param, &geom)) return rc;

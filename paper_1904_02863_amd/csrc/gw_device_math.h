@@ -15,6 +15,14 @@
 //   Eq. (3.18), with the 2.5PN term written phi_5 (1 + 3 ln v) and the 3PN log
 //   term -6848/21 ln v.  (The waveform model itself is named, not printed, in
 //   Sec. II of arXiv:1904.02863.)
+// * gw_pn_spin_terms: the aligned-spin additions for spins chi1, chi2 along
+//   the orbital angular momentum, written body by body (x_i = m_i / M):
+//   spin-orbit at 1.5PN (Kidder 1995), 2.5PN (Blanchet, Buonanno & Faye
+//   2006; it enters as phi_5 (1 + 3 ln v)), 3PN with its tail (Blanchet 2014,
+//   Living Rev. Relativ. 17, 2) and 3.5PN (Bohe, Marsat, Faye & Blanchet
+//   2013); spin-spin at 2PN, S1 S2 (Kidder 1995) and the black-hole
+//   quadrupole-monopole and self-spin terms (Poisson 1998).  The chi_eff
+//   study of Sec. III of arXiv:1904.02863 implies a spinning template.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -96,4 +104,29 @@ __device__ __forceinline__ void gw_pn_coefficients(double eta, double phi[8], do
            + (76055.0 / 1728.0) * eta2 - (127825.0 / 1296.0) * eta3;
     phi_log[6] = -6848.0 / 21.0;
     phi[7] = GW_PI * (77096675.0 / 254016.0 + (378515.0 / 1512.0) * eta - (74045.0 / 756.0) * eta2);
+}
+
+// Aligned-spin additions to phi[k] and phi_log[5] (see the header comment);
+// x1 = m1/M of the heavier body, x2 = 1 - x1, eta = x1 x2.
+__device__ __forceinline__ void gw_pn_spin_terms(double x1, double x2, double chi1, double chi2, double phi[8],
+                                                 double phi_log[8])
+{
+    const double eta = x1 * x2, eta2 = eta * eta;
+    double so3 = 0.0, so5 = 0.0, so6 = 0.0, so7 = 0.0;
+    const double xs[2] = {x1, x2}, cs[2] = {chi1, chi2};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double x = xs[i], c = cs[i];
+        so3 += x * (25.0 + 38.0 / 3.0 * x) * c;
+        so5 -= x * (13915.0 / 84.0 - 10.0 / 3.0 * eta + x * (12760.0 / 81.0 + 170.0 / 9.0 * eta)) * c;
+        so6 += GW_PI * x * (1490.0 / 3.0 + 260.0 * x) * c;
+        so7 += x * (-170978035.0 / 48384.0 + 2876425.0 / 672.0 * eta + 4735.0 / 144.0 * eta2 +
+                    x * (-7189233785.0 / 1524096.0 + 458555.0 / 3024.0 * eta - 5345.0 / 72.0 * eta2)) * c;
+    }
+    phi[3] += so3;
+    phi[4] += -395.0 / 4.0 * eta * chi1 * chi2 - 405.0 / 8.0 * (x1 * x1 * chi1 * chi1 + x2 * x2 * chi2 * chi2);
+    phi[5] += so5;
+    phi_log[5] += 3.0 * so5;
+    phi[6] += so6;
+    phi[7] += so7;
 }

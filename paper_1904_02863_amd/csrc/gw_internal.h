@@ -29,6 +29,14 @@ enum RecordField : int {
 };
 constexpr int record_fields(int n_out) { return kRecDet + kRecFieldsPerDet * n_out; }
 
+// Parameter rows: 5 (optimally oriented), 7 (the same with aligned spins
+// chi1, chi2 appended), 9 (with sky position, polarisation, inclination),
+// 11 (9 with chi1, chi2 appended).
+__host__ __device__ constexpr bool valid_n_param(int n) { return n == 5 || n == 7 || n == 9 || n == 11; }
+__host__ __device__ constexpr bool param_has_sky(int n) { return n == 9 || n == 11; }
+__host__ __device__ constexpr bool param_has_spins(int n) { return n == 7 || n == 11; }
+constexpr int kMaxParam = 11;
+
 // Per event-preparation block and detector: sums of |d|^2/S, a^2/S, ln(2 pi S)
 // over the block's 256 consecutive bins.  The event sums hold the same three
 // quantities summed over all bins, at [kPrepPerDet d + 0, 1, 2].

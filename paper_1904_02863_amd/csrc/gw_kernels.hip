@@ -328,14 +328,17 @@ __device__ __forceinline__ void prep_sample(double f_low, double df, int64_t n_b
                                             const DetGeom &geom, const double *__restrict__ theta,
                                             double *__restrict__ rec)
 {
-    double t[9];
+    double t[kMaxParam];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) t[i] = i < n_param ? theta[s * n_param + i] : 0.0;
+    for (int i = 0; i < kMaxParam; ++i) t[i] = i < n_param ? theta[s * n_param + i] : 0.0;
     int status = 0;
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
+    for (int i = 0; i < kMaxParam; ++i)
         if (i < n_param && !isfinite(t[i])) status = 2;
     if (status == 0 && (!(t[0] > 0.0) || !(t[1] > 0.0 && t[1] <= 1.0) || !(t[2] > 0.0))) status = 1;
+    const bool spins = param_has_spins(n_param);
+    const double chi1 = spins ? t[n_param - 2] : 0.0, chi2 = spins ? t[n_param - 1] : 0.0;
+    if (status == 0 && spins && (fabs(chi1) > 1.0 || fabs(chi2) > 1.0)) status = 1;
 
     const double mc = t[0], q = t[1], dl = t[2], phic = t[3], tc = t[4];
     const double eta = q / ((1.0 + q) * (1.0 + q));
@@ -344,6 +347,7 @@ __device__ __forceinline__ void prep_sample(double f_low, double df, int64_t n_b
     const double ln_alpha = log(alpha);
     double phi[8], phil[8];
     gw_pn_coefficients(eta, phi, phil);
+    if (spins) gw_pn_spin_terms(1.0 / (1.0 + q), q / (1.0 + q), chi1, chi2, phi, phil);
     const double pref = 3.0 / (128.0 * eta) / GW_TWO_PI;   // phase in turns
     double apow[8];
     {
@@ -365,11 +369,11 @@ __device__ __forceinline__ void prep_sample(double f_low, double df, int64_t n_b
     }
 
     // detector geometry
-    const double ci = n_param == 9 ? cos(t[8]) : 1.0;
+    const double ci = param_has_sky(n_param) ? cos(t[8]) : 1.0;
     double fp[kMaxDet], fx[kMaxDet], dt[kMaxDet];
 #pragma unroll
     for (int d = 0; d < kMaxDet; ++d) { fp[d] = 1.0; fx[d] = 0.0; dt[d] = 0.0; }
-    if (n_param == 9 && !polarisations) {
+    if (param_has_sky(n_param) && !polarisations) {
         const double ra = t[5], dec = t[6], psi = t[7];
         const double cra = cos(ra), sra = sin(ra), cde = cos(dec), sde = sin(dec), cps = cos(psi), sps = sin(psi);
         const double n[3] = {cde * cra, cde * sra, sde};

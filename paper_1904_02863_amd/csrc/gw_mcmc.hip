@@ -131,7 +131,8 @@ __device__ __forceinline__ double log_u_1mu(double x)
 
 // theta (9 columns, the layout of gw_lnl_batch) and the log prior density of x.
 __global__ __launch_bounds__(256) void to_theta_kernel(int dim, int64_t n, Box box, const double *__restrict__ x,
-                                                       double *__restrict__ theta, double *__restrict__ logprior)
+                                                       int theta_cols, double *__restrict__ theta,
+                                                       double *__restrict__ logprior)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(256) void to_theta_kernel(int dim, int64_t n, Box b
         p[i] = box.lo[i] + (box.hi[i] - box.lo[i]) * sigmoid(xi);
         lp += log_u_1mu(xi);
     }
-    double *th = theta + c * 9;
+    double *th = theta + c * theta_cols;
     th[0] = p[0];           // Mc
     th[1] = p[1];           // q
     th[2] = p[2];           // d_L
@@ -152,6 +153,10 @@ __global__ __launch_bounds__(256) void to_theta_kernel(int dim, int64_t n, Box b
     th[6] = asin(p[6]);     // Dec from sin Dec
     th[7] = p[7];           // psi
     th[8] = acos(p[8]);     // iota from cos iota
+    if (theta_cols == 11) {
+        th[9] = p[9];       // chi1
+        th[10] = p[10];     // chi2
+    }
     if (logprior) logprior[c] = lp;
 }
 
@@ -248,11 +253,12 @@ hipError_t normals_for_chains(int dim, int64_t n, uint64_t seed, uint32_t stream
     return hipGetLastError();
 }
 
-hipError_t to_theta(int dim, int64_t n, const Box &box, const double *x, double *theta, double *logprior,
-                    hipStream_t s)
+hipError_t to_theta(int dim, int64_t n, const Box &box, const double *x, int theta_cols, double *theta,
+                    double *logprior, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(to_theta_kernel, dim3(blocks_for(n)), dim3(256), 0, s, dim, n, box, x, theta, logprior);
+    hipLaunchKernelGGL(to_theta_kernel, dim3(blocks_for(n)), dim3(256), 0, s, dim, n, box, x, theta_cols, theta,
+                       logprior);
     return hipGetLastError();
 }
 
@@ -320,10 +326,12 @@ int gw_philox_chain_normals(int dim, int64_t n_chains, uint64_t seed, uint32_t s
 }
 
 int gw_mcmc_to_theta(int dim, int64_t n, const double *box_lo, const double *box_hi, const double *x,
-                     double *theta_out, double *logprior_out, hipStream_t stream)
+                     int theta_cols, double *theta_out, double *logprior_out, hipStream_t stream)
 {
     if ((dim != 9 && dim != 11) || n < 0 || !box_lo || !box_hi || (n > 0 && (!x || !theta_out)))
         return fail(GW_EINVAL, "bad arguments");
+    if (theta_cols != 9 && !(theta_cols == 11 && dim == 11))
+        return fail(GW_EINVAL, "theta_cols must be 9, or 11 with dim 11");
     gw::mcmc::Box box{};
     for (int i = 0; i < dim; ++i) {
         if (!(box_hi[i] > box_lo[i])) return fail(GW_EINVAL, "empty prior box");
@@ -332,7 +340,9 @@ int gw_mcmc_to_theta(int dim, int64_t n, const double *box_lo, const double *box
     }
     if (box.lo[6] < -1.0 || box.hi[6] > 1.0 || box.lo[8] < -1.0 || box.hi[8] > 1.0)
         return fail(GW_EINVAL, "sin Dec and cos iota boxes must lie in [-1, 1]");
-    hipError_t e = gw::mcmc::to_theta(dim, n, box, x, theta_out, logprior_out, stream);
+    if (theta_cols == 11 && (box.lo[9] < -1.0 || box.hi[9] > 1.0 || box.lo[10] < -1.0 || box.hi[10] > 1.0))
+        return fail(GW_EINVAL, "spin boxes must lie in [-1, 1]");
+    hipError_t e = gw::mcmc::to_theta(dim, n, box, x, theta_cols, theta_out, logprior_out, stream);
     return e == hipSuccess ? GW_OK : hip_fail(e, "gw_mcmc_to_theta");
 }
 

@@ -27,8 +27,8 @@ hipError_t philox_raw(uint64_t seed, uint32_t stream, uint32_t step, uint64_t fi
 hipError_t philox_fill(uint64_t seed, uint32_t stream, uint32_t step, int kind, int64_t n, double *out, hipStream_t s);
 hipError_t normals_for_chains(int dim, int64_t n, uint64_t seed, uint32_t stream, uint32_t step, double *out,
                               hipStream_t s);
-hipError_t to_theta(int dim, int64_t n, const Box &box, const double *x, double *theta, double *logprior,
-                    hipStream_t s);
+hipError_t to_theta(int dim, int64_t n, const Box &box, const double *x, int theta_cols, double *theta,
+                    double *logprior, hipStream_t s);
 hipError_t rw_propose(int dim, int64_t n, const double *x, const double *chol, uint64_t seed, uint32_t step,
                       const int *mode, double *x_prop, hipStream_t s);
 hipError_t accept(int dim, int64_t n, uint64_t seed, uint32_t step, double *x, double *lnp, double *logq,

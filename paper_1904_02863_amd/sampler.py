@@ -49,10 +49,15 @@ class Problem:
     box_lo: np.ndarray      # [dim]
     box_hi: np.ndarray      # [dim]
     precision: str = "fp64"
+    spins: bool = False     # dim 11: the last two coordinates enter lnL as aligned spins chi1, chi2
 
     @property
     def dim(self) -> int:
         return int(self.box_lo.shape[0])
+
+    @property
+    def theta_cols(self) -> int:
+        return 11 if self.spins else 9
 
 
 def to_sampler_coords(problem: Problem, params: np.ndarray) -> np.ndarray:
@@ -67,10 +72,10 @@ def from_sampler_coords(problem: Problem, x: np.ndarray) -> np.ndarray:
 
 
 class _Buffers:
-    def __init__(self, torch, n, dim, device):
+    def __init__(self, torch, n, dim, device, theta_cols=9):
         f64 = dict(dtype=torch.float64, device=device)
         self.x_prop = torch.empty((n, dim), **f64)
-        self.theta = torch.empty((n, 9), **f64)
+        self.theta = torch.empty((n, theta_cols), **f64)
         self.lp = torch.empty(n, **f64)
         self.lnl = torch.empty(n, **f64)
         self.z = torch.empty((n, dim), **f64)
@@ -107,7 +112,7 @@ def init_chains(problem: Problem, x0: np.ndarray, ws: Workspace) -> ChainState:
     import torch
     dev = problem.data.device
     x = torch.from_numpy(np.ascontiguousarray(x0, dtype=np.float64)).to(dev)
-    buf = _Buffers(torch, x.shape[0], problem.dim, dev)
+    buf = _Buffers(torch, x.shape[0], problem.dim, dev, problem.theta_cols)
     _evaluate(problem, x, buf, ws)
     lnp = (buf.lnl + buf.lp).contiguous()
     return ChainState(x, lnp, torch.zeros_like(lnp), 0)
@@ -128,7 +133,7 @@ def run_random_walk(problem: Problem, state: ChainState, n_steps: int, seed: int
     import torch
     n, dim = state.x.shape
     dev = state.x.device
-    buf = _Buffers(torch, n, dim, dev)
+    buf = _Buffers(torch, n, dim, dev, problem.theta_cols)
     chol_t = torch.from_numpy(np.ascontiguousarray(chol)).to(dev)
     records, collected = [], []
     log_scale, window_start = 0.0, 0
@@ -231,7 +236,7 @@ def run_flow_mh(problem: Problem, state: ChainState, flow: Flow, n_steps: int, s
     import torch
     n, dim = state.x.shape
     dev = state.x.device
-    buf = _Buffers(torch, n, dim, dev)
+    buf = _Buffers(torch, n, dim, dev, problem.theta_cols)
     chol_t = torch.from_numpy(np.ascontiguousarray(chol)).to(dev)
     mode = torch.zeros(n, dtype=torch.int32, device=dev)
     flow.inverse(state.x, z_out=buf.z, logq_out=state.logq)

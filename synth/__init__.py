@@ -384,3 +384,10 @@ def scale_distance(w: Workload, factor: float) -> Workload:
     inj[2] *= factor
     th[:, 2] *= factor
     return dataclasses.replace(w, theta_inj=inj, theta=th)
+
+
+def add_spins(theta: np.ndarray, rng: np.random.Generator, bound: float = 1.0) -> np.ndarray:
+    """theta with two aligned-spin columns chi1, chi2 ~ U[-bound, bound]
+    appended (5 -> 7 or 9 -> 11 parameters)."""
+    th = np.atleast_2d(np.asarray(theta, dtype=np.float64))
+    return np.hstack([th, rng.uniform(-bound, bound, (th.shape[0], 2))])

@@ -172,7 +172,7 @@ def test_argument_errors(gw):
         gw.lnl_batch((20.0, -1.0, 100), w.tensors, w.vertices, d, s, th)
     assert e.value.code == gw.GW_EINVAL
     with pytest.raises(gw.GwError) as e:
-        gw.lnl_batch(w.grid, w.tensors, w.vertices, d, s, th[:, :7].contiguous())
+        gw.lnl_batch(w.grid, w.tensors, w.vertices, d, s, th[:, :8].contiguous())
     assert e.value.code == gw.GW_EINVAL
 
 

@@ -70,6 +70,26 @@ def test_coordinates_to_theta(gw):
     np.testing.assert_allclose(lp.cpu().numpy(), lp_ref, rtol=1e-13)
 
 
+def test_coordinates_to_theta_with_spins(gw):
+    rng = np.random.default_rng(5)
+    x = rng.normal(scale=3.0, size=(200, 11))
+    lo, hi = BOX_LO.copy(), BOX_HI.copy()
+    lo[9:], hi[9:] = [-0.9, -0.5], [0.8, 1.0]
+    th9, _ = gw.mcmc_to_theta(lo, hi, torch.from_numpy(x).to(DEV))
+    th11, lp = gw.mcmc_to_theta(lo, hi, torch.from_numpy(x).to(DEV), theta_cols=11)
+    u = 1 / (1 + np.exp(-x))
+    p = lo + (hi - lo) * u
+    assert th11.shape == (200, 11)
+    assert torch.equal(th11[:, :9], th9)
+    np.testing.assert_allclose(th11[:, 9:].cpu().numpy(), p[:, 9:], rtol=1e-13, atol=1e-13)
+    bad = hi.copy()
+    bad[10] = 1.5
+    with pytest.raises(gw.GwError):
+        gw.mcmc_to_theta(lo, bad, torch.from_numpy(x).to(DEV), theta_cols=11)
+    with pytest.raises(gw.GwError):
+        gw.mcmc_to_theta(lo[:9], hi[:9], torch.from_numpy(x[:, :9].copy()).to(DEV), theta_cols=11)
+
+
 def test_random_walk_proposal_and_acceptance(gw):
     rng = np.random.default_rng(1)
     n, d = 513, 11
