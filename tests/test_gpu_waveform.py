@@ -72,3 +72,14 @@ def test_out_of_domain_rows_are_nan(gw):
     got = _run(gw, w.grid, w.tensors, w.vertices, th)
     assert np.isfinite(got[0]).all()
     assert np.isnan(got[1:]).all()
+
+
+@pytest.mark.parametrize("n_samples,n_bins", [(16, 1024), (17, 1025), (37, 3001), (100, 257)])
+def test_sample_groups_and_span_tails(gw, n_samples, n_bins):
+    """Blocks cover a group of samples x 1024 bins: whole and partial sample
+    groups, whole and ragged bin spans."""
+    w = synth.small_event(33, 3, n_bins, n_samples, 9)
+    g = w.grid
+    got = _run(gw, g, w.tensors, w.vertices, w.theta)
+    ref = oracle.waveform(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, w.theta)
+    _check(got, ref, f"S={n_samples} M={n_bins}")
