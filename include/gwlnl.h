@@ -148,8 +148,8 @@ int gw_workspace_reserve(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_
 int64_t gw_workspace_bytes(const gw_workspace *ws);
 
 /* Measurement support.  While timing is enabled (enable != 0), every
- * gw_lnl_batch, gw_waveform_batch, gw_pop_lnl and gw_rb_lnl call made with
- * this workspace records a pair of HIP events on its own stream around its
+ * gw_lnl_batch, gw_waveform_batch, gw_pop_lnl(_prepared) and gw_rb_lnl call
+ * made with this workspace records a pair of HIP events on its own stream around its
  * hot kernel: the tile kernel that forms Z for every sample, bin and
  * detector; the kernel that writes the templates; the kernel that forms the
  * population weights; the per-sample relative-binning kernel.  Enabling (or disabling) clears earlier records. */
@@ -253,6 +253,18 @@ int gw_lnl_ragged(gw_workspace *ws, int n_events, const gw_event *events,
  */
 int gw_pop_lnl(gw_workspace *ws, int64_t n_events, int64_t n_per_event, const double *samples, int64_t n_hyper,
                const double *hyper, double *lnl_out, hipStream_t stream);
+
+/* The recycled likelihood reuses the same posterior samples for every
+ * Lambda, so the per-sample logarithms can be taken once:
+ * gw_pop_prepare writes prepared_out (device, caller-owned, [8][n_events][n]
+ * doubles: m1, ln m1, ln q, ln a1 + ln a2, ln(1 - a1) + ln(1 - a2),
+ * cos t1 - 1, cos t2 - 1, ln p(theta | 0); m1 = -1 marks a sample outside
+ * the supports), and gw_pop_lnl_prepared takes that array in place of
+ * `samples`, with results identical to gw_pop_lnl on the raw samples. */
+int gw_pop_prepare(int64_t n_events, int64_t n_per_event, const double *samples, double *prepared_out,
+                   hipStream_t stream);
+int gw_pop_lnl_prepared(gw_workspace *ws, int64_t n_events, int64_t n_per_event, const double *prepared,
+                        int64_t n_hyper, const double *hyper, double *lnl_out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Relative binning: Eq. (cbclike) from about 10^3 frequencies.

@@ -32,8 +32,8 @@ FLAG_ADD_NORM = 4
 # Every symbol include/gwlnl.h declares.
 EXPORTED = ("gw_workspace_create", "gw_workspace_destroy", "gw_workspace_reserve", "gw_workspace_bytes",
             "gw_workspace_set_timing", "gw_workspace_kernel_time", "gw_waveform_batch", "gw_lnl_batch",
-            "gw_lnl_ragged", "gw_ragged_tuning", "gw_pop_lnl", "gw_rb_edges", "gw_rb_create", "gw_rb_destroy",
-            "gw_rb_lnl", "gw_rb_shape", "gw_rb_summary", "gw_last_error", "gw_version",
+            "gw_lnl_ragged", "gw_ragged_tuning", "gw_pop_lnl", "gw_pop_prepare", "gw_pop_lnl_prepared",
+            "gw_rb_edges", "gw_rb_create", "gw_rb_destroy", "gw_rb_lnl", "gw_rb_shape", "gw_rb_summary", "gw_last_error", "gw_version",
             "gw_philox_raw", "gw_philox_fill", "gw_philox_chain_normals", "gw_mcmc_to_theta", "gw_mcmc_rw_propose",
             "gw_mcmc_accept", "gw_mcmc_update_mode", "gw_flow_create", "gw_flow_destroy", "gw_flow_num_params",
             "gw_flow_set_params", "gw_flow_get_params", "gw_flow_forward", "gw_flow_inverse", "gw_flow_gradients",
@@ -84,6 +84,8 @@ def load_library() -> ctypes.CDLL:
         lib.gw_lnl_ragged.argtypes = [vp, i32, ctypes.POINTER(GwEvent), vp, vp, vp, i32, vp, i32, u32, vp]
         lib.gw_ragged_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         lib.gw_pop_lnl.argtypes = [vp, i64, i64, vp, i64, vp, vp, vp]
+        lib.gw_pop_prepare.argtypes = [i64, i64, vp, vp, vp]
+        lib.gw_pop_lnl_prepared.argtypes = [vp, i64, i64, vp, i64, vp, vp, vp]
         lib.gw_rb_edges.argtypes = [ctypes.POINTER(GwGrid), ctypes.c_double, ctypes.c_double, vp, i64,
                                     ctypes.POINTER(i64)]
         lib.gw_rb_create.argtypes = [vp, ctypes.POINTER(GwGrid), i32, ctypes.POINTER(GwDetector), vp, vp, vp, i32,
@@ -330,14 +332,30 @@ def lnl_ragged(events, n_events: int, data_packed, psd_packed, theta_packed, *, 
     return out
 
 
-def pop_lnl(samples, hyper, *, out=None, workspace: Workspace | None = None, stream=None):
-    """Population ln L (Eq. (poplike)) for every row of hyper [K, 12] over
-    samples [7, n_events, n] (m1, q, a1, a2, cos t1, cos t2, ln prior), both
-    float64 on the same GPU; returns float64 [K] there."""
+def pop_prepare(samples, *, out=None, stream=None):
+    """Prepared samples [8, n_events, n] (gw_pop_prepare) from raw samples [7, n_events, n]."""
     torch = _torch()
     samples = _cuda_tensor(samples, torch.float64, "samples")
     if samples.dim() != 3 or samples.shape[0] != 7:
         raise ValueError("samples must be [7, n_events, n_per_event]")
+    shape = (8, samples.shape[1], samples.shape[2])
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=samples.device)
+    out = _cuda_tensor(out, torch.float64, "out", shape)
+    _check(load_library().gw_pop_prepare(samples.shape[1], samples.shape[2], samples.data_ptr(), out.data_ptr(),
+                                         _stream_ptr(samples.device.index, stream)))
+    return out
+
+
+def pop_lnl(samples, hyper, *, out=None, workspace: Workspace | None = None, stream=None):
+    """Population ln L (Eq. (poplike)) for every row of hyper [K, 12] over
+    samples [7, n_events, n] (m1, q, a1, a2, cos t1, cos t2, ln prior), or over
+    prepared samples [8, n_events, n] from `pop_prepare`, both float64 on the
+    same GPU; returns float64 [K] there."""
+    torch = _torch()
+    samples = _cuda_tensor(samples, torch.float64, "samples")
+    if samples.dim() != 3 or samples.shape[0] not in (7, 8):
+        raise ValueError("samples must be [7, n_events, n_per_event] (raw) or [8, ...] (prepared)")
     hyper = _cuda_tensor(hyper, torch.float64, "hyper")
     if hyper.dim() != 2 or hyper.shape[1] != 12:
         raise ValueError("hyper must be [n_hyper, 12]")
@@ -349,8 +367,9 @@ def pop_lnl(samples, hyper, *, out=None, workspace: Workspace | None = None, str
         out = torch.empty(k, dtype=torch.float64, device=samples.device)
     out = _cuda_tensor(out, torch.float64, "out", (k,))
     ws = workspace or default_workspace(dev)
-    _check(load_library().gw_pop_lnl(ws.handle, samples.shape[1], samples.shape[2], samples.data_ptr(), k,
-                                     hyper.data_ptr(), out.data_ptr(), _stream_ptr(dev, stream)))
+    fn = load_library().gw_pop_lnl_prepared if samples.shape[0] == 8 else load_library().gw_pop_lnl
+    _check(fn(ws.handle, samples.shape[1], samples.shape[2], samples.data_ptr(), k, hyper.data_ptr(), out.data_ptr(),
+              _stream_ptr(dev, stream)))
     return out
 
 

@@ -649,6 +649,30 @@ double rb_level(const gw_grid &g, int64_t k, double psi0, double f_max, double c
     return std::floor((rb_phase_bound(f, g.f_low, f_max, chi) - psi0) / eps);
 }
 
+int pop_run(gw_workspace *ws, int64_t n_events, int64_t n_per_event, const double *samples, bool prepared,
+            int64_t n_hyper, const double *hyper, double *lnl_out, hipStream_t stream)
+{
+    if (!ws) return fail(GW_EINVAL, "workspace is NULL");
+    if (n_events < 1 || n_per_event < 1 || n_hyper < 0) return fail(GW_EINVAL, "bad population sizes");
+    if (!samples || (n_hyper > 0 && (!hyper || !lnl_out))) return fail(GW_EINVAL, "NULL population argument");
+    if (gw::pop::weight_blocks(n_events, n_per_event) > 0x7fffffffLL || n_hyper > 0x7fffffffLL ||
+        n_hyper * n_events / 4 > 0x7fffffffLL)
+        return fail(GW_EINVAL, "population batch too large for one launch");
+    if (n_hyper == 0) return GW_OK;
+    DeviceGuard g(ws->device);
+    if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
+    drop_ragged_graph(ws);               // the arena is about to be laid out for the population pass
+    if (int rc = ensure_capacity(ws, gw::pop::workspace_bytes(n_events, n_per_event, n_hyper))) return rc;
+    ws->tables_valid = false;
+    hipEvent_t t_start, t_stop;
+    if (int rc = timer_pair(ws, &t_start, &t_stop)) return rc;
+    hipError_t e = gw::pop::launch(n_events, n_per_event, samples, prepared, n_hyper, hyper, ws->base, lnl_out,
+                                   t_start, t_stop, stream);
+    if (e != hipSuccess) return hip_fail(e, "gw_pop_lnl");
+    if (t_stop) ++ws->timed;
+    return GW_OK;
+}
+
 }  // namespace
 
 namespace gw {
@@ -838,25 +862,23 @@ int gw_lnl_ragged(gw_workspace *ws, int n_events, const gw_event *events, const 
 int gw_pop_lnl(gw_workspace *ws, int64_t n_events, int64_t n_per_event, const double *samples, int64_t n_hyper,
                const double *hyper, double *lnl_out, hipStream_t stream)
 {
-    if (!ws) return fail(GW_EINVAL, "workspace is NULL");
-    if (n_events < 1 || n_per_event < 1 || n_hyper < 0) return fail(GW_EINVAL, "bad population sizes");
-    if (!samples || (n_hyper > 0 && (!hyper || !lnl_out))) return fail(GW_EINVAL, "NULL population argument");
-    if (gw::pop::weight_blocks(n_events, n_per_event) > 0x7fffffffLL || n_hyper > 0x7fffffffLL ||
-        n_hyper * n_events / 4 > 0x7fffffffLL)
-        return fail(GW_EINVAL, "population batch too large for one launch");
-    if (n_hyper == 0) return GW_OK;
-    DeviceGuard g(ws->device);
-    if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
-    drop_ragged_graph(ws);               // the arena is about to be laid out for the population pass
-    if (int rc = ensure_capacity(ws, gw::pop::workspace_bytes(n_events, n_per_event, n_hyper))) return rc;
-    ws->tables_valid = false;
-    hipEvent_t t_start, t_stop;
-    if (int rc = timer_pair(ws, &t_start, &t_stop)) return rc;
-    hipError_t e = gw::pop::launch(n_events, n_per_event, samples, n_hyper, hyper, ws->base, lnl_out, t_start, t_stop,
-                                   stream);
-    if (e != hipSuccess) return hip_fail(e, "gw_pop_lnl");
-    if (t_stop) ++ws->timed;
-    return GW_OK;
+    return pop_run(ws, n_events, n_per_event, samples, false, n_hyper, hyper, lnl_out, stream);
+}
+
+int gw_pop_prepare(int64_t n_events, int64_t n_per_event, const double *samples, double *prepared_out,
+                   hipStream_t stream)
+{
+    if (n_events < 1 || n_per_event < 1) return fail(GW_EINVAL, "bad population sizes");
+    if (!samples || !prepared_out) return fail(GW_EINVAL, "NULL population argument");
+    if ((n_events * n_per_event + 255) / 256 > 0x7fffffffLL) return fail(GW_EINVAL, "too many samples");
+    hipError_t e = gw::pop::prepare(n_events, n_per_event, samples, prepared_out, stream);
+    return e == hipSuccess ? GW_OK : hip_fail(e, "gw_pop_prepare");
+}
+
+int gw_pop_lnl_prepared(gw_workspace *ws, int64_t n_events, int64_t n_per_event, const double *prepared,
+                        int64_t n_hyper, const double *hyper, double *lnl_out, hipStream_t stream)
+{
+    return pop_run(ws, n_events, n_per_event, prepared, true, n_hyper, hyper, lnl_out, stream);
 }
 
 int gw_rb_edges(const gw_grid *grid, double chi, double eps, int64_t *edges_out, int64_t capacity, int64_t *n_edges)

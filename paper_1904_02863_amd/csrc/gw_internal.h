@@ -188,9 +188,12 @@ int lnl_ragged_blocks_per_cu(int n_det, int tile_bins, bool mixed, int form);
 namespace pop {
 size_t workspace_bytes(int64_t n_events, int64_t n_per, int64_t n_hyper);
 int64_t weight_blocks(int64_t n_events, int64_t n_per);
+hipError_t prepare(int64_t n_events, int64_t n_per, const double *samples, double *prepared, hipStream_t stream);
+// samples raw [7][N][n] or, with `prepared`, from prepare [8][N][n];
 // t_start / t_stop (either may be null): events recorded around the weights kernel.
-hipError_t launch(int64_t n_events, int64_t n_per, const double *samples, int64_t n_hyper, const double *hyper,
-                  void *work, double *lnl, hipEvent_t t_start, hipEvent_t t_stop, hipStream_t stream);
+hipError_t launch(int64_t n_events, int64_t n_per, const double *samples, bool prepared, int64_t n_hyper,
+                  const double *hyper, void *work, double *lnl, hipEvent_t t_start, hipEvent_t t_stop,
+                  hipStream_t stream);
 }  // namespace pop
 
 // Relative binning (gw_relbin.hip).  Device layout of one prepared event:

@@ -12,8 +12,10 @@
 // normalisation is closed-form and computed once per Lambda.
 //
 // Layout: samples field-major [7][N][n] (m1, q, a1, a2, cos t1, cos t2,
-// ln p(theta | 0)).  Each block keeps 4 samples per thread of one event in
-// registers (their logarithms computed once) and loops over every Lambda,
+// ln p(theta | 0)), or prepared once into [8][N][n] (prepare_kernel: the
+// logarithms and offsets that do not depend on Lambda, so that a call with
+// one Lambda evaluates no per-sample logarithm).  Each block keeps 4 samples
+// per thread of one event in registers and loops over every Lambda,
 // whose constants it reads with wave-uniform loads; each wave writes its own
 // partial sum, so the weights kernel has no barrier.  One wave per (Lambda,
 // event) then sums that event's partials and takes the log of the mean, and
@@ -126,6 +128,45 @@ __device__ __forceinline__ Sample load_sample(const double *__restrict__ s, int6
     return x;
 }
 
+// Prepared samples, field-major [kPrepFields][N][n]: the part of load_sample
+// that does not depend on Lambda, computed once (gw_pop_prepare).  A sample
+// outside the Lambda-independent supports carries m1 = -1, which every
+// population's mass support rejects.
+constexpr int kPrepFields = 8;   // m1, ln m1, ln q, ln a1 + ln a2, ln(1-a1) + ln(1-a2), c1 - 1, c2 - 1, ln prior
+
+__device__ __forceinline__ Sample load_prepared(const double *__restrict__ p, int64_t plane, int64_t idx, bool live)
+{
+    Sample x{};
+    x.ok = false;
+    if (!live) return x;
+    x.m1 = p[idx];
+    x.ok = x.m1 > 0.0;
+    x.ln_m1 = p[plane + idx];
+    x.ln_q = p[2 * plane + idx];
+    x.ln_a_sum = p[3 * plane + idx];
+    x.ln_1ma_sum = p[4 * plane + idx];
+    x.c1m = p[5 * plane + idx];
+    x.c2m = p[6 * plane + idx];
+    x.ln_prior = p[7 * plane + idx];
+    return x;
+}
+
+__global__ __launch_bounds__(kThreads) void prepare_kernel(int64_t plane, const double *__restrict__ s,
+                                                           double *__restrict__ p)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= plane) return;
+    const Sample x = load_sample(s, plane, i, true);
+    p[i] = x.ok ? x.m1 : -1.0;
+    p[plane + i] = x.ok ? x.ln_m1 : 0.0;
+    p[2 * plane + i] = x.ok ? x.ln_q : 0.0;
+    p[3 * plane + i] = x.ok ? x.ln_a_sum : 0.0;
+    p[4 * plane + i] = x.ok ? x.ln_1ma_sum : 0.0;
+    p[5 * plane + i] = x.ok ? x.c1m : 0.0;
+    p[6 * plane + i] = x.ok ? x.c2m : 0.0;
+    p[7 * plane + i] = x.ok ? x.ln_prior : 0.0;
+}
+
 // p(theta | Lambda) / p(theta | 0) of one sample.
 __device__ __forceinline__ double weight(const Sample &x, const HyperC &c)
 {
@@ -154,6 +195,7 @@ __device__ __forceinline__ double weight(const Sample &x, const HyperC &c)
 // Block b = event * chunks + chunk: kPerBlock samples of the event; for every
 // Lambda each wave writes the sum of its samples' weights to
 // partials[(k * n_events + event) * n_slots + chunk * kWaves + wave].
+template <bool PREPARED>
 __global__ __launch_bounds__(kThreads) void weights_kernel(int64_t n_events, int64_t n_per, int64_t chunks,
                                                            const double *__restrict__ s, int64_t n_hyper,
                                                            const HyperC *__restrict__ hc, int64_t n_slots,
@@ -167,7 +209,8 @@ __global__ __launch_bounds__(kThreads) void weights_kernel(int64_t n_events, int
     for (int i = 0; i < kPerThread; ++i) {
         // consecutive lanes read consecutive samples
         const int64_t j = chunk * kPerBlock + (int64_t)i * kThreads + threadIdx.x;
-        x[i] = load_sample(s, plane, event * n_per + j, j < n_per);
+        x[i] = PREPARED ? load_prepared(s, plane, event * n_per + j, j < n_per)
+                        : load_sample(s, plane, event * n_per + j, j < n_per);
     }
     for (int64_t k = 0; k < n_hyper; ++k) {
         const HyperC c = hc[k];
@@ -232,8 +275,17 @@ size_t workspace_bytes(int64_t n_events, int64_t n_per, int64_t n_hyper)
            (size_t)n_hyper * (size_t)n_events * (size_t)slots_per_event(n_per) * sizeof(double);
 }
 
-hipError_t launch(int64_t n_events, int64_t n_per, const double *samples, int64_t n_hyper, const double *hyper,
-                  void *work, double *lnl, hipEvent_t t_start, hipEvent_t t_stop, hipStream_t stream)
+hipError_t prepare(int64_t n_events, int64_t n_per, const double *samples, double *prepared, hipStream_t stream)
+{
+    const int64_t plane = n_events * n_per;
+    hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)((plane + kThreads - 1) / kThreads)), dim3(kThreads), 0, stream,
+                       plane, samples, prepared);
+    return hipGetLastError();
+}
+
+hipError_t launch(int64_t n_events, int64_t n_per, const double *samples, bool prepared, int64_t n_hyper,
+                  const double *hyper, void *work, double *lnl, hipEvent_t t_start, hipEvent_t t_stop,
+                  hipStream_t stream)
 {
     HyperC *hc = static_cast<HyperC *>(work);
     const size_t hc_bytes = ((size_t)n_hyper * sizeof(HyperC) + 255) / 256 * 256;
@@ -247,8 +299,12 @@ hipError_t launch(int64_t n_events, int64_t n_per, const double *samples, int64_
     const int64_t chunks = (n_per + kPerBlock - 1) / kPerBlock;
     const int64_t n_slots = slots_per_event(n_per);
     if (t_start && (e = hipEventRecord(t_start, stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(weights_kernel, dim3((unsigned)(chunks * n_events)), dim3(kThreads), 0, stream, n_events, n_per,
-                       chunks, samples, n_hyper, hc, n_slots, partials);
+    if (prepared)
+        hipLaunchKernelGGL(weights_kernel<true>, dim3((unsigned)(chunks * n_events)), dim3(kThreads), 0, stream,
+                           n_events, n_per, chunks, samples, n_hyper, hc, n_slots, partials);
+    else
+        hipLaunchKernelGGL(weights_kernel<false>, dim3((unsigned)(chunks * n_events)), dim3(kThreads), 0, stream,
+                           n_events, n_per, chunks, samples, n_hyper, hc, n_slots, partials);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (t_stop && (e = hipEventRecord(t_stop, stream)) != hipSuccess) return e;
     const int64_t n_pairs = n_hyper * n_events;
