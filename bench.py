@@ -270,8 +270,8 @@ def bench_ragged(args):
 
 def bench_flow(args):
     """Learned proposal on the 3-detector 128 s data with one injection at
-    network SNR 25, 11 sampler coordinates (9 physical + two aligned spins the
-    non-spinning waveform ignores), 4096 chains: random-walk MH (burn-in with
+    network SNR 25, 11 sampler coordinates (9 physical + two aligned spins,
+    prior-only unless --spins passes them to the likelihood), 4096 chains: random-walk MH (burn-in with
     covariance adaptation, then production), a flow trained on 2e5 of its
     samples, then flow-proposal MH from the same states.  Reports ESS/s of
     both (bulk ESS, minimum over coordinates, from 256 chains recorded at every
@@ -305,12 +305,15 @@ def bench_flow(args):
     data = (torch.from_numpy(w.noise).to(dev) + h).contiguous()
     box_lo = np.array([25.0, 0.5, 0.2 * inj[2], 0.0, -0.1, 0.0, -1.0, 0.0, -1.0, -1.0, -1.0])
     box_hi = np.array([35.0, 1.0, 3.0 * inj[2], 2 * math.pi, 0.1, 2 * math.pi, 1.0, math.pi, 1.0, 1.0, 1.0])
-    prob = sampler.Problem(g, w.tensors, w.vertices, data, psd, box_lo, box_hi, args.precision)
+    prob = sampler.Problem(g, w.tensors, w.vertices, data, psd, box_lo, box_hi, args.precision, spins=args.spins)
     p_inj = np.array([inj[0], inj[1], inj[2], inj[3], inj[4], inj[5], math.sin(inj[6]), inj[7], math.cos(inj[8]),
                       0.0, 0.0])
     rng = np.random.default_rng(5)
     x0 = sampler.to_sampler_coords(prob, p_inj)[None] + rng.normal(scale=1e-3, size=(n_chains, 11))
-    x0[:, 9:] = rng.normal(scale=1.0, size=(n_chains, 2))          # spins: prior-only coordinates
+    if args.spins:      # spins enter lnL: start near the injection's (zero) spins like the other coordinates
+        x0[:, 9:] = rng.normal(scale=1e-3, size=(n_chains, 2))
+    else:               # spins: prior-only coordinates
+        x0[:, 9:] = rng.normal(scale=1.0, size=(n_chains, 2))
     state = sampler.init_chains(prob, x0, ws)
     seed = 20190408
     chol = np.diag(np.full(11, 1e-3))
@@ -342,7 +345,7 @@ def bench_flow(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+bf16", "data": "synthetic",
         "config": {"workload": "flow-mcmc", "chains": n_chains, "ess_chains": track, "snr": 25.0,
                    "burn_in_steps": args.mcmc_burn, "flow_train_steps": args.flow_steps,
-                   "train_samples": int(len(train)), "precision": args.precision},
+                   "train_samples": int(len(train)), "precision": args.precision, "spins": args.spins},
         "random_walk": {"ess_per_s": ess_rw * scale / t_rw, "min_ess": ess_rw * scale, "seconds": t_rw,
                         "acceptance": acc_rw, "acceptance_burn_in": acc_burn, "burn_in_seconds": t_burn,
                         "ess_per_coordinate": (per_rw * scale).tolist()},
@@ -522,8 +525,9 @@ def rb_flops_per_pair(n_det: int) -> int:
 
 def bench_relbin(args):
     """Relative binning (named in Secs. I and V): the 15 Hz / 512 s neutron-star
-    event (3 detectors, 1,040,897 bins, network SNR 30) cut into ~10^3 bins by
-    the phase-bound rule (chi 1, eps 0.03); one step = one gw_rb_lnl call over
+    event (3 detectors, 1,040,897 bins, network SNR 30; or with --rb-band
+    5hz-8192s one detector, 16,736,257 bins) cut into ~10^3 bins by the
+    phase-bound rule (chi 1, eps 0.03); one step = one gw_rb_lnl call over
     65,536 rows near the fiducial (the injection)."""
     import torch
 
@@ -533,7 +537,8 @@ def bench_relbin(args):
     n = args.samples or 65536
     dev = torch.device("cuda", 0)
     ws = gw.Workspace(0)
-    w = synth.relbin_bns(15.0, 512.0, 3, n, index=6)
+    f_low, duration, n_det = {"15hz-512s": (15.0, 512.0, 3), "5hz-8192s": (5.0, 8192.0, 1)}[args.rb_band]
+    w = synth.relbin_bns(f_low, duration, n_det, n, index=6)
     g = w.grid
     psd = torch.from_numpy(w.psd).to(dev)
     h = gw.waveform_batch(g, w.tensors, w.vertices, torch.from_numpy(w.theta_inj[None]).to(dev), workspace=ws)[0]
@@ -578,15 +583,17 @@ def bench_relbin(args):
     err = (out[:m] - full).abs().max().item()
     flops = rb_flops_per_pair(n_det) * n * n_rb
     result = {
-        "metric": "lnL evals/s (relative binning, BNS 15 Hz 512 s, 3 det)", "value": n / t, "unit": "lnL evals/s",
+        "metric": f"lnL evals/s (relative binning, BNS {f_low:g} Hz {duration:g} s, {n_det} det)", "value": n / t,
+        "unit": "lnL evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "bns-relbin-15hz-512s", "n_samples": n, "n_det": n_det, "n_bins": g.n_bins,
+        "config": {"workload": f"bns-relbin-{args.rb_band}", "n_samples": n, "n_det": n_det, "n_bins": g.n_bins,
                    "rb_bins": n_rb, "chi": 1.0, "eps": 0.03},
         "roofline": {"bound": "alu", "achieved": flops / kernel_s / 1e12, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": flops / kernel_s / 1e12 / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic("relbin", RELBIN_PROFILE) if n == 65536 else None,
-                     "kernel": "relative-binning lnl_kernel<3>", "kernel_ms": kernel_s * 1e3,
+                     "traffic": (measured_traffic("relbin", RELBIN_PROFILE)
+                                 if n == 65536 and args.rb_band == "15hz-512s" else None),
+                     "kernel": f"relative-binning lnl_kernel<{n_det}>", "kernel_ms": kernel_s * 1e3,
                      "flops_per_pair": rb_flops_per_pair(n_det)},
         "preparation_ms": prep_s * 1e3,
         "full_likelihood": {"value": m / full_s, "ms_per_call": full_s * 1e3, "rows": m},
@@ -628,8 +635,11 @@ def main():
     ap.add_argument("--samples", type=int, default=None)
     ap.add_argument("--flags", type=int, default=0,
                     help="likelihood options: 1 direct form, 2 ISCO template end, 4 log prefactor (or-ed)")
+    ap.add_argument("--rb-band", default="15hz-512s", choices=["15hz-512s", "5hz-8192s"],
+                    help="bns-relbin: the neutron-star band (3 detectors from 15 Hz, or 1 detector from 5 Hz)")
     ap.add_argument("--spins", action="store_true",
-                    help="single-event workloads: aligned spins chi1, chi2 ~ U[-1, 1] on every row")
+                    help="single-event workloads: aligned spins chi1, chi2 ~ U[-1, 1] on every row; "
+                         "flow-mcmc: the two spin coordinates enter the likelihood")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",

@@ -16,6 +16,8 @@ element by element on the same seeded inputs).
 * The benchmark's workload (15 Hz / 512 s, 3 detectors, 1,040,897 bins,
   1,039 bins of relative binning, 65,536 rows in the benchmark's launch):
   sampled rows against the oracle, 1e-10 relative.
+* The longest band (5 Hz / 8192 s, 16,736,257 bins): totals, B0 of every bin
+  and sampled rows against the oracle.
 """
 import ctypes
 import math
@@ -226,4 +228,29 @@ def test_benchmark_workload_sampled_rows(gw):
     exact = oracle.lnl(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, data, w.psd, w.theta[rows[:6]])
     print(f"  max |RB - exact| over 6 rows: {np.abs(got[rows[:6]] - exact).max():.3e}", flush=True)
     assert np.abs(got[rows[:6]] - exact).max() < 0.05
+    h.close()
+
+
+def test_longest_band(gw):
+    """5 Hz / 8192 s, one detector: 16,736,257 grid bins carried by ~10^3
+    bins of relative binning; the summary's totals and sampled rows against
+    the oracle."""
+    import torch
+    w, data = _event(5.0, 8192.0, 1, 512, index=9)
+    g = w.grid
+    e = gw.rb_edges(g, 1.0, 0.03)
+    print(f"{g.n_bins} bins, {len(e) - 1} relative-binning bins", flush=True)
+    h = _prepare(gw, w, data, e)
+    raw, tot = h.summary()
+    (th,) = _dev(w.theta)
+    got = h.lnl(th)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    s = rb.summary(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, data, w.psd, w.theta_inj, e)
+    assert tot[0] == pytest.approx(s["dd"], rel=1e-12)
+    np.testing.assert_allclose(raw[:, 0, 4], s["B0"][0], rtol=1e-10)
+    rows = np.array([0, 1, 255, 256, 511])
+    want = rb.lnl(s, w.tensors, w.vertices, w.theta[rows])
+    np.testing.assert_allclose(got[rows], want, rtol=1e-10)
+    np.testing.assert_allclose(got[rows] + 0.5 * s["dd"], want + 0.5 * s["dd"], rtol=0, atol=1e-7)
     h.close()

@@ -83,3 +83,19 @@ def test_sample_groups_and_span_tails(gw, n_samples, n_bins):
     got = _run(gw, g, w.tensors, w.vertices, w.theta)
     ref = oracle.waveform(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, w.theta)
     _check(got, ref, f"S={n_samples} M={n_bins}")
+
+
+def test_benchmark_batch_sampled(gw):
+    """The benchmark's launch: 256 samples x 3 detectors x 259,585 bins
+    (3.2 GB written); sampled rows against the oracle, every bin of them."""
+    import torch
+    w = synth.bbh_3det_128s(256)
+    g = w.grid
+    th = torch.from_numpy(w.theta).to("cuda")
+    out = gw.waveform_batch(g, w.tensors, w.vertices, th)
+    torch.cuda.synchronize()
+    rows = [0, 3, 4, 127, 255]
+    got = out[rows].cpu().numpy()
+    del out
+    ref = oracle.waveform(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, w.theta[rows])
+    _check(got, ref, "benchmark batch")
