@@ -513,14 +513,16 @@ def bench_waveform(args):
     print(json.dumps(result), flush=True)
 
 
-def rb_flops_per_pair(n_det: int) -> int:
+def rb_flops_per_pair(n_det: int, mixed: bool = False) -> int:
     """Algorithmic FP64 flops of the relative-binning kernel per (sample, bin),
     i.e. per edge (FMA = 2, multiply or add = 1): the phase-difference
     polynomial 19 (9 FMA + 1 multiply); per detector the phasor 34, the ratio
     (P/P0) e^{-i dPhi} 6, the linear term 4, the squared term 5 and the cross
     term with the previous edge 5, plus 2 for the delay term on every
-    detector but the first."""
-    return 19 + 54 * n_det + 2 * (n_det - 1)
+    detector but the first.  The mixed path replaces the phasor by the
+    reduction to a fractional turn (1 add) and two FP32 hardware
+    transcendentals, which are not counted."""
+    return 19 + (54 - (33 if mixed else 0)) * n_det + 2 * (n_det - 1)
 
 
 def bench_relbin(args):
@@ -555,12 +557,12 @@ def bench_relbin(args):
     theta = torch.from_numpy(w.theta).to(dev)
     out = torch.empty(n, dtype=torch.float64, device=dev)
     for _ in range(args.warmup):
-        rbh.lnl(theta, out=out, workspace=ws)
+        rbh.lnl(theta, out=out, workspace=ws, precision=args.precision)
     torch.cuda.synchronize()
     ws.set_timing(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        rbh.lnl(theta, out=out, workspace=ws)
+        rbh.lnl(theta, out=out, workspace=ws, precision=args.precision)
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / args.steps
     kernel_ms, launches = ws.kernel_time()
@@ -579,22 +581,23 @@ def bench_relbin(args):
         gw.lnl_batch(g, w.tensors, w.vertices, data, psd, theta[:m].contiguous(), out=full, workspace=ws)
     torch.cuda.synchronize()
     full_s = (time.perf_counter() - t1) / 3
-    rbh.lnl(theta, out=out, workspace=ws)
+    rbh.lnl(theta, out=out, workspace=ws, precision=args.precision)
     err = (out[:m] - full).abs().max().item()
-    flops = rb_flops_per_pair(n_det) * n * n_rb
+    mixed = args.precision == "mixed"
+    flops = rb_flops_per_pair(n_det, mixed) * n * n_rb
     result = {
         "metric": f"lnL evals/s (relative binning, BNS {f_low:g} Hz {duration:g} s, {n_det} det)", "value": n / t,
         "unit": "lnL evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"bns-relbin-{args.rb_band}", "n_samples": n, "n_det": n_det, "n_bins": g.n_bins,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32" if mixed else "f64", "data": "synthetic",
+        "config": {"workload": f"bns-relbin-{args.rb_band}", "precision": args.precision, "n_samples": n, "n_det": n_det, "n_bins": g.n_bins,
                    "rb_bins": n_rb, "chi": 1.0, "eps": 0.03},
         "roofline": {"bound": "alu", "achieved": flops / kernel_s / 1e12, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": flops / kernel_s / 1e12 / FP64_PEAK_TFLOPS,
                      "traffic": (measured_traffic("relbin", RELBIN_PROFILE)
-                                 if n == 65536 and args.rb_band == "15hz-512s" else None),
+                                 if n == 65536 and args.rb_band == "15hz-512s" and not mixed else None),
                      "kernel": f"relative-binning lnl_kernel<{n_det}>", "kernel_ms": kernel_s * 1e3,
-                     "flops_per_pair": rb_flops_per_pair(n_det)},
+                     "flops_per_pair": rb_flops_per_pair(n_det, mixed)},
         "preparation_ms": prep_s * 1e3,
         "full_likelihood": {"value": m / full_s, "ms_per_call": full_s * 1e3, "rows": m},
         "max_abs_error_vs_full": err,

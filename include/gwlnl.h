@@ -328,12 +328,15 @@ int gw_rb_create(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_dete
 int gw_rb_destroy(gw_relbin *rb);
 
 /* Relative-binning lnL of every row of theta.
- *   ws       workspace on the handle's device: scratch for the sample records
- *            and partial sums, and the hot-kernel timer (gw_workspace_set_timing).
- *   theta    device [n_samples][n_param of the handle]; lnl_out device [n_samples].
+ *   ws        workspace on the handle's device: scratch for the sample records
+ *             and partial sums, and the hot-kernel timer (gw_workspace_set_timing).
+ *   theta     device [n_samples][n_param of the handle]; lnl_out device [n_samples].
+ *   precision GW_PREC_FP64, or GW_PREC_MIXED: the ratio's phasor from the FP32
+ *             hardware sine and cosine of the FP64 phase reduced to a
+ *             fractional turn; the ratio and every sum stay FP64.
  * Per-row domain rules as for gw_lnl_batch. */
 int gw_rb_lnl(gw_workspace *ws, const gw_relbin *rb, const double *theta, int64_t n_samples, double *lnl_out,
-              hipStream_t stream);
+              int precision, hipStream_t stream);
 
 /* Number of bins B and of detectors of a handle. */
 int gw_rb_shape(const gw_relbin *rb, int64_t *n_rb, int *n_det);

@@ -91,7 +91,7 @@ def load_library() -> ctypes.CDLL:
         lib.gw_rb_create.argtypes = [vp, ctypes.POINTER(GwGrid), i32, ctypes.POINTER(GwDetector), vp, vp, vp, i32,
                                      vp, i64, u32, ctypes.POINTER(vp), vp]
         lib.gw_rb_destroy.argtypes = [vp]
-        lib.gw_rb_lnl.argtypes = [vp, vp, vp, i64, vp, vp]
+        lib.gw_rb_lnl.argtypes = [vp, vp, vp, i64, vp, i32, vp]
         lib.gw_rb_shape.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]
         lib.gw_rb_summary.argtypes = [vp, vp, vp]
         u64, u32p = ctypes.c_uint64, ctypes.c_uint32
@@ -425,8 +425,9 @@ class RelativeBinning:
         _check(load_library().gw_rb_shape(self._h, ctypes.byref(nb), ctypes.byref(nd)))
         return nb.value, nd.value
 
-    def lnl(self, theta, *, out=None, workspace: Workspace | None = None, stream=None):
-        """Relative-binning lnL of every row of theta (float64 [S, n_param] on the handle's GPU)."""
+    def lnl(self, theta, *, out=None, precision: str = "fp64", workspace: Workspace | None = None, stream=None):
+        """Relative-binning lnL of every row of theta (float64 [S, n_param] on the handle's GPU);
+        precision "fp64" or "mixed" (FP32 hardware phasor of the ratio)."""
         torch = _torch()
         theta = _cuda_tensor(theta, torch.float64, "theta")
         if theta.dim() != 2 or theta.shape[1] != self.n_param:
@@ -439,7 +440,7 @@ class RelativeBinning:
         out = _cuda_tensor(out, torch.float64, "out", (n,))
         ws = workspace or self._ws
         _check(load_library().gw_rb_lnl(ws.handle, self._h, theta.data_ptr(), n, out.data_ptr(),
-                                        _stream_ptr(self.device, stream)))
+                                        PRECISIONS[precision], _stream_ptr(self.device, stream)))
         return out
 
     def summary(self) -> tuple[np.ndarray, np.ndarray]:

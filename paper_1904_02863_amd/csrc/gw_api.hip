@@ -1064,16 +1064,18 @@ int gw_rb_summary(const gw_relbin *rb, double *raw_out, double *totals_out)
 }
 
 int gw_rb_lnl(gw_workspace *ws, const gw_relbin *rb, const double *theta, int64_t n_samples, double *lnl_out,
-              hipStream_t stream)
+              int precision, hipStream_t stream)
 {
     if (!ws || !rb) return fail(GW_EINVAL, "workspace or handle is NULL");
     if (n_samples < 0) return fail(GW_EINVAL, "n_samples must be >= 0");
+    if (precision != GW_PREC_FP64 && precision != GW_PREC_MIXED) return fail(GW_EINVAL, "unknown precision");
+    const bool mixed = precision == GW_PREC_MIXED;
     if (ws->device != rb->device) return fail(GW_EINVAL, "workspace and handle are on different devices");
     if (n_samples == 0) return GW_OK;
     if (!theta || !lnl_out) return fail(GW_EINVAL, "theta or lnl_out is NULL");
     DeviceGuard g(ws->device);
     if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
-    const int n_chunks = gw::rb::lnl_chunks(n_samples, rb->n_rb, rb->n_det, ws->n_cu);
+    const int n_chunks = gw::rb::lnl_chunks(n_samples, rb->n_rb, rb->n_det, mixed, ws->n_cu);
     if ((n_samples + gw::kBlock - 1) / gw::kBlock * n_chunks > 0x7fffffffLL)
         return fail(GW_EINVAL, "too many samples for one launch");
     drop_ragged_graph(ws);               // the arena is about to be laid out for this pass
@@ -1090,8 +1092,8 @@ int gw_rb_lnl(gw_workspace *ws, const gw_relbin *rb, const double *theta, int64_
         return hip_fail(e, "sample prep");
     hipEvent_t t_start, t_stop;
     if (int rc = timer_pair(ws, &t_start, &t_stop)) return rc;
-    if ((e = gw::rb::launch_lnl(rb->n_det, n_samples, rb->n_rb, n_chunks, rb->edges, rb->coef, rb->ends, rb->fid,
-                                rec, part, t_start, t_stop, stream)) != hipSuccess)
+    if ((e = gw::rb::launch_lnl(rb->n_det, mixed, n_samples, rb->n_rb, n_chunks, rb->edges, rb->coef, rb->ends,
+                                rb->fid, rec, part, t_start, t_stop, stream)) != hipSuccess)
         return hip_fail(e, "relative-binning pass");
     if (t_stop) ++ws->timed;
     if ((e = gw::rb::launch_finalize(n_samples, n_chunks, part, rec, rb->totals, (rb->flags & GW_FLAG_ADD_NORM) != 0,

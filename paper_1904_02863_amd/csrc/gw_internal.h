@@ -237,8 +237,9 @@ hipError_t launch_summary(const gw_grid &grid, int n_det, int64_t n_rb, const in
                           const RbEdge *edges, double *raw, RbCoef *coef, RbEnds *ends, double *bin_dd,
                           double *totals, hipStream_t stream);
 // Chunks of bins per sample group for n_samples samples over n_rb bins.
-int lnl_chunks(int64_t n_samples, int64_t n_rb, int n_det, int n_cu);
-hipError_t launch_lnl(int n_det, int64_t n_samples, int64_t n_rb, int n_chunks, const RbEdge *edges,
+int lnl_chunks(int64_t n_samples, int64_t n_rb, int n_det, bool mixed, int n_cu);
+// mixed: FP32 hardware phasor of the ratio (the phase and every sum FP64).
+hipError_t launch_lnl(int n_det, bool mixed, int64_t n_samples, int64_t n_rb, int n_chunks, const RbEdge *edges,
                       const RbCoef *coef, const RbEnds *ends, const double *fid, const double *rec,
                       double *partials, hipEvent_t t_start, hipEvent_t t_stop, hipStream_t stream);
 hipError_t launch_finalize(int64_t n_samples, int n_chunks, const double *partials, const double *rec,

@@ -207,7 +207,10 @@ __global__ __launch_bounds__(kBlock) void totals_kernel(int64_t n_rb, const doub
 // the same for every lane of a wave (the loop index is uniform), so they come
 // through the scalar cache.  Writes the chunk's partial sum of
 // <d, h> - <h, h>/2 for every sample.
-template <int NDET>
+// MIXED: the phase difference and its reduction to a fractional turn stay
+// FP64, the phasor comes from the FP32 hardware sine and cosine (inputs in
+// turns), and the ratio and every sum stay FP64.
+template <int NDET, bool MIXED>
 __device__ __forceinline__ void edge_ratio(const PhaseCoef &c, const RbEdge &e, const double (&qr)[NDET],
                                            const double (&qi)[NDET], const double (&dl)[NDET], double (&rr)[NDET],
                                            double (&ri)[NDET])
@@ -215,14 +218,21 @@ __device__ __forceinline__ void edge_ratio(const PhaseCoef &c, const RbEdge &e, 
     const double dphi = turns_phase(c, e.t1);
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
+        const double x = d == 0 ? dphi : __builtin_fma(e.f, dl[d], dphi);
         double er, ei;
-        gw_phasor_turns(d == 0 ? dphi : __builtin_fma(e.f, dl[d], dphi), er, ei);
+        if constexpr (MIXED) {
+            const float r = (float)(x - __builtin_rint(x));
+            er = (double)__builtin_amdgcn_cosf(r);
+            ei = -(double)__builtin_amdgcn_sinf(r);
+        } else {
+            gw_phasor_turns(x, er, ei);
+        }
         rr[d] = qr[d] * er - qi[d] * ei;
         ri[d] = qr[d] * ei + qi[d] * er;
     }
 }
 
-template <int NDET>
+template <int NDET, bool MIXED>
 __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t n_rb, int n_chunks,
                                                       const RbEdge *__restrict__ edges,
                                                       const RbCoef *__restrict__ coef, const RbEnds *__restrict__ ends,
@@ -261,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
         dl[d] = delta - fid[kRecDet + kRecFieldsPerDet * d + 2];   // zero for detector 0
     }
     // first edge: the lower side of bin b0 only
-    edge_ratio<NDET>(c, edges[b0], qr, qi, dl, rr, ri);
+    edge_ratio<NDET, MIXED>(c, edges[b0], qr, qi, dl, rr, ri);
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
         const RbEnds k = ends[b0 * NDET + d];
@@ -272,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
     // edges inside the chunk: both bins that meet there
 #pragma unroll 2
     for (int64_t e = b0 + 1; e < b1; ++e) {
-        edge_ratio<NDET>(c, edges[e], qr, qi, dl, nr, ni);
+        edge_ratio<NDET, MIXED>(c, edges[e], qr, qi, dl, nr, ni);
 #pragma unroll
         for (int d = 0; d < NDET; ++d) {
             const RbCoef k = coef[e * NDET + d];
@@ -287,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
         }
     }
     // last edge: the upper side of bin b1 - 1 only
-    edge_ratio<NDET>(c, edges[b1], qr, qi, dl, nr, ni);
+    edge_ratio<NDET, MIXED>(c, edges[b1], qr, qi, dl, nr, ni);
     double total = 0.0;
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
@@ -324,9 +334,23 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(int64_t n_samples, int
 }
 
 template <int NDET>
-void *lnl_kernel_ptr()
+void *lnl_kernel_ptr(bool mixed)
 {
-    return reinterpret_cast<void *>(&lnl_kernel<NDET>);
+    return mixed ? reinterpret_cast<void *>(&lnl_kernel<NDET, true>) : reinterpret_cast<void *>(&lnl_kernel<NDET, false>);
+}
+
+void *lnl_kernel_for(int n_det, bool mixed)
+{
+    switch (n_det) {
+    case 1: return lnl_kernel_ptr<1>(mixed);
+    case 2: return lnl_kernel_ptr<2>(mixed);
+    case 3: return lnl_kernel_ptr<3>(mixed);
+    case 4: return lnl_kernel_ptr<4>(mixed);
+    case 5: return lnl_kernel_ptr<5>(mixed);
+    case 6: return lnl_kernel_ptr<6>(mixed);
+    case 7: return lnl_kernel_ptr<7>(mixed);
+    default: return lnl_kernel_ptr<8>(mixed);
+    }
 }
 
 }  // namespace
@@ -358,44 +382,40 @@ hipError_t launch_summary(const gw_grid &grid, int n_det, int64_t n_rb, const in
     return hipGetLastError();
 }
 
-int lnl_blocks_per_cu(int n_det)
+int lnl_blocks_per_cu(int n_det, bool mixed)
 {
-    static int cache[kMaxDet] = {};
+    static int cache[2][kMaxDet] = {};
     if (GW_RB_BLOCKS_PER_CU > 0) return GW_RB_BLOCKS_PER_CU;
     if (n_det < 1 || n_det > kMaxDet) return 1;
-    if (cache[n_det - 1] == 0) {
-        static void *const kernels[kMaxDet] = {lnl_kernel_ptr<1>(), lnl_kernel_ptr<2>(), lnl_kernel_ptr<3>(),
-                                               lnl_kernel_ptr<4>(), lnl_kernel_ptr<5>(), lnl_kernel_ptr<6>(),
-                                               lnl_kernel_ptr<7>(), lnl_kernel_ptr<8>()};
+    int &c = cache[mixed ? 1 : 0][n_det - 1];
+    if (c == 0) {
         int blocks = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernels[n_det - 1], kBlock, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, lnl_kernel_for(n_det, mixed), kBlock, 0) !=
+                hipSuccess ||
             blocks < 1)
             blocks = 4;
-        cache[n_det - 1] = blocks;
+        c = blocks;
     }
-    return cache[n_det - 1];
+    return c;
 }
 
-int lnl_chunks(int64_t n_samples, int64_t n_rb, int n_det, int n_cu)
+int lnl_chunks(int64_t n_samples, int64_t n_rb, int n_det, bool mixed, int n_cu)
 {
     const int64_t groups = (n_samples + kBlock - 1) / kBlock;
     // enough blocks to fill every compute unit to its occupancy limit in one
     // wave of blocks (more resident waves hide the latency of the long
     // dependent chains of the phasor polynomials), chunks of at least 16 bins
-    const int64_t target = (int64_t)lnl_blocks_per_cu(n_det) * (n_cu > 0 ? n_cu : 256);
+    const int64_t target = (int64_t)lnl_blocks_per_cu(n_det, mixed) * (n_cu > 0 ? n_cu : 256);
     int64_t chunks = (target + groups - 1) / groups;
     chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, n_rb / 16));
     chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, 4096));
     return (int)chunks;
 }
 
-hipError_t launch_lnl(int n_det, int64_t n_samples, int64_t n_rb, int n_chunks, const RbEdge *edges,
+hipError_t launch_lnl(int n_det, bool mixed, int64_t n_samples, int64_t n_rb, int n_chunks, const RbEdge *edges,
                       const RbCoef *coef, const RbEnds *ends, const double *fid, const double *rec,
                       double *partials, hipEvent_t t_start, hipEvent_t t_stop, hipStream_t stream)
 {
-    static void *const kernels[kMaxDet] = {lnl_kernel_ptr<1>(), lnl_kernel_ptr<2>(), lnl_kernel_ptr<3>(),
-                                           lnl_kernel_ptr<4>(), lnl_kernel_ptr<5>(), lnl_kernel_ptr<6>(),
-                                           lnl_kernel_ptr<7>(), lnl_kernel_ptr<8>()};
     if (n_det < 1 || n_det > kMaxDet) return hipErrorInvalidValue;
     const int64_t groups = (n_samples + kBlock - 1) / kBlock;
     const int64_t blocks = groups * n_chunks;
@@ -403,7 +423,7 @@ hipError_t launch_lnl(int n_det, int64_t n_samples, int64_t n_rb, int n_chunks, 
     void *args[] = {&n_samples, &n_rb, &n_chunks, &edges, &coef, &ends, &fid, &rec, &partials};
     hipError_t e;
     if (t_start && (e = hipEventRecord(t_start, stream)) != hipSuccess) return e;
-    e = hipLaunchKernel(kernels[n_det - 1], dim3((unsigned)blocks), dim3(kBlock), args, 0, stream);
+    e = hipLaunchKernel(lnl_kernel_for(n_det, mixed), dim3((unsigned)blocks), dim3(kBlock), args, 0, stream);
     if (e != hipSuccess) return e;
     if (t_stop && (e = hipEventRecord(t_stop, stream)) != hipSuccess) return e;
     return hipSuccess;

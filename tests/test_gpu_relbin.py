@@ -18,6 +18,8 @@ element by element on the same seeded inputs).
   sampled rows against the oracle, 1e-10 relative.
 * The longest band (5 Hz / 8192 s, 16,736,257 bins): totals, B0 of every bin
   and sampled rows against the oracle.
+* Mixed precision (FP32 hardware phasor of the ratio): within 1e-3 of the
+  FP64 pass at SNR 30 and 100.
 """
 import ctypes
 import math
@@ -253,4 +255,28 @@ def test_longest_band(gw):
     want = rb.lnl(s, w.tensors, w.vertices, w.theta[rows])
     np.testing.assert_allclose(got[rows], want, rtol=1e-10)
     np.testing.assert_allclose(got[rows] + 0.5 * s["dd"], want + 0.5 * s["dd"], rtol=0, atol=1e-7)
+    h.close()
+
+
+@pytest.mark.parametrize("snr", [30.0, 100.0])
+def test_mixed_precision(gw, snr):
+    """The FP32 hardware phasor of the ratio: |dlnL| <= 1e-3 against the FP64
+    pass (and the oracle) for near-fiducial rows at SNR 30 and 100."""
+    import torch
+    w, data = _event(30.0, 64.0, 3, 1000, snr=snr)
+    g = w.grid
+    e = gw.rb_edges(g, 1.0, 0.03)
+    h = _prepare(gw, w, data, e)
+    (th,) = _dev(w.theta)
+    a = h.lnl(th)
+    b = h.lnl(th, precision="mixed")
+    torch.cuda.synchronize()
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    s = rb.summary(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, data, w.psd, w.theta_inj, e)
+    want = rb.lnl(s, w.tensors, w.vertices, w.theta[:50])
+    print(f"SNR {snr}: max |mixed - fp64| {np.abs(b - a).max():.3e}", flush=True)
+    assert np.abs(b - a).max() <= 1e-3
+    assert np.abs(b[:50] - want).max() <= 1e-3
+    with pytest.raises(KeyError):
+        h.lnl(th, precision="fp16")
     h.close()

@@ -64,5 +64,5 @@ def test_create_rejects_bad_arguments_without_a_device(gw):
     rc = lib.gw_rb_create(None, ctypes.byref(g), 1, None, None, None, th.ctypes.data_as(ctypes.c_void_p), 5,
                           edges.ctypes.data_as(ctypes.c_void_p), 3, 0, ctypes.byref(h), None)
     assert rc == gw.GW_EINVAL and not h.value
-    assert lib.gw_rb_lnl(None, None, None, 1, None, None) == gw.GW_EINVAL
+    assert lib.gw_rb_lnl(None, None, None, 1, None, 0, None) == gw.GW_EINVAL
     assert lib.gw_rb_destroy(None) == gw.GW_OK
