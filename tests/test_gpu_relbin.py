@@ -226,6 +226,10 @@ def test_benchmark_workload_sampled_rows(gw):
     want = rb.lnl(s, w.tensors, w.vertices, w.theta[rows])
     np.testing.assert_allclose(got[rows], want, rtol=1e-10)
     np.testing.assert_allclose(got[rows] + 0.5 * s["dd"], want + 0.5 * s["dd"], rtol=0, atol=1e-7)
+    # the mixed pass in the same launch shape: every row within 1e-3 of the FP64 one
+    mixed = h.lnl(th, precision="mixed")
+    torch.cuda.synchronize()
+    assert np.abs(mixed.cpu().numpy() - got).max() <= 1e-3
     # the approximation against the full likelihood near the fiducial
     exact = oracle.lnl(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, data, w.psd, w.theta[rows[:6]])
     print(f"  max |RB - exact| over 6 rows: {np.abs(got[rows[:6]] - exact).max():.3e}", flush=True)
