@@ -284,3 +284,20 @@ def test_mixed_precision(gw, snr):
     with pytest.raises(KeyError):
         h.lnl(th, precision="fp16")
     h.close()
+
+
+def test_single_bin_and_single_row(gw, event):
+    """The smallest partition (one bin, two edges) and a batch of one row."""
+    import torch
+    w, data = event
+    g = w.grid
+    e = np.array([0, g.n_bins - 1], dtype=np.int64)
+    h = _prepare(gw, w, data, e)
+    assert h.shape == (1, 3)
+    for rows in (w.theta[:1], w.theta[:37]):
+        (th,) = _dev(rows)
+        got = h.lnl(th)
+        torch.cuda.synchronize()
+        s = rb.summary(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, data, w.psd, w.theta_inj, e)
+        np.testing.assert_allclose(got.cpu().numpy(), rb.lnl(s, w.tensors, w.vertices, rows), rtol=1e-10)
+    h.close()
