@@ -37,6 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # summary records their SHA-256 next to the traffic it measured.
 KERNEL_SOURCES = ("paper_1904_02863_amd/csrc/gw_kernels.hip", "paper_1904_02863_amd/csrc/gw_device_math.h",
                   "paper_1904_02863_amd/csrc/gw_internal.h", "paper_1904_02863_amd/csrc/gw_template.h",
+                  "paper_1904_02863_amd/csrc/gw_phasor_table.h", "paper_1904_02863_amd/csrc/gw_api.hip",
                   "paper_1904_02863_amd/csrc/gw_relbin.hip", "paper_1904_02863_amd/build.py")
 PROFILE_SUMMARY = "profiles/lnl_tile_kernel_bbh-3det-128s.md"
 WAVEFORM_PROFILE = "profiles/waveform_kernel_bbh-3det-128s.md"
@@ -47,7 +48,10 @@ def flops_per_pair(n_det: int, mixed: bool = False, direct: bool = False) -> int
     """Algorithmic FP64 flops of the tile kernel per (sample, bin) pair
     (FMA = 2, multiply or add = 1, rounding to an integer not counted):
     phase polynomial in u = f^(1/3) 19 (9 FMA + 1 multiply), phasor
-    e^{-2 pi i x} from the phase in turns 34 (15 FMA + 3 multiplies + 1 add),
+    e^{-2 pi i x} from the phase in turns at a fixed tally of 34 (the count of
+    the polynomial phasor gw_phasor_turns, 15 FMA + 3 multiplies + 1 add,
+    whichever implementation runs: the FP64 tile loop takes it from an LDS
+    table and two short polynomials, about 19 flops in 15 operations),
     detector-0 complex accumulation 8 (4 FMA), and for every further detector
     one Horner step S <- S conj(rho) + D e^{-i Phi} 14 (6 FMA + 2 multiplies).
     The mixed path replaces the phasor by the reduction to a fractional turn

@@ -187,30 +187,51 @@ int check_dets(int n_det, const gw_detector *dets, int n_param, gw::DetGeom *geo
 }
 
 #ifndef GW_TILE_LDS_BUDGET
-#define GW_TILE_LDS_BUDGET (40 * 1024)
+#define GW_TILE_LDS_BUDGET (56 * 1024)
+#endif
+// Work distribution of the single-event tile kernel: 0, one block per (group,
+// chunk) item in one wave of resident blocks; R >= 1, a persistent grid over
+// a work queue of R rounds of chunks, each round one item per resident block
+// and (R > 1) each round covering half the bins the earlier rounds left.  The
+// queue evens out what a static split leaves uneven: the wave arbiter favours
+// the oldest wave of a SIMD, so co-resident blocks of equal work finish far
+// apart, and a SIMD left with one wave issues at about half rate.
+#ifndef GW_TILE_ROUNDS
+#define GW_TILE_ROUNDS 6
 #endif
 
-int tile_bins_for(int n_det, int form)
+int tile_bins_for(int n_det, int form, bool mixed)
 {
     const size_t budget = GW_TILE_LDS_BUDGET;   // bytes of LDS per block: several blocks per CU fit in 160 KB
     int t = 2048;
-    while (t > 64 && gw::lnl_tile_lds_bytes(n_det, t, form) > budget) t /= 2;
+    while (t > 64 && gw::lnl_tile_lds_bytes(n_det, t, form, mixed) > budget) t /= 2;
     return t;
 }
 
 gw::TilePlan plan_tiles(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples, bool mixed, int form)
 {
     gw::TilePlan p;
-    p.tile_bins = tile_bins_for(n_det, form);
+    p.tile_bins = tile_bins_for(n_det, form, mixed);
     p.n_groups = (int)((n_samples + gw::kBlock - 1) / gw::kBlock);
     int &occ = ws->blocks_per_cu[form][mixed ? 1 : 0][n_det];
     if (occ == 0) occ = gw::lnl_tile_blocks_per_cu(n_det, p.tile_bins, mixed, form);
-    const int64_t target = (int64_t)ws->n_cu * occ;
-    int64_t chunks = (target + p.n_groups - 1) / p.n_groups;
+    const int64_t resident = (int64_t)ws->n_cu * occ;
+    int64_t chunks = (resident + p.n_groups - 1) / p.n_groups;
     const int64_t max_chunks = std::max<int64_t>(1, n_bins / 64);     // at least 64 bins per chunk
     chunks = std::max<int64_t>(1, std::min(chunks, max_chunks));
     p.chunk_bins = (n_bins + chunks - 1) / chunks;
     p.n_chunks = (int)((n_bins + p.chunk_bins - 1) / p.chunk_bins);
+    p.rounds = 0;
+    p.blocks = p.n_groups * p.n_chunks;
+    const int rounds = GW_TILE_ROUNDS;
+    // the ISCO end leaves the device-side band unknown here and usually short:
+    // one item per resident block
+    if (rounds >= 1 && form != gw::kFormSplitIsco && (int64_t)p.n_chunks * rounds * 64 <= n_bins) {
+        p.rounds = rounds;
+        p.n_chunks *= rounds;
+        p.chunk_bins = (n_bins + p.n_chunks - 1) / p.n_chunks;
+        p.blocks = (int)std::min<int64_t>((int64_t)p.n_groups * p.n_chunks, resident);
+    }
     return p;
 }
 
@@ -218,7 +239,7 @@ gw::TilePlan plan_tiles(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_s
 // sums are carved only when the call's flags use them.
 struct LnlLayout {
     size_t tab1, tab2, dcoef, edir, vdir, qprefix, qoffsets, prep_partials, event_sums, k_limit, records, partials,
-        total;
+        queue, total;
     int prep_blocks;
 };
 
@@ -240,6 +261,7 @@ LnlLayout lnl_layout(int64_t n_bins, int n_det, int64_t n_samples, const gw::Til
     l.k_limit = c.take(sizeof(int64_t));
     l.records = c.take(sizeof(double) * gw::record_fields(n_det) * std::max<int64_t>(n_samples, 1));
     l.partials = c.take(sizeof(double2) * (size_t)plan.n_chunks * n_samples * n_det);
+    l.queue = c.take(sizeof(unsigned));
     l.total = c.offset;
     return l;
 }
@@ -308,6 +330,7 @@ int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::De
     eb.prep_blocks = l.prep_blocks;
     eb.sums = at<double>(ws, l.event_sums);
     eb.k_limit = at<int64_t>(ws, l.k_limit);
+    eb.queue = plan.rounds > 0 ? at<unsigned>(ws, l.queue) : nullptr;
     auto *rec = at<double>(ws, l.records);
     auto *part = at<double2>(ws, l.partials);
     hipError_t e;
@@ -575,7 +598,7 @@ int ragged_run(gw_workspace *ws, int n_events, const gw_event *events, const std
     if (it == ws->ragged_tuning.end()) {
         float best = 0.0f;
         for (int tb : kTuneTiles) {
-            if (gw::lnl_tile_lds_bytes(max_det, tb, form) > 64 * 1024) continue;
+            if (gw::lnl_tile_lds_bytes(max_det, tb, form, mixed) > 64 * 1024) continue;
             for (int64_t cb : kTuneChunks) {
                 if (int rc = ragged_materialise(ws, na, ev, active_geoms, data, psd, theta, n_param, lnl, mixed, flags,
                                                 tb, cb, ws->capture_stream, &plan))

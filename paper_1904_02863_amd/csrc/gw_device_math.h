@@ -10,6 +10,10 @@
 //   which the vector ALU issues at full rate.  The polynomials carry the
 //   double angle's factors (sqrt(2) sin, -sqrt(2) cos), so the double angle
 //   costs one FMA and one multiply.  Coefficients come from gen_sincos.py.
+// * gw_phasor_table: the same phasor from a table of N = 1024 roots of unity
+//   (each rounded once) and degree-5/4 polynomials of the remainder, at most
+//   half a table step (15 operations instead of 20, and more accurate); the
+//   phase comes in scaled by N and the hot loops keep the table in LDS.
 // * gw_pn_coefficients: the non-spinning TaylorF2 phase coefficients through
 //   3.5PN, Buonanno, Iyer, Ochsner, Pan & Sathyaprakash, PRD 80, 084043 (2009),
 //   Eq. (3.18), with the 2.5PN term written phi_5 (1 + 3 ln v) and the 3PN log
@@ -26,6 +30,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include "gw_phasor_table.h"
 
 #define GW_PI 3.141592653589793
 #define GW_TWO_PI 6.283185307179586
@@ -82,6 +88,26 @@ __device__ __forceinline__ void gw_phasor_turns(double x, double &re, double &im
     const double c2 = __builtin_fma(z, c, -GW_SQRT2);
     re = __builtin_fma(-s2, s2, 1.0);
     im = s2 * c2;
+}
+
+// (re, im) = e^{-2 pi i x} for the scaled phase y = N x (x in turns, N =
+// GW_PHTAB_N) from the table tab[k] = e^{-2 pi i k / N} ((re, im) pairs, in
+// LDS) and short polynomials of the remainder: j = rint(y) by the
+// round-to-integer of adding 1.5 * 2^52 (|y| < 2^51), r = y - j exactly
+// (|r| <= 1/2), e^{-2 pi i x} = tab[j mod N] (cos(2 pi r / N) - i sin(2 pi r / N));
+// j mod N comes from the low bits of the sum.  15 operations; worst absolute
+// error 1.5e-16 (gen_phasor_table.py).
+__device__ __forceinline__ void gw_phasor_table(double y, const double2 *__restrict__ tab, double &re, double &im)
+{
+    constexpr double kRound = 6755399441055744.0;       // 1.5 * 2^52
+    const double t = y + kRound;
+    const double r = y - (t - kRound);
+    const double2 e = tab[__double2loint(t) & (GW_PHTAB_N - 1)];
+    const double z = r * r;
+    const double s = r * __builtin_fma(z, __builtin_fma(z, GW_PHTAB_S5, GW_PHTAB_S3), GW_PHTAB_S1);
+    const double c = __builtin_fma(z, __builtin_fma(z, GW_PHTAB_C4, GW_PHTAB_C2), 1.0);
+    re = __builtin_fma(e.x, c, e.y * s);
+    im = __builtin_fma(e.y, c, -(e.x * s));
 }
 
 // TaylorF2 coefficients phi[k], phi_log[k] (k = 0..7) at symmetric mass ratio eta.

@@ -126,8 +126,10 @@ struct RaggedLaunch {
 struct TilePlan {
     int n_groups;        // ceil(n_samples / kBlock)
     int n_chunks;        // bin chunks per sample group
-    int64_t chunk_bins;  // bins per chunk (the last may be shorter)
+    int64_t chunk_bins;  // bins per chunk (the last may be shorter); static launch only
     int tile_bins;       // bins staged in LDS at a time
+    int rounds;          // 0: one block per (group, chunk); >= 1: work queue, chunks in this many rounds
+    int blocks;          // blocks launched
 };
 
 // Sizes of workspace sections for one event.
@@ -151,6 +153,7 @@ struct EventBuffers {
     int prep_blocks;      // ceil(n_bins / kBlock)
     double *sums;         // [kEventSums]
     int64_t *k_limit;     // ISCO end: 1 + the largest K_s of the batch
+    unsigned *queue;      // work-queue counter of the tile kernel (zeroed by the event sums), or null
 };
 
 // ---- launchers (gw_kernels.hip); all enqueue on `stream` and return the launch status ----
@@ -247,7 +250,7 @@ hipError_t launch_finalize(int64_t n_samples, int n_chunks, const double *partia
 }  // namespace rb
 
 // LDS bytes of the tile kernel and its occupancy.
-size_t lnl_tile_lds_bytes(int n_det, int tile_bins, int form);
+size_t lnl_tile_lds_bytes(int n_det, int tile_bins, int form, bool mixed);
 int lnl_tile_blocks_per_cu(int n_det, int tile_bins, bool mixed, int form);
 
 }  // namespace gw

@@ -35,6 +35,11 @@
 #ifndef GW_TILE_WAVES_PER_EU
 #define GW_TILE_WAVES_PER_EU 0
 #endif
+// 1: the FP64 tile loops take e^{-i Phi} from the LDS table (gw_phasor_table);
+// 0: from the polynomial phasor (gw_phasor_turns).
+#ifndef GW_PHASOR_TABLE
+#define GW_PHASOR_TABLE 1
+#endif
 #if GW_TILE_WAVES_PER_EU > 0
 #define GW_TILE_ATTR __attribute__((amdgpu_waves_per_eu(GW_TILE_WAVES_PER_EU)))
 #else
@@ -226,13 +231,15 @@ __global__ __launch_bounds__(kBlock) void event_data_kernel(PrepView v, int dire
 }
 
 // Block j: sums[j] = the event-wide sum of quantity j (kPrepPerDet n_det blocks).
+// Also zeroes the tile kernel's work-queue counter when there is one.
 __global__ __launch_bounds__(kBlock) void event_sums_kernel(int n_blocks, int n_det,
                                                              const double *__restrict__ partials,
-                                                             double *__restrict__ sums)
+                                                             double *__restrict__ sums, unsigned *__restrict__ queue)
 {
     __shared__ double red[kBlock];
     const double t = column_total(n_blocks, kPrepPerDet * n_det, blockIdx.x, partials, red);
     if (threadIdx.x == 0) sums[blockIdx.x] = t;
+    if (queue && blockIdx.x == 0 && threadIdx.x == 0) *queue = 0u;
 }
 
 // Block d: qoffsets[d][b], the a^2/S total of the blocks before b.
@@ -518,10 +525,33 @@ struct EventView {
 
 // LDS layout of a tile: tab1 [tile], then per detector D (split) or d/a
 // (direct) [NDET][tile] double2, then for the direct form a^2/S [NDET][tile].
-__host__ __device__ constexpr size_t tile_lds_bytes(int n_det, int tile_bins, int form)
+// LDS of one tile block: the phasor table (FP64 path) and the tiles.
+__host__ __device__ constexpr size_t phasor_table_lds(bool mixed)
 {
-    return (size_t)tile_bins * (sizeof(Tab1) + (size_t)n_det * sizeof(double2) +
+    return (GW_PHASOR_TABLE && !mixed) ? (size_t)GW_PHTAB_N * sizeof(double2) : 0;
+}
+__host__ __device__ constexpr size_t tile_lds_bytes(int n_det, int tile_bins, int form, bool mixed)
+{
+    return phasor_table_lds(mixed) +
+           (size_t)tile_bins * (sizeof(Tab1) + (size_t)n_det * sizeof(double2) +
                                 (form == kFormDirect ? (size_t)n_det * sizeof(double) : 0));
+}
+
+// e^{-2 pi i k / N} for the LDS copy of every FP64 tile block.
+__constant__ __align__(16) double phasor_table_src[GW_PHTAB_N][2] = {GW_PHTAB_VALUES};
+
+// Copies the phasor table into the head of the block's LDS (FP64 path) and
+// returns where the tiles begin.  The tile loop's first barrier publishes it.
+template <bool MIXED>
+__device__ __forceinline__ double *stage_phasor_table(double4 *lds_raw)
+{
+    if constexpr (GW_PHASOR_TABLE && !MIXED) {
+        double2 *tab = reinterpret_cast<double2 *>(lds_raw);
+        for (int i = threadIdx.x; i < GW_PHTAB_N; i += kBlock)
+            tab[i] = make_double2(phasor_table_src[i][0], phasor_table_src[i][1]);
+        return reinterpret_cast<double *>(tab + GW_PHTAB_N);
+    }
+    return reinterpret_cast<double *>(lds_raw);
 }
 
 // The 256 samples of `group` (one per thread) against bins [k_begin, k_end)
@@ -539,6 +569,8 @@ template <int NDET, bool MIXED, int FORM>
 __device__ __forceinline__ void tile_chunk(const EventView &ev, int group, int64_t chunk, int64_t k_begin,
                                            int64_t k_end, int tile_bins, double *lds)
 {
+    // the phasor table sits just below the tiles (FP64 path)
+    const double2 *ptab = reinterpret_cast<const double2 *>(lds) - GW_PHTAB_N;
     constexpr bool kDirect = FORM == kFormDirect;
     constexpr bool kMasked = FORM != kFormSplit;
     const int64_t n_bins = ev.n_bins, n_samples = ev.n_samples;
@@ -553,7 +585,11 @@ __device__ __forceinline__ void tile_chunk(const EventView &ev, int group, int64
     double2 *ld = reinterpret_cast<double2 *>(lt + tile_bins);
     double *lv = reinterpret_cast<double *>(ld + NDET * tile_bins);
 
-    const PhaseCoef cf = load_coef(rec, n_samples, sr);
+    PhaseCoef cf = load_coef(rec, n_samples, sr);
+#if GW_PHASOR_TABLE
+    // the table phasor takes the phase in units of 1/N turn (exact: N = 2^10)
+    if constexpr (!MIXED) cf = scale_coef(cf, (double)GW_PHTAB_N);
+#endif
     const int64_t kcut = kMasked ? (int64_t)rec[kRecKcut * n_samples + sr] : n_bins - 1;
     double rho_re[NDET], rho_im[NDET], delta[NDET], p_re[NDET], p_im[NDET];
 #pragma unroll
@@ -616,7 +652,11 @@ __device__ __forceinline__ void tile_chunk(const EventView &ev, int group, int64
                 er = (double)__builtin_amdgcn_cosf(r);
                 ei = -(double)__builtin_amdgcn_sinf(r);
             } else {
+#if GW_PHASOR_TABLE
+                gw_phasor_table(turns_phase(cf, tb), ptab, er, ei);
+#else
                 gw_phasor_turns(turns_phase(cf, tb), er, ei);
+#endif
             }
             if (kMasked && j > jcut) {
                 er = 0.0;
@@ -685,30 +725,71 @@ __device__ __forceinline__ void tile_chunk(const EventView &ev, int group, int64
     }
 }
 
-// One event: block (chunk, group).  Blocks are dispatched round-robin over the
-// 8 XCDs; when the grid is a multiple of 8 the linear work index is remapped
-// so that the blocks of one XCD cover consecutive chunks (and all sample
-// groups of each), keeping their bin data in that XCD's L2.  With the ISCO
-// end (split form) the n_chunks chunks cover only bins below 1 + max K_s,
-// read from the device, so that no block works on bins every template has
-// left.
+// Bins [k_begin, k_end) of chunk c among n_chunks chunks of n_eff bins.
+// rounds <= 1: equal chunks.  rounds R > 1: the chunks come in R rounds of
+// n_chunks / R equal chunks each; round r < R - 1 covers the next half of the
+// bins still left (n_eff/2, n_eff/4, ...) and the last round the rest, so that
+// a queue handing out chunks in index order ends on small ones.
+__device__ __forceinline__ void chunk_range(int64_t n_eff, int64_t c, int n_chunks, int rounds, int64_t &k_begin,
+                                            int64_t &k_end)
+{
+    if (rounds <= 1) {
+        const int64_t cb = max((int64_t)1, (n_eff + n_chunks - 1) / n_chunks);
+        k_begin = min(n_eff, c * cb);
+        k_end = min(n_eff, k_begin + cb);
+        return;
+    }
+    const int64_t per = n_chunks / rounds;
+    const int64_t r = c / per, j = c % per;
+    const int64_t rb = n_eff - (n_eff >> r);
+    const int64_t re = (r == rounds - 1) ? n_eff : n_eff - (n_eff >> (r + 1));
+    k_begin = rb + (re - rb) * j / per;
+    k_end = rb + (re - rb) * (j + 1) / per;
+}
+
+// One event.  queue == null: one block per work item (chunk, group), the grid
+// being about one wave of resident blocks; blocks are dispatched round-robin
+// over the 8 XCDs, and when the grid is a multiple of 8 the linear work index
+// is remapped so that the blocks of one XCD cover consecutive chunks.
+// queue != null: a persistent grid; every block takes the next item from the
+// counter (zero at launch) until the n_groups x n_chunks items are gone, so
+// that blocks the wave arbiter favours, or CUs that clock higher, take more
+// items and every SIMD keeps its waves until the end.  Item i is chunk
+// i / n_groups of group i % n_groups (chunks in index order, all groups of a
+// chunk together).  With the ISCO end (split form) the chunks cover only the
+// bins below 1 + max K_s, read from the device, so that no block works on
+// bins every template has left.
 template <int NDET, bool MIXED, int FORM>
 __global__ __launch_bounds__(kBlock) GW_TILE_ATTR void lnl_tile_kernel(EventView ev, int n_groups, int n_chunks,
-                                                                       int64_t chunk_bins, int tile_bins)
+                                                                       int rounds, int tile_bins,
+                                                                       unsigned *__restrict__ queue)
 {
     extern __shared__ double4 lds_raw[];
-    const unsigned nb = gridDim.x, b = blockIdx.x;
-    const unsigned w = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + b / 8u : b;
-    const int group = (int)(w % (unsigned)n_groups);
-    const int64_t chunk = (int64_t)(w / (unsigned)n_groups);
-    int64_t n_eff = ev.n_bins, cb = chunk_bins;
-    if (FORM == kFormSplitIsco) {
-        n_eff = min(ev.n_bins, max((int64_t)0, *ev.k_limit));
-        cb = max((int64_t)1, (n_eff + n_chunks - 1) / n_chunks);
+    __shared__ int next;
+    const int64_t n_eff =
+        FORM == kFormSplitIsco ? min(ev.n_bins, max((int64_t)0, *ev.k_limit)) : ev.n_bins;
+    const int n_items = n_groups * n_chunks;
+    double *const tiles = stage_phasor_table<MIXED>(lds_raw);
+    if (queue == nullptr) {
+        const unsigned nb = gridDim.x, b = blockIdx.x;
+        const unsigned w = (nb % 8u == 0u) ? (b % 8u) * (nb / 8u) + b / 8u : b;
+        int64_t k_begin, k_end;
+        chunk_range(n_eff, (int64_t)(w / (unsigned)n_groups), n_chunks, rounds, k_begin, k_end);
+        tile_chunk<NDET, MIXED, FORM>(ev, (int)(w % (unsigned)n_groups), (int64_t)(w / (unsigned)n_groups), k_begin,
+                                      k_end, tile_bins, tiles);
+        return;
     }
-    const int64_t k_begin = min(n_eff, chunk * cb);
-    const int64_t k_end = min(n_eff, k_begin + cb);
-    tile_chunk<NDET, MIXED, FORM>(ev, group, chunk, k_begin, k_end, tile_bins, reinterpret_cast<double *>(lds_raw));
+    for (;;) {
+        __syncthreads();                 // every thread has read `next` and left the LDS tiles
+        if (threadIdx.x == 0) next = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int it = next;
+        if (it >= n_items) break;
+        const int64_t chunk = it / n_groups;
+        int64_t k_begin, k_end;
+        chunk_range(n_eff, chunk, n_chunks, rounds, k_begin, k_end);
+        tile_chunk<NDET, MIXED, FORM>(ev, it % n_groups, chunk, k_begin, k_end, tile_bins, tiles);
+    }
 }
 
 // Many events: a persistent grid.  Every block repeatedly takes the next work
@@ -723,6 +804,7 @@ __global__ __launch_bounds__(kBlock) GW_TILE_ATTR void lnl_ragged_kernel(const R
 {
     extern __shared__ double4 lds_raw[];
     __shared__ int next;
+    double *const tiles = stage_phasor_table<MIXED>(lds_raw);
     for (;;) {
         __syncthreads();                 // every thread has read `next` and left the LDS
         if (threadIdx.x == 0) next = (int)atomicAdd(counter, 1u);
@@ -745,8 +827,7 @@ __global__ __launch_bounds__(kBlock) GW_TILE_ATTR void lnl_ragged_kernel(const R
         ev.partials = re.partials;
         const int64_t k_begin = (int64_t)wi.chunk * re.chunk_bins;
         const int64_t k_end = min(re.n_bins, k_begin + re.chunk_bins);
-        tile_chunk<NDET, MIXED, FORM>(ev, wi.group, wi.chunk, k_begin, k_end, tile_bins,
-                                      reinterpret_cast<double *>(lds_raw));
+        tile_chunk<NDET, MIXED, FORM>(ev, wi.group, wi.chunk, k_begin, k_end, tile_bins, tiles);
     }
 }
 
@@ -814,9 +895,10 @@ __device__ __forceinline__ double finalize_row(int64_t s, int64_t n_samples, int
     return assemble_row(s, n_samples, n_det, n_bins, df, flags, zr, zi, resid, rec, sums, qprefix);
 }
 
-// One event: 32 rows per block, 8 threads per row; thread part p sums chunks
-// p, p + 8, ... in order, then the parts are added in order 0..7.
-constexpr int kFinRows = 32, kFinParts = kBlock / kFinRows;
+// One event: 16 rows per block, 16 threads per row; thread part p sums chunks
+// p, p + 16, ... in order (every detector of a chunk in one contiguous read),
+// then the parts are added in order 0..15.
+constexpr int kFinRows = 16, kFinParts = kBlock / kFinRows;
 
 __global__ __launch_bounds__(kBlock) void lnl_finalize_kernel(int64_t n_samples, int n_det, int n_chunks,
                                                                int64_t n_bins, double df, unsigned flags,
@@ -837,15 +919,25 @@ __global__ __launch_bounds__(kBlock) void lnl_finalize_kernel(int64_t n_samples,
             for (int c = part; c < n_chunks; c += kFinParts) acc += pd[(int64_t)c * n_samples + s];
             red[part][r][0] = acc;
         } else {
-            for (int d = 0; d < n_det; ++d) {
-                double zr = 0.0, zi = 0.0;
-                for (int c = part; c < n_chunks; c += kFinParts) {
-                    const double2 z = partials[((int64_t)c * n_samples + s) * n_det + d];
-                    zr += z.x;
-                    zi += z.y;
+            double zr[kMaxDet], zi[kMaxDet];
+#pragma unroll
+            for (int d = 0; d < kMaxDet; ++d) { zr[d] = 0.0; zi[d] = 0.0; }
+            for (int c = part; c < n_chunks; c += kFinParts) {
+                const double2 *z = partials + ((int64_t)c * n_samples + s) * n_det;
+#pragma unroll
+                for (int d = 0; d < kMaxDet; ++d) {
+                    if (d < n_det) {
+                        zr[d] += z[d].x;
+                        zi[d] += z[d].y;
+                    }
                 }
-                red[part][r][2 * d] = zr;
-                red[part][r][2 * d + 1] = zi;
+            }
+#pragma unroll
+            for (int d = 0; d < kMaxDet; ++d) {
+                if (d < n_det) {
+                    red[part][r][2 * d] = zr[d];
+                    red[part][r][2 * d + 1] = zi[d];
+                }
             }
         }
     }
@@ -989,7 +1081,7 @@ hipError_t launch_event_data(const gw_grid &grid, int n_det, const gw_c128 *data
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(event_sums_kernel, dim3(kPrepPerDet * n_det), dim3(kBlock), 0, stream, eb.prep_blocks, n_det,
-                       eb.prep, eb.sums);
+                       eb.prep, eb.sums, eb.queue);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (flags & GW_FLAG_TERM_ISCO) {
         hipLaunchKernelGGL(event_offsets_kernel, dim3(n_det), dim3(kBlock), 0, stream, (int64_t)eb.prep_blocks, n_det,
@@ -1018,7 +1110,10 @@ hipError_t launch_isco_limit(int64_t n_samples, const double *records, int64_t *
     return hipGetLastError();
 }
 
-size_t lnl_tile_lds_bytes(int n_det, int tile_bins, int form) { return tile_lds_bytes(n_det, tile_bins, form); }
+size_t lnl_tile_lds_bytes(int n_det, int tile_bins, int form, bool mixed)
+{
+    return tile_lds_bytes(n_det, tile_bins, form, mixed);
+}
 
 template <int NDET, bool MIXED>
 static const void *tile_kernel_form(int form)
@@ -1070,12 +1165,12 @@ static int occupancy(const void *fn, size_t lds)
 
 int lnl_tile_blocks_per_cu(int n_det, int tile_bins, bool mixed, int form)
 {
-    return occupancy(kernel_for(false, n_det, mixed, form), tile_lds_bytes(n_det, tile_bins, form));
+    return occupancy(kernel_for(false, n_det, mixed, form), tile_lds_bytes(n_det, tile_bins, form, mixed));
 }
 
 int lnl_ragged_blocks_per_cu(int n_det, int tile_bins, bool mixed, int form)
 {
-    return occupancy(kernel_for(true, n_det, mixed, form), tile_lds_bytes(n_det, tile_bins, form));
+    return occupancy(kernel_for(true, n_det, mixed, form), tile_lds_bytes(n_det, tile_bins, form, mixed));
 }
 
 hipError_t launch_lnl_tiles(const gw_grid &grid, int n_det, int64_t n_samples, const TilePlan &plan, bool mixed,
@@ -1096,11 +1191,12 @@ hipError_t launch_lnl_tiles(const gw_grid &grid, int n_det, int64_t n_samples, c
     ev.partials = partials;
     const void *fn = kernel_for(false, n_det, mixed, form);
     if (!fn) return hipErrorInvalidValue;
-    const unsigned blocks = (unsigned)plan.n_groups * (unsigned)plan.n_chunks;
-    int n_groups = plan.n_groups, n_chunks = plan.n_chunks, tile_bins = plan.tile_bins;
-    int64_t chunk_bins = plan.chunk_bins;
-    void *args[] = {&ev, &n_groups, &n_chunks, &chunk_bins, &tile_bins};
-    return hipLaunchKernel(fn, dim3(blocks), dim3(kBlock), args, tile_lds_bytes(n_det, plan.tile_bins, form), stream);
+    int n_groups = plan.n_groups, n_chunks = plan.n_chunks, rounds = plan.rounds, tile_bins = plan.tile_bins;
+    unsigned *queue = plan.rounds > 0 ? eb.queue : nullptr;
+    if (plan.rounds > 0 && !queue) return hipErrorInvalidValue;
+    void *args[] = {&ev, &n_groups, &n_chunks, &rounds, &tile_bins, &queue};
+    return hipLaunchKernel(fn, dim3((unsigned)plan.blocks), dim3(kBlock), args,
+                           tile_lds_bytes(n_det, plan.tile_bins, form, mixed), stream);
 }
 
 hipError_t launch_ragged(const RaggedLaunch &r, hipStream_t stream)
@@ -1134,7 +1230,8 @@ hipError_t launch_ragged(const RaggedLaunch &r, hipStream_t stream)
         int n_items = c.n_items, tile_bins = r.tile_bins;
         unsigned *counter = c.counter;
         void *args[] = {&events, &items, &n_items, &counter, &tile_bins};
-        e = hipLaunchKernel(fn, dim3(c.grid), dim3(kBlock), args, tile_lds_bytes(c.n_det, r.tile_bins, form), stream);
+        e = hipLaunchKernel(fn, dim3(c.grid), dim3(kBlock), args,
+                            tile_lds_bytes(c.n_det, r.tile_bins, form, r.mixed), stream);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(ragged_finalize_kernel, dim3(r.n_groups), dim3(kBlock), 0, stream, r.events, r.groups,

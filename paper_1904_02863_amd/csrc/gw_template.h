@@ -69,4 +69,21 @@ __device__ __forceinline__ PhaseCoef load_coef(const double *__restrict__ rec, i
     return c;
 }
 
+// Every coefficient times k; with k a power of two the phase comes out scaled
+// by k exactly.
+__device__ __forceinline__ PhaseCoef scale_coef(PhaseCoef c, double k)
+{
+    c.c8 *= k;
+    c.c7 *= k;
+    c.c6 *= k;
+    c.c6l *= k;
+    c.c5 *= k;
+    c.c5l *= k;
+    c.c4 *= k;
+    c.c3 *= k;
+    c.c2 *= k;
+    c.c0 *= k;
+    return c;
+}
+
 }  // namespace gw
