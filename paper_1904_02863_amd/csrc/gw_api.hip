@@ -261,7 +261,7 @@ LnlLayout lnl_layout(int64_t n_bins, int n_det, int64_t n_samples, const gw::Til
     l.k_limit = c.take(sizeof(int64_t));
     l.records = c.take(sizeof(double) * gw::record_fields(n_det) * std::max<int64_t>(n_samples, 1));
     l.partials = c.take(sizeof(double2) * (size_t)plan.n_chunks * n_samples * n_det);
-    l.queue = c.take(sizeof(unsigned));
+    l.queue = c.take(sizeof(unsigned) * gw::kQueues);
     l.total = c.offset;
     return l;
 }

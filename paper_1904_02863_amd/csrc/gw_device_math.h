@@ -110,6 +110,18 @@ __device__ __forceinline__ void gw_phasor_table(double y, const double2 *__restr
     im = __builtin_fma(e.y, c, -(e.x * s));
 }
 
+// The table of gw_phasor_table, (cos 2 pi k / N, -sin 2 pi k / N); each
+// kernel that uses it copies it into LDS with gw_stage_phasor_table.
+static __constant__ __align__(16) double gw_phasor_table_src[GW_PHTAB_N][2] = {GW_PHTAB_VALUES};
+
+// Copies the table into tab (LDS, GW_PHTAB_N entries) with the threads of a
+// block of block_threads threads; the caller's next barrier publishes it.
+__device__ __forceinline__ void gw_stage_phasor_table(double2 *tab, int block_threads)
+{
+    for (int i = threadIdx.x; i < GW_PHTAB_N; i += block_threads)
+        tab[i] = make_double2(gw_phasor_table_src[i][0], gw_phasor_table_src[i][1]);
+}
+
 // TaylorF2 coefficients phi[k], phi_log[k] (k = 0..7) at symmetric mass ratio eta.
 __device__ __forceinline__ void gw_pn_coefficients(double eta, double phi[8], double phi_log[8])
 {

@@ -12,6 +12,7 @@ namespace gw {
 
 constexpr int kBlock = 256;          // threads per block of every kernel; one sample per thread
 constexpr int kMaxDet = GW_MAX_DET;
+constexpr int kQueues = 8;      // work queues of the single-event tile kernel, one per XCD
 
 // Per-sample record, stored field-major ([field][n_samples]) so that a block
 // reads it with coalesced loads.  The ten phase coefficients are those of
@@ -153,7 +154,7 @@ struct EventBuffers {
     int prep_blocks;      // ceil(n_bins / kBlock)
     double *sums;         // [kEventSums]
     int64_t *k_limit;     // ISCO end: 1 + the largest K_s of the batch
-    unsigned *queue;      // work-queue counter of the tile kernel (zeroed by the event sums), or null
+    unsigned *queue;      // [kQueues] work-queue counters of the tile kernel (zeroed by the event sums), or null
 };
 
 // ---- launchers (gw_kernels.hip); all enqueue on `stream` and return the launch status ----

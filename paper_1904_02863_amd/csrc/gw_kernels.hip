@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void event_data_kernel(PrepView v, int dire
 }
 
 // Block j: sums[j] = the event-wide sum of quantity j (kPrepPerDet n_det blocks).
-// Also zeroes the tile kernel's work-queue counter when there is one.
+// Also zeroes the tile kernel's work-queue counters when there are any.
 __global__ __launch_bounds__(kBlock) void event_sums_kernel(int n_blocks, int n_det,
                                                              const double *__restrict__ partials,
                                                              double *__restrict__ sums, unsigned *__restrict__ queue)
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void event_sums_kernel(int n_blocks, int n_
     __shared__ double red[kBlock];
     const double t = column_total(n_blocks, kPrepPerDet * n_det, blockIdx.x, partials, red);
     if (threadIdx.x == 0) sums[blockIdx.x] = t;
-    if (queue && blockIdx.x == 0 && threadIdx.x == 0) *queue = 0u;
+    if (queue && blockIdx.x == 0 && threadIdx.x < kQueues) queue[threadIdx.x] = 0u;
 }
 
 // Block d: qoffsets[d][b], the a^2/S total of the blocks before b.
@@ -537,9 +537,6 @@ __host__ __device__ constexpr size_t tile_lds_bytes(int n_det, int tile_bins, in
                                 (form == kFormDirect ? (size_t)n_det * sizeof(double) : 0));
 }
 
-// e^{-2 pi i k / N} for the LDS copy of every FP64 tile block.
-__constant__ __align__(16) double phasor_table_src[GW_PHTAB_N][2] = {GW_PHTAB_VALUES};
-
 // Copies the phasor table into the head of the block's LDS (FP64 path) and
 // returns where the tiles begin.  The tile loop's first barrier publishes it.
 template <bool MIXED>
@@ -547,8 +544,7 @@ __device__ __forceinline__ double *stage_phasor_table(double4 *lds_raw)
 {
     if constexpr (GW_PHASOR_TABLE && !MIXED) {
         double2 *tab = reinterpret_cast<double2 *>(lds_raw);
-        for (int i = threadIdx.x; i < GW_PHTAB_N; i += kBlock)
-            tab[i] = make_double2(phasor_table_src[i][0], phasor_table_src[i][1]);
+        gw_stage_phasor_table(tab, kBlock);
         return reinterpret_cast<double *>(tab + GW_PHTAB_N);
     }
     return reinterpret_cast<double *>(lds_raw);
@@ -751,12 +747,14 @@ __device__ __forceinline__ void chunk_range(int64_t n_eff, int64_t c, int n_chun
 // being about one wave of resident blocks; blocks are dispatched round-robin
 // over the 8 XCDs, and when the grid is a multiple of 8 the linear work index
 // is remapped so that the blocks of one XCD cover consecutive chunks.
-// queue != null: a persistent grid; every block takes the next item from the
-// counter (zero at launch) until the n_groups x n_chunks items are gone, so
-// that blocks the wave arbiter favours, or CUs that clock higher, take more
-// items and every SIMD keeps its waves until the end.  Item i is chunk
-// i / n_groups of group i % n_groups (chunks in index order, all groups of a
-// chunk together).  With the ISCO end (split form) the chunks cover only the
+// queue != null: a persistent grid over kQueues work queues (counters zero
+// at launch), so that blocks the wave arbiter favours, or CUs that clock
+// higher, take more items and every SIMD keeps its waves until the end.
+// Queue x holds the chunks c = x (mod kQueues) in index order, all sample
+// groups of a chunk together; block b starts on queue b mod kQueues, which
+// under round-robin dispatch is the queue of its own XCD, so a chunk's bins
+// are fetched into one L2, and when its queue is empty takes items from the
+// others in turn.  With the ISCO end (split form) the chunks cover only the
 // bins below 1 + max K_s, read from the device, so that no block works on
 // bins every template has left.
 template <int NDET, bool MIXED, int FORM>
@@ -765,10 +763,9 @@ __global__ __launch_bounds__(kBlock) GW_TILE_ATTR void lnl_tile_kernel(EventView
                                                                        unsigned *__restrict__ queue)
 {
     extern __shared__ double4 lds_raw[];
-    __shared__ int next;
+    __shared__ int next_chunk, next_group;
     const int64_t n_eff =
         FORM == kFormSplitIsco ? min(ev.n_bins, max((int64_t)0, *ev.k_limit)) : ev.n_bins;
-    const int n_items = n_groups * n_chunks;
     double *const tiles = stage_phasor_table<MIXED>(lds_raw);
     if (queue == nullptr) {
         const unsigned nb = gridDim.x, b = blockIdx.x;
@@ -779,16 +776,32 @@ __global__ __launch_bounds__(kBlock) GW_TILE_ATTR void lnl_tile_kernel(EventView
                                       k_end, tile_bins, tiles);
         return;
     }
+    const unsigned home = blockIdx.x % kQueues;
+    unsigned visited = 0;                // queues found empty (thread 0)
     for (;;) {
-        __syncthreads();                 // every thread has read `next` and left the LDS tiles
-        if (threadIdx.x == 0) next = (int)atomicAdd(queue, 1u);
+        __syncthreads();                 // every thread has read the item and left the LDS tiles
+        if (threadIdx.x == 0) {
+            int chunk = -1, group = 0;
+            while (visited < kQueues) {
+                const unsigned x = (home + visited) % kQueues;
+                const int n_x = x < (unsigned)n_chunks ? n_groups * ((n_chunks - (int)x + kQueues - 1) / kQueues) : 0;
+                const int k = (int)atomicAdd(queue + x, 1u);
+                if (k < n_x) {
+                    chunk = (int)x + kQueues * (k / n_groups);
+                    group = k % n_groups;
+                    break;
+                }
+                ++visited;
+            }
+            next_chunk = chunk;
+            next_group = group;
+        }
         __syncthreads();
-        const int it = next;
-        if (it >= n_items) break;
-        const int64_t chunk = it / n_groups;
+        const int chunk = next_chunk;
+        if (chunk < 0) break;
         int64_t k_begin, k_end;
         chunk_range(n_eff, chunk, n_chunks, rounds, k_begin, k_end);
-        tile_chunk<NDET, MIXED, FORM>(ev, it % n_groups, chunk, k_begin, k_end, tile_bins, tiles);
+        tile_chunk<NDET, MIXED, FORM>(ev, next_group, chunk, k_begin, k_end, tile_bins, tiles);
     }
 }
 

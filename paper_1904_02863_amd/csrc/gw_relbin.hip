@@ -210,10 +210,12 @@ __global__ __launch_bounds__(kBlock) void totals_kernel(int64_t n_rb, const doub
 // MIXED: the phase difference and its reduction to a fractional turn stay
 // FP64, the phasor comes from the FP32 hardware sine and cosine (inputs in
 // turns), and the ratio and every sum stay FP64.
+// FP64: the phase comes in scaled by GW_PHTAB_N (coefficients and delay
+// differences scaled at load) and the phasor from the LDS table tab.
 template <int NDET, bool MIXED>
 __device__ __forceinline__ void edge_ratio(const PhaseCoef &c, const RbEdge &e, const double (&qr)[NDET],
                                            const double (&qi)[NDET], const double (&dl)[NDET], double (&rr)[NDET],
-                                           double (&ri)[NDET])
+                                           double (&ri)[NDET], const double2 *tab)
 {
     const double dphi = turns_phase(c, e.t1);
 #pragma unroll
@@ -225,7 +227,7 @@ __device__ __forceinline__ void edge_ratio(const PhaseCoef &c, const RbEdge &e, 
             er = (double)__builtin_amdgcn_cosf(r);
             ei = -(double)__builtin_amdgcn_sinf(r);
         } else {
-            gw_phasor_turns(x, er, ei);
+            gw_phasor_table(x, tab, er, ei);
         }
         rr[d] = qr[d] * er - qi[d] * ei;
         ri[d] = qr[d] * ei + qi[d] * er;
@@ -244,6 +246,11 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
     const int64_t s = group * kBlock + threadIdx.x;
     const int64_t sr = s < n_samples ? s : n_samples - 1;
     const int64_t b0 = n_rb * chunk / n_chunks, b1 = n_rb * (chunk + 1) / n_chunks;
+    __shared__ double2 tab[MIXED ? 1 : GW_PHTAB_N];
+    if constexpr (!MIXED) {
+        gw_stage_phasor_table(tab, kBlock);
+        __syncthreads();
+    }
 
     PhaseCoef c = load_coef(rec, n_samples, sr);
     const PhaseCoef c0 = load_coef(fid, 1, 0);
@@ -257,6 +264,9 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
     c.c3 -= c0.c3;
     c.c2 -= c0.c2;
     c.c0 -= c0.c0;
+    // FP64: phase in units of 1/N turn for the table phasor (exact: N = 2^10)
+    const double scale = MIXED ? 1.0 : (double)GW_PHTAB_N;
+    if constexpr (!MIXED) c = scale_coef(c, scale);
     double qr[NDET], qi[NDET], dl[NDET], rr[NDET], ri[NDET], nr[NDET], ni[NDET], acc[NDET];
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
@@ -268,10 +278,10 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
         const double inv = 1.0 / (p0r * p0r + p0i * p0i);
         qr[d] = (pr * p0r + pi * p0i) * inv;     // P / P0
         qi[d] = (pi * p0r - pr * p0i) * inv;
-        dl[d] = delta - fid[kRecDet + kRecFieldsPerDet * d + 2];   // zero for detector 0
+        dl[d] = (delta - fid[kRecDet + kRecFieldsPerDet * d + 2]) * scale;   // zero for detector 0
     }
     // first edge: the lower side of bin b0 only
-    edge_ratio<NDET, MIXED>(c, edges[b0], qr, qi, dl, rr, ri);
+    edge_ratio<NDET, MIXED>(c, edges[b0], qr, qi, dl, rr, ri, tab);
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
         const RbEnds k = ends[b0 * NDET + d];
@@ -282,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
     // edges inside the chunk: both bins that meet there
 #pragma unroll 2
     for (int64_t e = b0 + 1; e < b1; ++e) {
-        edge_ratio<NDET, MIXED>(c, edges[e], qr, qi, dl, nr, ni);
+        edge_ratio<NDET, MIXED>(c, edges[e], qr, qi, dl, nr, ni, tab);
 #pragma unroll
         for (int d = 0; d < NDET; ++d) {
             const RbCoef k = coef[e * NDET + d];
@@ -297,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
         }
     }
     // last edge: the upper side of bin b1 - 1 only
-    edge_ratio<NDET, MIXED>(c, edges[b1], qr, qi, dl, nr, ni);
+    edge_ratio<NDET, MIXED>(c, edges[b1], qr, qi, dl, nr, ni, tab);
     double total = 0.0;
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
