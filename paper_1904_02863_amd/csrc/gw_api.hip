@@ -187,7 +187,7 @@ int check_dets(int n_det, const gw_detector *dets, int n_param, gw::DetGeom *geo
 }
 
 #ifndef GW_TILE_LDS_BUDGET
-#define GW_TILE_LDS_BUDGET (56 * 1024)
+#define GW_TILE_LDS_BUDGET (72 * 1024)
 #endif
 // Work distribution of the single-event tile kernel: 0, one block per (group,
 // chunk) item in one wave of resident blocks; R >= 1, a persistent grid over
@@ -598,7 +598,7 @@ int ragged_run(gw_workspace *ws, int n_events, const gw_event *events, const std
     if (it == ws->ragged_tuning.end()) {
         float best = 0.0f;
         for (int tb : kTuneTiles) {
-            if (gw::lnl_tile_lds_bytes(max_det, tb, form, mixed) > 64 * 1024) continue;
+            if (gw::lnl_tile_lds_bytes(max_det, tb, form, mixed) > 80 * 1024) continue;
             for (int64_t cb : kTuneChunks) {
                 if (int rc = ragged_materialise(ws, na, ev, active_geoms, data, psd, theta, n_param, lnl, mixed, flags,
                                                 tb, cb, ws->capture_stream, &plan))

@@ -10,9 +10,9 @@
 //   which the vector ALU issues at full rate.  The polynomials carry the
 //   double angle's factors (sqrt(2) sin, -sqrt(2) cos), so the double angle
 //   costs one FMA and one multiply.  Coefficients come from gen_sincos.py.
-// * gw_phasor_table: the same phasor from a table of N = 1024 roots of unity
-//   (each rounded once) and degree-5/4 polynomials of the remainder, at most
-//   half a table step (15 operations instead of 20, and more accurate); the
+// * gw_phasor_table: the same phasor from a table of N = 2048 roots of unity
+//   (each rounded once) and degree-3/4 polynomials of the remainder, at most
+//   half a table step (14 operations instead of 20, and more accurate); the
 //   phase comes in scaled by N and the hot loops keep the table in LDS.
 // * gw_pn_coefficients: the non-spinning TaylorF2 phase coefficients through
 //   3.5PN, Buonanno, Iyer, Ochsner, Pan & Sathyaprakash, PRD 80, 084043 (2009),
@@ -95,8 +95,8 @@ __device__ __forceinline__ void gw_phasor_turns(double x, double &re, double &im
 // LDS) and short polynomials of the remainder: j = rint(y) by the
 // round-to-integer of adding 1.5 * 2^52 (|y| < 2^51), r = y - j exactly
 // (|r| <= 1/2), e^{-2 pi i x} = tab[j mod N] (cos(2 pi r / N) - i sin(2 pi r / N));
-// j mod N comes from the low bits of the sum.  15 operations; worst absolute
-// error 1.5e-16 (gen_phasor_table.py).
+// j mod N comes from the low bits of the sum.  14 operations; worst absolute
+// error 1.6e-16 (gen_phasor_table.py).
 __device__ __forceinline__ void gw_phasor_table(double y, const double2 *__restrict__ tab, double &re, double &im)
 {
     constexpr double kRound = 6755399441055744.0;       // 1.5 * 2^52
@@ -104,7 +104,7 @@ __device__ __forceinline__ void gw_phasor_table(double y, const double2 *__restr
     const double r = y - (t - kRound);
     const double2 e = tab[__double2loint(t) & (GW_PHTAB_N - 1)];
     const double z = r * r;
-    const double s = r * __builtin_fma(z, __builtin_fma(z, GW_PHTAB_S5, GW_PHTAB_S3), GW_PHTAB_S1);
+    const double s = r * __builtin_fma(z, GW_PHTAB_S3, GW_PHTAB_S1);
     const double c = __builtin_fma(z, __builtin_fma(z, GW_PHTAB_C4, GW_PHTAB_C2), 1.0);
     re = __builtin_fma(e.x, c, e.y * s);
     im = __builtin_fma(e.y, c, -(e.x * s));

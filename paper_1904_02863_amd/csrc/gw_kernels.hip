@@ -27,10 +27,16 @@
 #include "gw_internal.h"
 #include "gw_template.h"
 
-// Tuning of the tile kernel's inner loop: bins per unrolled step, and the
-// number of waves per SIMD the register allocation must leave room for.
+// Tuning of the tile kernel's inner loop: bins per unrolled step (FP64 and
+// mixed paths), and the number of waves per SIMD the register allocation
+// must leave room for.  The FP64 kernels run two blocks per CU (their LDS
+// holds the phasor table), so 8 bins per step fit their registers; the mixed
+// kernels run three, and 4 bins keep them within 168 VGPRs.
 #ifndef GW_TILE_UNROLL
-#define GW_TILE_UNROLL 4
+#define GW_TILE_UNROLL 8
+#endif
+#ifndef GW_TILE_UNROLL_MIXED
+#define GW_TILE_UNROLL_MIXED 4
 #endif
 #ifndef GW_TILE_WAVES_PER_EU
 #define GW_TILE_WAVES_PER_EU 0
@@ -48,7 +54,7 @@
 
 namespace gw {
 
-constexpr int kTileUnroll = GW_TILE_UNROLL;
+constexpr int kTileUnroll = GW_TILE_UNROLL, kTileUnrollMixed = GW_TILE_UNROLL_MIXED;
 
 // ---------------------------------------------------------------- event tables
 __device__ __forceinline__ void bin_tables(double f_low, double df, int64_t k, Tab1 *tab1, Tab2 *tab2)
@@ -583,7 +589,7 @@ __device__ __forceinline__ void tile_chunk(const EventView &ev, int group, int64
 
     PhaseCoef cf = load_coef(rec, n_samples, sr);
 #if GW_PHASOR_TABLE
-    // the table phasor takes the phase in units of 1/N turn (exact: N = 2^10)
+    // the table phasor takes the phase in units of 1/N turn (exact: N is a power of two)
     if constexpr (!MIXED) cf = scale_coef(cf, (double)GW_PHTAB_N);
 #endif
     const int64_t kcut = kMasked ? (int64_t)rec[kRecKcut * n_samples + sr] : n_bins - 1;
@@ -636,7 +642,7 @@ __device__ __forceinline__ void tile_chunk(const EventView &ev, int group, int64
                 si_[d] = p_re[d] * ri + p_im[d] * rr;
             }
         }
-#pragma unroll kTileUnroll
+#pragma unroll(MIXED ? kTileUnrollMixed : kTileUnroll)
         for (int j = 0; j < nk; ++j) {
             const Tab1 tb = lt[j];
             double er, ei;

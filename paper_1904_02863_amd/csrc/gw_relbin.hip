@@ -264,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
     c.c3 -= c0.c3;
     c.c2 -= c0.c2;
     c.c0 -= c0.c0;
-    // FP64: phase in units of 1/N turn for the table phasor (exact: N = 2^10)
+    // FP64: phase in units of 1/N turn for the table phasor (exact: N is a power of two)
     const double scale = MIXED ? 1.0 : (double)GW_PHTAB_N;
     if constexpr (!MIXED) c = scale_coef(c, scale);
     double qr[NDET], qi[NDET], dl[NDET], rr[NDET], ri[NDET], nr[NDET], ni[NDET], acc[NDET];

@@ -37,9 +37,9 @@ def test_table_entries():
         text = fh.read()
     n = int(re.search(r"#define GW_PHTAB_N (\d+)", text).group(1))
     rows = re.findall(r"\{(\S+), (\S+)\}", text)
-    assert len(rows) == n == 1024
+    assert len(rows) == n == 2048
     mp.mp.dps = 40
-    for k in (0, 1, 255, 256, 257, 511, 512, 768, 1000, 1023):
+    for k in (0, 1, 511, 512, 513, 1023, 1024, 1536, 2000, 2047):
         re_k, im_k = float.fromhex(rows[k][0]), float.fromhex(rows[k][1])
         assert re_k == float(mp.cospi(mp.mpf(2 * k) / n))
         assert im_k == float(-mp.sinpi(mp.mpf(2 * k) / n))
