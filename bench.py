@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # summary records their SHA-256 next to the traffic it measured.
 KERNEL_SOURCES = ("paper_1904_02863_amd/csrc/gw_kernels.hip", "paper_1904_02863_amd/csrc/gw_device_math.h",
                   "paper_1904_02863_amd/csrc/gw_internal.h", "paper_1904_02863_amd/csrc/gw_template.h",
-                  "paper_1904_02863_amd/csrc/gw_phasor_table.h", "paper_1904_02863_amd/csrc/gw_api.hip",
+                  "paper_1904_02863_amd/csrc/gw_phasor_table.h", "paper_1904_02863_amd/csrc/gw_plan.h",
                   "paper_1904_02863_amd/csrc/gw_relbin.hip", "paper_1904_02863_amd/build.py")
 PROFILE_SUMMARY = "profiles/lnl_tile_kernel_bbh-3det-128s.md"
 WAVEFORM_PROFILE = "profiles/waveform_kernel_bbh-3det-128s.md"

@@ -347,6 +347,20 @@ int gw_rb_shape(const gw_relbin *rb, int64_t *n_rb, int *n_det);
  *   totals_out  host [2]: <d,d> and sum ln(2 pi S).  Either may be NULL. */
 int gw_rb_summary(const gw_relbin *rb, double *raw_out, double *totals_out);
 
+/* How gw_lnl_batch splits a call of this shape on the workspace's device
+ * (inspection and test support; no device work):
+ *   tile_bins  bins staged in LDS at a time;
+ *   n_chunks   bin chunks per group of 256 samples (partial sums per chunk);
+ *   rounds     0: one block per (sample group, chunk) item, in one wave of
+ *              resident blocks; R >= 1: a persistent grid over one work queue
+ *              per XCD, the chunks in R rounds, each covering half the bins
+ *              the earlier rounds left (the last round the rest).
+ * n_bins >= 1, 1 <= n_det <= GW_MAX_DET, n_samples >= 1, precision and flags
+ * as for gw_lnl_batch; any output pointer may be NULL.  Returns GW_OK,
+ * GW_EINVAL or GW_EDEVICE. */
+int gw_lnl_plan(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples, int precision, unsigned flags,
+                int *tile_bins, int *n_chunks, int *rounds);
+
 /* Tile shape the last gw_lnl_ragged call used: bins staged in LDS per tile and
  * bins per work item.  The first call for a new size class times every
  * candidate shape once (several passes, results overwritten) and keeps the

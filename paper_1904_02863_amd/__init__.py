@@ -32,7 +32,7 @@ FLAG_ADD_NORM = 4
 # Every symbol include/gwlnl.h declares.
 EXPORTED = ("gw_workspace_create", "gw_workspace_destroy", "gw_workspace_reserve", "gw_workspace_bytes",
             "gw_workspace_set_timing", "gw_workspace_kernel_time", "gw_waveform_batch", "gw_lnl_batch",
-            "gw_lnl_ragged", "gw_ragged_tuning", "gw_pop_lnl", "gw_pop_prepare", "gw_pop_lnl_prepared",
+            "gw_lnl_ragged", "gw_lnl_plan", "gw_ragged_tuning", "gw_pop_lnl", "gw_pop_prepare", "gw_pop_lnl_prepared",
             "gw_rb_edges", "gw_rb_create", "gw_rb_destroy", "gw_rb_lnl", "gw_rb_shape", "gw_rb_summary", "gw_last_error", "gw_version",
             "gw_philox_raw", "gw_philox_fill", "gw_philox_chain_normals", "gw_mcmc_to_theta", "gw_mcmc_rw_propose",
             "gw_mcmc_accept", "gw_mcmc_update_mode", "gw_flow_create", "gw_flow_destroy", "gw_flow_num_params",
@@ -83,6 +83,8 @@ def load_library() -> ctypes.CDLL:
                                      i64, vp, i32, u32, vp]
         lib.gw_lnl_ragged.argtypes = [vp, i32, ctypes.POINTER(GwEvent), vp, vp, vp, i32, vp, i32, u32, vp]
         lib.gw_ragged_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        lib.gw_lnl_plan.argtypes = [vp, i64, i32, i64, i32, u32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                    ctypes.POINTER(i32)]
         lib.gw_pop_lnl.argtypes = [vp, i64, i64, vp, i64, vp, vp, vp]
         lib.gw_pop_prepare.argtypes = [i64, i64, vp, vp, vp]
         lib.gw_pop_lnl_prepared.argtypes = [vp, i64, i64, vp, i64, vp, vp, vp]
@@ -155,6 +157,14 @@ class Workspace:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         _check(load_library().gw_workspace_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def lnl_plan(self, n_bins: int, n_det: int, n_samples: int, precision: str = "fp64", flags: int = 0) -> dict:
+        """How gw_lnl_batch splits a call of this shape: LDS tile bins, chunks
+        per sample group and work-queue rounds (0: one block per item)."""
+        t, c, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(load_library().gw_lnl_plan(self._h, n_bins, n_det, n_samples, PRECISIONS[precision], int(flags),
+                                          ctypes.byref(t), ctypes.byref(c), ctypes.byref(r)))
+        return {"tile_bins": t.value, "n_chunks": c.value, "rounds": r.value}
 
     def ragged_tuning(self) -> tuple[int, int]:
         """(LDS tile bins, bins per work item) of the last ragged call."""

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "gw_internal.h"
+#include "gw_plan.h"
 #include "gwlnl.h"
 
 struct gw_workspace {
@@ -186,53 +187,12 @@ int check_dets(int n_det, const gw_detector *dets, int n_param, gw::DetGeom *geo
     return GW_OK;
 }
 
-#ifndef GW_TILE_LDS_BUDGET
-#define GW_TILE_LDS_BUDGET (72 * 1024)
-#endif
-// Work distribution of the single-event tile kernel: 0, one block per (group,
-// chunk) item in one wave of resident blocks; R >= 1, a persistent grid over
-// a work queue of R rounds of chunks, each round one item per resident block
-// and (R > 1) each round covering half the bins the earlier rounds left.  The
-// queue evens out what a static split leaves uneven: the wave arbiter favours
-// the oldest wave of a SIMD, so co-resident blocks of equal work finish far
-// apart, and a SIMD left with one wave issues at about half rate.
-#ifndef GW_TILE_ROUNDS
-#define GW_TILE_ROUNDS 6
-#endif
-
-int tile_bins_for(int n_det, int form, bool mixed)
-{
-    const size_t budget = GW_TILE_LDS_BUDGET;   // bytes of LDS per block: several blocks per CU fit in 160 KB
-    int t = 2048;
-    while (t > 64 && gw::lnl_tile_lds_bytes(n_det, t, form, mixed) > budget) t /= 2;
-    return t;
-}
-
 gw::TilePlan plan_tiles(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples, bool mixed, int form)
 {
-    gw::TilePlan p;
-    p.tile_bins = tile_bins_for(n_det, form, mixed);
-    p.n_groups = (int)((n_samples + gw::kBlock - 1) / gw::kBlock);
+    const int tile_bins = gw::tile_bins_for(n_det, form, mixed);
     int &occ = ws->blocks_per_cu[form][mixed ? 1 : 0][n_det];
-    if (occ == 0) occ = gw::lnl_tile_blocks_per_cu(n_det, p.tile_bins, mixed, form);
-    const int64_t resident = (int64_t)ws->n_cu * occ;
-    int64_t chunks = (resident + p.n_groups - 1) / p.n_groups;
-    const int64_t max_chunks = std::max<int64_t>(1, n_bins / 64);     // at least 64 bins per chunk
-    chunks = std::max<int64_t>(1, std::min(chunks, max_chunks));
-    p.chunk_bins = (n_bins + chunks - 1) / chunks;
-    p.n_chunks = (int)((n_bins + p.chunk_bins - 1) / p.chunk_bins);
-    p.rounds = 0;
-    p.blocks = p.n_groups * p.n_chunks;
-    const int rounds = GW_TILE_ROUNDS;
-    // the ISCO end leaves the device-side band unknown here and usually short:
-    // one item per resident block
-    if (rounds >= 1 && form != gw::kFormSplitIsco && (int64_t)p.n_chunks * rounds * 64 <= n_bins) {
-        p.rounds = rounds;
-        p.n_chunks *= rounds;
-        p.chunk_bins = (n_bins + p.n_chunks - 1) / p.n_chunks;
-        p.blocks = (int)std::min<int64_t>((int64_t)p.n_groups * p.n_chunks, resident);
-    }
-    return p;
+    if (occ == 0) occ = gw::lnl_tile_blocks_per_cu(n_det, tile_bins, mixed, form);
+    return gw::plan_single_event(n_bins, n_samples, form, tile_bins, (int64_t)ws->n_cu * occ);
 }
 
 // Workspace sections of one event.  The direct-form tables and the prefix
@@ -1122,6 +1082,22 @@ int gw_rb_lnl(gw_workspace *ws, const gw_relbin *rb, const double *theta, int64_
     if ((e = gw::rb::launch_finalize(n_samples, n_chunks, part, rec, rb->totals, (rb->flags & GW_FLAG_ADD_NORM) != 0,
                                      lnl_out, stream)) != hipSuccess)
         return hip_fail(e, "relative-binning finalize");
+    return GW_OK;
+}
+
+int gw_lnl_plan(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples, int precision, unsigned flags,
+                int *tile_bins, int *n_chunks, int *rounds)
+{
+    if (!ws) return fail(GW_EINVAL, "workspace is NULL");
+    if (n_bins < 1 || n_det < 1 || n_det > gw::kMaxDet || n_samples < 1) return fail(GW_EINVAL, "bad plan sizes");
+    if (precision != GW_PREC_FP64 && precision != GW_PREC_MIXED) return fail(GW_EINVAL, "unknown precision");
+    if (flags & ~kLnlFlags) return fail(GW_EINVAL, "unknown flag bits");
+    DeviceGuard g(ws->device);
+    if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
+    const gw::TilePlan p = plan_tiles(ws, n_bins, n_det, n_samples, precision == GW_PREC_MIXED, gw::tile_form(flags));
+    if (tile_bins) *tile_bins = p.tile_bins;
+    if (n_chunks) *n_chunks = p.n_chunks;
+    if (rounds) *rounds = p.rounds;
     return GW_OK;
 }
 
