@@ -102,3 +102,39 @@ def test_plan_rules(gw):
         ws.lnl_plan(0, 3, 4096)
     with pytest.raises(gw.GwError):
         ws.lnl_plan(1000, 3, 10, flags=1 << 20)
+
+
+def test_queue_launch_replays_from_a_graph(gw):
+    """gw_lnl_batch captured in a graph: the queue counters are zeroed by a
+    kernel of the call itself, so every replay starts from empty queues.
+    Three replays, with eager calls on another workspace and host
+    synchronisations between them, each equal the eager result bit for bit."""
+    import torch
+    w, theta, data = _event(31, 3, 40_001, 4000, False)
+    dev = torch.device("cuda", 0)
+    d = torch.from_numpy(np.ascontiguousarray(data)).to(dev)
+    s = torch.from_numpy(w.psd).to(dev)
+    th = torch.from_numpy(np.ascontiguousarray(theta)).to(dev)
+    ws = gw.Workspace(0)
+    assert ws.lnl_plan(40_001, 3, 4000)["rounds"] > 0
+    eager = gw.lnl_batch(w.grid, w.tensors, w.vertices, d, s, th, workspace=ws).clone()
+    out = torch.empty_like(eager)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        gw.lnl_batch(w.grid, w.tensors, w.vertices, d, s, th, workspace=ws, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gw.lnl_batch(w.grid, w.tensors, w.vertices, d, s, th, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    other = gw.Workspace(0)
+    th2 = th.flip(0).contiguous()
+    for rep in range(3):
+        out.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), eager.cpu().numpy(), err_msg=f"replay {rep}")
+        gw.lnl_batch(w.grid, w.tensors, w.vertices, d, s, th2, workspace=other)
+        torch.cuda.synchronize()
