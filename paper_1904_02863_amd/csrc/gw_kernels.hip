@@ -571,8 +571,9 @@ template <int NDET, bool MIXED, int FORM>
 __device__ __forceinline__ void tile_chunk(const EventView &ev, int group, int64_t chunk, int64_t k_begin,
                                            int64_t k_end, int tile_bins, double *lds)
 {
-    // the phasor table sits just below the tiles (FP64 path)
-    const double2 *ptab = reinterpret_cast<const double2 *>(lds) - GW_PHTAB_N;
+    // the phasor table sits just below the tiles (FP64 path; the mixed path has none)
+    const double2 *ptab =
+        (GW_PHASOR_TABLE && !MIXED) ? reinterpret_cast<const double2 *>(lds) - GW_PHTAB_N : nullptr;
     constexpr bool kDirect = FORM == kFormDirect;
     constexpr bool kMasked = FORM != kFormSplit;
     const int64_t n_bins = ev.n_bins, n_samples = ev.n_samples;
