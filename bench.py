@@ -654,7 +654,7 @@ def main():
                          "(reference dispatch for scaling hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(samples shard trivially across GPUs; see the design notes).", file=sys.stderr)
         sys.exit(2)
 

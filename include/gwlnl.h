@@ -104,7 +104,7 @@ enum {
     GW_EINVAL = -1,        /* invalid argument */
     GW_ENOMEM = -2,        /* device allocation failed */
     GW_EDEVICE = -3,       /* a HIP runtime call failed */
-    GW_EUNSUPPORTED = -4   /* valid request this build does not implement */
+    GW_EUNSUPPORTED = -4   /* valid request the library does not implement */
 };
 
 enum {
