@@ -31,7 +31,10 @@ namespace gw {
 namespace pop {
 
 constexpr int kThreads = 256;
-constexpr int kPerThread = 4;
+#ifndef GW_POP_PER_THREAD
+#define GW_POP_PER_THREAD 4
+#endif
+constexpr int kPerThread = GW_POP_PER_THREAD;     // samples per thread, held in registers
 constexpr int kPerBlock = kThreads * kPerThread;   // samples of one event per block
 constexpr int kWaves = kThreads / 64;
 static_assert(kThreads == 256, "the weights kernel fills its 256-entry exp table one entry per thread");
