@@ -25,6 +25,7 @@
 
 #include "gw_device_math.h"
 #include "gw_internal.h"
+#include "gw_plan.h"
 #include "gw_template.h"
 
 // Tuning of the tile kernel's inner loop: bins per unrolled step (FP64 and
@@ -728,28 +729,6 @@ __device__ __forceinline__ void tile_chunk(const EventView &ev, int group, int64
     }
 }
 
-// Bins [k_begin, k_end) of chunk c among n_chunks chunks of n_eff bins.
-// rounds <= 1: equal chunks.  rounds R > 1: the chunks come in R rounds of
-// n_chunks / R equal chunks each; round r < R - 1 covers the next half of the
-// bins still left (n_eff/2, n_eff/4, ...) and the last round the rest, so that
-// a queue handing out chunks in index order ends on small ones.
-__device__ __forceinline__ void chunk_range(int64_t n_eff, int64_t c, int n_chunks, int rounds, int64_t &k_begin,
-                                            int64_t &k_end)
-{
-    if (rounds <= 1) {
-        const int64_t cb = max((int64_t)1, (n_eff + n_chunks - 1) / n_chunks);
-        k_begin = min(n_eff, c * cb);
-        k_end = min(n_eff, k_begin + cb);
-        return;
-    }
-    const int64_t per = n_chunks / rounds;
-    const int64_t r = c / per, j = c % per;
-    const int64_t rb = n_eff - (n_eff >> r);
-    const int64_t re = (r == rounds - 1) ? n_eff : n_eff - (n_eff >> (r + 1));
-    k_begin = rb + (re - rb) * j / per;
-    k_end = rb + (re - rb) * (j + 1) / per;
-}
-
 // One event.  queue == null: one block per work item (chunk, group), the grid
 // being about one wave of resident blocks; blocks are dispatched round-robin
 // over the 8 XCDs, and when the grid is a multiple of 8 the linear work index
@@ -791,13 +770,8 @@ __global__ __launch_bounds__(kBlock) GW_TILE_ATTR void lnl_tile_kernel(EventView
             int chunk = -1, group = 0;
             while (visited < kQueues) {
                 const unsigned x = (home + visited) % kQueues;
-                const int n_x = x < (unsigned)n_chunks ? n_groups * ((n_chunks - (int)x + kQueues - 1) / kQueues) : 0;
                 const int k = (int)atomicAdd(queue + x, 1u);
-                if (k < n_x) {
-                    chunk = (int)x + kQueues * (k / n_groups);
-                    group = k % n_groups;
-                    break;
-                }
+                if (queue_item((int)x, k, n_groups, n_chunks, chunk, group)) break;
                 ++visited;
             }
             next_chunk = chunk;

@@ -27,6 +27,41 @@
 
 namespace gw {
 
+// Bins [k_begin, k_end) of chunk c among n_chunks chunks of n_eff bins.
+// rounds <= 1: equal chunks.  rounds R > 1: the chunks come in R rounds of
+// n_chunks / R equal chunks each; round r < R - 1 covers the next half of the
+// bins still left (n_eff/2, n_eff/4, ...) and the last round the rest, so that
+// a queue handing out chunks in index order ends on small ones.
+__host__ __device__ inline void chunk_range(int64_t n_eff, int64_t c, int n_chunks, int rounds, int64_t &k_begin,
+                                            int64_t &k_end)
+{
+    if (rounds <= 1) {
+        int64_t cb = (n_eff + n_chunks - 1) / n_chunks;
+        cb = cb > 1 ? cb : 1;
+        k_begin = c * cb < n_eff ? c * cb : n_eff;
+        k_end = k_begin + cb < n_eff ? k_begin + cb : n_eff;
+        return;
+    }
+    const int64_t per = n_chunks / rounds;
+    const int64_t r = c / per, j = c % per;
+    const int64_t rb = n_eff - (n_eff >> r);
+    const int64_t re = (r == rounds - 1) ? n_eff : n_eff - (n_eff >> (r + 1));
+    k_begin = rb + (re - rb) * j / per;
+    k_end = rb + (re - rb) * (j + 1) / per;
+}
+
+// Item k of work queue x (kQueues queues): queue x holds the chunks
+// c = x (mod kQueues) in index order, all n_groups sample groups of a chunk
+// together.  False once the queue is exhausted.
+__host__ __device__ inline bool queue_item(int x, int k, int n_groups, int n_chunks, int &chunk, int &group)
+{
+    const int n_x = x < n_chunks ? n_groups * ((n_chunks - x + kQueues - 1) / kQueues) : 0;
+    if (k >= n_x) return false;
+    chunk = x + kQueues * (k / n_groups);
+    group = k % n_groups;
+    return true;
+}
+
 inline int tile_bins_for(int n_det, int form, bool mixed)
 {
     int t = 2048;
