@@ -220,7 +220,7 @@ LnlLayout lnl_layout(int64_t n_bins, int n_det, int64_t n_samples, const gw::Til
     l.event_sums = c.take(sizeof(double) * gw::kEventSums);
     l.k_limit = c.take(sizeof(int64_t));
     l.records = c.take(sizeof(double) * gw::record_fields(n_det) * std::max<int64_t>(n_samples, 1));
-    l.partials = c.take(sizeof(double2) * (size_t)plan.n_chunks * n_samples * n_det);
+    l.partials = c.take(sizeof(double) * (size_t)plan.n_chunks * n_samples);   // one total per chunk and sample
     l.queue = c.take(sizeof(unsigned) * gw::kQueues);
     l.total = c.offset;
     return l;
@@ -375,7 +375,7 @@ RaggedPlan ragged_plan(gw_workspace *ws, int n_events, const gw_event *events, c
                            : nullptr;
         re.rec = reinterpret_cast<double *>(base + c.take(sizeof(double) * gw::record_fields(ev.n_det) *
                                                            std::max<int64_t>(s, 1)));
-        re.partials = reinterpret_cast<double2 *>(base + c.take(sizeof(double2) * re.n_chunks * s * ev.n_det));
+        re.partials = reinterpret_cast<double2 *>(base + c.take(sizeof(double) * re.n_chunks * s));
         re.prep = reinterpret_cast<double *>(base + c.take(sizeof(double) * gw::kPrepPerDet * ev.n_det *
                                                             re.prep_blocks));
         re.sums = reinterpret_cast<double *>(base + c.take(sizeof(double) * gw::kEventSums));

@@ -85,7 +85,7 @@ struct RaggedEvent {
     double *qprefix;      // ISCO end: prefix sums of a^2 / S per detector
     double *qoffsets;     // ISCO end: a^2 / S totals of the preceding 256-bin blocks [n_det][prep_blocks]
     double *rec;
-    double2 *partials;
+    double2 *partials;    // double [chunk][n_samples]: the chunk totals the finalize adds
     double *prep;
     double *sums;
 };

@@ -527,7 +527,7 @@ struct EventView {
     const double *vdir;        // direct form: a^2 / S [n_det][n_bins]
     const double *rec;
     const int64_t *k_limit;    // split form with the ISCO end: 1 + max K_s (device)
-    double2 *partials;         // split: [chunk][n_samples][NDET]; direct: double [chunk][n_samples]
+    double2 *partials;         // double [chunk][n_samples]: sum_det Re(P_det Z_det) (split), residual sum (direct)
 };
 
 // LDS layout of a tile: tab1 [tile], then per detector D (split) or d/a
@@ -719,13 +719,18 @@ __device__ __forceinline__ void tile_chunk(const EventView &ev, int group, int64
         }
     }
     if (s < n_samples) {
-        if (kDirect) {
-            reinterpret_cast<double *>(ev.partials)[chunk * n_samples + s] = acc;
-        } else {
+        if (!kDirect) {
+            // the chunk's share of sum_det Re(P_det Z_det), linear in Z
+            acc = 0.0;
 #pragma unroll
-            for (int d = 0; d < NDET; ++d)
-                ev.partials[(chunk * n_samples + s) * NDET + d] = make_double2(zr[d], zi[d]);
+            for (int d = 0; d < NDET; ++d) {
+                const double pr = rec[(kRecDet + kRecFieldsPerDet * d) * n_samples + s];
+                const double pi = rec[(kRecDet + kRecFieldsPerDet * d + 1) * n_samples + s];
+                acc = __builtin_fma(pr, zr[d], acc);
+                acc = __builtin_fma(-pi, zi[d], acc);
+            }
         }
+        reinterpret_cast<double *>(ev.partials)[chunk * n_samples + s] = acc;
     }
 }
 
@@ -831,9 +836,8 @@ __global__ __launch_bounds__(kBlock) GW_TILE_ATTR void lnl_ragged_kernel(const R
 // times the residual sum.  GW_FLAG_ADD_NORM subtracts sum ln(2 pi S).
 // sums: the event-wide totals of |d|^2/S, a^2/S, ln(2 pi S) per detector.
 __device__ __forceinline__ double assemble_row(int64_t s, int64_t n_samples, int n_det, int64_t n_bins, double df,
-                                               unsigned flags, const double *zr, const double *zi, double resid,
-                                               const double *__restrict__ rec, const double *__restrict__ sums,
-                                               const double *__restrict__ qprefix)
+                                               unsigned flags, double total, const double *__restrict__ rec,
+                                               const double *__restrict__ sums, const double *__restrict__ qprefix)
 {
     double dd = 0.0, norm = 0.0;
     for (int d = 0; d < n_det; ++d) {
@@ -843,17 +847,17 @@ __device__ __forceinline__ double assemble_row(int64_t s, int64_t n_samples, int
     dd *= 4.0 * df;
     double out;
     if (flags & GW_FLAG_DIRECT) {
-        out = -2.0 * df * resid;
+        out = -2.0 * df * total;
     } else {
         const bool isco = (flags & GW_FLAG_TERM_ISCO) != 0;
         const int64_t kcut = (int64_t)rec[kRecKcut * n_samples + s];
-        double acc = -0.5 * dd;
+        double acc = -0.5 * dd + total;
         for (int d = 0; d < n_det; ++d) {
             const double pr = rec[(kRecDet + kRecFieldsPerDet * d) * n_samples + s];
             const double pi = rec[(kRecDet + kRecFieldsPerDet * d + 1) * n_samples + s];
             double q = 4.0 * df * sums[kPrepPerDet * d + 1];
             if (isco) q = kcut >= 0 ? 4.0 * df * qprefix[(int64_t)d * n_bins + kcut] : 0.0;
-            acc += (pr * zr[d] - pi * zi[d]) - 0.5 * (pr * pr + pi * pi) * q;
+            acc -= 0.5 * (pr * pr + pi * pi) * q;
         }
         out = acc;
     }
@@ -870,28 +874,15 @@ __device__ __forceinline__ double finalize_row(int64_t s, int64_t n_samples, int
                                                const double2 *__restrict__ partials, const double *__restrict__ rec,
                                                const double *__restrict__ sums, const double *__restrict__ qprefix)
 {
-    double zr[kMaxDet], zi[kMaxDet], resid = 0.0;
-    if (flags & GW_FLAG_DIRECT) {
-        const double *pd = reinterpret_cast<const double *>(partials);
-        for (int c = 0; c < n_chunks; ++c) resid += pd[(int64_t)c * n_samples + s];
-    } else {
-        for (int d = 0; d < n_det; ++d) {
-            double r = 0.0, i = 0.0;
-            for (int c = 0; c < n_chunks; ++c) {
-                const double2 z = partials[((int64_t)c * n_samples + s) * n_det + d];
-                r += z.x;
-                i += z.y;
-            }
-            zr[d] = r;
-            zi[d] = i;
-        }
-    }
-    return assemble_row(s, n_samples, n_det, n_bins, df, flags, zr, zi, resid, rec, sums, qprefix);
+    const double *pd = reinterpret_cast<const double *>(partials);
+    double total = 0.0;
+    for (int c = 0; c < n_chunks; ++c) total += pd[(int64_t)c * n_samples + s];
+    return assemble_row(s, n_samples, n_det, n_bins, df, flags, total, rec, sums, qprefix);
 }
 
-// One event: 16 rows per block, 16 threads per row; thread part p sums chunks
-// p, p + 16, ... in order (every detector of a chunk in one contiguous read),
-// then the parts are added in order 0..15.
+// One event: 16 rows per block, 16 threads per row; thread part p sums the
+// chunk totals p, p + 16, ... in order, then the parts are added in order
+// 0..15.
 constexpr int kFinRows = 16, kFinParts = kBlock / kFinRows;
 
 __global__ __launch_bounds__(kBlock) void lnl_finalize_kernel(int64_t n_samples, int n_det, int n_chunks,
@@ -902,56 +893,20 @@ __global__ __launch_bounds__(kBlock) void lnl_finalize_kernel(int64_t n_samples,
                                                                const double *__restrict__ qprefix,
                                                                double *__restrict__ lnl)
 {
-    __shared__ double red[kFinParts][kFinRows][2 * kMaxDet];
+    __shared__ double red[kFinParts][kFinRows];
     const int r = threadIdx.x % kFinRows, part = threadIdx.x / kFinRows;
     const int64_t s = (int64_t)blockIdx.x * kFinRows + r;
-    const bool direct = (flags & GW_FLAG_DIRECT) != 0;
     if (s < n_samples) {
-        if (direct) {
-            const double *pd = reinterpret_cast<const double *>(partials);
-            double acc = 0.0;
-            for (int c = part; c < n_chunks; c += kFinParts) acc += pd[(int64_t)c * n_samples + s];
-            red[part][r][0] = acc;
-        } else {
-            double zr[kMaxDet], zi[kMaxDet];
-#pragma unroll
-            for (int d = 0; d < kMaxDet; ++d) { zr[d] = 0.0; zi[d] = 0.0; }
-            for (int c = part; c < n_chunks; c += kFinParts) {
-                const double2 *z = partials + ((int64_t)c * n_samples + s) * n_det;
-#pragma unroll
-                for (int d = 0; d < kMaxDet; ++d) {
-                    if (d < n_det) {
-                        zr[d] += z[d].x;
-                        zi[d] += z[d].y;
-                    }
-                }
-            }
-#pragma unroll
-            for (int d = 0; d < kMaxDet; ++d) {
-                if (d < n_det) {
-                    red[part][r][2 * d] = zr[d];
-                    red[part][r][2 * d + 1] = zi[d];
-                }
-            }
-        }
+        const double *pd = reinterpret_cast<const double *>(partials);
+        double acc = 0.0;
+        for (int c = part; c < n_chunks; c += kFinParts) acc += pd[(int64_t)c * n_samples + s];
+        red[part][r] = acc;
     }
     __syncthreads();
     if (part != 0 || s >= n_samples) return;
-    double zr[kMaxDet], zi[kMaxDet], resid = 0.0;
-    if (direct) {
-        for (int p = 0; p < kFinParts; ++p) resid += red[p][r][0];
-    } else {
-        for (int d = 0; d < n_det; ++d) {
-            double a = 0.0, b = 0.0;
-            for (int p = 0; p < kFinParts; ++p) {
-                a += red[p][r][2 * d];
-                b += red[p][r][2 * d + 1];
-            }
-            zr[d] = a;
-            zi[d] = b;
-        }
-    }
-    lnl[s] = assemble_row(s, n_samples, n_det, n_bins, df, flags, zr, zi, resid, rec, sums, qprefix);
+    double total = 0.0;
+    for (int p = 0; p < kFinParts; ++p) total += red[p][r];
+    lnl[s] = assemble_row(s, n_samples, n_det, n_bins, df, flags, total, rec, sums, qprefix);
 }
 
 // Ragged batch: block (event, group) finalizes the group's rows.
