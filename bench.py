@@ -51,7 +51,7 @@ def flops_per_pair(n_det: int, mixed: bool = False, direct: bool = False) -> int
     e^{-2 pi i x} from the phase in turns at a fixed tally of 34 (the count of
     the polynomial phasor gw_phasor_turns, 15 FMA + 3 multiplies + 1 add,
     whichever implementation runs: the FP64 tile loop takes it from an LDS
-    table and two short polynomials, about 19 flops in 15 operations),
+    table and two short polynomials, about 17 flops in 14 operations),
     detector-0 complex accumulation 8 (4 FMA), and for every further detector
     one Horner step S <- S conj(rho) + D e^{-i Phi} 14 (6 FMA + 2 multiplies).
     The mixed path replaces the phasor by the reduction to a fractional turn
