@@ -1,0 +1,53 @@
+"""Host logic of bench.py: the flop tallies per (sample, bin) pair that the
+roofline uses, and the reading of committed counter summaries, which must
+give nothing once the kernel sources no longer match the fingerprint the
+summary records."""
+import os
+import sys
+
+import pytest
+
+sys.path.insert(0, os.path.join(os.path.dirname(__file__), ".."))
+import bench  # noqa: E402
+
+
+def test_tile_flop_tally():
+    # phase 19, phasor 34 (fixed tally), detector 0: 8, each further detector 14
+    assert bench.flops_per_pair(3) == 19 + 34 + 8 + 2 * 14 == 89
+    assert bench.flops_per_pair(1) == 19 + 34 + 8
+    # mixed: the phasor becomes the reduction to a fractional turn (1 add)
+    assert bench.flops_per_pair(3, mixed=True) == 19 + 1 + 8 + 2 * 14
+    # direct form: 13 per detector plus 6 for each rotated one
+    assert bench.flops_per_pair(3, direct=True) == 19 + 34 + 13 + 2 * 19
+
+
+def test_relbin_flop_tally():
+    assert bench.rb_flops_per_pair(3) == 19 + 54 * 3 + 2 * 2 == 185
+    assert bench.rb_flops_per_pair(1, mixed=True) == 19 + 21
+
+
+def _summary(tmp_path, sha):
+    text = (f"# test\n\nkernel_source_sha256: {sha}\n\n"
+            "traffic_bytes_per_launch_fp64: 3.25e+07\nexecuted_fp64_flops_per_launch_fp64: 7.8e+10\n")
+    path = tmp_path / "summary.md"
+    path.write_text(text)
+    return str(path)
+
+
+def test_profile_values_follow_the_fingerprint(tmp_path):
+    # an absolute summary path is read as given
+    good = _summary(tmp_path, bench.kernel_fingerprint())
+    assert bench.measured_traffic("fp64", good) == pytest.approx(3.25e7)
+    assert bench.measured_executed_flops("fp64", good) == pytest.approx(7.8e10)
+    assert bench.measured_traffic("mixed", good) is None
+    stale = _summary(tmp_path, "0" * 64)
+    assert bench.measured_traffic("fp64", stale) is None
+    assert bench.measured_executed_flops("fp64", stale) is None
+    assert bench.measured_traffic("fp64", str(tmp_path / "missing.md")) is None
+
+
+def test_fingerprint_covers_the_kernel_sources():
+    names = [os.path.basename(p) for p in bench.KERNEL_SOURCES]
+    for must in ("gw_kernels.hip", "gw_device_math.h", "gw_plan.h", "gw_phasor_table.h", "gw_relbin.hip"):
+        assert must in names
+    assert len(bench.kernel_fingerprint()) == 64
