@@ -57,6 +57,18 @@
  *    after gw_workspace_reserve covers a shape, calls of that shape allocate
  *    nothing.  One workspace must not be used by two calls at once (calls on
  *    different streams with the same workspace race).
+ *  - Graph capture: gw_lnl_batch, gw_waveform_batch, gw_pop_lnl(_prepared)
+ *    and gw_rb_lnl may be captured into a HIP graph on `stream`.  The graph
+ *    holds every kernel that fills what it reads (the bin tables included),
+ *    so calls of other shapes on the same workspace between its replays do
+ *    not change its results; but it keeps pointing at the workspace's device
+ *    memory.  A call under capture therefore never grows the workspace (it
+ *    returns GW_EINVAL when the workspace is too small: reserve it first),
+ *    and once a call has been captured the workspace is pinned: any later
+ *    call that would grow it returns GW_EINVAL (use another workspace).
+ *    Destroying the workspace while a graph captured from it lives leaves the
+ *    graph pointing at freed memory.  Calls under capture record no
+ *    timing events (gw_workspace_set_timing).
  *
  * Errors
  *  - Every function returns GW_OK (0) or a negative code; gw_last_error()
@@ -104,7 +116,8 @@ enum {
     GW_EINVAL = -1,        /* invalid argument */
     GW_ENOMEM = -2,        /* device allocation failed */
     GW_EDEVICE = -3,       /* a HIP runtime call failed */
-    GW_EUNSUPPORTED = -4   /* valid request the library does not implement */
+    GW_EUNSUPPORTED = -4,  /* valid request the library does not implement */
+    GW_EABI = -5           /* the library's objects come from different builds (see gw_abi_layout) */
 };
 
 enum {
@@ -473,6 +486,23 @@ const char *gw_last_error(void);
 
 /* Library version as major*10000 + minor*100 + patch. */
 int gw_version(void);
+
+/* Layout check for bindings, which must not call into a library whose
+ * structures they describe differently.  sizes_out (host, `capacity`
+ * entries, may be NULL when capacity is 0) receives, in order:
+ * sizeof(gw_c128), sizeof(gw_grid), sizeof(gw_detector), sizeof(gw_event),
+ * offsetof(gw_event, dets) and GW_MAX_DET.  Returns the number of entries
+ * the library reports (6, of which the first min(6, capacity) are written),
+ * or GW_EABI when the library's translation units were compiled from
+ * different sources (a link of objects from different builds, whose internal
+ * structures need not agree).  gw_workspace_create and gw_flow_create refuse
+ * to work in such a library with the same code.  No device is used. */
+int gw_abi_layout(int64_t *sizes_out, int capacity);
+
+/* SHA-256 (64 hex digits) over the sources and public header the library was
+ * compiled from; a binding can compare it with its own source tree to detect
+ * a library left over from older sources.  Static storage; no device is used. */
+const char *gw_source_hash(void);
 
 #ifdef __cplusplus
 }

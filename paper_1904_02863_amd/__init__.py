@@ -21,7 +21,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgwlnl.so")
 
-GW_OK, GW_EINVAL, GW_ENOMEM, GW_EDEVICE, GW_EUNSUPPORTED = 0, -1, -2, -3, -4
+GW_OK, GW_EINVAL, GW_ENOMEM, GW_EDEVICE, GW_EUNSUPPORTED, GW_EABI = 0, -1, -2, -3, -4, -5
+# The library version this binding's argument types describe (gw_version).
+ABI_VERSION = 200
 PRECISIONS = {"fp64": 0, "mixed": 1}
 MAX_DET = 8
 # Options of the likelihood and waveform calls (GW_FLAG_* of include/gwlnl.h).
@@ -33,7 +35,8 @@ FLAG_ADD_NORM = 4
 EXPORTED = ("gw_workspace_create", "gw_workspace_destroy", "gw_workspace_reserve", "gw_workspace_bytes",
             "gw_workspace_set_timing", "gw_workspace_kernel_time", "gw_waveform_batch", "gw_lnl_batch",
             "gw_lnl_ragged", "gw_lnl_plan", "gw_ragged_tuning", "gw_pop_lnl", "gw_pop_prepare", "gw_pop_lnl_prepared",
-            "gw_rb_edges", "gw_rb_create", "gw_rb_destroy", "gw_rb_lnl", "gw_rb_shape", "gw_rb_summary", "gw_last_error", "gw_version",
+            "gw_rb_edges", "gw_rb_create", "gw_rb_destroy", "gw_rb_lnl", "gw_rb_shape", "gw_rb_summary", "gw_last_error",
+            "gw_version", "gw_abi_layout", "gw_source_hash",
             "gw_philox_raw", "gw_philox_fill", "gw_philox_chain_normals", "gw_mcmc_to_theta", "gw_mcmc_rw_propose",
             "gw_mcmc_accept", "gw_mcmc_update_mode", "gw_flow_create", "gw_flow_destroy", "gw_flow_num_params",
             "gw_flow_set_params", "gw_flow_get_params", "gw_flow_forward", "gw_flow_inverse", "gw_flow_gradients",
@@ -62,13 +65,61 @@ class GwEvent(ctypes.Structure):
 _lib = None
 
 
+def _layout() -> list[int]:
+    """What gw_abi_layout must report for the structures declared above:
+    sizeof gw_c128, gw_grid, gw_detector, gw_event, offsetof(gw_event, dets), GW_MAX_DET."""
+    return [16, ctypes.sizeof(GwGrid), ctypes.sizeof(GwDetector), ctypes.sizeof(GwEvent), GwEvent.dets.offset,
+            MAX_DET]
+
+
+def check_library(path: str, sources: bool = True) -> ctypes.CDLL:
+    """Open the shared library at `path` and check, before any argument types
+    are installed or any call with arguments is made, that it is the library
+    this binding describes: the same gw_version, the same structure layouts
+    (gw_abi_layout, which also fails when the library was linked from objects
+    of different builds) and, when `sources` is set and the source tree is
+    present, the same source hash as that tree (a library left over from
+    older sources is refused).  Raises RuntimeError otherwise."""
+    lib = ctypes.CDLL(path)
+    for name in ("gw_version", "gw_abi_layout", "gw_source_hash", "gw_last_error"):
+        if not hasattr(lib, name):
+            raise RuntimeError(f"{path} does not export {name}: not a library this binding can use")
+    lib.gw_version.argtypes = []
+    lib.gw_version.restype = ctypes.c_int
+    version = lib.gw_version()
+    if version != ABI_VERSION:
+        raise RuntimeError(f"{path} reports version {version}; this binding is for version {ABI_VERSION}")
+    lib.gw_last_error.argtypes = []
+    lib.gw_last_error.restype = ctypes.c_char_p
+    lib.gw_abi_layout.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.gw_abi_layout.restype = ctypes.c_int
+    want = _layout()
+    got = (ctypes.c_int64 * 16)()
+    n = lib.gw_abi_layout(got, 16)
+    if n < 0:
+        raise RuntimeError(f"{path}: {lib.gw_last_error().decode()}")
+    if n != len(want) or list(got[:n]) != want:
+        raise RuntimeError(f"{path} lays out its structures as {list(got[:max(n, 0)])}; this binding expects {want}")
+    lib.gw_source_hash.argtypes = []
+    lib.gw_source_hash.restype = ctypes.c_char_p
+    if sources:
+        from . import build as _build
+        if all(os.path.exists(f) for f in _build.source_files()):
+            have, tree = lib.gw_source_hash().decode(), _build.source_hash()
+            if have != tree:
+                raise RuntimeError(f"{path} was built from other sources than this tree ({have[:12]} against "
+                                   f"{tree[:12]}); rebuild it with `python -m paper_1904_02863_amd.build`")
+    return lib
+
+
 def load_library() -> ctypes.CDLL:
-    """Load libgwlnl.so (raises if it has not been built)."""
+    """Load libgwlnl.so, checked by check_library (raises if it has not been
+    built, or is not the library this binding describes)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1904_02863_amd.build`")
-        lib = ctypes.CDLL(LIB_PATH)
+        lib = check_library(LIB_PATH)
         vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint
         lib.gw_workspace_create.argtypes = [ctypes.POINTER(vp), i32]
         lib.gw_workspace_destroy.argtypes = [vp]
@@ -114,8 +165,6 @@ def load_library() -> ctypes.CDLL:
         lib.gw_flow_inverse.argtypes = [vp, vp, i64, vp, vp, vp]
         lib.gw_flow_gradients.argtypes = [vp, vp, i64, vp, vp, vp]
         lib.gw_flow_train_step.argtypes = [vp, vp, i64, ctypes.c_float, vp, vp]
-        lib.gw_last_error.restype = ctypes.c_char_p
-        lib.gw_version.restype = i32
         for name in EXPORTED:
             getattr(lib, name).restype = getattr(lib, name).restype or i32
         _lib = lib

@@ -8,6 +8,7 @@ one shared library.
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -31,6 +32,27 @@ HIPCC_FLAGS = [
 ]
 
 
+def source_files() -> list[str]:
+    """The files whose content fixes the library: every source and header
+    under csrc/ and the public header, in a fixed order."""
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".h")))
+    return [os.path.join(CSRC, f) for f in names] + [os.path.join(INCLUDE, "gwlnl.h")]
+
+
+def source_hash() -> str:
+    """SHA-256 over the names and contents of source_files(); compiled into
+    every translation unit, so that the library can report it
+    (gw_source_hash) and detect objects of different builds linked together."""
+    h = hashlib.sha256()
+    for path in source_files():
+        h.update(os.path.basename(path).encode())
+        h.update(b"\0")
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+        h.update(b"\0")
+    return h.hexdigest()
+
+
 def hipcc() -> str:
     path = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(path):
@@ -43,10 +65,11 @@ def build(verbose: bool = False, save_temps_dir: str | None = None) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     cc = hipcc()
+    ident = f'-DGW_SOURCE_HASH="{source_hash()}"'
 
     def compile_one(src):
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [cc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *HIPCC_FLAGS, ident, "-c", os.path.join(CSRC, src), "-o", obj]
         if save_temps_dir:
             os.makedirs(save_temps_dir, exist_ok=True)
             cmd += ["-save-temps=obj"]

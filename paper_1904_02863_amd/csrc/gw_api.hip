@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -13,6 +14,7 @@
 #include <tuple>
 #include <vector>
 
+#include "gw_build_id.h"
 #include "gw_internal.h"
 #include "gw_plan.h"
 #include "gwlnl.h"
@@ -42,6 +44,9 @@ struct gw_workspace {
     bool tables_valid = false;
     gw_grid tables_grid{};
     size_t tables_tab1 = 0, tables_tab2 = 0;
+    // a call on this workspace has been captured into a graph: the arena
+    // never grows again (growing frees it)
+    bool pinned = false;
 };
 
 // One event prepared for relative binning: a single device allocation
@@ -118,18 +123,31 @@ void drop_ragged_graph(gw_workspace *ws)
     ws->ragged_key.clear();
 }
 
+// True while `stream` is recording into a graph.  A captured call must carry
+// every kernel that fills what it reads, since its replays run later, after
+// other calls may have changed the arena.
+bool capturing(hipStream_t stream)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
 // Bin tables of `grid` at (tab1, tab2): launch their kernel unless the arena
-// already holds them there.
+// already holds them there.  A call under capture always records the kernel,
+// and pins the workspace; on a pinned workspace the tables are never taken as
+// held (a graph replay may rewrite the arena at any time), so every call
+// launches the kernel.
 hipError_t bin_tables(gw_workspace *ws, const gw_grid &grid, size_t off1, size_t off2, gw::Tab1 *tab1,
                       gw::Tab2 *tab2, hipStream_t stream)
 {
-    if (ws->tables_valid && ws->tables_tab1 == off1 && ws->tables_tab2 == off2 &&
+    if (capturing(stream)) ws->pinned = true;
+    if (!ws->pinned && ws->tables_valid && ws->tables_tab1 == off1 && ws->tables_tab2 == off2 &&
         ws->tables_grid.f_low == grid.f_low && ws->tables_grid.delta_f == grid.delta_f &&
         ws->tables_grid.n_bins == grid.n_bins)
         return hipSuccess;
     ws->tables_valid = false;
     hipError_t e = gw::launch_event_tables(grid, tab1, tab2, stream);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || ws->pinned) return e;
     ws->tables_valid = true;
     ws->tables_grid = grid;
     ws->tables_tab1 = off1;
@@ -137,9 +155,22 @@ hipError_t bin_tables(gw_workspace *ws, const gw_grid &grid, size_t off1, size_t
     return hipSuccess;
 }
 
-int ensure_capacity(gw_workspace *ws, size_t bytes)
+// Grows the arena to `bytes` (freeing the old one), unless it is large enough.
+// A call being captured into a graph may not grow it: the graph would hold
+// pointers into an arena allocated during capture.
+// Once a call on the workspace has been captured, the arena is pinned: a graph
+// may still refer to it, so it never grows (which would free it) again.
+int ensure_capacity(gw_workspace *ws, size_t bytes, hipStream_t stream)
 {
+    const bool captured = capturing(stream);
+    if (captured) ws->pinned = true;
     if (bytes <= ws->capacity) return GW_OK;
+    if (captured)
+        return fail(GW_EINVAL, "the workspace is too small for a call under graph capture: "
+                               "size it first (gw_workspace_reserve, or one eager call of the same shape)");
+    if (ws->pinned)
+        return fail(GW_EINVAL, "a graph captured from a call on this workspace may still use its memory, so it "
+                               "cannot grow; use another workspace for larger calls");
     ws->tables_valid = false;
     drop_ragged_graph(ws);               // its kernels point into the old arena
     if (ws->base) {
@@ -244,10 +275,10 @@ int check_common(gw_workspace *ws, const gw_grid *grid, int n_det_min, int n_det
 
 // The start/stop events of the next timed hot-kernel launch, or two nullptrs
 // while timing is off.  The pair counts once timer_stop has recorded its stop.
-int timer_pair(gw_workspace *ws, hipEvent_t *start, hipEvent_t *stop)
+int timer_pair(gw_workspace *ws, hipStream_t stream, hipEvent_t *start, hipEvent_t *stop)
 {
     *start = *stop = nullptr;
-    if (!ws->timing) return GW_OK;
+    if (!ws->timing || capturing(stream)) return GW_OK;
     while ((size_t)(2 * ws->timed + 2) > ws->events.size()) {
         hipEvent_t ev;
         hipError_t e = hipEventCreate(&ev);
@@ -277,7 +308,7 @@ int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::De
     const bool isco = (flags & GW_FLAG_TERM_ISCO) != 0;
     const gw::TilePlan plan = plan_tiles(ws, grid.n_bins, n_det, n_samples, mixed, form);
     const LnlLayout l = lnl_layout(grid.n_bins, n_det, n_samples, plan, flags);
-    if (int rc = ensure_capacity(ws, l.total)) return rc;
+    if (int rc = ensure_capacity(ws, l.total, stream)) return rc;
     gw::EventBuffers eb;
     eb.tab1 = at<gw::Tab1>(ws, l.tab1);
     eb.tab2 = at<gw::Tab2>(ws, l.tab2);
@@ -304,7 +335,7 @@ int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::De
     if (form == gw::kFormSplitIsco && (e = gw::launch_isco_limit(n_samples, rec, eb.k_limit, stream)) != hipSuccess)
         return hip_fail(e, "template-end limit");
     hipEvent_t t_start, t_stop;
-    if (int rc = timer_pair(ws, &t_start, &t_stop)) return rc;
+    if (int rc = timer_pair(ws, stream, &t_start, &t_stop)) return rc;
     if (t_start && (e = hipEventRecord(t_start, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if ((e = gw::launch_lnl_tiles(grid, n_det, n_samples, plan, mixed, form, eb, rec, part, stream)) != hipSuccess)
         return hip_fail(e, "lnl tiles");
@@ -447,7 +478,7 @@ int ragged_materialise(gw_workspace *ws, int n_events, const gw_event *events, c
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     RaggedPlan sizing = ragged_plan(ws, n_events, events, data, psd, theta, n_param, lnl, mixed, flags, tile_bins,
                                     chunk_bins, nullptr);
-    if (int rc = ensure_capacity(ws, sizing.total)) return rc;
+    if (int rc = ensure_capacity(ws, sizing.total, stream)) return rc;
     ws->tables_valid = false;            // the ragged layout overwrites the arena
     *out = ragged_plan(ws, n_events, events, data, psd, theta, n_param, lnl, mixed, flags, tile_bins, chunk_bins,
                        static_cast<char *>(ws->base));
@@ -645,10 +676,10 @@ int pop_run(gw_workspace *ws, int64_t n_events, int64_t n_per_event, const doubl
     DeviceGuard g(ws->device);
     if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
     drop_ragged_graph(ws);               // the arena is about to be laid out for the population pass
-    if (int rc = ensure_capacity(ws, gw::pop::workspace_bytes(n_events, n_per_event, n_hyper))) return rc;
+    if (int rc = ensure_capacity(ws, gw::pop::workspace_bytes(n_events, n_per_event, n_hyper), stream)) return rc;
     ws->tables_valid = false;
     hipEvent_t t_start, t_stop;
-    if (int rc = timer_pair(ws, &t_start, &t_stop)) return rc;
+    if (int rc = timer_pair(ws, stream, &t_start, &t_stop)) return rc;
     hipError_t e = gw::pop::launch(n_events, n_per_event, samples, prepared, n_hyper, hyper, ws->base, lnl_out,
                                    t_start, t_stop, stream);
     if (e != hipSuccess) return hip_fail(e, "gw_pop_lnl");
@@ -660,11 +691,38 @@ int pop_run(gw_workspace *ws, int64_t n_events, int64_t n_per_event, const doubl
 
 namespace gw {
 int set_error(int code, const std::string &msg) { return fail(code, msg); }
+
+int check_build()
+{
+    const char *mine = source_hash_api();
+    const char *units[] = {source_hash_kernels(), source_hash_flow(), source_hash_mcmc(), source_hash_pop(),
+                           source_hash_relbin()};
+    for (const char *u : units)
+        if (std::strcmp(u, mine) != 0)
+            return fail(GW_EABI, std::string("the library was linked from objects compiled from different sources (") +
+                                     mine + " and " + u + "); rebuild it from one source tree");
+    return GW_OK;
+}
 }  // namespace gw
+
+GW_DEFINE_SOURCE_HASH(api)
 
 extern "C" {
 
-int gw_version(void) { return 100; }
+int gw_version(void) { return 200; }
+
+const char *gw_source_hash(void) { return gw::source_hash_api(); }
+
+int gw_abi_layout(int64_t *sizes_out, int capacity)
+{
+    const int64_t v[] = {(int64_t)sizeof(gw_c128), (int64_t)sizeof(gw_grid), (int64_t)sizeof(gw_detector),
+                         (int64_t)sizeof(gw_event), (int64_t)offsetof(gw_event, dets), (int64_t)GW_MAX_DET};
+    const int n = (int)(sizeof(v) / sizeof(v[0]));
+    if (capacity < 0 || (capacity > 0 && !sizes_out)) return fail(GW_EINVAL, "bad output array");
+    if (int rc = gw::check_build()) return rc;
+    for (int i = 0; i < n && i < capacity; ++i) sizes_out[i] = v[i];
+    return n;
+}
 
 const char *gw_last_error(void) { return g_last_error.c_str(); }
 
@@ -672,6 +730,7 @@ int gw_workspace_create(gw_workspace **ws, int device)
 {
     if (!ws) return fail(GW_EINVAL, "ws is NULL");
     *ws = nullptr;
+    if (int rc = gw::check_build()) return rc;
     int dev = device;
     if (dev < 0) {
         hipError_t e = hipGetDevice(&dev);
@@ -753,7 +812,7 @@ int gw_workspace_reserve(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_
                                    GW_FLAG_DIRECT | GW_FLAG_TERM_ISCO | GW_FLAG_ADD_NORM);
     size_t wave = align_up(sizeof(gw::Tab1) * n_bins) + align_up(sizeof(gw::Tab2) * n_bins) +
                   align_up(sizeof(double) * gw::record_fields(std::max(n_det, 2)) * std::max<int64_t>(n_samples, 1));
-    return ensure_capacity(ws, std::max(l.total, wave));
+    return ensure_capacity(ws, std::max(l.total, wave), nullptr);
 }
 
 int64_t gw_workspace_bytes(const gw_workspace *ws) { return ws ? (int64_t)ws->capacity : 0; }
@@ -799,7 +858,7 @@ int gw_waveform_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw
     const size_t o1 = c.take(sizeof(gw::Tab1) * grid->n_bins);
     const size_t o2 = c.take(sizeof(gw::Tab2) * grid->n_bins);
     const size_t orec = c.take(sizeof(double) * gw::record_fields(n_out) * n_samples);
-    if (int rc = ensure_capacity(ws, c.offset)) return rc;
+    if (int rc = ensure_capacity(ws, c.offset, stream)) return rc;
     auto *tab1 = at<gw::Tab1>(ws, o1);
     auto *tab2 = at<gw::Tab2>(ws, o2);
     auto *rec = at<double>(ws, orec);
@@ -809,7 +868,7 @@ int gw_waveform_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw
                                     theta, rec, stream)) != hipSuccess)
         return hip_fail(e, "sample prep");
     hipEvent_t t_start, t_stop;
-    if (int rc = timer_pair(ws, &t_start, &t_stop)) return rc;
+    if (int rc = timer_pair(ws, stream, &t_start, &t_stop)) return rc;
     if (t_start && (e = hipEventRecord(t_start, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if ((e = gw::launch_waveform(*grid, n_out, n_samples, tab1, tab2, rec, h_out, stream)) != hipSuccess)
         return hip_fail(e, "waveform");
@@ -937,7 +996,7 @@ int gw_rb_create(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_dete
     const size_t o1 = w.take(sizeof(gw::Tab1) * grid->n_bins);
     const size_t o2 = w.take(sizeof(gw::Tab2) * grid->n_bins);
     const size_t oth = w.take(sizeof(double) * n_param);
-    if (int rc = ensure_capacity(ws, w.offset)) return rc;
+    if (int rc = ensure_capacity(ws, w.offset, stream)) return rc;
     Carver c;
     const size_t h_idx = c.take(sizeof(int64_t) * n_edges);
     const size_t h_edges = c.take(sizeof(gw::rb::RbEdge) * n_edges);
@@ -1065,7 +1124,7 @@ int gw_rb_lnl(gw_workspace *ws, const gw_relbin *rb, const double *theta, int64_
     Carver c;
     const size_t orec = c.take(sizeof(double) * gw::record_fields(rb->n_det) * n_samples);
     const size_t opart = c.take(sizeof(double) * n_chunks * n_samples);
-    if (int rc = ensure_capacity(ws, c.offset)) return rc;
+    if (int rc = ensure_capacity(ws, c.offset, stream)) return rc;
     ws->tables_valid = false;
     auto *rec = at<double>(ws, orec);
     auto *part = at<double>(ws, opart);
@@ -1074,7 +1133,7 @@ int gw_rb_lnl(gw_workspace *ws, const gw_relbin *rb, const double *theta, int64_
                                     stream)) != hipSuccess)
         return hip_fail(e, "sample prep");
     hipEvent_t t_start, t_stop;
-    if (int rc = timer_pair(ws, &t_start, &t_stop)) return rc;
+    if (int rc = timer_pair(ws, stream, &t_start, &t_stop)) return rc;
     if ((e = gw::rb::launch_lnl(rb->n_det, mixed, n_samples, rb->n_rb, n_chunks, rb->edges, rb->coef, rb->ends,
                                 rb->fid, rec, part, t_start, t_stop, stream)) != hipSuccess)
         return hip_fail(e, "relative-binning pass");

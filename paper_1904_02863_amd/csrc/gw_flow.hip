@@ -22,6 +22,7 @@
 #include <string>
 #include <vector>
 
+#include "gw_build_id.h"
 #include "gw_flow_internal.h"
 #include "gwlnl.h"
 
@@ -660,6 +661,7 @@ int gw_flow_create(gw_flow **out, int device, int dim, int n_layers, int hidden,
     if (dim < 2 || dim > kInPad || 2 * dim > kOutPad) return fail(GW_EINVAL, "dim must be in 2..16");
     if (n_layers < 1 || n_layers > 64 || hidden < 1 || hidden > 4096) return fail(GW_EINVAL, "bad flow shape");
     if (!cond_masks) return fail(GW_EINVAL, "cond_masks is NULL");
+    if (int rc = gw::check_build()) return rc;
     int dev = device;
     if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(GW_EDEVICE, "hipGetDevice");
     DeviceGuard g(dev);
@@ -797,3 +799,5 @@ int gw_flow_train_step(gw_flow *f, const double *x, int64_t n, float lr, double 
 }
 
 }  // extern "C"
+
+GW_DEFINE_SOURCE_HASH(flow)

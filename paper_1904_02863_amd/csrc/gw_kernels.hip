@@ -23,6 +23,7 @@
 
 #include <cmath>
 
+#include "gw_build_id.h"
 #include "gw_device_math.h"
 #include "gw_internal.h"
 #include "gw_plan.h"
@@ -1212,3 +1213,5 @@ hipError_t launch_waveform(const gw_grid &grid, int n_out, int64_t n_samples, co
 }
 
 }  // namespace gw
+
+GW_DEFINE_SOURCE_HASH(kernels)

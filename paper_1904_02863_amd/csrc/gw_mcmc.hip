@@ -20,6 +20,7 @@
 #include <cstdint>
 #include <string>
 
+#include "gw_build_id.h"
 #include "gw_mcmc_internal.h"
 #include "gwlnl.h"
 
@@ -377,3 +378,5 @@ int gw_mcmc_update_mode(int64_t n, int *window_accepts, int window, double thres
 }
 
 }  // extern "C"
+
+GW_DEFINE_SOURCE_HASH(mcmc)

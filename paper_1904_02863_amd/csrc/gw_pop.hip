@@ -25,6 +25,7 @@
 #include <cmath>
 #include <string>
 
+#include "gw_build_id.h"
 #include "gw_internal.h"
 
 namespace gw {
@@ -354,3 +355,5 @@ hipError_t launch(int64_t n_events, int64_t n_per, const double *samples, bool p
 
 }  // namespace pop
 }  // namespace gw
+
+GW_DEFINE_SOURCE_HASH(pop)

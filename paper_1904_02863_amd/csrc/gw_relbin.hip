@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "gw_build_id.h"
 #include "gw_device_math.h"
 #include "gw_internal.h"
 #include "gw_template.h"
@@ -449,3 +450,5 @@ hipError_t launch_finalize(int64_t n_samples, int n_chunks, const double *partia
 
 }  // namespace rb
 }  // namespace gw
+
+GW_DEFINE_SOURCE_HASH(relbin)

@@ -138,3 +138,41 @@ def test_queue_launch_replays_from_a_graph(gw):
         np.testing.assert_array_equal(out.cpu().numpy(), eager.cpu().numpy(), err_msg=f"replay {rep}")
         gw.lnl_batch(w.grid, w.tensors, w.vertices, d, s, th2, workspace=other)
         torch.cuda.synchronize()
+
+
+def test_captured_call_keeps_its_tables_and_pins_the_workspace(gw):
+    """A graph captured from gw_lnl_batch records the bin-table kernel too:
+    eager calls on the same workspace with another grid of the same size
+    (which rewrite the tables in the arena) between the replays leave every
+    replay equal to the eager result, and those eager calls, made after a
+    replay has rewritten the arena, equal a fresh workspace's.  The captured
+    workspace then refuses to grow."""
+    import torch
+    w, theta, data = _event(35, 3, 40_001, 4000, False)
+    dev = torch.device("cuda", 0)
+    d = torch.from_numpy(np.ascontiguousarray(data)).to(dev)
+    s = torch.from_numpy(w.psd).to(dev)
+    th = torch.from_numpy(np.ascontiguousarray(theta)).to(dev)
+    other_grid = (w.grid.f_low + 7.0, w.grid.delta_f, w.grid.n_bins)
+    ws = gw.Workspace(0)
+    eager = gw.lnl_batch(w.grid, w.tensors, w.vertices, d, s, th, workspace=ws).clone()
+    want_b = gw.lnl_batch(other_grid, w.tensors, w.vertices, d, s, th, workspace=gw.Workspace(0)).clone()
+    out = torch.empty_like(eager)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gw.lnl_batch(w.grid, w.tensors, w.vertices, d, s, th, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        got_b = gw.lnl_batch(other_grid, w.tensors, w.vertices, d, s, th, workspace=ws)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got_b.cpu().numpy(), want_b.cpu().numpy(), err_msg=f"eager {rep}")
+        out.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), eager.cpu().numpy(), err_msg=f"replay {rep}")
+    big = torch.zeros((3, 2 * w.grid.n_bins), dtype=torch.complex128, device=dev)
+    big_s = torch.ones((3, 2 * w.grid.n_bins), dtype=torch.float64, device=dev)
+    with pytest.raises(gw.GwError, match="cannot grow"):
+        gw.lnl_batch((w.grid.f_low, w.grid.delta_f, 2 * w.grid.n_bins), w.tensors, w.vertices, big, big_s, th,
+                     workspace=ws)
