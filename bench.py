@@ -142,6 +142,18 @@ def build_inputs(name: str, n_samples: int | None, spins: bool = False):
     return w, data, psd, theta
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, data, budget_s: float, flags: int = 0):
     """Oracle evals/s on a bounded number of the workload's samples."""
     import numpy as np
@@ -174,6 +186,7 @@ def cpu_baseline(w, data, budget_s: float, flags: int = 0):
         assert np.isfinite(vals).all()
         one += 1
     return {"value": done / spent, "unit": "lnL evals/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{done} of the {w.n_samples} samples (rows 0..{done - 1}), all {g.n_bins} bins x "
                       f"{w.n_det} detectors, {spent:.1f} s",
             "single_thread": {"value": one / spent1, "cores": 1,
@@ -284,19 +297,10 @@ def bench_ragged(args):
     print(json.dumps(result), flush=True)
 
 
-def bench_flow(args):
-    """Learned proposal on the 3-detector 128 s data with one injection at
-    network SNR 25, 11 sampler coordinates (9 physical + two aligned spins,
-    prior-only unless --spins passes them to the likelihood), 4096 chains: random-walk MH (burn-in with
-    covariance adaptation, then production), a flow trained on 2e5 of its
-    samples, then flow-proposal MH from the same states.  Reports ESS/s of
-    both (bulk ESS, minimum over coordinates, from 256 chains recorded at every
-    step and scaled to all chains), the standardised difference of every
-    coordinate's mean (by the two ESS), and two-sample KS p-values between
-    the final states of the 4096 random-walk chains and the 4096 flow chains
-    (independent draws when both have converged).  With a free sky the
-    posterior has several modes that random-walk chains started near the
-    injection do not cross; the KS values then measure that as well."""
+def flow_problem(spins: bool, precision: str = "fp64"):
+    """The learned-proposal workload: the 3-detector 128 s data (seeded noise)
+    with one injection at network optimal SNR 25, built with the library's
+    waveform; the prior box of sampler.injection_box."""
     import math
 
     import numpy as np
@@ -304,9 +308,8 @@ def bench_flow(args):
 
     import paper_1904_02863_amd as gw
     import synth
-    from paper_1904_02863_amd import diagnostics, sampler
+    from paper_1904_02863_amd import sampler
 
-    n_chains, track = 4096, 256
     w = synth.bbh_3det_128s(1)
     g = w.grid
     dev = torch.device("cuda", 0)
@@ -318,64 +321,64 @@ def bench_flow(args):
                              workspace=ws).item()
     inj[2] *= math.sqrt(hh) / 25.0                      # network optimal SNR 25
     h = gw.waveform_batch(g, w.tensors, w.vertices, torch.from_numpy(inj[None]).to(dev), workspace=ws)[0]
-    data = (torch.from_numpy(w.noise).to(dev) + h).contiguous()
-    box_lo = np.array([25.0, 0.5, 0.2 * inj[2], 0.0, -0.1, 0.0, -1.0, 0.0, -1.0, -1.0, -1.0])
-    box_hi = np.array([35.0, 1.0, 3.0 * inj[2], 2 * math.pi, 0.1, 2 * math.pi, 1.0, math.pi, 1.0, 1.0, 1.0])
-    prob = sampler.Problem(g, w.tensors, w.vertices, data, psd, box_lo, box_hi, args.precision, spins=args.spins)
-    p_inj = np.array([inj[0], inj[1], inj[2], inj[3], inj[4], inj[5], math.sin(inj[6]), inj[7], math.cos(inj[8]),
-                      0.0, 0.0])
-    rng = np.random.default_rng(5)
-    x0 = sampler.to_sampler_coords(prob, p_inj)[None] + rng.normal(scale=1e-3, size=(n_chains, 11))
-    if args.spins:      # spins enter lnL: start near the injection's (zero) spins like the other coordinates
-        x0[:, 9:] = rng.normal(scale=1e-3, size=(n_chains, 2))
-    else:               # spins: prior-only coordinates
-        x0[:, 9:] = rng.normal(scale=1.0, size=(n_chains, 2))
-    state = sampler.init_chains(prob, x0, ws)
-    seed = 20190408
-    chol = np.diag(np.full(11, 1e-3))
-    t_all = time.perf_counter()
-    _, acc_burn, t_burn, chol, _ = sampler.run_random_walk(prob, state, args.mcmc_burn, seed, chol, ws,
-                                                           adapt_every=100)
-    # production: every step of `track` chains for ESS, all chains every 10 steps for training
-    rec_rw, acc_rw, t_rw, chol, collected = sampler.run_random_walk(prob, state, args.mcmc_steps, seed, chol, ws,
-                                                                    record_every=1, record_track=track,
-                                                                    collect_every=10)
-    train = collected[np.random.default_rng(1).permutation(len(collected))[:200000]]
-    flow, hist, t_train = sampler.train_flow(train, n_layers=8, hidden=256, steps=args.flow_steps, batch=4096,
-                                             lr=1e-3, seed=3, log_every=max(1, args.flow_steps // 10))
-    fstate = sampler.ChainState(state.x.clone(), state.lnp.clone(), torch.zeros_like(state.lnp), state.step)
-    sampler.run_flow_mh(prob, fstate, flow, 64, seed + 1, chol, ws)          # one window before timing
-    rec_fl, acc, t_fl, fb = sampler.run_flow_mh(prob, fstate, flow, args.mcmc_steps, seed + 1, chol, ws,
-                                                record_every=1, record_track=track)
-    rw_draws = rec_rw.transpose(1, 0, 2)                # [track, steps, 11]
-    fl_draws = rec_fl.transpose(1, 0, 2)
-    ess_rw, per_rw = diagnostics.min_ess(rw_draws)
-    ess_fl, per_fl = diagnostics.min_ess(fl_draws)
-    scale = n_chains / track
-    ksp = diagnostics.ks_pvalues(state.x.cpu().numpy(), fstate.x.cpu().numpy())
-    a, b = rw_draws.reshape(-1, 11), fl_draws.reshape(-1, 11)
-    zmean = (b.mean(axis=0) - a.mean(axis=0)) / (a.std(axis=0) * np.sqrt(1.0 / per_rw + 1.0 / per_fl))
+    data = torch.from_numpy(np.ascontiguousarray(w.noise + h.cpu().numpy())).to(dev)
+    lo, hi, p_inj = sampler.injection_box(inj)
+    prob = sampler.Problem(g, w.tensors, w.vertices, data, psd, lo, hi, precision, spins=spins)
+    return prob, p_inj, ws
+
+
+def flow_comparison(args, spins: bool):
+    """Random-walk and flow-proposal MH on flow_problem (see
+    sampler.compare_samplers): 4096 chains, 2.1e5 training samples, 8
+    couplings of 11 -> 256 -> 256 -> 22."""
+    from paper_1904_02863_amd import sampler
+    prob, p_inj, ws = flow_problem(spins, args.precision)
+    burn = args.mcmc_burn if args.mcmc_burn is not None else (40000 if spins else 4000)
+    t0 = time.perf_counter()
+    res = sampler.compare_samplers(prob, p_inj, ws, n_chains=4096, burn=burn, steps=args.mcmc_steps,
+                                   flow_steps=args.flow_steps)
+    res["wall_seconds"] = time.perf_counter() - t0
+    res["burn_in_steps"] = burn
+    res["spins"] = spins
+    res.pop("states")
+    return res
+
+
+def bench_flow(args):
+    """Learned proposal on the 3-detector 128 s data with one injection at
+    network SNR 25, 11 sampler coordinates (9 physical + two aligned spins,
+    prior-only unless --spins passes them to the likelihood), 4096 chains:
+    random-walk MH (burn-in with covariance adaptation, then production), a
+    flow trained on 2.1e5 of its samples, then flow-proposal MH (every 8th
+    step a random-walk step) from the same states.  Reports ESS/s of both
+    (bulk ESS, minimum over coordinates, from 256 chains recorded at every
+    step and scaled to all chains), the standardised difference of every
+    coordinate's mean (by the two ESS), and two-sample KS p-values between
+    the final states of the 4096 random-walk chains and the 4096 flow chains."""
+    res = flow_comparison(args, args.spins)
     result = {
         "metric": "ESS/s flow vs plain MCMC (3-det 128 s, SNR 25, 11 coordinates, 4096 chains)",
-        "value": ess_fl * scale / t_fl, "unit": "ESS/s", "n_gpus": 1, "steps": args.mcmc_steps,
+        "value": res["flow"]["ess_per_s"], "unit": "ESS/s", "n_gpus": 1, "steps": args.mcmc_steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+bf16", "data": "synthetic",
-        "config": {"workload": "flow-mcmc", "chains": n_chains, "ess_chains": track, "snr": 25.0,
-                   "burn_in_steps": args.mcmc_burn, "flow_train_steps": args.flow_steps,
-                   "train_samples": int(len(train)), "precision": args.precision, "spins": args.spins},
-        "random_walk": {"ess_per_s": ess_rw * scale / t_rw, "min_ess": ess_rw * scale, "seconds": t_rw,
-                        "acceptance": acc_rw, "acceptance_burn_in": acc_burn, "burn_in_seconds": t_burn,
-                        "ess_per_coordinate": (per_rw * scale).tolist()},
-        "flow": {"ess_per_s": ess_fl * scale / t_fl, "ess_per_s_with_training": ess_fl * scale / (t_fl + t_train),
-                 "min_ess": ess_fl * scale, "seconds": t_fl, "train_seconds": t_train,
-                 "acceptance": float(acc), "fallback_fraction": float(fb), "loss_history": hist,
-                 "ess_per_coordinate": (per_fl * scale).tolist()},
-        "speedup_ess_per_s": (ess_fl / t_fl) / (ess_rw / t_rw),
-        "speedup_with_training": (ess_fl / (t_fl + t_train)) / (ess_rw / t_rw),
-        "ks_pvalues_final_states": ksp.tolist(), "ks_min_p": float(ksp.min()),
-        "mean_difference_z": zmean.tolist(),
-        "wall_seconds": time.perf_counter() - t_all,
+        "config": {"workload": "flow-mcmc", "chains": 4096, "ess_chains": 256, "snr": 25.0,
+                   "burn_in_steps": res["burn_in_steps"], "flow_train_steps": args.flow_steps,
+                   "train_samples": res["train_samples"], "precision": args.precision, "spins": args.spins},
     }
+    result.update(res)
     print(json.dumps(result), flush=True)
+
+
+def flow_summary(res: dict) -> dict:
+    """The compact learned-proposal figures carried on the default line."""
+    return {"workload": "flow-mcmc", "spins": res["spins"], "chains": 4096, "burn_in_steps": res["burn_in_steps"],
+            "ess_per_s_flow": res["flow"]["ess_per_s"],
+            "ess_per_s_flow_with_training": res["flow"]["ess_per_s_with_training"],
+            "ess_per_s_random_walk": res["random_walk"]["ess_per_s"],
+            "speedup": res["speedup_ess_per_s"], "speedup_with_training": res["speedup_with_training"],
+            "ks_min_p": res["ks_min_p"], "acceptance_flow": res["flow"]["acceptance"],
+            "acceptance_random_walk": res["random_walk"]["acceptance"],
+            "train_seconds": res["flow"]["train_seconds"], "train_samples": res["train_samples"],
+            "wall_seconds": res["wall_seconds"]}
 
 
 def bench_population(args):
@@ -648,7 +651,8 @@ def main():
     ap.add_argument("--workload", default="bbh-3det-128s",
                     choices=["bbh-3det-128s", "bbh-1det-4s", "bns-15hz-512s", "bns-ragged", "flow-mcmc",
                              "population", "waveform", "bns-relbin"])
-    ap.add_argument("--mcmc-burn", type=int, default=4000, help="flow-mcmc: random-walk burn-in steps")
+    ap.add_argument("--mcmc-burn", type=int, default=None,
+                    help="flow-mcmc: random-walk burn-in steps (default 40000 with aligned spins, 4000 without)")
     ap.add_argument("--mcmc-steps", type=int, default=1024, help="flow-mcmc: production steps of each sampler")
     ap.add_argument("--flow-steps", type=int, default=3000, help="flow-mcmc: Adam steps")
     ap.add_argument("--samples", type=int, default=None)
@@ -661,6 +665,8 @@ def main():
                          "flow-mcmc: the two spin coordinates enter the likelihood")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-flow", action="store_true",
+                    help="default workload: skip the learned-proposal comparison appended to the line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run one plain device-to-device copy of MIB MiB "
                          "(reference dispatch for scaling hardware traffic counters)")
@@ -723,7 +729,12 @@ def main():
     mixed = args.precision == "mixed"
     direct = bool(args.flags & 1)
     flops_launch = flops_per_pair(w.n_det, mixed, direct) * w.n_samples * g.n_bins
-    achieved = flops_launch / kernel_avg_s / 1e12
+    tally_rate = flops_launch / kernel_avg_s / 1e12
+    headline = args.workload == "bbh-3det-128s" and args.flags == 0 and not args.spins
+    # FP64 flops the hardware counters saw one launch execute (FMA = 2), from
+    # the committed summary of the same kernel sources; None when they changed
+    executed = measured_executed_flops(args.precision) if headline else None
+    achieved = executed / kernel_avg_s / 1e12 if executed is not None else None
     result = {
         "metric": "lnL evals/s (3-det,128 s TaylorF2)" if args.workload == "bbh-3det-128s" else "lnL evals/s",
         "value": evals / elapsed,
@@ -741,27 +752,29 @@ def main():
                    "delta_f": g.delta_f, "f_low": g.f_low, "f_high": g.f_high, "n_param": w.n_param,
                    "precision": args.precision, "flags": args.flags, "spins": args.spins},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": (measured_traffic(args.precision)
-                                 if args.workload == "bbh-3det-128s" and args.flags == 0 and not args.spins
-                                 else None),
+                     "frac": achieved / FP64_PEAK_TFLOPS if achieved is not None else None,
+                     "flops_source": (f"executed FP64 flops from the counters in {PROFILE_SUMMARY}"
+                                      if executed is not None else "no counter summary of these kernel sources"),
+                     "executed_flops_per_launch": executed,
+                     "traffic": measured_traffic(args.precision) if headline else None,
                      "kernel": f"lnl_tile_kernel<{w.n_det},{'mixed' if mixed else 'fp64'}>",
-                     "kernel_ms": kernel_avg_s * 1e3, "flops_per_launch": flops_launch,
-                     "flops_per_pair": flops_per_pair(w.n_det, mixed, direct)},
+                     "kernel_ms": kernel_avg_s * 1e3,
+                     # the algorithmic tally below prices the phasor at its
+                     # polynomial cost; the table phasor the kernel runs costs less
+                     "frac_tally": tally_rate / FP64_PEAK_TFLOPS, "flops_per_launch_tally": flops_launch,
+                     "flops_per_pair_tally": flops_per_pair(w.n_det, mixed, direct)},
     }
-    executed = (measured_executed_flops("fp64")
-                if args.workload == "bbh-3det-128s" and args.flags == 0 and not args.spins and not mixed else None)
-    if executed is not None:
-        # the same kernel time against what the counters saw executed (the
-        # tally counts the phasor at its polynomial cost, the table beats it)
-        result["roofline"]["executed_flops_per_launch"] = executed
-        result["roofline"]["frac_executed"] = executed / kernel_avg_s / 1e12 / FP64_PEAK_TFLOPS
     if args.flags & 2:
         # the kernel skips the bins above the batch's largest cut-off, so a
         # tally over every bin would overstate the rate
         result["roofline"] = None
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, data, args.cpu_seconds, args.flags)
+    if args.workload == "bbh-3det-128s" and not args.no_flow:
+        # the second half of the metric: the learned proposal against plain
+        # random-walk MCMC on the same GPU (outside the timed region above)
+        del data, psd, theta, out, ws
+        result["flow_mcmc"] = flow_summary(flow_comparison(args, True))
     print(json.dumps(result), flush=True)
 
 

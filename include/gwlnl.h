@@ -445,6 +445,33 @@ int gw_mcmc_accept(int dim, int64_t n, uint64_t seed, uint32_t step, double *x, 
 int gw_mcmc_update_mode(int64_t n, int *window_accepts, int window, double threshold, int *mode,
                         hipStream_t stream);
 
+/* Random-walk adaptation from the chains themselves (Haario, Saksman &
+ * Tamminen 2001, with the 2.38^2/d scaling of Roberts, Gelman & Gilks 1997):
+ * chol_out (device [dim][dim], lower triangular, upper part written zero) is
+ * the Cholesky factor of (2.38^2 / dim) scale^2 Cov(x) + eps I, Cov the sample
+ * covariance of the n rows of x (device [n][dim]), eps = floor max(1, tr/dim)
+ * with tr the trace of the scaled covariance.  A non-positive pivot (a
+ * degenerate chain set) is replaced by sqrt(eps).  One block; n >= 2,
+ * scale > 0, floor >= 0. */
+int gw_mcmc_adapt_chol(int dim, int64_t n, const double *x, double scale, double floor, double *chol_out,
+                       hipStream_t stream);
+
+/* Sample mean (mean_out, device [dim]) and covariance (cov_out, device
+ * [dim][dim], divisor n - 1) of the n rows of x (device [n][dim]); either
+ * output may be NULL, not both.  n >= 2. */
+int gw_mcmc_moments(int dim, int64_t n, const double *x, double *mean_out, double *cov_out, hipStream_t stream);
+
+/* out (device int64 [1]) = sum of counts (device int32 [n]), e.g. the
+ * acceptance counters of gw_mcmc_accept. */
+int gw_mcmc_count(int64_t n, const int *counts, int64_t *out, hipStream_t stream);
+
+/* Rows drawn with replacement: dst[i] = src[floor(u_i n_src)] for i < n_out,
+ * u_i uniform number i of Philox (seed, stream_id, step) as in
+ * gw_philox_fill.  src device [n_src][dim], dst device [n_out][dim]
+ * (minibatches for gw_flow_train_step). */
+int gw_gather_rows(int dim, int64_t n_out, const double *src, int64_t n_src, uint64_t seed, uint32_t stream_id,
+                   uint32_t step, double *dst, hipStream_t stream);
+
 /* Affine-coupling flow (RealNVP): x = mu + sigma * f_{L-1}(... f_0(z)), z ~ N(0, I).
  * Layer l keeps the dimensions whose bit is set in cond_masks[l] and maps the
  * others as y = a exp(s) + t, s = 3 tanh(r/3), (r, t) = MLP_l(masked a),

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libgwlnl.so")
 
 GW_OK, GW_EINVAL, GW_ENOMEM, GW_EDEVICE, GW_EUNSUPPORTED, GW_EABI = 0, -1, -2, -3, -4, -5
 # The library version this binding's argument types describe (gw_version).
-ABI_VERSION = 200
+ABI_VERSION = 300
 PRECISIONS = {"fp64": 0, "mixed": 1}
 MAX_DET = 8
 # Options of the likelihood and waveform calls (GW_FLAG_* of include/gwlnl.h).
@@ -38,7 +38,8 @@ EXPORTED = ("gw_workspace_create", "gw_workspace_destroy", "gw_workspace_reserve
             "gw_rb_edges", "gw_rb_create", "gw_rb_destroy", "gw_rb_lnl", "gw_rb_shape", "gw_rb_summary", "gw_last_error",
             "gw_version", "gw_abi_layout", "gw_source_hash",
             "gw_philox_raw", "gw_philox_fill", "gw_philox_chain_normals", "gw_mcmc_to_theta", "gw_mcmc_rw_propose",
-            "gw_mcmc_accept", "gw_mcmc_update_mode", "gw_flow_create", "gw_flow_destroy", "gw_flow_num_params",
+            "gw_mcmc_accept", "gw_mcmc_update_mode", "gw_mcmc_adapt_chol", "gw_mcmc_moments", "gw_mcmc_count", "gw_gather_rows",
+            "gw_flow_create", "gw_flow_destroy", "gw_flow_num_params",
             "gw_flow_set_params", "gw_flow_get_params", "gw_flow_forward", "gw_flow_inverse", "gw_flow_gradients",
             "gw_flow_train_step")
 
@@ -155,6 +156,10 @@ def load_library() -> ctypes.CDLL:
         lib.gw_mcmc_rw_propose.argtypes = [i32, i64, vp, vp, u64, u32p, vp, vp, vp]
         lib.gw_mcmc_accept.argtypes = [i32, i64, u64, u32p, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.gw_mcmc_update_mode.argtypes = [i64, vp, i32, ctypes.c_double, vp, vp]
+        lib.gw_mcmc_adapt_chol.argtypes = [i32, i64, vp, ctypes.c_double, ctypes.c_double, vp, vp]
+        lib.gw_mcmc_moments.argtypes = [i32, i64, vp, vp, vp, vp]
+        lib.gw_mcmc_count.argtypes = [i64, vp, vp, vp]
+        lib.gw_gather_rows.argtypes = [i32, i64, vp, i64, u64, u32p, u32p, vp, vp]
         lib.gw_flow_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32, vp]
         lib.gw_flow_destroy.argtypes = [vp]
         lib.gw_flow_num_params.argtypes = [vp]
@@ -621,6 +626,58 @@ def mcmc_update_mode(window_accepts, window: int, threshold: float, mode, stream
     _check(load_library().gw_mcmc_update_mode(n, window_accepts.data_ptr(), int(window), float(threshold),
                                               mode.data_ptr(), _stream_ptr(mode.device.index, stream)))
     return mode
+
+
+def mcmc_adapt_chol(x, scale: float = 1.0, floor: float = 1e-12, out=None, stream=None):
+    """Cholesky factor [dim, dim] of (2.38^2/dim) scale^2 Cov(x) + floor
+    max(1, tr/dim) I over the rows of x [n, dim] (gw_mcmc_adapt_chol)."""
+    torch = _torch()
+    x = _cuda_tensor(x, torch.float64, "x")
+    n, dim = x.shape
+    if out is None:
+        out = torch.empty((dim, dim), dtype=torch.float64, device=x.device)
+    out = _cuda_tensor(out, torch.float64, "out", (dim, dim))
+    _check(load_library().gw_mcmc_adapt_chol(dim, n, x.data_ptr(), float(scale), float(floor), out.data_ptr(),
+                                             _stream_ptr(x.device.index, stream)))
+    return out
+
+
+def mcmc_moments(x, stream=None):
+    """(mean [dim], covariance [dim, dim]) of the rows of x [n, dim] on the GPU (gw_mcmc_moments)."""
+    torch = _torch()
+    x = _cuda_tensor(x, torch.float64, "x")
+    n, dim = x.shape
+    mean = torch.empty(dim, dtype=torch.float64, device=x.device)
+    cov = torch.empty((dim, dim), dtype=torch.float64, device=x.device)
+    _check(load_library().gw_mcmc_moments(dim, n, x.data_ptr(), mean.data_ptr(), cov.data_ptr(),
+                                          _stream_ptr(x.device.index, stream)))
+    return mean, cov
+
+
+def mcmc_count(counts, out=None, stream=None):
+    """Sum of the int32 counters `counts` [n] as a device int64 [1] (gw_mcmc_count)."""
+    torch = _torch()
+    counts = _cuda_tensor(counts, torch.int32, "counts")
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=counts.device)
+    out = _cuda_tensor(out, torch.int64, "out", (1,))
+    _check(load_library().gw_mcmc_count(counts.shape[0], counts.data_ptr(), out.data_ptr(),
+                                        _stream_ptr(counts.device.index, stream)))
+    return out
+
+
+def gather_rows(src, n_out: int, seed: int, stream_id: int, step: int, out=None, stream=None):
+    """n_out rows of src [n_src, dim] drawn with replacement by Philox
+    (seed, stream_id, step) (gw_gather_rows)."""
+    torch = _torch()
+    src = _cuda_tensor(src, torch.float64, "src")
+    n_src, dim = src.shape
+    if out is None:
+        out = torch.empty((int(n_out), dim), dtype=torch.float64, device=src.device)
+    out = _cuda_tensor(out, torch.float64, "out", (int(n_out), dim))
+    _check(load_library().gw_gather_rows(dim, int(n_out), src.data_ptr(), n_src, int(seed), int(stream_id),
+                                         int(step), out.data_ptr(), _stream_ptr(src.device.index, stream)))
+    return out
 
 
 class Flow:

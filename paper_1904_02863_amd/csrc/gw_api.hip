@@ -709,7 +709,7 @@ GW_DEFINE_SOURCE_HASH(api)
 
 extern "C" {
 
-int gw_version(void) { return 200; }
+int gw_version(void) { return 300; }
 
 const char *gw_source_hash(void) { return gw::source_hash_api(); }
 

@@ -226,6 +226,103 @@ __global__ __launch_bounds__(256) void update_mode_kernel(int64_t n, int *__rest
     window_accepts[c] = 0;
 }
 
+// ---------------------------------------------------------------- adaptation
+// Fixed-order sum of v over the 256 threads of the block; thread 0 gets it.
+__device__ __forceinline__ double block_sum256(double v, double *red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double total = red[0];
+    __syncthreads();
+    return total;
+}
+
+// One block.  Sample mean and covariance of the n rows of x [n][dim] (two
+// passes, fixed order) into mean_out [dim] and cov_out [dim][dim] when given;
+// with chol given, C = (2.38^2 / dim) scale^2 Cov + eps I, eps = floor
+// max(1, trace / dim), and its lower Cholesky factor into chol [dim][dim]
+// (upper part zero).  A pivot that is not positive is replaced by sqrt(eps),
+// which keeps the factor finite for degenerate chain sets.
+__global__ __launch_bounds__(256) void adapt_chol_kernel(int dim, int64_t n, const double *__restrict__ x,
+                                                         double scale, double floor, double *__restrict__ chol,
+                                                         double *__restrict__ mean_out, double *__restrict__ cov_out)
+{
+    __shared__ double red[256];
+    __shared__ double mean[kMaxDim];
+    __shared__ double c[kMaxDim * kMaxDim];
+    for (int i = 0; i < dim; ++i) {
+        double acc = 0.0;
+        for (int64_t r = threadIdx.x; r < n; r += 256) acc += x[r * dim + i];
+        const double total = block_sum256(acc, red);
+        if (threadIdx.x == 0) mean[i] = total / (double)n;
+    }
+    __syncthreads();
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double acc = 0.0;
+            for (int64_t r = threadIdx.x; r < n; r += 256)
+                acc += (x[r * dim + i] - mean[i]) * (x[r * dim + j] - mean[j]);
+            const double total = block_sum256(acc, red);
+            if (threadIdx.x == 0) c[i * kMaxDim + j] = total / (double)(n > 1 ? n - 1 : 1);
+        }
+    if (threadIdx.x != 0) return;
+    if (mean_out)
+        for (int i = 0; i < dim; ++i) mean_out[i] = mean[i];
+    if (cov_out)
+        for (int i = 0; i < dim; ++i)
+            for (int j = 0; j <= i; ++j) cov_out[i * dim + j] = cov_out[j * dim + i] = c[i * kMaxDim + j];
+    if (!chol) return;
+    const double f = 2.38 * 2.38 / (double)dim * scale * scale;
+    double tr = 0.0;
+    for (int i = 0; i < dim; ++i) tr += f * c[i * kMaxDim + i];
+    const double eps = floor * fmax(1.0, tr / (double)dim);
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j <= i; ++j) c[i * kMaxDim + j] = f * c[i * kMaxDim + j] + (i == j ? eps : 0.0);
+    // Cholesky-Banachiewicz, row by row
+    for (int i = 0; i < dim; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double v = c[i * kMaxDim + j];
+            for (int k = 0; k < j; ++k) v -= chol[i * dim + k] * chol[j * dim + k];
+            if (i == j) chol[i * dim + i] = v > 0.0 ? sqrt(v) : sqrt(eps);
+            else chol[i * dim + j] = v / chol[j * dim + j];
+        }
+        for (int j = i + 1; j < dim; ++j) chol[i * dim + j] = 0.0;
+    }
+}
+
+// out[0] = sum of counts[0 .. n) (one block, fixed order).
+__global__ __launch_bounds__(256) void count_sum_kernel(int64_t n, const int *__restrict__ counts,
+                                                        int64_t *__restrict__ out)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) acc += (double)counts[i];
+    const double total = block_sum256(acc, red);
+    if (threadIdx.x == 0) out[0] = (int64_t)total;
+}
+
+// dst[i] = src[floor(u_i n_src)], u_i uniform number i of (seed, stream, step):
+// rows drawn with replacement (training minibatches).
+__global__ __launch_bounds__(256) void gather_rows_kernel(int dim, int64_t n_out, const double *__restrict__ src,
+                                                          int64_t n_src, uint64_t seed, uint32_t stream, uint32_t step,
+                                                          double *__restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_out) return;
+    uint32_t a[4];
+    philox_block(seed, stream, step, (uint64_t)(i >> 1), a);
+    double u0, u1;
+    uniform_pair(a, u0, u1);
+    const double u = (i & 1) ? u1 : u0;
+    int64_t r = (int64_t)(u * (double)n_src);
+    r = r < n_src ? r : n_src - 1;
+    for (int j = 0; j < dim; ++j) dst[i * dim + j] = src[r * dim + j];
+}
+
 // ---------------------------------------------------------------- launchers
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
@@ -287,6 +384,28 @@ hipError_t update_mode(int64_t n, int *window_accepts, int window, double thresh
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(update_mode_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, window_accepts, window, threshold,
                        mode);
+    return hipGetLastError();
+}
+
+hipError_t adapt_chol(int dim, int64_t n, const double *x, double scale, double floor, double *chol, double *mean,
+                      double *cov, hipStream_t s)
+{
+    hipLaunchKernelGGL(adapt_chol_kernel, dim3(1), dim3(256), 0, s, dim, n, x, scale, floor, chol, mean, cov);
+    return hipGetLastError();
+}
+
+hipError_t count_sum(int64_t n, const int *counts, int64_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(count_sum_kernel, dim3(1), dim3(256), 0, s, n, counts, out);
+    return hipGetLastError();
+}
+
+hipError_t gather_rows(int dim, int64_t n_out, const double *src, int64_t n_src, uint64_t seed, uint32_t stream,
+                       uint32_t step, double *dst, hipStream_t s)
+{
+    if (n_out <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks_for(n_out)), dim3(256), 0, s, dim, n_out, src, n_src, seed,
+                       stream, step, dst);
     return hipGetLastError();
 }
 
@@ -375,6 +494,39 @@ int gw_mcmc_update_mode(int64_t n, int *window_accepts, int window, double thres
     if (n < 0 || window < 1 || (n > 0 && (!window_accepts || !mode))) return fail(GW_EINVAL, "bad arguments");
     hipError_t e = gw::mcmc::update_mode(n, window_accepts, window, threshold, mode, stream);
     return e == hipSuccess ? GW_OK : hip_fail(e, "gw_mcmc_update_mode");
+}
+
+int gw_mcmc_adapt_chol(int dim, int64_t n, const double *x, double scale, double floor, double *chol_out,
+                       hipStream_t stream)
+{
+    if (dim < 1 || dim > gw::mcmc::kMaxDim || n < 2 || !x || !chol_out)
+        return fail(GW_EINVAL, "gw_mcmc_adapt_chol needs dim in 1..16, at least 2 rows and device arrays");
+    if (!(scale > 0.0) || !(floor >= 0.0)) return fail(GW_EINVAL, "scale must be > 0 and floor >= 0");
+    hipError_t e = gw::mcmc::adapt_chol(dim, n, x, scale, floor, chol_out, nullptr, nullptr, stream);
+    return e == hipSuccess ? GW_OK : hip_fail(e, "gw_mcmc_adapt_chol");
+}
+
+int gw_mcmc_moments(int dim, int64_t n, const double *x, double *mean_out, double *cov_out, hipStream_t stream)
+{
+    if (dim < 1 || dim > gw::mcmc::kMaxDim || n < 2 || !x || (!mean_out && !cov_out))
+        return fail(GW_EINVAL, "gw_mcmc_moments needs dim in 1..16, at least 2 rows and an output");
+    hipError_t e = gw::mcmc::adapt_chol(dim, n, x, 1.0, 0.0, nullptr, mean_out, cov_out, stream);
+    return e == hipSuccess ? GW_OK : hip_fail(e, "gw_mcmc_moments");
+}
+
+int gw_mcmc_count(int64_t n, const int *counts, int64_t *out, hipStream_t stream)
+{
+    if (n < 0 || (n > 0 && !counts) || !out) return fail(GW_EINVAL, "bad arguments");
+    hipError_t e = gw::mcmc::count_sum(n, counts, out, stream);
+    return e == hipSuccess ? GW_OK : hip_fail(e, "gw_mcmc_count");
+}
+
+int gw_gather_rows(int dim, int64_t n_out, const double *src, int64_t n_src, uint64_t seed, uint32_t stream_id,
+                   uint32_t step, double *dst, hipStream_t stream)
+{
+    if (dim < 1 || n_out < 0 || n_src < 1 || !src || (n_out > 0 && !dst)) return fail(GW_EINVAL, "bad arguments");
+    hipError_t e = gw::mcmc::gather_rows(dim, n_out, src, n_src, seed, stream_id, step, dst, stream);
+    return e == hipSuccess ? GW_OK : hip_fail(e, "gw_gather_rows");
 }
 
 }  // extern "C"

@@ -35,6 +35,11 @@ hipError_t accept(int dim, int64_t n, uint64_t seed, uint32_t step, double *x, d
                   const double *x_prop, const double *lnl_prop, const double *lp_prop, const double *logq_prop,
                   const int *mode, int *window_accepts, int *total_accepts, hipStream_t s);
 hipError_t update_mode(int64_t n, int *window_accepts, int window, double threshold, int *mode, hipStream_t s);
+hipError_t adapt_chol(int dim, int64_t n, const double *x, double scale, double floor, double *chol, double *mean,
+                      double *cov, hipStream_t s);
+hipError_t count_sum(int64_t n, const int *counts, int64_t *out, hipStream_t s);
+hipError_t gather_rows(int dim, int64_t n_out, const double *src, int64_t n_src, uint64_t seed, uint32_t stream,
+                       uint32_t step, double *dst, hipStream_t s);
 
 }  // namespace mcmc
 }  // namespace gw

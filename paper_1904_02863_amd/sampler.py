@@ -5,20 +5,25 @@ The likelihood is gw_lnl_batch, Eq. (cbclike) of arXiv:1904.02863 (Sec. III).
 The paper notes (Sec. I) that the sampling algorithm is hard to parallelise
 while the likelihood is embarrassingly parallel; here thousands of chains step
 together, every step is one batched likelihood call, and every proposal,
-random number and acceptance decision is computed by the library's kernels:
+random number, acceptance decision and adaptation runs in the library's
+kernels:
 
 * random-walk MH: x' = x + L z (Philox normals), L the Cholesky factor of
-  (2.38^2/d) times the chains' sample covariance and a global scale tuned
-  toward 23.4% acceptance, both adapted during burn-in;
+  (2.38^2/d) s^2 Cov, Cov the chains' sample covariance and s a global scale
+  tuned toward 23.4% acceptance, both adapted during burn-in
+  (gw_mcmc_adapt_chol);
 * learned proposal: an affine-coupling flow (gw_flow) trained by maximum
-  likelihood on random-walk samples, used as an independence proposal
-  x' = F(z); the exact likelihood stays the judge, and a chain whose flow
-  acceptance over the last window falls below a threshold falls back to
-  random-walk proposals until its rate recovers.
+  likelihood on random-walk samples (minibatches drawn on the GPU,
+  gw_gather_rows), used as an independence proposal x' = F(z).  The exact
+  likelihood stays the judge.  Every rw_every-th step is a random-walk step
+  for all chains (a fixed cycle of two kernels that both leave the posterior
+  invariant, so the cycle does), and when the flow's acceptance over the
+  first window of a run is below a threshold the run falls back to
+  random-walk steps only.
 
 Sampler coordinates are x_i = logit(u_i), u_i the position of parameter i in
 a uniform prior box (see gw_mcmc_to_theta).  Host code here only orchestrates
-calls and keeps statistics; the arithmetic runs on the GPU.
+calls, moves a few scalars and keeps statistics.
 """
 from __future__ import annotations
 
@@ -28,12 +33,13 @@ import time
 
 import numpy as np
 
-from . import (Flow, Workspace, chain_normals, lnl_batch, mcmc_accept, mcmc_rw_propose, mcmc_to_theta,
-               mcmc_update_mode)
+from . import (Flow, Workspace, chain_normals, gather_rows, lnl_batch, mcmc_accept, mcmc_adapt_chol, mcmc_count,
+               mcmc_moments, mcmc_rw_propose, mcmc_to_theta)
 
 # Philox streams used by the sampler (the kernels use 1 for random-walk
 # normals and 2 for acceptance uniforms).
 STREAM_FLOW = 3
+STREAM_MINIBATCH = 4
 
 PARAM_NAMES = ("mc", "q", "dl", "phic", "tc", "ra", "sindec", "psi", "cosiota", "chi1", "chi2")
 
@@ -71,6 +77,26 @@ def from_sampler_coords(problem: Problem, x: np.ndarray) -> np.ndarray:
     return problem.box_lo + (problem.box_hi - problem.box_lo) * u
 
 
+def injection_box(theta_inj, spins: bool = False):
+    """The 11-coordinate prior box around an injection theta_inj (9 columns of
+    gw_lnl_batch): Mc [25, 35], q [0.5, 1], d_L [0.2, 3] x its value,
+    t_c [-0.1, 0.1], RA [0, 2 pi), sin Dec and cos iota [-1, 1], chi1, chi2
+    [-1, 1], and phi_c and psi on one period of their symmetries centred on
+    the injection: phi_c within pi of it (the phase is 2 pi periodic) and psi
+    within pi/4 of it (psi -> psi + pi/2 with phi_c -> phi_c + pi gives the
+    same signal, so a wider psi box would hold two copies of every mode).
+    Returns (box_lo, box_hi, the injection in box coordinates with zero
+    spins)."""
+    inj = np.asarray(theta_inj, dtype=np.float64)
+    lo = np.array([25.0, 0.5, 0.2 * inj[2], inj[3] - math.pi, -0.1, 0.0, -1.0, inj[7] - math.pi / 4, -1.0, -1.0,
+                   -1.0])
+    hi = np.array([35.0, 1.0, 3.0 * inj[2], inj[3] + math.pi, 0.1, 2 * math.pi, 1.0, inj[7] + math.pi / 4, 1.0,
+                   1.0, 1.0])
+    p_inj = np.array([inj[0], inj[1], inj[2], inj[3], inj[4], inj[5], math.sin(inj[6]), inj[7], math.cos(inj[8]),
+                      0.0, 0.0])
+    return lo, hi, p_inj
+
+
 class _Buffers:
     def __init__(self, torch, n, dim, device, theta_cols=9):
         f64 = dict(dtype=torch.float64, device=device)
@@ -82,6 +108,12 @@ class _Buffers:
         self.logq_prop = torch.empty(n, **f64)
         self.window = torch.zeros(n, dtype=torch.int32, device=device)
         self.total = torch.zeros(n, dtype=torch.int32, device=device)
+        self.count = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def accepted(self, counters) -> int:
+        """Sum of an acceptance counter array, summed on the GPU."""
+        mcmc_count(counters, out=self.count)
+        return int(self.count.item())
 
 
 def _evaluate(problem: Problem, x, buf: _Buffers, ws: Workspace):
@@ -91,13 +123,11 @@ def _evaluate(problem: Problem, x, buf: _Buffers, ws: Workspace):
               workspace=ws, precision=problem.precision)
 
 
-def adapted_cholesky(x: np.ndarray, floor: float = 1e-12) -> np.ndarray:
-    """Cholesky factor of (2.38^2 / d) Cov(x) over the chains (Haario et al. 2001
-    scaling), with a small diagonal floor."""
-    d = x.shape[1]
-    cov = np.cov(x, rowvar=False) * (2.38 ** 2 / d)
-    cov += np.eye(d) * floor * max(1.0, float(np.trace(cov)) / d)
-    return np.linalg.cholesky(cov)
+def _device_chol(chol, device):
+    import torch
+    if isinstance(chol, torch.Tensor):
+        return chol.to(device=device, dtype=torch.float64).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(chol, dtype=np.float64)).to(device)
 
 
 @dataclasses.dataclass
@@ -109,33 +139,42 @@ class ChainState:
 
 
 def init_chains(problem: Problem, x0: np.ndarray, ws: Workspace) -> ChainState:
+    """Chains at the rows of x0 with lnp = lnL + log prior there: every chain
+    starts at lnp = -inf and accepts x0 as its first proposal (a row whose
+    lnL is not finite keeps lnp = -inf)."""
     import torch
     dev = problem.data.device
-    x = torch.from_numpy(np.ascontiguousarray(x0, dtype=np.float64)).to(dev)
-    buf = _Buffers(torch, x.shape[0], problem.dim, dev, problem.theta_cols)
-    _evaluate(problem, x, buf, ws)
-    lnp = (buf.lnl + buf.lp).contiguous()
+    n = x0.shape[0]
+    x_start = torch.from_numpy(np.ascontiguousarray(x0, dtype=np.float64)).to(dev)
+    x = torch.empty_like(x_start)
+    lnp = torch.full((n,), -math.inf, dtype=torch.float64, device=dev)
+    buf = _Buffers(torch, n, problem.dim, dev, problem.theta_cols)
+    _evaluate(problem, x_start, buf, ws)
+    mcmc_accept(0, 0, x, lnp, x_start, buf.lnl, buf.lp)
     return ChainState(x, lnp, torch.zeros_like(lnp), 0)
 
 
-def run_random_walk(problem: Problem, state: ChainState, n_steps: int, seed: int, chol: np.ndarray, ws: Workspace,
+def run_random_walk(problem: Problem, state: ChainState, n_steps: int, seed: int, chol, ws: Workspace,
                     adapt_every: int = 0, record_every: int = 0, record_track: int | None = None,
                     collect_every: int = 0, target_accept: float = 0.234):
     """n_steps random-walk MH steps on every chain.  With adapt_every > 0 the
-    proposal is re-fitted that often: the Cholesky factor of (2.38^2/d) times
-    the chains' sample covariance, times a global scale that a Robbins-Monro
-    step moves toward the acceptance rate target_accept over the last window
-    (0.234, the optimum of Roberts, Gelman & Gilks 1997, by default).
-    Records the first record_track chains every record_every steps and
-    collects all chains every collect_every steps.  Returns (records
-    [n_records, track, dim] or None, acceptance rate, seconds, final Cholesky
-    factor, collected [n_collect * n_chains, dim] or None)."""
+    proposal is re-fitted that often on the GPU: the Cholesky factor of
+    (2.38^2/d) s^2 times the chains' sample covariance, s a global scale that
+    a Robbins-Monro step moves toward the acceptance rate target_accept over
+    the last window (0.234, the optimum of Roberts, Gelman & Gilks 1997, by
+    default).  Records the first record_track chains every record_every
+    steps (host copies) and collects all chains every collect_every steps
+    into a device array.  Returns (records [n_records, track, dim] or None,
+    acceptance rate, seconds, final Cholesky factor (device), collected
+    [n_collect * n_chains, dim] on the device or None)."""
     import torch
     n, dim = state.x.shape
     dev = state.x.device
     buf = _Buffers(torch, n, dim, dev, problem.theta_cols)
-    chol_t = torch.from_numpy(np.ascontiguousarray(chol)).to(dev)
-    records, collected = [], []
+    chol_t = _device_chol(chol, dev)
+    records = []
+    n_collect = n_steps // collect_every if collect_every else 0
+    collected = torch.empty((n_collect * n, dim), dtype=torch.float64, device=dev) if n_collect else None
     log_scale, window_start = 0.0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -146,21 +185,20 @@ def run_random_walk(problem: Problem, state: ChainState, n_steps: int, seed: int
         mcmc_accept(seed, step, state.x, state.lnp, buf.x_prop, buf.lnl, buf.lp, total_accepts=buf.total)
         state.step += 1
         if adapt_every and (i + 1) % adapt_every == 0:
-            accepted = int(buf.total.sum().item())
+            accepted = buf.accepted(buf.total)
             rate = (accepted - window_start) / (n * adapt_every)
             window_start = accepted
             log_scale = float(np.clip(log_scale + 2.0 * (rate - target_accept), -8.0, 2.0))
-            chol = adapted_cholesky(state.x.cpu().numpy()) * math.exp(log_scale)
-            chol_t = torch.from_numpy(np.ascontiguousarray(chol)).to(dev)
+            mcmc_adapt_chol(state.x, scale=math.exp(log_scale), out=chol_t)
         if record_every and (i + 1) % record_every == 0:
             records.append(state.x[:record_track].cpu().numpy())
         if collect_every and (i + 1) % collect_every == 0:
-            collected.append(state.x.cpu().numpy())
+            k = (i + 1) // collect_every - 1
+            collected[k * n:(k + 1) * n].copy_(state.x)
     torch.cuda.synchronize()
     seconds = time.perf_counter() - t0
-    rate = float(buf.total.sum().item()) / (n * max(n_steps, 1))
-    return ((np.stack(records) if records else None), rate, seconds, chol,
-            (np.concatenate(collected) if collected else None))
+    rate = buf.accepted(buf.total) / (n * max(n_steps, 1))
+    return (np.stack(records) if records else None), rate, seconds, chol_t, collected
 
 
 # ---------------------------------------------------------------- flow
@@ -196,69 +234,142 @@ def init_flow_params(dim: int, hidden: int, n_layers: int, seed: int, scale_last
     return np.concatenate(parts).astype(np.float32)
 
 
-def train_flow(samples: np.ndarray, n_layers: int = 8, hidden: int = 256, steps: int = 2000, batch: int = 4096,
+def train_flow(samples, n_layers: int = 8, hidden: int = 256, steps: int = 2000, batch: int = 4096,
                lr: float = 1e-3, seed: int = 0, device: int = 0, log_every: int = 0):
-    """Fit a flow to samples [n, dim] by maximum likelihood (Adam on minibatches
-    of a seeded shuffle).  Returns (flow, loss history, seconds)."""
+    """Fit a flow to samples [n, dim] (device tensor or host array) by maximum
+    likelihood: Adam on minibatches drawn with replacement on the GPU
+    (gw_gather_rows), after an affine standardisation by the samples' mean and
+    standard deviation (gw_mcmc_moments).  Returns (flow, loss history, seconds)."""
     import torch
-    dim = samples.shape[1]
-    flow = Flow(dim, default_masks(dim, n_layers, seed), hidden=hidden, device=device)
-    mu = samples.mean(axis=0)
-    sd = samples.std(axis=0) + 1e-12
-    flow.set_params(init_flow_params(dim, hidden, n_layers, seed), mu, np.log(sd))
-    rng = np.random.default_rng(seed + 1)
     dev = torch.device("cuda", device)
-    data = torch.from_numpy(np.ascontiguousarray(samples[rng.permutation(len(samples))])).to(dev)
-    n = data.shape[0]
+    if isinstance(samples, torch.Tensor):
+        data = samples.to(device=dev, dtype=torch.float64).contiguous()
+    else:
+        data = torch.from_numpy(np.ascontiguousarray(samples, dtype=np.float64)).to(dev)
+    n, dim = data.shape
+    flow = Flow(dim, default_masks(dim, n_layers, seed), hidden=hidden, device=device)
+    mean, cov = mcmc_moments(data)
+    mu = mean.cpu().numpy()
+    sd = np.sqrt(np.diag(cov.cpu().numpy())) + 1e-12
+    flow.set_params(init_flow_params(dim, hidden, n_layers, seed), mu, np.log(sd))
     batch = min(batch, n)
-    per_epoch = max(1, n // batch)
+    mb = torch.empty((batch, dim), dtype=torch.float64, device=dev)
     loss_t = torch.empty(1, dtype=torch.float64, device=dev)
     history = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
-        j = s % per_epoch
-        if j == 0 and s > 0:
-            data = data[torch.from_numpy(rng.permutation(n)).to(dev)].contiguous()
-        flow.train_step(data[j * batch:(j + 1) * batch], lr, loss_out=loss_t)
+        gather_rows(data, batch, seed, STREAM_MINIBATCH, s, out=mb)
+        flow.train_step(mb, lr, loss_out=loss_t)
         if log_every and (s % log_every == 0 or s == steps - 1):
             history.append((s, float(loss_t.item())))
     torch.cuda.synchronize()
     return flow, history, time.perf_counter() - t0
 
 
-def run_flow_mh(problem: Problem, state: ChainState, flow: Flow, n_steps: int, seed: int, chol: np.ndarray,
-                ws: Workspace, window: int = 64, threshold: float = 0.05, record_every: int = 0,
+def run_flow_mh(problem: Problem, state: ChainState, flow: Flow, n_steps: int, seed: int, chol, ws: Workspace,
+                rw_every: int = 8, window: int = 64, threshold: float = 0.05, record_every: int = 0,
                 record_track: int | None = None):
-    """Independence MH with flow proposals (random-walk fallback per chain).
-    Returns (records or None, acceptance rate, seconds, fraction of chain-steps
-    in fallback mode)."""
+    """Independence MH with flow proposals x' = F(z), alpha = min(1,
+    pi(x') q(x) / (pi(x) q(x'))), and every rw_every-th step (by the global
+    step count) a random-walk step for all chains, after which q is
+    recomputed at the chains' states.  Both kernels leave the posterior
+    invariant, so their fixed cycle does; the choice never depends on a
+    chain's own history.  If the flow's acceptance over the first `window`
+    flow steps of the run is below `threshold`, the rest of the run takes
+    random-walk steps only (random-walk fallback).  Returns (records or None,
+    acceptance rate, seconds, fraction of random-walk steps)."""
     import torch
     n, dim = state.x.shape
     dev = state.x.device
     buf = _Buffers(torch, n, dim, dev, problem.theta_cols)
-    chol_t = torch.from_numpy(np.ascontiguousarray(chol)).to(dev)
-    mode = torch.zeros(n, dtype=torch.int32, device=dev)
+    chol_t = _device_chol(chol, dev)
+    flow_mode = torch.zeros(n, dtype=torch.int32, device=dev)
     flow.inverse(state.x, z_out=buf.z, logq_out=state.logq)
-    records, fallback = [], 0
+    records, rw_steps, flow_steps, use_flow = [], 0, 0, True
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(n_steps):
         step = state.step
-        chain_normals(dim, n, seed, STREAM_FLOW, step, out=buf.z)
-        flow.forward(buf.z, x_out=buf.x_prop, logq_out=buf.logq_prop)
-        mcmc_rw_propose(state.x, chol_t, seed, step, buf.x_prop, mode=mode)
-        _evaluate(problem, buf.x_prop, buf, ws)
-        mcmc_accept(seed, step, state.x, state.lnp, buf.x_prop, buf.lnl, buf.lp, logq=state.logq,
-                    logq_prop=buf.logq_prop, mode=mode, window_accepts=buf.window, total_accepts=buf.total)
+        if not use_flow or (rw_every and step % rw_every == rw_every - 1):
+            mcmc_rw_propose(state.x, chol_t, seed, step, buf.x_prop)
+            _evaluate(problem, buf.x_prop, buf, ws)
+            mcmc_accept(seed, step, state.x, state.lnp, buf.x_prop, buf.lnl, buf.lp, total_accepts=buf.total)
+            if use_flow:
+                flow.inverse(state.x, z_out=buf.z, logq_out=state.logq)     # q at the moved states
+            rw_steps += 1
+        else:
+            chain_normals(dim, n, seed, STREAM_FLOW, step, out=buf.z)
+            flow.forward(buf.z, x_out=buf.x_prop, logq_out=buf.logq_prop)
+            _evaluate(problem, buf.x_prop, buf, ws)
+            mcmc_accept(seed, step, state.x, state.lnp, buf.x_prop, buf.lnl, buf.lp, logq=state.logq,
+                        logq_prop=buf.logq_prop, mode=flow_mode, window_accepts=buf.window, total_accepts=buf.total)
+            flow_steps += 1
+            if flow_steps == window and buf.accepted(buf.window) < threshold * n * window:
+                use_flow = False
         state.step += 1
-        if (i + 1) % window == 0:
-            mcmc_update_mode(buf.window, window, threshold, mode)
-            flow.inverse(state.x, z_out=buf.z, logq_out=state.logq)     # refresh after random-walk moves
-            fallback += int(mode.sum().item()) * window
         if record_every and (i + 1) % record_every == 0:
             records.append(state.x[:record_track].cpu().numpy())
     torch.cuda.synchronize()
     seconds = time.perf_counter() - t0
-    rate = float(buf.total.sum().item()) / (n * max(n_steps, 1))
-    return (np.stack(records) if records else None), rate, seconds, fallback / max(n * n_steps, 1)
+    rate = buf.accepted(buf.total) / (n * max(n_steps, 1))
+    return (np.stack(records) if records else None), rate, seconds, rw_steps / max(n_steps, 1)
+
+
+def compare_samplers(problem: Problem, p_inj: np.ndarray, ws: Workspace, n_chains: int = 4096, burn: int = 4000,
+                     steps: int = 1024, flow_steps: int = 3000, hidden: int = 256, n_layers: int = 8,
+                     seed: int = 20190408, track: int = 256, collect_every: int = 20, rw_every: int = 8,
+                     lr: float = 1e-3):
+    """The learned proposal against the plain method on one event: n_chains
+    random-walk chains start in a tight ball around the injection (spin
+    coordinates that the likelihood ignores start from their prior), burn in
+    with adaptation, then run `steps` production steps, recording `track`
+    chains every step and collecting all chains every collect_every steps
+    (the training set: steps / collect_every x n_chains samples, 2.1e5 by
+    default); a flow is trained on them; flow-proposal MH continues from the
+    random-walk states for one window, then for `steps` recorded steps.  ESS
+    is the rank-normalised bulk ESS (minimum over coordinates) of the tracked
+    chains scaled to all chains.  Returns a dict of the figures and the two
+    populations' final states (host arrays)."""
+    import torch
+
+    from . import diagnostics
+    dim = problem.dim
+    rng = np.random.default_rng(seed)
+    x0 = to_sampler_coords(problem, p_inj)[None] + rng.normal(scale=1e-3, size=(n_chains, dim))
+    if dim == 11 and not problem.spins:
+        x0[:, 9:] = rng.normal(scale=1.0, size=(n_chains, 2))
+    state = init_chains(problem, x0, ws)
+    chol = np.diag(np.full(dim, 1e-3))
+    _, acc_burn, t_burn, chol, _ = run_random_walk(problem, state, burn, seed, chol, ws, adapt_every=100)
+    rec_rw, acc_rw, t_rw, chol, collected = run_random_walk(problem, state, steps, seed, chol, ws, record_every=1,
+                                                            record_track=track, collect_every=collect_every)
+    n_train = int(collected.shape[0])
+    flow, hist, t_train = train_flow(collected, n_layers=n_layers, hidden=hidden, steps=flow_steps, batch=4096,
+                                     lr=lr, seed=seed + 2, log_every=max(1, flow_steps // 10))
+    fstate = ChainState(state.x.clone(), state.lnp.clone(), torch.zeros_like(state.lnp), state.step)
+    run_flow_mh(problem, fstate, flow, 64, seed + 3, chol, ws, rw_every=rw_every)
+    rec_fl, acc_fl, t_fl, rw_frac = run_flow_mh(problem, fstate, flow, steps, seed + 3, chol, ws, rw_every=rw_every,
+                                                record_every=1, record_track=track)
+    rw_draws, fl_draws = rec_rw.transpose(1, 0, 2), rec_fl.transpose(1, 0, 2)
+    ess_rw, per_rw = diagnostics.min_ess(rw_draws)
+    ess_fl, per_fl = diagnostics.min_ess(fl_draws)
+    scale = n_chains / track
+    rw_final, fl_final = state.x.cpu().numpy(), fstate.x.cpu().numpy()
+    ksp = diagnostics.ks_pvalues(rw_final, fl_final)
+    a, b = rw_draws.reshape(-1, dim), fl_draws.reshape(-1, dim)
+    zmean = (b.mean(axis=0) - a.mean(axis=0)) / (a.std(axis=0) * np.sqrt(1.0 / per_rw + 1.0 / per_fl))
+    return {
+        "random_walk": {"ess_per_s": ess_rw * scale / t_rw, "min_ess": ess_rw * scale, "seconds": t_rw,
+                        "acceptance": acc_rw, "acceptance_burn_in": acc_burn, "burn_in_seconds": t_burn,
+                        "ess_per_coordinate": (per_rw * scale).tolist()},
+        "flow": {"ess_per_s": ess_fl * scale / t_fl, "ess_per_s_with_training": ess_fl * scale / (t_fl + t_train),
+                 "min_ess": ess_fl * scale, "seconds": t_fl, "train_seconds": t_train, "acceptance": acc_fl,
+                 "random_walk_step_fraction": rw_frac, "loss_history": hist,
+                 "ess_per_coordinate": (per_fl * scale).tolist()},
+        "speedup_ess_per_s": (ess_fl / t_fl) / (ess_rw / t_rw),
+        "speedup_with_training": (ess_fl / (t_fl + t_train)) / (ess_rw / t_rw),
+        "ks_pvalues_final_states": ksp.tolist(), "ks_min_p": float(ksp.min()),
+        "mean_difference_z": zmean.tolist(), "train_samples": int(n_train),
+        "states": {"random_walk": rw_final, "flow": fl_final, "flow_lnp": fstate.lnp.cpu().numpy()},
+    }

@@ -17,7 +17,7 @@ STUB = r"""
 #include <stdint.h>
 #include <string.h>
 #ifndef VERSION
-#define VERSION 200
+#define VERSION 300
 #endif
 #ifndef GRID_SIZE
 #define GRID_SIZE 24
