@@ -206,6 +206,35 @@ int gw_lnl_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_dete
                  const double *theta, int n_param, int64_t n_samples,
                  double *lnl_out, int precision, unsigned flags, hipStream_t stream);
 
+/*
+ * gw_lnl_batch_static -- gw_lnl_batch without a workspace, allocating nothing.
+ * For callers that cannot allocate device memory during a call: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Arguments, results and kernels are those of gw_lnl_batch (same values bit
+ * for bit); its intermediate buffers live in one static device array of
+ * GW_STATIC_SCRATCH_BYTES per GPU, which the library holds on every GPU it
+ * runs on until the process ends.  The call uses the array of the current
+ * device.  Every call on a GPU shares that array: two calls that overlap on
+ * one GPU (different streams, or host threads without ordering) race and
+ * give wrong results; calls ordered on one stream are safe.  A call whose
+ * buffers exceed the array (gw_lnl_batch_static_bytes > GW_STATIC_SCRATCH_BYTES)
+ * returns GW_EINVAL and enqueues nothing; 64 MiB covers, for example, 3
+ * detectors x 259,585 bins x 4096 samples.  No bin tables are kept between
+ * calls, so each call costs one more short pass over the bins than a
+ * repeated gw_lnl_batch on a workspace.
+ */
+#define GW_STATIC_SCRATCH_BYTES (64ll << 20)
+int gw_lnl_batch_static(const gw_grid *grid, int n_det, const gw_detector *dets,
+                        const gw_c128 *data, const double *psd,
+                        const double *theta, int n_param, int64_t n_samples,
+                        double *lnl_out, int precision, unsigned flags, hipStream_t stream);
+
+/* Bytes of the static array a gw_lnl_batch_static call of this shape on the
+ * current device needs (a negative error code for bad arguments), and the
+ * array's size. */
+int64_t gw_lnl_batch_static_bytes(const gw_grid *grid, int n_det, int64_t n_samples, int precision, unsigned flags);
+int64_t gw_lnl_batch_static_capacity(void);
+
 /* One event of a ragged batch: its own grid, detectors, and rows. */
 typedef struct {
     gw_grid grid;

@@ -34,6 +34,7 @@ FLAG_ADD_NORM = 4
 # Every symbol include/gwlnl.h declares.
 EXPORTED = ("gw_workspace_create", "gw_workspace_destroy", "gw_workspace_reserve", "gw_workspace_bytes",
             "gw_workspace_set_timing", "gw_workspace_kernel_time", "gw_waveform_batch", "gw_lnl_batch",
+            "gw_lnl_batch_static", "gw_lnl_batch_static_bytes", "gw_lnl_batch_static_capacity",
             "gw_lnl_ragged", "gw_lnl_plan", "gw_ragged_tuning", "gw_pop_lnl", "gw_pop_prepare", "gw_pop_lnl_prepared",
             "gw_rb_edges", "gw_rb_create", "gw_rb_destroy", "gw_rb_lnl", "gw_rb_shape", "gw_rb_summary", "gw_last_error",
             "gw_version", "gw_abi_layout", "gw_source_hash",
@@ -133,6 +134,12 @@ def load_library() -> ctypes.CDLL:
                                           vp, u32, vp]
         lib.gw_lnl_batch.argtypes = [vp, ctypes.POINTER(GwGrid), i32, ctypes.POINTER(GwDetector), vp, vp, vp, i32,
                                      i64, vp, i32, u32, vp]
+        lib.gw_lnl_batch_static.argtypes = [ctypes.POINTER(GwGrid), i32, ctypes.POINTER(GwDetector), vp, vp, vp,
+                                            i32, i64, vp, i32, u32, vp]
+        lib.gw_lnl_batch_static_bytes.argtypes = [ctypes.POINTER(GwGrid), i32, i64, i32, u32]
+        lib.gw_lnl_batch_static_bytes.restype = i64
+        lib.gw_lnl_batch_static_capacity.argtypes = []
+        lib.gw_lnl_batch_static_capacity.restype = i64
         lib.gw_lnl_ragged.argtypes = [vp, i32, ctypes.POINTER(GwEvent), vp, vp, vp, i32, vp, i32, u32, vp]
         lib.gw_ragged_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         lib.gw_lnl_plan.argtypes = [vp, i64, i32, i64, i32, u32, ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -322,6 +329,52 @@ def lnl_batch(grid, tensors, vertices, data, psd, theta, *, precision: str = "fp
                                        theta.data_ptr(), n_param, n_samples, out.data_ptr(),
                                        PRECISIONS[precision], int(flags), _stream_ptr(dev, stream)))
     return out
+
+
+def lnl_batch_static(grid, tensors, vertices, data, psd, theta, *, precision: str = "fp64", flags: int = 0,
+                     out=None, stream=None):
+    """lnl_batch through gw_lnl_batch_static: no workspace, no device
+    allocation by the library (its buffers are a static array per GPU).
+    `out` must be given by callers that may not allocate either."""
+    torch = _torch()
+    g = make_grid(grid)
+    theta = _cuda_tensor(theta, torch.float64, "theta")
+    if theta.dim() != 2:
+        raise ValueError("theta must be [n_samples, n_param]")
+    n_samples, n_param = theta.shape
+    n_det = data.shape[0] if data.dim() == 2 else -1
+    data = _cuda_tensor(data, torch.complex128, "data", (n_det, g.n_bins))
+    psd = _cuda_tensor(psd, torch.float64, "psd", (n_det, g.n_bins))
+    dev = theta.device.index
+    if data.device.index != dev or psd.device.index != dev:
+        raise ValueError("data, psd and theta must be on the same device")
+    if out is None:
+        out = torch.empty(n_samples, dtype=torch.float64, device=theta.device)
+    out = _cuda_tensor(out, torch.float64, "out", (n_samples,))
+    dets = make_detectors(tensors, vertices) if n_param in (9, 11) or tensors is not None else (GwDetector * 1)()
+    with torch.cuda.device(dev):
+        _check(load_library().gw_lnl_batch_static(ctypes.byref(g), n_det, dets, data.data_ptr(), psd.data_ptr(),
+                                                  theta.data_ptr(), n_param, n_samples, out.data_ptr(),
+                                                  PRECISIONS[precision], int(flags), _stream_ptr(dev, stream)))
+    return out
+
+
+def lnl_batch_static_bytes(grid, n_det: int, n_samples: int, precision: str = "fp64", flags: int = 0,
+                           device: int = 0) -> int:
+    """Bytes of the static array a gw_lnl_batch_static call of this shape needs."""
+    torch = _torch()
+    g = make_grid(grid)
+    with torch.cuda.device(device):
+        n = load_library().gw_lnl_batch_static_bytes(ctypes.byref(g), int(n_det), int(n_samples),
+                                                     PRECISIONS[precision], int(flags))
+    if n < 0:
+        _check(int(n))
+    return int(n)
+
+
+def lnl_batch_static_capacity() -> int:
+    """GW_STATIC_SCRATCH_BYTES: the size of the static array per GPU."""
+    return int(load_library().gw_lnl_batch_static_capacity())
 
 
 def waveform_batch(grid, tensors, vertices, theta, *, flags: int = 0, out=None, workspace: Workspace | None = None,

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -218,12 +219,20 @@ int check_dets(int n_det, const gw_detector *dets, int n_param, gw::DetGeom *geo
     return GW_OK;
 }
 
-gw::TilePlan plan_tiles(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples, bool mixed, int form)
+// Launch plan of one event for a device with n_cu compute units; occ caches
+// the tile kernel's blocks per CU by form, precision and detector count.
+gw::TilePlan plan_tiles_on(int n_cu, int (&occ)[gw::kForms][2][gw::kMaxDet + 1], int64_t n_bins, int n_det,
+                           int64_t n_samples, bool mixed, int form)
 {
     const int tile_bins = gw::tile_bins_for(n_det, form, mixed);
-    int &occ = ws->blocks_per_cu[form][mixed ? 1 : 0][n_det];
-    if (occ == 0) occ = gw::lnl_tile_blocks_per_cu(n_det, tile_bins, mixed, form);
-    return gw::plan_single_event(n_bins, n_samples, form, tile_bins, (int64_t)ws->n_cu * occ);
+    int &o = occ[form][mixed ? 1 : 0][n_det];
+    if (o == 0) o = gw::lnl_tile_blocks_per_cu(n_det, tile_bins, mixed, form);
+    return gw::plan_single_event(n_bins, n_samples, form, tile_bins, (int64_t)n_cu * o);
+}
+
+gw::TilePlan plan_tiles(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples, bool mixed, int form)
+{
+    return plan_tiles_on(ws->n_cu, ws->blocks_per_cu, n_bins, n_det, n_samples, mixed, form);
 }
 
 // Workspace sections of one event.  The direct-form tables and the prefix
@@ -299,34 +308,38 @@ int timer_stop(gw_workspace *ws, hipEvent_t stop, hipStream_t stream)
     return GW_OK;
 }
 
-int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::DetGeom &geom, const gw_c128 *data,
-                  const double *psd, const double *theta, int n_param, int64_t n_samples, double *lnl_out,
-                  bool mixed, unsigned flags, hipStream_t stream)
+// The kernels of one gw_lnl_batch call over device memory at `base`, laid
+// out by `l` for `plan`.  With a workspace, the bin tables it already holds
+// are reused and the hot kernel is timed when timing is on; without one
+// (ws == nullptr) every kernel is launched and nothing is timed.
+int lnl_enqueue(gw_workspace *ws, char *base, const LnlLayout &l, const gw::TilePlan &plan, const gw_grid &grid,
+                int n_det, const gw::DetGeom &geom, const gw_c128 *data, const double *psd, const double *theta,
+                int n_param, int64_t n_samples, double *lnl_out, bool mixed, unsigned flags, hipStream_t stream)
 {
-    drop_ragged_graph(ws);               // the arena is about to be laid out for one event
     const int form = gw::tile_form(flags);
     const bool isco = (flags & GW_FLAG_TERM_ISCO) != 0;
-    const gw::TilePlan plan = plan_tiles(ws, grid.n_bins, n_det, n_samples, mixed, form);
-    const LnlLayout l = lnl_layout(grid.n_bins, n_det, n_samples, plan, flags);
-    if (int rc = ensure_capacity(ws, l.total, stream)) return rc;
+    auto sec = [base](size_t offset) { return static_cast<void *>(base + offset); };
     gw::EventBuffers eb;
-    eb.tab1 = at<gw::Tab1>(ws, l.tab1);
-    eb.tab2 = at<gw::Tab2>(ws, l.tab2);
-    eb.dcoef = at<double2>(ws, l.dcoef);
-    eb.edir = l.edir ? at<double2>(ws, l.edir) : nullptr;
-    eb.vdir = l.vdir ? at<double>(ws, l.vdir) : nullptr;
-    eb.qprefix = l.qprefix ? at<double>(ws, l.qprefix) : nullptr;
-    eb.qoffsets = l.qoffsets ? at<double>(ws, l.qoffsets) : nullptr;
-    eb.prep = at<double>(ws, l.prep_partials);
+    eb.tab1 = static_cast<gw::Tab1 *>(sec(l.tab1));
+    eb.tab2 = static_cast<gw::Tab2 *>(sec(l.tab2));
+    eb.dcoef = static_cast<double2 *>(sec(l.dcoef));
+    eb.edir = l.edir ? static_cast<double2 *>(sec(l.edir)) : nullptr;
+    eb.vdir = l.vdir ? static_cast<double *>(sec(l.vdir)) : nullptr;
+    eb.qprefix = l.qprefix ? static_cast<double *>(sec(l.qprefix)) : nullptr;
+    eb.qoffsets = l.qoffsets ? static_cast<double *>(sec(l.qoffsets)) : nullptr;
+    eb.prep = static_cast<double *>(sec(l.prep_partials));
     eb.prep_blocks = l.prep_blocks;
-    eb.sums = at<double>(ws, l.event_sums);
-    eb.k_limit = at<int64_t>(ws, l.k_limit);
-    eb.queue = plan.rounds > 0 ? at<unsigned>(ws, l.queue) : nullptr;
-    auto *rec = at<double>(ws, l.records);
-    auto *part = at<double2>(ws, l.partials);
+    eb.sums = static_cast<double *>(sec(l.event_sums));
+    eb.k_limit = static_cast<int64_t *>(sec(l.k_limit));
+    eb.queue = plan.rounds > 0 ? static_cast<unsigned *>(sec(l.queue)) : nullptr;
+    auto *rec = static_cast<double *>(sec(l.records));
+    auto *part = static_cast<double2 *>(sec(l.partials));
     hipError_t e;
-    if ((e = bin_tables(ws, grid, l.tab1, l.tab2, eb.tab1, eb.tab2, stream)) != hipSuccess)
-        return hip_fail(e, "event tables");
+    if (ws)
+        e = bin_tables(ws, grid, l.tab1, l.tab2, eb.tab1, eb.tab2, stream);
+    else
+        e = gw::launch_event_tables(grid, eb.tab1, eb.tab2, stream);
+    if (e != hipSuccess) return hip_fail(e, "event tables");
     if ((e = gw::launch_event_data(grid, n_det, data, psd, eb, flags, stream)) != hipSuccess)
         return hip_fail(e, "event data");
     if ((e = gw::launch_sample_prep(grid, n_samples, n_param, n_det, false, isco, geom, theta, rec, stream)) !=
@@ -334,15 +347,73 @@ int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::De
         return hip_fail(e, "sample prep");
     if (form == gw::kFormSplitIsco && (e = gw::launch_isco_limit(n_samples, rec, eb.k_limit, stream)) != hipSuccess)
         return hip_fail(e, "template-end limit");
-    hipEvent_t t_start, t_stop;
-    if (int rc = timer_pair(ws, stream, &t_start, &t_stop)) return rc;
+    hipEvent_t t_start = nullptr, t_stop = nullptr;
+    if (ws) {
+        if (int rc = timer_pair(ws, stream, &t_start, &t_stop)) return rc;
+    }
     if (t_start && (e = hipEventRecord(t_start, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if ((e = gw::launch_lnl_tiles(grid, n_det, n_samples, plan, mixed, form, eb, rec, part, stream)) != hipSuccess)
         return hip_fail(e, "lnl tiles");
-    if (int rc = timer_stop(ws, t_stop, stream)) return rc;
+    if (ws) {
+        if (int rc = timer_stop(ws, t_stop, stream)) return rc;
+    }
     if ((e = gw::launch_lnl_finalize(grid, n_samples, n_det, plan, part, rec, eb, flags, lnl_out, stream)) !=
         hipSuccess)
         return hip_fail(e, "lnl finalize");
+    return GW_OK;
+}
+
+int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::DetGeom &geom, const gw_c128 *data,
+                  const double *psd, const double *theta, int n_param, int64_t n_samples, double *lnl_out,
+                  bool mixed, unsigned flags, hipStream_t stream)
+{
+    drop_ragged_graph(ws);               // the arena is about to be laid out for one event
+    const gw::TilePlan plan = plan_tiles(ws, grid.n_bins, n_det, n_samples, mixed, gw::tile_form(flags));
+    const LnlLayout l = lnl_layout(grid.n_bins, n_det, n_samples, plan, flags);
+    if (int rc = ensure_capacity(ws, l.total, stream)) return rc;
+    return lnl_enqueue(ws, static_cast<char *>(ws->base), l, plan, grid, n_det, geom, data, psd, theta, n_param,
+                       n_samples, lnl_out, mixed, flags, stream);
+}
+
+// ------------------------------------------------------------------ allocation-free likelihood
+// Device memory of gw_lnl_batch_static: one array per GPU, held from the
+// library's load until the process ends.  Host code never passes `scratch`
+// itself to a kernel or a copy (in host code the name is a host-side stand-in,
+// not a device address); it uses the address hipGetSymbolAddress returns for
+// the device that is current.
+constexpr size_t kStaticScratchBytes = (size_t)GW_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kStaticMaxDevices = 64;
+
+struct StaticDevice {
+    bool ready = false;
+    char *ptr = nullptr;                 // device address of `scratch` on this device
+    int n_cu = 0;
+    int blocks_per_cu[gw::kForms][2][gw::kMaxDet + 1] = {};
+};
+
+std::mutex g_static_mutex;
+StaticDevice g_static[kStaticMaxDevices];
+
+// The scratch address and CU count of the current device, looked up once
+// per device (with that device current).  Allocates nothing.
+int static_device(int device, StaticDevice **out)
+{
+    if (device < 0 || device >= kStaticMaxDevices) return fail(GW_EINVAL, "device index out of range");
+    StaticDevice &d = g_static[device];
+    if (!d.ready) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        int n_cu = 0;
+        e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
+        if (e != hipSuccess || n_cu < 1) return hip_fail(e, "hipDeviceGetAttribute(multiprocessor count)");
+        d.ptr = static_cast<char *>(ptr);
+        d.n_cu = n_cu;
+        d.ready = true;
+    }
+    *out = &d;
     return GW_OK;
 }
 
@@ -833,6 +904,59 @@ int gw_lnl_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_dete
     if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
     return lnl_one_event(ws, *grid, n_det, geom, data, psd, theta, n_param, n_samples, lnl_out,
                          precision == GW_PREC_MIXED, flags, stream);
+}
+
+int64_t gw_lnl_batch_static_capacity(void) { return (int64_t)kStaticScratchBytes; }
+
+int64_t gw_lnl_batch_static_bytes(const gw_grid *grid, int n_det, int64_t n_samples, int precision, unsigned flags)
+{
+    if (check_grid(grid) != GW_OK) return -1;
+    if (n_det < 1 || n_det > gw::kMaxDet || n_samples < 0) return fail(GW_EINVAL, "n_det or n_samples out of range");
+    if (precision != GW_PREC_FP64 && precision != GW_PREC_MIXED) return fail(GW_EINVAL, "unknown precision");
+    if (flags & ~kLnlFlags) return fail(GW_EINVAL, "unknown flag bits");
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_static_mutex);
+    StaticDevice *d = nullptr;
+    if (int rc = static_device(device, &d)) return rc;
+    const gw::TilePlan plan = plan_tiles_on(d->n_cu, d->blocks_per_cu, grid->n_bins, n_det, n_samples,
+                                            precision == GW_PREC_MIXED, gw::tile_form(flags));
+    return (int64_t)lnl_layout(grid->n_bins, n_det, n_samples, plan, flags).total;
+}
+
+int gw_lnl_batch_static(const gw_grid *grid, int n_det, const gw_detector *dets, const gw_c128 *data,
+                        const double *psd, const double *theta, int n_param, int64_t n_samples, double *lnl_out,
+                        int precision, unsigned flags, hipStream_t stream)
+{
+    if (int rc = check_grid(grid)) return rc;
+    if (n_det < 1 || n_det > gw::kMaxDet) return fail(GW_EINVAL, "n_det out of range");
+    if (!gw::valid_n_param(n_param)) return fail(GW_EINVAL, "n_param must be 5, 7, 9 or 11");
+    if (n_samples < 0) return fail(GW_EINVAL, "n_samples must be >= 0");
+    if (!data || !psd) return fail(GW_EINVAL, "data or psd is NULL");
+    if (n_samples > 0 && (!theta || !lnl_out)) return fail(GW_EINVAL, "theta or lnl_out is NULL");
+    if (precision != GW_PREC_FP64 && precision != GW_PREC_MIXED) return fail(GW_EINVAL, "unknown precision");
+    if (flags & ~kLnlFlags) return fail(GW_EINVAL, "unknown flag bits");
+    if (int rc = gw::check_build()) return rc;
+    gw::DetGeom geom;
+    if (int rc = check_dets(n_det, dets, n_param, &geom)) return rc;
+    if (n_samples == 0) return GW_OK;
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    const bool mixed = precision == GW_PREC_MIXED;
+    std::lock_guard<std::mutex> lock(g_static_mutex);
+    StaticDevice *d = nullptr;
+    if (int rc = static_device(device, &d)) return rc;
+    const gw::TilePlan plan = plan_tiles_on(d->n_cu, d->blocks_per_cu, grid->n_bins, n_det, n_samples, mixed,
+                                            gw::tile_form(flags));
+    const LnlLayout l = lnl_layout(grid->n_bins, n_det, n_samples, plan, flags);
+    if (l.total > kStaticScratchBytes)
+        return fail(GW_EINVAL, "gw_lnl_batch_static: this call needs " + std::to_string(l.total) +
+                                   " bytes of scratch, more than the library's static " +
+                                   std::to_string(kStaticScratchBytes) + "; use gw_lnl_batch with a workspace");
+    return lnl_enqueue(nullptr, d->ptr, l, plan, *grid, n_det, geom, data, psd, theta, n_param, n_samples, lnl_out,
+                       mixed, flags, stream);
 }
 
 int gw_waveform_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_detector *dets,
