@@ -33,15 +33,19 @@ if ROOT not in sys.path:
 
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector peak
 HBM_PEAK_GBS = 8000.0
-# Sources whose content fixes the tile kernel's machine code; a profile
-# summary records their SHA-256 next to the traffic it measured.
-KERNEL_SOURCES = ("paper_1904_02863_amd/csrc/gw_kernels.hip", "paper_1904_02863_amd/csrc/gw_device_math.h",
-                  "paper_1904_02863_amd/csrc/gw_internal.h", "paper_1904_02863_amd/csrc/gw_template.h",
-                  "paper_1904_02863_amd/csrc/gw_phasor_table.h", "paper_1904_02863_amd/csrc/gw_plan.h",
-                  "paper_1904_02863_amd/csrc/gw_relbin.hip", "paper_1904_02863_amd/build.py")
 PROFILE_SUMMARY = "profiles/lnl_tile_kernel_bbh-3det-128s.md"
 WAVEFORM_PROFILE = "profiles/waveform_kernel_bbh-3det-128s.md"
 RELBIN_PROFILE = "profiles/relbin_lnl_kernel_bns-15hz-512s.md"
+# Sources whose content fixes each profiled kernel's machine code and launch;
+# a profile summary records their SHA-256 next to the figures it measured.
+_CSRC = "paper_1904_02863_amd/csrc/"
+_COMMON = tuple(_CSRC + f for f in ("gw_device_math.h", "gw_internal.h", "gw_template.h", "gw_phasor_table.h")) + (
+    "paper_1904_02863_amd/build.py",)
+PROFILE_SOURCES = {
+    PROFILE_SUMMARY: (_CSRC + "gw_kernels.hip", _CSRC + "gw_plan.h") + _COMMON,
+    WAVEFORM_PROFILE: (_CSRC + "gw_waveform.hip",) + _COMMON,
+    RELBIN_PROFILE: (_CSRC + "gw_relbin.hip",) + _COMMON,
+}
 
 
 def flops_per_pair(n_det: int, mixed: bool = False, direct: bool = False) -> int:
@@ -63,38 +67,40 @@ def flops_per_pair(n_det: int, mixed: bool = False, direct: bool = False) -> int
     return 19 + (1 if mixed else 34) + per_det[0] + per_det[1] * (n_det - 1)
 
 
-def kernel_fingerprint() -> str:
+def kernel_fingerprint(summary: str = PROFILE_SUMMARY) -> str:
+    """SHA-256 over the sources of the kernel a profile summary covers."""
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in PROFILE_SOURCES[summary]:
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def _profile_value(name: str, summary: str):
-    """A named figure of a committed counter summary, or None when the kernel
-    sources changed since it was taken."""
+def _profile_value(name: str, summary: str, sources: str | None = None):
+    """A named figure of a committed counter summary, or None when the
+    sources of its kernel (those of `sources`, a key of PROFILE_SOURCES,
+    by default the summary itself) changed since it was taken."""
     path = os.path.join(ROOT, summary)
     if not os.path.exists(path):
         return None
     text = open(path).read()
     sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
     val = re.search(rf"{name}:\s*([0-9.eE+]+)", text)
-    if not sha or not val or sha.group(1) != kernel_fingerprint():
+    if not sha or not val or sha.group(1) != kernel_fingerprint(sources or summary):
         return None
     return float(val.group(1))
 
 
-def measured_traffic(key: str, summary: str = PROFILE_SUMMARY):
+def measured_traffic(key: str, summary: str = PROFILE_SUMMARY, sources: str | None = None):
     """HBM bytes per launch of a kernel from a committed counter summary, or
     None when the kernel sources changed since it was taken."""
-    return _profile_value(f"traffic_bytes_per_launch_{key}", summary)
+    return _profile_value(f"traffic_bytes_per_launch_{key}", summary, sources)
 
 
-def measured_executed_flops(key: str, summary: str = PROFILE_SUMMARY):
+def measured_executed_flops(key: str, summary: str = PROFILE_SUMMARY, sources: str | None = None):
     """FP64 flops per launch the hardware counters saw the kernel execute
     (FMA = 2), or None as for measured_traffic."""
-    return _profile_value(f"executed_fp64_flops_per_launch_{key}", summary)
+    return _profile_value(f"executed_fp64_flops_per_launch_{key}", summary, sources)
 
 
 def calibration_copy(mib: int, device):
@@ -507,16 +513,33 @@ def bench_waveform(args):
         raise SystemExit("non-finite waveform")
     written = out.numel() * 16
     read = g.n_bins * (32 + 16)
+    # the write ceiling: the library's plain store kernel over the same buffer
+    for _ in range(3):
+        gw.fill_c128(out, 0.0)
+    t_fill = []
+    for _ in range(max(args.steps // 5, 5)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        gw.fill_c128(out, 0.0)
+        b.record()
+        t_fill.append((a, b))
+    torch.cuda.synchronize()
+    fill_s = sum(a.elapsed_time(b) for a, b in t_fill) / len(t_fill) / 1e3
+    store_gbs = written / fill_s / 1e9
+    achieved = (written + read) / kernel_s / 1e9
     result = {
         "metric": "waveforms/s (3-det,128 s TaylorF2 responses)", "value": n / t, "unit": "waveforms/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "waveform", "n_samples": n, "n_det": w.n_det, "n_bins": g.n_bins},
-        "roofline": {"bound": "hbm", "achieved": (written + read) / kernel_s / 1e9, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": (written + read) / kernel_s / 1e9 / HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("waveform", WAVEFORM_PROFILE) if n == 256 else None,
                      "kernel": "waveform_kernel", "kernel_ms": kernel_s * 1e3,
-                     "algorithmic_bytes": written + read},
+                     "algorithmic_bytes": written + read,
+                     "store_ceiling": {"kernel": "fill_c128_kernel", "bytes_written": written,
+                                       "kernel_ms": fill_s * 1e3, "achieved": store_gbs},
+                     "frac_of_store_ceiling": achieved / store_gbs},
     }
     if not args.no_cpu_baseline:
         import oracle

@@ -189,6 +189,11 @@ int gw_waveform_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw
                       const double *theta, int n_param, int64_t n_samples,
                       gw_c128 *h_out, unsigned flags, hipStream_t stream);
 
+/* out[i] = re + i im for i < n (device complex array): a plain store stream
+ * with the store pattern of gw_waveform_batch, e.g. to clear a template
+ * buffer; it is also the write ceiling that call is measured against. */
+int gw_fill_c128(gw_c128 *out, int64_t n, double re, double im, hipStream_t stream);
+
 /*
  * gw_lnl_batch -- Eq. (cbclike) for every sample of one event.
  *   grid      host, the frequency grid shared by all detectors.

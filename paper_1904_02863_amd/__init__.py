@@ -33,7 +33,7 @@ FLAG_ADD_NORM = 4
 
 # Every symbol include/gwlnl.h declares.
 EXPORTED = ("gw_workspace_create", "gw_workspace_destroy", "gw_workspace_reserve", "gw_workspace_bytes",
-            "gw_workspace_set_timing", "gw_workspace_kernel_time", "gw_waveform_batch", "gw_lnl_batch",
+            "gw_workspace_set_timing", "gw_workspace_kernel_time", "gw_waveform_batch", "gw_fill_c128", "gw_lnl_batch",
             "gw_lnl_batch_static", "gw_lnl_batch_static_bytes", "gw_lnl_batch_static_capacity",
             "gw_lnl_ragged", "gw_lnl_plan", "gw_ragged_tuning", "gw_pop_lnl", "gw_pop_prepare", "gw_pop_lnl_prepared",
             "gw_rb_edges", "gw_rb_create", "gw_rb_destroy", "gw_rb_lnl", "gw_rb_shape", "gw_rb_summary", "gw_last_error",
@@ -134,6 +134,7 @@ def load_library() -> ctypes.CDLL:
                                           vp, u32, vp]
         lib.gw_lnl_batch.argtypes = [vp, ctypes.POINTER(GwGrid), i32, ctypes.POINTER(GwDetector), vp, vp, vp, i32,
                                      i64, vp, i32, u32, vp]
+        lib.gw_fill_c128.argtypes = [vp, i64, ctypes.c_double, ctypes.c_double, vp]
         lib.gw_lnl_batch_static.argtypes = [ctypes.POINTER(GwGrid), i32, ctypes.POINTER(GwDetector), vp, vp, vp,
                                             i32, i64, vp, i32, u32, vp]
         lib.gw_lnl_batch_static_bytes.argtypes = [ctypes.POINTER(GwGrid), i32, i64, i32, u32]
@@ -328,6 +329,17 @@ def lnl_batch(grid, tensors, vertices, data, psd, theta, *, precision: str = "fp
     _check(load_library().gw_lnl_batch(ws.handle, ctypes.byref(g), n_det, dets, data.data_ptr(), psd.data_ptr(),
                                        theta.data_ptr(), n_param, n_samples, out.data_ptr(),
                                        PRECISIONS[precision], int(flags), _stream_ptr(dev, stream)))
+    return out
+
+
+def fill_c128(out, value: complex = 0.0, stream=None):
+    """out[...] = value for a contiguous complex128 CUDA tensor (gw_fill_c128)."""
+    torch = _torch()
+    out = _cuda_tensor(out, torch.complex128, "out")
+    dev = out.device.index
+    with torch.cuda.device(dev):
+        _check(load_library().gw_fill_c128(out.data_ptr(), out.numel(), float(complex(value).real),
+                                           float(complex(value).imag), _stream_ptr(dev, stream)))
     return out
 
 

@@ -20,7 +20,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgwlnl.so")
-SOURCES = ["gw_api.hip", "gw_kernels.hip", "gw_flow.hip", "gw_mcmc.hip", "gw_pop.hip", "gw_relbin.hip"]
+SOURCES = ["gw_api.hip", "gw_kernels.hip", "gw_waveform.hip", "gw_flow.hip", "gw_mcmc.hip", "gw_pop.hip",
+           "gw_relbin.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -60,8 +61,9 @@ def hipcc() -> str:
     return path
 
 
-def build(verbose: bool = False, save_temps_dir: str | None = None) -> str:
-    """Compile every source and link libgwlnl.so; returns its path."""
+def build(verbose: bool = False, save_temps_dir: str | None = None, defines: tuple[str, ...] = ()) -> str:
+    """Compile every source and link libgwlnl.so; returns its path.
+    `defines` (e.g. "GW_TILE_UNROLL=4") set the tuning macros of the kernels."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     cc = hipcc()
@@ -69,7 +71,7 @@ def build(verbose: bool = False, save_temps_dir: str | None = None) -> str:
 
     def compile_one(src):
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [cc, *HIPCC_FLAGS, ident, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *HIPCC_FLAGS, *[f"-D{d}" for d in defines], ident, "-c", os.path.join(CSRC, src), "-o", obj]
         if save_temps_dir:
             os.makedirs(save_temps_dir, exist_ok=True)
             cmd += ["-save-temps=obj"]
@@ -94,4 +96,4 @@ def build(verbose: bool = False, save_temps_dir: str | None = None) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, defines=tuple(a[2:] for a in sys.argv[1:] if a.startswith("-D"))))

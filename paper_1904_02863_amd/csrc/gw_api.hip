@@ -767,7 +767,7 @@ int check_build()
 {
     const char *mine = source_hash_api();
     const char *units[] = {source_hash_kernels(), source_hash_flow(), source_hash_mcmc(), source_hash_pop(),
-                           source_hash_relbin()};
+                           source_hash_relbin(), source_hash_waveform()};
     for (const char *u : units)
         if (std::strcmp(u, mine) != 0)
             return fail(GW_EABI, std::string("the library was linked from objects compiled from different sources (") +
@@ -997,6 +997,17 @@ int gw_waveform_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw
     if ((e = gw::launch_waveform(*grid, n_out, n_samples, tab1, tab2, rec, h_out, stream)) != hipSuccess)
         return hip_fail(e, "waveform");
     return timer_stop(ws, t_stop, stream);
+}
+
+int gw_fill_c128(gw_c128 *out, int64_t n, double re, double im, hipStream_t stream)
+{
+    if (n < 0 || (n > 0 && !out)) return fail(GW_EINVAL, "bad arguments");
+    int device = 0, n_cu = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess || n_cu < 1) return hip_fail(e, "gw_fill_c128: device attributes");
+    e = gw::launch_fill_c128(n, re, im, out, n_cu, stream);
+    return e == hipSuccess ? GW_OK : hip_fail(e, "gw_fill_c128");
 }
 
 int gw_lnl_ragged(gw_workspace *ws, int n_events, const gw_event *events, const gw_c128 *data_packed,

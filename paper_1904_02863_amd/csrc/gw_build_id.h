@@ -17,6 +17,7 @@ const char *source_hash_flow();
 const char *source_hash_mcmc();
 const char *source_hash_pop();
 const char *source_hash_relbin();
+const char *source_hash_waveform();
 // GW_OK when every translation unit reports the same hash, else GW_EABI
 // (with the message of gw_last_error set).
 int check_build();

@@ -183,6 +183,7 @@ hipError_t launch_lnl_finalize(const gw_grid &grid, int64_t n_samples, int n_det
 
 hipError_t launch_waveform(const gw_grid &grid, int n_out, int64_t n_samples, const Tab1 *tab1, const Tab2 *tab2,
                            const double *records, gw_c128 *h_out, hipStream_t stream);
+hipError_t launch_fill_c128(int64_t n, double re, double im, gw_c128 *out, int n_cu, hipStream_t stream);
 
 hipError_t launch_ragged(const RaggedLaunch &r, hipStream_t stream);
 int lnl_ragged_blocks_per_cu(int n_det, int tile_bins, bool mixed, int form);

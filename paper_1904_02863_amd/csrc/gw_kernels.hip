@@ -922,83 +922,6 @@ __global__ __launch_bounds__(kBlock) void ragged_finalize_kernel(const RaggedEve
                              re.sums, re.qprefix);
 }
 
-// ---------------------------------------------------------------- waveform materialisation
-// h[s][ch][k] = a_k P_ch e^{-i Phi_0,k} e^{-2 pi i f_k delta_ch} for k <= K_s
-// (zero above the template end).  Block (span of kWaveBins bins, group of
-// kWaveSamples samples): thread t holds the tables of bins span + t + kBlock j,
-// j < kWaveSteps, in registers and writes them for every sample of the group,
-// so the tables are read once per group rather than once per sample (read
-// per sample they cost as many bytes as the output at 256 samples), and
-// every store instruction of a wave covers 64 consecutive bins.  A sample's
-// record is the same for the whole block (scalar loads).  The delay phasor of
-// each channel is evaluated exactly at the thread's first bin and advanced by
-// the fixed rotation e^{-2 pi i kBlock df delta} to its next bins.
-constexpr int kWaveSteps = 4;
-constexpr int kWaveBins = kBlock * kWaveSteps;
-#ifndef GW_WAVE_SAMPLES
-#define GW_WAVE_SAMPLES 4
-#endif
-constexpr int kWaveSamples = GW_WAVE_SAMPLES;
-
-__global__ __launch_bounds__(kBlock) void waveform_kernel(int64_t n_bins, int n_out, int64_t n_samples,
-                                                           int64_t n_spans, double df,
-                                                           const Tab1 *__restrict__ tab1,
-                                                           const Tab2 *__restrict__ tab2,
-                                                           const double *__restrict__ rec,
-                                                           double2 *__restrict__ h_out)
-{
-    const int64_t span = (int64_t)blockIdx.x % n_spans;
-    const int64_t s0 = ((int64_t)blockIdx.x / n_spans) * kWaveSamples;
-    const int64_t k0 = span * kWaveBins + threadIdx.x;
-    if (k0 >= n_bins) return;
-    Tab1 t[kWaveSteps];
-    double amp[kWaveSteps];
-#pragma unroll
-    for (int j = 0; j < kWaveSteps; ++j) {
-        const int64_t k = min(k0 + (int64_t)kBlock * j, n_bins - 1);
-        t[j] = tab1[k];
-        amp[j] = tab2[k].amp;
-    }
-    const double f0 = tab2[k0].f;
-    const int64_t s_end = min(s0 + (int64_t)kWaveSamples, n_samples);
-    for (int64_t s = s0; s < s_end; ++s) {
-        const int status = (int)rec[kRecStatus * n_samples + s];
-        const int64_t kcut = (int64_t)rec[kRecKcut * n_samples + s];
-        const PhaseCoef cf = load_coef(rec, n_samples, s);
-        double er[kWaveSteps], ei[kWaveSteps];
-#pragma unroll
-        for (int j = 0; j < kWaveSteps; ++j) gw_phasor_turns(turns_phase(cf, t[j]), er[j], ei[j]);
-        for (int d = 0; d < n_out; ++d) {
-            const double pr = rec[(kRecDet + kRecFieldsPerDet * d) * n_samples + s];
-            const double pi = rec[(kRecDet + kRecFieldsPerDet * d + 1) * n_samples + s];
-            const double delta = rec[(kRecDet + kRecFieldsPerDet * d + 2) * n_samples + s];
-            // T = P e^{-2 pi i f delta} at the thread's first bin; step rotation
-            double rr = 1.0, ri = 0.0, sr = 1.0, si = 0.0;
-            if (delta != 0.0) {
-                gw_phasor_turns(f0 * delta, rr, ri);
-                gw_phasor_turns((double)kBlock * df * delta, sr, si);
-            }
-            double tr = pr * rr - pi * ri, ti = pr * ri + pi * rr;
-            double2 *out = h_out + ((int64_t)s * n_out + d) * n_bins;
-#pragma unroll
-            for (int j = 0; j < kWaveSteps; ++j) {
-                const int64_t k = k0 + (int64_t)kBlock * j;
-                if (k < n_bins) {
-                    double2 h;
-                    h.x = amp[j] * (tr * er[j] - ti * ei[j]);
-                    h.y = amp[j] * (tr * ei[j] + ti * er[j]);
-                    if (k > kcut) h = make_double2(0.0, 0.0);
-                    if (status != 0) h = make_double2(NAN, NAN);
-                    out[k] = h;
-                }
-                const double nr = tr * sr - ti * si;
-                ti = tr * si + ti * sr;
-                tr = nr;
-            }
-        }
-    }
-}
-
 // ---------------------------------------------------------------- launchers
 static int grid_blocks(int64_t n, int cap)
 {
@@ -1200,17 +1123,6 @@ hipError_t launch_lnl_finalize(const gw_grid &grid, int64_t n_samples, int n_det
     return hipGetLastError();
 }
 
-hipError_t launch_waveform(const gw_grid &grid, int n_out, int64_t n_samples, const Tab1 *tab1, const Tab2 *tab2,
-                           const double *records, gw_c128 *h_out, hipStream_t stream)
-{
-    const int64_t spans = (grid.n_bins + kWaveBins - 1) / kWaveBins;
-    const int64_t groups = (n_samples + kWaveSamples - 1) / kWaveSamples;
-    const int64_t blocks = spans * groups;
-    if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(waveform_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, grid.n_bins, n_out,
-                       n_samples, spans, grid.delta_f, tab1, tab2, records, reinterpret_cast<double2 *>(h_out));
-    return hipGetLastError();
-}
 
 }  // namespace gw
 

@@ -35,19 +35,25 @@ def _summary(tmp_path, sha):
 
 
 def test_profile_values_follow_the_fingerprint(tmp_path):
-    # an absolute summary path is read as given
-    good = _summary(tmp_path, bench.kernel_fingerprint())
-    assert bench.measured_traffic("fp64", good) == pytest.approx(3.25e7)
-    assert bench.measured_executed_flops("fp64", good) == pytest.approx(7.8e10)
-    assert bench.measured_traffic("mixed", good) is None
+    # an absolute summary path is read as given, checked against the tile kernel's sources
+    tile = bench.PROFILE_SUMMARY
+    good = _summary(tmp_path, bench.kernel_fingerprint(tile))
+    assert bench.measured_traffic("fp64", good, tile) == pytest.approx(3.25e7)
+    assert bench.measured_executed_flops("fp64", good, tile) == pytest.approx(7.8e10)
+    assert bench.measured_traffic("mixed", good, tile) is None
     stale = _summary(tmp_path, "0" * 64)
-    assert bench.measured_traffic("fp64", stale) is None
-    assert bench.measured_executed_flops("fp64", stale) is None
-    assert bench.measured_traffic("fp64", str(tmp_path / "missing.md")) is None
+    assert bench.measured_traffic("fp64", stale, tile) is None
+    assert bench.measured_executed_flops("fp64", stale, tile) is None
+    assert bench.measured_traffic("fp64", str(tmp_path / "missing.md"), tile) is None
+    # another kernel's sources give another fingerprint
+    assert bench.measured_traffic("fp64", good, bench.WAVEFORM_PROFILE) is None
 
 
-def test_fingerprint_covers_the_kernel_sources():
-    names = [os.path.basename(p) for p in bench.KERNEL_SOURCES]
-    for must in ("gw_kernels.hip", "gw_device_math.h", "gw_plan.h", "gw_phasor_table.h", "gw_relbin.hip"):
-        assert must in names
-    assert len(bench.kernel_fingerprint()) == 64
+def test_fingerprints_cover_each_kernels_sources():
+    names = {k: [os.path.basename(p) for p in v] for k, v in bench.PROFILE_SOURCES.items()}
+    for must in ("gw_kernels.hip", "gw_device_math.h", "gw_plan.h", "gw_phasor_table.h", "build.py"):
+        assert must in names[bench.PROFILE_SUMMARY]
+    assert "gw_waveform.hip" in names[bench.WAVEFORM_PROFILE]
+    assert "gw_relbin.hip" in names[bench.RELBIN_PROFILE]
+    prints = {bench.kernel_fingerprint(k) for k in bench.PROFILE_SOURCES}
+    assert len(prints) == 3 and all(len(p) == 64 for p in prints)

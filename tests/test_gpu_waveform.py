@@ -99,3 +99,17 @@ def test_benchmark_batch_sampled(gw):
     del out
     ref = oracle.waveform(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, w.theta[rows])
     _check(got, ref, "benchmark batch")
+
+
+def test_fill_writes_every_element():
+    import torch
+
+    import paper_1904_02863_amd as gw
+    gw.load_library()
+    for n in (1, 255, 256, 100_003, 3 * 259_585):
+        out = torch.full((n,), complex(7.0, 7.0), dtype=torch.complex128, device="cuda:0")
+        gw.fill_c128(out, complex(-1.5, 2.25))
+        torch.cuda.synchronize()
+        assert bool((out == complex(-1.5, 2.25)).all())
+    empty = torch.empty(0, dtype=torch.complex128, device="cuda:0")
+    gw.fill_c128(empty, 1.0)
