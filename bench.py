@@ -758,6 +758,9 @@ def main():
     # the committed summary of the same kernel sources; None when they changed
     executed = measured_executed_flops(args.precision) if headline else None
     achieved = executed / kernel_avg_s / 1e12 if executed is not None else None
+    # VALU issue cycles per SIMD per launch (every instruction at its measured
+    # issue cost: the mixed path's FP32 transcendentals take two slots)
+    issue = _profile_value(f"valu_issue_cycles_per_simd_{args.precision}", PROFILE_SUMMARY) if headline else None
     result = {
         "metric": "lnL evals/s (3-det,128 s TaylorF2)" if args.workload == "bbh-3det-128s" else "lnL evals/s",
         "value": evals / elapsed,
@@ -779,6 +782,7 @@ def main():
                      "flops_source": (f"executed FP64 flops from the counters in {PROFILE_SUMMARY}"
                                       if executed is not None else "no counter summary of these kernel sources"),
                      "executed_flops_per_launch": executed,
+                     "issue_frac": (issue / (kernel_avg_s * 2.4e9) if issue is not None else None),
                      "traffic": measured_traffic(args.precision) if headline else None,
                      "kernel": f"lnl_tile_kernel<{w.n_det},{'mixed' if mixed else 'fp64'}>",
                      "kernel_ms": kernel_avg_s * 1e3,
