@@ -223,14 +223,16 @@ struct RbEdge {
 // (the linear model r = r0 + r1 (f - fm) written in the two edge values).
 // At an edge e inside a chunk the two bins that meet there are combined:
 // L = Lhi(e-1) + Llo(e), q = beta(e-1) + alpha(e); xb = X(e-1) is the cross
-// term of the bin that ends at e.
+// term of the bin that ends at e.  (lr, li, xb first: the per-sample pass
+// reads those three at every edge, q only through its prefix sums.)
 struct RbCoef {
-    double lr, li, q, xb;
+    double lr, li, xb, q;
 };
 // The same per bin side: hi = the bin that ends at e (e - 1), lo = the bin that
-// starts there (e); used at the last and first edge of a chunk.
+// starts there (e); used at the last and first edge of a chunk.  qcum = the
+// sum of RbCoef::q over the edges below e (an exclusive prefix sum).
 struct RbEnds {
-    double hi_r, hi_i, hi_q, lo_r, lo_i, lo_q, pad0, pad1;
+    double hi_r, hi_i, hi_q, lo_r, lo_i, lo_q, qcum, pad1;
 };
 constexpr int kRawPerDet = 7;
 

@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void coef_kernel(int n_det, int64_t n_rb, c
     const int64_t e = i / n_det;
     const int d = (int)(i % n_det);
     RbEnds x;
-    x.hi_r = x.hi_i = x.hi_q = x.lo_r = x.lo_i = x.lo_q = x.pad0 = x.pad1 = 0.0;
+    x.hi_r = x.hi_i = x.hi_q = x.lo_r = x.lo_i = x.lo_q = x.qcum = x.pad1 = 0.0;
     double xb = 0.0;
     if (e >= 1) {          // bin e - 1 ends at e
         const double *v = raw + ((e - 1) * n_det + d) * kRawPerDet;
@@ -181,6 +181,37 @@ __global__ __launch_bounds__(kBlock) void coef_kernel(int n_det, int64_t n_rb, c
     ends[i] = x;
 }
 
+// One block per detector d: ends[e].qcum = sum of coef[e'].q over e' < e, in
+// a fixed order (each thread a contiguous run of edges, then the runs' sums
+// in thread order), for e = 0 .. n_rb.
+__global__ __launch_bounds__(kBlock) void qcum_kernel(int n_det, int64_t n_rb, const RbCoef *__restrict__ coef,
+                                                       RbEnds *__restrict__ ends)
+{
+    __shared__ double run[kBlock];
+    const int d = blockIdx.x;
+    const int64_t n = n_rb + 1;
+    const int64_t per = (n + kBlock - 1) / kBlock;
+    const int64_t e0 = min(n, (int64_t)threadIdx.x * per), e1 = min(n, e0 + per);
+    double acc = 0.0;
+    for (int64_t e = e0; e < e1; ++e) acc += coef[e * n_det + d].q;
+    run[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int t = 0; t < kBlock; ++t) {
+            const double v = run[t];
+            run[t] = sum;
+            sum += v;
+        }
+    }
+    __syncthreads();
+    double prefix = run[threadIdx.x];
+    for (int64_t e = e0; e < e1; ++e) {
+        ends[e * n_det + d].qcum = prefix;
+        prefix += coef[e * n_det + d].q;
+    }
+}
+
 // One block: totals[0] = <d, d>, totals[1] = sum ln(2 pi S) from the per-bin
 // sums (each thread a strided set of bins, then the fixed block tree).
 __global__ __launch_bounds__(kBlock) void totals_kernel(int64_t n_rb, const double *__restrict__ bin_dd,
@@ -201,10 +232,19 @@ __global__ __launch_bounds__(kBlock) void totals_kernel(int64_t n_rb, const doub
 
 // ---------------------------------------------------------------- per-sample pass
 // Block (sample group g, chunk c): thread t takes sample 256 g + t over the
-// bins [b0, b1) of chunk c, i.e. the edges b0 .. b1.  The ratio is formed
+// bins [b0, b1) of chunk c, i.e. the edges b0 .. b1.  The items (g, c) are
+// dealt to the XCDs in contiguous runs, the chunks of a group one after the
+// other: the grid is a multiple of 8 and block b, which the dispatcher places
+// on XCD b mod 8, takes item (b mod 8) (grid / 8) + b / 8, so the chunk blocks
+// of a group share one L2 and read the group's sample records from memory
+// once.  The ratio is formed
 // once per edge; each edge adds its linear and squared terms (one-sided at
 // the chunk's two end edges, whose other bin belongs to the next chunk) and
-// the cross term of the bin below it.  The edge tables and coefficients are
+// the cross term of the bin below it.  The squared terms need no per-edge
+// work: r_d = q_d e^{-2 pi i x} has |r_d|^2 = |q_d|^2 at every edge, so they
+// add |q_d|^2 times the chunk's sum of the squared-term coefficients (from
+// the prefix sums qcum and the one-sided end coefficients).  The edge tables
+// and coefficients are
 // the same for every lane of a wave (the loop index is uniform), so they come
 // through the scalar cache.  Writes the chunk's partial sum of
 // <d, h> - <h, h>/2 for every sample.
@@ -242,8 +282,12 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
                                                       const double *__restrict__ fid, const double *__restrict__ rec,
                                                       double *__restrict__ partials)
 {
-    const int64_t group = blockIdx.x / n_chunks;
-    const int chunk = (int)(blockIdx.x % n_chunks);
+    const int64_t per_xcd = (int64_t)gridDim.x / 8;
+    const int64_t item = (int64_t)(blockIdx.x % 8u) * per_xcd + (int64_t)(blockIdx.x / 8u);
+    const int64_t n_groups = (n_samples + kBlock - 1) / kBlock;
+    if (item >= n_groups * n_chunks) return;
+    const int64_t group = item / n_chunks;
+    const int chunk = (int)(item % n_chunks);
     const int64_t s = group * kBlock + threadIdx.x;
     const int64_t sr = s < n_samples ? s : n_samples - 1;
     const int64_t b0 = n_rb * chunk / n_chunks, b1 = n_rb * (chunk + 1) / n_chunks;
@@ -286,12 +330,10 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
         const RbEnds k = ends[b0 * NDET + d];
-        double a = k.lo_r * rr[d];
-        a = __builtin_fma(k.lo_i, ri[d], a);
-        acc[d] = __builtin_fma(k.lo_q, __builtin_fma(rr[d], rr[d], ri[d] * ri[d]), a);
+        acc[d] = __builtin_fma(k.lo_i, ri[d], k.lo_r * rr[d]);
     }
     // edges inside the chunk: both bins that meet there
-#pragma unroll 2
+#pragma unroll 4
     for (int64_t e = b0 + 1; e < b1; ++e) {
         edge_ratio<NDET, MIXED>(c, edges[e], qr, qi, dl, nr, ni, tab);
 #pragma unroll
@@ -301,25 +343,28 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
             a = __builtin_fma(k.xb, __builtin_fma(rr[d], nr[d], ri[d] * ni[d]), a);
             a = __builtin_fma(k.lr, nr[d], a);
             a = __builtin_fma(k.li, ni[d], a);
-            a = __builtin_fma(k.q, __builtin_fma(nr[d], nr[d], ni[d] * ni[d]), a);
             acc[d] = a;
             rr[d] = nr[d];
             ri[d] = ni[d];
         }
     }
-    // last edge: the upper side of bin b1 - 1 only
+    // last edge: the upper side of bin b1 - 1 only; then the squared terms
     edge_ratio<NDET, MIXED>(c, edges[b1], qr, qi, dl, nr, ni, tab);
     double total = 0.0;
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
         const RbEnds k = ends[b1 * NDET + d];
+        const RbEnds k0 = ends[b0 * NDET + d];
         const double xb = coef[b1 * NDET + d].xb;
         double a = acc[d];
         a = __builtin_fma(xb, __builtin_fma(rr[d], nr[d], ri[d] * ni[d]), a);
         a = __builtin_fma(k.hi_r, nr[d], a);
         a = __builtin_fma(k.hi_i, ni[d], a);
-        a = __builtin_fma(k.hi_q, __builtin_fma(nr[d], nr[d], ni[d] * ni[d]), a);
-        total += a;
+        // squared-term coefficients of the chunk: the lower side of its first
+        // edge, both sides of every inner edge, the upper side of its last edge
+        const double qsum = (k0.lo_q + (k.qcum - ends[(b0 + 1) * NDET + d].qcum)) + k.hi_q;
+        const double q2 = __builtin_fma(qr[d], qr[d], qi[d] * qi[d]);
+        total += __builtin_fma(qsum, q2, a);
     }
     if (s < n_samples) partials[(int64_t)chunk * n_samples + s] = total;
 }
@@ -390,6 +435,8 @@ hipError_t launch_summary(const gw_grid &grid, int n_det, int64_t n_rb, const in
     const int64_t n = (n_rb + 1) * n_det;
     hipLaunchKernelGGL(coef_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, stream, n_det, n_rb,
                        edges, raw, coef, ends);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(qcum_kernel, dim3((unsigned)n_det), dim3(kBlock), 0, stream, n_det, n_rb, coef, ends);
     return hipGetLastError();
 }
 
@@ -429,7 +476,7 @@ hipError_t launch_lnl(int n_det, bool mixed, int64_t n_samples, int64_t n_rb, in
 {
     if (n_det < 1 || n_det > kMaxDet) return hipErrorInvalidValue;
     const int64_t groups = (n_samples + kBlock - 1) / kBlock;
-    const int64_t blocks = groups * n_chunks;
+    const int64_t blocks = (groups * n_chunks + 7) / 8 * 8;     // a multiple of the 8 XCDs
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     void *args[] = {&n_samples, &n_rb, &n_chunks, &edges, &coef, &ends, &fid, &rec, &partials};
     hipError_t e;
