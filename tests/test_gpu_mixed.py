@@ -30,6 +30,45 @@ def gw():
     return gw
 
 
+REPORT_HEADER = ("injection,snr,dh_injection,abs_dlnl_injection,rel_dh_injection,max_abs_dlnl_8rows,"
+                 "max_abs_mixed_minus_fp64_4096rows")
+
+
+def summarize_report(r: np.ndarray) -> str:
+    """Markdown summary of the per-injection records (columns of
+    REPORT_HEADER): quantiles of each error over the injections, the errors
+    by network SNR band, and the five worst injections."""
+    cols = {"abs dlnL at the injection (mixed vs oracle)": r[:, 3],
+            "relative <d,h> error at the injection": r[:, 4],
+            "max abs dlnL over the 8 oracle rows": r[:, 5],
+            "max abs (mixed - FP64) over all 4096 rows": r[:, 6]}
+    out = [f"{len(r)} injections, network optimal SNR {r[:, 1].min():.2f} to {r[:, 1].max():.2f}; bar "
+           f"|dlnL| <= {TOL_MIXED:g}.\n",
+           "| quantity | median | 90% | 99% | max |", "|---|---|---|---|---|"]
+    for name, v in cols.items():
+        q = np.quantile(v, [0.5, 0.9, 0.99])
+        out.append(f"| {name} | {q[0]:.3e} | {q[1]:.3e} | {q[2]:.3e} | {v.max():.3e} |")
+    out += ["", "By SNR band (injection rows):", "",
+            "| SNR | injections | <d,h> median | median abs dlnL | max abs dlnL | median rel <d,h> | max rel <d,h> | "
+            "max abs mixed - FP64 (4096 rows) |",
+            "|---|---|---|---|---|---|---|---|"]
+    edges = [8.0, 12.0, 20.0, 35.0, 60.0, 100.0 + 1e-9]
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        m = (r[:, 1] >= lo) & (r[:, 1] < hi)
+        if not m.any():
+            continue
+        b = r[m]
+        out.append(f"| {lo:g}-{min(hi, 100.0):g} | {m.sum()} | {np.median(b[:, 2]):.4g} | {np.median(b[:, 3]):.2e} | "
+                   f"{b[:, 3].max():.2e} | {np.median(b[:, 4]):.2e} | {b[:, 4].max():.2e} | {b[:, 6].max():.2e} |")
+    out += ["", "Five largest abs dlnL over the 8 oracle rows:", "",
+            "| injection | SNR | <d,h> | abs dlnL (injection) | rel <d,h> | max abs dlnL (8 rows) | "
+            "max abs mixed - FP64 |", "|---|---|---|---|---|---|---|"]
+    for i in np.argsort(-r[:, 5])[:5]:
+        x = r[i]
+        out.append(f"| {int(x[0])} | {x[1]:.2f} | {x[2]:.5g} | {x[3]:.2e} | {x[4]:.2e} | {x[5]:.2e} | {x[6]:.2e} |")
+    return "\n".join(out) + "\n"
+
+
 @pytest.fixture(scope="module")
 def event():
     return synth.bbh_3det_128s(8)
@@ -116,7 +155,15 @@ def test_mixed_precision_over_1024_injections(gw):
     prior, half close to the injection).  Per injection the oracle checks the
     injection and 7 more rows for both paths (FP64 1e-10 relative, mixed 1e-3),
     and all 4096 mixed values stay within 1e-3 of the FP64 ones.  Injections
-    are made with the oracle's waveform, 64 at a time."""
+    are made with the oracle's waveform, 64 at a time.  Per injection the
+    test records the largest |dlnL| of the mixed path against the oracle and
+    the relative error of <d,h> it implies (the mixed path changes only the
+    phasor, so dlnL = d<d,h>; <d,h> = lnL(d) - lnL(0) + <d,d>/2 from the
+    oracle); with GW_REPORT_DIR set it writes them there as
+    mixed_precision_per_injection.csv, with a summary (summarize_report) as
+    mixed_precision_summary.md."""
+    import os
+
     import torch
     w = synth.bbh_3det_128s(8)
     g = w.grid
@@ -125,8 +172,10 @@ def test_mixed_precision_over_1024_injections(gw):
     psd_t = torch.from_numpy(w.psd).to(dev)
     noise_t = torch.from_numpy(w.noise).to(dev)
     weight = 4.0 * g.delta_f / w.psd
+    zero = np.zeros_like(w.noise)
     n_inj, batch = 1024, 64
     worst_mixed, worst_all, worst_fp64 = 0.0, 0.0, 0.0
+    report = []
     for b0 in range(0, n_inj, batch):
         injs = synth.Prior().sample(rng, batch, 9)
         hs = oracle.waveform(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, injs)
@@ -146,14 +195,31 @@ def test_mixed_precision_over_1024_injections(gw):
             th_t = torch.from_numpy(rows).to(dev)
             fp64 = gw.lnl_batch(g, w.tensors, w.vertices, d_t, psd_t, th_t).cpu().numpy()
             mixed = gw.lnl_batch(g, w.tensors, w.vertices, d_t, psd_t, th_t, precision="mixed").cpu().numpy()
-            worst_all = max(worst_all, float(np.abs(mixed - fp64).max()))
+            all_err = float(np.abs(mixed - fp64).max())
+            worst_all = max(worst_all, all_err)
             pick = np.concatenate([[0], rng.choice(np.arange(1, 4096), 7, replace=False)])
             data = w.noise + hs[i] * scale
             ref = oracle.lnl(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, data, w.psd, rows[pick])
-            worst_mixed = max(worst_mixed, float(np.abs(mixed[pick] - ref).max()))
+            l0 = oracle.lnl(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, zero, w.psd, rows[pick[:1]])
+            far = rows[:1].copy()
+            far[0, 2] = 1e30
+            dd_half = -oracle.lnl(g.f_low, g.delta_f, g.n_bins, w.tensors, w.vertices, data, w.psd, far)[0]
+            dh_inj = ref[0] - l0[0] + dd_half        # <d,h> at the injection, about SNR^2
+            err = np.abs(mixed[pick] - ref)
+            worst_mixed = max(worst_mixed, float(err.max()))
             worst_fp64 = max(worst_fp64, float((np.abs(fp64[pick] - ref) / np.abs(ref)).max()))
+            report.append((b0 + i, target[i], dh_inj, err[0], err[0] / abs(dh_inj), float(err.max()), all_err))
         print(f"{b0 + batch} injections: worst |mixed - oracle| {worst_mixed:.2e}, "
               f"worst |mixed - fp64| {worst_all:.2e}, worst fp64 rel {worst_fp64:.2e}", flush=True)
+    out_dir = os.environ.get("GW_REPORT_DIR")
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, "mixed_precision_per_injection.csv"), "w") as fh:
+            fh.write(REPORT_HEADER + "\n")
+            for r in report:
+                fh.write(f"{r[0]},{r[1]:.4f},{r[2]:.6g},{r[3]:.3e},{r[4]:.3e},{r[5]:.3e},{r[6]:.3e}\n")
+        with open(os.path.join(out_dir, "mixed_precision_summary.md"), "w") as fh:
+            fh.write(summarize_report(np.array(report, dtype=np.float64)))
     assert worst_fp64 <= RTOL_FP64
     assert worst_mixed <= TOL_MIXED
     assert worst_all <= TOL_MIXED
