@@ -85,7 +85,7 @@ def _profile_value(name: str, summary: str, sources: str | None = None):
         return None
     text = open(path).read()
     sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
-    val = re.search(rf"{name}:\s*([0-9.eE+]+)", text)
+    val = re.search(rf"{re.escape(name)}:\s*([0-9.eE+]+)", text)
     if not sha or not val or sha.group(1) != kernel_fingerprint(sources or summary):
         return None
     return float(val.group(1))
@@ -101,6 +101,23 @@ def measured_executed_flops(key: str, summary: str = PROFILE_SUMMARY, sources: s
     """FP64 flops per launch the hardware counters saw the kernel execute
     (FMA = 2), or None as for measured_traffic."""
     return _profile_value(f"executed_fp64_flops_per_launch_{key}", summary, sources)
+
+
+def plan_key(precision: str, plan: dict) -> str:
+    """Key of a likelihood plan's figures in the tile kernel's counter
+    summary: precision@TILExROUNDS."""
+    return f"{precision}@{plan['tile_bins']}x{plan['rounds']}"
+
+
+def profiled_plans(precision: str, summary: str = PROFILE_SUMMARY, sources: str | None = None) -> list[str]:
+    """The plans (TILExROUNDS) a counter summary holds executed-flop figures
+    for at this precision, while its kernel sources still match."""
+    path = os.path.join(ROOT, summary)
+    if not os.path.exists(path):
+        return []
+    found = re.findall(rf"executed_fp64_flops_per_launch_{re.escape(precision)}@(\d+x\d+):", open(path).read())
+    return [p for p in found if _profile_value(f"executed_fp64_flops_per_launch_{precision}@{p}", summary, sources)
+            is not None]
 
 
 def calibration_copy(mib: int, device):
@@ -685,6 +702,8 @@ def main():
     ap.add_argument("--mcmc-steps", type=int, default=1024, help="flow-mcmc: production steps of each sampler")
     ap.add_argument("--flow-steps", type=int, default=3000, help="flow-mcmc: Adam steps")
     ap.add_argument("--samples", type=int, default=None)
+    ap.add_argument("--plan", default=None, metavar="TILE,ROUNDS",
+                    help="run this likelihood plan (LDS tile bins, work-queue rounds) instead of the autotuned one")
     ap.add_argument("--flags", type=int, default=0,
                     help="likelihood options: 1 direct form, 2 ISCO template end, 4 log prefactor (or-ed)")
     ap.add_argument("--rb-band", default="15hz-512s", choices=["15hz-512s", "5hz-8192s"],
@@ -736,6 +755,12 @@ def main():
         gw.lnl_batch(g, w.tensors, w.vertices, data, psd, theta, out=out, workspace=ws, precision=args.precision,
                      flags=args.flags)
 
+    if args.plan:
+        tile, rounds = (int(v) for v in args.plan.split(","))
+        ws.set_tuning(False)
+        ws.set_plan(g.n_bins, w.n_det, w.n_samples, tile, rounds, args.precision, args.flags)
+    step()                             # first call: times the candidate plans, keeps the fastest (untimed)
+    plan = ws.lnl_plan(g.n_bins, w.n_det, w.n_samples, args.precision, args.flags)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -760,13 +785,15 @@ def main():
     flops_launch = flops_per_pair(w.n_det, mixed, direct) * w.n_samples * g.n_bins
     tally_rate = flops_launch / kernel_avg_s / 1e12
     headline = args.workload == "bbh-3det-128s" and args.flags == 0 and not args.spins
+    # the counters hold for the plan they were taken under
+    key = plan_key(args.precision, plan)
     # FP64 flops the hardware counters saw one launch execute (FMA = 2), from
     # the committed summary of the same kernel sources; None when they changed
-    executed = measured_executed_flops(args.precision) if headline else None
+    executed = measured_executed_flops(key) if headline else None
     achieved = executed / kernel_avg_s / 1e12 if executed is not None else None
     # VALU issue cycles per SIMD per launch (every instruction at its measured
     # issue cost: the mixed path's FP32 transcendentals take two slots)
-    issue = _profile_value(f"valu_issue_cycles_per_simd_{args.precision}", PROFILE_SUMMARY) if headline else None
+    issue = _profile_value(f"valu_issue_cycles_per_simd_{key}", PROFILE_SUMMARY) if headline else None
     result = {
         "metric": "lnL evals/s (3-det,128 s TaylorF2)" if args.workload == "bbh-3det-128s" else "lnL evals/s",
         "value": evals / elapsed,
@@ -782,14 +809,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n_samples": w.n_samples, "n_det": w.n_det, "n_bins": g.n_bins,
                    "delta_f": g.delta_f, "f_low": g.f_low, "f_high": g.f_high, "n_param": w.n_param,
-                   "precision": args.precision, "flags": args.flags, "spins": args.spins},
+                   "precision": args.precision, "flags": args.flags, "spins": args.spins, "plan": plan},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS if achieved is not None else None,
                      "flops_source": (f"executed FP64 flops from the counters in {PROFILE_SUMMARY}"
-                                      if executed is not None else "no counter summary of these kernel sources"),
+                                      if executed is not None else
+                                      f"no counter summary of these kernel sources under plan {key} "
+                                      f"(profiled: {profiled_plans(args.precision)})"),
                      "executed_flops_per_launch": executed,
                      "issue_frac": (issue / (kernel_avg_s * 2.4e9) if issue is not None else None),
-                     "traffic": measured_traffic(args.precision) if headline else None,
+                     "traffic": measured_traffic(key) if headline else None,
                      "kernel": f"lnl_tile_kernel<{w.n_det},{'mixed' if mixed else 'fp64'}>",
                      "kernel_ms": kernel_avg_s * 1e3,
                      # the algorithmic tally below prices the phasor at its

@@ -154,11 +154,30 @@ int gw_workspace_destroy(gw_workspace *ws);
 
 /* Size the workspace for events of up to n_bins bins and n_det detectors and
  * batches of up to n_samples samples, so that later calls within these sizes
- * allocate nothing. */
+ * allocate nothing (under the default plans, the plans already tuned and any
+ * plan the autotuner may pick; a plan set with gw_workspace_set_plan may need
+ * more). */
 int gw_workspace_reserve(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples);
 
 /* Bytes of device memory the workspace currently holds. */
 int64_t gw_workspace_bytes(const gw_workspace *ws);
+
+/* Plan autotuning of gw_lnl_batch on this workspace.  While it is on (the
+ * default), the first call of a size class (detector count, precision,
+ * template end, floor(log2 n_bins), floor(log2 n_samples)) with at least 2^24
+ * (sample, bin) pairs times the call under each candidate plan (the largest
+ * LDS tile and half of it; 0, 4, 6 or 8 work-queue rounds, 0 only with the
+ * ISCO end), writing lnl_out once per candidate and waiting for the stream,
+ * and later calls of the class use the fastest (the default plan unless the
+ * fastest beats it by 3%, so that plans of equal speed do not flip with
+ * timing noise from one process to the next).  Calls under stream capture
+ * and on a workspace that has been captured are never tuned; they use a
+ * class's tuned plan when there is one, else the default.
+ *   enable  1: on; 0: off (tuned plans are kept and still used);
+ *           -1: off, and the tuned plans are forgotten (the default plans
+ *           are used again).
+ * Returns GW_OK or GW_EINVAL (ws NULL). */
+int gw_workspace_set_tuning(gw_workspace *ws, int enable);
 
 /* Measurement support.  While timing is enabled (enable != 0), every
  * gw_lnl_batch, gw_waveform_batch, gw_pop_lnl(_prepared) and gw_rb_lnl call
@@ -215,8 +234,11 @@ int gw_lnl_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_dete
  * gw_lnl_batch_static -- gw_lnl_batch without a workspace, allocating nothing.
  * For callers that cannot allocate device memory during a call: code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
- * Arguments, results and kernels are those of gw_lnl_batch (same values bit
- * for bit); its intermediate buffers live in one static device array of
+ * Arguments, results and kernels are those of gw_lnl_batch; it always runs
+ * the default plan, so its values equal bit for bit those of gw_lnl_batch on
+ * a workspace with plan autotuning off (gw_workspace_set_tuning), and those
+ * of a tuned plan to the rounding of FP64 sums taken in another order.  Its
+ * intermediate buffers live in one static device array of
  * GW_STATIC_SCRATCH_BYTES per GPU, which the library holds on every GPU it
  * runs on until the process ends.  The call uses the array of the current
  * device.  Every call on a GPU shares that array: two calls that overlap on
@@ -394,7 +416,8 @@ int gw_rb_shape(const gw_relbin *rb, int64_t *n_rb, int *n_det);
  *   totals_out  host [2]: <d,d> and sum ln(2 pi S).  Either may be NULL. */
 int gw_rb_summary(const gw_relbin *rb, double *raw_out, double *totals_out);
 
-/* How gw_lnl_batch splits a call of this shape on the workspace's device
+/* How gw_lnl_batch splits a call of this shape on the workspace's device:
+ * the plan tuned for its size class when there is one, else the default
  * (inspection and test support; no device work):
  *   tile_bins  bins staged in LDS at a time;
  *   n_chunks   bin chunks per group of 256 samples (partial sums per chunk);
@@ -407,6 +430,21 @@ int gw_rb_summary(const gw_relbin *rb, double *raw_out, double *totals_out);
  * GW_EINVAL or GW_EDEVICE. */
 int gw_lnl_plan(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples, int precision, unsigned flags,
                 int *tile_bins, int *n_chunks, int *rounds);
+
+/* Set the plan gw_lnl_batch uses on this workspace for the size class of
+ * (n_bins, n_det, n_samples, precision, flags), as the autotuner records it:
+ * for reproducing a plan read with gw_lnl_plan on another workspace or in
+ * another process (plans differ only in the order of FP64 additions) or for
+ * comparing plans.
+ *   tile_bins  bins staged in LDS per tile: a multiple of 64, at most the
+ *              largest tile the LDS budget allows for the size class;
+ *   rounds     work-queue rounds, 0..16 (0: one block per item; a size that
+ *              cannot take R rounds, and the ISCO end, use 0).
+ * tile_bins == 0 and rounds == 0 remove the class's plan (the default is used
+ * again, or the autotuner's choice once it has timed the class anew).  Sizes,
+ * precision and flags as for gw_lnl_plan.  Returns GW_OK or GW_EINVAL. */
+int gw_workspace_set_plan(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples, int precision,
+                          unsigned flags, int tile_bins, int rounds);
 
 /* Tile shape the last gw_lnl_ragged call used: bins staged in LDS per tile and
  * bins per work item.  The first call for a new size class times every

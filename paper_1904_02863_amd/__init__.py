@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libgwlnl.so")
 
 GW_OK, GW_EINVAL, GW_ENOMEM, GW_EDEVICE, GW_EUNSUPPORTED, GW_EABI = 0, -1, -2, -3, -4, -5
 # The library version this binding's argument types describe (gw_version).
-ABI_VERSION = 300
+ABI_VERSION = 301
 PRECISIONS = {"fp64": 0, "mixed": 1}
 MAX_DET = 8
 # Options of the likelihood and waveform calls (GW_FLAG_* of include/gwlnl.h).
@@ -33,9 +33,9 @@ FLAG_ADD_NORM = 4
 
 # Every symbol include/gwlnl.h declares.
 EXPORTED = ("gw_workspace_create", "gw_workspace_destroy", "gw_workspace_reserve", "gw_workspace_bytes",
-            "gw_workspace_set_timing", "gw_workspace_kernel_time", "gw_waveform_batch", "gw_fill_c128", "gw_lnl_batch",
+            "gw_workspace_set_timing", "gw_workspace_set_tuning", "gw_workspace_kernel_time", "gw_waveform_batch", "gw_fill_c128", "gw_lnl_batch",
             "gw_lnl_batch_static", "gw_lnl_batch_static_bytes", "gw_lnl_batch_static_capacity",
-            "gw_lnl_ragged", "gw_lnl_plan", "gw_ragged_tuning", "gw_pop_lnl", "gw_pop_prepare", "gw_pop_lnl_prepared",
+            "gw_lnl_ragged", "gw_lnl_plan", "gw_workspace_set_plan", "gw_ragged_tuning", "gw_pop_lnl", "gw_pop_prepare", "gw_pop_lnl_prepared",
             "gw_rb_edges", "gw_rb_create", "gw_rb_destroy", "gw_rb_lnl", "gw_rb_shape", "gw_rb_summary", "gw_last_error",
             "gw_version", "gw_abi_layout", "gw_source_hash",
             "gw_philox_raw", "gw_philox_fill", "gw_philox_chain_normals", "gw_mcmc_to_theta", "gw_mcmc_rw_propose",
@@ -129,6 +129,8 @@ def load_library() -> ctypes.CDLL:
         lib.gw_workspace_bytes.argtypes = [vp]
         lib.gw_workspace_bytes.restype = i64
         lib.gw_workspace_set_timing.argtypes = [vp, i32]
+        lib.gw_workspace_set_tuning.argtypes = [vp, i32]
+        lib.gw_workspace_set_plan.argtypes = [vp, i64, i32, i64, i32, u32, i32, i32]
         lib.gw_workspace_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         lib.gw_waveform_batch.argtypes = [vp, ctypes.POINTER(GwGrid), i32, ctypes.POINTER(GwDetector), vp, i32, i64,
                                           vp, u32, vp]
@@ -214,6 +216,12 @@ class Workspace:
         """Record HIP events around the hot kernel of every likelihood call."""
         _check(load_library().gw_workspace_set_timing(self._h, 1 if enable else 0))
 
+    def set_tuning(self, enable: bool, forget: bool = False):
+        """Time candidate plans on the first likelihood call of each size class
+        and use the fastest (on by default).  forget=True turns tuning off and
+        drops the tuned plans, so that the default plans are used again."""
+        _check(load_library().gw_workspace_set_tuning(self._h, -1 if forget else (1 if enable else 0)))
+
     def kernel_time(self) -> tuple[float, int]:
         """(total milliseconds, launches) of the hot kernel since timing was enabled."""
         ms, n = ctypes.c_double(), ctypes.c_int64()
@@ -221,12 +229,21 @@ class Workspace:
         return ms.value, n.value
 
     def lnl_plan(self, n_bins: int, n_det: int, n_samples: int, precision: str = "fp64", flags: int = 0) -> dict:
-        """How gw_lnl_batch splits a call of this shape: LDS tile bins, chunks
-        per sample group and work-queue rounds (0: one block per item)."""
+        """How gw_lnl_batch splits a call of this shape (the tuned plan of its
+        size class once one is tuned): LDS tile bins, chunks per sample group
+        and work-queue rounds (0: one block per item)."""
         t, c, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(load_library().gw_lnl_plan(self._h, n_bins, n_det, n_samples, PRECISIONS[precision], int(flags),
                                           ctypes.byref(t), ctypes.byref(c), ctypes.byref(r)))
         return {"tile_bins": t.value, "n_chunks": c.value, "rounds": r.value}
+
+    def set_plan(self, n_bins: int, n_det: int, n_samples: int, tile_bins: int, rounds: int,
+                 precision: str = "fp64", flags: int = 0):
+        """Use this plan (LDS tile bins, work-queue rounds) for every
+        gw_lnl_batch call of this size class on the workspace; tile_bins=0
+        and rounds=0 drop the class's plan."""
+        _check(load_library().gw_workspace_set_plan(self._h, n_bins, n_det, n_samples, PRECISIONS[precision],
+                                                    int(flags), tile_bins, rounds))
 
     def ragged_tuning(self) -> tuple[int, int]:
         """(LDS tile bins, bins per work item) of the last ragged call."""

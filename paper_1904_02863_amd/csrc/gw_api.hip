@@ -20,11 +20,17 @@
 #include "gw_plan.h"
 #include "gwlnl.h"
 
+// Tile-kernel blocks per CU by (form, precision, detectors, tile bins).
+using OccupancyCache = std::map<std::tuple<int, int, int, int>, int>;
+
 struct gw_workspace {
     int device = 0;
     int n_cu = 0;
-    // tile-kernel occupancy by form, precision and detector count (0 = unknown)
-    int blocks_per_cu[gw::kForms][2][gw::kMaxDet + 1] = {};
+    OccupancyCache occupancy;
+    // single-event plans chosen by timing, by (detectors, precision and form,
+    // log2 bins, log2 samples): (tile bins, work-queue rounds)
+    bool tune_single = true;
+    std::map<std::tuple<int, int, int, int>, std::pair<int, int>> single_tuning;
     void *base = nullptr;
     size_t capacity = 0;
     bool timing = false;
@@ -219,20 +225,35 @@ int check_dets(int n_det, const gw_detector *dets, int n_param, gw::DetGeom *geo
     return GW_OK;
 }
 
-// Launch plan of one event for a device with n_cu compute units; occ caches
-// the tile kernel's blocks per CU by form, precision and detector count.
-gw::TilePlan plan_tiles_on(int n_cu, int (&occ)[gw::kForms][2][gw::kMaxDet + 1], int64_t n_bins, int n_det,
-                           int64_t n_samples, bool mixed, int form)
+// Launch plan of one event for a device with n_cu compute units, with the
+// given tile size and work-queue rounds (tile_bins 0: the largest tile the
+// LDS budget allows; rounds < 0: GW_TILE_ROUNDS).  occ caches occupancies.
+gw::TilePlan plan_tiles_on(int n_cu, OccupancyCache &occ, int64_t n_bins, int n_det, int64_t n_samples, bool mixed,
+                           int form, int tile_bins = 0, int rounds = -1)
 {
-    const int tile_bins = gw::tile_bins_for(n_det, form, mixed);
-    int &o = occ[form][mixed ? 1 : 0][n_det];
+    if (tile_bins <= 0) tile_bins = gw::tile_bins_for(n_det, form, mixed);
+    int &o = occ[std::make_tuple(form, mixed ? 1 : 0, n_det, tile_bins)];
     if (o == 0) o = gw::lnl_tile_blocks_per_cu(n_det, tile_bins, mixed, form);
-    return gw::plan_single_event(n_bins, n_samples, form, tile_bins, (int64_t)n_cu * o);
+    return gw::plan_single_event(n_bins, n_samples, form, tile_bins, (int64_t)n_cu * o,
+                                 rounds < 0 ? GW_TILE_ROUNDS : rounds);
 }
 
+int log2_bucket(int64_t n) { return n > 0 ? (int)std::floor(std::log2((double)n)) : 0; }
+
+std::tuple<int, int, int, int> tuning_key(int64_t n_bins, int n_det, int64_t n_samples, bool mixed, int form)
+{
+    return std::make_tuple(n_det, (mixed ? 1 : 0) + 2 * form, log2_bucket(n_bins), log2_bucket(n_samples));
+}
+
+// The plan gw_lnl_batch uses on this workspace: the tuned one of the size
+// bucket when the autotuner has timed it, else the default.
 gw::TilePlan plan_tiles(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples, bool mixed, int form)
 {
-    return plan_tiles_on(ws->n_cu, ws->blocks_per_cu, n_bins, n_det, n_samples, mixed, form);
+    auto it = ws->single_tuning.find(tuning_key(n_bins, n_det, n_samples, mixed, form));
+    if (it != ws->single_tuning.end())
+        return plan_tiles_on(ws->n_cu, ws->occupancy, n_bins, n_det, n_samples, mixed, form, it->second.first,
+                             it->second.second);
+    return plan_tiles_on(ws->n_cu, ws->occupancy, n_bins, n_det, n_samples, mixed, form);
 }
 
 // Workspace sections of one event.  The direct-form tables and the prefix
@@ -363,12 +384,114 @@ int lnl_enqueue(gw_workspace *ws, char *base, const LnlLayout &l, const gw::Tile
     return GW_OK;
 }
 
+bool same_plan(const gw::TilePlan &a, const gw::TilePlan &b)
+{
+    return a.tile_bins == b.tile_bins && a.rounds == b.rounds && a.chunk_bins == b.chunk_bins &&
+           a.n_chunks == b.n_chunks && a.n_groups == b.n_groups && a.blocks == b.blocks;
+}
+
+// The distinct plans the autotuner times for a size class: tile bins, the
+// largest the LDS budget allows and half of it; work-queue rounds 0, 4, 6 and
+// 8 (only 0 with the template end).  A rounds request the size cannot take
+// falls back to one item per block, so some requests give the same plan.
+std::vector<gw::TilePlan> tuning_candidates(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples,
+                                            bool mixed, int form)
+{
+    const int big = gw::tile_bins_for(n_det, form, mixed);
+    std::vector<gw::TilePlan> plans;
+    for (int tb : {big, big / 2}) {
+        if (tb < 64) continue;
+        for (int r : {0, 4, 6, 8}) {
+            if (form == gw::kFormSplitIsco && r > 0) continue;
+            const gw::TilePlan p = plan_tiles_on(ws->n_cu, ws->occupancy, n_bins, n_det, n_samples, mixed, form, tb, r);
+            bool seen = false;
+            for (const gw::TilePlan &q : plans) seen = seen || same_plan(p, q);
+            if (!seen) plans.push_back(p);
+        }
+    }
+    return plans;
+}
+
+// Calls of at least this many (sample, bin) pairs are worth timing plans for.
+constexpr double kTuneMinPairs = 1 << 24;
+// A candidate replaces the default plan only when it is faster by this
+// fraction, so that timing noise between plans of equal speed does not make
+// the choice differ from one run to the next.
+constexpr float kTuneMargin = 0.03f;
+
+// The autotuner of gw_lnl_batch: times the whole call under every candidate
+// plan of the size class, twice each in interleaved passes after one warm-up
+// call, and records for the class the fastest by its shorter time, or the
+// default plan unless the fastest beats it by kTuneMargin.  The caller then
+// computes the call's result with that plan.  It waits for the caller's
+// stream.
+int tune_single_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::DetGeom &geom,
+                      const gw_c128 *data, const double *psd, const double *theta, int n_param, int64_t n_samples,
+                      double *lnl_out, bool mixed, unsigned flags, hipStream_t stream)
+{
+    const int form = gw::tile_form(flags);
+    const std::vector<gw::TilePlan> plans = tuning_candidates(ws, grid.n_bins, n_det, n_samples, mixed, form);
+    size_t need = 0;
+    for (const gw::TilePlan &p : plans) need = std::max(need, lnl_layout(grid.n_bins, n_det, n_samples, p, flags).total);
+    if (int rc = ensure_capacity(ws, need, stream)) return rc;
+    const bool timing = ws->timing;
+    ws->timing = false;                  // the trial calls are not measurements of the caller's
+    hipEvent_t ev[2];
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess && (e = hipEventCreate(&ev[1])) != hipSuccess) (void)hipEventDestroy(ev[0]);
+    if (e != hipSuccess) {
+        ws->timing = timing;
+        return hip_fail(e, "hipEventCreate");
+    }
+    std::vector<float> best(plans.size(), 0.0f);
+    int rc = GW_OK;
+    for (int pass = -1; pass < 2 && rc == GW_OK; ++pass) {
+        for (size_t i = 0; i < plans.size() && rc == GW_OK; ++i) {
+            if (pass < 0 && i > 0) break;    // one warm-up call lets the clock settle
+            const LnlLayout l = lnl_layout(grid.n_bins, n_det, n_samples, plans[i], flags);
+            if ((e = hipEventRecord(ev[0], stream)) != hipSuccess) { rc = hip_fail(e, "hipEventRecord"); break; }
+            if ((rc = lnl_enqueue(ws, static_cast<char *>(ws->base), l, plans[i], grid, n_det, geom, data, psd, theta,
+                                  n_param, n_samples, lnl_out, mixed, flags, stream)) != GW_OK)
+                break;
+            float ms = 0.0f;
+            if ((e = hipEventRecord(ev[1], stream)) != hipSuccess || (e = hipEventSynchronize(ev[1])) != hipSuccess ||
+                (e = hipEventElapsedTime(&ms, ev[0], ev[1])) != hipSuccess) {
+                rc = hip_fail(e, "timing a plan");
+                break;
+            }
+            if (pass >= 0 && (pass == 0 || ms < best[i])) best[i] = ms;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    ws->timing = timing;
+    if (rc != GW_OK) return rc;
+    const gw::TilePlan def = plan_tiles_on(ws->n_cu, ws->occupancy, grid.n_bins, n_det, n_samples, mixed, form);
+    size_t pick = 0, dflt = plans.size();
+    for (size_t i = 0; i < plans.size(); ++i) {
+        if (best[i] < best[pick]) pick = i;
+        if (same_plan(plans[i], def)) dflt = i;
+    }
+    if (dflt < plans.size() && best[pick] > (1.0f - kTuneMargin) * best[dflt]) pick = dflt;
+    ws->single_tuning[tuning_key(grid.n_bins, n_det, n_samples, mixed, form)] = {plans[pick].tile_bins,
+                                                                                  plans[pick].rounds};
+    return GW_OK;
+}
+
 int lnl_one_event(gw_workspace *ws, const gw_grid &grid, int n_det, const gw::DetGeom &geom, const gw_c128 *data,
                   const double *psd, const double *theta, int n_param, int64_t n_samples, double *lnl_out,
                   bool mixed, unsigned flags, hipStream_t stream)
 {
     drop_ragged_graph(ws);               // the arena is about to be laid out for one event
-    const gw::TilePlan plan = plan_tiles(ws, grid.n_bins, n_det, n_samples, mixed, gw::tile_form(flags));
+    const int form = gw::tile_form(flags);
+    if (ws->tune_single && !ws->pinned && !capturing(stream) &&
+        (double)grid.n_bins * (double)n_samples >= kTuneMinPairs &&
+        ws->single_tuning.find(tuning_key(grid.n_bins, n_det, n_samples, mixed, form)) == ws->single_tuning.end()) {
+        if (int rc = tune_single_event(ws, grid, n_det, geom, data, psd, theta, n_param, n_samples, lnl_out, mixed,
+                                       flags, stream))
+            return rc;
+    }
+    const gw::TilePlan plan = plan_tiles(ws, grid.n_bins, n_det, n_samples, mixed, form);
     const LnlLayout l = lnl_layout(grid.n_bins, n_det, n_samples, plan, flags);
     if (int rc = ensure_capacity(ws, l.total, stream)) return rc;
     return lnl_enqueue(ws, static_cast<char *>(ws->base), l, plan, grid, n_det, geom, data, psd, theta, n_param,
@@ -390,7 +513,7 @@ struct StaticDevice {
     bool ready = false;
     char *ptr = nullptr;                 // device address of `scratch` on this device
     int n_cu = 0;
-    int blocks_per_cu[gw::kForms][2][gw::kMaxDet + 1] = {};
+    OccupancyCache occupancy;
 };
 
 std::mutex g_static_mutex;
@@ -780,7 +903,7 @@ GW_DEFINE_SOURCE_HASH(api)
 
 extern "C" {
 
-int gw_version(void) { return 300; }
+int gw_version(void) { return 301; }
 
 const char *gw_source_hash(void) { return gw::source_hash_api(); }
 
@@ -873,20 +996,30 @@ int gw_workspace_reserve(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_
     if (n_bins < 1 || n_det < 1 || n_det > gw::kMaxDet || n_samples < 0) return fail(GW_EINVAL, "bad reserve sizes");
     DeviceGuard g(ws->device);
     if (!g.ok) return fail(GW_EDEVICE, "cannot select the workspace device");
-    gw::TilePlan plan = plan_tiles(ws, n_bins, n_det, n_samples, false, gw::kFormSplit);
+    // every plan a call within these sizes may run: the current one of each
+    // form and precision and every candidate of the autotuner
+    const unsigned all_flags = GW_FLAG_DIRECT | GW_FLAG_TERM_ISCO | GW_FLAG_ADD_NORM;
+    size_t need = 0;
     for (int form = 0; form < gw::kForms; ++form)
         for (int mixed = 0; mixed < 2; ++mixed) {
-            const gw::TilePlan p = plan_tiles(ws, n_bins, n_det, n_samples, mixed != 0, form);
-            if (p.n_chunks > plan.n_chunks) plan = p;
+            std::vector<gw::TilePlan> plans = tuning_candidates(ws, n_bins, n_det, n_samples, mixed != 0, form);
+            plans.push_back(plan_tiles(ws, n_bins, n_det, n_samples, mixed != 0, form));
+            for (const gw::TilePlan &p : plans) need = std::max(need, lnl_layout(n_bins, n_det, n_samples, p, all_flags).total);
         }
-    const LnlLayout l = lnl_layout(n_bins, n_det, n_samples, plan,
-                                   GW_FLAG_DIRECT | GW_FLAG_TERM_ISCO | GW_FLAG_ADD_NORM);
     size_t wave = align_up(sizeof(gw::Tab1) * n_bins) + align_up(sizeof(gw::Tab2) * n_bins) +
                   align_up(sizeof(double) * gw::record_fields(std::max(n_det, 2)) * std::max<int64_t>(n_samples, 1));
-    return ensure_capacity(ws, std::max(l.total, wave), nullptr);
+    return ensure_capacity(ws, std::max(need, wave), nullptr);
 }
 
 int64_t gw_workspace_bytes(const gw_workspace *ws) { return ws ? (int64_t)ws->capacity : 0; }
+
+int gw_workspace_set_tuning(gw_workspace *ws, int enable)
+{
+    if (!ws) return fail(GW_EINVAL, "workspace is NULL");
+    ws->tune_single = enable > 0;
+    if (enable < 0) ws->single_tuning.clear();
+    return GW_OK;
+}
 
 int gw_lnl_batch(gw_workspace *ws, const gw_grid *grid, int n_det, const gw_detector *dets, const gw_c128 *data,
                  const double *psd, const double *theta, int n_param, int64_t n_samples, double *lnl_out,
@@ -920,7 +1053,7 @@ int64_t gw_lnl_batch_static_bytes(const gw_grid *grid, int n_det, int64_t n_samp
     std::lock_guard<std::mutex> lock(g_static_mutex);
     StaticDevice *d = nullptr;
     if (int rc = static_device(device, &d)) return rc;
-    const gw::TilePlan plan = plan_tiles_on(d->n_cu, d->blocks_per_cu, grid->n_bins, n_det, n_samples,
+    const gw::TilePlan plan = plan_tiles_on(d->n_cu, d->occupancy, grid->n_bins, n_det, n_samples,
                                             precision == GW_PREC_MIXED, gw::tile_form(flags));
     return (int64_t)lnl_layout(grid->n_bins, n_det, n_samples, plan, flags).total;
 }
@@ -948,7 +1081,7 @@ int gw_lnl_batch_static(const gw_grid *grid, int n_det, const gw_detector *dets,
     std::lock_guard<std::mutex> lock(g_static_mutex);
     StaticDevice *d = nullptr;
     if (int rc = static_device(device, &d)) return rc;
-    const gw::TilePlan plan = plan_tiles_on(d->n_cu, d->blocks_per_cu, grid->n_bins, n_det, n_samples, mixed,
+    const gw::TilePlan plan = plan_tiles_on(d->n_cu, d->occupancy, grid->n_bins, n_det, n_samples, mixed,
                                             gw::tile_form(flags));
     const LnlLayout l = lnl_layout(grid->n_bins, n_det, n_samples, plan, flags);
     if (l.total > kStaticScratchBytes)
@@ -1292,6 +1425,27 @@ int gw_lnl_plan(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples, 
     if (tile_bins) *tile_bins = p.tile_bins;
     if (n_chunks) *n_chunks = p.n_chunks;
     if (rounds) *rounds = p.rounds;
+    return GW_OK;
+}
+
+int gw_workspace_set_plan(gw_workspace *ws, int64_t n_bins, int n_det, int64_t n_samples, int precision,
+                          unsigned flags, int tile_bins, int rounds)
+{
+    if (!ws) return fail(GW_EINVAL, "workspace is NULL");
+    if (n_bins < 1 || n_det < 1 || n_det > gw::kMaxDet || n_samples < 1) return fail(GW_EINVAL, "bad plan sizes");
+    if (precision != GW_PREC_FP64 && precision != GW_PREC_MIXED) return fail(GW_EINVAL, "unknown precision");
+    if (flags & ~kLnlFlags) return fail(GW_EINVAL, "unknown flag bits");
+    const bool mixed = precision == GW_PREC_MIXED;
+    const int form = gw::tile_form(flags);
+    const auto key = tuning_key(n_bins, n_det, n_samples, mixed, form);
+    if (tile_bins == 0 && rounds == 0) {
+        ws->single_tuning.erase(key);
+        return GW_OK;
+    }
+    if (tile_bins < 64 || tile_bins % 64 != 0 || tile_bins > gw::tile_bins_for(n_det, form, mixed))
+        return fail(GW_EINVAL, "tile_bins must be a multiple of 64 within the LDS budget");
+    if (rounds < 0 || rounds > 16) return fail(GW_EINVAL, "rounds must be within 0..16");
+    ws->single_tuning[key] = {tile_bins, rounds};
     return GW_OK;
 }
 

@@ -69,8 +69,10 @@ inline int tile_bins_for(int n_det, int form, bool mixed)
     return t;
 }
 
-// resident: blocks of this kernel that fit on the device at once.
-inline TilePlan plan_single_event(int64_t n_bins, int64_t n_samples, int form, int tile_bins, int64_t resident)
+// resident: blocks of this kernel that fit on the device at once; rounds:
+// work-queue rounds (0: one block per item), GW_TILE_ROUNDS by default.
+inline TilePlan plan_single_event(int64_t n_bins, int64_t n_samples, int form, int tile_bins, int64_t resident,
+                                  int rounds = GW_TILE_ROUNDS)
 {
     TilePlan p;
     p.tile_bins = tile_bins;
@@ -82,7 +84,6 @@ inline TilePlan plan_single_event(int64_t n_bins, int64_t n_samples, int form, i
     p.n_chunks = (int)((n_bins + p.chunk_bins - 1) / p.chunk_bins);
     p.rounds = 0;
     p.blocks = p.n_groups * p.n_chunks;
-    const int rounds = GW_TILE_ROUNDS;
     // the ISCO end leaves the device-side band unknown here and usually short:
     // one item per resident block
     if (rounds >= 1 && form != kFormSplitIsco && (int64_t)p.n_chunks * rounds * 64 <= n_bins) {

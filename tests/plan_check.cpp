@@ -59,12 +59,18 @@ int main()
         if (n_bins < 1) continue;
         for (int64_t n_samples : samples)
             for (int form : {0, 1, 2})
-                for (int64_t resident : {256LL, 512LL, 768LL}) {
-                    const gw::TilePlan p = gw::plan_single_event(n_bins, n_samples, form, 512, resident);
+                for (int64_t resident : {256LL, 512LL, 768LL})
+                for (int tile : {256, 512, 1024})
+                for (int want : {-1, 0, 4, 6, 8}) {
+                    // want < 0: the default number of rounds
+                    const gw::TilePlan p = want < 0 ? gw::plan_single_event(n_bins, n_samples, form, tile, resident)
+                                                    : gw::plan_single_event(n_bins, n_samples, form, tile, resident, want);
+                    const int rounds = want < 0 ? GW_TILE_ROUNDS : want;
                     const int groups = (int)((n_samples + 255) / 256);
+                    if (p.tile_bins != tile) return fail("plan tile", n_bins, n_samples, p.tile_bins, tile);
                     if (p.n_groups != groups) return fail("plan groups", n_bins, n_samples, p.n_groups, groups);
                     if (p.n_chunks < 1 || (int64_t)p.n_chunks > n_bins) return fail("plan chunks", n_bins, n_samples, p.n_chunks, 0);
-                    if (p.rounds != 0 && p.rounds != GW_TILE_ROUNDS) return fail("plan rounds", n_bins, n_samples, p.rounds, 0);
+                    if (p.rounds != 0 && p.rounds != rounds) return fail("plan rounds", n_bins, n_samples, p.rounds, rounds);
                     if (form == 1 && p.rounds != 0) return fail("plan isco static", n_bins, n_samples, p.rounds, 0);
                     if (p.rounds > 0) {
                         if (p.n_chunks % p.rounds != 0) return fail("plan round split", n_bins, n_samples, p.n_chunks, p.rounds);

@@ -17,7 +17,7 @@ STUB = r"""
 #include <stdint.h>
 #include <string.h>
 #ifndef VERSION
-#define VERSION 300
+#define VERSION 301
 #endif
 #ifndef GRID_SIZE
 #define GRID_SIZE 24

@@ -28,7 +28,8 @@ def test_relbin_flop_tally():
 
 def _summary(tmp_path, sha):
     text = (f"# test\n\nkernel_source_sha256: {sha}\n\n"
-            "traffic_bytes_per_launch_fp64: 3.25e+07\nexecuted_fp64_flops_per_launch_fp64: 7.8e+10\n")
+            "traffic_bytes_per_launch_fp64@512x6: 3.25e+07\nexecuted_fp64_flops_per_launch_fp64@512x6: 7.8e+10\n"
+            "executed_fp64_flops_per_launch_fp64@256x6: 7.9e+10\n")
     path = tmp_path / "summary.md"
     path.write_text(text)
     return str(path)
@@ -38,15 +39,26 @@ def test_profile_values_follow_the_fingerprint(tmp_path):
     # an absolute summary path is read as given, checked against the tile kernel's sources
     tile = bench.PROFILE_SUMMARY
     good = _summary(tmp_path, bench.kernel_fingerprint(tile))
-    assert bench.measured_traffic("fp64", good, tile) == pytest.approx(3.25e7)
-    assert bench.measured_executed_flops("fp64", good, tile) == pytest.approx(7.8e10)
-    assert bench.measured_traffic("mixed", good, tile) is None
+    assert bench.measured_traffic("fp64@512x6", good, tile) == pytest.approx(3.25e7)
+    assert bench.measured_executed_flops("fp64@512x6", good, tile) == pytest.approx(7.8e10)
+    assert bench.measured_executed_flops("fp64@256x6", good, tile) == pytest.approx(7.9e10)
+    assert bench.measured_traffic("fp64@256x6", good, tile) is None
+    assert bench.measured_traffic("mixed@512x6", good, tile) is None
     stale = _summary(tmp_path, "0" * 64)
-    assert bench.measured_traffic("fp64", stale, tile) is None
-    assert bench.measured_executed_flops("fp64", stale, tile) is None
-    assert bench.measured_traffic("fp64", str(tmp_path / "missing.md"), tile) is None
+    assert bench.measured_traffic("fp64@512x6", stale, tile) is None
+    assert bench.measured_executed_flops("fp64@512x6", stale, tile) is None
+    assert bench.measured_traffic("fp64@512x6", str(tmp_path / "missing.md"), tile) is None
     # another kernel's sources give another fingerprint
-    assert bench.measured_traffic("fp64", good, bench.WAVEFORM_PROFILE) is None
+    assert bench.measured_traffic("fp64@512x6", good, bench.WAVEFORM_PROFILE) is None
+
+
+def test_figures_are_kept_per_plan(tmp_path):
+    tile = bench.PROFILE_SUMMARY
+    good = _summary(tmp_path, bench.kernel_fingerprint(tile))
+    assert bench.plan_key("fp64", {"tile_bins": 256, "rounds": 6}) == "fp64@256x6"
+    assert sorted(bench.profiled_plans("fp64", good, tile)) == ["256x6", "512x6"]
+    assert bench.profiled_plans("mixed", good, tile) == []
+    assert bench.profiled_plans("fp64", _summary(tmp_path, "0" * 64), tile) == []
 
 
 def test_fingerprints_cover_each_kernels_sources():

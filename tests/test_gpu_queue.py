@@ -7,7 +7,8 @@ gw_lnl_plan before each call) and ragged in both sample count and bin count.
 Bar: every row within 1e-10 relative of the oracle.  The queue hands items to
 blocks in an order that changes from call to call, but each item's partial
 sums are formed over fixed bins in a fixed order and added in chunk order,
-so repeated calls, also on another stream, agree bit for bit.
+so repeated calls, also on another stream, agree bit for bit.  The tests
+run the default plan (plan autotuning off), whose shape they check.
 """
 import numpy as np
 import pytest
@@ -37,6 +38,12 @@ def gw():
     return gw
 
 
+def _ws(gw):
+    ws = gw.Workspace(0)
+    ws.set_tuning(False)
+    return ws
+
+
 def _event(seed, n_det, n_bins, n_samples, spins):
     w = synth.small_event(seed, n_det, n_bins, n_samples, 9, delta_f=1.0 / 64.0)
     theta = synth.add_spins(w.theta, np.random.default_rng(seed), 0.8) if spins else w.theta
@@ -63,7 +70,7 @@ def _run(gw, w, theta, data, ws, stream=None):
 @pytest.mark.parametrize("seed,n_det,n_bins,n_samples,spins", QUEUE_CASES)
 def test_queue_launch_matches_oracle(gw, seed, n_det, n_bins, n_samples, spins):
     w, theta, data = _event(seed, n_det, n_bins, n_samples, spins)
-    ws = gw.Workspace(0)
+    ws = _ws(gw)
     plan = ws.lnl_plan(n_bins, n_det, n_samples)
     print(f"seed {seed} det {n_det} bins {n_bins} S {n_samples} spins {spins}: plan {plan}", flush=True)
     assert plan["rounds"] > 0 and plan["n_chunks"] % plan["rounds"] == 0
@@ -79,17 +86,17 @@ def test_queue_launch_matches_oracle(gw, seed, n_det, n_bins, n_samples, spins):
 def test_queue_launch_is_bitwise_repeatable(gw):
     import torch
     w, theta, data = _event(31, 3, 40_001, 4000, False)
-    ws = gw.Workspace(0)
+    ws = _ws(gw)
     assert ws.lnl_plan(40_001, 3, 4000)["rounds"] > 0
     a = _run(gw, w, theta, data, ws)
     b = _run(gw, w, theta, data, ws)
-    c = _run(gw, w, theta, data, gw.Workspace(0), stream=torch.cuda.Stream())
+    c = _run(gw, w, theta, data, _ws(gw), stream=torch.cuda.Stream())
     np.testing.assert_array_equal(a, b)
     np.testing.assert_array_equal(a, c)
 
 
 def test_plan_rules(gw):
-    ws = gw.Workspace(0)
+    ws = _ws(gw)
     # small events: one block per item
     assert ws.lnl_plan(3001, 3, 300)["rounds"] == 0
     # the template end keeps one block per item (its band is known only on the device)
@@ -115,7 +122,7 @@ def test_queue_launch_replays_from_a_graph(gw):
     d = torch.from_numpy(np.ascontiguousarray(data)).to(dev)
     s = torch.from_numpy(w.psd).to(dev)
     th = torch.from_numpy(np.ascontiguousarray(theta)).to(dev)
-    ws = gw.Workspace(0)
+    ws = _ws(gw)
     assert ws.lnl_plan(40_001, 3, 4000)["rounds"] > 0
     eager = gw.lnl_batch(w.grid, w.tensors, w.vertices, d, s, th, workspace=ws).clone()
     out = torch.empty_like(eager)
@@ -129,7 +136,7 @@ def test_queue_launch_replays_from_a_graph(gw):
     with torch.cuda.graph(graph):
         gw.lnl_batch(w.grid, w.tensors, w.vertices, d, s, th, workspace=ws, out=out)
     torch.cuda.synchronize()
-    other = gw.Workspace(0)
+    other = _ws(gw)
     th2 = th.flip(0).contiguous()
     for rep in range(3):
         out.zero_()
@@ -154,9 +161,9 @@ def test_captured_call_keeps_its_tables_and_pins_the_workspace(gw):
     s = torch.from_numpy(w.psd).to(dev)
     th = torch.from_numpy(np.ascontiguousarray(theta)).to(dev)
     other_grid = (w.grid.f_low + 7.0, w.grid.delta_f, w.grid.n_bins)
-    ws = gw.Workspace(0)
+    ws = _ws(gw)
     eager = gw.lnl_batch(w.grid, w.tensors, w.vertices, d, s, th, workspace=ws).clone()
-    want_b = gw.lnl_batch(other_grid, w.tensors, w.vertices, d, s, th, workspace=gw.Workspace(0)).clone()
+    want_b = gw.lnl_batch(other_grid, w.tensors, w.vertices, d, s, th, workspace=_ws(gw)).clone()
     out = torch.empty_like(eager)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()

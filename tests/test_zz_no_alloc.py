@@ -29,6 +29,7 @@ def test_static_entry_matches_workspace_call_on_two_calls():
     import paper_1904_02863_amd as gw
     gw.load_library()
     ws = gw.Workspace(0)
+    ws.set_tuning(False)                 # the default plan, which the static entry point uses
     cap = gw.lnl_batch_static_capacity()
     assert cap == 64 << 20
     big = synth.bbh_3det_128s(4096)
