@@ -359,7 +359,7 @@ def flow_comparison(args, spins: bool):
     burn = args.mcmc_burn if args.mcmc_burn is not None else (40000 if spins else 4000)
     t0 = time.perf_counter()
     res = sampler.compare_samplers(prob, p_inj, ws, n_chains=4096, burn=burn, steps=args.mcmc_steps,
-                                   flow_steps=args.flow_steps)
+                                   flow_steps=args.flow_steps, lr=args.flow_lr, lr_final=args.flow_lr_final)
     res["wall_seconds"] = time.perf_counter() - t0
     res["burn_in_steps"] = burn
     res["spins"] = spins
@@ -385,6 +385,7 @@ def bench_flow(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+bf16", "data": "synthetic",
         "config": {"workload": "flow-mcmc", "chains": 4096, "ess_chains": 256, "snr": 25.0,
                    "burn_in_steps": res["burn_in_steps"], "flow_train_steps": args.flow_steps,
+                   "flow_lr": args.flow_lr, "flow_lr_final": args.flow_lr_final,
                    "train_samples": res["train_samples"], "precision": args.precision, "spins": args.spins},
     }
     result.update(res)
@@ -701,6 +702,9 @@ def main():
                     help="flow-mcmc: random-walk burn-in steps (default 40000 with aligned spins, 4000 without)")
     ap.add_argument("--mcmc-steps", type=int, default=1024, help="flow-mcmc: production steps of each sampler")
     ap.add_argument("--flow-steps", type=int, default=3000, help="flow-mcmc: Adam steps")
+    ap.add_argument("--flow-lr", type=float, default=1e-3, help="flow-mcmc: Adam step size")
+    ap.add_argument("--flow-lr-final", type=float, default=None,
+                    help="flow-mcmc: end the step size here on a half cosine (default: constant)")
     ap.add_argument("--samples", type=int, default=None)
     ap.add_argument("--plan", default=None, metavar="TILE,ROUNDS",
                     help="run this likelihood plan (LDS tile bins, work-queue rounds) instead of the autotuned one")

@@ -43,25 +43,113 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_floa
 // ---------------------------------------------------------------- GEMM on MFMA
 // C[M x N] = A[M x K] B[K x N] (+ bias[N]) (ReLU if relu), FP32 accumulation.
 // A(i, k) = A[i sa_i + k sa_k], B(k, j) = B[k sb_k + j sb_j], both BF16.
-// Block: 256 threads, 64 x 64 output tile (blockIdx.z: K slice when split),
-// K in steps of 16 through LDS; each
-// of the 4 waves owns a 32 x 32 quarter as 2 x 2 tiles of
-// v_mfma_f32_16x16x16_bf16.  Operand layout of that instruction (wave64):
-// lane l supplies A(row l%16, k = 4(l/16)+0..3) and B(k = 4(l/16)+0..3,
-// col l%16) and receives D(row 4(l/16)+0..3, col l%16).
-typedef short short4_t __attribute__((ext_vector_type(4)));
+// Block: 256 threads, a 64 x 64 output tile (blockIdx.z: K slice when split).
+// The K range goes through LDS in chunks of up to 128: both operands are
+// stored k-contiguous (A as [row][k], B as [col][k]) so that every lane reads
+// its 8 consecutive k with one 16-byte LDS load, and the next chunk's global
+// loads are issued before the current chunk's products; the bias is read at
+// the start, under the first wait.  (Chunks of 256, one wait for every
+// product of the flow, measured no faster: the LDS then holds two blocks per
+// CU instead of four.)  Global loads move 8 BF16 (16 bytes)
+// along whichever index the operand is contiguous in (template flags: A_KC /
+// B_KC when contiguous in k), element by element where a vector would leave
+// the matrix or is misaligned.  Each of the 4 waves owns a 32 x 32 quarter as
+// 2 x 2 tiles of v_mfma_f32_16x16x32_bf16: lane l supplies A(row l%16, 8
+// consecutive k of group l/16) and B(the same k, col l%16), A and B with the
+// same k order, and receives D(row 4(l/16)+0..3, col l%16).
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
+constexpr int kTileMN = 64;           // output tile edge
+constexpr int kChunkK = 128;          // K per LDS chunk
+constexpr int kLdsK = kChunkK + 8;    // LDS row length in BF16 (16-byte aligned rows, staggered banks)
+constexpr int kVecPerThread = kTileMN * kChunkK / 8 / 256;   // 16-byte vectors per thread and operand
+
+__device__ __forceinline__ uint16_t u16_at(uint4 v, int e)
 {
-    __shared__ uint16_t as[64][16 + 2];
-    __shared__ uint16_t bs[16][64 + 2];
+    const uint32_t w = e < 2 ? v.x : e < 4 ? v.y : e < 6 ? v.z : v.w;
+    return (uint16_t)((e & 1) ? (w >> 16) : (w & 0xffffu));
+}
+
+// 8 BF16 of a matrix with strides (s_c, s_o) along its contiguous and other
+// index: elements (c0 + e, o) for e < 8, zero where c0 + e >= c_end or the
+// row is out of range (o_ok false).  vec: the 8 elements may be read as one
+// aligned 16-byte vector whenever all of them are in range.
+__device__ __forceinline__ uint4 load8(const uint16_t *__restrict__ base, int64_t s_o, int c0, int c_end, int o,
+                                       bool o_ok, bool vec)
+{
+    uint4 r = make_uint4(0u, 0u, 0u, 0u);
+    if (!o_ok || c0 >= c_end) return r;
+    const uint16_t *p = base + (int64_t)o * s_o + c0;
+    if (vec && c0 + 8 <= c_end) return *reinterpret_cast<const uint4 *>(p);
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if (c0 + e < c_end) w[e >> 1] |= (uint32_t)p[e] << ((e & 1) * 16);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// One operand's share of a chunk: KC = true when the operand is contiguous
+// in k.  Tile rows (A rows or B columns) t0 .. t0 + 63 below t_end, k in
+// [k0, k0 + kc) below k_hi.  Vector v of this thread: KC, tile row
+// v / (kChunkK / 8) and k group v % (kChunkK / 8) (8 k each); otherwise
+// k = v / 8 and tile-row group v % 8.
+template <bool KC>
+__device__ __forceinline__ void load_chunk(const uint16_t *__restrict__ X, int64_t s_t, int64_t s_k, int t0,
+                                           int t_end, int k0, int kc, int k_hi, bool vec, uint4 (&reg)[kVecPerThread])
+{
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < kVecPerThread; ++e) {
+        const int v = tid + 256 * e;
+        if (KC) {
+            const int t = v / (kChunkK / 8), kg = v % (kChunkK / 8);
+            const int k = k0 + 8 * kg;
+            // contiguous in k: the 8 elements run along k, rows along t
+            reg[e] = (8 * kg < kc) ? load8(X, s_t, k, k_hi, t0 + t, t0 + t < t_end, vec) : make_uint4(0u, 0u, 0u, 0u);
+        } else {
+            const int kk = v >> 3, tg = v & 7;
+            const int k = k0 + kk;
+            reg[e] = (kk < kc) ? load8(X, s_k, t0 + 8 * tg, t_end, k, k < k_hi, vec) : make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
+}
+
+template <bool KC>
+__device__ __forceinline__ void store_chunk(uint16_t (*lds)[kLdsK], int kc, const uint4 (&reg)[kVecPerThread])
+{
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < kVecPerThread; ++e) {
+        const int v = tid + 256 * e;
+        if (KC) {
+            const int t = v / (kChunkK / 8), kg = v % (kChunkK / 8);
+            if (8 * kg < kc) *reinterpret_cast<uint4 *>(&lds[t][8 * kg]) = reg[e];
+        } else {
+            const int kk = v >> 3, tg = v & 7;
+            if (kk < kc) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) lds[8 * tg + q][kk] = u16_at(reg[e], q);
+            }
+        }
+    }
+}
+
+// K of the chunk starting at k0: up to kChunkK, rounded up to the 32 of one product step.
+__device__ __forceinline__ int chunk_len(int k0, int k_hi) { return min(kChunkK, (k_hi - k0 + 31) / 32 * 32); }
+
+template <bool A_KC, bool B_KC>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int vec_a, int vec_b)
+{
+    __shared__ __align__(16) uint16_t as[kTileMN][kLdsK];
+    __shared__ __align__(16) uint16_t bs[kTileMN][kLdsK];
+    __shared__ double colred[2][4][kTileMN];   // column sums: [row half][lane group][tile column]
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
+    const int row0 = blockIdx.y * kTileMN, col0 = blockIdx.x * kTileMN;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-    // K slice of this block (the whole range unless split)
-    const int ks = ((g.K + g.split - 1) / g.split + 15) / 16 * 16;
+    // K slice of this block (the whole range unless split), a multiple of 32
+    const int ks = ((g.K + g.split - 1) / g.split + 31) / 32 * 32;
     const int k_lo = (int)blockIdx.z * ks, k_hi = min(g.K, k_lo + ks);
     float4_t acc[2][2];
 #pragma unroll
@@ -69,39 +157,49 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = float4_t{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = k_lo; k0 < k_hi; k0 += 16) {
-        __syncthreads();
+    const int rq = 4 * (lane >> 4), lc = lane & 15;
+    const bool to_partial = g.split > 1 || g.defer;
+    float bias[2] = {0.f, 0.f};
+    if (g.bias && !to_partial) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int idx = tid + 256 * e;          // 0 .. 1023
-            {   // A tile 64 x 16
-                const int i = idx >> 4, k = idx & 15;
-                const int gi = row0 + i, gk = k0 + k;
-                as[i][k] = (gi < g.M && gk < k_hi) ? g.A[(int64_t)gi * g.sa_i + (int64_t)gk * g.sa_k] : (uint16_t)0;
-            }
-            {   // B tile 16 x 64
-                const int k = idx >> 6, j = idx & 63;
-                const int gk = k0 + k, gj = col0 + j;
-                bs[k][j] = (gk < k_hi && gj < g.N) ? g.B[(int64_t)gk * g.sb_k + (int64_t)gj * g.sb_j] : (uint16_t)0;
-            }
-        }
-        __syncthreads();
-        const int kq = 4 * (lane >> 4), lr = lane & 15;
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            short4_t av;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) av[r] = (short)as[wr + 16 * a + lr][kq + r];
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                short4_t bv;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) bv[r] = (short)bs[kq + r][wc + 16 * b + lr];
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[a][b], 0, 0, 0);
-            }
+        for (int b = 0; b < 2; ++b) {
+            const int j = col0 + wc + 16 * b + lc;
+            bias[b] = j < g.N ? g.bias[j] : 0.f;
         }
     }
-    const int rq = 4 * (lane >> 4), lc = lane & 15;
+    uint4 ra[kVecPerThread], rb[kVecPerThread];
+    if (k_lo < k_hi) {
+        const int kc = chunk_len(k_lo, k_hi);
+        load_chunk<A_KC>(g.A, g.sa_i, g.sa_k, row0, g.M, k_lo, kc, k_hi, vec_a != 0, ra);
+        load_chunk<B_KC>(g.B, g.sb_j, g.sb_k, col0, g.N, k_lo, kc, k_hi, vec_b != 0, rb);
+    }
+    for (int k0 = k_lo; k0 < k_hi; k0 += kChunkK) {
+        const int kc = chunk_len(k0, k_hi);
+        __syncthreads();                       // the previous chunk's reads are done
+        store_chunk<A_KC>(as, kc, ra);
+        store_chunk<B_KC>(bs, kc, rb);
+        __syncthreads();
+        const int kn = k0 + kChunkK;
+        if (kn < k_hi) {                       // next chunk in flight during the products
+            const int kcn = chunk_len(kn, k_hi);
+            load_chunk<A_KC>(g.A, g.sa_i, g.sa_k, row0, g.M, kn, kcn, k_hi, vec_a != 0, ra);
+            load_chunk<B_KC>(g.B, g.sb_j, g.sb_k, col0, g.N, kn, kcn, k_hi, vec_b != 0, rb);
+        }
+        const int kq = 8 * (lane >> 4), lr = lane & 15;
+        for (int kk = 0; kk < kc; kk += 32) {
+            bf16x8_t av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = *reinterpret_cast<const bf16x8_t *>(&as[wr + 16 * a + lr][kk + kq]);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = *reinterpret_cast<const bf16x8_t *>(&bs[wc + 16 * b + lr][kk + kq]);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+    }
+    double csum[2] = {0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -112,16 +210,37 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
                 const int j = col0 + wc + 16 * b + lc;
                 if (i < g.M && j < g.N) {
                     float v = acc[a][b][r];
-                    if (g.split > 1) {
+                    if (to_partial) {
                         g.partial[((int64_t)blockIdx.z * g.M + i) * g.N + j] = v;
                         continue;
                     }
-                    if (g.bias) v += g.bias[j];
+                    if (g.bias) v += bias[b];
                     if (g.relu) v = v > 0.f ? v : 0.f;
+                    if (g.relu_of) {
+                        const uint16_t h = g.relu_of[(int64_t)i * g.ld_relu + j];
+                        v = ((h & 0x7fffu) != 0 && !(h & 0x8000u)) ? v : 0.f;
+                    }
                     if (g.C) g.C[(int64_t)i * g.ldc + j] = v;
                     if (g.Cb) g.Cb[(int64_t)i * g.ldcb + j] = f32_to_bf16(v);
+                    csum[b] += (double)v;
                 }
             }
+    if (g.col_part && !to_partial) {
+        // the block's 64 rows: each lane's 8, then the 4 lane groups and the
+        // two row halves, in that fixed order
+#pragma unroll
+        for (int b = 0; b < 2; ++b) colred[wave >> 1][lane >> 4][wc + 16 * b + lc] = csum[b];
+        __syncthreads();
+        const int j = col0 + tid;
+        if (tid < kTileMN && j < g.N) {
+            double t = 0.0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) t += colred[h][q][tid];
+            g.col_part[(int64_t)blockIdx.y * g.N + j] = t;
+        }
+    }
 }
 
 // Sums the split-K slices in slice order, then bias, ReLU and the outputs.
@@ -138,14 +257,35 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g)
     if (g.Cb) g.Cb[(int64_t)i * g.ldcb + j] = f32_to_bf16(v);
 }
 
+// An operand can be read in 16-byte vectors along its contiguous index when
+// that stride is 1, the other stride is a multiple of 8 elements and the base
+// is 16-byte aligned (vectors start at multiples of 8 along the contiguous index).
+static bool vector_ok(const uint16_t *p, int64_t s_contig, int64_t s_other)
+{
+    return s_contig == 1 && s_other % 8 == 0 && (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+}
+
 hipError_t gemm_bf16(const GemmArgs &g, hipStream_t stream)
 {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
-    if (g.split < 1 || g.split > kMaxSplit || (g.split > 1 && !g.partial)) return hipErrorInvalidValue;
-    const dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.split);
-    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, stream, g);
+    if (g.split < 1 || g.split > kMaxSplit || ((g.split > 1 || g.defer) && !g.partial)) return hipErrorInvalidValue;
+    if ((g.col_part || g.relu_of) && (g.split > 1 || g.defer)) return hipErrorInvalidValue;
+    // A is read along k when its k stride is 1, else along i (stride 1 required then)
+    const bool a_kc = g.sa_k == 1, b_kc = g.sb_k == 1;
+    if ((!a_kc && g.sa_i != 1) || (!b_kc && g.sb_j != 1)) return hipErrorInvalidValue;
+    const int va = a_kc ? vector_ok(g.A, g.sa_k, g.sa_i) : vector_ok(g.A, g.sa_i, g.sa_k);
+    const int vb = b_kc ? vector_ok(g.B, g.sb_k, g.sb_j) : vector_ok(g.B, g.sb_j, g.sb_k);
+    const dim3 grid((g.N + kTileMN - 1) / kTileMN, (g.M + kTileMN - 1) / kTileMN, g.split);
+    if (a_kc && b_kc)
+        hipLaunchKernelGGL((gemm_bf16_kernel<true, true>), grid, dim3(256), 0, stream, g, va, vb);
+    else if (a_kc)
+        hipLaunchKernelGGL((gemm_bf16_kernel<true, false>), grid, dim3(256), 0, stream, g, va, vb);
+    else if (b_kc)
+        hipLaunchKernelGGL((gemm_bf16_kernel<false, true>), grid, dim3(256), 0, stream, g, va, vb);
+    else
+        hipLaunchKernelGGL((gemm_bf16_kernel<false, false>), grid, dim3(256), 0, stream, g, va, vb);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || g.split == 1) return e;
+    if (e != hipSuccess || g.split == 1 || g.defer) return e;
     const int64_t total = (int64_t)g.M * g.N;
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, g);
     return hipGetLastError();
@@ -279,42 +419,78 @@ __global__ __launch_bounds__(256) void coupling_inv_backward_kernel(int n, int d
     }
 }
 
-// dpre = dh * (h > 0) in place (FP32) and as BF16.
-__global__ __launch_bounds__(256) void relu_backward_kernel(int64_t count, float *__restrict__ dh,
-                                                            const uint16_t *__restrict__ h, uint16_t *__restrict__ db)
+// Column sums of m [rows][cols] (leading dimension ld, cols <= 64) over each
+// block of 64 rows, in FP64 and a fixed order: the block's 4 waves take rows
+// 4 q + w of it, then their sums are added in wave order; part [block][cols].
+// The same 64-row blocks as the GEMM's column sums.
+__global__ __launch_bounds__(256) void column_part_kernel(int rows, int cols, int ld, const float *__restrict__ m,
+                                                          double *__restrict__ part)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= count) return;
-    const float v = (h[idx] & 0x7fffu) != 0 && !(h[idx] & 0x8000u) ? dh[idx] : 0.f;
-    dh[idx] = v;
-    db[idx] = f32_to_bf16(v);
+    __shared__ double red[4][64];
+    const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r0 = (int)blockIdx.x * 64, r1 = min(rows, r0 + 64);
+    double acc = 0.0;
+    if (c < cols) {
+#pragma unroll 4
+        for (int b = r0 + w; b < r1; b += 4) acc += (double)m[(int64_t)b * ld + c];
+    }
+    red[w][c] = acc;
+    __syncthreads();
+    if (w == 0 && c < cols) part[(int64_t)blockIdx.x * cols + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
 }
 
-// out[j] = sum_b m[b][j] (fixed order over b), j < cols.
-// Column sums of m [rows][cols] (leading dimension ld) in two passes: slice
-// y of the rows into part[y][cols] (FP64), then the slices in order.
-constexpr int kColSlices = 32;
+// Gradient of every parameter from the partial sums the backward pass left,
+// one thread per parameter, in a fixed order.  Layer l's parameters are
+// w1 [H][D], b1 [H], w2 [H][H], b2 [H], w3 [2D][H], b3 [2D]; its weight
+// partials (FP32) are split slices of each matrix at wpart + l * w_layer
+// (w1, w2, w3 regions of kMaxSplit slices each), summed in slice order in
+// FP32; its bias partials (FP64) are 64-row block sums of the gradients of
+// the three layers' outputs (b1, b2: rb64 blocks of H each; b3: rb64 blocks
+// of 2D), summed in block order.
+struct GradParts {
+    int D, H, split, rb64, rb64_cap;
+    int64_t per_layer, n_params, w_layer, b_layer;
+    const float *wpart;
+    const double *bpart;
+};
 
-__global__ __launch_bounds__(256) void column_partial_kernel(int rows, int cols, int ld, const float *__restrict__ m,
-                                                             double *__restrict__ part)
+__global__ __launch_bounds__(256) void grad_finish_kernel(GradParts gp, float *__restrict__ grads)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cols) return;
-    const int per = (rows + kColSlices - 1) / kColSlices;
-    const int r0 = (int)blockIdx.y * per, r1 = min(rows, r0 + per);
-    double acc = 0.0;
-    for (int b = r0; b < r1; ++b) acc += (double)m[(int64_t)b * ld + j];
-    part[(int64_t)blockIdx.y * cols + j] = acc;
-}
-
-__global__ __launch_bounds__(256) void column_finish_kernel(int cols, const double *__restrict__ part,
-                                                            float *__restrict__ out)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cols) return;
-    double acc = 0.0;
-    for (int y = 0; y < kColSlices; ++y) acc += part[(int64_t)y * cols + j];
-    out[j] = (float)acc;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= gp.n_params) return;
+    const int64_t D = gp.D, H = gp.H;
+    const int64_t l = p / gp.per_layer;
+    int64_t q = p - l * gp.per_layer;
+    const float *w = gp.wpart + l * gp.w_layer;
+    const double *bp = gp.bpart + l * gp.b_layer;
+    const int64_t sz1 = H * D, sz2 = H * H, sz3 = 2 * D * H;
+    const float *wr = nullptr;
+    int64_t wsz = 0;
+    const double *br = nullptr;
+    int64_t bcols = 0, bn = 0;
+    if (q < sz1) {
+        wr = w, wsz = sz1;
+    } else if ((q -= sz1) < H) {
+        br = bp, bcols = H, bn = gp.rb64;
+    } else if ((q -= H) < sz2) {
+        wr = w + kMaxSplit * sz1, wsz = sz2;
+    } else if ((q -= sz2) < H) {
+        br = bp + gp.rb64_cap * H, bcols = H, bn = gp.rb64;
+    } else if ((q -= H) < sz3) {
+        wr = w + kMaxSplit * (sz1 + sz2), wsz = sz3;
+    } else {
+        q -= sz3;
+        br = bp + 2 * gp.rb64_cap * H, bcols = 2 * D, bn = gp.rb64;
+    }
+    if (wr) {
+        float v = 0.f;
+        for (int z = 0; z < gp.split; ++z) v += wr[z * wsz + q];
+        grads[p] = v;
+    } else {
+        double t = 0.0;
+        for (int64_t y = 0; y < bn; ++y) t += br[y * bcols + q];
+        grads[p] = (float)t;
+    }
 }
 
 // d loss / d y for the conditioning dimensions: add the MLP input gradient.
@@ -342,13 +518,15 @@ __global__ __launch_bounds__(256) void adam_kernel(int64_t count, float *__restr
     p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
-// BF16 copies of the weight matrices (FP32 master -> BF16).
-__global__ __launch_bounds__(256) void to_bf16_kernel(int64_t count, const float *__restrict__ src,
-                                                      uint16_t *__restrict__ dst)
+// BF16 copies of the weight matrices (FP32 master -> BF16): parameter i of
+// layer i / per_layer goes to dst[layer * dst_stride + i % per_layer].
+__global__ __launch_bounds__(256) void to_bf16_kernel(int64_t count, int64_t per_layer, int64_t dst_stride,
+                                                      const float *__restrict__ src, uint16_t *__restrict__ dst)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    dst[i] = f32_to_bf16(src[i]);
+    const int64_t l = i / per_layer;
+    dst[l * dst_stride + (i - l * per_layer)] = f32_to_bf16(src[i]);
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(int64_t n, double *__restrict__ p)
@@ -381,6 +559,7 @@ struct gw_flow {
     int dim = 0, layers = 0, hidden = 0;
     std::vector<unsigned> cond;           // conditioning mask per layer
     int64_t per_layer = 0, n_params = 0;
+    int64_t wb_stride = 0;                // layer stride of the BF16 copy (per_layer rounded up to 8)
     float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
     uint16_t *wb = nullptr;               // BF16 copy of params
     double *mu = nullptr, *log_sigma = nullptr;
@@ -398,8 +577,14 @@ struct gw_flow {
     float *dh = nullptr;                  // [cap][hidden]
     uint16_t *dpre_b = nullptr;           // [cap][hidden]
     float *dxm = nullptr;                 // [cap][dim]
-    float *splitk = nullptr;              // split-K partials of the weight gradients
-    double *colpart = nullptr;            // column-sum partials [kColSlices][max(hidden, 2 dim)]
+    uint16_t *dpre2_b = nullptr;          // [cap][hidden], the other layer's BF16 pre-activation gradient
+    // partial sums of the gradients (summed by grad_finish_kernel): per layer,
+    // split-K slices of the three weight matrices (FP32, w_layer floats) and
+    // row-block sums of the three biases (FP64, b_layer doubles)
+    float *wpart = nullptr;
+    double *bpart = nullptr;
+    int64_t w_layer = 0, b_layer = 0;
+    int rb64_cap = 0;
 };
 
 namespace {
@@ -431,13 +616,18 @@ struct DeviceGuard {
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-// offsets of one layer's parameters (floats)
-struct LayerOff { int64_t w1, b1, w2, b2, w3, b3; };
+// Offsets of one layer's parameters: p the layer's start in the FP32
+// parameters (and gradients), q its start in the BF16 copy, whose layers
+// start at multiples of 8 elements (wb_stride) so that the weight matrices
+// are 16-byte aligned for the GEMM's vector loads; w1 .. b3 within the layer.
+struct LayerOff { int64_t p, q, w1, b1, w2, b2, w3, b3; };
 LayerOff layer_off(const gw_flow *f, int l)
 {
     const int64_t D = f->dim, H = f->hidden;
     LayerOff o;
-    o.w1 = l * f->per_layer;
+    o.p = l * f->per_layer;
+    o.q = l * f->wb_stride;
+    o.w1 = 0;
     o.b1 = o.w1 + H * D;
     o.w2 = o.b1 + H;
     o.b2 = o.w2 + H * H;
@@ -455,12 +645,13 @@ hipError_t alloc(T **p, int64_t count)
 void free_batch(gw_flow *f)
 {
     void *ptrs[] = {f->bound, f->s_store, f->sum_s, f->loss, f->g, f->gy, f->xm_b, f->h1_b, f->h2_b,
-                    f->out_f, f->dout_f, f->dout_b, f->dh, f->dpre_b, f->dxm, f->splitk, f->colpart};
+                    f->out_f, f->dout_f, f->dout_b, f->dh, f->dpre_b, f->dpre2_b, f->dxm, f->wpart, f->bpart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    f->bound = f->s_store = f->sum_s = f->loss = f->g = f->gy = f->colpart = nullptr;
+    f->bound = f->s_store = f->sum_s = f->loss = f->g = f->gy = f->bpart = nullptr;
+    f->dpre2_b = nullptr;
     f->xm_b = f->h1_b = f->h2_b = f->dout_b = f->dpre_b = nullptr;
-    f->out_f = f->dout_f = f->dh = f->dxm = f->splitk = nullptr;
+    f->out_f = f->dout_f = f->dh = f->dxm = f->wpart = nullptr;
     f->cap = 0;
 }
 
@@ -472,17 +663,22 @@ int ensure_batch(gw_flow *f, int64_t n)
     free_batch(f);
     const int64_t c = std::max<int64_t>(n, 256);
     const int64_t D = f->dim, H = f->hidden, L = f->layers;
+    const int rb64 = (int)((c + 63) / 64);
+    const int64_t w_layer = (int64_t)gw::flow::kMaxSplit * (H * D + H * H + 2 * D * H);
+    const int64_t b_layer = (int64_t)rb64 * (2 * H + 2 * D);
     if (alloc(&f->bound, (L + 2) * c * D) || alloc(&f->s_store, L * c * D) || alloc(&f->sum_s, c) ||
         alloc(&f->loss, c) || alloc(&f->g, c * D) || alloc(&f->gy, c * D) || alloc(&f->xm_b, L * c * kInPad) ||
         alloc(&f->h1_b, L * c * H) || alloc(&f->h2_b, L * c * H) || alloc(&f->out_f, c * 2 * D) ||
         alloc(&f->dout_f, c * kOutPad) || alloc(&f->dout_b, c * kOutPad) || alloc(&f->dh, c * H) ||
         alloc(&f->dpre_b, c * H) || alloc(&f->dxm, c * D) ||
-        alloc(&f->splitk, (int64_t)gw::flow::kMaxSplit * std::max<int64_t>(H, 2 * D) * H) ||
-        alloc(&f->colpart, (int64_t)gw::flow::kColSlices * std::max<int64_t>(H, 2 * D))) {
+        alloc(&f->dpre2_b, c * H) || alloc(&f->wpart, L * w_layer) || alloc(&f->bpart, L * b_layer)) {
         free_batch(f);
         return fail(GW_ENOMEM, "flow batch buffers");
     }
     f->cap = c;
+    f->w_layer = w_layer;
+    f->b_layer = b_layer;
+    f->rb64_cap = rb64;
     return GW_OK;
 }
 
@@ -500,11 +696,13 @@ hipError_t mlp_forward(gw_flow *f, int l, int n, const double *a, hipStream_t s)
     hipLaunchKernelGGL(gw::flow::mask_input_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], a, xm);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    GemmArgs g1{n, H, D, xm, kInPad, 1, f->wb + o.w1, 1, D, nullptr, 0, h1, H, f->params + o.b1, 1};
+    const uint16_t *wq = f->wb + o.q;
+    const float *pp = f->params + o.p;
+    GemmArgs g1{n, H, D, xm, kInPad, 1, wq + o.w1, 1, D, nullptr, 0, h1, H, pp + o.b1, 1};
     if ((e = gw::flow::gemm_bf16(g1, s)) != hipSuccess) return e;
-    GemmArgs g2{n, H, H, h1, H, 1, f->wb + o.w2, 1, H, nullptr, 0, h2, H, f->params + o.b2, 1};
+    GemmArgs g2{n, H, H, h1, H, 1, wq + o.w2, 1, H, nullptr, 0, h2, H, pp + o.b2, 1};
     if ((e = gw::flow::gemm_bf16(g2, s)) != hipSuccess) return e;
-    GemmArgs g3{n, 2 * D, H, h2, H, 1, f->wb + o.w3, 1, H, f->out_f, 2 * D, nullptr, 0, f->params + o.b3, 0};
+    GemmArgs g3{n, 2 * D, H, h2, H, 1, wq + o.w3, 1, H, f->out_f, 2 * D, nullptr, 0, pp + o.b3, 0};
     return gw::flow::gemm_bf16(g3, s);
 }
 
@@ -563,16 +761,6 @@ hipError_t forward_pass(gw_flow *f, int n, const double *z, hipStream_t s)
 
 // Gradient of the mean negative log density of rows x[0, n) with respect to
 // every parameter (into f->grads); the mean loss goes to loss_out (device).
-// Column sums of m [n][cols] (leading dimension ld) into out [cols].
-hipError_t column_sum(gw_flow *f, int n, int cols, int ld, const float *m, float *out, hipStream_t s)
-{
-    hipLaunchKernelGGL(gw::flow::column_partial_kernel, dim3(blocks_for(cols), gw::flow::kColSlices), dim3(256), 0, s,
-                       n, cols, ld, m, f->colpart);
-    GW_TRY(hipGetLastError());
-    hipLaunchKernelGGL(gw::flow::column_finish_kernel, dim3(blocks_for(cols)), dim3(256), 0, s, cols, f->colpart, out);
-    return hipGetLastError();
-}
-
 hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipStream_t s)
 {
     const int D = f->dim, H = f->hidden, L = f->layers;
@@ -589,9 +777,18 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
     hipLaunchKernelGGL(gw::flow::grad_init_kernel, dim3(blocks_for((int64_t)n * D)), dim3(256), 0, s, n, D,
                        boundary(f, 0), f->g);
     GW_TRY(hipGetLastError());
-    // the inverse pass applied couplings L-1 .. 0; go back through 0 .. L-1
+    // the inverse pass applied couplings L-1 .. 0; go back through 0 .. L-1.
+    // Every gradient of layer l is left as partial sums (split-K slices of the
+    // weights, row-block sums of the biases) and summed by one kernel at the end.
+    const int rb64 = (n + 63) / 64;
     for (int l = 0; l < L; ++l) {
         const LayerOff o = layer_off(f, l);
+        const uint16_t *wq = f->wb + o.q;
+        float *wp = f->wpart + l * f->w_layer;
+        double *bp = f->bpart + l * f->b_layer;
+        float *wp1 = wp, *wp2 = wp + (int64_t)gw::flow::kMaxSplit * H * D,
+              *wp3 = wp + (int64_t)gw::flow::kMaxSplit * (H * D + H * H);
+        double *bp1 = bp, *bp2 = bp + (int64_t)f->rb64_cap * H, *bp3 = bp + 2 * (int64_t)f->rb64_cap * H;
         const uint16_t *xm = f->xm_b + (int64_t)l * f->cap * kInPad;
         const uint16_t *h1 = f->h1_b + (int64_t)l * f->cap * H;
         const uint16_t *h2 = f->h2_b + (int64_t)l * f->cap * H;
@@ -599,46 +796,45 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
                            f->cond[l], f->g, boundary(f, l), f->s_store + (int64_t)l * f->cap * D, f->dout_b,
                            f->dout_f, f->gy);
         GW_TRY(hipGetLastError());
-        // layer 3: dW3 = dout^T h2, db3 = colsum(dout), dh2 = dout W3
-        GemmArgs gw3{2 * D, H, n, f->dout_b, 1, kOutPad, h2, H, 1, f->grads + o.w3, H, nullptr, 0, nullptr, 0,
-                     split, f->splitk};
+        hipLaunchKernelGGL(gw::flow::column_part_kernel, dim3(rb64), dim3(256), 0, s, n, 2 * D, kOutPad, f->dout_f, bp3);
+        GW_TRY(hipGetLastError());
+        // layer 3: dW3 = dout^T h2, db3 = colsum(dout), dh2 = dout W3,
+        // dpre2 = dh2 (h2 > 0) with db2 = colsum(dpre2) in the same pass
+        GemmArgs gw3{2 * D, H, n, f->dout_b, 1, kOutPad, h2, H, 1, nullptr, 0, nullptr, 0, nullptr, 0, split, wp3, 1};
         GW_TRY(gw::flow::gemm_bf16(gw3, s));
-        GW_TRY(column_sum(f, n, 2 * D, kOutPad, f->dout_f, f->grads + o.b3, s));
-        GemmArgs gh2{n, H, 2 * D, f->dout_b, kOutPad, 1, f->wb + o.w3, H, 1, f->dh, H, nullptr, 0, nullptr, 0};
+        GemmArgs gh2{n, H, 2 * D, f->dout_b, kOutPad, 1, wq + o.w3, H, 1, f->dh, H, f->dpre_b, H, nullptr, 0};
+        gh2.relu_of = h2;
+        gh2.ld_relu = H;
+        gh2.col_part = bp2;
         GW_TRY(gw::flow::gemm_bf16(gh2, s));
-        hipLaunchKernelGGL(gw::flow::relu_backward_kernel, dim3(blocks_for((int64_t)n * H)), dim3(256), 0, s,
-                           (int64_t)n * H, f->dh, h2, f->dpre_b);
-        GW_TRY(hipGetLastError());
-        // layer 2: dW2 = dpre2^T h1, db2 = colsum(dpre2), dh1 = dpre2 W2
-        GemmArgs gw2{H, H, n, f->dpre_b, 1, H, h1, H, 1, f->grads + o.w2, H, nullptr, 0, nullptr, 0,
-                     split, f->splitk};
+        // layer 2: dW2 = dpre2^T h1, dh1 = dpre2 W2, dpre1 = dh1 (h1 > 0), db1 = colsum(dpre1)
+        GemmArgs gw2{H, H, n, f->dpre_b, 1, H, h1, H, 1, nullptr, 0, nullptr, 0, nullptr, 0, split, wp2, 1};
         GW_TRY(gw::flow::gemm_bf16(gw2, s));
-        GW_TRY(column_sum(f, n, H, H, f->dh, f->grads + o.b2, s));
-        GemmArgs gh1{n, H, H, f->dpre_b, H, 1, f->wb + o.w2, H, 1, f->dh, H, nullptr, 0, nullptr, 0};
-        // dh1 overwrites dh only after the two reads above have been enqueued before it (stream order)
+        GemmArgs gh1{n, H, H, f->dpre_b, H, 1, wq + o.w2, H, 1, f->dh, H, f->dpre2_b, H, nullptr, 0};
+        gh1.relu_of = h1;
+        gh1.ld_relu = H;
+        gh1.col_part = bp1;
         GW_TRY(gw::flow::gemm_bf16(gh1, s));
-        hipLaunchKernelGGL(gw::flow::relu_backward_kernel, dim3(blocks_for((int64_t)n * H)), dim3(256), 0, s,
-                           (int64_t)n * H, f->dh, h1, f->dpre_b);
-        GW_TRY(hipGetLastError());
-        // layer 1: dW1 = dpre1^T xm, db1 = colsum(dpre1), dxm = dpre1 W1
-        GemmArgs gw1{H, D, n, f->dpre_b, 1, H, xm, kInPad, 1, f->grads + o.w1, D, nullptr, 0, nullptr, 0,
-                     split, f->splitk};
+        // layer 1: dW1 = dpre1^T xm, dxm = dpre1 W1
+        GemmArgs gw1{H, D, n, f->dpre2_b, 1, H, xm, kInPad, 1, nullptr, 0, nullptr, 0, nullptr, 0, split, wp1, 1};
         GW_TRY(gw::flow::gemm_bf16(gw1, s));
-        GW_TRY(column_sum(f, n, H, H, f->dh, f->grads + o.b1, s));
-        GemmArgs gx{n, D, H, f->dpre_b, H, 1, f->wb + o.w1, D, 1, f->dxm, D, nullptr, 0, nullptr, 0};
+        GemmArgs gx{n, D, H, f->dpre2_b, H, 1, wq + o.w1, D, 1, f->dxm, D, nullptr, 0, nullptr, 0};
         GW_TRY(gw::flow::gemm_bf16(gx, s));
         hipLaunchKernelGGL(gw::flow::add_input_grad_kernel, dim3(blocks_for((int64_t)n * D)), dim3(256), 0, s, n, D,
                            f->cond[l], f->dxm, f->gy);
         GW_TRY(hipGetLastError());
         std::swap(f->g, f->gy);      // d loss / d(boundary l + 1)
     }
-    return hipSuccess;
+    gw::flow::GradParts parts{D, H, split, rb64, f->rb64_cap, f->per_layer, f->n_params, f->w_layer, f->b_layer,
+                              f->wpart, f->bpart};
+    hipLaunchKernelGGL(gw::flow::grad_finish_kernel, dim3(blocks_for(f->n_params)), dim3(256), 0, s, parts, f->grads);
+    return hipGetLastError();
 }
 
 hipError_t refresh_bf16(gw_flow *f, hipStream_t s)
 {
     hipLaunchKernelGGL(gw::flow::to_bf16_kernel, dim3(blocks_for(f->n_params)), dim3(256), 0, s, f->n_params,
-                       f->params, f->wb);
+                       f->per_layer, f->wb_stride, f->params, f->wb);
     return hipGetLastError();
 }
 
@@ -675,8 +871,9 @@ int gw_flow_create(gw_flow **out, int device, int dim, int n_layers, int hidden,
     const int64_t D = dim, H = hidden;
     f->per_layer = H * D + H + H * H + H + 2 * D * H + 2 * D;
     f->n_params = f->per_layer * n_layers;
+    f->wb_stride = (f->per_layer + 7) / 8 * 8;
     if (alloc(&f->params, f->n_params) || alloc(&f->grads, f->n_params) || alloc(&f->adam_m, f->n_params) ||
-        alloc(&f->adam_v, f->n_params) || alloc(&f->wb, f->n_params) || alloc(&f->mu, dim) ||
+        alloc(&f->adam_v, f->n_params) || alloc(&f->wb, f->wb_stride * n_layers) || alloc(&f->mu, dim) ||
         alloc(&f->log_sigma, dim)) {
         gw_flow_destroy(f);
         return fail(GW_ENOMEM, "flow parameters");

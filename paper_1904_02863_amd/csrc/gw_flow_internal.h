@@ -32,6 +32,16 @@ struct GemmArgs {
     // them in slice order and applies bias, ReLU and the outputs
     int split = 1;
     float *partial = nullptr;
+    // defer: the slices go to partial (also with split 1) and are left there
+    // for the caller to sum (no second kernel)
+    int defer = 0;
+    // backward ReLU (split 1): outputs are kept where relu_of(i, j), a BF16
+    // activation [M][ld_relu], is > 0, and zeroed elsewhere
+    const uint16_t *relu_of = nullptr;
+    int64_t ld_relu = 0;
+    // (split 1) column sums of the final FP32 outputs over each 64-row block
+    // of the tile grid, in FP64 and a fixed order: col_part [ceil(M/64)][N]
+    double *col_part = nullptr;
 };
 
 constexpr int kMaxSplit = 16;

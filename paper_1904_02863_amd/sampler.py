@@ -235,11 +235,13 @@ def init_flow_params(dim: int, hidden: int, n_layers: int, seed: int, scale_last
 
 
 def train_flow(samples, n_layers: int = 8, hidden: int = 256, steps: int = 2000, batch: int = 4096,
-               lr: float = 1e-3, seed: int = 0, device: int = 0, log_every: int = 0):
+               lr: float = 1e-3, seed: int = 0, device: int = 0, log_every: int = 0, lr_final: float | None = None):
     """Fit a flow to samples [n, dim] (device tensor or host array) by maximum
     likelihood: Adam on minibatches drawn with replacement on the GPU
     (gw_gather_rows), after an affine standardisation by the samples' mean and
-    standard deviation (gw_mcmc_moments).  Returns (flow, loss history, seconds)."""
+    standard deviation (gw_mcmc_moments).  The step size is lr throughout, or
+    with lr_final given falls from lr to lr_final on a half cosine over the
+    steps.  Returns (flow, loss history, seconds)."""
     import torch
     dev = torch.device("cuda", device)
     if isinstance(samples, torch.Tensor):
@@ -259,8 +261,11 @@ def train_flow(samples, n_layers: int = 8, hidden: int = 256, steps: int = 2000,
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
+        rate = lr
+        if lr_final is not None and steps > 1:
+            rate = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * s / (steps - 1)))
         gather_rows(data, batch, seed, STREAM_MINIBATCH, s, out=mb)
-        flow.train_step(mb, lr, loss_out=loss_t)
+        flow.train_step(mb, rate, loss_out=loss_t)
         if log_every and (s % log_every == 0 or s == steps - 1):
             history.append((s, float(loss_t.item())))
     torch.cuda.synchronize()
@@ -319,7 +324,7 @@ def run_flow_mh(problem: Problem, state: ChainState, flow: Flow, n_steps: int, s
 def compare_samplers(problem: Problem, p_inj: np.ndarray, ws: Workspace, n_chains: int = 4096, burn: int = 4000,
                      steps: int = 1024, flow_steps: int = 3000, hidden: int = 256, n_layers: int = 8,
                      seed: int = 20190408, track: int = 256, collect_every: int = 20, rw_every: int = 8,
-                     lr: float = 1e-3):
+                     lr: float = 1e-3, lr_final: float | None = None):
     """The learned proposal against the plain method on one event: n_chains
     random-walk chains start in a tight ball around the injection (spin
     coordinates that the likelihood ignores start from their prior), burn in
@@ -346,7 +351,7 @@ def compare_samplers(problem: Problem, p_inj: np.ndarray, ws: Workspace, n_chain
                                                             record_track=track, collect_every=collect_every)
     n_train = int(collected.shape[0])
     flow, hist, t_train = train_flow(collected, n_layers=n_layers, hidden=hidden, steps=flow_steps, batch=4096,
-                                     lr=lr, seed=seed + 2, log_every=max(1, flow_steps // 10))
+                                     lr=lr, seed=seed + 2, log_every=max(1, flow_steps // 10), lr_final=lr_final)
     fstate = ChainState(state.x.clone(), state.lnp.clone(), torch.zeros_like(state.lnp), state.step)
     run_flow_mh(problem, fstate, flow, 64, seed + 3, chol, ws, rw_every=rw_every)
     rec_fl, acc_fl, t_fl, rw_frac = run_flow_mh(problem, fstate, flow, steps, seed + 3, chol, ws, rw_every=rw_every,

@@ -206,14 +206,19 @@ def test_flow_matches_oracle(gw):
     np.testing.assert_allclose(lq2.cpu().numpy(), lq, atol=1e-9)
 
 
-def test_flow_gradients_match_oracle(gw):
+@pytest.mark.parametrize("n", [4096, 1000])
+def test_flow_gradients_match_oracle(gw, n):
     """Every weight and bias gradient of the 8-layer 11 -> 256 -> 256 -> 22
     flow against the float64 oracle's autograd gradient, element by element,
     within the BF16 rounding bound (grouped per layer and per matrix or bias
-    vector); the loss likewise."""
+    vector); the loss likewise.  Batches of 4096 rows (16 split-K slices of
+    256) and 1000 (3 slices of 352, two K chunks each, ragged row blocks).
+    Smaller batches are left to the next test: there one row's share of a
+    gradient (1/n) reaches the bound, and a ReLU whose pre-activation sits at
+    zero can fall on either side under different roundings."""
     from oracle.flow import parameter_groups, rounding_spread, rounding_tolerance
     f, args = _flow_pair(gw, scale_last=0.5)
-    x = np.random.default_rng(6).standard_normal((4096, 11)) * 1.3 + 0.2
+    x = np.random.default_rng(6).standard_normal((n, 11)) * 1.3 + 0.2
     g, loss = f.gradients(torch.from_numpy(x).to(DEV))
     g = g.cpu().numpy().astype(np.float64)
 
@@ -233,6 +238,26 @@ def test_flow_gradients_match_oracle(gw):
     for l, m in enumerate(args[1]):
         off = np.array([(int(m) >> i) & 1 == 0 for i in range(11)])
         assert (g[where[f"l{l}.w1"]].reshape(256, 11)[:, off] == 0).all()
+
+
+def test_flow_gradients_of_repeated_rows(gw):
+    """The loss is a mean over rows, so a batch and the same batch twice have
+    the same gradient.  300 rows (one K slice, ragged row blocks of 64 and
+    256) against 600 (two slices): every element within FP32 rounding of
+    sums of that length."""
+    from oracle.flow import parameter_groups
+    f, _ = _flow_pair(gw, scale_last=0.5)
+    x = np.random.default_rng(8).standard_normal((300, 11)) * 1.3 + 0.2
+    g1, l1 = f.gradients(torch.from_numpy(x).to(DEV))
+    g2, l2 = f.gradients(torch.from_numpy(np.vstack([x, x])).to(DEV))
+    g1, g2 = g1.cpu().numpy().astype(np.float64), g2.cpu().numpy().astype(np.float64)
+    assert float(l1.item()) == pytest.approx(float(l2.item()), rel=1e-12)
+    for name, sl in parameter_groups(11, 256, 8):
+        a, b = g1[sl], g2[sl]
+        bound = 1e-5 * np.abs(a).max() + 1e-6 * np.abs(a)
+        err = np.abs(a - b)
+        assert (err <= bound).all(), f"{name}: worst {err.max():.3e} (scale {np.abs(a).max():.3e})"
+    assert np.abs(g1).max() > 0
 
 
 def test_flow_learns_a_gaussian(gw):
