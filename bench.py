@@ -356,10 +356,12 @@ def flow_comparison(args, spins: bool):
     couplings of 11 -> 256 -> 256 -> 22."""
     from paper_1904_02863_amd import sampler
     prob, p_inj, ws = flow_problem(spins, args.precision)
-    burn = args.mcmc_burn if args.mcmc_burn is not None else (40000 if spins else 4000)
+    burn = args.mcmc_burn if args.mcmc_burn is not None else (120000 if spins else 4000)
     t0 = time.perf_counter()
     res = sampler.compare_samplers(prob, p_inj, ws, n_chains=4096, burn=burn, steps=args.mcmc_steps,
-                                   flow_steps=args.flow_steps, lr=args.flow_lr, lr_final=args.flow_lr_final)
+                                   log=lambda m: print(m, file=sys.stderr, flush=True),
+                                   flow_steps=args.flow_steps, lr=args.flow_lr,
+                                   lr_final=args.flow_lr_final if args.flow_lr_final > 0 else None)
     res["wall_seconds"] = time.perf_counter() - t0
     res["burn_in_steps"] = burn
     res["spins"] = spins
@@ -390,6 +392,47 @@ def bench_flow(args):
     }
     result.update(res)
     print(json.dumps(result), flush=True)
+
+
+MIXED_REPORT = "profiles/mixed_precision_bbh-3det-128s.md"
+
+
+def mixed_comparison(args, step_args, fp64_out, fp64_s: float) -> dict:
+    """The precision extension on the same batch, after the timed FP64 steps:
+    the mixed path timed the same way (its own workspace, first call tuning
+    its plan), its largest |lnL difference| from the FP64 values of the batch,
+    and the per-injection figures of the committed 1024-injection report."""
+    import torch
+
+    import paper_1904_02863_amd as gw
+    g, w, data, psd, theta = step_args
+    ws = gw.Workspace(0)
+    out = torch.empty_like(fp64_out)
+
+    def step():
+        gw.lnl_batch(g, w.tensors, w.vertices, data, psd, theta, out=out, workspace=ws, precision="mixed")
+
+    step()
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    res = {"value": w.n_samples / t, "unit": "lnL evals/s", "ms_per_step": t * 1e3, "speedup_vs_fp64": fp64_s / t,
+           "plan": ws.lnl_plan(g.n_bins, w.n_det, w.n_samples, "mixed"),
+           "max_abs_dlnl_vs_fp64_this_batch": float((out - fp64_out).abs().max().item()), "tolerance": 1e-3}
+    path = os.path.join(ROOT, MIXED_REPORT)
+    if os.path.exists(path):
+        text = open(path).read()
+        for key in ("max_abs_dlnl_vs_oracle", "max_rel_dh_vs_oracle", "injections"):
+            m = re.search(rf"{key}:\s*([0-9.eE+-]+)", text)
+            if m:
+                res[f"report_{key}"] = float(m.group(1))
+        res["report"] = MIXED_REPORT
+    return res
 
 
 def flow_summary(res: dict) -> dict:
@@ -699,12 +742,12 @@ def main():
                     choices=["bbh-3det-128s", "bbh-1det-4s", "bns-15hz-512s", "bns-ragged", "flow-mcmc",
                              "population", "waveform", "bns-relbin"])
     ap.add_argument("--mcmc-burn", type=int, default=None,
-                    help="flow-mcmc: random-walk burn-in steps (default 40000 with aligned spins, 4000 without)")
+                    help="flow-mcmc: random-walk burn-in steps (default 120000 with aligned spins, 4000 without)")
     ap.add_argument("--mcmc-steps", type=int, default=1024, help="flow-mcmc: production steps of each sampler")
-    ap.add_argument("--flow-steps", type=int, default=3000, help="flow-mcmc: Adam steps")
-    ap.add_argument("--flow-lr", type=float, default=1e-3, help="flow-mcmc: Adam step size")
-    ap.add_argument("--flow-lr-final", type=float, default=None,
-                    help="flow-mcmc: end the step size here on a half cosine (default: constant)")
+    ap.add_argument("--flow-steps", type=int, default=1500, help="flow-mcmc: Adam steps")
+    ap.add_argument("--flow-lr", type=float, default=2e-3, help="flow-mcmc: Adam step size")
+    ap.add_argument("--flow-lr-final", type=float, default=2e-5,
+                    help="flow-mcmc: the step size falls to this on a half cosine (<= 0: constant)")
     ap.add_argument("--samples", type=int, default=None)
     ap.add_argument("--plan", default=None, metavar="TILE,ROUNDS",
                     help="run this likelihood plan (LDS tile bins, work-queue rounds) instead of the autotuned one")
@@ -834,6 +877,9 @@ def main():
         # the kernel skips the bins above the batch's largest cut-off, so a
         # tally over every bin would overstate the rate
         result["roofline"] = None
+    if headline and args.precision == "fp64":
+        result["mixed_precision"] = mixed_comparison(args, step_args=(g, w, data, psd, theta), fp64_out=out,
+                                                     fp64_s=elapsed / args.steps)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, data, args.cpu_seconds, args.flags)
     if args.workload == "bbh-3det-128s" and not args.no_flow:

@@ -30,13 +30,8 @@ namespace gw {
 namespace flow {
 
 // ---------------------------------------------------------------- BF16 helpers
-__device__ __forceinline__ uint16_t f32_to_bf16(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);   // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);                                               // round to nearest even
-    return (uint16_t)(u >> 16);
-}
+// FP32 -> BF16, rounding to nearest even (one v_cvt_pk_bf16_f32 on gfx950).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
@@ -203,28 +198,44 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int vec_a, i
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < 2; ++b) {
+            const int i0 = row0 + wr + 16 * a + rq;     // this lane's 4 consecutive rows
+            const int j = col0 + wc + 16 * b + lc;
+            if (j >= g.N) continue;
+            float v[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = row0 + wr + 16 * a + rq + r;
-                const int j = col0 + wc + 16 * b + lc;
-                if (i < g.M && j < g.N) {
-                    float v = acc[a][b][r];
-                    if (to_partial) {
-                        g.partial[((int64_t)blockIdx.z * g.M + i) * g.N + j] = v;
-                        continue;
-                    }
-                    if (g.bias) v += bias[b];
-                    if (g.relu) v = v > 0.f ? v : 0.f;
-                    if (g.relu_of) {
-                        const uint16_t h = g.relu_of[(int64_t)i * g.ld_relu + j];
-                        v = ((h & 0x7fffu) != 0 && !(h & 0x8000u)) ? v : 0.f;
-                    }
-                    if (g.C) g.C[(int64_t)i * g.ldc + j] = v;
-                    if (g.Cb) g.Cb[(int64_t)i * g.ldcb + j] = f32_to_bf16(v);
-                    csum[b] += (double)v;
+                const int i = i0 + r;
+                v[r] = acc[a][b][r];
+                if (i >= g.M) continue;
+                if (to_partial) {
+                    g.partial[((int64_t)blockIdx.z * g.M + i) * g.N + j] = v[r];
+                    continue;
+                }
+                if (g.bias) v[r] += bias[b];
+                if (g.relu) v[r] = v[r] > 0.f ? v[r] : 0.f;
+                if (g.relu_of) {
+                    const uint16_t h = g.relu_of[(int64_t)i * g.ld_relu + j];
+                    v[r] = ((h & 0x7fffu) != 0 && !(h & 0x8000u)) ? v[r] : 0.f;
+                }
+                if (g.C) g.C[(int64_t)i * g.ldc + j] = v[r];
+                if (g.Cb) g.Cb[(int64_t)i * g.ldcb + j] = f32_to_bf16(v[r]);
+                csum[b] += (double)v[r];
+            }
+            if (g.CbT && !to_partial) {
+                // transposed BF16 copy: the 4 rows are consecutive in column j's row of CbT
+                uint16_t *t = g.CbT + (int64_t)j * g.ldcbT + i0;
+                if (i0 + 3 < g.M) {
+                    const uint32_t lo = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
+                    const uint32_t hi = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
+                    *reinterpret_cast<uint2 *>(t) = make_uint2(lo, hi);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (i0 + r < g.M) t[r] = f32_to_bf16(v[r]);
                 }
             }
+        }
     if (g.col_part && !to_partial) {
         // the block's 64 rows: each lane's 8, then the 4 lane groups and the
         // two row halves, in that fixed order
@@ -269,7 +280,9 @@ hipError_t gemm_bf16(const GemmArgs &g, hipStream_t stream)
 {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
     if (g.split < 1 || g.split > kMaxSplit || ((g.split > 1 || g.defer) && !g.partial)) return hipErrorInvalidValue;
-    if ((g.col_part || g.relu_of) && (g.split > 1 || g.defer)) return hipErrorInvalidValue;
+    if ((g.col_part || g.relu_of || g.CbT) && (g.split > 1 || g.defer)) return hipErrorInvalidValue;
+    // the transposed copy is written 4 rows (8 bytes) at a time
+    if (g.CbT && (g.ldcbT % 4 != 0 || (reinterpret_cast<uintptr_t>(g.CbT) & 7u) != 0)) return hipErrorInvalidValue;
     // A is read along k when its k stride is 1, else along i (stride 1 required then)
     const bool a_kc = g.sa_k == 1, b_kc = g.sb_k == 1;
     if ((!a_kc && g.sa_i != 1) || (!b_kc && g.sb_j != 1)) return hipErrorInvalidValue;
@@ -297,14 +310,18 @@ hipError_t gemm_bf16(const GemmArgs &g, hipStream_t stream)
 
 // MLP input: the conditioning dimensions of a, the others zero, as BF16 in a
 // row of kInPad entries (the GEMM's K is dim; the padding stays zero).
+// With xmT given, also the transposed copy xmT[i ldT + b] (for the weight gradients).
 __global__ __launch_bounds__(256) void mask_input_kernel(int n, int dim, unsigned cond, const double *__restrict__ a,
-                                                         uint16_t *__restrict__ xm)
+                                                         uint16_t *__restrict__ xm, uint16_t *__restrict__ xmT,
+                                                         int64_t ldT)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
     for (int i = 0; i < kInPad; ++i) {
         const bool on = i < dim && ((cond >> i) & 1u);
-        xm[(int64_t)b * kInPad + i] = on ? f32_to_bf16((float)a[(int64_t)b * dim + i]) : (uint16_t)0;
+        const uint16_t v = on ? f32_to_bf16((float)a[(int64_t)b * dim + i]) : (uint16_t)0;
+        xm[(int64_t)b * kInPad + i] = v;
+        if (xmT) xmT[i * ldT + b] = v;
     }
 }
 
@@ -384,15 +401,17 @@ __global__ __launch_bounds__(256) void grad_init_kernel(int n, int dim, const do
 
 // Backward of one inverse coupling x = (y - t) e^{-s} (T dims), x_C = y_C, with
 // the loss term sum_T s / n.  g = d loss / d x.  Writes d loss / d(r, t) as
-// BF16 and FP32 rows of kOutPad, and the direct part of d loss / d y (the MLP's
-// contribution to the conditioning dimensions is added later).
+// BF16 and FP32 rows of kOutPad and as BF16 columns (doutT[c ldT + b]), and
+// the direct part of d loss / d y (the MLP's contribution to the conditioning
+// dimensions is added later).
 __global__ __launch_bounds__(256) void coupling_inv_backward_kernel(int n, int dim, unsigned cond,
                                                                     const double *__restrict__ g,
                                                                     const double *__restrict__ x,
                                                                     const double *__restrict__ s,
                                                                     uint16_t *__restrict__ dout_b,
                                                                     float *__restrict__ dout_f,
-                                                                    double *__restrict__ gy)
+                                                                    double *__restrict__ gy,
+                                                                    uint16_t *__restrict__ doutT, int64_t ldT)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
@@ -400,6 +419,7 @@ __global__ __launch_bounds__(256) void coupling_inv_backward_kernel(int n, int d
     for (int i = 0; i < kOutPad; ++i) {
         dout_b[(int64_t)b * kOutPad + i] = 0;
         dout_f[(int64_t)b * kOutPad + i] = 0.f;
+        doutT[i * ldT + b] = 0;
     }
     for (int i = 0; i < dim; ++i) {
         const int64_t o = (int64_t)b * dim + i;
@@ -415,6 +435,8 @@ __global__ __launch_bounds__(256) void coupling_inv_backward_kernel(int n, int d
             dout_f[(int64_t)b * kOutPad + dim + i] = (float)dt;
             dout_b[(int64_t)b * kOutPad + i] = f32_to_bf16((float)dr);
             dout_b[(int64_t)b * kOutPad + dim + i] = f32_to_bf16((float)dt);
+            doutT[i * ldT + b] = f32_to_bf16((float)dr);
+            doutT[(dim + i) * ldT + b] = f32_to_bf16((float)dt);
         }
     }
 }
@@ -519,14 +541,33 @@ __global__ __launch_bounds__(256) void adam_kernel(int64_t count, float *__restr
 }
 
 // BF16 copies of the weight matrices (FP32 master -> BF16): parameter i of
-// layer i / per_layer goes to dst[layer * dst_stride + i % per_layer].
+// layer i / per_layer goes to dst[layer * dst_stride + i % per_layer], and
+// the weights also transposed into dstT (layer stride t_stride): W1^T [D][H],
+// W2^T [H][H], W3^T [H][kOutPad] (rows padded), the backward pass's operands.
 __global__ __launch_bounds__(256) void to_bf16_kernel(int64_t count, int64_t per_layer, int64_t dst_stride,
-                                                      const float *__restrict__ src, uint16_t *__restrict__ dst)
+                                                      int D, int H, int64_t t_stride, const float *__restrict__ src,
+                                                      uint16_t *__restrict__ dst, uint16_t *__restrict__ dstT)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const int64_t l = i / per_layer;
-    dst[l * dst_stride + (i - l * per_layer)] = f32_to_bf16(src[i]);
+    int64_t q = i - l * per_layer;
+    const uint16_t v = f32_to_bf16(src[i]);
+    dst[l * dst_stride + q] = v;
+    uint16_t *t = dstT + l * t_stride;
+    const int64_t s1 = (int64_t)H * D, s2 = (int64_t)H * H, s3 = 2 * (int64_t)D * H;
+    if (q < s1) {                                   // W1 [H][D] -> W1^T [D][H]
+        t[(q % D) * H + q / D] = v;
+        return;
+    }
+    q -= s1 + H;
+    if (q < 0) return;                              // b1
+    if (q < s2) {                                   // W2 [H][H] -> W2^T
+        t[s1 + (q % H) * H + q / H] = v;
+        return;
+    }
+    q -= s2 + H;
+    if (q >= 0 && q < s3) t[s1 + s2 + (q % H) * kOutPad + q / H] = v;   // W3 [2D][H] -> W3^T [H][kOutPad]
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(int64_t n, double *__restrict__ p)
@@ -562,6 +603,8 @@ struct gw_flow {
     int64_t wb_stride = 0;                // layer stride of the BF16 copy (per_layer rounded up to 8)
     float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
     uint16_t *wb = nullptr;               // BF16 copy of params
+    uint16_t *wbT = nullptr;              // BF16 transposed weights per layer (to_bf16_kernel)
+    int64_t wbT_stride = 0;               // D H + H H + H kOutPad
     double *mu = nullptr, *log_sigma = nullptr;
     int64_t adam_t = 0;
     // batch scratch, capacity `cap` rows
@@ -578,6 +621,12 @@ struct gw_flow {
     uint16_t *dpre_b = nullptr;           // [cap][hidden]
     float *dxm = nullptr;                 // [cap][dim]
     uint16_t *dpre2_b = nullptr;          // [cap][hidden], the other layer's BF16 pre-activation gradient
+    // transposed BF16 copies for the weight gradients (row length ldT, a
+    // multiple of 64 >= cap): activations [layers][hidden][ldT], inputs
+    // [layers][kInPad][ldT], output gradients [kOutPad][ldT], the two
+    // pre-activation gradients [hidden][ldT]
+    int64_t ldT = 0;
+    uint16_t *h1T = nullptr, *h2T = nullptr, *xmT = nullptr, *doutT = nullptr, *dpreT = nullptr, *dpre2T = nullptr;
     // partial sums of the gradients (summed by grad_finish_kernel): per layer,
     // split-K slices of the three weight matrices (FP32, w_layer floats) and
     // row-block sums of the three biases (FP64, b_layer doubles)
@@ -645,11 +694,12 @@ hipError_t alloc(T **p, int64_t count)
 void free_batch(gw_flow *f)
 {
     void *ptrs[] = {f->bound, f->s_store, f->sum_s, f->loss, f->g, f->gy, f->xm_b, f->h1_b, f->h2_b,
-                    f->out_f, f->dout_f, f->dout_b, f->dh, f->dpre_b, f->dpre2_b, f->dxm, f->wpart, f->bpart};
+                    f->out_f, f->dout_f, f->dout_b, f->dh, f->dpre_b, f->dpre2_b, f->dxm, f->wpart, f->bpart,
+                    f->h1T, f->h2T, f->xmT, f->doutT, f->dpreT, f->dpre2T};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     f->bound = f->s_store = f->sum_s = f->loss = f->g = f->gy = f->bpart = nullptr;
-    f->dpre2_b = nullptr;
+    f->dpre2_b = f->h1T = f->h2T = f->xmT = f->doutT = f->dpreT = f->dpre2T = nullptr;
     f->xm_b = f->h1_b = f->h2_b = f->dout_b = f->dpre_b = nullptr;
     f->out_f = f->dout_f = f->dh = f->dxm = f->wpart = nullptr;
     f->cap = 0;
@@ -666,16 +716,20 @@ int ensure_batch(gw_flow *f, int64_t n)
     const int rb64 = (int)((c + 63) / 64);
     const int64_t w_layer = (int64_t)gw::flow::kMaxSplit * (H * D + H * H + 2 * D * H);
     const int64_t b_layer = (int64_t)rb64 * (2 * H + 2 * D);
+    const int64_t ldT = (c + 63) / 64 * 64;
     if (alloc(&f->bound, (L + 2) * c * D) || alloc(&f->s_store, L * c * D) || alloc(&f->sum_s, c) ||
         alloc(&f->loss, c) || alloc(&f->g, c * D) || alloc(&f->gy, c * D) || alloc(&f->xm_b, L * c * kInPad) ||
         alloc(&f->h1_b, L * c * H) || alloc(&f->h2_b, L * c * H) || alloc(&f->out_f, c * 2 * D) ||
         alloc(&f->dout_f, c * kOutPad) || alloc(&f->dout_b, c * kOutPad) || alloc(&f->dh, c * H) ||
         alloc(&f->dpre_b, c * H) || alloc(&f->dxm, c * D) ||
-        alloc(&f->dpre2_b, c * H) || alloc(&f->wpart, L * w_layer) || alloc(&f->bpart, L * b_layer)) {
+        alloc(&f->dpre2_b, c * H) || alloc(&f->wpart, L * w_layer) || alloc(&f->bpart, L * b_layer) ||
+        alloc(&f->h1T, L * H * ldT) || alloc(&f->h2T, L * H * ldT) || alloc(&f->xmT, L * kInPad * ldT) ||
+        alloc(&f->doutT, kOutPad * ldT) || alloc(&f->dpreT, H * ldT) || alloc(&f->dpre2T, H * ldT)) {
         free_batch(f);
         return fail(GW_ENOMEM, "flow batch buffers");
     }
     f->cap = c;
+    f->ldT = ldT;
     f->w_layer = w_layer;
     f->b_layer = b_layer;
     f->rb64_cap = rb64;
@@ -685,22 +739,30 @@ int ensure_batch(gw_flow *f, int64_t n)
 double *boundary(gw_flow *f, int i) { return f->bound + (int64_t)i * f->cap * f->dim; }
 
 // The MLP of layer l on the masked input of rows [0, n): writes out_f (r, t)
-// and keeps the BF16 activations of layer l for the backward pass.
-hipError_t mlp_forward(gw_flow *f, int l, int n, const double *a, hipStream_t s)
+// and keeps the BF16 activations of layer l for the backward pass (with
+// keep_t also transposed, the weight gradients' operands).
+hipError_t mlp_forward(gw_flow *f, int l, int n, const double *a, bool keep_t, hipStream_t s)
 {
     const int D = f->dim, H = f->hidden;
     const LayerOff o = layer_off(f, l);
     uint16_t *xm = f->xm_b + (int64_t)l * f->cap * kInPad;
     uint16_t *h1 = f->h1_b + (int64_t)l * f->cap * H;
     uint16_t *h2 = f->h2_b + (int64_t)l * f->cap * H;
-    hipLaunchKernelGGL(gw::flow::mask_input_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], a, xm);
+    uint16_t *xmT = keep_t ? f->xmT + (int64_t)l * kInPad * f->ldT : nullptr;
+    hipLaunchKernelGGL(gw::flow::mask_input_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], a, xm,
+                       xmT, f->ldT);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const uint16_t *wq = f->wb + o.q;
     const float *pp = f->params + o.p;
     GemmArgs g1{n, H, D, xm, kInPad, 1, wq + o.w1, 1, D, nullptr, 0, h1, H, pp + o.b1, 1};
-    if ((e = gw::flow::gemm_bf16(g1, s)) != hipSuccess) return e;
     GemmArgs g2{n, H, H, h1, H, 1, wq + o.w2, 1, H, nullptr, 0, h2, H, pp + o.b2, 1};
+    if (keep_t) {
+        g1.CbT = f->h1T + (int64_t)l * H * f->ldT;
+        g2.CbT = f->h2T + (int64_t)l * H * f->ldT;
+        g1.ldcbT = g2.ldcbT = f->ldT;
+    }
+    if ((e = gw::flow::gemm_bf16(g1, s)) != hipSuccess) return e;
     if ((e = gw::flow::gemm_bf16(g2, s)) != hipSuccess) return e;
     GemmArgs g3{n, 2 * D, H, h2, H, 1, wq + o.w3, 1, H, f->out_f, 2 * D, nullptr, 0, pp + o.b3, 0};
     return gw::flow::gemm_bf16(g3, s);
@@ -723,7 +785,7 @@ hipError_t zero(int64_t n, double *p, hipStream_t s)
 // normalised x, then the couplings L-1 .. 0 invert down to boundary 0 = z;
 // sum_s = sum log sigma + sum over layers of sum_T s.  Activations of every
 // layer are kept for the backward pass.
-hipError_t inverse_pass(gw_flow *f, int n, const double *x, hipStream_t s)
+hipError_t inverse_pass(gw_flow *f, int n, const double *x, bool keep_t, hipStream_t s)
 {
     const int D = f->dim, L = f->layers;
     GW_TRY(zero(n, f->sum_s, s));
@@ -732,7 +794,7 @@ hipError_t inverse_pass(gw_flow *f, int n, const double *x, hipStream_t s)
                        boundary(f, L + 1), boundary(f, L), f->sum_s);
     GW_TRY(hipGetLastError());
     for (int l = L - 1; l >= 0; --l) {
-        GW_TRY(mlp_forward(f, l, n, boundary(f, l + 1), s));
+        GW_TRY(mlp_forward(f, l, n, boundary(f, l + 1), keep_t, s));
         hipLaunchKernelGGL(gw::flow::coupling_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], -1,
                            boundary(f, l + 1), f->out_f, boundary(f, l), f->sum_s,
                            f->s_store + (int64_t)l * f->cap * D);
@@ -749,7 +811,7 @@ hipError_t forward_pass(gw_flow *f, int n, const double *z, hipStream_t s)
     GW_TRY(zero(n, f->sum_s, s));
     GW_TRY(hipMemcpyAsync(boundary(f, 0), z, sizeof(double) * (size_t)n * D, hipMemcpyDeviceToDevice, s));
     for (int l = 0; l < L; ++l) {
-        GW_TRY(mlp_forward(f, l, n, boundary(f, l), s));
+        GW_TRY(mlp_forward(f, l, n, boundary(f, l), false, s));
         hipLaunchKernelGGL(gw::flow::coupling_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], 1,
                            boundary(f, l), f->out_f, boundary(f, l + 1), f->sum_s, nullptr);
         GW_TRY(hipGetLastError());
@@ -766,7 +828,7 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
     const int D = f->dim, H = f->hidden, L = f->layers;
     // weight gradients sum over the n rows: split K = n into slices of >= 256 rows
     const int split = std::max(1, std::min(gw::flow::kMaxSplit, n / 256));
-    GW_TRY(inverse_pass(f, n, x, s));
+    GW_TRY(inverse_pass(f, n, x, true, s));
     hipLaunchKernelGGL(gw::flow::base_density_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, boundary(f, 0),
                        f->sum_s, nullptr, f->loss);
     GW_TRY(hipGetLastError());
@@ -782,43 +844,53 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
     // weights, row-block sums of the biases) and summed by one kernel at the end.
     const int rb64 = (n + 63) / 64;
     for (int l = 0; l < L; ++l) {
-        const LayerOff o = layer_off(f, l);
-        const uint16_t *wq = f->wb + o.q;
         float *wp = f->wpart + l * f->w_layer;
         double *bp = f->bpart + l * f->b_layer;
         float *wp1 = wp, *wp2 = wp + (int64_t)gw::flow::kMaxSplit * H * D,
               *wp3 = wp + (int64_t)gw::flow::kMaxSplit * (H * D + H * H);
         double *bp1 = bp, *bp2 = bp + (int64_t)f->rb64_cap * H, *bp3 = bp + 2 * (int64_t)f->rb64_cap * H;
-        const uint16_t *xm = f->xm_b + (int64_t)l * f->cap * kInPad;
         const uint16_t *h1 = f->h1_b + (int64_t)l * f->cap * H;
         const uint16_t *h2 = f->h2_b + (int64_t)l * f->cap * H;
+        const int64_t T = f->ldT;
+        const uint16_t *h1T = f->h1T + (int64_t)l * H * T, *h2T = f->h2T + (int64_t)l * H * T;
+        const uint16_t *xmT = f->xmT + (int64_t)l * kInPad * T;
+        // transposed BF16 weights of the layer: W1^T [D][H], W2^T [H][H], W3^T [H][kOutPad]
+        const uint16_t *wt = f->wbT + (int64_t)l * f->wbT_stride;
+        const int64_t w2t = (int64_t)D * H, w3t = (int64_t)D * H + (int64_t)H * H;
         hipLaunchKernelGGL(gw::flow::coupling_inv_backward_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D,
                            f->cond[l], f->g, boundary(f, l), f->s_store + (int64_t)l * f->cap * D, f->dout_b,
-                           f->dout_f, f->gy);
+                           f->dout_f, f->gy, f->doutT, T);
         GW_TRY(hipGetLastError());
         hipLaunchKernelGGL(gw::flow::column_part_kernel, dim3(rb64), dim3(256), 0, s, n, 2 * D, kOutPad, f->dout_f, bp3);
         GW_TRY(hipGetLastError());
+        // Every operand below is read k-contiguous: the sums over the batch
+        // from the transposed copies (rows of length T), the products with
+        // the weights from the transposed BF16 weights.
         // layer 3: dW3 = dout^T h2, db3 = colsum(dout), dh2 = dout W3,
         // dpre2 = dh2 (h2 > 0) with db2 = colsum(dpre2) in the same pass
-        GemmArgs gw3{2 * D, H, n, f->dout_b, 1, kOutPad, h2, H, 1, nullptr, 0, nullptr, 0, nullptr, 0, split, wp3, 1};
+        GemmArgs gw3{2 * D, H, n, f->doutT, T, 1, h2T, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split, wp3, 1};
         GW_TRY(gw::flow::gemm_bf16(gw3, s));
-        GemmArgs gh2{n, H, 2 * D, f->dout_b, kOutPad, 1, wq + o.w3, H, 1, f->dh, H, f->dpre_b, H, nullptr, 0};
+        GemmArgs gh2{n, H, 2 * D, f->dout_b, kOutPad, 1, wt + w3t, 1, kOutPad, f->dh, H, f->dpre_b, H, nullptr, 0};
         gh2.relu_of = h2;
         gh2.ld_relu = H;
         gh2.col_part = bp2;
+        gh2.CbT = f->dpreT;
+        gh2.ldcbT = T;
         GW_TRY(gw::flow::gemm_bf16(gh2, s));
         // layer 2: dW2 = dpre2^T h1, dh1 = dpre2 W2, dpre1 = dh1 (h1 > 0), db1 = colsum(dpre1)
-        GemmArgs gw2{H, H, n, f->dpre_b, 1, H, h1, H, 1, nullptr, 0, nullptr, 0, nullptr, 0, split, wp2, 1};
+        GemmArgs gw2{H, H, n, f->dpreT, T, 1, h1T, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split, wp2, 1};
         GW_TRY(gw::flow::gemm_bf16(gw2, s));
-        GemmArgs gh1{n, H, H, f->dpre_b, H, 1, wq + o.w2, H, 1, f->dh, H, f->dpre2_b, H, nullptr, 0};
+        GemmArgs gh1{n, H, H, f->dpre_b, H, 1, wt + w2t, 1, H, f->dh, H, f->dpre2_b, H, nullptr, 0};
         gh1.relu_of = h1;
         gh1.ld_relu = H;
         gh1.col_part = bp1;
+        gh1.CbT = f->dpre2T;
+        gh1.ldcbT = T;
         GW_TRY(gw::flow::gemm_bf16(gh1, s));
         // layer 1: dW1 = dpre1^T xm, dxm = dpre1 W1
-        GemmArgs gw1{H, D, n, f->dpre2_b, 1, H, xm, kInPad, 1, nullptr, 0, nullptr, 0, nullptr, 0, split, wp1, 1};
+        GemmArgs gw1{H, D, n, f->dpre2T, T, 1, xmT, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split, wp1, 1};
         GW_TRY(gw::flow::gemm_bf16(gw1, s));
-        GemmArgs gx{n, D, H, f->dpre2_b, H, 1, wq + o.w1, D, 1, f->dxm, D, nullptr, 0, nullptr, 0};
+        GemmArgs gx{n, D, H, f->dpre2_b, H, 1, wt, 1, H, f->dxm, D, nullptr, 0, nullptr, 0};
         GW_TRY(gw::flow::gemm_bf16(gx, s));
         hipLaunchKernelGGL(gw::flow::add_input_grad_kernel, dim3(blocks_for((int64_t)n * D)), dim3(256), 0, s, n, D,
                            f->cond[l], f->dxm, f->gy);
@@ -834,7 +906,7 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
 hipError_t refresh_bf16(gw_flow *f, hipStream_t s)
 {
     hipLaunchKernelGGL(gw::flow::to_bf16_kernel, dim3(blocks_for(f->n_params)), dim3(256), 0, s, f->n_params,
-                       f->per_layer, f->wb_stride, f->params, f->wb);
+                       f->per_layer, f->wb_stride, f->dim, f->hidden, f->wbT_stride, f->params, f->wb, f->wbT);
     return hipGetLastError();
 }
 
@@ -872,11 +944,17 @@ int gw_flow_create(gw_flow **out, int device, int dim, int n_layers, int hidden,
     f->per_layer = H * D + H + H * H + H + 2 * D * H + 2 * D;
     f->n_params = f->per_layer * n_layers;
     f->wb_stride = (f->per_layer + 7) / 8 * 8;
+    f->wbT_stride = (D * H + H * H + H * gw::flow::kOutPad + 7) / 8 * 8;
     if (alloc(&f->params, f->n_params) || alloc(&f->grads, f->n_params) || alloc(&f->adam_m, f->n_params) ||
-        alloc(&f->adam_v, f->n_params) || alloc(&f->wb, f->wb_stride * n_layers) || alloc(&f->mu, dim) ||
-        alloc(&f->log_sigma, dim)) {
+        alloc(&f->adam_v, f->n_params) || alloc(&f->wb, f->wb_stride * n_layers) ||
+        alloc(&f->wbT, f->wbT_stride * n_layers) || alloc(&f->mu, dim) || alloc(&f->log_sigma, dim)) {
         gw_flow_destroy(f);
         return fail(GW_ENOMEM, "flow parameters");
+    }
+    // the padding of W3^T's rows is never written by to_bf16_kernel: zero it once
+    if (hipMemset(f->wbT, 0, sizeof(uint16_t) * (size_t)(f->wbT_stride * n_layers)) != hipSuccess) {
+        gw_flow_destroy(f);
+        return fail(GW_EDEVICE, "flow parameters");
     }
     *out = f;
     return GW_OK;
@@ -888,7 +966,7 @@ int gw_flow_destroy(gw_flow *f)
     DeviceGuard g(f->device);
     (void)hipDeviceSynchronize();
     free_batch(f);
-    void *ptrs[] = {f->params, f->grads, f->adam_m, f->adam_v, f->wb, f->mu, f->log_sigma};
+    void *ptrs[] = {f->params, f->grads, f->adam_m, f->adam_v, f->wb, f->wbT, f->mu, f->log_sigma};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete f;
@@ -951,7 +1029,7 @@ int gw_flow_inverse(gw_flow *f, const double *x, int64_t n, double *z_out, doubl
     if (n == 0) return GW_OK;
     DeviceGuard g(f->device);
     if (int rc = ensure_batch(f, n)) return rc;
-    hipError_t e = inverse_pass(f, (int)n, x, stream);
+    hipError_t e = inverse_pass(f, (int)n, x, false, stream);
     if (e == hipSuccess && z_out)
         e = hipMemcpyAsync(z_out, boundary(f, 0), sizeof(double) * n * f->dim, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess && logq_out) {

@@ -42,6 +42,10 @@ struct GemmArgs {
     // (split 1) column sums of the final FP32 outputs over each 64-row block
     // of the tile grid, in FP64 and a fixed order: col_part [ceil(M/64)][N]
     double *col_part = nullptr;
+    // (split 1) transposed BF16 copy of the output: CbT[j ldcbT + i]
+    // (ldcbT a multiple of 4, CbT 8-byte aligned)
+    uint16_t *CbT = nullptr;
+    int64_t ldcbT = 0;
 };
 
 constexpr int kMaxSplit = 16;

@@ -156,7 +156,7 @@ def init_chains(problem: Problem, x0: np.ndarray, ws: Workspace) -> ChainState:
 
 def run_random_walk(problem: Problem, state: ChainState, n_steps: int, seed: int, chol, ws: Workspace,
                     adapt_every: int = 0, record_every: int = 0, record_track: int | None = None,
-                    collect_every: int = 0, target_accept: float = 0.234):
+                    collect_every: int = 0, target_accept: float = 0.234, progress=None):
     """n_steps random-walk MH steps on every chain.  With adapt_every > 0 the
     proposal is re-fitted that often on the GPU: the Cholesky factor of
     (2.38^2/d) s^2 times the chains' sample covariance, s a global scale that
@@ -166,7 +166,8 @@ def run_random_walk(problem: Problem, state: ChainState, n_steps: int, seed: int
     steps (host copies) and collects all chains every collect_every steps
     into a device array.  Returns (records [n_records, track, dim] or None,
     acceptance rate, seconds, final Cholesky factor (device), collected
-    [n_collect * n_chains, dim] on the device or None)."""
+    [n_collect * n_chains, dim] on the device or None).  progress, if given,
+    is called with the number of steps done every 10,000 steps."""
     import torch
     n, dim = state.x.shape
     dev = state.x.device
@@ -195,6 +196,8 @@ def run_random_walk(problem: Problem, state: ChainState, n_steps: int, seed: int
         if collect_every and (i + 1) % collect_every == 0:
             k = (i + 1) // collect_every - 1
             collected[k * n:(k + 1) * n].copy_(state.x)
+        if progress is not None and (i + 1) % 10000 == 0:
+            progress(i + 1)
     torch.cuda.synchronize()
     seconds = time.perf_counter() - t0
     rate = buf.accepted(buf.total) / (n * max(n_steps, 1))
@@ -322,9 +325,9 @@ def run_flow_mh(problem: Problem, state: ChainState, flow: Flow, n_steps: int, s
 
 
 def compare_samplers(problem: Problem, p_inj: np.ndarray, ws: Workspace, n_chains: int = 4096, burn: int = 4000,
-                     steps: int = 1024, flow_steps: int = 3000, hidden: int = 256, n_layers: int = 8,
+                     steps: int = 1024, flow_steps: int = 1500, hidden: int = 256, n_layers: int = 8,
                      seed: int = 20190408, track: int = 256, collect_every: int = 20, rw_every: int = 8,
-                     lr: float = 1e-3, lr_final: float | None = None):
+                     lr: float = 2e-3, lr_final: float | None = 2e-5, log=None):
     """The learned proposal against the plain method on one event: n_chains
     random-walk chains start in a tight ball around the injection (spin
     coordinates that the likelihood ignores start from their prior), burn in
@@ -334,7 +337,8 @@ def compare_samplers(problem: Problem, p_inj: np.ndarray, ws: Workspace, n_chain
     default); a flow is trained on them; flow-proposal MH continues from the
     random-walk states for one window, then for `steps` recorded steps.  ESS
     is the rank-normalised bulk ESS (minimum over coordinates) of the tracked
-    chains scaled to all chains.  Returns a dict of the figures and the two
+    chains scaled to all chains.  log, if given, receives a progress line
+    every 10,000 burn-in steps.  Returns a dict of the figures and the two
     populations' final states (host arrays)."""
     import torch
 
@@ -346,7 +350,11 @@ def compare_samplers(problem: Problem, p_inj: np.ndarray, ws: Workspace, n_chain
         x0[:, 9:] = rng.normal(scale=1.0, size=(n_chains, 2))
     state = init_chains(problem, x0, ws)
     chol = np.diag(np.full(dim, 1e-3))
-    _, acc_burn, t_burn, chol, _ = run_random_walk(problem, state, burn, seed, chol, ws, adapt_every=100)
+    def burn_progress(done):
+        if log is not None:
+            log(f"random-walk burn-in: {done} of {burn} steps")
+    _, acc_burn, t_burn, chol, _ = run_random_walk(problem, state, burn, seed, chol, ws, adapt_every=100,
+                                                   progress=burn_progress)
     rec_rw, acc_rw, t_rw, chol, collected = run_random_walk(problem, state, steps, seed, chol, ws, record_every=1,
                                                             record_track=track, collect_every=collect_every)
     n_train = int(collected.shape[0])

@@ -44,6 +44,8 @@ def summarize_report(r: np.ndarray) -> str:
             "max abs (mixed - FP64) over all 4096 rows": r[:, 6]}
     out = [f"{len(r)} injections, network optimal SNR {r[:, 1].min():.2f} to {r[:, 1].max():.2f}; bar "
            f"|dlnL| <= {TOL_MIXED:g}.\n",
+           f"injections: {len(r)}", f"max_abs_dlnl_vs_oracle: {r[:, 5].max():.4e}",
+           f"max_rel_dh_vs_oracle: {r[:, 4].max():.4e}", "",
            "| quantity | median | 90% | 99% | max |", "|---|---|---|---|---|"]
     for name, v in cols.items():
         q = np.quantile(v, [0.5, 0.9, 0.99])
