@@ -394,6 +394,45 @@ def bench_flow(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_flow_train(args):
+    """Training of the learned proposal alone: the flow of the flow-mcmc
+    workload (8 couplings 11 -> 256 -> 256 -> 22) fitted to 208,896 synthetic
+    11-parameter rows (a seeded correlated Gaussian, the size of the
+    random-walk training set), minibatches of 4096, --flow-steps Adam steps
+    with the flow-mcmc schedule.  Reports Adam steps per second and the MFMA
+    rate of the step's matrix products (three products of 2 n (D H + H^2 +
+    2 D H) flops per layer: forward, input gradients, weight gradients)."""
+    import numpy as np
+    import torch
+
+    from paper_1904_02863_amd import sampler
+    rng = np.random.default_rng(20190408)
+    d, n_rows = 11, 208896
+    a = rng.standard_normal((d, d)) * 0.3 + np.eye(d)
+    x = torch.from_numpy(rng.standard_normal((n_rows, d)) @ a.T + rng.uniform(-5, 5, d)).to("cuda")
+    lr_final = args.flow_lr_final if args.flow_lr_final > 0 else None
+    sampler.train_flow(x, steps=max(1, args.warmup), lr=args.flow_lr, lr_final=lr_final)       # warm-up
+    flow, hist, secs = sampler.train_flow(x, steps=args.flow_steps, lr=args.flow_lr, lr_final=lr_final,
+                                          log_every=max(1, args.flow_steps // 4))
+    h, layers, batch = 256, 8, 4096
+    flops = 3 * 2 * batch * (d * h + h * h + 2 * d * h) * layers
+    per = secs / args.flow_steps
+    result = {
+        "metric": "flow training Adam steps/s (8 couplings 11-256-256-22, batch 4096)",
+        "value": 1.0 / per, "unit": "steps/s", "n_gpus": 1, "steps": args.flow_steps,
+        "warmup": max(1, args.warmup), "ms_per_step": per * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16+f32+f64", "data": "synthetic",
+        "config": {"workload": "flow-train", "rows": n_rows, "dim": d, "hidden": h, "layers": layers,
+                   "batch": batch, "lr": args.flow_lr, "lr_final": lr_final},
+        "loss_history": hist,
+        "roofline": {"bound": "mfma", "achieved": flops / per / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": flops / per / 1e12 / 2500.0, "traffic": None,
+                     "kernel": "whole training step (about 120 launches, 72 of them BF16 GEMMs)",
+                     "gemm_flops_per_step": flops},
+    }
+    print(json.dumps(result), flush=True)
+
+
 MIXED_REPORT = "profiles/mixed_precision_bbh-3det-128s.md"
 
 
@@ -740,7 +779,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--workload", default="bbh-3det-128s",
                     choices=["bbh-3det-128s", "bbh-1det-4s", "bns-15hz-512s", "bns-ragged", "flow-mcmc",
-                             "population", "waveform", "bns-relbin"])
+                             "flow-train", "population", "waveform", "bns-relbin"])
     ap.add_argument("--mcmc-burn", type=int, default=None,
                     help="flow-mcmc: random-walk burn-in steps (default 120000 with aligned spins, 4000 without)")
     ap.add_argument("--mcmc-steps", type=int, default=1024, help="flow-mcmc: production steps of each sampler")
@@ -782,6 +821,9 @@ def main():
         return
     if args.workload == "flow-mcmc":
         bench_flow(args)
+        return
+    if args.workload == "flow-train":
+        bench_flow_train(args)
         return
     if args.workload == "population":
         bench_population(args)

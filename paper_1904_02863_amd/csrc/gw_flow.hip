@@ -220,6 +220,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int vec_a, i
                 }
                 if (g.C) g.C[(int64_t)i * g.ldc + j] = v[r];
                 if (g.Cb) g.Cb[(int64_t)i * g.ldcb + j] = f32_to_bf16(v[r]);
+                if (g.add_to && ((g.add_mask >> j) & 1u)) g.add_to[(int64_t)i * g.ld_add + j] += (double)v[r];
                 csum[b] += (double)v[r];
             }
             if (g.CbT && !to_partial) {
@@ -280,7 +281,8 @@ hipError_t gemm_bf16(const GemmArgs &g, hipStream_t stream)
 {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
     if (g.split < 1 || g.split > kMaxSplit || ((g.split > 1 || g.defer) && !g.partial)) return hipErrorInvalidValue;
-    if ((g.col_part || g.relu_of || g.CbT) && (g.split > 1 || g.defer)) return hipErrorInvalidValue;
+    if ((g.col_part || g.relu_of || g.CbT || g.add_to) && (g.split > 1 || g.defer)) return hipErrorInvalidValue;
+    if (g.add_to && g.N > 32) return hipErrorInvalidValue;
     // the transposed copy is written 4 rows (8 bytes) at a time
     if (g.CbT && (g.ldcbT % 4 != 0 || (reinterpret_cast<uintptr_t>(g.CbT) & 7u) != 0)) return hipErrorInvalidValue;
     // A is read along k when its k stride is 1, else along i (stride 1 required then)
@@ -310,6 +312,28 @@ hipError_t gemm_bf16(const GemmArgs &g, hipStream_t stream)
 
 // MLP input: the conditioning dimensions of a, the others zero, as BF16 in a
 // row of kInPad entries (the GEMM's K is dim; the padding stays zero).
+// The masked MLP input of the next coupling, written by the kernel that
+// produces that coupling's input: row b of a as BF16 in xm[b][kInPad] with
+// the dimensions outside cond zero, and with xmT given also transposed,
+// xmT[i ldT + b] (for the weight gradients).  xm == nullptr: none.
+struct NextMask {
+    uint16_t *xm;
+    uint16_t *xmT;
+    int64_t ldT;
+    unsigned cond;
+};
+
+__device__ __forceinline__ void write_mask(const NextMask &nm, int b, int dim, const double *__restrict__ row)
+{
+    if (!nm.xm) return;
+    for (int i = 0; i < kInPad; ++i) {
+        const bool on = i < dim && ((nm.cond >> i) & 1u);
+        const uint16_t v = on ? f32_to_bf16((float)row[i]) : (uint16_t)0;
+        nm.xm[(int64_t)b * kInPad + i] = v;
+        if (nm.xmT) nm.xmT[i * nm.ldT + b] = v;
+    }
+}
+
 // With xmT given, also the transposed copy xmT[i ldT + b] (for the weight gradients).
 __global__ __launch_bounds__(256) void mask_input_kernel(int n, int dim, unsigned cond, const double *__restrict__ a,
                                                          uint16_t *__restrict__ xm, uint16_t *__restrict__ xmT,
@@ -332,7 +356,7 @@ __global__ __launch_bounds__(256) void mask_input_kernel(int n, int dim, unsigne
 __global__ __launch_bounds__(256) void coupling_kernel(int n, int dim, unsigned cond, int dir,
                                                        const double *__restrict__ a, const float *__restrict__ out,
                                                        double *__restrict__ y, double *__restrict__ sum_s,
-                                                       double *__restrict__ s_out)
+                                                       double *__restrict__ s_out, NextMask nm)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
@@ -351,14 +375,16 @@ __global__ __launch_bounds__(256) void coupling_kernel(int n, int dim, unsigned 
         if (s_out) s_out[(int64_t)b * dim + i] = s;
     }
     sum_s[b] += acc;
+    write_mask(nm, b, dim, y + (int64_t)b * dim);
 }
 
 // Affine normalisation around the coupling stack: forward x = mu + sigma u,
 // inverse u = (x - mu) / sigma; sum_s[b] += sum log sigma in both directions.
+// init_sum: sum_s[b] starts from zero here.
 __global__ __launch_bounds__(256) void affine_kernel(int n, int dim, int dir, const double *__restrict__ mu,
                                                      const double *__restrict__ log_sigma,
                                                      const double *__restrict__ a, double *__restrict__ y,
-                                                     double *__restrict__ sum_s)
+                                                     double *__restrict__ sum_s, int init_sum, NextMask nm)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
@@ -368,7 +394,8 @@ __global__ __launch_bounds__(256) void affine_kernel(int n, int dim, int dir, co
         y[(int64_t)b * dim + i] = dir > 0 ? mu[i] + exp(log_sigma[i]) * v : (v - mu[i]) * exp(-log_sigma[i]);
         acc += log_sigma[i];
     }
-    sum_s[b] += acc;
+    sum_s[b] = (init_sum ? 0.0 : sum_s[b]) + acc;
+    write_mask(nm, b, dim, y + (int64_t)b * dim);
 }
 
 // log q = -|z|^2/2 - dim/2 log(2 pi) - sum_s; the per-row training loss is
@@ -515,16 +542,6 @@ __global__ __launch_bounds__(256) void grad_finish_kernel(GradParts gp, float *_
     }
 }
 
-// d loss / d y for the conditioning dimensions: add the MLP input gradient.
-__global__ __launch_bounds__(256) void add_input_grad_kernel(int n, int dim, unsigned cond,
-                                                             const float *__restrict__ dxm, double *__restrict__ gy)
-{
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * dim) return;
-    const int i = idx % dim;
-    if ((cond >> i) & 1u) gy[idx] += (double)dxm[idx];
-}
-
 // Adam (Kingma & Ba 2015) on FP32 master parameters.
 __global__ __launch_bounds__(256) void adam_kernel(int64_t count, float *__restrict__ p, const float *__restrict__ grad,
                                                    float *__restrict__ m, float *__restrict__ v, float lr, float beta1,
@@ -619,7 +636,6 @@ struct gw_flow {
     uint16_t *dout_b = nullptr;           // [cap][kOutPad]
     float *dh = nullptr;                  // [cap][hidden]
     uint16_t *dpre_b = nullptr;           // [cap][hidden]
-    float *dxm = nullptr;                 // [cap][dim]
     uint16_t *dpre2_b = nullptr;          // [cap][hidden], the other layer's BF16 pre-activation gradient
     // transposed BF16 copies for the weight gradients (row length ldT, a
     // multiple of 64 >= cap): activations [layers][hidden][ldT], inputs
@@ -694,14 +710,14 @@ hipError_t alloc(T **p, int64_t count)
 void free_batch(gw_flow *f)
 {
     void *ptrs[] = {f->bound, f->s_store, f->sum_s, f->loss, f->g, f->gy, f->xm_b, f->h1_b, f->h2_b,
-                    f->out_f, f->dout_f, f->dout_b, f->dh, f->dpre_b, f->dpre2_b, f->dxm, f->wpart, f->bpart,
+                    f->out_f, f->dout_f, f->dout_b, f->dh, f->dpre_b, f->dpre2_b, f->wpart, f->bpart,
                     f->h1T, f->h2T, f->xmT, f->doutT, f->dpreT, f->dpre2T};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     f->bound = f->s_store = f->sum_s = f->loss = f->g = f->gy = f->bpart = nullptr;
     f->dpre2_b = f->h1T = f->h2T = f->xmT = f->doutT = f->dpreT = f->dpre2T = nullptr;
     f->xm_b = f->h1_b = f->h2_b = f->dout_b = f->dpre_b = nullptr;
-    f->out_f = f->dout_f = f->dh = f->dxm = f->wpart = nullptr;
+    f->out_f = f->dout_f = f->dh = f->wpart = nullptr;
     f->cap = 0;
 }
 
@@ -721,7 +737,7 @@ int ensure_batch(gw_flow *f, int64_t n)
         alloc(&f->loss, c) || alloc(&f->g, c * D) || alloc(&f->gy, c * D) || alloc(&f->xm_b, L * c * kInPad) ||
         alloc(&f->h1_b, L * c * H) || alloc(&f->h2_b, L * c * H) || alloc(&f->out_f, c * 2 * D) ||
         alloc(&f->dout_f, c * kOutPad) || alloc(&f->dout_b, c * kOutPad) || alloc(&f->dh, c * H) ||
-        alloc(&f->dpre_b, c * H) || alloc(&f->dxm, c * D) ||
+        alloc(&f->dpre_b, c * H) ||
         alloc(&f->dpre2_b, c * H) || alloc(&f->wpart, L * w_layer) || alloc(&f->bpart, L * b_layer) ||
         alloc(&f->h1T, L * H * ldT) || alloc(&f->h2T, L * H * ldT) || alloc(&f->xmT, L * kInPad * ldT) ||
         alloc(&f->doutT, kOutPad * ldT) || alloc(&f->dpreT, H * ldT) || alloc(&f->dpre2T, H * ldT)) {
@@ -741,18 +757,13 @@ double *boundary(gw_flow *f, int i) { return f->bound + (int64_t)i * f->cap * f-
 // The MLP of layer l on the masked input of rows [0, n): writes out_f (r, t)
 // and keeps the BF16 activations of layer l for the backward pass (with
 // keep_t also transposed, the weight gradients' operands).
-hipError_t mlp_forward(gw_flow *f, int l, int n, const double *a, bool keep_t, hipStream_t s)
+hipError_t mlp_forward(gw_flow *f, int l, int n, bool keep_t, hipStream_t s)
 {
     const int D = f->dim, H = f->hidden;
     const LayerOff o = layer_off(f, l);
-    uint16_t *xm = f->xm_b + (int64_t)l * f->cap * kInPad;
+    const uint16_t *xm = f->xm_b + (int64_t)l * f->cap * kInPad;
     uint16_t *h1 = f->h1_b + (int64_t)l * f->cap * H;
     uint16_t *h2 = f->h2_b + (int64_t)l * f->cap * H;
-    uint16_t *xmT = keep_t ? f->xmT + (int64_t)l * kInPad * f->ldT : nullptr;
-    hipLaunchKernelGGL(gw::flow::mask_input_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], a, xm,
-                       xmT, f->ldT);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     const uint16_t *wq = f->wb + o.q;
     const float *pp = f->params + o.p;
     GemmArgs g1{n, H, D, xm, kInPad, 1, wq + o.w1, 1, D, nullptr, 0, h1, H, pp + o.b1, 1};
@@ -762,10 +773,20 @@ hipError_t mlp_forward(gw_flow *f, int l, int n, const double *a, bool keep_t, h
         g2.CbT = f->h2T + (int64_t)l * H * f->ldT;
         g1.ldcbT = g2.ldcbT = f->ldT;
     }
+    hipError_t e;
     if ((e = gw::flow::gemm_bf16(g1, s)) != hipSuccess) return e;
     if ((e = gw::flow::gemm_bf16(g2, s)) != hipSuccess) return e;
     GemmArgs g3{n, 2 * D, H, h2, H, 1, wq + o.w3, 1, H, f->out_f, 2 * D, nullptr, 0, pp + o.b3, 0};
     return gw::flow::gemm_bf16(g3, s);
+}
+
+// Where the kernel producing layer l's input writes that layer's masked
+// MLP input (and, with keep_t, its transposed copy); none for l outside the stack.
+gw::flow::NextMask mask_of(gw_flow *f, int l, bool keep_t)
+{
+    if (l < 0 || l >= f->layers) return gw::flow::NextMask{nullptr, nullptr, 0, 0u};
+    return gw::flow::NextMask{f->xm_b + (int64_t)l * f->cap * kInPad,
+                              keep_t ? f->xmT + (int64_t)l * kInPad * f->ldT : nullptr, f->ldT, f->cond[l]};
 }
 
 #define GW_TRY(expr)                         \
@@ -781,23 +802,22 @@ hipError_t zero(int64_t n, double *p, hipStream_t s)
     return hipGetLastError();
 }
 
-// Inverse pass x -> z over rows [0, n): boundary L+1 = x, boundary L = the
-// normalised x, then the couplings L-1 .. 0 invert down to boundary 0 = z;
-// sum_s = sum log sigma + sum over layers of sum_T s.  Activations of every
-// layer are kept for the backward pass.
+// Inverse pass x -> z over rows [0, n): boundary L = the normalised x, then
+// the couplings L-1 .. 0 invert down to boundary 0 = z; sum_s = sum log sigma
+// + sum over layers of sum_T s.  Activations of every layer are kept for the
+// backward pass (with keep_t also the transposed copies).  Each kernel that
+// produces a coupling's input also writes that coupling's masked MLP input.
 hipError_t inverse_pass(gw_flow *f, int n, const double *x, bool keep_t, hipStream_t s)
 {
     const int D = f->dim, L = f->layers;
-    GW_TRY(zero(n, f->sum_s, s));
-    GW_TRY(hipMemcpyAsync(boundary(f, L + 1), x, sizeof(double) * (size_t)n * D, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL(gw::flow::affine_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, -1, f->mu, f->log_sigma,
-                       boundary(f, L + 1), boundary(f, L), f->sum_s);
+                       x, boundary(f, L), f->sum_s, 1, mask_of(f, L - 1, keep_t));
     GW_TRY(hipGetLastError());
     for (int l = L - 1; l >= 0; --l) {
-        GW_TRY(mlp_forward(f, l, n, boundary(f, l + 1), keep_t, s));
+        GW_TRY(mlp_forward(f, l, n, keep_t, s));
         hipLaunchKernelGGL(gw::flow::coupling_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], -1,
                            boundary(f, l + 1), f->out_f, boundary(f, l), f->sum_s,
-                           f->s_store + (int64_t)l * f->cap * D);
+                           f->s_store + (int64_t)l * f->cap * D, mask_of(f, l - 1, keep_t));
         GW_TRY(hipGetLastError());
     }
     return hipSuccess;
@@ -810,14 +830,19 @@ hipError_t forward_pass(gw_flow *f, int n, const double *z, hipStream_t s)
     const int D = f->dim, L = f->layers;
     GW_TRY(zero(n, f->sum_s, s));
     GW_TRY(hipMemcpyAsync(boundary(f, 0), z, sizeof(double) * (size_t)n * D, hipMemcpyDeviceToDevice, s));
+    const gw::flow::NextMask m0 = mask_of(f, 0, false);
+    hipLaunchKernelGGL(gw::flow::mask_input_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, m0.cond, z, m0.xm,
+                       nullptr, f->ldT);
+    GW_TRY(hipGetLastError());
     for (int l = 0; l < L; ++l) {
-        GW_TRY(mlp_forward(f, l, n, boundary(f, l), false, s));
+        GW_TRY(mlp_forward(f, l, n, false, s));
         hipLaunchKernelGGL(gw::flow::coupling_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], 1,
-                           boundary(f, l), f->out_f, boundary(f, l + 1), f->sum_s, nullptr);
+                           boundary(f, l), f->out_f, boundary(f, l + 1), f->sum_s, nullptr,
+                           mask_of(f, l + 1, false));
         GW_TRY(hipGetLastError());
     }
     hipLaunchKernelGGL(gw::flow::affine_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, 1, f->mu, f->log_sigma,
-                       boundary(f, L), boundary(f, L + 1), f->sum_s);
+                       boundary(f, L), boundary(f, L + 1), f->sum_s, 0, mask_of(f, -1, false));
     return hipGetLastError();
 }
 
@@ -890,11 +915,12 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
         // layer 1: dW1 = dpre1^T xm, dxm = dpre1 W1
         GemmArgs gw1{H, D, n, f->dpre2T, T, 1, xmT, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split, wp1, 1};
         GW_TRY(gw::flow::gemm_bf16(gw1, s));
-        GemmArgs gx{n, D, H, f->dpre2_b, H, 1, wt, 1, H, f->dxm, D, nullptr, 0, nullptr, 0};
+        // d loss / d y += dxm on the conditioning dimensions, in the epilogue
+        GemmArgs gx{n, D, H, f->dpre2_b, H, 1, wt, 1, H, nullptr, 0, nullptr, 0, nullptr, 0};
+        gx.add_to = f->gy;
+        gx.ld_add = D;
+        gx.add_mask = f->cond[l];
         GW_TRY(gw::flow::gemm_bf16(gx, s));
-        hipLaunchKernelGGL(gw::flow::add_input_grad_kernel, dim3(blocks_for((int64_t)n * D)), dim3(256), 0, s, n, D,
-                           f->cond[l], f->dxm, f->gy);
-        GW_TRY(hipGetLastError());
         std::swap(f->g, f->gy);      // d loss / d(boundary l + 1)
     }
     gw::flow::GradParts parts{D, H, split, rb64, f->rb64_cap, f->per_layer, f->n_params, f->w_layer, f->b_layer,

@@ -46,6 +46,11 @@ struct GemmArgs {
     // (ldcbT a multiple of 4, CbT 8-byte aligned)
     uint16_t *CbT = nullptr;
     int64_t ldcbT = 0;
+    // (split 1) add_to[i ld_add + j] += output (in FP64) for the columns j
+    // whose bit is set in add_mask (j < 32)
+    double *add_to = nullptr;
+    int64_t ld_add = 0;
+    unsigned add_mask = 0;
 };
 
 constexpr int kMaxSplit = 16;

@@ -127,7 +127,7 @@ def _full_size_problem(gw, torch, spins):
     return prob, p_inj, gw.Workspace(0)
 
 
-def test_learned_proposal_at_full_size_with_aligned_spins():
+def test_learned_proposal_at_full_size_with_aligned_spins(capsys):
     """The learned proposal at the stated size: the 11-parameter posterior (9
     extrinsic and intrinsic parameters and two aligned spins that enter the
     phase) of the 3-detector 128 s event at SNR 25, 4096 chains, a flow of 8
@@ -149,8 +149,12 @@ def test_learned_proposal_at_full_size_with_aligned_spins():
     import paper_1904_02863_amd as gw
     from paper_1904_02863_amd import sampler
     prob, p_inj, ws = _full_size_problem(gw, torch, spins=True)
-    res = sampler.compare_samplers(prob, p_inj, ws, n_chains=4096, burn=120000, steps=1024,
-                                   log=lambda m: print(m, flush=True))
+    def log(message):
+        # the burn-in takes minutes: report progress past pytest's output capture
+        with capsys.disabled():
+            print(message, flush=True)
+
+    res = sampler.compare_samplers(prob, p_inj, ws, n_chains=4096, burn=120000, steps=1024, log=log)
     states = res.pop("states")
     print(json.dumps(res), flush=True)
     assert res["train_samples"] >= 200000

@@ -151,7 +151,7 @@ def test_mixed_small_shapes(gw, n_det, n_bins, n_samples):
     assert np.abs(got - ref).max() <= TOL_MIXED
 
 
-def test_mixed_precision_over_1024_injections(gw):
+def test_mixed_precision_over_1024_injections(gw, capsys):
     """1024 injections on the 3-detector 128 s grid, network optimal SNR
     log-uniform in [8, 100], each with 4096 rows (the injection, half from the
     prior, half close to the injection).  Per injection the oracle checks the
@@ -211,8 +211,9 @@ def test_mixed_precision_over_1024_injections(gw):
             worst_mixed = max(worst_mixed, float(err.max()))
             worst_fp64 = max(worst_fp64, float((np.abs(fp64[pick] - ref) / np.abs(ref)).max()))
             report.append((b0 + i, target[i], dh_inj, err[0], err[0] / abs(dh_inj), float(err.max()), all_err))
-        print(f"{b0 + batch} injections: worst |mixed - oracle| {worst_mixed:.2e}, "
-              f"worst |mixed - fp64| {worst_all:.2e}, worst fp64 rel {worst_fp64:.2e}", flush=True)
+        with capsys.disabled():     # progress past pytest's output capture: the test takes minutes
+            print(f"{b0 + batch} injections: worst |mixed - oracle| {worst_mixed:.2e}, "
+                  f"worst |mixed - fp64| {worst_all:.2e}, worst fp64 rel {worst_fp64:.2e}", flush=True)
     out_dir = os.environ.get("GW_REPORT_DIR")
     if out_dir:
         os.makedirs(out_dir, exist_ok=True)
