@@ -94,6 +94,18 @@ __device__ __forceinline__ void load_chunk(const uint16_t *__restrict__ X, int64
                                            int t_end, int k0, int kc, int k_hi, bool vec, uint4 (&reg)[kVecPerThread])
 {
     const int tid = threadIdx.x;
+    if (KC && vec && t0 + kTileMN <= t_end && k0 + kc <= k_hi) {
+        // the whole chunk lies inside the matrix (the same for every thread
+        // of the block): one 16-byte load per vector, rows kRowsPerPass apart
+        constexpr int kGroups = kChunkK / 8, kRowsPerPass = 256 / kGroups;
+        const int kg = tid % kGroups;
+        const uint16_t *p = X + (int64_t)(t0 + tid / kGroups) * s_t + (k0 + 8 * kg);
+        const int64_t step = (int64_t)kRowsPerPass * s_t;
+#pragma unroll
+        for (int e = 0; e < kVecPerThread; ++e)
+            reg[e] = 8 * kg < kc ? *reinterpret_cast<const uint4 *>(p + e * step) : make_uint4(0u, 0u, 0u, 0u);
+        return;
+    }
 #pragma unroll
     for (int e = 0; e < kVecPerThread; ++e) {
         const int v = tid + 256 * e;
@@ -560,7 +572,9 @@ __global__ __launch_bounds__(256) void adam_kernel(int64_t count, float *__restr
 // BF16 copies of the weight matrices (FP32 master -> BF16): parameter i of
 // layer i / per_layer goes to dst[layer * dst_stride + i % per_layer], and
 // the weights also transposed into dstT (layer stride t_stride): W1^T [D][H],
-// W2^T [H][H], W3^T [H][kOutPad] (rows padded), the backward pass's operands.
+// W2^T [H][H], W3^T [H][kOutPad] (rows padded), the backward pass's operands,
+// then W1 with its rows padded to kInPad, [H][kInPad], the first product's
+// operand in 16-byte vectors.
 __global__ __launch_bounds__(256) void to_bf16_kernel(int64_t count, int64_t per_layer, int64_t dst_stride,
                                                       int D, int H, int64_t t_stride, const float *__restrict__ src,
                                                       uint16_t *__restrict__ dst, uint16_t *__restrict__ dstT)
@@ -573,8 +587,9 @@ __global__ __launch_bounds__(256) void to_bf16_kernel(int64_t count, int64_t per
     dst[l * dst_stride + q] = v;
     uint16_t *t = dstT + l * t_stride;
     const int64_t s1 = (int64_t)H * D, s2 = (int64_t)H * H, s3 = 2 * (int64_t)D * H;
-    if (q < s1) {                                   // W1 [H][D] -> W1^T [D][H]
+    if (q < s1) {                                   // W1 [H][D] -> W1^T [D][H], and padded rows
         t[(q % D) * H + q / D] = v;
+        t[s1 + s2 + (int64_t)H * kOutPad + (q / D) * kInPad + q % D] = v;
         return;
     }
     q -= s1 + H;
@@ -766,7 +781,11 @@ hipError_t mlp_forward(gw_flow *f, int l, int n, bool keep_t, hipStream_t s)
     uint16_t *h2 = f->h2_b + (int64_t)l * f->cap * H;
     const uint16_t *wq = f->wb + o.q;
     const float *pp = f->params + o.p;
-    GemmArgs g1{n, H, D, xm, kInPad, 1, wq + o.w1, 1, D, nullptr, 0, h1, H, pp + o.b1, 1};
+    // W1 with rows padded to kInPad (in the transposed copy's block); the
+    // padding of both operands is zero, so K = kInPad adds exact zeros only
+    const uint16_t *w1p = f->wbT + (int64_t)l * f->wbT_stride + (int64_t)D * H + (int64_t)H * H +
+                          (int64_t)H * kOutPad;
+    GemmArgs g1{n, H, kInPad, xm, kInPad, 1, w1p, 1, kInPad, nullptr, 0, h1, H, pp + o.b1, 1};
     GemmArgs g2{n, H, H, h1, H, 1, wq + o.w2, 1, H, nullptr, 0, h2, H, pp + o.b2, 1};
     if (keep_t) {
         g1.CbT = f->h1T + (int64_t)l * H * f->ldT;
@@ -970,14 +989,14 @@ int gw_flow_create(gw_flow **out, int device, int dim, int n_layers, int hidden,
     f->per_layer = H * D + H + H * H + H + 2 * D * H + 2 * D;
     f->n_params = f->per_layer * n_layers;
     f->wb_stride = (f->per_layer + 7) / 8 * 8;
-    f->wbT_stride = (D * H + H * H + H * gw::flow::kOutPad + 7) / 8 * 8;
+    f->wbT_stride = (D * H + H * H + H * gw::flow::kOutPad + H * gw::flow::kInPad + 7) / 8 * 8;
     if (alloc(&f->params, f->n_params) || alloc(&f->grads, f->n_params) || alloc(&f->adam_m, f->n_params) ||
         alloc(&f->adam_v, f->n_params) || alloc(&f->wb, f->wb_stride * n_layers) ||
         alloc(&f->wbT, f->wbT_stride * n_layers) || alloc(&f->mu, dim) || alloc(&f->log_sigma, dim)) {
         gw_flow_destroy(f);
         return fail(GW_ENOMEM, "flow parameters");
     }
-    // the padding of W3^T's rows is never written by to_bf16_kernel: zero it once
+    // the padding of W3^T's and W1's rows is never written by to_bf16_kernel: zero it once
     if (hipMemset(f->wbT, 0, sizeof(uint16_t) * (size_t)(f->wbT_stride * n_layers)) != hipSuccess) {
         gw_flow_destroy(f);
         return fail(GW_EDEVICE, "flow parameters");

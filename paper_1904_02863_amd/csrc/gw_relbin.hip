@@ -253,27 +253,33 @@ __global__ __launch_bounds__(kBlock) void totals_kernel(int64_t n_rb, const doub
 // turns), and the ratio and every sum stay FP64.
 // FP64: the phase comes in scaled by GW_PHTAB_N (coefficients and delay
 // differences scaled at load) and the phasor from the LDS table tab.
+// The template's phasor e_d = e^{-2 pi i x_d} at edge e for every detector:
+// x_0 the phase difference from the fiducial waveform at the edge, x_d =
+// x_0 + f_e (delta_d - delta_d^0) for the others (in turns, scaled by the
+// table size on the FP64 path).  The ratio to the fiducial waveform is
+// r_d = q_d e_d, q_d = P_d / P_d^0.
 template <int NDET, bool MIXED>
-__device__ __forceinline__ void edge_ratio(const PhaseCoef &c, const RbEdge &e, const double (&qr)[NDET],
-                                           const double (&qi)[NDET], const double (&dl)[NDET], double (&rr)[NDET],
-                                           double (&ri)[NDET], const double2 *tab)
+__device__ __forceinline__ void edge_phasor(const PhaseCoef &c, const RbEdge &e, const double (&dl)[NDET],
+                                            double (&er)[NDET], double (&ei)[NDET], const double2 *tab)
 {
     const double dphi = turns_phase(c, e.t1);
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
         const double x = d == 0 ? dphi : __builtin_fma(e.f, dl[d], dphi);
-        double er, ei;
         if constexpr (MIXED) {
             const float r = (float)(x - __builtin_rint(x));
-            er = (double)__builtin_amdgcn_cosf(r);
-            ei = -(double)__builtin_amdgcn_sinf(r);
+            er[d] = (double)__builtin_amdgcn_cosf(r);
+            ei[d] = -(double)__builtin_amdgcn_sinf(r);
         } else {
-            gw_phasor_table(x, tab, er, ei);
+            gw_phasor_table(x, tab, er[d], ei[d]);
         }
-        rr[d] = qr[d] * er - qi[d] * ei;
-        ri[d] = qr[d] * ei + qi[d] * er;
     }
 }
+
+// Edges per unrolled step of the relative-binning edge loop.
+#ifndef GW_RB_UNROLL
+#define GW_RB_UNROLL 4
+#endif
 
 template <int NDET, bool MIXED>
 __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t n_rb, int n_chunks,
@@ -312,7 +318,7 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
     // FP64: phase in units of 1/N turn for the table phasor (exact: N is a power of two)
     const double scale = MIXED ? 1.0 : (double)GW_PHTAB_N;
     if constexpr (!MIXED) c = scale_coef(c, scale);
-    double qr[NDET], qi[NDET], dl[NDET], rr[NDET], ri[NDET], nr[NDET], ni[NDET], acc[NDET];
+    double qr[NDET], qi[NDET], dl[NDET];
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
         const double pr = rec[(kRecDet + kRecFieldsPerDet * d) * n_samples + sr];
@@ -325,46 +331,51 @@ __global__ __launch_bounds__(kBlock) void lnl_kernel(int64_t n_samples, int64_t 
         qi[d] = (pi * p0r - pr * p0i) * inv;
         dl[d] = (delta - fid[kRecDet + kRecFieldsPerDet * d + 2]) * scale;   // zero for detector 0
     }
+    // With r = q e, the linear terms Re(conj(l) r) = qr U + qi V for
+    // U = sum (l_r e_r + l_i e_i), V = sum (l_i e_r - l_r e_i), and the cross
+    // terms x_b Re(r_prev conj(r_next)) = |q|^2 x_b Re(e_prev conj(e_next)):
+    // the sums run over the template's phasors alone and q enters once, at
+    // the end.
+    double er[NDET], ei[NDET], pr[NDET], pi[NDET], U[NDET], V[NDET], X[NDET];
     // first edge: the lower side of bin b0 only
-    edge_ratio<NDET, MIXED>(c, edges[b0], qr, qi, dl, rr, ri, tab);
+    edge_phasor<NDET, MIXED>(c, edges[b0], dl, pr, pi, tab);
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
         const RbEnds k = ends[b0 * NDET + d];
-        acc[d] = __builtin_fma(k.lo_i, ri[d], k.lo_r * rr[d]);
+        U[d] = __builtin_fma(k.lo_r, pr[d], k.lo_i * pi[d]);
+        V[d] = __builtin_fma(k.lo_i, pr[d], -(k.lo_r * pi[d]));
+        X[d] = 0.0;
     }
     // edges inside the chunk: both bins that meet there
-#pragma unroll 4
+#pragma unroll GW_RB_UNROLL
     for (int64_t e = b0 + 1; e < b1; ++e) {
-        edge_ratio<NDET, MIXED>(c, edges[e], qr, qi, dl, nr, ni, tab);
+        edge_phasor<NDET, MIXED>(c, edges[e], dl, er, ei, tab);
 #pragma unroll
         for (int d = 0; d < NDET; ++d) {
             const RbCoef k = coef[e * NDET + d];
-            double a = acc[d];
-            a = __builtin_fma(k.xb, __builtin_fma(rr[d], nr[d], ri[d] * ni[d]), a);
-            a = __builtin_fma(k.lr, nr[d], a);
-            a = __builtin_fma(k.li, ni[d], a);
-            acc[d] = a;
-            rr[d] = nr[d];
-            ri[d] = ni[d];
+            X[d] = __builtin_fma(k.xb, __builtin_fma(pr[d], er[d], pi[d] * ei[d]), X[d]);
+            U[d] = __builtin_fma(k.lr, er[d], __builtin_fma(k.li, ei[d], U[d]));
+            V[d] = __builtin_fma(k.li, er[d], __builtin_fma(-k.lr, ei[d], V[d]));
+            pr[d] = er[d];
+            pi[d] = ei[d];
         }
     }
     // last edge: the upper side of bin b1 - 1 only; then the squared terms
-    edge_ratio<NDET, MIXED>(c, edges[b1], qr, qi, dl, nr, ni, tab);
+    edge_phasor<NDET, MIXED>(c, edges[b1], dl, er, ei, tab);
     double total = 0.0;
 #pragma unroll
     for (int d = 0; d < NDET; ++d) {
         const RbEnds k = ends[b1 * NDET + d];
         const RbEnds k0 = ends[b0 * NDET + d];
         const double xb = coef[b1 * NDET + d].xb;
-        double a = acc[d];
-        a = __builtin_fma(xb, __builtin_fma(rr[d], nr[d], ri[d] * ni[d]), a);
-        a = __builtin_fma(k.hi_r, nr[d], a);
-        a = __builtin_fma(k.hi_i, ni[d], a);
+        const double x = __builtin_fma(xb, __builtin_fma(pr[d], er[d], pi[d] * ei[d]), X[d]);
+        const double u = __builtin_fma(k.hi_r, er[d], __builtin_fma(k.hi_i, ei[d], U[d]));
+        const double v = __builtin_fma(k.hi_i, er[d], __builtin_fma(-k.hi_r, ei[d], V[d]));
         // squared-term coefficients of the chunk: the lower side of its first
         // edge, both sides of every inner edge, the upper side of its last edge
         const double qsum = (k0.lo_q + (k.qcum - ends[(b0 + 1) * NDET + d].qcum)) + k.hi_q;
         const double q2 = __builtin_fma(qr[d], qr[d], qi[d] * qi[d]);
-        total += __builtin_fma(qsum, q2, a);
+        total += __builtin_fma(q2, qsum + x, __builtin_fma(qr[d], u, qi[d] * v));
     }
     if (s < n_samples) partials[(int64_t)chunk * n_samples + s] = total;
 }
