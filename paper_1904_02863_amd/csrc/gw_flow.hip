@@ -365,20 +365,18 @@ __global__ __launch_bounds__(256) void mask_input_kernel(int n, int dim, unsigne
 //   forward (dir > 0): y_T = a_T exp(s) + t;  inverse (dir < 0): y_T = (a_T - t) exp(-s);
 // s = 3 tanh(r/3); conditioning dimensions are copied.  sum_s[b] += sum_T s in
 // both directions (log q = log N(z) - sum_s); s is stored when s_out is set.
-__global__ __launch_bounds__(256) void coupling_kernel(int n, int dim, unsigned cond, int dir,
-                                                       const double *__restrict__ a, const float *__restrict__ out,
-                                                       double *__restrict__ y, double *__restrict__ sum_s,
-                                                       double *__restrict__ s_out, NextMask nm)
+// Row b of the coupling, its MLP output row at out (r at [0, dim), t at [dim, 2 dim)).
+__device__ __forceinline__ void coupling_row(int b, int dim, unsigned cond, int dir, const double *__restrict__ a,
+                                             const float *out, double *__restrict__ y, double *__restrict__ sum_s,
+                                             double *__restrict__ s_out, const NextMask &nm)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n) return;
     double acc = 0.0;
     for (int i = 0; i < dim; ++i) {
         const double ai = a[(int64_t)b * dim + i];
         double yi = ai, s = 0.0;
         if (!((cond >> i) & 1u)) {
-            const double r = (double)out[(int64_t)b * 2 * dim + i];
-            const double t = (double)out[(int64_t)b * 2 * dim + dim + i];
+            const double r = (double)out[i];
+            const double t = (double)out[dim + i];
             s = 3.0 * tanh(r / 3.0);
             yi = dir > 0 ? ai * exp(s) + t : (ai - t) * exp(-s);
             acc += s;
@@ -388,6 +386,136 @@ __global__ __launch_bounds__(256) void coupling_kernel(int n, int dim, unsigned 
     }
     sum_s[b] += acc;
     write_mask(nm, b, dim, y + (int64_t)b * dim);
+}
+
+__global__ __launch_bounds__(256) void coupling_kernel(int n, int dim, unsigned cond, int dir,
+                                                       const double *__restrict__ a, const float *__restrict__ out,
+                                                       double *__restrict__ y, double *__restrict__ sum_s,
+                                                       double *__restrict__ s_out, NextMask nm)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    coupling_row(b, dim, cond, dir, a, out + (int64_t)b * 2 * dim, y, sum_s, s_out, nm);
+}
+
+// ---------------------------------------------------------------- one coupling in one kernel
+// A coupling of the flow on kLayerRows rows per block, for hidden widths
+// H = 128 and 256: the MLP's three products on the matrix cores with both
+// hidden activations held in LDS, then the coupling of each row.  Each of the
+// 4 waves owns H/4 hidden columns; lane l works on rows l%16 and k group l/16
+// as in the GEMM, with the same v_mfma_f32_16x16x32_bf16 sequence over k, so
+// the activations and outputs equal the GEMM path's bit for bit.  The
+// weights come straight from global memory (L2-resident) in 16-byte
+// fragments: W1 with padded rows (K = kInPad, zero padding), W2 [H][H] and
+// W3 [2 dim][H] as stored (out, in).
+constexpr int kLayerRows = 16;
+
+struct LayerArgs {
+    int n, dim, dir;
+    unsigned cond;
+    const uint16_t *xm;                   // [n][kInPad] masked MLP input
+    const uint16_t *w1p, *w2, *w3;
+    const float *b1, *b2, *b3;
+    uint16_t *h1, *h2;                    // [n][H] activations, kept for the backward pass
+    uint16_t *h1T, *h2T;                  // transposed copies (training) or null
+    int64_t ldT;
+    const double *a;
+    double *y, *sum_s, *s_out;
+    NextMask nm;
+};
+
+__device__ __forceinline__ bf16x8_t ld_bf16x8(const uint16_t *p) { return *reinterpret_cast<const bf16x8_t *>(p); }
+
+template <int H>
+__device__ __forceinline__ void store_hidden(const LayerArgs &p, uint16_t (*hs)[H + 8], uint16_t *hg, uint16_t *hT,
+                                             const float4_t (&acc)[H / 64], const float *__restrict__ bias, int r0,
+                                             int c0, int g, int lr)
+{
+#pragma unroll
+    for (int t = 0; t < H / 64; ++t) {
+        const int j = c0 + 16 * t + lr;
+        const float bj = bias[j];
+        uint16_t q[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float v = acc[t][r] + bj;
+            v = v > 0.f ? v : 0.f;
+            q[r] = f32_to_bf16(v);
+            hs[4 * g + r][j] = q[r];
+            const int i = r0 + 4 * g + r;
+            if (i < p.n) hg[(int64_t)i * H + j] = q[r];
+        }
+        if (hT) {
+            uint16_t *t4 = hT + (int64_t)j * p.ldT + r0 + 4 * g;
+            if (r0 + 4 * g + 3 < p.n) {
+                *reinterpret_cast<uint2 *>(t4) = make_uint2((uint32_t)q[0] | ((uint32_t)q[1] << 16),
+                                                            (uint32_t)q[2] | ((uint32_t)q[3] << 16));
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (r0 + 4 * g + r < p.n) t4[r] = q[r];
+            }
+        }
+    }
+}
+
+template <int H>
+__global__ __launch_bounds__(256) void layer_kernel(LayerArgs p)
+{
+    __shared__ __align__(16) uint16_t h1s[kLayerRows][H + 8];
+    __shared__ __align__(16) uint16_t h2s[kLayerRows][H + 8];
+    __shared__ float outs[kLayerRows][kOutPad];
+    constexpr int NT = H / 64;            // 16-column tiles per wave
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r0 = blockIdx.x * kLayerRows;
+    const int lr = lane & 15, g = lane >> 4;
+    const int c0 = wave * (H / 4);
+    const bool row_ok = r0 + lr < p.n;
+    const bf16x8_t zero8 = {};
+    // h1 = relu(xm W1^T + b1), K = kInPad padded to 32 by zeros
+    float4_t acc[NT];
+    {
+        const bf16x8_t av = (g < 2 && row_ok) ? ld_bf16x8(p.xm + (int64_t)(r0 + lr) * kInPad + 8 * g) : zero8;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const bf16x8_t bv = g < 2 ? ld_bf16x8(p.w1p + (int64_t)(c0 + 16 * t + lr) * kInPad + 8 * g) : zero8;
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        }
+    }
+    store_hidden<H>(p, h1s, p.h1, p.h1T, acc, p.b1, r0, c0, g, lr);
+    __syncthreads();
+    // h2 = relu(h1 W2^T + b2), K = H
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < H; kk += 32) {
+        const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&h1s[lr][kk + 8 * g]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const bf16x8_t bv = ld_bf16x8(p.w2 + (int64_t)(c0 + 16 * t + lr) * H + kk + 8 * g);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+        }
+    }
+    store_hidden<H>(p, h2s, p.h2, p.h2T, acc, p.b2, r0, c0, g, lr);
+    __syncthreads();
+    // out = h2 W3^T + b3: 2 dim <= 32 columns, one 16-column tile for each of waves 0 and 1
+    const int n_out = 2 * p.dim;
+    if (wave < 2) {
+        const int col = 16 * wave + lr;
+        float4_t o = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < H; kk += 32) {
+            const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&h2s[lr][kk + 8 * g]);
+            const bf16x8_t bv = col < n_out ? ld_bf16x8(p.w3 + (int64_t)col * H + kk + 8 * g) : zero8;
+            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, o, 0, 0, 0);
+        }
+        const float bc = col < n_out ? p.b3[col] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) outs[4 * g + r][col] = o[r] + bc;
+    }
+    __syncthreads();
+    const int b = r0 + tid;
+    if (tid < kLayerRows && b < p.n) coupling_row(b, p.dim, p.cond, p.dir, p.a, outs[tid], p.y, p.sum_s, p.s_out, p.nm);
 }
 
 // Affine normalisation around the coupling stack: forward x = mu + sigma u,
@@ -426,6 +554,161 @@ __global__ __launch_bounds__(256) void base_density_kernel(int n, int dim, const
     const double l = 0.5 * zz + sum_s[b];
     if (logq) logq[b] = -l - 0.5 * dim * 1.8378770664093453;   // log(2 pi)
     if (loss) loss[b] = l;
+}
+
+// ---------------------------------------------------------------- one coupling's backward in one kernel
+// The row-local part of coupling l's backward pass on kLayerRows rows per
+// block (hidden width H = 128 or 256), in the order of the separate kernels
+// it replaces and with the same products (v_mfma_f32_16x16x32_bf16 over k in
+// order):
+//   dout = d loss / d(r, t) from the inverse coupling and the direct part of
+//   d loss / d y (into gy); dh2 = dout W3 masked by h2 > 0; dh1 = dh2 W2
+//   masked by h1 > 0; dxm = dh1 W1 added into gy on the conditioning
+//   dimensions.
+// The weight gradients need sums over all rows and stay split-K GEMMs; this
+// kernel writes their transposed BF16 operands (doutT, dpreT, dpre2T) and the
+// bias gradients' partial sums over its rows (FP64, fixed order) into
+// bpart: [block][H] for b1 and b2 (at bp1, bp2), [block][2 dim] for b3.
+struct BackArgs {
+    int n, dim;
+    unsigned cond;
+    const double *g, *x, *s;              // d loss / d x, x = the coupling's output (inverse direction), s
+    double *gy;                           // d loss / d y
+    const uint16_t *h1, *h2;              // [n][H] activations of the forward pass
+    const uint16_t *w1t, *w2t, *w3t;      // W1^T [D][H], W2^T [H][H], W3^T [H][kOutPad]
+    uint16_t *doutT, *dpreT, *dpre2T;     // transposed operands of the weight gradients (row length ldT)
+    int64_t ldT;
+    double *bp1, *bp2, *bp3;              // bias partials [block][H], [block][H], [block][2 dim]
+};
+
+template <int H>
+__device__ __forceinline__ void masked_hidden(const BackArgs &p, uint16_t (*ds)[H + 8], uint16_t *dT, double *bp,
+                                              const float4_t (&acc)[H / 64], const uint16_t *__restrict__ h, int r0,
+                                              int c0, int g, int lr)
+{
+#pragma unroll
+    for (int t = 0; t < H / 64; ++t) {
+        const int j = c0 + 16 * t + lr;
+        uint16_t q[4];
+        double cs = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = r0 + 4 * g + r;
+            float v = acc[t][r];
+            if (i < p.n) {
+                const uint16_t hv = h[(int64_t)i * H + j];
+                v = ((hv & 0x7fffu) != 0 && !(hv & 0x8000u)) ? v : 0.f;
+            } else {
+                v = 0.f;
+            }
+            q[r] = f32_to_bf16(v);
+            ds[4 * g + r][j] = q[r];
+            cs += (double)v;
+        }
+        uint16_t *t4 = dT + (int64_t)j * p.ldT + r0 + 4 * g;
+        if (r0 + 4 * g + 3 < p.n) {
+            *reinterpret_cast<uint2 *>(t4) = make_uint2((uint32_t)q[0] | ((uint32_t)q[1] << 16),
+                                                        (uint32_t)q[2] | ((uint32_t)q[3] << 16));
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r0 + 4 * g + r < p.n) t4[r] = q[r];
+        }
+        // the column's sum over the block's 16 rows: each lane's 4, then the 4 lane groups
+        cs += __shfl_xor(cs, 16);
+        cs += __shfl_xor(cs, 32);
+        if (g == 0) bp[(int64_t)blockIdx.x * H + j] = cs;
+    }
+}
+
+template <int H>
+__global__ __launch_bounds__(256) void layer_back_kernel(BackArgs p)
+{
+    __shared__ float dos[kLayerRows][kOutPad];
+    __shared__ __align__(16) uint16_t d2s[kLayerRows][H + 8];
+    __shared__ __align__(16) uint16_t d1s[kLayerRows][H + 8];
+    constexpr int NT = H / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r0 = blockIdx.x * kLayerRows;
+    const int lr = lane & 15, g = lane >> 4;
+    const int c0 = wave * (H / 4);
+    const int D = p.dim;
+    // the inverse coupling's backward, one row per thread
+    if (tid < kLayerRows) {
+        const int b = r0 + tid;
+        for (int c = 0; c < kOutPad; ++c) dos[tid][c] = 0.f;
+        if (b < p.n) {
+            const double inv_n = 1.0 / (double)p.n;
+            for (int i = 0; i < D; ++i) {
+                const int64_t o = (int64_t)b * D + i;
+                if ((p.cond >> i) & 1u) {
+                    p.gy[o] = p.g[o];
+                } else {
+                    const double si = p.s[o], e = exp(-si);
+                    const double dt = -p.g[o] * e;
+                    const double ds = -p.g[o] * p.x[o] + inv_n;
+                    const double dr = ds * (1.0 - (si / 3.0) * (si / 3.0));
+                    p.gy[o] = p.g[o] * e;
+                    dos[tid][i] = (float)dr;
+                    dos[tid][D + i] = (float)dt;
+                }
+            }
+            for (int c = 0; c < kOutPad; ++c) p.doutT[(int64_t)c * p.ldT + b] = f32_to_bf16(dos[tid][c]);
+        }
+    }
+    __syncthreads();
+    if (tid < 2 * D) {
+        double t = 0.0;
+        for (int r = 0; r < kLayerRows; ++r) t += (double)dos[r][tid];
+        p.bp3[(int64_t)blockIdx.x * 2 * D + tid] = t;
+    }
+    // dh2 = dout W3 (K = 2 dim <= 32 in one step), masked by h2 > 0
+    float4_t acc[NT];
+    {
+        bf16x8_t av;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[e] = (__bf16)dos[lr][8 * g + e];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const bf16x8_t bv = ld_bf16x8(p.w3t + (int64_t)(c0 + 16 * t + lr) * kOutPad + 8 * g);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        }
+    }
+    masked_hidden<H>(p, d2s, p.dpreT, p.bp2, acc, p.h2, r0, c0, g, lr);
+    __syncthreads();
+    // dh1 = dpre2 W2 (B(k, j) = W2[k][j] = W2^T[j][k]), masked by h1 > 0
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < H; kk += 32) {
+        const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&d2s[lr][kk + 8 * g]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const bf16x8_t bv = ld_bf16x8(p.w2t + (int64_t)(c0 + 16 * t + lr) * H + kk + 8 * g);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+        }
+    }
+    masked_hidden<H>(p, d1s, p.dpre2T, p.bp1, acc, p.h1, r0, c0, g, lr);
+    __syncthreads();
+    // dxm = dpre1 W1 (B(k, d) = W1[k][d] = W1^T[d][k]), added into gy on the conditioning dims
+    if (wave == 0) {
+        const int col = lr;
+        const bf16x8_t zero8 = {};
+        float4_t o = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < H; kk += 32) {
+            const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&d1s[lr][kk + 8 * g]);
+            const bf16x8_t bv = col < D ? ld_bf16x8(p.w1t + (int64_t)col * H + kk + 8 * g) : zero8;
+            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, o, 0, 0, 0);
+        }
+        if (col < D && ((p.cond >> col) & 1u)) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = r0 + 4 * g + r;
+                if (i < p.n) p.gy[(int64_t)i * D + col] += (double)o[r];
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------- training backward
@@ -509,7 +792,7 @@ __global__ __launch_bounds__(256) void column_part_kernel(int rows, int cols, in
 // the three layers' outputs (b1, b2: rb64 blocks of H each; b3: rb64 blocks
 // of 2D), summed in block order.
 struct GradParts {
-    int D, H, split, rb64, rb64_cap;
+    int D, H, split, rb, rb_cap;        // row blocks of the bias partials (used, allocated)
     int64_t per_layer, n_params, w_layer, b_layer;
     const float *wpart;
     const double *bpart;
@@ -532,16 +815,16 @@ __global__ __launch_bounds__(256) void grad_finish_kernel(GradParts gp, float *_
     if (q < sz1) {
         wr = w, wsz = sz1;
     } else if ((q -= sz1) < H) {
-        br = bp, bcols = H, bn = gp.rb64;
+        br = bp, bcols = H, bn = gp.rb;
     } else if ((q -= H) < sz2) {
         wr = w + kMaxSplit * sz1, wsz = sz2;
     } else if ((q -= sz2) < H) {
-        br = bp + gp.rb64_cap * H, bcols = H, bn = gp.rb64;
+        br = bp + gp.rb_cap * H, bcols = H, bn = gp.rb;
     } else if ((q -= H) < sz3) {
         wr = w + kMaxSplit * (sz1 + sz2), wsz = sz3;
     } else {
         q -= sz3;
-        br = bp + 2 * gp.rb64_cap * H, bcols = 2 * D, bn = gp.rb64;
+        br = bp + 2 * gp.rb_cap * H, bcols = 2 * D, bn = gp.rb;
     }
     if (wr) {
         float v = 0.f;
@@ -664,7 +947,7 @@ struct gw_flow {
     float *wpart = nullptr;
     double *bpart = nullptr;
     int64_t w_layer = 0, b_layer = 0;
-    int rb64_cap = 0;
+    int rb_cap = 0;                      // row blocks the bias partials are sized for (16-row blocks)
 };
 
 namespace {
@@ -744,9 +1027,9 @@ int ensure_batch(gw_flow *f, int64_t n)
     free_batch(f);
     const int64_t c = std::max<int64_t>(n, 256);
     const int64_t D = f->dim, H = f->hidden, L = f->layers;
-    const int rb64 = (int)((c + 63) / 64);
+    const int rb_cap = (int)((c + gw::flow::kLayerRows - 1) / gw::flow::kLayerRows);
     const int64_t w_layer = (int64_t)gw::flow::kMaxSplit * (H * D + H * H + 2 * D * H);
-    const int64_t b_layer = (int64_t)rb64 * (2 * H + 2 * D);
+    const int64_t b_layer = (int64_t)rb_cap * (2 * H + 2 * D);
     const int64_t ldT = (c + 63) / 64 * 64;
     if (alloc(&f->bound, (L + 2) * c * D) || alloc(&f->s_store, L * c * D) || alloc(&f->sum_s, c) ||
         alloc(&f->loss, c) || alloc(&f->g, c * D) || alloc(&f->gy, c * D) || alloc(&f->xm_b, L * c * kInPad) ||
@@ -763,7 +1046,7 @@ int ensure_batch(gw_flow *f, int64_t n)
     f->ldT = ldT;
     f->w_layer = w_layer;
     f->b_layer = b_layer;
-    f->rb64_cap = rb64;
+    f->rb_cap = rb_cap;
     return GW_OK;
 }
 
@@ -797,6 +1080,47 @@ hipError_t mlp_forward(gw_flow *f, int l, int n, bool keep_t, hipStream_t s)
     if ((e = gw::flow::gemm_bf16(g2, s)) != hipSuccess) return e;
     GemmArgs g3{n, 2 * D, H, h2, H, 1, wq + o.w3, 1, H, f->out_f, 2 * D, nullptr, 0, pp + o.b3, 0};
     return gw::flow::gemm_bf16(g3, s);
+}
+
+// Coupling l as one kernel (hidden width 128 or 256), or false when the
+// width has no such kernel and the products run as separate GEMMs.
+bool fused_width(const gw_flow *f) { return f->hidden == 128 || f->hidden == 256; }
+
+hipError_t layer_fused(gw_flow *f, int l, int n, int dir, const double *a, double *y, double *s_out, bool keep_t,
+                       gw::flow::NextMask nm, hipStream_t s)
+{
+    const int D = f->dim, H = f->hidden;
+    const LayerOff o = layer_off(f, l);
+    const uint16_t *wq = f->wb + o.q;
+    const float *pp = f->params + o.p;
+    gw::flow::LayerArgs la;
+    la.n = n;
+    la.dim = D;
+    la.dir = dir;
+    la.cond = f->cond[l];
+    la.xm = f->xm_b + (int64_t)l * f->cap * kInPad;
+    la.w1p = f->wbT + (int64_t)l * f->wbT_stride + (int64_t)D * H + (int64_t)H * H + (int64_t)H * kOutPad;
+    la.w2 = wq + o.w2;
+    la.w3 = wq + o.w3;
+    la.b1 = pp + o.b1;
+    la.b2 = pp + o.b2;
+    la.b3 = pp + o.b3;
+    la.h1 = f->h1_b + (int64_t)l * f->cap * H;
+    la.h2 = f->h2_b + (int64_t)l * f->cap * H;
+    la.h1T = keep_t ? f->h1T + (int64_t)l * H * f->ldT : nullptr;
+    la.h2T = keep_t ? f->h2T + (int64_t)l * H * f->ldT : nullptr;
+    la.ldT = f->ldT;
+    la.a = a;
+    la.y = y;
+    la.sum_s = f->sum_s;
+    la.s_out = s_out;
+    la.nm = nm;
+    const dim3 grid((unsigned)((n + gw::flow::kLayerRows - 1) / gw::flow::kLayerRows));
+    if (H == 256)
+        hipLaunchKernelGGL(gw::flow::layer_kernel<256>, grid, dim3(256), 0, s, la);
+    else
+        hipLaunchKernelGGL(gw::flow::layer_kernel<128>, grid, dim3(256), 0, s, la);
+    return hipGetLastError();
 }
 
 // Where the kernel producing layer l's input writes that layer's masked
@@ -833,10 +1157,15 @@ hipError_t inverse_pass(gw_flow *f, int n, const double *x, bool keep_t, hipStre
                        x, boundary(f, L), f->sum_s, 1, mask_of(f, L - 1, keep_t));
     GW_TRY(hipGetLastError());
     for (int l = L - 1; l >= 0; --l) {
+        double *s_out = f->s_store + (int64_t)l * f->cap * D;
+        if (fused_width(f)) {
+            GW_TRY(layer_fused(f, l, n, -1, boundary(f, l + 1), boundary(f, l), s_out, keep_t,
+                               mask_of(f, l - 1, keep_t), s));
+            continue;
+        }
         GW_TRY(mlp_forward(f, l, n, keep_t, s));
         hipLaunchKernelGGL(gw::flow::coupling_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], -1,
-                           boundary(f, l + 1), f->out_f, boundary(f, l), f->sum_s,
-                           f->s_store + (int64_t)l * f->cap * D, mask_of(f, l - 1, keep_t));
+                           boundary(f, l + 1), f->out_f, boundary(f, l), f->sum_s, s_out, mask_of(f, l - 1, keep_t));
         GW_TRY(hipGetLastError());
     }
     return hipSuccess;
@@ -854,6 +1183,11 @@ hipError_t forward_pass(gw_flow *f, int n, const double *z, hipStream_t s)
                        nullptr, f->ldT);
     GW_TRY(hipGetLastError());
     for (int l = 0; l < L; ++l) {
+        if (fused_width(f)) {
+            GW_TRY(layer_fused(f, l, n, 1, boundary(f, l), boundary(f, l + 1), nullptr, false,
+                               mask_of(f, l + 1, false), s));
+            continue;
+        }
         GW_TRY(mlp_forward(f, l, n, false, s));
         hipLaunchKernelGGL(gw::flow::coupling_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], 1,
                            boundary(f, l), f->out_f, boundary(f, l + 1), f->sum_s, nullptr,
@@ -886,13 +1220,13 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
     // the inverse pass applied couplings L-1 .. 0; go back through 0 .. L-1.
     // Every gradient of layer l is left as partial sums (split-K slices of the
     // weights, row-block sums of the biases) and summed by one kernel at the end.
-    const int rb64 = (n + 63) / 64;
+    const int rb64 = (n + 63) / 64, rb16 = (n + gw::flow::kLayerRows - 1) / gw::flow::kLayerRows;
     for (int l = 0; l < L; ++l) {
         float *wp = f->wpart + l * f->w_layer;
         double *bp = f->bpart + l * f->b_layer;
         float *wp1 = wp, *wp2 = wp + (int64_t)gw::flow::kMaxSplit * H * D,
               *wp3 = wp + (int64_t)gw::flow::kMaxSplit * (H * D + H * H);
-        double *bp1 = bp, *bp2 = bp + (int64_t)f->rb64_cap * H, *bp3 = bp + 2 * (int64_t)f->rb64_cap * H;
+        double *bp1 = bp, *bp2 = bp + (int64_t)f->rb_cap * H, *bp3 = bp + 2 * (int64_t)f->rb_cap * H;
         const uint16_t *h1 = f->h1_b + (int64_t)l * f->cap * H;
         const uint16_t *h2 = f->h2_b + (int64_t)l * f->cap * H;
         const int64_t T = f->ldT;
@@ -901,6 +1235,24 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
         // transposed BF16 weights of the layer: W1^T [D][H], W2^T [H][H], W3^T [H][kOutPad]
         const uint16_t *wt = f->wbT + (int64_t)l * f->wbT_stride;
         const int64_t w2t = (int64_t)D * H, w3t = (int64_t)D * H + (int64_t)H * H;
+        if (fused_width(f)) {
+            gw::flow::BackArgs ba{n, D, f->cond[l], f->g, boundary(f, l), f->s_store + (int64_t)l * f->cap * D, f->gy,
+                                  h1, h2, wt, wt + w2t, wt + w3t, f->doutT, f->dpreT, f->dpre2T, T, bp1, bp2, bp3};
+            const dim3 grid((unsigned)rb16);
+            if (H == 256)
+                hipLaunchKernelGGL(gw::flow::layer_back_kernel<256>, grid, dim3(256), 0, s, ba);
+            else
+                hipLaunchKernelGGL(gw::flow::layer_back_kernel<128>, grid, dim3(256), 0, s, ba);
+            GW_TRY(hipGetLastError());
+            GemmArgs fw3{2 * D, H, n, f->doutT, T, 1, h2T, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split, wp3, 1};
+            GW_TRY(gw::flow::gemm_bf16(fw3, s));
+            GemmArgs fw2{H, H, n, f->dpreT, T, 1, h1T, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split, wp2, 1};
+            GW_TRY(gw::flow::gemm_bf16(fw2, s));
+            GemmArgs fw1{H, D, n, f->dpre2T, T, 1, xmT, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split, wp1, 1};
+            GW_TRY(gw::flow::gemm_bf16(fw1, s));
+            std::swap(f->g, f->gy);      // d loss / d(boundary l + 1)
+            continue;
+        }
         hipLaunchKernelGGL(gw::flow::coupling_inv_backward_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D,
                            f->cond[l], f->g, boundary(f, l), f->s_store + (int64_t)l * f->cap * D, f->dout_b,
                            f->dout_f, f->gy, f->doutT, T);
@@ -942,8 +1294,8 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
         GW_TRY(gw::flow::gemm_bf16(gx, s));
         std::swap(f->g, f->gy);      // d loss / d(boundary l + 1)
     }
-    gw::flow::GradParts parts{D, H, split, rb64, f->rb64_cap, f->per_layer, f->n_params, f->w_layer, f->b_layer,
-                              f->wpart, f->bpart};
+    gw::flow::GradParts parts{D, H, split, fused_width(f) ? rb16 : rb64, f->rb_cap, f->per_layer, f->n_params,
+                              f->w_layer, f->b_layer, f->wpart, f->bpart};
     hipLaunchKernelGGL(gw::flow::grad_finish_kernel, dim3(blocks_for(f->n_params)), dim3(256), 0, s, parts, f->grads);
     return hipGetLastError();
 }
