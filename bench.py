@@ -337,6 +337,9 @@ def flow_problem(spins: bool, precision: str = "fp64"):
     g = w.grid
     dev = torch.device("cuda", 0)
     ws = gw.Workspace(0)
+    # the default likelihood plan: a plan tuned on the box would change the
+    # sums' rounding, and through the accept decisions the chains, from box to box
+    ws.set_tuning(False)
     psd = torch.from_numpy(w.psd).to(dev)
     inj = w.theta_inj.copy()
     zero = torch.zeros((3, g.n_bins), dtype=torch.complex128, device=dev)

@@ -830,11 +830,39 @@ __global__ __launch_bounds__(256) void grad_finish_kernel(GradParts gp, float *_
         float v = 0.f;
         for (int z = 0; z < gp.split; ++z) v += wr[z * wsz + q];
         grads[p] = v;
-    } else {
+    } else if (bn <= 64) {
         double t = 0.0;
         for (int64_t y = 0; y < bn; ++y) t += br[y * bcols + q];
         grads[p] = (float)t;
     }
+    // more row blocks: bias_finish_kernel
+    (void)bcols;
+}
+
+// The biases when their partials come in more than 64 row blocks: one wave
+// per bias element (layer l, then b1, b2, b3), lane k summing the blocks
+// k, k + 64, ... in order, then the 64 lane sums by a fixed butterfly.
+__global__ __launch_bounds__(64) void bias_finish_kernel(GradParts gp, float *__restrict__ grads)
+{
+    const int64_t H = gp.H, D = gp.D, per = 2 * H + 2 * D;
+    const int64_t l = blockIdx.x / per, r = blockIdx.x % per;
+    const double *bp = gp.bpart + l * gp.b_layer;
+    const double *br;
+    int64_t bcols, q, p;
+    const int64_t base = l * gp.per_layer;
+    if (r < H) {
+        br = bp, bcols = H, q = r, p = base + H * D + r;
+    } else if (r < 2 * H) {
+        br = bp + gp.rb_cap * H, bcols = H, q = r - H, p = base + H * D + H + H * H + (r - H);
+    } else {
+        br = bp + 2 * gp.rb_cap * H, bcols = 2 * D, q = r - 2 * H,
+        p = base + H * D + 2 * H + H * H + 2 * D * H + (r - 2 * H);
+    }
+    double t = 0.0;
+    for (int64_t y = threadIdx.x; y < gp.rb; y += 64) t += br[y * bcols + q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (threadIdx.x == 0) grads[p] = (float)t;
 }
 
 // Adam (Kingma & Ba 2015) on FP32 master parameters.
@@ -1297,7 +1325,13 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
     gw::flow::GradParts parts{D, H, split, fused_width(f) ? rb16 : rb64, f->rb_cap, f->per_layer, f->n_params,
                               f->w_layer, f->b_layer, f->wpart, f->bpart};
     hipLaunchKernelGGL(gw::flow::grad_finish_kernel, dim3(blocks_for(f->n_params)), dim3(256), 0, s, parts, f->grads);
-    return hipGetLastError();
+    GW_TRY(hipGetLastError());
+    if (parts.rb > 64) {
+        hipLaunchKernelGGL(gw::flow::bias_finish_kernel, dim3((unsigned)(L * (2 * H + 2 * D))), dim3(64), 0, s, parts,
+                           f->grads);
+        GW_TRY(hipGetLastError());
+    }
+    return hipSuccess;
 }
 
 hipError_t refresh_bf16(gw_flow *f, hipStream_t s)

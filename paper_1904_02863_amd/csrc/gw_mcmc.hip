@@ -254,21 +254,41 @@ __global__ __launch_bounds__(256) void adapt_chol_kernel(int dim, int64_t n, con
     __shared__ double red[256];
     __shared__ double mean[kMaxDim];
     __shared__ double c[kMaxDim * kMaxDim];
-    for (int i = 0; i < dim; ++i) {
-        double acc = 0.0;
-        for (int64_t r = threadIdx.x; r < n; r += 256) acc += x[r * dim + i];
-        const double total = block_sum256(acc, red);
+    // every column's sum in one pass over the rows (each thread its rows
+    // tid, tid + 256, ... in order), then the block sums column by column
+    double acc[kMaxDim];
+#pragma unroll
+    for (int i = 0; i < kMaxDim; ++i) acc[i] = 0.0;
+    for (int64_t r = threadIdx.x; r < n; r += 256)
+#pragma unroll
+        for (int i = 0; i < kMaxDim; ++i)
+            if (i < dim) acc[i] += x[r * dim + i];
+#pragma unroll
+    for (int i = 0; i < kMaxDim; ++i) {
+        if (i >= dim) break;
+        const double total = block_sum256(acc[i], red);
         if (threadIdx.x == 0) mean[i] = total / (double)n;
     }
     __syncthreads();
-    for (int i = 0; i < dim; ++i)
-        for (int j = 0; j <= i; ++j) {
-            double acc = 0.0;
-            for (int64_t r = threadIdx.x; r < n; r += 256)
-                acc += (x[r * dim + i] - mean[i]) * (x[r * dim + j] - mean[j]);
-            const double total = block_sum256(acc, red);
+    // row i of the covariance (j <= i) in one pass over the rows, the same
+    // per-thread order as the means
+    for (int i = 0; i < dim; ++i) {
+#pragma unroll
+        for (int j = 0; j < kMaxDim; ++j) acc[j] = 0.0;
+        const double mi = mean[i];
+        for (int64_t r = threadIdx.x; r < n; r += 256) {
+            const double di = x[r * dim + i] - mi;
+#pragma unroll
+            for (int j = 0; j < kMaxDim; ++j)
+                if (j <= i) acc[j] += di * (x[r * dim + j] - mean[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < kMaxDim; ++j) {
+            if (j > i) break;
+            const double total = block_sum256(acc[j], red);
             if (threadIdx.x == 0) c[i * kMaxDim + j] = total / (double)(n > 1 ? n - 1 : 1);
         }
+    }
     if (threadIdx.x != 0) return;
     if (mean_out)
         for (int i = 0; i < dim; ++i) mean_out[i] = mean[i];

@@ -124,7 +124,11 @@ def _full_size_problem(gw, torch, spins):
     lo, hi, p_inj = sampler.injection_box(inj)
     prob = sampler.Problem(g, w.tensors, w.vertices, torch.from_numpy(data).to(dev),
                            torch.from_numpy(np.ascontiguousarray(w.psd)).to(dev), lo, hi, spins=spins)
-    return prob, p_inj, gw.Workspace(0)
+    ws = gw.Workspace(0)
+    # the default likelihood plan: a plan tuned on the box would change the
+    # sums' rounding, and through the accept decisions the chains, from box to box
+    ws.set_tuning(False)
+    return prob, p_inj, ws
 
 
 def test_learned_proposal_at_full_size_with_aligned_spins(capsys):
