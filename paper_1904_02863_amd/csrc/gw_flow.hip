@@ -145,19 +145,20 @@ __device__ __forceinline__ void store_chunk(uint16_t (*lds)[kLdsK], int kc, cons
 // K of the chunk starting at k0: up to kChunkK, rounded up to the 32 of one product step.
 __device__ __forceinline__ int chunk_len(int k0, int k_hi) { return min(kChunkK, (k_hi - k0 + 31) / 32 * 32); }
 
+// The output tile (bx, by) of K slice bz; LDS and barriers are the block's.
 template <bool A_KC, bool B_KC>
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int vec_a, int vec_b)
+__device__ __forceinline__ void gemm_tile(const GemmArgs &g, int vec_a, int vec_b, int bx, int by, int bz)
 {
     __shared__ __align__(16) uint16_t as[kTileMN][kLdsK];
     __shared__ __align__(16) uint16_t bs[kTileMN][kLdsK];
     __shared__ double colred[2][4][kTileMN];   // column sums: [row half][lane group][tile column]
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int row0 = blockIdx.y * kTileMN, col0 = blockIdx.x * kTileMN;
+    const int row0 = by * kTileMN, col0 = bx * kTileMN;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     // K slice of this block (the whole range unless split), a multiple of 32
     const int ks = ((g.K + g.split - 1) / g.split + 31) / 32 * 32;
-    const int k_lo = (int)blockIdx.z * ks, k_hi = min(g.K, k_lo + ks);
+    const int k_lo = bz * ks, k_hi = min(g.K, k_lo + ks);
     float4_t acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int vec_a, i
                 v[r] = acc[a][b][r];
                 if (i >= g.M) continue;
                 if (to_partial) {
-                    g.partial[((int64_t)blockIdx.z * g.M + i) * g.N + j] = v[r];
+                    g.partial[((int64_t)bz * g.M + i) * g.N + j] = v[r];
                     continue;
                 }
                 if (g.bias) v[r] += bias[b];
@@ -262,9 +263,38 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int vec_a, i
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) t += colred[h][q][tid];
-            g.col_part[(int64_t)blockIdx.y * g.N + j] = t;
+            g.col_part[(int64_t)by * g.N + j] = t;
         }
     }
+}
+
+template <bool A_KC, bool B_KC>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int vec_a, int vec_b)
+{
+    gemm_tile<A_KC, B_KC>(g, vec_a, vec_b, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Up to three independent products, k-contiguous operands, in one launch:
+// blocks [start[p], start[p + 1]) work on product p, tile x fastest, then
+// tile y, then K slice.
+struct GemmGroup {
+    GemmArgs g0, g1, g2;
+    int va[3], vb[3], gx[3], gy[3], start[4];
+};
+
+__global__ __launch_bounds__(256) void gemm_group_kernel(GemmGroup gg)
+{
+    const int b = blockIdx.x;
+    const int p = (b >= gg.start[1]) + (b >= gg.start[2]);
+    const int local = b - gg.start[p];
+    const int bx = local % gg.gx[p], rest = local / gg.gx[p];
+    const int by = rest % gg.gy[p], bz = rest / gg.gy[p];
+    if (p == 0)
+        gemm_tile<true, true>(gg.g0, gg.va[0], gg.vb[0], bx, by, bz);
+    else if (p == 1)
+        gemm_tile<true, true>(gg.g1, gg.va[1], gg.vb[1], bx, by, bz);
+    else
+        gemm_tile<true, true>(gg.g2, gg.va[2], gg.vb[2], bx, by, bz);
 }
 
 // Sums the split-K slices in slice order, then bias, ReLU and the outputs.
@@ -287,6 +317,33 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g)
 static bool vector_ok(const uint16_t *p, int64_t s_contig, int64_t s_other)
 {
     return s_contig == 1 && s_other % 8 == 0 && (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+}
+
+// Three products with k-contiguous operands (sa_k = sb_k = 1) in one
+// launch; each as gemm_bf16 would run it (split-K with defer, no reduce kernel).
+hipError_t gemm_bf16_group3(const GemmArgs &a, const GemmArgs &b, const GemmArgs &c, hipStream_t stream)
+{
+    const GemmArgs *gs[3] = {&a, &b, &c};
+    GemmGroup gg;
+    gg.g0 = a;
+    gg.g1 = b;
+    gg.g2 = c;
+    int start = 0;
+    for (int p = 0; p < 3; ++p) {
+        const GemmArgs &g = *gs[p];
+        if (g.M <= 0 || g.N <= 0 || g.sa_k != 1 || g.sb_k != 1 || g.split < 1 || g.split > kMaxSplit ||
+            ((g.split > 1 || g.defer) && !g.partial) || (g.split == 1 && !g.defer))
+            return hipErrorInvalidValue;
+        gg.va[p] = vector_ok(g.A, g.sa_k, g.sa_i);
+        gg.vb[p] = vector_ok(g.B, g.sb_k, g.sb_j);
+        gg.gx[p] = (g.N + kTileMN - 1) / kTileMN;
+        gg.gy[p] = (g.M + kTileMN - 1) / kTileMN;
+        gg.start[p] = start;
+        start += gg.gx[p] * gg.gy[p] * g.split;
+    }
+    gg.start[3] = start;
+    hipLaunchKernelGGL(gemm_group_kernel, dim3((unsigned)start), dim3(256), 0, stream, gg);
+    return hipGetLastError();
 }
 
 hipError_t gemm_bf16(const GemmArgs &g, hipStream_t stream)
@@ -459,6 +516,34 @@ __device__ __forceinline__ void store_hidden(const LayerArgs &p, uint16_t (*hs)[
     }
 }
 
+// acc[t] += rows of xs (LDS, [16][H + 8]) times the H x H matrix w read as
+// B(k, j) = w[j H + k] (16-byte fragments from global memory), for this
+// wave's columns c0 + 16 t + lr; the next k step's fragments are loaded
+// while the current step's products run.
+template <int H>
+__device__ __forceinline__ void products_from_lds(float4_t (&acc)[H / 64], const uint16_t (*xs)[H + 8],
+                                                  const uint16_t *__restrict__ w, int c0, int g, int lr)
+{
+    constexpr int NT = H / 64;
+    bf16x8_t bv[NT], bn[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bv[t] = ld_bf16x8(w + (int64_t)(c0 + 16 * t + lr) * H + 8 * g);
+#pragma unroll
+    for (int kk = 0; kk < H; kk += 32) {
+        if (kk + 32 < H) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) bn[t] = ld_bf16x8(w + (int64_t)(c0 + 16 * t + lr) * H + kk + 32 + 8 * g);
+        }
+        const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&xs[lr][kk + 8 * g]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[t], acc[t], 0, 0, 0);
+        if (kk + 32 < H) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) bv[t] = bn[t];
+        }
+    }
+}
+
 template <int H>
 __global__ __launch_bounds__(256) void layer_kernel(LayerArgs p)
 {
@@ -487,15 +572,7 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerArgs p)
     // h2 = relu(h1 W2^T + b2), K = H
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = float4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kk = 0; kk < H; kk += 32) {
-        const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&h1s[lr][kk + 8 * g]);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const bf16x8_t bv = ld_bf16x8(p.w2 + (int64_t)(c0 + 16 * t + lr) * H + kk + 8 * g);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
-        }
-    }
+    products_from_lds<H>(acc, h1s, p.w2, c0, g, lr);
     store_hidden<H>(p, h2s, p.h2, p.h2T, acc, p.b2, r0, c0, g, lr);
     __syncthreads();
     // out = h2 W3^T + b3: 2 dim <= 32 columns, one 16-column tile for each of waves 0 and 1
@@ -679,15 +756,7 @@ __global__ __launch_bounds__(256) void layer_back_kernel(BackArgs p)
     // dh1 = dpre2 W2 (B(k, j) = W2[k][j] = W2^T[j][k]), masked by h1 > 0
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = float4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kk = 0; kk < H; kk += 32) {
-        const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&d2s[lr][kk + 8 * g]);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const bf16x8_t bv = ld_bf16x8(p.w2t + (int64_t)(c0 + 16 * t + lr) * H + kk + 8 * g);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
-        }
-    }
+    products_from_lds<H>(acc, d2s, p.w2t, c0, g, lr);
     masked_hidden<H>(p, d1s, p.dpre2T, p.bp1, acc, p.h1, r0, c0, g, lr);
     __syncthreads();
     // dxm = dpre1 W1 (B(k, d) = W1[k][d] = W1^T[d][k]), added into gy on the conditioning dims
@@ -1272,12 +1341,11 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
             else
                 hipLaunchKernelGGL(gw::flow::layer_back_kernel<128>, grid, dim3(256), 0, s, ba);
             GW_TRY(hipGetLastError());
+            // the coupling's three weight gradients in one launch
             GemmArgs fw3{2 * D, H, n, f->doutT, T, 1, h2T, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split, wp3, 1};
-            GW_TRY(gw::flow::gemm_bf16(fw3, s));
             GemmArgs fw2{H, H, n, f->dpreT, T, 1, h1T, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split, wp2, 1};
-            GW_TRY(gw::flow::gemm_bf16(fw2, s));
             GemmArgs fw1{H, D, n, f->dpre2T, T, 1, xmT, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split, wp1, 1};
-            GW_TRY(gw::flow::gemm_bf16(fw1, s));
+            GW_TRY(gw::flow::gemm_bf16_group3(fw3, fw2, fw1, s));
             std::swap(f->g, f->gy);      // d loss / d(boundary l + 1)
             continue;
         }

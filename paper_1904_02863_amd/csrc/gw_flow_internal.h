@@ -56,6 +56,9 @@ struct GemmArgs {
 constexpr int kMaxSplit = 16;
 
 hipError_t gemm_bf16(const GemmArgs &g, hipStream_t stream);
+// Three products in one launch (k-contiguous operands, split-K slices left
+// in their partial buffers).
+hipError_t gemm_bf16_group3(const GemmArgs &a, const GemmArgs &b, const GemmArgs &c, hipStream_t stream);
 
 }  // namespace flow
 }  // namespace gw
