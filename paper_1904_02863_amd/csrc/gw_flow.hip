@@ -550,6 +550,7 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerArgs p)
     __shared__ __align__(16) uint16_t h1s[kLayerRows][H + 8];
     __shared__ __align__(16) uint16_t h2s[kLayerRows][H + 8];
     __shared__ float outs[kLayerRows][kOutPad];
+    __shared__ double sdet[kLayerRows][16];
     constexpr int NT = H / 64;            // 16-column tiles per wave
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r0 = blockIdx.x * kLayerRows;
@@ -557,6 +558,14 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerArgs p)
     const int c0 = wave * (H / 4);
     const bool row_ok = r0 + lr < p.n;
     const bf16x8_t zero8 = {};
+    // the output layer's weight fragments (waves 0 and 1), loaded now so that
+    // they have arrived by the third product
+    const int n_out = 2 * p.dim;
+    const int ocol = 16 * (wave & 1) + lr;
+    bf16x8_t w3f[H / 32];
+#pragma unroll
+    for (int k = 0; k < H / 32; ++k)
+        w3f[k] = (wave < 2 && ocol < n_out) ? ld_bf16x8(p.w3 + (int64_t)ocol * H + 32 * k + 8 * g) : zero8;
     // h1 = relu(xm W1^T + b1), K = kInPad padded to 32 by zeros
     float4_t acc[NT];
     {
@@ -576,23 +585,55 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerArgs p)
     store_hidden<H>(p, h2s, p.h2, p.h2T, acc, p.b2, r0, c0, g, lr);
     __syncthreads();
     // out = h2 W3^T + b3: 2 dim <= 32 columns, one 16-column tile for each of waves 0 and 1
-    const int n_out = 2 * p.dim;
     if (wave < 2) {
-        const int col = 16 * wave + lr;
+        const int col = ocol;
         float4_t o = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kk = 0; kk < H; kk += 32) {
-            const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&h2s[lr][kk + 8 * g]);
-            const bf16x8_t bv = col < n_out ? ld_bf16x8(p.w3 + (int64_t)col * H + kk + 8 * g) : zero8;
-            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, o, 0, 0, 0);
+        for (int k = 0; k < H / 32; ++k) {
+            const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&h2s[lr][32 * k + 8 * g]);
+            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w3f[k], o, 0, 0, 0);
         }
         const float bc = col < n_out ? p.b3[col] : 0.f;
 #pragma unroll
         for (int r = 0; r < 4; ++r) outs[4 * g + r][col] = o[r] + bc;
     }
     __syncthreads();
-    const int b = r0 + tid;
-    if (tid < kLayerRows && b < p.n) coupling_row(b, p.dim, p.cond, p.dir, p.a, outs[tid], p.y, p.sum_s, p.s_out, p.nm);
+    // the coupling: thread (row, i) = (tid / 16, tid % 16) takes dimension i
+    // of a row, then each row's log-determinant terms are added in dimension
+    // order by one thread (the order of the row-at-a-time kernel)
+    {
+        const int rr = tid >> 4, i = tid & 15;
+        const int b = r0 + rr;
+        double sv = 0.0;
+        if (b < p.n && i < p.dim) {
+            const double ai = p.a[(int64_t)b * p.dim + i];
+            double yi = ai;
+            if (!((p.cond >> i) & 1u)) {
+                const double r = (double)outs[rr][i];
+                const double t = (double)outs[rr][p.dim + i];
+                sv = 3.0 * tanh(r / 3.0);
+                yi = p.dir > 0 ? ai * exp(sv) + t : (ai - t) * exp(-sv);
+            }
+            p.y[(int64_t)b * p.dim + i] = yi;
+            if (p.s_out) p.s_out[(int64_t)b * p.dim + i] = sv;
+            if (p.nm.xm) {
+                const uint16_t v = ((p.nm.cond >> i) & 1u) ? f32_to_bf16((float)yi) : (uint16_t)0;
+                p.nm.xm[(int64_t)b * kInPad + i] = v;
+                if (p.nm.xmT) p.nm.xmT[i * p.nm.ldT + b] = v;
+            }
+        } else if (b < p.n && p.nm.xm) {
+            p.nm.xm[(int64_t)b * kInPad + i] = 0;         // dimensions past dim of the next input
+            if (p.nm.xmT) p.nm.xmT[i * p.nm.ldT + b] = 0;
+        }
+        sdet[rr][i] = sv;
+    }
+    __syncthreads();
+    if (tid < kLayerRows && r0 + tid < p.n) {
+        double acc = 0.0;
+        for (int i = 0; i < p.dim; ++i)
+            if (!((p.cond >> i) & 1u)) acc += sdet[tid][i];
+        p.sum_s[r0 + tid] += acc;
+    }
 }
 
 // Affine normalisation around the coupling stack: forward x = mu + sigma u,
@@ -710,27 +751,42 @@ __global__ __launch_bounds__(256) void layer_back_kernel(BackArgs p)
     const int lr = lane & 15, g = lane >> 4;
     const int c0 = wave * (H / 4);
     const int D = p.dim;
-    // the inverse coupling's backward, one row per thread
-    if (tid < kLayerRows) {
-        const int b = r0 + tid;
-        for (int c = 0; c < kOutPad; ++c) dos[tid][c] = 0.f;
-        if (b < p.n) {
-            const double inv_n = 1.0 / (double)p.n;
-            for (int i = 0; i < D; ++i) {
-                const int64_t o = (int64_t)b * D + i;
-                if ((p.cond >> i) & 1u) {
-                    p.gy[o] = p.g[o];
-                } else {
-                    const double si = p.s[o], e = exp(-si);
-                    const double dt = -p.g[o] * e;
-                    const double ds = -p.g[o] * p.x[o] + inv_n;
-                    const double dr = ds * (1.0 - (si / 3.0) * (si / 3.0));
-                    p.gy[o] = p.g[o] * e;
-                    dos[tid][i] = (float)dr;
-                    dos[tid][D + i] = (float)dt;
-                }
+    const bf16x8_t zero8 = {};
+    // weight fragments of the first and the last product, loaded now so
+    // that they have arrived when needed
+    bf16x8_t w3f[NT], w1f[H / 32];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) w3f[t] = ld_bf16x8(p.w3t + (int64_t)(c0 + 16 * t + lr) * kOutPad + 8 * g);
+#pragma unroll
+    for (int k = 0; k < H / 32; ++k)
+        w1f[k] = (wave == 0 && lr < D) ? ld_bf16x8(p.w1t + (int64_t)lr * H + 32 * k + 8 * g) : zero8;
+    // the inverse coupling's backward: thread (row, i) = (tid / 16, tid % 16)
+    // takes dimension i of a row (dout columns i and D + i)
+    {
+        const int rr = tid >> 4, i = tid & 15;
+        const int b = r0 + rr;
+        dos[rr][i] = 0.f;
+        dos[rr][16 + i] = 0.f;
+        __syncthreads();
+        if (b < p.n && i < D) {
+            const int64_t o = (int64_t)b * D + i;
+            if ((p.cond >> i) & 1u) {
+                p.gy[o] = p.g[o];
+            } else {
+                const double inv_n = 1.0 / (double)p.n;
+                const double si = p.s[o], e = exp(-si);
+                const double dt = -p.g[o] * e;
+                const double ds = -p.g[o] * p.x[o] + inv_n;
+                const double dr = ds * (1.0 - (si / 3.0) * (si / 3.0));
+                p.gy[o] = p.g[o] * e;
+                dos[rr][i] = (float)dr;
+                dos[rr][D + i] = (float)dt;
             }
-            for (int c = 0; c < kOutPad; ++c) p.doutT[(int64_t)c * p.ldT + b] = f32_to_bf16(dos[tid][c]);
+        }
+        __syncthreads();
+        if (b < p.n) {
+            p.doutT[(int64_t)i * p.ldT + b] = f32_to_bf16(dos[rr][i]);
+            p.doutT[(int64_t)(16 + i) * p.ldT + b] = f32_to_bf16(dos[rr][16 + i]);
         }
     }
     __syncthreads();
@@ -746,10 +802,8 @@ __global__ __launch_bounds__(256) void layer_back_kernel(BackArgs p)
 #pragma unroll
         for (int e = 0; e < 8; ++e) av[e] = (__bf16)dos[lr][8 * g + e];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const bf16x8_t bv = ld_bf16x8(p.w3t + (int64_t)(c0 + 16 * t + lr) * kOutPad + 8 * g);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-        }
+        for (int t = 0; t < NT; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w3f[t], float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
     }
     masked_hidden<H>(p, d2s, p.dpreT, p.bp2, acc, p.h2, r0, c0, g, lr);
     __syncthreads();
@@ -762,13 +816,11 @@ __global__ __launch_bounds__(256) void layer_back_kernel(BackArgs p)
     // dxm = dpre1 W1 (B(k, d) = W1[k][d] = W1^T[d][k]), added into gy on the conditioning dims
     if (wave == 0) {
         const int col = lr;
-        const bf16x8_t zero8 = {};
         float4_t o = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kk = 0; kk < H; kk += 32) {
-            const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&d1s[lr][kk + 8 * g]);
-            const bf16x8_t bv = col < D ? ld_bf16x8(p.w1t + (int64_t)col * H + kk + 8 * g) : zero8;
-            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, o, 0, 0, 0);
+        for (int k = 0; k < H / 32; ++k) {
+            const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&d1s[lr][32 * k + 8 * g]);
+            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w1f[k], o, 0, 0, 0);
         }
         if (col < D && ((p.cond >> col) & 1u)) {
 #pragma unroll
