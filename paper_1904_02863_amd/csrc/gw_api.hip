@@ -361,11 +361,15 @@ int lnl_enqueue(gw_workspace *ws, char *base, const LnlLayout &l, const gw::Tile
     else
         e = gw::launch_event_tables(grid, eb.tab1, eb.tab2, stream);
     if (e != hipSuccess) return hip_fail(e, "event tables");
-    if ((e = gw::launch_event_data(grid, n_det, data, psd, eb, flags, stream)) != hipSuccess)
-        return hip_fail(e, "event data");
-    if ((e = gw::launch_sample_prep(grid, n_samples, n_param, n_det, false, isco, geom, theta, rec, stream)) !=
-        hipSuccess)
-        return hip_fail(e, "sample prep");
+    gw::SamplePrep sp;
+    sp.n_samples = n_samples;
+    sp.n_param = n_param;
+    sp.isco = isco ? 1 : 0;
+    sp.geom = geom;
+    sp.theta = theta;
+    sp.records = rec;
+    if ((e = gw::launch_event_data(grid, n_det, data, psd, eb, flags, &sp, stream)) != hipSuccess)
+        return hip_fail(e, "event data and sample prep");
     if (form == gw::kFormSplitIsco && (e = gw::launch_isco_limit(n_samples, rec, eb.k_limit, stream)) != hipSuccess)
         return hip_fail(e, "template-end limit");
     hipEvent_t t_start = nullptr, t_stop = nullptr;

@@ -160,10 +160,23 @@ struct EventBuffers {
 // ---- launchers (gw_kernels.hip); all enqueue on `stream` and return the launch status ----
 hipError_t launch_event_tables(const gw_grid &grid, Tab1 *tab1, Tab2 *tab2, hipStream_t stream);
 
+// The sample records of a likelihood call (one detector channel each), when
+// launch_event_data prepares them in its own launch; isco: K_s from the
+// template end (else n_bins - 1).
+struct SamplePrep {
+    int64_t n_samples;
+    int n_param;
+    int isco;
+    DetGeom geom;
+    const double *theta;
+    double *records;
+};
+
 // D, the event sums and, as `flags` ask, the direct-form tables and the
-// prefix sums of a^2/S.
+// prefix sums of a^2/S; with sp, the sample records too, in the launch that
+// computes D (the two share no data).
 hipError_t launch_event_data(const gw_grid &grid, int n_det, const gw_c128 *data, const double *psd,
-                             const EventBuffers &eb, unsigned flags, hipStream_t stream);
+                             const EventBuffers &eb, unsigned flags, const SamplePrep *sp, hipStream_t stream);
 
 // Per-sample records; with isco, K_s from the template end (else n_bins - 1).
 hipError_t launch_sample_prep(const gw_grid &grid, int64_t n_samples, int n_param, int n_out, bool polarisations,

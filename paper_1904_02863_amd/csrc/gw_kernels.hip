@@ -230,14 +230,6 @@ __global__ __launch_bounds__(kBlock) void event_tables_kernel(double f_low, doub
         bin_tables(f_low, df, k, tab1, tab2);
 }
 
-// One block per 256 consecutive bins.
-__global__ __launch_bounds__(kBlock) void event_data_kernel(PrepView v, int direct, int norm,
-                                                             double *__restrict__ partials)
-{
-    __shared__ double red[kBlock];
-    prep_block(v, blockIdx.x, direct != 0, norm != 0, red, partials + (int64_t)blockIdx.x * kPrepPerDet * v.n_det);
-}
-
 // Block j: sums[j] = the event-wide sum of quantity j (kPrepPerDet n_det blocks).
 // Also zeroes the tile kernel's work-queue counters when there are any.
 __global__ __launch_bounds__(kBlock) void event_sums_kernel(int n_blocks, int n_det,
@@ -477,6 +469,26 @@ __global__ __launch_bounds__(kBlock) void sample_prep_kernel(double f_low, doubl
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= n_samples) return;
     prep_sample(f_low, df, n_bins, s, n_samples, n_param, n_out, polarisations != 0, isco != 0, geom, theta, rec);
+}
+
+// One block per 256 consecutive bins, after sample_blocks blocks of 256
+// samples each (sample records, when sample_blocks > 0).  The two parts share
+// no data, so one launch runs them side by side; the sample blocks come
+// first, since each of their threads has the longer serial work.
+__global__ __launch_bounds__(kBlock) void event_data_kernel(PrepView v, int direct, int norm,
+                                                             double *__restrict__ partials, int sample_blocks,
+                                                             double f_low, SamplePrep sp)
+{
+    if ((int)blockIdx.x < sample_blocks) {
+        const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+        if (s < sp.n_samples)
+            prep_sample(f_low, v.df, v.n_bins, s, sp.n_samples, sp.n_param, v.n_det, false, sp.isco != 0, sp.geom,
+                        sp.theta, sp.records);
+        return;
+    }
+    __shared__ double red[kBlock];
+    const int64_t b = (int64_t)blockIdx.x - sample_blocks;
+    prep_block(v, b, direct != 0, norm != 0, red, partials + b * kPrepPerDet * v.n_det);
 }
 
 // *k_limit = 1 + the largest K_s of the batch (one block).
@@ -937,7 +949,7 @@ hipError_t launch_event_tables(const gw_grid &grid, Tab1 *tab1, Tab2 *tab2, hipS
 }
 
 hipError_t launch_event_data(const gw_grid &grid, int n_det, const gw_c128 *data, const double *psd,
-                             const EventBuffers &eb, unsigned flags, hipStream_t stream)
+                             const EventBuffers &eb, unsigned flags, const SamplePrep *sp, hipStream_t stream)
 {
     PrepView v;
     v.n_bins = grid.n_bins;
@@ -950,7 +962,10 @@ hipError_t launch_event_data(const gw_grid &grid, int n_det, const gw_c128 *data
     v.edir = eb.edir;
     v.vdir = eb.vdir;
     const int direct = (flags & GW_FLAG_DIRECT) ? 1 : 0, norm = (flags & GW_FLAG_ADD_NORM) ? 1 : 0;
-    hipLaunchKernelGGL(event_data_kernel, dim3(eb.prep_blocks), dim3(kBlock), 0, stream, v, direct, norm, eb.prep);
+    SamplePrep none{};
+    const int sample_blocks = sp ? (int)grid_blocks(sp->n_samples, 1 << 30) : 0;
+    hipLaunchKernelGGL(event_data_kernel, dim3(eb.prep_blocks + sample_blocks), dim3(kBlock), 0, stream, v, direct,
+                       norm, eb.prep, sample_blocks, grid.f_low, sp ? *sp : none);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(event_sums_kernel, dim3(kPrepPerDet * n_det), dim3(kBlock), 0, stream, eb.prep_blocks, n_det,
