@@ -123,6 +123,20 @@ def _evaluate(problem: Problem, x, buf: _Buffers, ws: Workspace):
               workspace=ws, precision=problem.precision)
 
 
+def _records(torch, n_steps: int, record_every: int, track, x):
+    """Device array for the records of the first `track` chains every
+    record_every steps, or None when nothing is recorded."""
+    n_records = n_steps // record_every if record_every else 0
+    if n_records == 0:
+        return None
+    rows = x[:track].shape[0]
+    return torch.empty((n_records, rows, x.shape[1]), dtype=x.dtype, device=x.device)
+
+
+def _host(records):
+    return None if records is None else records.cpu().numpy()
+
+
 def _device_chol(chol, device):
     import torch
     if isinstance(chol, torch.Tensor):
@@ -163,8 +177,9 @@ def run_random_walk(problem: Problem, state: ChainState, n_steps: int, seed: int
     a Robbins-Monro step moves toward the acceptance rate target_accept over
     the last window (0.234, the optimum of Roberts, Gelman & Gilks 1997, by
     default).  Records the first record_track chains every record_every
-    steps (host copies) and collects all chains every collect_every steps
-    into a device array.  Returns (records [n_records, track, dim] or None,
+    steps and collects all chains every collect_every steps, both into device
+    arrays (the records are copied to the host once, after the last step, so
+    that recording never makes the host wait for the GPU).  Returns (records [n_records, track, dim] or None,
     acceptance rate, seconds, final Cholesky factor (device), collected
     [n_collect * n_chains, dim] on the device or None).  progress, if given,
     is called with the number of steps done every 10,000 steps."""
@@ -173,7 +188,7 @@ def run_random_walk(problem: Problem, state: ChainState, n_steps: int, seed: int
     dev = state.x.device
     buf = _Buffers(torch, n, dim, dev, problem.theta_cols)
     chol_t = _device_chol(chol, dev)
-    records = []
+    records = _records(torch, n_steps, record_every, record_track, state.x)
     n_collect = n_steps // collect_every if collect_every else 0
     collected = torch.empty((n_collect * n, dim), dtype=torch.float64, device=dev) if n_collect else None
     log_scale, window_start = 0.0, 0
@@ -191,8 +206,8 @@ def run_random_walk(problem: Problem, state: ChainState, n_steps: int, seed: int
             window_start = accepted
             log_scale = float(np.clip(log_scale + 2.0 * (rate - target_accept), -8.0, 2.0))
             mcmc_adapt_chol(state.x, scale=math.exp(log_scale), out=chol_t)
-        if record_every and (i + 1) % record_every == 0:
-            records.append(state.x[:record_track].cpu().numpy())
+        if records is not None and (i + 1) % record_every == 0:
+            records[(i + 1) // record_every - 1].copy_(state.x[:record_track])
         if collect_every and (i + 1) % collect_every == 0:
             k = (i + 1) // collect_every - 1
             collected[k * n:(k + 1) * n].copy_(state.x)
@@ -201,7 +216,7 @@ def run_random_walk(problem: Problem, state: ChainState, n_steps: int, seed: int
     torch.cuda.synchronize()
     seconds = time.perf_counter() - t0
     rate = buf.accepted(buf.total) / (n * max(n_steps, 1))
-    return (np.stack(records) if records else None), rate, seconds, chol_t, collected
+    return _host(records), rate, seconds, chol_t, collected
 
 
 # ---------------------------------------------------------------- flow
@@ -294,7 +309,8 @@ def run_flow_mh(problem: Problem, state: ChainState, flow: Flow, n_steps: int, s
     chol_t = _device_chol(chol, dev)
     flow_mode = torch.zeros(n, dtype=torch.int32, device=dev)
     flow.inverse(state.x, z_out=buf.z, logq_out=state.logq)
-    records, rw_steps, flow_steps, use_flow = [], 0, 0, True
+    records = _records(torch, n_steps, record_every, record_track, state.x)
+    rw_steps, flow_steps, use_flow = 0, 0, True
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(n_steps):
@@ -316,12 +332,12 @@ def run_flow_mh(problem: Problem, state: ChainState, flow: Flow, n_steps: int, s
             if flow_steps == window and buf.accepted(buf.window) < threshold * n * window:
                 use_flow = False
         state.step += 1
-        if record_every and (i + 1) % record_every == 0:
-            records.append(state.x[:record_track].cpu().numpy())
+        if records is not None and (i + 1) % record_every == 0:
+            records[(i + 1) // record_every - 1].copy_(state.x[:record_track])
     torch.cuda.synchronize()
     seconds = time.perf_counter() - t0
     rate = buf.accepted(buf.total) / (n * max(n_steps, 1))
-    return (np.stack(records) if records else None), rate, seconds, rw_steps / max(n_steps, 1)
+    return _host(records), rate, seconds, rw_steps / max(n_steps, 1)
 
 
 def compare_samplers(problem: Problem, p_inj: np.ndarray, ws: Workspace, n_chains: int = 4096, burn: int = 4000,
