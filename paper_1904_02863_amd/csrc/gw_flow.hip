@@ -485,13 +485,13 @@ __device__ __forceinline__ bf16x8_t ld_bf16x8(const uint16_t *p) { return *reint
 
 template <int H>
 __device__ __forceinline__ void store_hidden(const LayerArgs &p, uint16_t (*hs)[H + 8], uint16_t *hg, uint16_t *hT,
-                                             const float4_t (&acc)[H / 64], const float *__restrict__ bias, int r0,
+                                             const float4_t (&acc)[H / 64], const float (&bias)[H / 64], int r0,
                                              int c0, int g, int lr)
 {
 #pragma unroll
     for (int t = 0; t < H / 64; ++t) {
         const int j = c0 + 16 * t + lr;
-        const float bj = bias[j];
+        const float bj = bias[t];
         uint16_t q[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -516,31 +516,33 @@ __device__ __forceinline__ void store_hidden(const LayerArgs &p, uint16_t (*hs)[
     }
 }
 
-// acc[t] += rows of xs (LDS, [16][H + 8]) times the H x H matrix w read as
-// B(k, j) = w[j H + k] (16-byte fragments from global memory), for this
-// wave's columns c0 + 16 t + lr; the next k step's fragments are loaded
-// while the current step's products run.
+// The fragments of the H x H matrix w read as B(k, j) = w[j H + k] that this
+// wave's columns c0 + 16 t + lr take in the k step kk = 32 k: f[t][k], 16
+// bytes each from global memory.  The coupling kernels load them all at
+// their start (128 VGPRs at H = 256; a block of 4 waves runs one wave per
+// SIMD), so that the loads overlap the first product instead of making each
+// k step of the middle one wait on L2.
+template <int H>
+__device__ __forceinline__ void load_square_frags(bf16x8_t (&f)[H / 64][H / 32], const uint16_t *__restrict__ w,
+                                                  int c0, int g, int lr)
+{
+#pragma unroll
+    for (int k = 0; k < H / 32; ++k)
+#pragma unroll
+        for (int t = 0; t < H / 64; ++t) f[t][k] = ld_bf16x8(w + (int64_t)(c0 + 16 * t + lr) * H + 32 * k + 8 * g);
+}
+
+// acc[t] += rows of xs (LDS, [16][H + 8]) times w, from its fragments f
+// (load_square_frags), k step by k step.
 template <int H>
 __device__ __forceinline__ void products_from_lds(float4_t (&acc)[H / 64], const uint16_t (*xs)[H + 8],
-                                                  const uint16_t *__restrict__ w, int c0, int g, int lr)
+                                                  const bf16x8_t (&f)[H / 64][H / 32], int g, int lr)
 {
-    constexpr int NT = H / 64;
-    bf16x8_t bv[NT], bn[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) bv[t] = ld_bf16x8(w + (int64_t)(c0 + 16 * t + lr) * H + 8 * g);
+    for (int k = 0; k < H / 32; ++k) {
+        const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&xs[lr][32 * k + 8 * g]);
 #pragma unroll
-    for (int kk = 0; kk < H; kk += 32) {
-        if (kk + 32 < H) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) bn[t] = ld_bf16x8(w + (int64_t)(c0 + 16 * t + lr) * H + kk + 32 + 8 * g);
-        }
-        const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&xs[lr][kk + 8 * g]);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[t], acc[t], 0, 0, 0);
-        if (kk + 32 < H) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) bv[t] = bn[t];
-        }
+        for (int t = 0; t < H / 64; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, f[t][k], acc[t], 0, 0, 0);
     }
 }
 
@@ -558,31 +560,49 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerArgs p)
     const int c0 = wave * (H / 4);
     const bool row_ok = r0 + lr < p.n;
     const bf16x8_t zero8 = {};
-    // the output layer's weight fragments (waves 0 and 1), loaded now so that
-    // they have arrived by the third product
+    // Every operand is loaded now, unconditionally (clamped to valid rows), in
+    // the order of use: the loads complete in order, so that a use waits only
+    // for its own load and those before it, and a load under a branch would
+    // make the wave wait for all of them.  The biases and this thread's input
+    // element of the coupling, the first product's input rows and W1
+    // fragments, then W2's, then W3's.
     const int n_out = 2 * p.dim;
     const int ocol = 16 * (wave & 1) + lr;
+    float b1v[NT], b2v[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        b1v[t] = p.b1[c0 + 16 * t + lr];
+        b2v[t] = p.b2[c0 + 16 * t + lr];
+    }
+    const float b3v = p.b3[min(ocol, n_out - 1)];
+    const int crr = tid >> 4, ci = tid & 15;
+    const double a_in = p.a[(int64_t)min(r0 + crr, p.n - 1) * p.dim + min(ci, p.dim - 1)];
+    const bf16x8_t xl = ld_bf16x8(p.xm + (int64_t)min(r0 + lr, p.n - 1) * kInPad + 8 * (g & 1));
+    // lane groups 2 and 3 hold the zero padding of K from kInPad to 32 (in the
+    // input rows, so W1's fragments there may repeat real ones)
+    bf16x8_t w1f[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) w1f[t] = ld_bf16x8(p.w1p + (int64_t)(c0 + 16 * t + lr) * kInPad + 8 * (g & 1));
+    bf16x8_t w2f[NT][H / 32];
+    load_square_frags<H>(w2f, p.w2, c0, g, lr);
+    // output columns past 2 dim repeat the last one (never read)
     bf16x8_t w3f[H / 32];
 #pragma unroll
-    for (int k = 0; k < H / 32; ++k)
-        w3f[k] = (wave < 2 && ocol < n_out) ? ld_bf16x8(p.w3 + (int64_t)ocol * H + 32 * k + 8 * g) : zero8;
+    for (int k = 0; k < H / 32; ++k) w3f[k] = ld_bf16x8(p.w3 + (int64_t)min(ocol, n_out - 1) * H + 32 * k + 8 * g);
+    __builtin_amdgcn_sched_barrier(0);   // all loads issued before the first product waits on its own
     // h1 = relu(xm W1^T + b1), K = kInPad padded to 32 by zeros
+    const bf16x8_t xa = (g < 2 && row_ok) ? xl : zero8;
     float4_t acc[NT];
-    {
-        const bf16x8_t av = (g < 2 && row_ok) ? ld_bf16x8(p.xm + (int64_t)(r0 + lr) * kInPad + 8 * g) : zero8;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const bf16x8_t bv = g < 2 ? ld_bf16x8(p.w1p + (int64_t)(c0 + 16 * t + lr) * kInPad + 8 * g) : zero8;
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-        }
-    }
-    store_hidden<H>(p, h1s, p.h1, p.h1T, acc, p.b1, r0, c0, g, lr);
+    for (int t = 0; t < NT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa, w1f[t], float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    store_hidden<H>(p, h1s, p.h1, p.h1T, acc, b1v, r0, c0, g, lr);
     __syncthreads();
     // h2 = relu(h1 W2^T + b2), K = H
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = float4_t{0.f, 0.f, 0.f, 0.f};
-    products_from_lds<H>(acc, h1s, p.w2, c0, g, lr);
-    store_hidden<H>(p, h2s, p.h2, p.h2T, acc, p.b2, r0, c0, g, lr);
+    products_from_lds<H>(acc, h1s, w2f, g, lr);
+    store_hidden<H>(p, h2s, p.h2, p.h2T, acc, b2v, r0, c0, g, lr);
     __syncthreads();
     // out = h2 W3^T + b3: 2 dim <= 32 columns, one 16-column tile for each of waves 0 and 1
     if (wave < 2) {
@@ -593,7 +613,7 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerArgs p)
             const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&h2s[lr][32 * k + 8 * g]);
             o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w3f[k], o, 0, 0, 0);
         }
-        const float bc = col < n_out ? p.b3[col] : 0.f;
+        const float bc = col < n_out ? b3v : 0.f;
 #pragma unroll
         for (int r = 0; r < 4; ++r) outs[4 * g + r][col] = o[r] + bc;
     }
@@ -602,11 +622,11 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerArgs p)
     // of a row, then each row's log-determinant terms are added in dimension
     // order by one thread (the order of the row-at-a-time kernel)
     {
-        const int rr = tid >> 4, i = tid & 15;
+        const int rr = crr, i = ci;
         const int b = r0 + rr;
         double sv = 0.0;
         if (b < p.n && i < p.dim) {
-            const double ai = p.a[(int64_t)b * p.dim + i];
+            const double ai = a_in;
             double yi = ai;
             if (!((p.cond >> i) & 1u)) {
                 const double r = (double)outs[rr][i];
@@ -692,7 +712,7 @@ struct BackArgs {
     unsigned cond;
     const double *g, *x, *s;              // d loss / d x, x = the coupling's output (inverse direction), s
     double *gy;                           // d loss / d y
-    const uint16_t *h1, *h2;              // [n][H] activations of the forward pass
+    const uint16_t *h1T, *h2T;            // [H][ldT] activations of the forward pass, transposed
     const uint16_t *w1t, *w2t, *w3t;      // W1^T [D][H], W2^T [H][H], W3^T [H][kOutPad]
     uint16_t *doutT, *dpreT, *dpre2T;     // transposed operands of the weight gradients (row length ldT)
     int64_t ldT;
@@ -701,7 +721,7 @@ struct BackArgs {
 
 template <int H>
 __device__ __forceinline__ void masked_hidden(const BackArgs &p, uint16_t (*ds)[H + 8], uint16_t *dT, double *bp,
-                                              const float4_t (&acc)[H / 64], const uint16_t *__restrict__ h, int r0,
+                                              const float4_t (&acc)[H / 64], const uint2 (&h4)[H / 64], int r0,
                                               int c0, int g, int lr)
 {
 #pragma unroll
@@ -714,7 +734,8 @@ __device__ __forceinline__ void masked_hidden(const BackArgs &p, uint16_t (*ds)[
             const int i = r0 + 4 * g + r;
             float v = acc[t][r];
             if (i < p.n) {
-                const uint16_t hv = h[(int64_t)i * H + j];
+                const uint32_t w = r < 2 ? h4[t].x : h4[t].y;
+                const uint16_t hv = (uint16_t)(r % 2 == 0 ? w & 0xffffu : w >> 16);
                 v = ((hv & 0x7fffu) != 0 && !(hv & 0x8000u)) ? v : 0.f;
             } else {
                 v = 0.f;
@@ -751,19 +772,31 @@ __global__ __launch_bounds__(256) void layer_back_kernel(BackArgs p)
     const int lr = lane & 15, g = lane >> 4;
     const int c0 = wave * (H / 4);
     const int D = p.dim;
-    const bf16x8_t zero8 = {};
-    // weight fragments of the first and the last product, loaded now so
-    // that they have arrived when needed
-    bf16x8_t w3f[NT], w1f[H / 32];
+    // Every operand is loaded now, unconditionally (clamped to valid rows), in
+    // the order of use (the loads complete in order; a load under a branch
+    // would make the wave wait for all of them): this thread's element of the
+    // head, the activations' signs for the two ReLU masks (4 rows of a
+    // column in 8 bytes of the transposed copies), then the weight fragments
+    // of the three products (W1's rows past dim repeat the last, never read).
+    const int rr = tid >> 4, i = tid & 15;   // the head's (row, dimension)
+    const int64_t oc = (int64_t)min(r0 + rr, p.n - 1) * D + min(i, D - 1);
+    const double gv = p.g[oc], xv = p.x[oc], sv = p.s[oc];
+    uint2 m2[NT], m1[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int64_t at = (int64_t)(c0 + 16 * t + lr) * p.ldT + r0 + 4 * g;
+        m2[t] = *reinterpret_cast<const uint2 *>(p.h2T + at);
+        m1[t] = *reinterpret_cast<const uint2 *>(p.h1T + at);
+    }
+    bf16x8_t w3f[NT], w2f[NT][H / 32], w1f[H / 32];
 #pragma unroll
     for (int t = 0; t < NT; ++t) w3f[t] = ld_bf16x8(p.w3t + (int64_t)(c0 + 16 * t + lr) * kOutPad + 8 * g);
+    load_square_frags<H>(w2f, p.w2t, c0, g, lr);
 #pragma unroll
-    for (int k = 0; k < H / 32; ++k)
-        w1f[k] = (wave == 0 && lr < D) ? ld_bf16x8(p.w1t + (int64_t)lr * H + 32 * k + 8 * g) : zero8;
+    for (int k = 0; k < H / 32; ++k) w1f[k] = ld_bf16x8(p.w1t + (int64_t)min(lr, D - 1) * H + 32 * k + 8 * g);
     // the inverse coupling's backward: thread (row, i) = (tid / 16, tid % 16)
     // takes dimension i of a row (dout columns i and D + i)
     {
-        const int rr = tid >> 4, i = tid & 15;
         const int b = r0 + rr;
         dos[rr][i] = 0.f;
         dos[rr][16 + i] = 0.f;
@@ -771,14 +804,14 @@ __global__ __launch_bounds__(256) void layer_back_kernel(BackArgs p)
         if (b < p.n && i < D) {
             const int64_t o = (int64_t)b * D + i;
             if ((p.cond >> i) & 1u) {
-                p.gy[o] = p.g[o];
+                p.gy[o] = gv;
             } else {
                 const double inv_n = 1.0 / (double)p.n;
-                const double si = p.s[o], e = exp(-si);
-                const double dt = -p.g[o] * e;
-                const double ds = -p.g[o] * p.x[o] + inv_n;
+                const double si = sv, e = exp(-si);
+                const double dt = -gv * e;
+                const double ds = -gv * xv + inv_n;
                 const double dr = ds * (1.0 - (si / 3.0) * (si / 3.0));
-                p.gy[o] = p.g[o] * e;
+                p.gy[o] = gv * e;
                 dos[rr][i] = (float)dr;
                 dos[rr][D + i] = (float)dt;
             }
@@ -805,13 +838,13 @@ __global__ __launch_bounds__(256) void layer_back_kernel(BackArgs p)
         for (int t = 0; t < NT; ++t)
             acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w3f[t], float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
     }
-    masked_hidden<H>(p, d2s, p.dpreT, p.bp2, acc, p.h2, r0, c0, g, lr);
+    masked_hidden<H>(p, d2s, p.dpreT, p.bp2, acc, m2, r0, c0, g, lr);
     __syncthreads();
     // dh1 = dpre2 W2 (B(k, j) = W2[k][j] = W2^T[j][k]), masked by h1 > 0
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = float4_t{0.f, 0.f, 0.f, 0.f};
-    products_from_lds<H>(acc, d2s, p.w2t, c0, g, lr);
-    masked_hidden<H>(p, d1s, p.dpre2T, p.bp1, acc, p.h1, r0, c0, g, lr);
+    products_from_lds<H>(acc, d2s, w2f, g, lr);
+    masked_hidden<H>(p, d1s, p.dpre2T, p.bp1, acc, m1, r0, c0, g, lr);
     __syncthreads();
     // dxm = dpre1 W1 (B(k, d) = W1[k][d] = W1^T[d][k]), added into gy on the conditioning dims
     if (wave == 0) {
@@ -1386,7 +1419,7 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
         const int64_t w2t = (int64_t)D * H, w3t = (int64_t)D * H + (int64_t)H * H;
         if (fused_width(f)) {
             gw::flow::BackArgs ba{n, D, f->cond[l], f->g, boundary(f, l), f->s_store + (int64_t)l * f->cap * D, f->gy,
-                                  h1, h2, wt, wt + w2t, wt + w3t, f->doutT, f->dpreT, f->dpre2T, T, bp1, bp2, bp3};
+                                  h1T, h2T, wt, wt + w2t, wt + w3t, f->doutT, f->dpreT, f->dpre2T, T, bp1, bp2, bp3};
             const dim3 grid((unsigned)rb16);
             if (H == 256)
                 hipLaunchKernelGGL(gw::flow::layer_back_kernel<256>, grid, dim3(256), 0, s, ba);
