@@ -658,29 +658,42 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerArgs p)
 
 // Affine normalisation around the coupling stack: forward x = mu + sigma u,
 // inverse u = (x - mu) / sigma; sum_s[b] += sum log sigma in both directions.
-// init_sum: sum_s[b] starts from zero here.
+// init_sum: sum_s[b] starts from zero here.  Thread (row, i) = (tid / 16,
+// tid % 16) of a block of 16 rows takes element i of a row, and column i of
+// the next coupling's masked BF16 input (zeros past dim).
 __global__ __launch_bounds__(256) void affine_kernel(int n, int dim, int dir, const double *__restrict__ mu,
                                                      const double *__restrict__ log_sigma,
                                                      const double *__restrict__ a, double *__restrict__ y,
                                                      double *__restrict__ sum_s, int init_sum, NextMask nm)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.x * 16 + (int)(threadIdx.x >> 4), i = threadIdx.x & 15;
     if (b >= n) return;
-    double acc = 0.0;
-    for (int i = 0; i < dim; ++i) {
+    double yi = 0.0;
+    if (i < dim) {
         const double v = a[(int64_t)b * dim + i];
-        y[(int64_t)b * dim + i] = dir > 0 ? mu[i] + exp(log_sigma[i]) * v : (v - mu[i]) * exp(-log_sigma[i]);
-        acc += log_sigma[i];
+        yi = dir > 0 ? mu[i] + exp(log_sigma[i]) * v : (v - mu[i]) * exp(-log_sigma[i]);
+        y[(int64_t)b * dim + i] = yi;
     }
-    sum_s[b] = (init_sum ? 0.0 : sum_s[b]) + acc;
-    write_mask(nm, b, dim, y + (int64_t)b * dim);
+    if (i == 0) {
+        double acc = 0.0;
+        for (int k = 0; k < dim; ++k) acc += log_sigma[k];
+        sum_s[b] = (init_sum ? 0.0 : sum_s[b]) + acc;
+    }
+    if (nm.xm) {
+        const bool on = i < dim && ((nm.cond >> i) & 1u);
+        const uint16_t v = on ? f32_to_bf16((float)yi) : (uint16_t)0;
+        nm.xm[(int64_t)b * kInPad + i] = v;
+        if (nm.xmT) nm.xmT[i * nm.ldT + b] = v;
+    }
 }
 
 // log q = -|z|^2/2 - dim/2 log(2 pi) - sum_s; the per-row training loss is
-// |z|^2/2 + sum_s (the negative log density up to the constant).
+// |z|^2/2 + sum_s (the negative log density up to the constant), and with g
+// given the start of its gradient, d loss / d z = z / n for the mean loss.
 __global__ __launch_bounds__(256) void base_density_kernel(int n, int dim, const double *__restrict__ z,
                                                            const double *__restrict__ sum_s,
-                                                           double *__restrict__ logq, double *__restrict__ loss)
+                                                           double *__restrict__ logq, double *__restrict__ loss,
+                                                           double *__restrict__ g)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
@@ -688,6 +701,7 @@ __global__ __launch_bounds__(256) void base_density_kernel(int n, int dim, const
     for (int i = 0; i < dim; ++i) {
         const double v = z[(int64_t)b * dim + i];
         zz += v * v;
+        if (g) g[(int64_t)b * dim + i] = v / (double)n;
     }
     const double l = 0.5 * zz + sum_s[b];
     if (logq) logq[b] = -l - 0.5 * dim * 1.8378770664093453;   // log(2 pi)
@@ -866,14 +880,6 @@ __global__ __launch_bounds__(256) void layer_back_kernel(BackArgs p)
 }
 
 // ---------------------------------------------------------------- training backward
-// g = d loss / d z for loss = mean_b(|z_b|^2/2 + sum_s_b): z / n.
-__global__ __launch_bounds__(256) void grad_init_kernel(int n, int dim, const double *__restrict__ z,
-                                                        double *__restrict__ g)
-{
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * dim) return;
-    g[idx] = z[idx] / (double)n;
-}
 
 // Backward of one inverse coupling x = (y - t) e^{-s} (T dims), x_C = y_C, with
 // the loss term sum_T s / n.  g = d loss / d x.  Writes d loss / d(r, t) as
@@ -952,10 +958,13 @@ struct GradParts {
     const double *bpart;
 };
 
-__global__ __launch_bounds__(256) void grad_finish_kernel(GradParts gp, float *__restrict__ grads)
+// Parameter p's gradient from its partial sums, when a thread finishes it:
+// the weights' split-K slices in slice order, and the biases' row-block
+// partials in block order when there are at most 64 of them (more: a wave
+// per bias element, bias_gradient).  Returns false for the biases left to the
+// waves.
+__device__ __forceinline__ bool param_gradient(const GradParts &gp, int64_t p, float &grad)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= gp.n_params) return;
     const int64_t D = gp.D, H = gp.H;
     const int64_t l = p / gp.per_layer;
     int64_t q = p - l * gp.per_layer;
@@ -965,44 +974,45 @@ __global__ __launch_bounds__(256) void grad_finish_kernel(GradParts gp, float *_
     const float *wr = nullptr;
     int64_t wsz = 0;
     const double *br = nullptr;
-    int64_t bcols = 0, bn = 0;
+    int64_t bcols = 0;
     if (q < sz1) {
         wr = w, wsz = sz1;
     } else if ((q -= sz1) < H) {
-        br = bp, bcols = H, bn = gp.rb;
+        br = bp, bcols = H;
     } else if ((q -= H) < sz2) {
         wr = w + kMaxSplit * sz1, wsz = sz2;
     } else if ((q -= sz2) < H) {
-        br = bp + gp.rb_cap * H, bcols = H, bn = gp.rb;
+        br = bp + gp.rb_cap * H, bcols = H;
     } else if ((q -= H) < sz3) {
         wr = w + kMaxSplit * (sz1 + sz2), wsz = sz3;
     } else {
         q -= sz3;
-        br = bp + 2 * gp.rb_cap * H, bcols = 2 * D, bn = gp.rb;
+        br = bp + 2 * gp.rb_cap * H, bcols = 2 * D;
     }
     if (wr) {
         float v = 0.f;
         for (int z = 0; z < gp.split; ++z) v += wr[z * wsz + q];
-        grads[p] = v;
-    } else if (bn <= 64) {
-        double t = 0.0;
-        for (int64_t y = 0; y < bn; ++y) t += br[y * bcols + q];
-        grads[p] = (float)t;
+        grad = v;
+        return true;
     }
-    // more row blocks: bias_finish_kernel
-    (void)bcols;
+    if (gp.rb > 64) return false;
+    double t = 0.0;
+    for (int64_t y = 0; y < gp.rb; ++y) t += br[y * bcols + q];
+    grad = (float)t;
+    return true;
 }
 
-// The biases when their partials come in more than 64 row blocks: one wave
-// per bias element (layer l, then b1, b2, b3), lane k summing the blocks
-// k, k + 64, ... in order, then the 64 lane sums by a fixed butterfly.
-__global__ __launch_bounds__(64) void bias_finish_kernel(GradParts gp, float *__restrict__ grads)
+// Bias element e (layer e / (2 H + 2 dim), then b1, b2, b3) summed over its
+// row-block partials by the 64 lanes of a wave: lane k the blocks k, k + 64,
+// ... in order, then the 64 lane sums by a fixed butterfly (every lane gets
+// the total).  p: the element's parameter index.
+__device__ __forceinline__ float bias_gradient(const GradParts &gp, int64_t e, int lane, int64_t &p)
 {
     const int64_t H = gp.H, D = gp.D, per = 2 * H + 2 * D;
-    const int64_t l = blockIdx.x / per, r = blockIdx.x % per;
+    const int64_t l = e / per, r = e % per;
     const double *bp = gp.bpart + l * gp.b_layer;
     const double *br;
-    int64_t bcols, q, p;
+    int64_t bcols, q;
     const int64_t base = l * gp.per_layer;
     if (r < H) {
         br = bp, bcols = H, q = r, p = base + H * D + r;
@@ -1013,68 +1023,32 @@ __global__ __launch_bounds__(64) void bias_finish_kernel(GradParts gp, float *__
         p = base + H * D + 2 * H + H * H + 2 * D * H + (r - 2 * H);
     }
     double t = 0.0;
-    for (int64_t y = threadIdx.x; y < gp.rb; y += 64) t += br[y * bcols + q];
+    for (int64_t y = lane; y < gp.rb; y += 64) t += br[y * bcols + q];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
-    if (threadIdx.x == 0) grads[p] = (float)t;
+    return (float)t;
 }
 
-// Adam (Kingma & Ba 2015) on FP32 master parameters.
-__global__ __launch_bounds__(256) void adam_kernel(int64_t count, float *__restrict__ p, const float *__restrict__ grad,
-                                                   float *__restrict__ m, float *__restrict__ v, float lr, float beta1,
-                                                   float beta2, float eps, float bc1, float bc2)
+__global__ __launch_bounds__(256) void grad_finish_kernel(GradParts gp, float *__restrict__ grads)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    const float gi = grad[i];
-    const float mi = beta1 * m[i] + (1.f - beta1) * gi;
-    const float vi = beta2 * v[i] + (1.f - beta2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= gp.n_params) return;
+    float g;
+    if (param_gradient(gp, p, g)) grads[p] = g;
 }
 
-// BF16 copies of the weight matrices (FP32 master -> BF16): parameter i of
-// layer i / per_layer goes to dst[layer * dst_stride + i % per_layer], and
-// the weights also transposed into dstT (layer stride t_stride): W1^T [D][H],
-// W2^T [H][H], W3^T [H][kOutPad] (rows padded), the backward pass's operands,
-// then W1 with its rows padded to kInPad, [H][kInPad], the first product's
-// operand in 16-byte vectors.
-__global__ __launch_bounds__(256) void to_bf16_kernel(int64_t count, int64_t per_layer, int64_t dst_stride,
-                                                      int D, int H, int64_t t_stride, const float *__restrict__ src,
-                                                      uint16_t *__restrict__ dst, uint16_t *__restrict__ dstT)
+// The biases when their partials come in more than 64 row blocks: one wave
+// per bias element.
+__global__ __launch_bounds__(64) void bias_finish_kernel(GradParts gp, float *__restrict__ grads)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    const int64_t l = i / per_layer;
-    int64_t q = i - l * per_layer;
-    const uint16_t v = f32_to_bf16(src[i]);
-    dst[l * dst_stride + q] = v;
-    uint16_t *t = dstT + l * t_stride;
-    const int64_t s1 = (int64_t)H * D, s2 = (int64_t)H * H, s3 = 2 * (int64_t)D * H;
-    if (q < s1) {                                   // W1 [H][D] -> W1^T [D][H], and padded rows
-        t[(q % D) * H + q / D] = v;
-        t[s1 + s2 + (int64_t)H * kOutPad + (q / D) * kInPad + q % D] = v;
-        return;
-    }
-    q -= s1 + H;
-    if (q < 0) return;                              // b1
-    if (q < s2) {                                   // W2 [H][H] -> W2^T
-        t[s1 + (q % H) * H + q / H] = v;
-        return;
-    }
-    q -= s2 + H;
-    if (q >= 0 && q < s3) t[s1 + s2 + (q % H) * kOutPad + q / H] = v;   // W3 [2D][H] -> W3^T [H][kOutPad]
+    int64_t p;
+    const float g = bias_gradient(gp, blockIdx.x, threadIdx.x, p);
+    if (threadIdx.x == 0) grads[p] = g;
 }
 
-__global__ __launch_bounds__(256) void zero_kernel(int64_t n, double *__restrict__ p)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0.0;
-}
-
-// mean of loss[0..n) into out[0] (one block, fixed order).
-__global__ __launch_bounds__(256) void mean_kernel(int n, const double *__restrict__ loss, double *__restrict__ out)
+// out[0] = the mean of loss[0, n) (one block of 256 threads: thread t sums
+// the rows t, t + 256, ... in order, then a fixed tree over the threads).
+__device__ __forceinline__ void mean_block(int n, const double *__restrict__ loss, double *__restrict__ out)
 {
     __shared__ double red[256];
     double acc = 0.0;
@@ -1088,6 +1062,111 @@ __global__ __launch_bounds__(256) void mean_kernel(int n, const double *__restri
     if (threadIdx.x == 0) out[0] = red[0] / (double)n;
 }
 
+__global__ __launch_bounds__(256) void mean_kernel(int n, const double *__restrict__ loss, double *__restrict__ out)
+{
+    mean_block(n, loss, out);
+}
+
+// BF16 copies of the weight matrices (FP32 master -> BF16): parameter i of
+// layer i / per_layer goes to dst[layer * dst_stride + i % per_layer], and
+// the weights also transposed into dstT (layer stride t_stride): W1^T [D][H],
+// W2^T [H][H], W3^T [H][kOutPad] (rows padded), the backward pass's operands,
+// then W1 with its rows padded to kInPad, [H][kInPad], the first product's
+// operand in 16-byte vectors.
+struct Bf16Copies {
+    int64_t per_layer, dst_stride, t_stride;
+    int D, H;
+    uint16_t *dst, *dstT;
+};
+
+__device__ __forceinline__ void write_bf16(const Bf16Copies &c, int64_t i, float value)
+{
+    const int64_t l = i / c.per_layer;
+    int64_t q = i - l * c.per_layer;
+    const int64_t D = c.D, H = c.H;
+    const uint16_t v = f32_to_bf16(value);
+    c.dst[l * c.dst_stride + q] = v;
+    uint16_t *t = c.dstT + l * c.t_stride;
+    const int64_t s1 = H * D, s2 = H * H, s3 = 2 * D * H;
+    if (q < s1) {                                   // W1 [H][D] -> W1^T [D][H], and padded rows
+        t[(q % D) * H + q / D] = v;
+        t[s1 + s2 + H * kOutPad + (q / D) * kInPad + q % D] = v;
+        return;
+    }
+    q -= s1 + H;
+    if (q < 0) return;                              // b1
+    if (q < s2) {                                   // W2 [H][H] -> W2^T
+        t[s1 + (q % H) * H + q / H] = v;
+        return;
+    }
+    q -= s2 + H;
+    if (q >= 0 && q < s3) t[s1 + s2 + (q % H) * kOutPad + q / H] = v;   // W3 [2D][H] -> W3^T [H][kOutPad]
+}
+
+__global__ __launch_bounds__(256) void to_bf16_kernel(int64_t count, Bf16Copies c, const float *__restrict__ src)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) write_bf16(c, i, src[i]);
+}
+
+// Adam (Kingma & Ba 2015) on FP32 master parameters: the step of parameter
+// i with gradient gi; returns the new value.
+struct AdamStep {
+    float *p, *m, *v;
+    float lr, beta1, beta2, eps, bc1, bc2;
+};
+
+__device__ __forceinline__ float adam_update(const AdamStep &a, int64_t i, float gi)
+{
+    const float mi = a.beta1 * a.m[i] + (1.f - a.beta1) * gi;
+    const float vi = a.beta2 * a.v[i] + (1.f - a.beta2) * gi * gi;
+    a.m[i] = mi;
+    a.v[i] = vi;
+    const float pi = a.p[i] - a.lr * (mi / a.bc1) / (sqrtf(vi / a.bc2) + a.eps);
+    a.p[i] = pi;
+    return pi;
+}
+
+// The end of a training step in one launch: every parameter's gradient from
+// its partial sums (the orders of grad_finish_kernel and bias_finish_kernel),
+// its Adam update and its BF16 copies.  Blocks below weight_blocks take one
+// parameter per thread; the biases that param_gradient leaves to waves go to
+// the blocks after them, one wave per bias element; with loss_out given, the
+// last block writes the mean of the n_rows per-row losses there (mean_block).
+__global__ __launch_bounds__(256) void finish_update_kernel(GradParts gp, float *__restrict__ grads, AdamStep a,
+                                                            Bf16Copies c, int weight_blocks, int64_t n_bias,
+                                                            int n_rows, const double *__restrict__ loss,
+                                                            double *__restrict__ loss_out)
+{
+    if (loss_out && blockIdx.x == gridDim.x - 1) {
+        mean_block(n_rows, loss, loss_out);
+        return;
+    }
+    if ((int)blockIdx.x < weight_blocks) {
+        const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        float g;
+        if (p >= gp.n_params || !param_gradient(gp, p, g)) return;
+        grads[p] = g;
+        write_bf16(c, p, adam_update(a, p, g));
+        return;
+    }
+    const int64_t e = (int64_t)(blockIdx.x - weight_blocks) * 4 + (threadIdx.x >> 6);
+    if (e >= n_bias) return;                        // whole waves
+    const int lane = threadIdx.x & 63;
+    int64_t p;
+    const float g = bias_gradient(gp, e, lane, p);
+    if (lane != 0) return;
+    grads[p] = g;
+    write_bf16(c, p, adam_update(a, p, g));
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(int64_t n, double *__restrict__ p)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// mean of loss[0..n) into out[0] (one block, fixed order).
 }  // namespace flow
 }  // namespace gw
 
@@ -1335,7 +1414,7 @@ hipError_t zero(int64_t n, double *p, hipStream_t s)
 hipError_t inverse_pass(gw_flow *f, int n, const double *x, bool keep_t, hipStream_t s)
 {
     const int D = f->dim, L = f->layers;
-    hipLaunchKernelGGL(gw::flow::affine_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, -1, f->mu, f->log_sigma,
+    hipLaunchKernelGGL(gw::flow::affine_kernel, dim3((n + 15) / 16), dim3(256), 0, s, n, D, -1, f->mu, f->log_sigma,
                        x, boundary(f, L), f->sum_s, 1, mask_of(f, L - 1, keep_t));
     GW_TRY(hipGetLastError());
     for (int l = L - 1; l >= 0; --l) {
@@ -1376,29 +1455,35 @@ hipError_t forward_pass(gw_flow *f, int n, const double *z, hipStream_t s)
                            mask_of(f, l + 1, false));
         GW_TRY(hipGetLastError());
     }
-    hipLaunchKernelGGL(gw::flow::affine_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, 1, f->mu, f->log_sigma,
+    hipLaunchKernelGGL(gw::flow::affine_kernel, dim3((n + 15) / 16), dim3(256), 0, s, n, D, 1, f->mu, f->log_sigma,
                        boundary(f, L), boundary(f, L + 1), f->sum_s, 0, mask_of(f, -1, false));
     return hipGetLastError();
 }
 
+// The BF16 copies of the flow's weights that the kernels read.
+gw::flow::Bf16Copies bf16_copies(const gw_flow *f)
+{
+    return gw::flow::Bf16Copies{f->per_layer, f->wb_stride, f->wbT_stride, f->dim, f->hidden, f->wb, f->wbT};
+}
+
 // Gradient of the mean negative log density of rows x[0, n) with respect to
 // every parameter (into f->grads); the mean loss goes to loss_out (device).
-hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipStream_t s)
+// With adam, the Adam step and the refresh of the BF16 copies follow in the
+// launch that finishes the gradients.
+hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipStream_t s,
+                     const gw::flow::AdamStep *adam = nullptr)
 {
     const int D = f->dim, H = f->hidden, L = f->layers;
     // weight gradients sum over the n rows: split K = n into slices of >= 256 rows
     const int split = std::max(1, std::min(gw::flow::kMaxSplit, n / 256));
     GW_TRY(inverse_pass(f, n, x, true, s));
     hipLaunchKernelGGL(gw::flow::base_density_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, boundary(f, 0),
-                       f->sum_s, nullptr, f->loss);
+                       f->sum_s, nullptr, f->loss, f->g);
     GW_TRY(hipGetLastError());
-    if (loss_out) {
+    if (loss_out && !adam) {     // a training step takes the mean in its last launch
         hipLaunchKernelGGL(gw::flow::mean_kernel, dim3(1), dim3(256), 0, s, n, f->loss, loss_out);
         GW_TRY(hipGetLastError());
     }
-    hipLaunchKernelGGL(gw::flow::grad_init_kernel, dim3(blocks_for((int64_t)n * D)), dim3(256), 0, s, n, D,
-                       boundary(f, 0), f->g);
-    GW_TRY(hipGetLastError());
     // the inverse pass applied couplings L-1 .. 0; go back through 0 .. L-1.
     // Every gradient of layer l is left as partial sums (split-K slices of the
     // weights, row-block sums of the biases) and summed by one kernel at the end.
@@ -1477,6 +1562,15 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
     }
     gw::flow::GradParts parts{D, H, split, fused_width(f) ? rb16 : rb64, f->rb_cap, f->per_layer, f->n_params,
                               f->w_layer, f->b_layer, f->wpart, f->bpart};
+    if (adam) {
+        // the gradients' sums, the Adam step and the BF16 copies in one launch
+        const int wblocks = blocks_for(f->n_params);
+        const int64_t n_bias = parts.rb > 64 ? (int64_t)L * (2 * H + 2 * D) : 0;
+        const int64_t blocks = wblocks + (n_bias + 3) / 4 + (loss_out ? 1 : 0);
+        hipLaunchKernelGGL(gw::flow::finish_update_kernel, dim3((unsigned)blocks), dim3(256), 0, s, parts, f->grads,
+                           *adam, bf16_copies(f), wblocks, n_bias, n, f->loss, loss_out);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(gw::flow::grad_finish_kernel, dim3(blocks_for(f->n_params)), dim3(256), 0, s, parts, f->grads);
     GW_TRY(hipGetLastError());
     if (parts.rb > 64) {
@@ -1490,7 +1584,7 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
 hipError_t refresh_bf16(gw_flow *f, hipStream_t s)
 {
     hipLaunchKernelGGL(gw::flow::to_bf16_kernel, dim3(blocks_for(f->n_params)), dim3(256), 0, s, f->n_params,
-                       f->per_layer, f->wb_stride, f->dim, f->hidden, f->wbT_stride, f->params, f->wb, f->wbT);
+                       bf16_copies(f), f->params);
     return hipGetLastError();
 }
 
@@ -1601,7 +1695,7 @@ int gw_flow_forward(gw_flow *f, const double *z, int64_t n, double *x_out, doubl
                            stream);
     if (e == hipSuccess && logq_out) {
         hipLaunchKernelGGL(gw::flow::base_density_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, (int)n, f->dim,
-                           boundary(f, 0), f->sum_s, logq_out, nullptr);
+                           boundary(f, 0), f->sum_s, logq_out, nullptr, nullptr);
         e = hipGetLastError();
     }
     return e == hipSuccess ? GW_OK : hip_fail(e, "gw_flow_forward");
@@ -1618,7 +1712,7 @@ int gw_flow_inverse(gw_flow *f, const double *x, int64_t n, double *z_out, doubl
         e = hipMemcpyAsync(z_out, boundary(f, 0), sizeof(double) * n * f->dim, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess && logq_out) {
         hipLaunchKernelGGL(gw::flow::base_density_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, (int)n, f->dim,
-                           boundary(f, 0), f->sum_s, logq_out, nullptr);
+                           boundary(f, 0), f->sum_s, logq_out, nullptr, nullptr);
         e = hipGetLastError();
     }
     return e == hipSuccess ? GW_OK : hip_fail(e, "gw_flow_inverse");
@@ -1643,18 +1737,14 @@ int gw_flow_train_step(gw_flow *f, const double *x, int64_t n, float lr, double 
     if (!(lr > 0.0f)) return fail(GW_EINVAL, "learning rate must be > 0");
     DeviceGuard g(f->device);
     if (int rc = ensure_batch(f, n)) return rc;
-    hipError_t e = gradients(f, (int)n, x, loss_out, stream);
-    if (e == hipSuccess) {
-        ++f->adam_t;
-        const float b1 = 0.9f, b2 = 0.999f;
-        const float bc1 = 1.0f - (float)std::pow(b1, (double)f->adam_t);
-        const float bc2 = 1.0f - (float)std::pow(b2, (double)f->adam_t);
-        hipLaunchKernelGGL(gw::flow::adam_kernel, dim3(blocks_for(f->n_params)), dim3(256), 0, stream, f->n_params,
-                           f->params, f->grads, f->adam_m, f->adam_v, lr, b1, b2, 1e-8f, bc1, bc2);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = refresh_bf16(f, stream);
-    return e == hipSuccess ? GW_OK : hip_fail(e, "gw_flow_train_step");
+    const float b1 = 0.9f, b2 = 0.999f;
+    const int64_t t = f->adam_t + 1;
+    const gw::flow::AdamStep adam{f->params, f->adam_m, f->adam_v, lr, b1, b2, 1e-8f,
+                                  1.0f - (float)std::pow(b1, (double)t), 1.0f - (float)std::pow(b2, (double)t)};
+    hipError_t e = gradients(f, (int)n, x, loss_out, stream, &adam);
+    if (e != hipSuccess) return hip_fail(e, "gw_flow_train_step");
+    f->adam_t = t;
+    return GW_OK;
 }
 
 }  // extern "C"
