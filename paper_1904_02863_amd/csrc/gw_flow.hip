@@ -280,21 +280,34 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int vec_a, i
 struct GemmGroup {
     GemmArgs g0, g1, g2;
     int va[3], vb[3], gx[3], gy[3], start[4];
+    LayerStrides ls;                      // per-layer strides (launches over several layers)
 };
 
+// Product p of the group for layer `layer`: its operands moved by the layer strides.
+__device__ __forceinline__ void gemm_group_tile(GemmArgs g, const GemmGroup &gg, int p, int layer, int bx, int by,
+                                                int bz)
+{
+    g.A += layer * gg.ls.sA[p];
+    g.B += layer * gg.ls.sB[p];
+    g.partial += layer * gg.ls.sP[p];
+    gemm_tile<true, true>(g, gg.va[p], gg.vb[p], bx, by, bz);
+}
+
+// Blocks layer by layer, each layer's as start[] lays out its three products.
 __global__ __launch_bounds__(256) void gemm_group_kernel(GemmGroup gg)
 {
-    const int b = blockIdx.x;
+    const int layer = (int)blockIdx.x / gg.start[3];
+    const int b = (int)blockIdx.x - layer * gg.start[3];
     const int p = (b >= gg.start[1]) + (b >= gg.start[2]);
     const int local = b - gg.start[p];
     const int bx = local % gg.gx[p], rest = local / gg.gx[p];
     const int by = rest % gg.gy[p], bz = rest / gg.gy[p];
     if (p == 0)
-        gemm_tile<true, true>(gg.g0, gg.va[0], gg.vb[0], bx, by, bz);
+        gemm_group_tile(gg.g0, gg, 0, layer, bx, by, bz);
     else if (p == 1)
-        gemm_tile<true, true>(gg.g1, gg.va[1], gg.vb[1], bx, by, bz);
+        gemm_group_tile(gg.g1, gg, 1, layer, bx, by, bz);
     else
-        gemm_tile<true, true>(gg.g2, gg.va[2], gg.vb[2], bx, by, bz);
+        gemm_group_tile(gg.g2, gg, 2, layer, bx, by, bz);
 }
 
 // Sums the split-K slices in slice order, then bias, ReLU and the outputs.
@@ -321,13 +334,18 @@ static bool vector_ok(const uint16_t *p, int64_t s_contig, int64_t s_other)
 
 // Three products with k-contiguous operands (sa_k = sb_k = 1) in one
 // launch; each as gemm_bf16 would run it (split-K with defer, no reduce kernel).
-hipError_t gemm_bf16_group3(const GemmArgs &a, const GemmArgs &b, const GemmArgs &c, hipStream_t stream)
+hipError_t gemm_bf16_group3(const GemmArgs &a, const GemmArgs &b, const GemmArgs &c, hipStream_t stream, int layers,
+                            const LayerStrides *strides)
 {
+    if (layers < 1 || (layers > 1 && !strides)) return hipErrorInvalidValue;
     const GemmArgs *gs[3] = {&a, &b, &c};
     GemmGroup gg;
     gg.g0 = a;
     gg.g1 = b;
     gg.g2 = c;
+    gg.ls = strides ? *strides : LayerStrides{};
+    for (int p = 0; p < 3; ++p)
+        if (gg.ls.sA[p] % 8 != 0 || gg.ls.sB[p] % 8 != 0 || gg.ls.sP[p] % 8 != 0) return hipErrorInvalidValue;
     int start = 0;
     for (int p = 0; p < 3; ++p) {
         const GemmArgs &g = *gs[p];
@@ -342,7 +360,8 @@ hipError_t gemm_bf16_group3(const GemmArgs &a, const GemmArgs &b, const GemmArgs
         start += gg.gx[p] * gg.gy[p] * g.split;
     }
     gg.start[3] = start;
-    hipLaunchKernelGGL(gemm_group_kernel, dim3((unsigned)start), dim3(256), 0, stream, gg);
+    if ((int64_t)start * layers > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gemm_group_kernel, dim3((unsigned)(start * layers)), dim3(256), 0, stream, gg);
     return hipGetLastError();
 }
 
@@ -1299,7 +1318,7 @@ int ensure_batch(gw_flow *f, int64_t n)
         alloc(&f->dpre_b, c * H) ||
         alloc(&f->dpre2_b, c * H) || alloc(&f->wpart, L * w_layer) || alloc(&f->bpart, L * b_layer) ||
         alloc(&f->h1T, L * H * ldT) || alloc(&f->h2T, L * H * ldT) || alloc(&f->xmT, L * kInPad * ldT) ||
-        alloc(&f->doutT, kOutPad * ldT) || alloc(&f->dpreT, H * ldT) || alloc(&f->dpre2T, H * ldT)) {
+        alloc(&f->doutT, L * kOutPad * ldT) || alloc(&f->dpreT, L * H * ldT) || alloc(&f->dpre2T, L * H * ldT)) {
         free_batch(f);
         return fail(GW_ENOMEM, "flow batch buffers");
     }
@@ -1503,19 +1522,17 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
         const uint16_t *wt = f->wbT + (int64_t)l * f->wbT_stride;
         const int64_t w2t = (int64_t)D * H, w3t = (int64_t)D * H + (int64_t)H * H;
         if (fused_width(f)) {
+            // the coupling's transposed operands of its weight gradients go to
+            // layer l's slices, for the one launch of all layers' products below
             gw::flow::BackArgs ba{n, D, f->cond[l], f->g, boundary(f, l), f->s_store + (int64_t)l * f->cap * D, f->gy,
-                                  h1T, h2T, wt, wt + w2t, wt + w3t, f->doutT, f->dpreT, f->dpre2T, T, bp1, bp2, bp3};
+                                  h1T, h2T, wt, wt + w2t, wt + w3t, f->doutT + (int64_t)l * kOutPad * T,
+                                  f->dpreT + (int64_t)l * H * T, f->dpre2T + (int64_t)l * H * T, T, bp1, bp2, bp3};
             const dim3 grid((unsigned)rb16);
             if (H == 256)
                 hipLaunchKernelGGL(gw::flow::layer_back_kernel<256>, grid, dim3(256), 0, s, ba);
             else
                 hipLaunchKernelGGL(gw::flow::layer_back_kernel<128>, grid, dim3(256), 0, s, ba);
             GW_TRY(hipGetLastError());
-            // the coupling's three weight gradients in one launch
-            GemmArgs fw3{2 * D, H, n, f->doutT, T, 1, h2T, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split, wp3, 1};
-            GemmArgs fw2{H, H, n, f->dpreT, T, 1, h1T, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split, wp2, 1};
-            GemmArgs fw1{H, D, n, f->dpre2T, T, 1, xmT, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split, wp1, 1};
-            GW_TRY(gw::flow::gemm_bf16_group3(fw3, fw2, fw1, s));
             std::swap(f->g, f->gy);      // d loss / d(boundary l + 1)
             continue;
         }
@@ -1559,6 +1576,19 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
         gx.add_mask = f->cond[l];
         GW_TRY(gw::flow::gemm_bf16(gx, s));
         std::swap(f->g, f->gy);      // d loss / d(boundary l + 1)
+    }
+    if (fused_width(f)) {
+        // every coupling's three weight gradients in one launch, layer by layer
+        const int64_t T = f->ldT;
+        float *wp = f->wpart;
+        GemmArgs fw3{2 * D, H, n, f->doutT, T, 1, f->h2T, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split,
+                     wp + (int64_t)gw::flow::kMaxSplit * (H * D + H * H), 1};
+        GemmArgs fw2{H, H, n, f->dpreT, T, 1, f->h1T, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split,
+                     wp + (int64_t)gw::flow::kMaxSplit * H * D, 1};
+        GemmArgs fw1{H, D, n, f->dpre2T, T, 1, f->xmT, 1, T, nullptr, 0, nullptr, 0, nullptr, 0, split, wp, 1};
+        const gw::flow::LayerStrides ls{{kOutPad * T, H * T, H * T}, {H * T, H * T, kInPad * T},
+                                        {f->w_layer, f->w_layer, f->w_layer}};
+        GW_TRY(gw::flow::gemm_bf16_group3(fw3, fw2, fw1, s, L, &ls));
     }
     gw::flow::GradParts parts{D, H, split, fused_width(f) ? rb16 : rb64, f->rb_cap, f->per_layer, f->n_params,
                               f->w_layer, f->b_layer, f->wpart, f->bpart};

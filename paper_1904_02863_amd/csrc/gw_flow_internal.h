@@ -56,9 +56,18 @@ struct GemmArgs {
 constexpr int kMaxSplit = 16;
 
 hipError_t gemm_bf16(const GemmArgs &g, hipStream_t stream);
+// Per-layer element strides of a grouped launch over several layers: product
+// p of layer l reads A + l sA[p] and B + l sB[p] and writes its slices to
+// partial + l sP[p] (multiples of 8 elements).
+struct LayerStrides {
+    int64_t sA[3], sB[3], sP[3];
+};
+
 // Three products in one launch (k-contiguous operands, split-K slices left
-// in their partial buffers).
-hipError_t gemm_bf16_group3(const GemmArgs &a, const GemmArgs &b, const GemmArgs &c, hipStream_t stream);
+// in their partial buffers); with layers > 1 and strides, the same three for
+// each of `layers` layers, layer by layer.
+hipError_t gemm_bf16_group3(const GemmArgs &a, const GemmArgs &b, const GemmArgs &c, hipStream_t stream,
+                            int layers = 1, const LayerStrides *strides = nullptr);
 
 }  // namespace flow
 }  // namespace gw
