@@ -565,11 +565,27 @@ __device__ __forceinline__ void products_from_lds(float4_t (&acc)[H / 64], const
     }
 }
 
+// A chain of couplings applied to the same rows in the order of c.layer[]:
+// coupling li + 1 takes coupling li's output rows.  A row's chain does not
+// involve the other rows, so one block carries its 16 rows through every
+// coupling of the chain: the output element of thread (row, dimension) stays
+// in its register as that thread's input of the next coupling, the next
+// coupling's masked BF16 input in LDS, and each row's sum of log-scales in a
+// register of one thread.  Every coupling still writes its outputs to global
+// memory (the backward pass and the weight gradients read them).  The
+// couplings share n, dim and sum_s.
+constexpr int kMaxChain = 16;
+struct LayerChain {
+    LayerArgs layer[kMaxChain];
+    int count;
+};
+
 template <int H>
-__global__ __launch_bounds__(256) void layer_kernel(LayerArgs p)
+__global__ __launch_bounds__(256) void layer_kernel(LayerChain c)
 {
     __shared__ __align__(16) uint16_t h1s[kLayerRows][H + 8];
     __shared__ __align__(16) uint16_t h2s[kLayerRows][H + 8];
+    __shared__ __align__(16) uint16_t xin[kLayerRows][kInPad];
     __shared__ float outs[kLayerRows][kOutPad];
     __shared__ double sdet[kLayerRows][16];
     constexpr int NT = H / 64;            // 16-column tiles per wave
@@ -577,102 +593,115 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerArgs p)
     const int r0 = blockIdx.x * kLayerRows;
     const int lr = lane & 15, g = lane >> 4;
     const int c0 = wave * (H / 4);
-    const bool row_ok = r0 + lr < p.n;
+    const int crr = tid >> 4, ci = tid & 15;   // the coupling's (row, dimension)
     const bf16x8_t zero8 = {};
-    // Every operand is loaded now, unconditionally (clamped to valid rows), in
-    // the order of use: the loads complete in order, so that a use waits only
-    // for its own load and those before it, and a load under a branch would
-    // make the wave wait for all of them.  The biases and this thread's input
-    // element of the coupling, the first product's input rows and W1
-    // fragments, then W2's, then W3's.
-    const int n_out = 2 * p.dim;
-    const int ocol = 16 * (wave & 1) + lr;
-    float b1v[NT], b2v[NT];
+    const int n = c.layer[0].n, dim = c.layer[0].dim;
+    const bool row_ok = r0 + lr < n;
+    // the rows' inputs of the first coupling, loaded first (rows clamped to valid ones)
+    double yv = c.layer[0].a[(int64_t)min(r0 + crr, n - 1) * dim + min(ci, dim - 1)];
+    const bf16x8_t xl0 = ld_bf16x8(c.layer[0].xm + (int64_t)min(r0 + lr, n - 1) * kInPad + 8 * (g & 1));
+    double srow = c.layer[0].sum_s[min(r0 + (tid & 15), n - 1)];   // used by threads 0-15
+    for (int li = 0; li < c.count; ++li) {
+        const LayerArgs &p = c.layer[li];
+        // Every operand of the coupling is loaded now, unconditionally
+        // (clamped to valid rows), in the order of use: the loads complete in
+        // order, so that a use waits only for its own load and those before
+        // it, and a load under a branch would make the wave wait for all of
+        // them.  The biases, W1's fragments, then W2's, then W3's.
+        const int n_out = 2 * dim;
+        const int ocol = 16 * (wave & 1) + lr;
+        float b1v[NT], b2v[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        b1v[t] = p.b1[c0 + 16 * t + lr];
-        b2v[t] = p.b2[c0 + 16 * t + lr];
-    }
-    const float b3v = p.b3[min(ocol, n_out - 1)];
-    const int crr = tid >> 4, ci = tid & 15;
-    const double a_in = p.a[(int64_t)min(r0 + crr, p.n - 1) * p.dim + min(ci, p.dim - 1)];
-    const bf16x8_t xl = ld_bf16x8(p.xm + (int64_t)min(r0 + lr, p.n - 1) * kInPad + 8 * (g & 1));
-    // lane groups 2 and 3 hold the zero padding of K from kInPad to 32 (in the
-    // input rows, so W1's fragments there may repeat real ones)
-    bf16x8_t w1f[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) w1f[t] = ld_bf16x8(p.w1p + (int64_t)(c0 + 16 * t + lr) * kInPad + 8 * (g & 1));
-    bf16x8_t w2f[NT][H / 32];
-    load_square_frags<H>(w2f, p.w2, c0, g, lr);
-    // output columns past 2 dim repeat the last one (never read)
-    bf16x8_t w3f[H / 32];
-#pragma unroll
-    for (int k = 0; k < H / 32; ++k) w3f[k] = ld_bf16x8(p.w3 + (int64_t)min(ocol, n_out - 1) * H + 32 * k + 8 * g);
-    __builtin_amdgcn_sched_barrier(0);   // all loads issued before the first product waits on its own
-    // h1 = relu(xm W1^T + b1), K = kInPad padded to 32 by zeros
-    const bf16x8_t xa = (g < 2 && row_ok) ? xl : zero8;
-    float4_t acc[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa, w1f[t], float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-    store_hidden<H>(p, h1s, p.h1, p.h1T, acc, b1v, r0, c0, g, lr);
-    __syncthreads();
-    // h2 = relu(h1 W2^T + b2), K = H
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = float4_t{0.f, 0.f, 0.f, 0.f};
-    products_from_lds<H>(acc, h1s, w2f, g, lr);
-    store_hidden<H>(p, h2s, p.h2, p.h2T, acc, b2v, r0, c0, g, lr);
-    __syncthreads();
-    // out = h2 W3^T + b3: 2 dim <= 32 columns, one 16-column tile for each of waves 0 and 1
-    if (wave < 2) {
-        const int col = ocol;
-        float4_t o = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int k = 0; k < H / 32; ++k) {
-            const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&h2s[lr][32 * k + 8 * g]);
-            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w3f[k], o, 0, 0, 0);
+        for (int t = 0; t < NT; ++t) {
+            b1v[t] = p.b1[c0 + 16 * t + lr];
+            b2v[t] = p.b2[c0 + 16 * t + lr];
         }
-        const float bc = col < n_out ? b3v : 0.f;
+        const float b3v = p.b3[min(ocol, n_out - 1)];
+        // lane groups 2 and 3 hold the zero padding of K from kInPad to 32 (in
+        // the input rows, so W1's fragments there may repeat real ones)
+        bf16x8_t w1f[NT];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) outs[4 * g + r][col] = o[r] + bc;
-    }
-    __syncthreads();
-    // the coupling: thread (row, i) = (tid / 16, tid % 16) takes dimension i
-    // of a row, then each row's log-determinant terms are added in dimension
-    // order by one thread (the order of the row-at-a-time kernel)
-    {
-        const int rr = crr, i = ci;
-        const int b = r0 + rr;
-        double sv = 0.0;
-        if (b < p.n && i < p.dim) {
-            const double ai = a_in;
-            double yi = ai;
-            if (!((p.cond >> i) & 1u)) {
-                const double r = (double)outs[rr][i];
-                const double t = (double)outs[rr][p.dim + i];
-                sv = 3.0 * tanh(r / 3.0);
-                yi = p.dir > 0 ? ai * exp(sv) + t : (ai - t) * exp(-sv);
+        for (int t = 0; t < NT; ++t)
+            w1f[t] = ld_bf16x8(p.w1p + (int64_t)(c0 + 16 * t + lr) * kInPad + 8 * (g & 1));
+        bf16x8_t w2f[NT][H / 32];
+        load_square_frags<H>(w2f, p.w2, c0, g, lr);
+        // output columns past 2 dim repeat the last one (never read)
+        bf16x8_t w3f[H / 32];
+#pragma unroll
+        for (int k = 0; k < H / 32; ++k)
+            w3f[k] = ld_bf16x8(p.w3 + (int64_t)min(ocol, n_out - 1) * H + 32 * k + 8 * g);
+        __builtin_amdgcn_sched_barrier(0);   // all loads issued before the first product waits on its own
+        // h1 = relu(xm W1^T + b1), K = kInPad padded to 32 by zeros; the input
+        // rows of the first coupling from global memory, of the others from LDS
+        const bf16x8_t xs = *reinterpret_cast<const bf16x8_t *>(&xin[lr][8 * (g & 1)]);
+        const bf16x8_t xa = (g < 2 && row_ok) ? (li == 0 ? xl0 : xs) : zero8;
+        float4_t acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa, w1f[t], float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        store_hidden<H>(p, h1s, p.h1, p.h1T, acc, b1v, r0, c0, g, lr);
+        __syncthreads();
+        // h2 = relu(h1 W2^T + b2), K = H
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = float4_t{0.f, 0.f, 0.f, 0.f};
+        products_from_lds<H>(acc, h1s, w2f, g, lr);
+        store_hidden<H>(p, h2s, p.h2, p.h2T, acc, b2v, r0, c0, g, lr);
+        __syncthreads();
+        // out = h2 W3^T + b3: 2 dim <= 32 columns, one 16-column tile for each of waves 0 and 1
+        if (wave < 2) {
+            const int col = ocol;
+            float4_t o = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < H / 32; ++k) {
+                const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&h2s[lr][32 * k + 8 * g]);
+                o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w3f[k], o, 0, 0, 0);
             }
-            p.y[(int64_t)b * p.dim + i] = yi;
-            if (p.s_out) p.s_out[(int64_t)b * p.dim + i] = sv;
-            if (p.nm.xm) {
-                const uint16_t v = ((p.nm.cond >> i) & 1u) ? f32_to_bf16((float)yi) : (uint16_t)0;
-                p.nm.xm[(int64_t)b * kInPad + i] = v;
-                if (p.nm.xmT) p.nm.xmT[i * p.nm.ldT + b] = v;
-            }
-        } else if (b < p.n && p.nm.xm) {
-            p.nm.xm[(int64_t)b * kInPad + i] = 0;         // dimensions past dim of the next input
-            if (p.nm.xmT) p.nm.xmT[i * p.nm.ldT + b] = 0;
+            const float bc = col < n_out ? b3v : 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) outs[4 * g + r][col] = o[r] + bc;
         }
-        sdet[rr][i] = sv;
+        __syncthreads();
+        // the coupling: thread (row, i) = (tid / 16, tid % 16) takes dimension
+        // i of a row, then each row's log-determinant terms are added in
+        // dimension order by one thread (the order of the row-at-a-time kernel)
+        {
+            const int rr = crr, i = ci;
+            const int b = r0 + rr;
+            double sv = 0.0;
+            uint16_t xv = 0;
+            if (b < n && i < dim) {
+                const double ai = yv;
+                double yi = ai;
+                if (!((p.cond >> i) & 1u)) {
+                    const double r = (double)outs[rr][i];
+                    const double t = (double)outs[rr][dim + i];
+                    sv = 3.0 * tanh(r / 3.0);
+                    yi = p.dir > 0 ? ai * exp(sv) + t : (ai - t) * exp(-sv);
+                }
+                p.y[(int64_t)b * dim + i] = yi;
+                if (p.s_out) p.s_out[(int64_t)b * dim + i] = sv;
+                xv = ((p.nm.cond >> i) & 1u) ? f32_to_bf16((float)yi) : (uint16_t)0;
+                if (p.nm.xm) {
+                    p.nm.xm[(int64_t)b * kInPad + i] = xv;
+                    if (p.nm.xmT) p.nm.xmT[i * p.nm.ldT + b] = xv;
+                }
+                yv = yi;
+            } else if (b < n && p.nm.xm) {
+                p.nm.xm[(int64_t)b * kInPad + i] = 0;         // dimensions past dim of the next input
+                if (p.nm.xmT) p.nm.xmT[i * p.nm.ldT + b] = 0;
+            }
+            sdet[rr][i] = sv;
+            xin[rr][i] = xv;                                  // the next coupling's input row
+        }
+        __syncthreads();
+        if (tid < kLayerRows) {
+            double acc_s = 0.0;
+            for (int i = 0; i < dim; ++i)
+                if (!((p.cond >> i) & 1u)) acc_s += sdet[tid][i];
+            srow += acc_s;
+        }
     }
-    __syncthreads();
-    if (tid < kLayerRows && r0 + tid < p.n) {
-        double acc = 0.0;
-        for (int i = 0; i < p.dim; ++i)
-            if (!((p.cond >> i) & 1u)) acc += sdet[tid][i];
-        p.sum_s[r0 + tid] += acc;
-    }
+    if (tid < kLayerRows && r0 + tid < n) c.layer[0].sum_s[r0 + tid] = srow;
 }
 
 // Affine normalisation around the coupling stack: forward x = mu + sigma u,
@@ -1366,8 +1395,19 @@ hipError_t mlp_forward(gw_flow *f, int l, int n, bool keep_t, hipStream_t s)
 // width has no such kernel and the products run as separate GEMMs.
 bool fused_width(const gw_flow *f) { return f->hidden == 128 || f->hidden == 256; }
 
-hipError_t layer_fused(gw_flow *f, int l, int n, int dir, const double *a, double *y, double *s_out, bool keep_t,
-                       gw::flow::NextMask nm, hipStream_t s)
+// Where the kernel producing layer l's input writes that layer's masked
+// MLP input (and, with keep_t, its transposed copy); none for l outside the stack.
+gw::flow::NextMask mask_of(gw_flow *f, int l, bool keep_t)
+{
+    if (l < 0 || l >= f->layers) return gw::flow::NextMask{nullptr, nullptr, 0, 0u};
+    return gw::flow::NextMask{f->xm_b + (int64_t)l * f->cap * kInPad,
+                              keep_t ? f->xmT + (int64_t)l * kInPad * f->ldT : nullptr, f->ldT, f->cond[l]};
+}
+
+// The arguments of coupling l of the one-kernel path: input rows a, output
+// rows y (and with s_out the log-scales), the next coupling's masked input nm.
+gw::flow::LayerArgs layer_args(gw_flow *f, int l, int n, int dir, const double *a, double *y, double *s_out,
+                               bool keep_t, gw::flow::NextMask nm)
 {
     const int D = f->dim, H = f->hidden;
     const LayerOff o = layer_off(f, l);
@@ -1395,21 +1435,40 @@ hipError_t layer_fused(gw_flow *f, int l, int n, int dir, const double *a, doubl
     la.sum_s = f->sum_s;
     la.s_out = s_out;
     la.nm = nm;
-    const dim3 grid((unsigned)((n + gw::flow::kLayerRows - 1) / gw::flow::kLayerRows));
-    if (H == 256)
-        hipLaunchKernelGGL(gw::flow::layer_kernel<256>, grid, dim3(256), 0, s, la);
-    else
-        hipLaunchKernelGGL(gw::flow::layer_kernel<128>, grid, dim3(256), 0, s, la);
-    return hipGetLastError();
+    return la;
 }
 
-// Where the kernel producing layer l's input writes that layer's masked
-// MLP input (and, with keep_t, its transposed copy); none for l outside the stack.
-gw::flow::NextMask mask_of(gw_flow *f, int l, bool keep_t)
+// Couplings first, first + step, ... (count of them, step +1 or -1) applied in
+// that order to rows [0, n) by one launch per kMaxChain couplings.  dir: +1
+// the forward direction (z -> x), -1 the inverse.  Boundary l is coupling l's
+// input in the forward direction; with keep_t (inverse, training) the
+// transposed activations and inputs and the log-scales are kept.
+hipError_t layer_chain(gw_flow *f, int n, int dir, int first, int count, bool keep_t, hipStream_t s)
 {
-    if (l < 0 || l >= f->layers) return gw::flow::NextMask{nullptr, nullptr, 0, 0u};
-    return gw::flow::NextMask{f->xm_b + (int64_t)l * f->cap * kInPad,
-                              keep_t ? f->xmT + (int64_t)l * kInPad * f->ldT : nullptr, f->ldT, f->cond[l]};
+    const int H = f->hidden, D = f->dim;
+    const int step = dir > 0 ? 1 : -1;
+    for (int done = 0; done < count;) {
+        gw::flow::LayerChain c;
+        c.count = std::min(count - done, gw::flow::kMaxChain);
+        for (int k = 0; k < c.count; ++k) {
+            const int l = first + step * (done + k);
+            if (dir > 0)
+                c.layer[k] = layer_args(f, l, n, 1, boundary(f, l), boundary(f, l + 1), nullptr, false,
+                                        mask_of(f, l + 1, false));
+            else
+                c.layer[k] = layer_args(f, l, n, -1, boundary(f, l + 1), boundary(f, l),
+                                        f->s_store + (int64_t)l * f->cap * D, keep_t, mask_of(f, l - 1, keep_t));
+        }
+        const dim3 grid((unsigned)((n + gw::flow::kLayerRows - 1) / gw::flow::kLayerRows));
+        if (H == 256)
+            hipLaunchKernelGGL(gw::flow::layer_kernel<256>, grid, dim3(256), 0, s, c);
+        else
+            hipLaunchKernelGGL(gw::flow::layer_kernel<128>, grid, dim3(256), 0, s, c);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        done += c.count;
+    }
+    return hipSuccess;
 }
 
 #define GW_TRY(expr)                         \
@@ -1436,13 +1495,9 @@ hipError_t inverse_pass(gw_flow *f, int n, const double *x, bool keep_t, hipStre
     hipLaunchKernelGGL(gw::flow::affine_kernel, dim3((n + 15) / 16), dim3(256), 0, s, n, D, -1, f->mu, f->log_sigma,
                        x, boundary(f, L), f->sum_s, 1, mask_of(f, L - 1, keep_t));
     GW_TRY(hipGetLastError());
+    if (fused_width(f)) return layer_chain(f, n, -1, L - 1, L, keep_t, s);
     for (int l = L - 1; l >= 0; --l) {
         double *s_out = f->s_store + (int64_t)l * f->cap * D;
-        if (fused_width(f)) {
-            GW_TRY(layer_fused(f, l, n, -1, boundary(f, l + 1), boundary(f, l), s_out, keep_t,
-                               mask_of(f, l - 1, keep_t), s));
-            continue;
-        }
         GW_TRY(mlp_forward(f, l, n, keep_t, s));
         hipLaunchKernelGGL(gw::flow::coupling_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], -1,
                            boundary(f, l + 1), f->out_f, boundary(f, l), f->sum_s, s_out, mask_of(f, l - 1, keep_t));
@@ -1462,12 +1517,8 @@ hipError_t forward_pass(gw_flow *f, int n, const double *z, hipStream_t s)
     hipLaunchKernelGGL(gw::flow::mask_input_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, m0.cond, z, m0.xm,
                        nullptr, f->ldT);
     GW_TRY(hipGetLastError());
-    for (int l = 0; l < L; ++l) {
-        if (fused_width(f)) {
-            GW_TRY(layer_fused(f, l, n, 1, boundary(f, l), boundary(f, l + 1), nullptr, false,
-                               mask_of(f, l + 1, false), s));
-            continue;
-        }
+    if (fused_width(f)) GW_TRY(layer_chain(f, n, 1, 0, L, false, s));
+    for (int l = 0; l < L && !fused_width(f); ++l) {
         GW_TRY(mlp_forward(f, l, n, false, s));
         hipLaunchKernelGGL(gw::flow::coupling_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], 1,
                            boundary(f, l), f->out_f, boundary(f, l + 1), f->sum_s, nullptr,
