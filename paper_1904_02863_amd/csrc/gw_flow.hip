@@ -822,109 +822,130 @@ __device__ __forceinline__ void masked_hidden(const BackArgs &p, uint16_t (*ds)[
     }
 }
 
+// The backward couplings of a chain, in the order of c.layer[], carried
+// through by one block per 16 rows as in layer_kernel: coupling li + 1 takes
+// d loss / d y of coupling li as its d loss / d x, kept in LDS between them
+// (the direct part from the head, then the MLP's part on the conditioning
+// dimensions added to it).  Every coupling still writes its transposed
+// operands of the weight gradients and its bias partials to global memory;
+// the last one also writes d loss / d y.  The couplings share n and dim.
+struct BackChain {
+    BackArgs layer[kMaxChain];
+    int count;
+};
+
 template <int H>
-__global__ __launch_bounds__(256) void layer_back_kernel(BackArgs p)
+__global__ __launch_bounds__(256) void layer_back_kernel(BackChain c)
 {
     __shared__ float dos[kLayerRows][kOutPad];
     __shared__ __align__(16) uint16_t d2s[kLayerRows][H + 8];
     __shared__ __align__(16) uint16_t d1s[kLayerRows][H + 8];
+    __shared__ double gys[kLayerRows][16];
     constexpr int NT = H / 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r0 = blockIdx.x * kLayerRows;
     const int lr = lane & 15, g = lane >> 4;
     const int c0 = wave * (H / 4);
-    const int D = p.dim;
-    // Every operand is loaded now, unconditionally (clamped to valid rows), in
-    // the order of use (the loads complete in order; a load under a branch
-    // would make the wave wait for all of them): this thread's element of the
-    // head, the activations' signs for the two ReLU masks (4 rows of a
-    // column in 8 bytes of the transposed copies), then the weight fragments
-    // of the three products (W1's rows past dim repeat the last, never read).
+    const int n = c.layer[0].n, D = c.layer[0].dim;
     const int rr = tid >> 4, i = tid & 15;   // the head's (row, dimension)
-    const int64_t oc = (int64_t)min(r0 + rr, p.n - 1) * D + min(i, D - 1);
-    const double gv = p.g[oc], xv = p.x[oc], sv = p.s[oc];
-    uint2 m2[NT], m1[NT];
+    const int64_t oc = (int64_t)min(r0 + rr, n - 1) * D + min(i, D - 1);
+    double gv = c.layer[0].g[oc];            // d loss / d x of the first coupling, loaded first
+    for (int li = 0; li < c.count; ++li) {
+        const BackArgs &p = c.layer[li];
+        // Every operand is loaded now, unconditionally (clamped to valid
+        // rows), in the order of use (the loads complete in order; a load
+        // under a branch would make the wave wait for all of them): this
+        // thread's element of the head, the activations' signs for the two
+        // ReLU masks (4 rows of a column in 8 bytes of the transposed copies),
+        // then the weight fragments of the three products (W1's rows past dim
+        // repeat the last, never read).
+        const double xv = p.x[oc], sv = p.s[oc];
+        uint2 m2[NT], m1[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int64_t at = (int64_t)(c0 + 16 * t + lr) * p.ldT + r0 + 4 * g;
-        m2[t] = *reinterpret_cast<const uint2 *>(p.h2T + at);
-        m1[t] = *reinterpret_cast<const uint2 *>(p.h1T + at);
-    }
-    bf16x8_t w3f[NT], w2f[NT][H / 32], w1f[H / 32];
+        for (int t = 0; t < NT; ++t) {
+            const int64_t at = (int64_t)(c0 + 16 * t + lr) * p.ldT + r0 + 4 * g;
+            m2[t] = *reinterpret_cast<const uint2 *>(p.h2T + at);
+            m1[t] = *reinterpret_cast<const uint2 *>(p.h1T + at);
+        }
+        bf16x8_t w3f[NT], w2f[NT][H / 32], w1f[H / 32];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) w3f[t] = ld_bf16x8(p.w3t + (int64_t)(c0 + 16 * t + lr) * kOutPad + 8 * g);
-    load_square_frags<H>(w2f, p.w2t, c0, g, lr);
+        for (int t = 0; t < NT; ++t) w3f[t] = ld_bf16x8(p.w3t + (int64_t)(c0 + 16 * t + lr) * kOutPad + 8 * g);
+        load_square_frags<H>(w2f, p.w2t, c0, g, lr);
 #pragma unroll
-    for (int k = 0; k < H / 32; ++k) w1f[k] = ld_bf16x8(p.w1t + (int64_t)min(lr, D - 1) * H + 32 * k + 8 * g);
-    // the inverse coupling's backward: thread (row, i) = (tid / 16, tid % 16)
-    // takes dimension i of a row (dout columns i and D + i)
-    {
-        const int b = r0 + rr;
-        dos[rr][i] = 0.f;
-        dos[rr][16 + i] = 0.f;
-        __syncthreads();
-        if (b < p.n && i < D) {
-            const int64_t o = (int64_t)b * D + i;
-            if ((p.cond >> i) & 1u) {
-                p.gy[o] = gv;
-            } else {
-                const double inv_n = 1.0 / (double)p.n;
-                const double si = sv, e = exp(-si);
-                const double dt = -gv * e;
-                const double ds = -gv * xv + inv_n;
-                const double dr = ds * (1.0 - (si / 3.0) * (si / 3.0));
-                p.gy[o] = gv * e;
-                dos[rr][i] = (float)dr;
-                dos[rr][D + i] = (float)dt;
+        for (int k = 0; k < H / 32; ++k) w1f[k] = ld_bf16x8(p.w1t + (int64_t)min(lr, D - 1) * H + 32 * k + 8 * g);
+        // the inverse coupling's backward: thread (row, i) = (tid / 16, tid % 16)
+        // takes dimension i of a row (dout columns i and D + i)
+        {
+            const int b = r0 + rr;
+            dos[rr][i] = 0.f;
+            dos[rr][16 + i] = 0.f;
+            if (li > 0) gv = gys[rr][i];     // the previous coupling's d loss / d y
+            __syncthreads();
+            double gd = 0.0;                 // the direct part of d loss / d y
+            if (b < n && i < D) {
+                if ((p.cond >> i) & 1u) {
+                    gd = gv;
+                } else {
+                    const double inv_n = 1.0 / (double)n;
+                    const double si = sv, e = exp(-si);
+                    const double dt = -gv * e;
+                    const double ds = -gv * xv + inv_n;
+                    const double dr = ds * (1.0 - (si / 3.0) * (si / 3.0));
+                    gd = gv * e;
+                    dos[rr][i] = (float)dr;
+                    dos[rr][D + i] = (float)dt;
+                }
+            }
+            gys[rr][i] = gd;
+            __syncthreads();
+            if (b < n) {
+                p.doutT[(int64_t)i * p.ldT + b] = f32_to_bf16(dos[rr][i]);
+                p.doutT[(int64_t)(16 + i) * p.ldT + b] = f32_to_bf16(dos[rr][16 + i]);
             }
         }
         __syncthreads();
-        if (b < p.n) {
-            p.doutT[(int64_t)i * p.ldT + b] = f32_to_bf16(dos[rr][i]);
-            p.doutT[(int64_t)(16 + i) * p.ldT + b] = f32_to_bf16(dos[rr][16 + i]);
+        if (tid < 2 * D) {
+            double t = 0.0;
+            for (int r = 0; r < kLayerRows; ++r) t += (double)dos[r][tid];
+            p.bp3[(int64_t)blockIdx.x * 2 * D + tid] = t;
         }
-    }
-    __syncthreads();
-    if (tid < 2 * D) {
-        double t = 0.0;
-        for (int r = 0; r < kLayerRows; ++r) t += (double)dos[r][tid];
-        p.bp3[(int64_t)blockIdx.x * 2 * D + tid] = t;
-    }
-    // dh2 = dout W3 (K = 2 dim <= 32 in one step), masked by h2 > 0
-    float4_t acc[NT];
-    {
-        bf16x8_t av;
+        // dh2 = dout W3 (K = 2 dim <= 32 in one step), masked by h2 > 0
+        float4_t acc[NT];
+        {
+            bf16x8_t av;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) av[e] = (__bf16)dos[lr][8 * g + e];
+            for (int e = 0; e < 8; ++e) av[e] = (__bf16)dos[lr][8 * g + e];
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w3f[t], float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-    }
-    masked_hidden<H>(p, d2s, p.dpreT, p.bp2, acc, m2, r0, c0, g, lr);
-    __syncthreads();
-    // dh1 = dpre2 W2 (B(k, j) = W2[k][j] = W2^T[j][k]), masked by h1 > 0
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = float4_t{0.f, 0.f, 0.f, 0.f};
-    products_from_lds<H>(acc, d2s, w2f, g, lr);
-    masked_hidden<H>(p, d1s, p.dpre2T, p.bp1, acc, m1, r0, c0, g, lr);
-    __syncthreads();
-    // dxm = dpre1 W1 (B(k, d) = W1[k][d] = W1^T[d][k]), added into gy on the conditioning dims
-    if (wave == 0) {
-        const int col = lr;
-        float4_t o = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int k = 0; k < H / 32; ++k) {
-            const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&d1s[lr][32 * k + 8 * g]);
-            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w1f[k], o, 0, 0, 0);
+            for (int t = 0; t < NT; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w3f[t], float4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
         }
-        if (col < D && ((p.cond >> col) & 1u)) {
+        masked_hidden<H>(p, d2s, p.dpreT, p.bp2, acc, m2, r0, c0, g, lr);
+        __syncthreads();
+        // dh1 = dpre2 W2 (B(k, j) = W2[k][j] = W2^T[j][k]), masked by h1 > 0
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = r0 + 4 * g + r;
-                if (i < p.n) p.gy[(int64_t)i * D + col] += (double)o[r];
+        for (int t = 0; t < NT; ++t) acc[t] = float4_t{0.f, 0.f, 0.f, 0.f};
+        products_from_lds<H>(acc, d2s, w2f, g, lr);
+        masked_hidden<H>(p, d1s, p.dpre2T, p.bp1, acc, m1, r0, c0, g, lr);
+        __syncthreads();
+        // dxm = dpre1 W1 (B(k, d) = W1[k][d] = W1^T[d][k]), added into d loss / d y on the conditioning dims
+        if (wave == 0) {
+            const int col = lr;
+            float4_t o = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < H / 32; ++k) {
+                const bf16x8_t av = *reinterpret_cast<const bf16x8_t *>(&d1s[lr][32 * k + 8 * g]);
+                o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w1f[k], o, 0, 0, 0);
+            }
+            if (col < D && ((p.cond >> col) & 1u)) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (r0 + 4 * g + r < n) gys[4 * g + r][col] += (double)o[r];
             }
         }
+        __syncthreads();
     }
+    const BackArgs &pl = c.layer[c.count - 1];
+    if (r0 + rr < n && i < D) pl.gy[(int64_t)(r0 + rr) * D + i] = gys[rr][i];
 }
 
 // ---------------------------------------------------------------- training backward
@@ -1558,6 +1579,8 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
     // Every gradient of layer l is left as partial sums (split-K slices of the
     // weights, row-block sums of the biases) and summed by one kernel at the end.
     const int rb64 = (n + 63) / 64, rb16 = (n + gw::flow::kLayerRows - 1) / gw::flow::kLayerRows;
+    gw::flow::BackChain chain;
+    chain.count = 0;
     for (int l = 0; l < L; ++l) {
         float *wp = f->wpart + l * f->w_layer;
         double *bp = f->bpart + l * f->b_layer;
@@ -1574,16 +1597,21 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
         const int64_t w2t = (int64_t)D * H, w3t = (int64_t)D * H + (int64_t)H * H;
         if (fused_width(f)) {
             // the coupling's transposed operands of its weight gradients go to
-            // layer l's slices, for the one launch of all layers' products below
+            // layer l's slices, for the one launch of all layers' products
+            // below; the couplings go out in chains of up to kMaxChain
             gw::flow::BackArgs ba{n, D, f->cond[l], f->g, boundary(f, l), f->s_store + (int64_t)l * f->cap * D, f->gy,
                                   h1T, h2T, wt, wt + w2t, wt + w3t, f->doutT + (int64_t)l * kOutPad * T,
                                   f->dpreT + (int64_t)l * H * T, f->dpre2T + (int64_t)l * H * T, T, bp1, bp2, bp3};
-            const dim3 grid((unsigned)rb16);
-            if (H == 256)
-                hipLaunchKernelGGL(gw::flow::layer_back_kernel<256>, grid, dim3(256), 0, s, ba);
-            else
-                hipLaunchKernelGGL(gw::flow::layer_back_kernel<128>, grid, dim3(256), 0, s, ba);
-            GW_TRY(hipGetLastError());
+            chain.layer[chain.count++] = ba;
+            if (chain.count == gw::flow::kMaxChain || l == L - 1) {
+                const dim3 grid((unsigned)rb16);
+                if (H == 256)
+                    hipLaunchKernelGGL(gw::flow::layer_back_kernel<256>, grid, dim3(256), 0, s, chain);
+                else
+                    hipLaunchKernelGGL(gw::flow::layer_back_kernel<128>, grid, dim3(256), 0, s, chain);
+                GW_TRY(hipGetLastError());
+                chain.count = 0;
+            }
             std::swap(f->g, f->gy);      // d loss / d(boundary l + 1)
             continue;
         }
