@@ -240,6 +240,63 @@ def test_flow_gradients_match_oracle(gw, n):
         assert (g[where[f"l{l}.w1"]].reshape(256, 11)[:, off] == 0).all()
 
 
+def test_flow_longer_than_one_launch(gw):
+    """20 couplings of hidden width 128: a launch carries the rows through at
+    most 16 couplings of a pass, so the rows cross from one launch to the
+    next in both directions.  The forward pass equals bit for bit two
+    10-coupling flows in a row (the first with the identity normalisation),
+    whose passes each fit one launch; the forward pass and every gradient
+    agree with the float64 oracle within the BF16 rounding bound, as in the
+    tests above (4096 rows, as there: one row's share of a gradient, which a
+    ReLU decided on the other side of zero moves, stays below the bound), and
+    the inverse undoes the forward."""
+    from oracle.flow import parameter_groups, rounding_spread, rounding_tolerance
+    layers, hidden = 20, 128
+    f, args = _flow_pair(gw, hidden=hidden, layers=layers, seed=4)
+    n = 600
+    z = np.random.default_rng(7).standard_normal((n, 11))
+    zt = torch.from_numpy(z).to(DEV)
+    x, lq = f.forward(zt)
+    _, masks, _, p, mu, ls = args
+    per = p.size // layers
+    first = gw.Flow(11, masks[:10], hidden=hidden)
+    first.set_params(p[:10 * per], np.zeros(11), np.zeros(11))
+    second = gw.Flow(11, masks[10:], hidden=hidden)
+    second.set_params(p[10 * per:], mu, ls)
+    u, _ = first.forward(zt)
+    x2, _ = second.forward(u)
+    assert torch.equal(x2, x)
+    x, lq = x.cpu().numpy(), lq.cpu().numpy()
+
+    def forward(flow):
+        ex, elq = flow.forward(torch.tensor(z))
+        return np.concatenate([ex.detach().numpy().ravel(), elq.detach().numpy()])
+
+    exact, sigma = rounding_spread(lambda r: OracleFlow(*args, rounding=r), forward, runs=24, seed=13)
+    tol = rounding_tolerance(sigma, [("x", slice(0, 11 * n)), ("logq", slice(11 * n, 12 * n))])
+    _check_within_rounding("x", x.ravel(), exact[:11 * n], tol[:11 * n])
+    _check_within_rounding("log q", lq, exact[11 * n:], tol[11 * n:])
+    z2, lq2 = f.inverse(torch.from_numpy(x).to(DEV))
+    np.testing.assert_allclose(z2.cpu().numpy(), z, atol=1e-9)
+    np.testing.assert_allclose(lq2.cpu().numpy(), lq, atol=1e-9)
+
+    xs = np.random.default_rng(8).standard_normal((4096, 11)) * 1.3 + 0.2
+    g, loss = f.gradients(torch.from_numpy(xs).to(DEV))
+    g = g.cpu().numpy().astype(np.float64)
+
+    def gradients(flow):
+        grad, l = flow.gradients(xs)
+        return np.concatenate([grad, [l]])
+
+    exact, sigma = rounding_spread(lambda r: OracleFlow(*args, rounding=r), gradients, runs=24, seed=14)
+    groups = parameter_groups(11, hidden, layers)
+    npar = g.size
+    tol = rounding_tolerance(sigma, groups + [("loss", slice(npar, npar + 1))])
+    for name, sl in groups:
+        _check_within_rounding(name, g[sl], exact[sl], tol[sl])
+    _check_within_rounding("loss", np.array([float(loss.item())]), exact[npar:], tol[npar:])
+
+
 def test_flow_gradients_of_repeated_rows(gw):
     """The loss is a mean over rows, so a batch and the same batch twice have
     the same gradient.  300 rows (one K slice, ragged row blocks of 64 and
