@@ -579,6 +579,7 @@ struct LayerChain {
     LayerArgs layer[kMaxChain];
     int count;
 };
+static_assert(sizeof(LayerChain) <= 4096, "a chain is passed by value as the kernel's arguments (4 KiB at most)");
 
 template <int H>
 __global__ __launch_bounds__(256) void layer_kernel(LayerChain c)
@@ -833,6 +834,7 @@ struct BackChain {
     BackArgs layer[kMaxChain];
     int count;
 };
+static_assert(sizeof(BackChain) <= 4096, "a chain is passed by value as the kernel's arguments (4 KiB at most)");
 
 template <int H>
 __global__ __launch_bounds__(256) void layer_back_kernel(BackChain c)
