@@ -1269,11 +1269,13 @@ struct gw_flow {
     uint16_t *dpre2_b = nullptr;          // [cap][hidden], the other layer's BF16 pre-activation gradient
     // transposed BF16 copies for the weight gradients (row length ldT, a
     // multiple of 64 >= cap): activations [layers][hidden][ldT], inputs
-    // [layers][kInPad][ldT], output gradients [kOutPad][ldT], the two
-    // pre-activation gradients [hidden][ldT]
+    // [layers][kInPad][ldT], output gradients [layers][kOutPad][ldT], the two
+    // pre-activation gradients [layers][hidden][ldT] (the GEMM path uses the
+    // first layer's slices of the last three for every layer)
     int64_t ldT = 0;
     uint16_t *h1T = nullptr, *h2T = nullptr, *xmT = nullptr, *doutT = nullptr, *dpreT = nullptr, *dpre2T = nullptr;
-    // partial sums of the gradients (summed by grad_finish_kernel): per layer,
+    // partial sums of the gradients (summed by grad_finish_kernel or, in a
+    // training step, finish_update_kernel): per layer,
     // split-K slices of the three weight matrices (FP32, w_layer floats) and
     // row-block sums of the three biases (FP64, b_layer doubles)
     float *wpart = nullptr;
