@@ -563,7 +563,8 @@ int64_t gw_flow_num_params(const gw_flow *flow);
 int gw_flow_set_params(gw_flow *flow, const float *params, const double *mu, const double *log_sigma);
 int gw_flow_get_params(const gw_flow *flow, float *params, double *mu, double *log_sigma);
 
-/* z (device) [n][dim] -> x_out [n][dim] and log q(x) (logq_out may be NULL). */
+/* z (device) [n][dim] -> x_out [n][dim] (may be z itself) and log q(x)
+ * (logq_out may be NULL). */
 int gw_flow_forward(gw_flow *flow, const double *z, int64_t n, double *x_out, double *logq_out,
                     hipStream_t stream);
 

@@ -573,11 +573,14 @@ __device__ __forceinline__ void products_from_lds(float4_t (&acc)[H / 64], const
 // coupling's masked BF16 input in LDS, and each row's sum of log-scales in a
 // register of one thread.  Every coupling still writes its outputs to global
 // memory (the backward pass and the weight gradients read them).  The
-// couplings share n, dim and sum_s.
+// couplings share n, dim and sum_s; the first coupling's masked BF16 input is
+// formed from its input rows (layer[0].xm is not read), and with init_sum
+// the rows' sums of log-scales start from zero instead of sum_s.
 constexpr int kMaxChain = 16;
 struct LayerChain {
     LayerArgs layer[kMaxChain];
     int count;
+    int init_sum;
 };
 static_assert(sizeof(LayerChain) <= 4096, "a chain is passed by value as the kernel's arguments (4 KiB at most)");
 
@@ -598,10 +601,13 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerChain c)
     const bf16x8_t zero8 = {};
     const int n = c.layer[0].n, dim = c.layer[0].dim;
     const bool row_ok = r0 + lr < n;
-    // the rows' inputs of the first coupling, loaded first (rows clamped to valid ones)
+    // the rows' inputs of the first coupling, loaded first (rows clamped to
+    // valid ones), and its masked BF16 input rows formed from them
     double yv = c.layer[0].a[(int64_t)min(r0 + crr, n - 1) * dim + min(ci, dim - 1)];
-    const bf16x8_t xl0 = ld_bf16x8(c.layer[0].xm + (int64_t)min(r0 + lr, n - 1) * kInPad + 8 * (g & 1));
-    double srow = c.layer[0].sum_s[min(r0 + (tid & 15), n - 1)];   // used by threads 0-15
+    double srow = c.init_sum ? 0.0 : c.layer[0].sum_s[min(r0 + (tid & 15), n - 1)];   // used by threads 0-15
+    xin[crr][ci] = (r0 + crr < n && ci < dim && ((c.layer[0].cond >> ci) & 1u)) ? f32_to_bf16((float)yv)
+                                                                                  : (uint16_t)0;
+    __syncthreads();
     for (int li = 0; li < c.count; ++li) {
         const LayerArgs &p = c.layer[li];
         // Every operand of the coupling is loaded now, unconditionally
@@ -632,10 +638,9 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerChain c)
         for (int k = 0; k < H / 32; ++k)
             w3f[k] = ld_bf16x8(p.w3 + (int64_t)min(ocol, n_out - 1) * H + 32 * k + 8 * g);
         __builtin_amdgcn_sched_barrier(0);   // all loads issued before the first product waits on its own
-        // h1 = relu(xm W1^T + b1), K = kInPad padded to 32 by zeros; the input
-        // rows of the first coupling from global memory, of the others from LDS
+        // h1 = relu(xm W1^T + b1), K = kInPad padded to 32 by zeros
         const bf16x8_t xs = *reinterpret_cast<const bf16x8_t *>(&xin[lr][8 * (g & 1)]);
-        const bf16x8_t xa = (g < 2 && row_ok) ? (li == 0 ? xl0 : xs) : zero8;
+        const bf16x8_t xa = (g < 2 && row_ok) ? xs : zero8;
         float4_t acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
@@ -1468,13 +1473,17 @@ gw::flow::LayerArgs layer_args(gw_flow *f, int l, int n, int dir, const double *
 // the forward direction (z -> x), -1 the inverse.  Boundary l is coupling l's
 // input in the forward direction; with keep_t (inverse, training) the
 // transposed activations and inputs and the log-scales are kept.
-hipError_t layer_chain(gw_flow *f, int n, int dir, int first, int count, bool keep_t, hipStream_t s)
+// a_first: the first coupling's input rows (null: its boundary); init_sum:
+// the sums of log-scales start from zero rather than from f->sum_s.
+hipError_t layer_chain(gw_flow *f, int n, int dir, int first, int count, bool keep_t, hipStream_t s,
+                       const double *a_first = nullptr, bool init_sum = false)
 {
     const int H = f->hidden, D = f->dim;
     const int step = dir > 0 ? 1 : -1;
     for (int done = 0; done < count;) {
         gw::flow::LayerChain c;
         c.count = std::min(count - done, gw::flow::kMaxChain);
+        c.init_sum = init_sum && done == 0 ? 1 : 0;
         for (int k = 0; k < c.count; ++k) {
             const int l = first + step * (done + k);
             if (dir > 0)
@@ -1484,6 +1493,7 @@ hipError_t layer_chain(gw_flow *f, int n, int dir, int first, int count, bool ke
                 c.layer[k] = layer_args(f, l, n, -1, boundary(f, l + 1), boundary(f, l),
                                         f->s_store + (int64_t)l * f->cap * D, keep_t, mask_of(f, l - 1, keep_t));
         }
+        if (done == 0 && a_first) c.layer[0].a = a_first;
         const dim3 grid((unsigned)((n + gw::flow::kLayerRows - 1) / gw::flow::kLayerRows));
         if (H == 256)
             hipLaunchKernelGGL(gw::flow::layer_kernel<256>, grid, dim3(256), 0, s, c);
@@ -1533,25 +1543,33 @@ hipError_t inverse_pass(gw_flow *f, int n, const double *x, bool keep_t, hipStre
 
 // Forward pass z -> x over rows [0, n): boundary 0 = z, couplings 0 .. L-1,
 // then the affine normalisation to boundary L+1 = x; sum_s as in the inverse.
-hipError_t forward_pass(gw_flow *f, int n, const double *z, hipStream_t s)
+// Forward pass z -> x_out over rows [0, n): couplings 0 .. L-1, then the
+// affine normalisation; sum_s as in the inverse.  The one-kernel path takes z
+// as the first coupling's input directly; the GEMM path copies it to
+// boundary 0 first.
+hipError_t forward_pass(gw_flow *f, int n, const double *z, double *x_out, hipStream_t s)
 {
     const int D = f->dim, L = f->layers;
-    GW_TRY(zero(n, f->sum_s, s));
-    GW_TRY(hipMemcpyAsync(boundary(f, 0), z, sizeof(double) * (size_t)n * D, hipMemcpyDeviceToDevice, s));
-    const gw::flow::NextMask m0 = mask_of(f, 0, false);
-    hipLaunchKernelGGL(gw::flow::mask_input_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, m0.cond, z, m0.xm,
-                       nullptr, f->ldT);
-    GW_TRY(hipGetLastError());
-    if (fused_width(f)) GW_TRY(layer_chain(f, n, 1, 0, L, false, s));
-    for (int l = 0; l < L && !fused_width(f); ++l) {
-        GW_TRY(mlp_forward(f, l, n, false, s));
-        hipLaunchKernelGGL(gw::flow::coupling_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], 1,
-                           boundary(f, l), f->out_f, boundary(f, l + 1), f->sum_s, nullptr,
-                           mask_of(f, l + 1, false));
+    if (fused_width(f)) {
+        GW_TRY(layer_chain(f, n, 1, 0, L, false, s, z, true));
+    } else {
+        GW_TRY(zero(n, f->sum_s, s));
+        if (z != boundary(f, 0))
+            GW_TRY(hipMemcpyAsync(boundary(f, 0), z, sizeof(double) * (size_t)n * D, hipMemcpyDeviceToDevice, s));
+        const gw::flow::NextMask m0 = mask_of(f, 0, false);
+        hipLaunchKernelGGL(gw::flow::mask_input_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, m0.cond, z, m0.xm,
+                           nullptr, f->ldT);
         GW_TRY(hipGetLastError());
+        for (int l = 0; l < L; ++l) {
+            GW_TRY(mlp_forward(f, l, n, false, s));
+            hipLaunchKernelGGL(gw::flow::coupling_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], 1,
+                               boundary(f, l), f->out_f, boundary(f, l + 1), f->sum_s, nullptr,
+                               mask_of(f, l + 1, false));
+            GW_TRY(hipGetLastError());
+        }
     }
     hipLaunchKernelGGL(gw::flow::affine_kernel, dim3((n + 15) / 16), dim3(256), 0, s, n, D, 1, f->mu, f->log_sigma,
-                       boundary(f, L), boundary(f, L + 1), f->sum_s, 0, mask_of(f, -1, false));
+                       boundary(f, L), x_out, f->sum_s, 0, mask_of(f, -1, false));
     return hipGetLastError();
 }
 
@@ -1802,13 +1820,20 @@ int gw_flow_forward(gw_flow *f, const double *z, int64_t n, double *x_out, doubl
     if (n == 0) return GW_OK;
     DeviceGuard g(f->device);
     if (int rc = ensure_batch(f, n)) return rc;
-    hipError_t e = forward_pass(f, (int)n, z, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(x_out, boundary(f, f->layers + 1), sizeof(double) * n * f->dim, hipMemcpyDeviceToDevice,
-                           stream);
+    // the passes read z to the end (log q), so an x_out that overlaps it
+    // takes a copy of z first
+    const size_t bytes = sizeof(double) * (size_t)n * f->dim;
+    const char *zb = reinterpret_cast<const char *>(z), *xb = reinterpret_cast<const char *>(x_out);
+    const double *zin = z;
+    hipError_t e = hipSuccess;
+    if (zb < xb + bytes && xb < zb + bytes) {
+        zin = boundary(f, 0);
+        e = hipMemcpyAsync(boundary(f, 0), z, bytes, hipMemcpyDeviceToDevice, stream);
+    }
+    if (e == hipSuccess) e = forward_pass(f, (int)n, zin, x_out, stream);
     if (e == hipSuccess && logq_out) {
         hipLaunchKernelGGL(gw::flow::base_density_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, (int)n, f->dim,
-                           boundary(f, 0), f->sum_s, logq_out, nullptr, nullptr);
+                           zin, f->sum_s, logq_out, nullptr, nullptr);
         e = hipGetLastError();
     }
     return e == hipSuccess ? GW_OK : hip_fail(e, "gw_flow_forward");

@@ -191,6 +191,11 @@ def test_flow_matches_oracle(gw):
     z = np.random.default_rng(5).standard_normal((n, 11))
     x, lq = f.forward(torch.from_numpy(z).to(DEV))
     x, lq = x.cpu().numpy(), lq.cpu().numpy()
+    # in place (x_out = z): the same values
+    zz = torch.from_numpy(z).to(DEV)
+    xi, lqi = f.forward(zz, x_out=zz)
+    np.testing.assert_array_equal(xi.cpu().numpy(), x)
+    np.testing.assert_array_equal(lqi.cpu().numpy(), lq)
 
     def evaluate(flow):
         ex, elq = flow.forward(torch.tensor(z))
