@@ -245,6 +245,23 @@ def test_flow_gradients_match_oracle(gw, n):
         assert (g[where[f"l{l}.w1"]].reshape(256, 11)[:, off] == 0).all()
 
 
+def test_flow_rows_do_not_depend_on_the_batch(gw):
+    """A row's way through the couplings never involves another row: the
+    forward and inverse passes of the first k rows of a batch equal, bit for
+    bit, those rows of the whole batch's passes, for batches that fill part
+    of one 16-row block (k = 1, 5), spill into a second (17) or end one row
+    short of the whole batch (999)."""
+    f, _ = _flow_pair(gw)
+    z = torch.from_numpy(np.random.default_rng(9).standard_normal((1000, 11))).to(DEV)
+    x, lq = f.forward(z)
+    zb, lqb = f.inverse(x)
+    for k in (1, 5, 17, 999):
+        xk, lqk = f.forward(z[:k].contiguous())
+        assert torch.equal(xk, x[:k]) and torch.equal(lqk, lq[:k]), k
+        zk, lqik = f.inverse(x[:k].contiguous())
+        assert torch.equal(zk, zb[:k]) and torch.equal(lqik, lqb[:k]), k
+
+
 def test_flow_longer_than_one_launch(gw):
     """20 couplings of hidden width 128: a launch carries the rows through at
     most 16 couplings of a pass, so the rows cross from one launch to the
