@@ -103,6 +103,22 @@ def measured_executed_flops(key: str, summary: str = PROFILE_SUMMARY, sources: s
     return _profile_value(f"executed_fp64_flops_per_launch_{key}", summary, sources)
 
 
+# (sample, bin) pairs of one launch of the batch the tile kernel's counter
+# summary was taken on: 4096 samples x 259,585 bins
+PROFILED_PAIRS = 4096 * 259585
+
+
+def executed_flops_per_pair(precision: str, summary: str = PROFILE_SUMMARY, sources: str | None = None):
+    """FP64 flops the counters saw the split-form tile loop execute per
+    (sample, bin) pair at this precision: the mean over the plans of a
+    matching summary, or None when there is none."""
+    plans = profiled_plans(precision, summary, sources)
+    if not plans:
+        return None
+    total = sum(measured_executed_flops(f"{precision}@{p}", summary, sources) for p in plans)
+    return total / len(plans) / PROFILED_PAIRS
+
+
 def plan_key(precision: str, plan: dict) -> str:
     """Key of a likelihood plan's figures in the tile kernel's counter
     summary: precision@TILExROUNDS."""
@@ -280,6 +296,10 @@ def bench_ragged(args):
         raise SystemExit("non-finite lnL in the ragged batch")
     pairs = sum(c * e.grid.n_bins for c, e in zip(counts, evs))
     flops = flops_per_pair(3, prec == "mixed") * pairs
+    # the ragged kernel runs the tile kernel's per-tile loop, so the flops the
+    # counters saw that loop execute per pair price this pass too
+    per_pair = executed_flops_per_pair(prec)
+    executed = per_pair * pairs if per_pair is not None else None
     result = {
         "metric": "lnL evals/s (256 ragged BNS events, 3 det, 512 proposals each)",
         "value": rows / rag_s, "unit": "lnL evals/s", "n_gpus": 1, "steps": steps, "warmup": 2,
@@ -289,9 +309,16 @@ def bench_ragged(args):
                    "sample_bin_pairs": pairs, "precision": prec, "tile_bins": tuning[0], "chunk_bins": tuning[1]},
         "separate_launches": {"value": rows / sep_s, "ms_per_step": sep_s * 1e3},
         "speedup_vs_separate": sep_s / rag_s,
-        "roofline": {"bound": "alu", "achieved": flops / rag_s / 1e12, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": flops / rag_s / 1e12 / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "whole ragged pass (graph)", "flops_per_pair": flops_per_pair(3, prec == "mixed")},
+        "roofline": {"bound": "alu", "achieved": executed / rag_s / 1e12 if executed else None,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": executed / rag_s / 1e12 / FP64_PEAK_TFLOPS if executed else None, "traffic": None,
+                     "kernel": "whole ragged pass (graph)",
+                     "flops_source": ("executed FP64 flops per (sample, bin) of the same tile loop, from the counters "
+                                      "in " + PROFILE_SUMMARY if executed
+                                      else "no counter summary of these kernel sources"),
+                     "executed_flops_per_pair": per_pair,
+                     "frac_tally": flops / rag_s / 1e12 / FP64_PEAK_TFLOPS,
+                     "flops_per_pair_tally": flops_per_pair(3, prec == "mixed")},
     }
     if not args.no_cpu_baseline:
         import oracle

@@ -61,6 +61,18 @@ def test_figures_are_kept_per_plan(tmp_path):
     assert bench.profiled_plans("fp64", _summary(tmp_path, "0" * 64), tile) == []
 
 
+def test_executed_flops_per_pair(tmp_path):
+    # the mean over the summary's plans, per pair of the profiled batch
+    tile = bench.PROFILE_SUMMARY
+    good = _summary(tmp_path, bench.kernel_fingerprint(tile))
+    assert bench.executed_flops_per_pair("fp64", good, tile) == pytest.approx(7.85e10 / (4096 * 259585))
+    assert bench.executed_flops_per_pair("mixed", good, tile) is None
+    assert bench.executed_flops_per_pair("fp64", _summary(tmp_path, "0" * 64), tile) is None
+    # the committed summary: about 73 FP64 flops per pair on the FP64 path
+    committed = bench.executed_flops_per_pair("fp64")
+    assert committed is not None and 60 < committed < 89
+
+
 def test_fingerprints_cover_each_kernels_sources():
     names = {k: [os.path.basename(p) for p in v] for k, v in bench.PROFILE_SOURCES.items()}
     for must in ("gw_kernels.hip", "gw_device_math.h", "gw_plan.h", "gw_phasor_table.h", "build.py"):
