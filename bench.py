@@ -910,6 +910,16 @@ def main():
     # FP64 flops the hardware counters saw one launch execute (FMA = 2), from
     # the committed summary of the same kernel sources; None when they changed
     executed = measured_executed_flops(key) if headline else None
+    source = f"executed FP64 flops from the counters in {PROFILE_SUMMARY}" if executed is not None else None
+    if executed is None and w.n_det == 3 and args.flags == 0:
+        # another batch on the same 3-detector split-form loop (other bins,
+        # samples or aligned spins, which change only the per-sample
+        # coefficients): the counted flops per (sample, bin) of that loop
+        per_pair = executed_flops_per_pair(args.precision)
+        if per_pair is not None:
+            executed = per_pair * w.n_samples * g.n_bins
+            source = ("executed FP64 flops per (sample, bin) of the same tile loop, from the counters in "
+                      + PROFILE_SUMMARY)
     achieved = executed / kernel_avg_s / 1e12 if executed is not None else None
     # VALU issue cycles per SIMD per launch (every instruction at its measured
     # issue cost: the mixed path's FP32 transcendentals take two slots)
@@ -932,8 +942,7 @@ def main():
                    "precision": args.precision, "flags": args.flags, "spins": args.spins, "plan": plan},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS if achieved is not None else None,
-                     "flops_source": (f"executed FP64 flops from the counters in {PROFILE_SUMMARY}"
-                                      if executed is not None else
+                     "flops_source": (source if executed is not None else
                                       f"no counter summary of these kernel sources under plan {key} "
                                       f"(profiled: {profiled_plans(args.precision)})"),
                      "executed_flops_per_launch": executed,
