@@ -1203,14 +1203,80 @@ __device__ __forceinline__ float adam_update(const AdamStep &a, int64_t i, float
     return pi;
 }
 
+// Bias tiles of the training step's last launch: 8 consecutive elements of
+// one bias vector (b1, b2 or b3) of one layer.  Their row-block partials are
+// staged through LDS 128 row blocks at a time, each row block's 8 values one
+// contiguous 64-byte load, and each wave then sums two of the columns in the
+// order of bias_gradient (lane k the blocks k, k + 64, ... in order, then the
+// same butterfly).
+constexpr int kBiasCols = 8, kBiasRows = 128;
+
+__device__ __forceinline__ int64_t bias_tiles_per_layer(const GradParts &gp)
+{
+    return 2 * ((gp.H + kBiasCols - 1) / kBiasCols) + (2 * gp.D + kBiasCols - 1) / kBiasCols;
+}
+
+__device__ __forceinline__ void bias_tile(const GradParts &gp, int64_t tile, float *__restrict__ grads,
+                                          const AdamStep &a, const Bf16Copies &c)
+{
+    __shared__ double bt[kBiasRows][kBiasCols + 1];
+    const int64_t H = gp.H, D = gp.D, th = (H + kBiasCols - 1) / kBiasCols;
+    const int64_t l = tile / bias_tiles_per_layer(gp), r = tile % bias_tiles_per_layer(gp);
+    const double *bp = gp.bpart + l * gp.b_layer;
+    const int64_t base = l * gp.per_layer;
+    const double *br;
+    int64_t bcols, len, q0, p0;
+    if (r < th) {
+        br = bp, bcols = H, len = H, q0 = r * kBiasCols, p0 = base + H * D;
+    } else if (r < 2 * th) {
+        br = bp + gp.rb_cap * H, bcols = H, len = H, q0 = (r - th) * kBiasCols, p0 = base + H * D + H + H * H;
+    } else {
+        br = bp + 2 * gp.rb_cap * H, bcols = 2 * D, len = 2 * D, q0 = (r - 2 * th) * kBiasCols,
+        p0 = base + H * D + 2 * H + H * H + 2 * D * H;
+    }
+    const int ncols = (int)min((int64_t)kBiasCols, len - q0);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double t0 = 0.0, t1 = 0.0;                       // this lane's sums of columns wave and wave + 4
+    for (int64_t y0 = 0; y0 < gp.rb; y0 += kBiasRows) {
+        const int rows = (int)min((int64_t)kBiasRows, gp.rb - y0);
+        __syncthreads();                             // the previous rows are summed
+        for (int i = threadIdx.x; i < rows * kBiasCols; i += blockDim.x) {
+            const int y = i / kBiasCols, cc = i % kBiasCols;
+            if (cc < ncols) bt[y][cc] = br[(y0 + y) * bcols + q0 + cc];
+        }
+        __syncthreads();
+        // lane k takes the rows y0 + y with y = k (mod 64), in order
+        for (int y = (int)((lane - y0 % 64 + 64) % 64); y < rows; y += 64) {
+            if (wave < ncols) t0 += bt[y][wave];
+            if (wave + 4 < ncols) t1 += bt[y][wave + 4];
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        t0 += __shfl_xor(t0, off);
+        t1 += __shfl_xor(t1, off);
+    }
+    if (lane != 0) return;
+    if (wave < ncols) {
+        const int64_t p = p0 + q0 + wave;
+        grads[p] = (float)t0;
+        write_bf16(c, p, adam_update(a, p, (float)t0));
+    }
+    if (wave + 4 < ncols) {
+        const int64_t p = p0 + q0 + wave + 4;
+        grads[p] = (float)t1;
+        write_bf16(c, p, adam_update(a, p, (float)t1));
+    }
+}
+
 // The end of a training step in one launch: every parameter's gradient from
 // its partial sums (the orders of grad_finish_kernel and bias_finish_kernel),
 // its Adam update and its BF16 copies.  Blocks below weight_blocks take one
 // parameter per thread; the biases that param_gradient leaves to waves go to
-// the blocks after them, one wave per bias element; with loss_out given, the
-// last block writes the mean of the n_rows per-row losses there (mean_block).
+// the bias_tiles blocks after them (bias_tile); with loss_out given, the last
+// block writes the mean of the n_rows per-row losses there (mean_block).
 __global__ __launch_bounds__(256) void finish_update_kernel(GradParts gp, float *__restrict__ grads, AdamStep a,
-                                                            Bf16Copies c, int weight_blocks, int64_t n_bias,
+                                                            Bf16Copies c, int weight_blocks, int64_t bias_tiles,
                                                             int n_rows, const double *__restrict__ loss,
                                                             double *__restrict__ loss_out)
 {
@@ -1226,14 +1292,8 @@ __global__ __launch_bounds__(256) void finish_update_kernel(GradParts gp, float 
         write_bf16(c, p, adam_update(a, p, g));
         return;
     }
-    const int64_t e = (int64_t)(blockIdx.x - weight_blocks) * 4 + (threadIdx.x >> 6);
-    if (e >= n_bias) return;                        // whole waves
-    const int lane = threadIdx.x & 63;
-    int64_t p;
-    const float g = bias_gradient(gp, e, lane, p);
-    if (lane != 0) return;
-    grads[p] = g;
-    write_bf16(c, p, adam_update(a, p, g));
+    const int64_t tile = (int64_t)blockIdx.x - weight_blocks;
+    if (tile < bias_tiles) bias_tile(gp, tile, grads, a, c);
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(int64_t n, double *__restrict__ p)
@@ -1696,10 +1756,12 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
     if (adam) {
         // the gradients' sums, the Adam step and the BF16 copies in one launch
         const int wblocks = blocks_for(f->n_params);
-        const int64_t n_bias = parts.rb > 64 ? (int64_t)L * (2 * H + 2 * D) : 0;
-        const int64_t blocks = wblocks + (n_bias + 3) / 4 + (loss_out ? 1 : 0);
+        const int64_t per_layer_tiles = 2 * ((H + gw::flow::kBiasCols - 1) / gw::flow::kBiasCols) +
+                                        (2 * D + gw::flow::kBiasCols - 1) / gw::flow::kBiasCols;
+        const int64_t tiles = parts.rb > 64 ? (int64_t)L * per_layer_tiles : 0;
+        const int64_t blocks = wblocks + tiles + (loss_out ? 1 : 0);
         hipLaunchKernelGGL(gw::flow::finish_update_kernel, dim3((unsigned)blocks), dim3(256), 0, s, parts, f->grads,
-                           *adam, bf16_copies(f), wblocks, n_bias, n, f->loss, loss_out);
+                           *adam, bf16_copies(f), wblocks, tiles, n, f->loss, loss_out);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(gw::flow::grad_finish_kernel, dim3(blocks_for(f->n_params)), dim3(256), 0, s, parts, f->grads);
