@@ -457,8 +457,9 @@ def bench_flow_train(args):
         "loss_history": hist,
         "roofline": {"bound": "mfma", "achieved": flops / per / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": flops / per / 1e12 / 2500.0, "traffic": None,
-                     "kernel": "whole training step (7 launches: one through all 8 couplings in each direction, "
-                               "one of all couplings' weight-gradient GEMMs, 4 short ones)",
+                     "kernel": "whole training step (5 launches: the minibatch gather, one through all 8 couplings "
+                               "in each direction, one of all couplings' weight-gradient GEMMs, one for the "
+                               "gradient sums and Adam)",
                      "gemm_flops_per_step": flops},
     }
     print(json.dumps(result), flush=True)

@@ -574,13 +574,28 @@ __device__ __forceinline__ void products_from_lds(float4_t (&acc)[H / 64], const
 // register of one thread.  Every coupling still writes its outputs to global
 // memory (the backward pass and the weight gradients read them).  The
 // couplings share n, dim and sum_s; the first coupling's masked BF16 input is
-// formed from its input rows (layer[0].xm is not read), and with init_sum
-// the rows' sums of log-scales start from zero instead of sum_s.
+// formed from its input rows (layer[0].xm is not read).
 constexpr int kMaxChain = 16;
+
+// What a chain launch does around its couplings (the flow's ends, so that a
+// pass needs no other launch).
+struct ChainEnds {
+    int init_sum;             // the rows' sums of log-scales start from zero (else from sum_s)
+    int affine_in;            // the first coupling's input is (a - mu) / sigma of the rows a = layer[0].a,
+                              // and the sums start from sum log sigma
+    NextMask in_mask;         // with affine_in: where the first coupling's masked input is kept (xm may be null)
+    double *affine_out;       // x = mu + sigma y of the last coupling's output rows goes here (null: none),
+                              // and the sums gain sum log sigma
+    const double *mu, *log_sigma;
+    int density;              // after the couplings, the base density of z: the last coupling's output rows,
+    const double *z_in;       // or these rows (the pass's input in the forward direction) when given
+    double *logq, *loss, *g;  // -|z|^2/2 - dim/2 log 2 pi - sum_s, |z|^2/2 + sum_s, z / n (each may be null)
+};
+
 struct LayerChain {
     LayerArgs layer[kMaxChain];
     int count;
-    int init_sum;
+    ChainEnds e;
 };
 static_assert(sizeof(LayerChain) <= 4096, "a chain is passed by value as the kernel's arguments (4 KiB at most)");
 
@@ -601,12 +616,30 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerChain c)
     const bf16x8_t zero8 = {};
     const int n = c.layer[0].n, dim = c.layer[0].dim;
     const bool row_ok = r0 + lr < n;
+    const ChainEnds &e = c.e;
     // the rows' inputs of the first coupling, loaded first (rows clamped to
     // valid ones), and its masked BF16 input rows formed from them
-    double yv = c.layer[0].a[(int64_t)min(r0 + crr, n - 1) * dim + min(ci, dim - 1)];
-    double srow = c.init_sum ? 0.0 : c.layer[0].sum_s[min(r0 + (tid & 15), n - 1)];   // used by threads 0-15
-    xin[crr][ci] = (r0 + crr < n && ci < dim && ((c.layer[0].cond >> ci) & 1u)) ? f32_to_bf16((float)yv)
-                                                                                  : (uint16_t)0;
+    const int64_t oc = (int64_t)min(r0 + crr, n - 1) * dim + min(ci, dim - 1);
+    double yv = c.layer[0].a[oc];
+    double srow;                                     // used by threads 0-15
+    if (e.affine_in) {
+        const int k = min(ci, dim - 1);
+        yv = (yv - e.mu[k]) * exp(-e.log_sigma[k]);
+        double acc = 0.0;
+        for (int j = 0; j < dim; ++j) acc += e.log_sigma[j];
+        srow = 0.0 + acc;
+    } else {
+        srow = e.init_sum ? 0.0 : c.layer[0].sum_s[min(r0 + (tid & 15), n - 1)];
+    }
+    {
+        const uint16_t x0 = (r0 + crr < n && ci < dim && ((c.layer[0].cond >> ci) & 1u)) ? f32_to_bf16((float)yv)
+                                                                                         : (uint16_t)0;
+        xin[crr][ci] = x0;
+        if (e.affine_in && e.in_mask.xm && r0 + crr < n) {
+            e.in_mask.xm[(int64_t)(r0 + crr) * kInPad + ci] = x0;
+            if (e.in_mask.xmT) e.in_mask.xmT[ci * e.in_mask.ldT + r0 + crr] = x0;
+        }
+    }
     __syncthreads();
     for (int li = 0; li < c.count; ++li) {
         const LayerArgs &p = c.layer[li];
@@ -707,7 +740,32 @@ __global__ __launch_bounds__(256) void layer_kernel(LayerChain c)
             srow += acc_s;
         }
     }
+    if (e.affine_out) {
+        if (r0 + crr < n && ci < dim)
+            e.affine_out[(int64_t)(r0 + crr) * dim + ci] = e.mu[ci] + exp(e.log_sigma[ci]) * yv;
+        double acc = 0.0;
+        for (int j = 0; j < dim; ++j) acc += e.log_sigma[j];
+        srow = srow + acc;
+    }
     if (tid < kLayerRows && r0 + tid < n) c.layer[0].sum_s[r0 + tid] = srow;
+    if (e.density) {
+        // z_i to LDS, then each row's |z|^2 in dimension order by one thread
+        const double zi = e.z_in ? e.z_in[oc] : yv;
+        if (e.g && r0 + crr < n && ci < dim) e.g[(int64_t)(r0 + crr) * dim + ci] = zi / (double)n;
+        __syncthreads();                             // the last coupling's sums have read sdet
+        sdet[crr][ci] = zi;
+        __syncthreads();
+        if (tid < kLayerRows && r0 + tid < n) {
+            double zz = 0.0;
+            for (int j = 0; j < dim; ++j) {
+                const double v = sdet[tid][j];
+                zz += v * v;
+            }
+            const double l = 0.5 * zz + srow;
+            if (e.logq) e.logq[r0 + tid] = -l - 0.5 * dim * 1.8378770664093453;   // log(2 pi)
+            if (e.loss) e.loss[r0 + tid] = l;
+        }
+    }
 }
 
 // Affine normalisation around the coupling stack: forward x = mu + sigma u,
@@ -1533,17 +1591,23 @@ gw::flow::LayerArgs layer_args(gw_flow *f, int l, int n, int dir, const double *
 // the forward direction (z -> x), -1 the inverse.  Boundary l is coupling l's
 // input in the forward direction; with keep_t (inverse, training) the
 // transposed activations and inputs and the log-scales are kept.
-// a_first: the first coupling's input rows (null: its boundary); init_sum:
-// the sums of log-scales start from zero rather than from f->sum_s.
+// a_first: the first coupling's input rows (null: its boundary); ends: what
+// the first launch does before the couplings (init_sum, affine_in, in_mask)
+// and the last one after them (affine_out, density).
 hipError_t layer_chain(gw_flow *f, int n, int dir, int first, int count, bool keep_t, hipStream_t s,
-                       const double *a_first = nullptr, bool init_sum = false)
+                       const double *a_first, const gw::flow::ChainEnds &ends)
 {
     const int H = f->hidden, D = f->dim;
     const int step = dir > 0 ? 1 : -1;
     for (int done = 0; done < count;) {
         gw::flow::LayerChain c;
         c.count = std::min(count - done, gw::flow::kMaxChain);
-        c.init_sum = init_sum && done == 0 ? 1 : 0;
+        c.e = ends;
+        if (done > 0) c.e.init_sum = c.e.affine_in = 0;
+        if (done + c.count < count) {
+            c.e.affine_out = nullptr;
+            c.e.density = 0;
+        }
         for (int k = 0; k < c.count; ++k) {
             const int l = first + step * (done + k);
             if (dir > 0)
@@ -1579,18 +1643,37 @@ hipError_t zero(int64_t n, double *p, hipStream_t s)
     return hipGetLastError();
 }
 
-// Inverse pass x -> z over rows [0, n): boundary L = the normalised x, then
-// the couplings L-1 .. 0 invert down to boundary 0 = z; sum_s = sum log sigma
-// + sum over layers of sum_T s.  Activations of every layer are kept for the
-// backward pass (with keep_t also the transposed copies).  Each kernel that
-// produces a coupling's input also writes that coupling's masked MLP input.
-hipError_t inverse_pass(gw_flow *f, int n, const double *x, bool keep_t, hipStream_t s)
+// Where a pass leaves the base density of its z (each may be null; all
+// null: none): log q = -|z|^2/2 - dim/2 log 2 pi - sum_s, the training loss
+// |z|^2/2 + sum_s, and its gradient z / n.
+struct DensityOut {
+    double *logq = nullptr, *loss = nullptr, *g = nullptr;
+    bool any() const { return logq || loss || g; }
+};
+
+// Inverse pass x -> z = boundary 0 over rows [0, n): the affine
+// normalisation, then couplings L-1 .. 0; sum_s[b] = sum log sigma + the
+// couplings' log-scales.  With keep_t the transposed activations and inputs
+// are kept for the weight gradients; the log-scales always are.
+hipError_t inverse_pass(gw_flow *f, int n, const double *x, bool keep_t, hipStream_t s, const DensityOut &den)
 {
     const int D = f->dim, L = f->layers;
+    if (fused_width(f)) {
+        // one launch: the normalisation before the couplings, the density after them
+        gw::flow::ChainEnds e{};
+        e.affine_in = 1;
+        e.in_mask = mask_of(f, L - 1, keep_t);
+        e.mu = f->mu;
+        e.log_sigma = f->log_sigma;
+        e.density = den.any() ? 1 : 0;
+        e.logq = den.logq;
+        e.loss = den.loss;
+        e.g = den.g;
+        return layer_chain(f, n, -1, L - 1, L, keep_t, s, x, e);
+    }
     hipLaunchKernelGGL(gw::flow::affine_kernel, dim3((n + 15) / 16), dim3(256), 0, s, n, D, -1, f->mu, f->log_sigma,
                        x, boundary(f, L), f->sum_s, 1, mask_of(f, L - 1, keep_t));
     GW_TRY(hipGetLastError());
-    if (fused_width(f)) return layer_chain(f, n, -1, L - 1, L, keep_t, s);
     for (int l = L - 1; l >= 0; --l) {
         double *s_out = f->s_store + (int64_t)l * f->cap * D;
         GW_TRY(mlp_forward(f, l, n, keep_t, s));
@@ -1598,39 +1681,55 @@ hipError_t inverse_pass(gw_flow *f, int n, const double *x, bool keep_t, hipStre
                            boundary(f, l + 1), f->out_f, boundary(f, l), f->sum_s, s_out, mask_of(f, l - 1, keep_t));
         GW_TRY(hipGetLastError());
     }
+    if (den.any()) {
+        hipLaunchKernelGGL(gw::flow::base_density_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, boundary(f, 0),
+                           f->sum_s, den.logq, den.loss, den.g);
+        GW_TRY(hipGetLastError());
+    }
     return hipSuccess;
 }
 
-// Forward pass z -> x over rows [0, n): boundary 0 = z, couplings 0 .. L-1,
-// then the affine normalisation to boundary L+1 = x; sum_s as in the inverse.
 // Forward pass z -> x_out over rows [0, n): couplings 0 .. L-1, then the
-// affine normalisation; sum_s as in the inverse.  The one-kernel path takes z
-// as the first coupling's input directly; the GEMM path copies it to
-// boundary 0 first.
-hipError_t forward_pass(gw_flow *f, int n, const double *z, double *x_out, hipStream_t s)
+// affine normalisation; sum_s as in the inverse; logq (may be null) the log
+// density of x_out.  The one-kernel path is one launch that takes z as the
+// first coupling's input directly; the GEMM path copies it to boundary 0
+// first.  z must not overlap x_out.
+hipError_t forward_pass(gw_flow *f, int n, const double *z, double *x_out, double *logq, hipStream_t s)
 {
     const int D = f->dim, L = f->layers;
     if (fused_width(f)) {
-        GW_TRY(layer_chain(f, n, 1, 0, L, false, s, z, true));
-    } else {
-        GW_TRY(zero(n, f->sum_s, s));
-        if (z != boundary(f, 0))
-            GW_TRY(hipMemcpyAsync(boundary(f, 0), z, sizeof(double) * (size_t)n * D, hipMemcpyDeviceToDevice, s));
-        const gw::flow::NextMask m0 = mask_of(f, 0, false);
-        hipLaunchKernelGGL(gw::flow::mask_input_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, m0.cond, z, m0.xm,
-                           nullptr, f->ldT);
+        gw::flow::ChainEnds e{};
+        e.init_sum = 1;
+        e.affine_out = x_out;
+        e.mu = f->mu;
+        e.log_sigma = f->log_sigma;
+        e.density = logq ? 1 : 0;
+        e.z_in = z;
+        e.logq = logq;
+        return layer_chain(f, n, 1, 0, L, false, s, z, e);
+    }
+    GW_TRY(zero(n, f->sum_s, s));
+    if (z != boundary(f, 0))
+        GW_TRY(hipMemcpyAsync(boundary(f, 0), z, sizeof(double) * (size_t)n * D, hipMemcpyDeviceToDevice, s));
+    const gw::flow::NextMask m0 = mask_of(f, 0, false);
+    hipLaunchKernelGGL(gw::flow::mask_input_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, m0.cond, z, m0.xm,
+                       nullptr, f->ldT);
+    GW_TRY(hipGetLastError());
+    for (int l = 0; l < L; ++l) {
+        GW_TRY(mlp_forward(f, l, n, false, s));
+        hipLaunchKernelGGL(gw::flow::coupling_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], 1,
+                           boundary(f, l), f->out_f, boundary(f, l + 1), f->sum_s, nullptr, mask_of(f, l + 1, false));
         GW_TRY(hipGetLastError());
-        for (int l = 0; l < L; ++l) {
-            GW_TRY(mlp_forward(f, l, n, false, s));
-            hipLaunchKernelGGL(gw::flow::coupling_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, f->cond[l], 1,
-                               boundary(f, l), f->out_f, boundary(f, l + 1), f->sum_s, nullptr,
-                               mask_of(f, l + 1, false));
-            GW_TRY(hipGetLastError());
-        }
     }
     hipLaunchKernelGGL(gw::flow::affine_kernel, dim3((n + 15) / 16), dim3(256), 0, s, n, D, 1, f->mu, f->log_sigma,
                        boundary(f, L), x_out, f->sum_s, 0, mask_of(f, -1, false));
-    return hipGetLastError();
+    GW_TRY(hipGetLastError());
+    if (logq) {
+        hipLaunchKernelGGL(gw::flow::base_density_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, z, f->sum_s,
+                           logq, nullptr, nullptr);
+        GW_TRY(hipGetLastError());
+    }
+    return hipSuccess;
 }
 
 // The BF16 copies of the flow's weights that the kernels read.
@@ -1649,10 +1748,10 @@ hipError_t gradients(gw_flow *f, int n, const double *x, double *loss_out, hipSt
     const int D = f->dim, H = f->hidden, L = f->layers;
     // weight gradients sum over the n rows: split K = n into slices of >= 256 rows
     const int split = std::max(1, std::min(gw::flow::kMaxSplit, n / 256));
-    GW_TRY(inverse_pass(f, n, x, true, s));
-    hipLaunchKernelGGL(gw::flow::base_density_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, D, boundary(f, 0),
-                       f->sum_s, nullptr, f->loss, f->g);
-    GW_TRY(hipGetLastError());
+    DensityOut den;
+    den.loss = f->loss;
+    den.g = f->g;
+    GW_TRY(inverse_pass(f, n, x, true, s, den));
     if (loss_out && !adam) {     // a training step takes the mean in its last launch
         hipLaunchKernelGGL(gw::flow::mean_kernel, dim3(1), dim3(256), 0, s, n, f->loss, loss_out);
         GW_TRY(hipGetLastError());
@@ -1892,12 +1991,7 @@ int gw_flow_forward(gw_flow *f, const double *z, int64_t n, double *x_out, doubl
         zin = boundary(f, 0);
         e = hipMemcpyAsync(boundary(f, 0), z, bytes, hipMemcpyDeviceToDevice, stream);
     }
-    if (e == hipSuccess) e = forward_pass(f, (int)n, zin, x_out, stream);
-    if (e == hipSuccess && logq_out) {
-        hipLaunchKernelGGL(gw::flow::base_density_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, (int)n, f->dim,
-                           zin, f->sum_s, logq_out, nullptr, nullptr);
-        e = hipGetLastError();
-    }
+    if (e == hipSuccess) e = forward_pass(f, (int)n, zin, x_out, logq_out, stream);
     return e == hipSuccess ? GW_OK : hip_fail(e, "gw_flow_forward");
 }
 
@@ -1907,14 +2001,11 @@ int gw_flow_inverse(gw_flow *f, const double *x, int64_t n, double *z_out, doubl
     if (n == 0) return GW_OK;
     DeviceGuard g(f->device);
     if (int rc = ensure_batch(f, n)) return rc;
-    hipError_t e = inverse_pass(f, (int)n, x, false, stream);
+    DensityOut den;
+    den.logq = logq_out;
+    hipError_t e = inverse_pass(f, (int)n, x, false, stream, den);
     if (e == hipSuccess && z_out)
         e = hipMemcpyAsync(z_out, boundary(f, 0), sizeof(double) * n * f->dim, hipMemcpyDeviceToDevice, stream);
-    if (e == hipSuccess && logq_out) {
-        hipLaunchKernelGGL(gw::flow::base_density_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, (int)n, f->dim,
-                           boundary(f, 0), f->sum_s, logq_out, nullptr, nullptr);
-        e = hipGetLastError();
-    }
     return e == hipSuccess ? GW_OK : hip_fail(e, "gw_flow_inverse");
 }
 
